@@ -1,0 +1,140 @@
+"""Seeded synthetic inputs shared by the GPU path, the oracle and the benchmark.
+
+This module only builds input arrays (particle packings, per-sample parameters).  It
+holds none of the method's arithmetic: no lattice-Boltzmann, contact or coupling
+formula lives here, so both sides of every parity check consume identical inputs
+without sharing any of the code under test.
+
+Packings follow the setups of the paper (arXiv 1808.08921):
+  * FCC packing of equal spheres with end layers fixed and periodic sides
+    (Sec. "Face-centered cubic packing of frictionless spheres"), radius
+    R = R0 + |u_n|/2 where R0 leaves zero overlap and |u_n| is the overlap;
+  * a single sphere settling under a body force (Sec. "Terminal velocity");
+  * a chain of spheres along the propagation axis (Sec. "Pressure wave ...").
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# face codes shared with the C interfaces (-x,+x,-y,+y,-z,+z order)
+PERIODIC, WALL, PRESSURE = 0, 1, 2
+WAVE_NONE, WAVE_SINE, WAVE_COSINE, WAVE_STEP = 0, 1, 2, 3
+
+# FCC basis in units of the cubic cell edge
+_FCC_BASIS = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]])
+
+
+def fcc_packing(ncx: int, ncy: int, ncz: int, a: float = 24.0, overlap_rel: float = 1e-3,
+                jitter: float = 0.05, seed: int = 0, z_shift: float | None = None,
+                fix_end_layers: bool = True, touching: bool = True, radius: float | None = None):
+    """FCC packing of ncx*ncy*ncz cubic cells (4 spheres each), cell edge ``a``.
+
+    R0 = a / (2 sqrt 2) is the touching radius (zero overlap).  Each sphere gets an
+    overlap u_p = overlap_rel * R0 * (1 + jitter * (2 U_p - 1)), U_p ~ U(0,1) from
+    ``numpy.random.default_rng(seed)``, and radius R0 + u_p / 2.  With
+    ``touching=False`` every sphere has the literal ``radius`` instead.
+    Centres sit on the FCC sites shifted by ``z_shift`` (default a/4) along z so that
+    both z ends cut the packing alike.  Spheres of the lowest and highest z layer are
+    flagged fixed.  Returns dict(x (n,3), radius (n,), fixed (n,) uint8, shape (nx,ny,nz)).
+    """
+    if z_shift is None:
+        z_shift = a / 4.0
+    sites = []
+    for k in range(ncz):
+        for j in range(ncy):
+            for i in range(ncx):
+                for b in _FCC_BASIS:
+                    sites.append(((i + b[0]) * a, (j + b[1]) * a, (k + b[2]) * a + z_shift))
+    x = np.array(sites, dtype=np.float64)
+    # order spheres by (z, y, x) so that indices grow along the propagation axis
+    order = np.lexsort((x[:, 0], x[:, 1], x[:, 2]))
+    x = x[order]
+    n = x.shape[0]
+    rng = np.random.default_rng(seed)
+    u = rng.random(n)
+    r0 = a / (2.0 * math.sqrt(2.0))
+    if touching:
+        overlap = overlap_rel * r0 * (1.0 + jitter * (2.0 * u - 1.0))
+        rad = r0 + 0.5 * overlap
+    else:
+        rad = np.full(n, float(radius if radius is not None else r0))
+    fixed = np.zeros(n, dtype=np.uint8)
+    if fix_end_layers and n:
+        zmin, zmax = x[:, 2].min(), x[:, 2].max()
+        fixed[np.isclose(x[:, 2], zmin)] = 1
+        fixed[np.isclose(x[:, 2], zmax)] = 1
+    shape = (int(round(ncx * a)), int(round(ncy * a)), int(round(ncz * a)))
+    return {"x": x, "radius": rad, "fixed": fixed, "shape": shape}
+
+
+def wave_fcc_case(seed: int = 0, ncx: int = 4, ncy: int = 4, ncz: int = 16, a: float = 24.0,
+                  overlap_rel: float = 1e-3, period: float = 200.0, amp: float = 1e-3):
+    """FCC wave-propagation workload: periodic x,y, density inlet at z = 0 driven by a
+    single-period cosine pulse, constant density at the top face, probes every 16 lu.
+    Material constants follow the paper's parameter table in lattice units
+    (rho_p* = 2.466, E* = 10.37, nu_p = 0.2, mu = 0, tau* = 1)."""
+    pk = fcc_packing(ncx, ncy, ncz, a=a, overlap_rel=overlap_rel, seed=seed)
+    nx, ny, nz = pk["shape"]
+    params = dict(nx=nx, ny=ny, nz=nz, tau=1.0, rho_f=1.0,
+                  bc=(PERIODIC, PERIODIC, PERIODIC, PERIODIC, PRESSURE, PRESSURE),
+                  wave=WAVE_COSINE, amp=amp, omega=2.0 * math.pi / period, t_n=int(round(period)),
+                  E=10.37, nu=0.2, mu=0.0, rho_p=2.466,
+                  probe_z=tuple(range(0, nz, 16)))
+    return params, pk
+
+
+def settling_case(n: int = 32, radius: float = 6.0, density_ratio: float = 2.0, g: float = 1e-5,
+                  tau: float = 0.8, centre=None):
+    """Single sphere settling in a closed box with half-way walls on every face.  The
+    fluid carries no body force; the sphere gets its weight net of buoyancy,
+    F_g = (rho_p - rho_f) (4/3) pi R^3 g, pointing to -z."""
+    if centre is None:
+        centre = (n / 2 - 0.5, n / 2 - 0.5, n - 8.5)
+    vol = 4.0 / 3.0 * math.pi * radius ** 3
+    fg = np.array([[0.0, 0.0, -(density_ratio - 1.0) * vol * g]])
+    params = dict(nx=n, ny=n, nz=n, tau=tau, rho_f=1.0, bc=(WALL,) * 6, wave=WAVE_NONE, amp=0.0,
+                  omega=0.0, t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=density_ratio, probe_z=())
+    pk = {"x": np.array([centre], dtype=np.float64), "radius": np.array([radius]),
+          "fixed": np.zeros(1, np.uint8), "fg": fg, "shape": (n, n, n)}
+    return params, pk
+
+
+def chain_case(n_spheres: int = 60, r0: float = 5.0, overlap: float = 0.01, side: int = 12,
+               length: int = 620, fixed: bool = False):
+    """Granular chain along z (Sec. "Pressure wave in fluids ..."): spheres of radius
+    R0 + overlap/2 at z = i (2R - overlap), i = 1..n, centred at x = y = side/2."""
+    rad = r0 + 0.5 * overlap
+    z = np.array([i * (2.0 * rad - overlap) for i in range(1, n_spheres + 1)])
+    x = np.stack([np.full(n_spheres, side / 2.0), np.full(n_spheres, side / 2.0), z], axis=1)
+    return {"x": x, "radius": np.full(n_spheres, rad),
+            "fixed": np.full(n_spheres, 1 if fixed else 0, np.uint8), "shape": (side, side, length)}
+
+
+def ensemble_members(n: int = 64, base_seed: int = 1000, a: float = 24.0):
+    """Uneven FCC samples for the batched ensemble: sample s draws, from
+    default_rng(base_seed + s), n_xy in {2,3,4}, n_z in {8..16}, overlap
+    10**U(-4,-2) of R0 and an inlet period in {50..400} steps."""
+    out = []
+    for s in range(n):
+        rng = np.random.default_rng(base_seed + s)
+        nxy = int(rng.integers(2, 5))
+        ncz = int(rng.integers(8, 17))
+        ov = float(10.0 ** rng.uniform(-4.0, -2.0))
+        period = int(rng.integers(50, 401))
+        params, pk = wave_fcc_case(seed=base_seed + s, ncx=nxy, ncy=nxy, ncz=ncz, a=a, overlap_rel=ov,
+                                   period=period)
+        out.append((params, pk))
+    return out
+
+
+def random_populations(shape, rho_f: float = 1.0, amp: float = 1e-3, seed: int = 0):
+    """Seeded near-equilibrium populations [19][nz][ny][nx]: rest weights times
+    (rho_f + noise).  The weights are the D3Q19 lattice weights listed in the paper
+    (1/3 rest, 1/18 axis, 1/36 diagonal), indexed as in its velocity matrix."""
+    w = np.array([1 / 18] * 6 + [1 / 36] * 12 + [1 / 3])
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    noise = amp * (2.0 * rng.random((19, nz, ny, nx)) - 1.0)
+    return w[:, None, None, None] * (rho_f + noise)
