@@ -1,0 +1,200 @@
+/*
+ * lbdem.h -- C interface of the MI355X (gfx950) coupled lattice-Boltzmann / DEM library.
+ *
+ * The library advances the hydro-micromechanical model of Cheng, Luding, Rivas, Harting
+ * and Magnanimo, "Hydro-micromechanical modeling of wave propagation in saturated
+ * granular media" (arXiv 1808.08921):
+ *   - a D3Q19 BGK fluid (Sec. 2.1, Eqs. bgk, stream, BGKequili, rhoAndU, Eq. 3d19q),
+ *   - spherical DEM particles with Hertz normal and Mindlin tangential contacts and
+ *     Newton-Euler motion (Sec. 2.2, Eqs. translate, rotate, fdLawn, fdLaws),
+ *   - two-way coupling by momentum exchange: half-way bounce-back on moving particle
+ *     surfaces, link force and torque, and conversion of covered / uncovered nodes
+ *     (Sec. 2.3, Eqs. mem, fFS, convertFS, convertSF, coupleF, coupleT),
+ *   - a density-prescribed face driven by an oscillating waveform (Sec. 2.4, Eq. source,
+ *     Table 2 "tab:source").
+ * One call to lbdem_step advances every lattice of a set by whole time steps on the GPU.
+ *
+ * Conventions (all functions):
+ *   - Every function returns 0 (LBDEM_OK) or a negative LBDEM_E* code and never throws
+ *     across this interface; lbdem_last_error() gives a message for the calling thread.
+ *   - Lattice units, dx = dt = 1.  Node (i,j,k) sits at coordinate (i,j,k); fields are
+ *     stored with x fastest: cell n = (k*ny + j)*nx + i.
+ *   - Face order everywhere: -x, +x, -y, +y, -z, +z.
+ *   - Host pointers are caller-owned, read or written during the call only, and the
+ *     call synchronises the library's stream before returning when it copies data.
+ *   - Device work is queued on the HIP stream given to lbdem_create (or later to
+ *     lbdem_set_stream); lbdem_step is asynchronous with respect to the host.
+ *   - Particle indices are per lattice, in the caller's order, 0..n-1.
+ *   - Populations are exchanged as double, [19][nz][ny][nx], direction d = 0..18 being
+ *     the paper's d = 1..19 of Eq. (3d19q) (d = 18 is the rest population).
+ */
+#ifndef LBDEM_H
+#define LBDEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBDEM_OK 0
+#define LBDEM_EINVAL (-1)    /* an argument is out of range or inconsistent */
+#define LBDEM_EDEVICE (-2)   /* the HIP runtime reported an error */
+#define LBDEM_ECAPACITY (-3) /* a fixed-capacity device table overflowed (lbdem_status) */
+#define LBDEM_ENOMEM (-4)    /* the workspace is too small or host memory ran out */
+#define LBDEM_ESTATE (-5)    /* the call is not valid in the current state */
+#define LBDEM_ERANGE (-6)    /* a requested step range is not (or no longer) recorded */
+
+/* face boundary kinds */
+#define LBDEM_PERIODIC 0 /* periodic pair of faces */
+#define LBDEM_WALL 1     /* stationary half-way bounce-back wall half a node outside */
+#define LBDEM_PRESSURE 2 /* prescribed density (z faces only): -z follows the waveform, +z keeps rho_f */
+
+/* waveform of the density at the -z face, Eq. (source) and Table 2 (tab:source) */
+#define LBDEM_WAVE_NONE 0   /* rho = rho_f */
+#define LBDEM_WAVE_SINE 1   /* rho_f + A sin(omega t)        for t <= t_n */
+#define LBDEM_WAVE_COSINE 2 /* rho_f + A (1 - cos(omega t))  for t <= t_n */
+#define LBDEM_WAVE_STEP 3   /* rho_f + A                     for t <= t_n */
+
+/* storage precision of the populations (collision arithmetic in brackets) */
+#define LBDEM_FP64 0    /* double [double] */
+#define LBDEM_FP32 1    /* float [float] */
+#define LBDEM_FP16DEV 2 /* IEEE half of q = f/w_d - rho_f [float] */
+#define LBDEM_BF16DEV 3 /* bfloat16 of q = f/w_d - rho_f [float] */
+
+#define LBDEM_MAX_PROBES 64
+
+/* status bits returned by lbdem_status */
+#define LBDEM_STATUS_WAVE_SLOT_OVERFLOW 0x1u /* link partials spilled to atomics (results valid, order not fixed) */
+#define LBDEM_STATUS_NEAR_OVERFLOW 0x2u      /* a particle had more near neighbours than the table holds (error) */
+#define LBDEM_STATUS_CHANGE_OVERFLOW 0x4u    /* node-change list spilled; a full map copy was used (results valid) */
+#define LBDEM_STATUS_HISTORY_OVERFLOW 0x8u   /* tangential contact history table full (error) */
+#define LBDEM_STATUS_TOO_FAST 0x10u          /* a particle moved more than 0.25 lu in one step (error) */
+#define LBDEM_STATUS_NODE_SLOT_OVERFLOW 0x20u /* a fluid node touched more particles than its slots (results valid) */
+
+/* One lattice and its physics (Sec. 2; Table 1 "tab:params" for the FCC runs). */
+typedef struct lbdem_params {
+    int32_t nx, ny, nz;      /* lattice size, each >= 1 */
+    int32_t face_bc[6];      /* LBDEM_PERIODIC / LBDEM_WALL / LBDEM_PRESSURE per face */
+    double tau;              /* BGK relaxation time, > 0.5 (Sec. 2.1) */
+    double rho_f;            /* mean fluid density */
+    int32_t wave;            /* LBDEM_WAVE_* at the -z face when it is LBDEM_PRESSURE */
+    double rho_amp;          /* waveform amplitude rho' */
+    double omega;            /* angular frequency, rad per step */
+    int64_t t_n;             /* last time level at which the waveform is applied */
+    double young_E;          /* contact Young's modulus E_p (Eq. fdLawn) */
+    double poisson_nu;       /* contact Poisson ratio nu_p */
+    double friction_mu;      /* Coulomb friction coefficient (0: frictionless) */
+    double rho_p;            /* particle density; m = rho_p 4/3 pi R^3, I = 2/5 m R^2 */
+    int32_t n_probe;         /* number of probe planes (0..LBDEM_MAX_PROBES) */
+    int32_t probe_z[LBDEM_MAX_PROBES]; /* z index of each probe plane */
+    int32_t max_particles;   /* particle capacity of this lattice (>= 0) */
+} lbdem_params;
+
+/* Settings shared by all lattices of a set. */
+typedef struct lbdem_config {
+    int32_t precision;    /* LBDEM_FP64 / LBDEM_FP32 / LBDEM_FP16DEV / LBDEM_BF16DEV */
+    int32_t probe_ring;   /* number of most recent steps whose probes are kept (>= 1) */
+    int32_t tile_x;       /* x extent of a fluid-kernel tile: 8, 16, 32, 64, or 0 = automatic */
+    int32_t z_per_thread; /* z planes per fluid-kernel thread: 1..16, or 0 = automatic */
+    int32_t graph_steps;  /* steps per replayed HIP graph: 1..64, or 0 = no graph (eager launches) */
+} lbdem_config;
+
+typedef struct lbdem_set lbdem_set;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbdem_last_error(void);
+
+/* Fill *cfg with the defaults (FP32, automatic tiles, 4096-step probe ring, graphs of 8 steps). */
+int lbdem_default_config(lbdem_config *cfg);
+
+/* Bytes of device workspace needed by lbdem_create for n_lat lattices.
+ * lat: array of n_lat parameter blocks; cfg: may be NULL for the defaults. */
+int lbdem_workspace_size(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg, size_t *bytes);
+
+/* Create a set of n_lat independent lattices advanced together (a batched ensemble when
+ * n_lat > 1).  device_workspace: a device allocation of at least lbdem_workspace_size
+ * bytes, aligned to 256 bytes and owned by the caller, who keeps it alive until
+ * lbdem_destroy; or NULL, in which case the library allocates (and later frees) it.
+ * hip_stream: the hipStream_t to queue work on (NULL = the null stream).
+ * The populations start at rest, f_d = w_d rho_f, and the lattices hold no particles.
+ * Errors: LBDEM_EINVAL for invalid parameters (tau <= 0.5, a periodic face paired with a
+ * non-periodic one, LBDEM_PRESSURE on an x or y face, ...), LBDEM_ENOMEM, LBDEM_EDEVICE. */
+int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg, void *device_workspace,
+                 size_t workspace_bytes, void *hip_stream, lbdem_set **out);
+
+/* Release the set (waits for its queued work first). */
+int lbdem_destroy(lbdem_set *set);
+
+/* Change the stream used for subsequent work. */
+int lbdem_set_stream(lbdem_set *set, void *hip_stream);
+
+/* Place n spheres in lattice `lattice` (replacing any previous ones) and project them on
+ * the lattice (Sec. 2.3, Fig. mem): a node is solid when d^2 <= R^2 (closed ball); a node
+ * inside several spheres belongs to the one with the smallest d^2, then the smallest
+ * index.  Host arrays: x, v, w, fg are n x 3 (position, velocity, angular velocity, and a
+ * constant external force added in Eq. translate); radius is n; fixed is n (1 = the
+ * particle never moves and has V = Omega = 0).  v, w, fg and fixed may be NULL (zeros).
+ * Populations are not modified.  Errors: LBDEM_EINVAL when n exceeds max_particles, a
+ * radius is not positive, a centre lies outside a non-periodic extent, or a periodic
+ * axis is shorter than 2 R + 4. */
+int lbdem_particles_set(lbdem_set *set, int32_t lattice, int32_t n, const double *x, const double *v,
+                        const double *w, const double *radius, const double *fg, const uint8_t *fixed);
+
+/* Copy the current particle state of lattice `lattice` to host arrays (n x 3 each, any
+ * may be NULL): position, velocity, angular velocity, and the hydrodynamic force and
+ * torque of the last step, F_f-s and T_f-s of Eqs. (coupleF), (coupleT) (link sums plus
+ * the conversion impulses applied in that step).  n must equal the particle count. */
+int lbdem_particles_get(lbdem_set *set, int32_t lattice, int32_t n, double *x, double *v, double *w,
+                        double *force, double *torque);
+
+/* Queue nsteps coupled time steps of every lattice of the set.  Each step: pull
+ * streaming with moving-surface bounce-back and link forces, the density faces, BGK
+ * collision and probes (one fused kernel); link-force finalisation, contacts and
+ * symplectic-Euler motion (one kernel); re-projection with refill / emptying (one
+ * kernel).  Asynchronous; errors found on the device are reported by lbdem_status. */
+int lbdem_step(lbdem_set *set, int64_t nsteps);
+
+/* Number of steps taken so far (synchronises). */
+int lbdem_time(lbdem_set *set, int64_t *t);
+
+/* Wait for all queued work of the set. */
+int lbdem_synchronize(lbdem_set *set);
+
+/* Device status bits (LBDEM_STATUS_*) accumulated since create or the last clear
+ * (synchronises).  Returns LBDEM_ECAPACITY when an error bit is set. */
+int lbdem_status(lbdem_set *set, uint32_t *bits, int clear);
+
+/* Probe records of steps [first, first + n) of lattice `lattice` into
+ * out[n][n_probe][4]: for each probe plane, over its fluid nodes after the collision
+ * moments of that step (time level step + 1): node count, sum of rho - rho_f, sum of
+ * rho u_z, and sum of rho.  The cross-section averages of the paper (Sec. 3.2 and
+ * Sec. 4.3) are sum rho' / count and sum rho u_z / sum rho.  Errors: LBDEM_ERANGE if a
+ * step is in the future or older than the probe ring. */
+int lbdem_probe_read(lbdem_set *set, int32_t lattice, int64_t first, int64_t n, double *out);
+
+/* Current post-collision populations of lattice `lattice` as double [19][ncell]
+ * (decoded from the storage precision).  Values at solid nodes are unspecified. */
+int lbdem_populations_get(lbdem_set *set, int32_t lattice, double *f);
+
+/* Overwrite the populations of lattice `lattice` (encoded to the storage precision). */
+int lbdem_populations_set(lbdem_set *set, int32_t lattice, const double *f);
+
+/* Node map of lattice `lattice`: -1 for fluid, else the index of the covering particle. */
+int lbdem_owner_get(lbdem_set *set, int32_t lattice, int32_t *owner);
+
+/* Kernel timing with HIP events on the set's stream.  While enabled, lbdem_step launches
+ * kernels one by one and brackets every launch with a pair of events.  lbdem_timing_read
+ * synchronises and returns, for kernel k = 0 (fluid), 1 (particles), 2 (re-projection),
+ * the summed milliseconds ms[k] and the number of launches count[k] since enabling. */
+int lbdem_timing_enable(lbdem_set *set, int enable);
+int lbdem_timing_read(lbdem_set *set, double *ms, int64_t *count);
+
+/* Tile geometry actually used for lattice `lattice`: tile_x, tile_y, z_per_thread. */
+int lbdem_tile_info(lbdem_set *set, int32_t lattice, int32_t *tile_x, int32_t *tile_y, int32_t *z_per_thread);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBDEM_H */

@@ -1,0 +1,852 @@
+// lbdem_api.cpp -- host side of the C interface declared in include/lbdem.h.
+//
+// Validates arguments, lays the device buffers of a set out in one workspace, uploads
+// the per-lattice tables, and queues the three step kernels, either one by one or as
+// replays of a HIP graph built from kernel nodes.  No step arithmetic happens here: the
+// host only prepares tables (waveform values, probe maps) and copies data in and out.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbdem.h"
+#include "lbdem_internal.hpp"
+
+using namespace lbdem;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(LBDEM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_size(int prec)
+{
+    switch (prec) {
+    case PREC_FP64: return 8;
+    case PREC_FP32: return 4;
+    default: return 2;
+    }
+}
+
+// Carves aligned sub-buffers out of a base pointer; with base == nullptr it only sizes.
+struct Carver {
+    char *base = nullptr;
+    size_t off = 0;
+    template <class T> T *take(size_t n)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+struct Geometry {
+    std::vector<MemberDev> mem;
+    long long cells = 0;
+    int tiles = 0;
+    int ptot = 0;
+    int nprobe = 0;
+    long long ring_doubles = 0;
+    long long wave_doubles = 0;
+    long long pz = 0;
+    int nzt = 4;
+    int ring_len = 1;
+    int chg_cap = 0;
+    int prec = PREC_FP32;
+};
+
+bool is_pow2_tile(int v) { return v == 8 || v == 16 || v == 32 || v == 64; }
+
+int validate(int32_t n, const lbdem_params *lat, const lbdem_config *cfg)
+{
+    if (n < 1 || n > 4096 || !lat) return fail(LBDEM_EINVAL, "need 1..4096 lattices, got %d", n);
+    if (cfg->precision < 0 || cfg->precision > 3) return fail(LBDEM_EINVAL, "unknown precision %d", cfg->precision);
+    if (cfg->probe_ring < 1) return fail(LBDEM_EINVAL, "probe_ring must be >= 1");
+    if (cfg->tile_x != 0 && !is_pow2_tile(cfg->tile_x)) return fail(LBDEM_EINVAL, "tile_x must be 0, 8, 16, 32 or 64");
+    if (cfg->z_per_thread < 0 || cfg->z_per_thread > 16) return fail(LBDEM_EINVAL, "z_per_thread must be 0..16");
+    if (cfg->graph_steps < 0 || cfg->graph_steps > 64) return fail(LBDEM_EINVAL, "graph_steps must be 0..64");
+    for (int m = 0; m < n; ++m) {
+        const lbdem_params &p = lat[m];
+        if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(LBDEM_EINVAL, "lattice %d: sizes must be >= 1", m);
+        const long long nc = (long long)p.nx * p.ny * p.nz;
+        if (nc * kQ >= (1LL << 31)) return fail(LBDEM_EINVAL, "lattice %d: more than 113M cells", m);
+        const long long pop_bytes = nc * kQ * (cfg->precision == LBDEM_FP64 ? 8 : cfg->precision == LBDEM_FP32 ? 4 : 2);
+        if (pop_bytes >= (1LL << 32))
+            return fail(LBDEM_EINVAL, "lattice %d: its 19 population arrays must stay below 4 GiB", m);
+        if (!(p.tau > 0.5)) return fail(LBDEM_EINVAL, "lattice %d: tau must exceed 1/2 (got %g)", m, p.tau);
+        if (!(p.rho_f > 0.0)) return fail(LBDEM_EINVAL, "lattice %d: rho_f must be positive", m);
+        for (int f = 0; f < 6; ++f)
+            if (p.face_bc[f] < 0 || p.face_bc[f] > 2) return fail(LBDEM_EINVAL, "lattice %d: face %d kind", m, f);
+        for (int a = 0; a < 3; ++a)
+            if ((p.face_bc[2 * a] == LBDEM_PERIODIC) != (p.face_bc[2 * a + 1] == LBDEM_PERIODIC))
+                return fail(LBDEM_EINVAL, "lattice %d: axis %d mixes periodic and non-periodic faces", m, a);
+        for (int f = 0; f < 4; ++f)
+            if (p.face_bc[f] == LBDEM_PRESSURE) return fail(LBDEM_EINVAL, "lattice %d: density faces must be z faces", m);
+        if ((p.face_bc[4] == LBDEM_PRESSURE || p.face_bc[5] == LBDEM_PRESSURE) && p.nz < 2)
+            return fail(LBDEM_EINVAL, "lattice %d: density faces need nz >= 2", m);
+        if (p.wave < 0 || p.wave > 3) return fail(LBDEM_EINVAL, "lattice %d: wave kind", m);
+        if (p.t_n < 0 || p.t_n > (1LL << 28)) return fail(LBDEM_EINVAL, "lattice %d: t_n out of range", m);
+        if (p.n_probe < 0 || p.n_probe > LBDEM_MAX_PROBES) return fail(LBDEM_EINVAL, "lattice %d: n_probe", m);
+        for (int k = 0; k < p.n_probe; ++k) {
+            if (p.probe_z[k] < 0 || p.probe_z[k] >= p.nz) return fail(LBDEM_EINVAL, "lattice %d: probe %d outside", m, k);
+            for (int k2 = 0; k2 < k; ++k2)
+                if (p.probe_z[k2] == p.probe_z[k]) return fail(LBDEM_EINVAL, "lattice %d: duplicate probe plane", m);
+        }
+        if (p.max_particles < 0 || p.max_particles > (1 << 20)) return fail(LBDEM_EINVAL, "lattice %d: max_particles", m);
+        if (!(p.young_E >= 0.0) || !(p.poisson_nu > -1.0 && p.poisson_nu < 1.0) || !(p.friction_mu >= 0.0) ||
+            !(p.rho_p > 0.0))
+            return fail(LBDEM_EINVAL, "lattice %d: material constants out of range", m);
+    }
+    return LBDEM_OK;
+}
+
+int choose_tile_x(int nx, int req)
+{
+    if (req) return req;
+    int best = 64;
+    long long waste_best = -1;
+    for (int bx : {64, 32, 16, 8}) {
+        long long waste = (long long)((nx + bx - 1) / bx) * bx - nx;
+        if (waste_best < 0 || waste < waste_best) { waste_best = waste; best = bx; }
+    }
+    return best;
+}
+
+void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg, Geometry &G)
+{
+    G.mem.assign(n, MemberDev{});
+    G.prec = cfg->precision;
+    int nzt = cfg->z_per_thread ? cfg->z_per_thread : 2;
+    int nzmin = lat[0].nz;
+    for (int m = 1; m < n; ++m) nzmin = std::min(nzmin, lat[m].nz);
+    G.nzt = std::max(1, std::min(nzt, nzmin));
+    G.ring_len = cfg->probe_ring;
+    long long cells = 0, ring = 0, wave = 0, pz = 0;
+    int tiles = 0, pt = 0, npr = 0;
+    for (int m = 0; m < n; ++m) {
+        const lbdem_params &p = lat[m];
+        MemberDev &M = G.mem[m];
+        M.nx = p.nx; M.ny = p.ny; M.nz = p.nz;
+        M.bx = choose_tile_x(p.nx, cfg->tile_x);
+        M.bx_log2 = (int)std::lround(std::log2((double)M.bx));
+        M.by = 256 / M.bx;
+        M.ntx = (p.nx + M.bx - 1) / M.bx;
+        M.nty = (p.ny + M.by - 1) / M.by;
+        M.ntz = (p.nz + G.nzt - 1) / G.nzt;
+        M.tile_off = tiles;
+        tiles += M.ntx * M.nty * M.ntz;
+        for (int f = 0; f < 6; ++f) M.bc[f] = p.face_bc[f];
+        const int dims[3] = {p.nx, p.ny, p.nz};
+        for (int a = 0; a < 3; ++a) {
+            M.per[a] = p.face_bc[2 * a] == LBDEM_PERIODIC;
+            M.box[a] = (double)dims[a];
+        }
+        M.ncell = (long long)p.nx * p.ny * p.nz;
+        M.cell_off = cells;
+        M.pop_off = cells * kQ;
+        cells += M.ncell;
+        M.omega = 1.0 / p.tau;
+        M.rho_f = p.rho_f;
+        M.wave_off = wave;
+        M.t_n = p.t_n;
+        wave += p.t_n + 2;
+        M.pz_off = (int)pz;
+        pz += p.nz;
+        M.plist_off = npr;
+        M.n_probe = p.n_probe;
+        npr += p.n_probe;
+        M.ring_off = ring;
+        ring += (long long)G.ring_len * std::max(p.n_probe, 1) * 4;
+        M.p_off = pt;
+        M.p_cap = p.max_particles;
+        M.np = 0;
+        pt += p.max_particles;
+        M.E = p.young_E; M.nu = p.poisson_nu; M.mu = p.friction_mu; M.rho_p = p.rho_p;
+    }
+    G.cells = cells;
+    G.tiles = tiles;
+    G.ptot = pt;
+    G.nprobe = npr;
+    G.ring_doubles = ring;
+    G.wave_doubles = wave;
+    G.pz = pz;
+    G.chg_cap = (int)std::min<long long>(std::max<long long>(65536, 256LL * pt), 1LL << 26);
+}
+
+// Lays out (or sizes, when base is null) every device buffer; fills the pointers of s.
+size_t carve(const Geometry &G, char *base, DevSet &s)
+{
+    Carver c;
+    c.base = base;
+    const size_t es = elem_size(G.prec);
+    const int P = std::max(G.ptot, 1);
+    s.nmem = (int)G.mem.size();
+    s.mem = c.take<MemberDev>(G.mem.size());
+    s.tiles_total = G.tiles;
+    s.nzt = G.nzt;
+    s.popA = c.take<char>(es * kQ * (size_t)G.cells);
+    s.popB = c.take<char>(es * kQ * (size_t)G.cells);
+    s.own[0] = c.take<int>(G.cells);
+    s.own[1] = c.take<int>(G.cells);
+    s.chg_cap = G.chg_cap;
+    s.chg[0] = c.take<int>(2 * (size_t)G.chg_cap);
+    s.chg[1] = c.take<int>(2 * (size_t)G.chg_cap);
+    s.chgcnt = c.take<int>(2);
+    s.wcnt = c.take<int>((size_t)G.tiles * 4);
+    s.wpid = c.take<int>((size_t)G.tiles * 4 * kWaveSlots);
+    s.wval = c.take<double>((size_t)G.tiles * 4 * kWaveSlots * 6);
+    s.pprt = c.take<double>((size_t)G.tiles * G.nzt * 4);
+    s.ring = c.take<double>(G.ring_doubles);
+    s.ring_len = G.ring_len;
+    s.pzmap = c.take<short>(G.pz);
+    s.plist = c.take<int>(std::max(G.nprobe, 1));
+    s.nprobe_total = G.nprobe;
+    s.wave = c.take<double>(G.wave_doubles);
+    s.ptot = G.ptot;
+    for (int k = 0; k < 2; ++k) {
+        s.X[k] = c.take<double>(3 * (size_t)P);
+        s.V[k] = c.take<double>(3 * (size_t)P);
+        s.W[k] = c.take<double>(3 * (size_t)P);
+    }
+    s.R = c.take<double>(P);
+    s.m = c.take<double>(P);
+    s.I = c.take<double>(P);
+    s.Fg = c.take<double>(3 * (size_t)P);
+    s.Fh = c.take<double>(3 * (size_t)P);
+    s.Th = c.take<double>(3 * (size_t)P);
+    s.Ph = c.take<double>(3 * (size_t)P);
+    s.Lh = c.take<double>(3 * (size_t)P);
+    s.Xref = c.take<double>(3 * (size_t)P);
+    s.margin = c.take<double>(P);
+    s.ovf = c.take<double>(6 * (size_t)P);
+    s.fixed = c.take<int>(P);
+    s.pmem = c.take<int>(P);
+    s.nearl = c.take<int>((size_t)P * kNearCap);
+    s.nnear = c.take<int>(P);
+    for (int k = 0; k < 2; ++k) {
+        s.hj[k] = c.take<int>((size_t)P * kHistCap);
+        s.hf[k] = c.take<double>((size_t)P * kHistCap * 3);
+        s.hn[k] = c.take<int>(P);
+    }
+    s.tstep = c.take<long long>(1);
+    s.k3done = c.take<unsigned int>(1);
+    s.flags = c.take<unsigned int>(1);
+    return (c.off + 255) & ~size_t(255);
+}
+
+uint16_t f32_to_bf16_host(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float bf16_to_f32_host(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+const double kWh[kQ] = {1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36,
+                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                        1.0 / 36, 1.0 / 36, 1.0 / 3};
+const float kInvWh[kQ] = {18, 18, 18, 18, 18, 18, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 3};
+
+} // namespace
+
+struct lbdem_set {
+    Geometry G;
+    DevSet ds{};
+    std::vector<lbdem_params> params;
+    lbdem_config cfg{};
+    hipStream_t stream = nullptr;
+    void *ws = nullptr;
+    bool owns_ws = false;
+    int64_t t_host = 0;
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_steps = 0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_pending[3];
+    double ms_acc[3] = {0, 0, 0};
+    int64_t ms_cnt[3] = {0, 0, 0};
+    size_t ev_next = 0;
+};
+
+namespace {
+
+int sync_set(lbdem_set *S)
+{
+    HIPCHK(hipStreamSynchronize(S->stream));
+    return LBDEM_OK;
+}
+
+int upload_member(lbdem_set *S, int m)
+{
+    HIPCHK(hipMemcpyAsync((void *)(S->ds.mem + m), &S->G.mem[m], sizeof(MemberDev), hipMemcpyHostToDevice, S->stream));
+    return LBDEM_OK;
+}
+
+int destroy_graph(lbdem_set *S)
+{
+    if (S->gexec) { (void)hipGraphExecDestroy(S->gexec); S->gexec = nullptr; }
+    if (S->graph) { (void)hipGraphDestroy(S->graph); S->graph = nullptr; }
+    return LBDEM_OK;
+}
+
+int build_graph(lbdem_set *S, int steps)
+{
+    destroy_graph(S);
+    HIPCHK(hipGraphCreate(&S->graph, 0));
+    static int mode0 = 0, only_all = -1;
+    void *fluid_args[] = {(void *)&S->ds};
+    void *part_args[] = {(void *)&S->ds, (void *)&mode0, (void *)&only_all};
+    hipGraphNode_t prev = nullptr;
+    for (int k = 0; k < steps; ++k) {
+        hipKernelNodeParams kp{};
+        hipGraphNode_t n1, n2, n3;
+        kp.func = fluid_kernel_ptr(S->G.prec);
+        kp.gridDim = dim3(S->ds.tiles_total);
+        kp.blockDim = dim3(256);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = fluid_args;
+        kp.extra = nullptr;
+        HIPCHK(hipGraphAddKernelNode(&n1, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        kp.func = particles_kernel_ptr();
+        kp.gridDim = dim3(particles_grid(S->ds));
+        kp.kernelParams = part_args;
+        HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n1, 1, &kp));
+        kp.func = remap_kernel_ptr_prec(S->G.prec);
+        kp.gridDim = dim3(remap_grid(S->ds));
+        kp.kernelParams = part_args;
+        HIPCHK(hipGraphAddKernelNode(&n3, S->graph, &n2, 1, &kp));
+        prev = n3;
+    }
+    HIPCHK(hipGraphInstantiate(&S->gexec, S->graph, nullptr, nullptr, 0));
+    S->graph_steps = steps;
+    return LBDEM_OK;
+}
+
+int harvest_events(lbdem_set *S)
+{
+    for (int k = 0; k < 3; ++k) {
+        for (auto &pr : S->ev_pending[k]) {
+            float ms = 0.0f;
+            HIPCHK(hipEventSynchronize(S->ev_pool[pr.second]));
+            HIPCHK(hipEventElapsedTime(&ms, S->ev_pool[pr.first], S->ev_pool[pr.second]));
+            S->ms_acc[k] += ms;
+            S->ms_cnt[k] += 1;
+        }
+        S->ev_pending[k].clear();
+    }
+    S->ev_next = 0;
+    return LBDEM_OK;
+}
+
+int launch_step_eager(lbdem_set *S)
+{
+    for (int k = 0; k < 3; ++k) {
+        int e0 = -1, e1 = -1;
+        if (S->timing) {
+            if (S->ev_next + 2 > S->ev_pool.size()) {
+                int rc = harvest_events(S);
+                if (rc) return rc;
+            }
+            e0 = (int)S->ev_next++;
+            e1 = (int)S->ev_next++;
+            HIPCHK(hipEventRecord(S->ev_pool[e0], S->stream));
+        }
+        hipError_t err;
+        if (k == 0) err = launch_fluid(S->G.prec, S->ds, S->stream);
+        else if (k == 1) err = launch_particles(S->ds, 0, -1, S->stream);
+        else err = launch_remap_prec(S->G.prec, S->ds, 0, -1, S->stream);
+        if (err != hipSuccess) return fail(LBDEM_EDEVICE, "kernel launch %d: %s", k, hipGetErrorString(err));
+        if (S->timing) {
+            HIPCHK(hipEventRecord(S->ev_pool[e1], S->stream));
+            S->ev_pending[k].push_back({e0, e1});
+        }
+    }
+    return LBDEM_OK;
+}
+
+int check_lattice(lbdem_set *S, int32_t lattice)
+{
+    if (!S) return fail(LBDEM_EINVAL, "null set");
+    if (lattice < 0 || lattice >= (int)S->G.mem.size()) return fail(LBDEM_EINVAL, "lattice index %d out of range", lattice);
+    return LBDEM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *lbdem_last_error(void) { return g_err.c_str(); }
+
+int lbdem_default_config(lbdem_config *cfg)
+{
+    if (!cfg) return fail(LBDEM_EINVAL, "null config");
+    cfg->precision = LBDEM_FP32;
+    cfg->probe_ring = 4096;
+    cfg->tile_x = 0;
+    cfg->z_per_thread = 0;
+    cfg->graph_steps = 8;
+    return LBDEM_OK;
+}
+
+int lbdem_workspace_size(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg, size_t *bytes)
+{
+    lbdem_config c;
+    if (cfg) c = *cfg; else lbdem_default_config(&c);
+    if (!bytes) return fail(LBDEM_EINVAL, "null output");
+    int rc = validate(n_lat, lat, &c);
+    if (rc) return rc;
+    Geometry G;
+    build_geometry(n_lat, lat, &c, G);
+    DevSet s{};
+    *bytes = carve(G, nullptr, s);
+    return LBDEM_OK;
+}
+
+int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg, void *device_workspace,
+                 size_t workspace_bytes, void *hip_stream, lbdem_set **out)
+{
+    if (!out) return fail(LBDEM_EINVAL, "null output");
+    *out = nullptr;
+    lbdem_config c;
+    if (cfg) c = *cfg; else lbdem_default_config(&c);
+    int rc = validate(n_lat, lat, &c);
+    if (rc) return rc;
+    lbdem_set *S = new (std::nothrow) lbdem_set();
+    if (!S) return fail(LBDEM_ENOMEM, "host allocation failed");
+    S->cfg = c;
+    S->params.assign(lat, lat + n_lat);
+    S->stream = (hipStream_t)hip_stream;
+    build_geometry(n_lat, lat, &c, S->G);
+    DevSet probe{};
+    const size_t need = carve(S->G, nullptr, probe);
+    if (device_workspace) {
+        if (workspace_bytes < need) {
+            delete S;
+            return fail(LBDEM_ENOMEM, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
+        }
+        if (((uintptr_t)device_workspace & 255u) != 0) {
+            delete S;
+            return fail(LBDEM_EINVAL, "workspace must be 256-byte aligned");
+        }
+        S->ws = device_workspace;
+    } else {
+        hipError_t e = hipMalloc(&S->ws, need);
+        if (e != hipSuccess) {
+            delete S;
+            return fail(LBDEM_ENOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+        }
+        S->owns_ws = true;
+    }
+    carve(S->G, (char *)S->ws, S->ds);
+    DevSet &s = S->ds;
+    hipStream_t st = S->stream;
+    auto cleanup = [&](int code) {
+        lbdem_destroy(S);
+        return code;
+    };
+#define CHK(expr)                                                                            \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return cleanup(fail(LBDEM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+    // tables
+    CHK(hipMemcpyAsync((void *)s.mem, S->G.mem.data(), sizeof(MemberDev) * n_lat, hipMemcpyHostToDevice, st));
+    std::vector<short> pz(S->G.pz, (short)-1);
+    std::vector<int> plist(std::max(S->G.nprobe, 1), 0);
+    std::vector<double> wave(S->G.wave_doubles);
+    std::vector<int> pmem(std::max(S->G.ptot, 1), 0);
+    for (int m = 0; m < n_lat; ++m) {
+        const lbdem_params &p = lat[m];
+        const MemberDev &M = S->G.mem[m];
+        for (int k = 0; k < p.n_probe; ++k) {
+            pz[M.pz_off + p.probe_z[k]] = (short)k;
+            plist[M.plist_off + k] = p.probe_z[k];
+        }
+        // waveform values rho(t) of Eq. (source) / Table (tab:source) for t = 0..t_n,
+        // then rho_f for every later time level
+        for (long long tt = 0; tt <= p.t_n; ++tt) {
+            double v = p.rho_f;
+            if (p.wave != LBDEM_WAVE_NONE) {
+                const double wt = p.omega * (double)tt;
+                if (p.wave == LBDEM_WAVE_SINE) v = p.rho_f + p.rho_amp * sin(wt);
+                else if (p.wave == LBDEM_WAVE_COSINE) v = p.rho_f + p.rho_amp * (1.0 - cos(wt));
+                else v = p.rho_f + p.rho_amp;
+            }
+            wave[M.wave_off + tt] = v;
+        }
+        wave[M.wave_off + p.t_n + 1] = p.rho_f;
+        for (int q = 0; q < M.p_cap; ++q) pmem[M.p_off + q] = m;
+    }
+    CHK(hipMemcpyAsync((void *)s.pzmap, pz.data(), sizeof(short) * pz.size(), hipMemcpyHostToDevice, st));
+    CHK(hipMemcpyAsync((void *)s.plist, plist.data(), sizeof(int) * plist.size(), hipMemcpyHostToDevice, st));
+    CHK(hipMemcpyAsync((void *)s.wave, wave.data(), sizeof(double) * wave.size(), hipMemcpyHostToDevice, st));
+    CHK(hipMemcpyAsync(s.pmem, pmem.data(), sizeof(int) * pmem.size(), hipMemcpyHostToDevice, st));
+    // state
+    const int P = std::max(S->G.ptot, 1);
+    CHK(hipMemsetAsync(s.own[0], 0xff, sizeof(int) * S->G.cells, st));
+    CHK(hipMemsetAsync(s.own[1], 0xff, sizeof(int) * S->G.cells, st));
+    CHK(hipMemsetAsync(s.chgcnt, 0, sizeof(int) * 2, st));
+    CHK(hipMemsetAsync(s.wcnt, 0, sizeof(int) * S->G.tiles * 4, st));
+    CHK(hipMemsetAsync(s.pprt, 0, sizeof(double) * S->G.tiles * S->G.nzt * 4, st));
+    CHK(hipMemsetAsync(s.ring, 0, sizeof(double) * S->G.ring_doubles, st));
+    for (int k = 0; k < 2; ++k) {
+        CHK(hipMemsetAsync(s.X[k], 0, sizeof(double) * 3 * P, st));
+        CHK(hipMemsetAsync(s.V[k], 0, sizeof(double) * 3 * P, st));
+        CHK(hipMemsetAsync(s.W[k], 0, sizeof(double) * 3 * P, st));
+        CHK(hipMemsetAsync(s.hn[k], 0, sizeof(int) * P, st));
+    }
+    double *zero3[] = {s.Fg, s.Fh, s.Th, s.Ph, s.Lh, s.Xref};
+    for (double *z : zero3) CHK(hipMemsetAsync(z, 0, sizeof(double) * 3 * P, st));
+    CHK(hipMemsetAsync(s.ovf, 0, sizeof(double) * 6 * P, st));
+    CHK(hipMemsetAsync(s.margin, 0, sizeof(double) * P, st));
+    CHK(hipMemsetAsync(s.nnear, 0, sizeof(int) * P, st));
+    CHK(hipMemsetAsync(s.tstep, 0, sizeof(long long), st));
+    CHK(hipMemsetAsync(s.k3done, 0, sizeof(unsigned), st));
+    CHK(hipMemsetAsync(s.flags, 0, sizeof(unsigned), st));
+    CHK(launch_init_pops(S->G.prec, s, S->G.cells, st));
+    CHK(hipStreamSynchronize(st));
+#undef CHK
+    if (c.graph_steps > 0) {
+        rc = build_graph(S, c.graph_steps);
+        if (rc) return cleanup(rc);
+    }
+    S->ev_pool.resize(6 * 1024);
+    for (auto &e : S->ev_pool) {
+        hipError_t er = hipEventCreate(&e);
+        if (er != hipSuccess) return cleanup(fail(LBDEM_EDEVICE, "hipEventCreate: %s", hipGetErrorString(er)));
+    }
+    *out = S;
+    return LBDEM_OK;
+}
+
+int lbdem_destroy(lbdem_set *S)
+{
+    if (!S) return LBDEM_OK;
+    (void)hipStreamSynchronize(S->stream);
+    destroy_graph(S);
+    for (auto &e : S->ev_pool)
+        if (e) (void)hipEventDestroy(e);
+    if (S->owns_ws && S->ws) (void)hipFree(S->ws);
+    delete S;
+    return LBDEM_OK;
+}
+
+int lbdem_set_stream(lbdem_set *S, void *hip_stream)
+{
+    if (!S) return fail(LBDEM_EINVAL, "null set");
+    HIPCHK(hipStreamSynchronize(S->stream));
+    S->stream = (hipStream_t)hip_stream;
+    return LBDEM_OK;
+}
+
+int lbdem_particles_set(lbdem_set *S, int32_t lattice, int32_t n, const double *x, const double *v, const double *w,
+                        const double *radius, const double *fg, const uint8_t *fixed)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    MemberDev &M = S->G.mem[lattice];
+    if (n < 0 || n > M.p_cap) return fail(LBDEM_EINVAL, "lattice %d holds at most %d particles, got %d", lattice, M.p_cap, n);
+    if (n > 0 && (!x || !radius)) return fail(LBDEM_EINVAL, "positions and radii are required");
+    const int dims[3] = {M.nx, M.ny, M.nz};
+    std::vector<double> X(3 * (size_t)n), Vv(3 * (size_t)n, 0.0), Wv(3 * (size_t)n, 0.0), F(3 * (size_t)n, 0.0);
+    std::vector<double> Rv(n), mv(n), Iv(n);
+    std::vector<int> fx(n, 0);
+    for (int q = 0; q < n; ++q) {
+        const double R = radius[q];
+        if (!(R > 0.0) || !std::isfinite(R)) return fail(LBDEM_EINVAL, "particle %d: radius must be positive", q);
+        for (int a = 0; a < 3; ++a) {
+            double c = x[3 * q + a];
+            if (!std::isfinite(c)) return fail(LBDEM_EINVAL, "particle %d: non-finite position", q);
+            if (M.per[a]) {
+                if (dims[a] < 2.0 * R + 4.0)
+                    return fail(LBDEM_EINVAL, "particle %d: periodic axis %d shorter than 2R + 4", q, a);
+                c = std::fmod(c, (double)dims[a]);
+                if (c < 0.0) c += dims[a];
+            } else if (c < 0.0 || c > dims[a] - 1) {
+                return fail(LBDEM_EINVAL, "particle %d: centre outside the non-periodic extent of axis %d", q, a);
+            }
+            X[3 * q + a] = c;
+            if (fg) F[3 * q + a] = fg[3 * q + a];
+        }
+        fx[q] = fixed ? (fixed[q] != 0) : 0;
+        if (!fx[q]) {
+            for (int a = 0; a < 3; ++a) {
+                if (v) Vv[3 * q + a] = v[3 * q + a];
+                if (w) Wv[3 * q + a] = w[3 * q + a];
+            }
+        }
+        Rv[q] = R;
+        mv[q] = M.rho_p * (4.0 / 3.0) * M_PI * R * R * R;
+        Iv[q] = 0.4 * mv[q] * R * R;
+    }
+    rc = sync_set(S);
+    if (rc) return rc;
+    long long t = 0;
+    HIPCHK(hipMemcpy(&t, S->ds.tstep, sizeof(long long), hipMemcpyDeviceToHost));
+    const int par = (int)(t & 1);
+    DevSet &s = S->ds;
+    hipStream_t st = S->stream;
+    const size_t o3 = 3 * (size_t)M.p_off, o1 = M.p_off;
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(s.X[par] + o3, X.data(), 8 * 3 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s.V[par] + o3, Vv.data(), 8 * 3 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s.W[par] + o3, Wv.data(), 8 * 3 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s.Xref + o3, X.data(), 8 * 3 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s.Fg + o3, F.data(), 8 * 3 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s.R + o1, Rv.data(), 8 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s.m + o1, mv.data(), 8 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s.I + o1, Iv.data(), 8 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s.fixed + o1, fx.data(), 4 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(s.Fh + o3, 0, 8 * 3 * n, st));
+        HIPCHK(hipMemsetAsync(s.Th + o3, 0, 8 * 3 * n, st));
+        HIPCHK(hipMemsetAsync(s.Ph + o3, 0, 8 * 3 * n, st));
+        HIPCHK(hipMemsetAsync(s.Lh + o3, 0, 8 * 3 * n, st));
+        HIPCHK(hipMemsetAsync(s.ovf + 6 * o1, 0, 8 * 6 * n, st));
+        HIPCHK(hipMemsetAsync(s.hn[0] + o1, 0, 4 * n, st));
+        HIPCHK(hipMemsetAsync(s.hn[1] + o1, 0, 4 * n, st));
+    }
+    // fresh projection: clear both node maps of this lattice, then classify
+    HIPCHK(hipMemsetAsync(s.own[0] + M.cell_off, 0xff, sizeof(int) * M.ncell, st));
+    HIPCHK(hipMemsetAsync(s.own[1] + M.cell_off, 0xff, sizeof(int) * M.ncell, st));
+    M.np = n;
+    rc = upload_member(S, lattice);
+    if (rc) return rc;
+    hipError_t e = launch_particles(s, 1, lattice, st);
+    if (e != hipSuccess) return fail(LBDEM_EDEVICE, "near-list kernel: %s", hipGetErrorString(e));
+    e = launch_remap_prec(S->G.prec, s, 1, lattice, st);
+    if (e != hipSuccess) return fail(LBDEM_EDEVICE, "projection kernel: %s", hipGetErrorString(e));
+    // both node maps of this lattice now agree; a pending change list may still name its
+    // old cells, so the next fluid pass copies the current maps whole instead of applying it
+    int cnt[2];
+    HIPCHK(hipMemcpyAsync(cnt, s.chgcnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    cnt[par ^ 1] = s.chg_cap + 1;
+    HIPCHK(hipMemcpyAsync(s.chgcnt, cnt, sizeof(cnt), hipMemcpyHostToDevice, st));
+    return sync_set(S);
+}
+
+int lbdem_particles_get(lbdem_set *S, int32_t lattice, int32_t n, double *x, double *v, double *w, double *force,
+                        double *torque)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    const MemberDev &M = S->G.mem[lattice];
+    if (n != M.np) return fail(LBDEM_EINVAL, "lattice %d has %d particles, asked for %d", lattice, M.np, n);
+    rc = sync_set(S);
+    if (rc) return rc;
+    if (n == 0) return LBDEM_OK;
+    long long t = 0;
+    HIPCHK(hipMemcpy(&t, S->ds.tstep, sizeof(long long), hipMemcpyDeviceToHost));
+    const int par = (int)(t & 1);
+    const size_t o3 = 3 * (size_t)M.p_off, b = 8 * 3 * (size_t)n;
+    if (x) HIPCHK(hipMemcpy(x, S->ds.X[par] + o3, b, hipMemcpyDeviceToHost));
+    if (v) HIPCHK(hipMemcpy(v, S->ds.V[par] + o3, b, hipMemcpyDeviceToHost));
+    if (w) HIPCHK(hipMemcpy(w, S->ds.W[par] + o3, b, hipMemcpyDeviceToHost));
+    if (force) HIPCHK(hipMemcpy(force, S->ds.Fh + o3, b, hipMemcpyDeviceToHost));
+    if (torque) HIPCHK(hipMemcpy(torque, S->ds.Th + o3, b, hipMemcpyDeviceToHost));
+    return LBDEM_OK;
+}
+
+int lbdem_step(lbdem_set *S, int64_t nsteps)
+{
+    if (!S) return fail(LBDEM_EINVAL, "null set");
+    if (nsteps < 0) return fail(LBDEM_EINVAL, "negative step count");
+    int64_t left = nsteps;
+    if (!S->timing && S->gexec && S->graph_steps > 0) {
+        while (left >= S->graph_steps) {
+            HIPCHK(hipGraphLaunch(S->gexec, S->stream));
+            left -= S->graph_steps;
+        }
+    }
+    for (; left > 0; --left) {
+        int rc = launch_step_eager(S);
+        if (rc) return rc;
+    }
+    S->t_host += nsteps;
+    return LBDEM_OK;
+}
+
+int lbdem_time(lbdem_set *S, int64_t *t)
+{
+    if (!S || !t) return fail(LBDEM_EINVAL, "null argument");
+    int rc = sync_set(S);
+    if (rc) return rc;
+    long long tt = 0;
+    HIPCHK(hipMemcpy(&tt, S->ds.tstep, sizeof(long long), hipMemcpyDeviceToHost));
+    *t = tt;
+    return LBDEM_OK;
+}
+
+int lbdem_synchronize(lbdem_set *S)
+{
+    if (!S) return fail(LBDEM_EINVAL, "null set");
+    return sync_set(S);
+}
+
+int lbdem_status(lbdem_set *S, uint32_t *bits, int clear)
+{
+    if (!S || !bits) return fail(LBDEM_EINVAL, "null argument");
+    int rc = sync_set(S);
+    if (rc) return rc;
+    unsigned f = 0;
+    HIPCHK(hipMemcpy(&f, S->ds.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
+    *bits = f;
+    if (clear) HIPCHK(hipMemset(S->ds.flags, 0, sizeof(unsigned)));
+    const unsigned errs = LBDEM_STATUS_NEAR_OVERFLOW | LBDEM_STATUS_HISTORY_OVERFLOW | LBDEM_STATUS_TOO_FAST;
+    if (f & errs) return fail(LBDEM_ECAPACITY, "device status 0x%x", f);
+    return LBDEM_OK;
+}
+
+int lbdem_probe_read(lbdem_set *S, int32_t lattice, int64_t first, int64_t n, double *out)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && !out)) return fail(LBDEM_EINVAL, "bad output");
+    int64_t t = 0;
+    rc = lbdem_time(S, &t);
+    if (rc) return rc;
+    const MemberDev &M = S->G.mem[lattice];
+    if (first < 0 || first + n > t || first < t - S->G.ring_len)
+        return fail(LBDEM_ERANGE, "steps [%lld, %lld) not held (t = %lld, ring %d)", (long long)first,
+                    (long long)(first + n), (long long)t, S->G.ring_len);
+    if (M.n_probe == 0 || n == 0) return LBDEM_OK;
+    const size_t rec = (size_t)M.n_probe * 4;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t slot = (first + k) % S->G.ring_len;
+        HIPCHK(hipMemcpy(out + k * rec, S->ds.ring + M.ring_off + slot * rec, rec * 8, hipMemcpyDeviceToHost));
+    }
+    return LBDEM_OK;
+}
+
+int lbdem_populations_get(lbdem_set *S, int32_t lattice, double *f)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    if (!f) return fail(LBDEM_EINVAL, "null output");
+    int64_t t = 0;
+    rc = lbdem_time(S, &t);
+    if (rc) return rc;
+    const MemberDev &M = S->G.mem[lattice];
+    const size_t es = elem_size(S->G.prec), cnt = (size_t)kQ * M.ncell;
+    const char *src = (const char *)((t & 1) ? S->ds.popB : S->ds.popA) + es * M.pop_off;
+    std::vector<char> raw(es * cnt);
+    HIPCHK(hipMemcpy(raw.data(), src, raw.size(), hipMemcpyDeviceToHost));
+    const float rf = (float)M.rho_f;
+    for (size_t k = 0; k < cnt; ++k) {
+        const int d = (int)(k / M.ncell);
+        switch (S->G.prec) {
+        case PREC_FP64: f[k] = ((const double *)raw.data())[k]; break;
+        case PREC_FP32: f[k] = ((const float *)raw.data())[k]; break;
+        case PREC_FP16DEV: f[k] = (double)((float)kWh[d] * (rf + (float)((const _Float16 *)raw.data())[k])); break;
+        default: f[k] = (double)((float)kWh[d] * (rf + bf16_to_f32_host(((const uint16_t *)raw.data())[k]))); break;
+        }
+    }
+    return LBDEM_OK;
+}
+
+int lbdem_populations_set(lbdem_set *S, int32_t lattice, const double *f)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    if (!f) return fail(LBDEM_EINVAL, "null input");
+    int64_t t = 0;
+    rc = lbdem_time(S, &t);
+    if (rc) return rc;
+    const MemberDev &M = S->G.mem[lattice];
+    const size_t es = elem_size(S->G.prec), cnt = (size_t)kQ * M.ncell;
+    char *dst = (char *)((t & 1) ? S->ds.popB : S->ds.popA) + es * M.pop_off;
+    std::vector<char> raw(es * cnt);
+    const float rf = (float)M.rho_f;
+    for (size_t k = 0; k < cnt; ++k) {
+        const int d = (int)(k / M.ncell);
+        switch (S->G.prec) {
+        case PREC_FP64: ((double *)raw.data())[k] = f[k]; break;
+        case PREC_FP32: ((float *)raw.data())[k] = (float)f[k]; break;
+        case PREC_FP16DEV: ((_Float16 *)raw.data())[k] = (_Float16)((float)f[k] * kInvWh[d] - rf); break;
+        default: ((uint16_t *)raw.data())[k] = f32_to_bf16_host((float)f[k] * kInvWh[d] - rf); break;
+        }
+    }
+    HIPCHK(hipMemcpy(dst, raw.data(), raw.size(), hipMemcpyHostToDevice));
+    return LBDEM_OK;
+}
+
+int lbdem_owner_get(lbdem_set *S, int32_t lattice, int32_t *owner)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    if (!owner) return fail(LBDEM_EINVAL, "null output");
+    int64_t t = 0;
+    rc = lbdem_time(S, &t);
+    if (rc) return rc;
+    const MemberDev &M = S->G.mem[lattice];
+    HIPCHK(hipMemcpy(owner, S->ds.own[t & 1] + M.cell_off, sizeof(int) * M.ncell, hipMemcpyDeviceToHost));
+    for (long long k = 0; k < M.ncell; ++k)
+        if (owner[k] >= 0) owner[k] -= M.p_off;
+    return LBDEM_OK;
+}
+
+int lbdem_timing_enable(lbdem_set *S, int enable)
+{
+    if (!S) return fail(LBDEM_EINVAL, "null set");
+    int rc = sync_set(S);
+    if (rc) return rc;
+    rc = harvest_events(S);
+    if (rc) return rc;
+    S->timing = enable != 0;
+    for (int k = 0; k < 3; ++k) { S->ms_acc[k] = 0.0; S->ms_cnt[k] = 0; }
+    return LBDEM_OK;
+}
+
+int lbdem_timing_read(lbdem_set *S, double *ms, int64_t *count)
+{
+    if (!S || !ms || !count) return fail(LBDEM_EINVAL, "null argument");
+    int rc = sync_set(S);
+    if (rc) return rc;
+    rc = harvest_events(S);
+    if (rc) return rc;
+    for (int k = 0; k < 3; ++k) { ms[k] = S->ms_acc[k]; count[k] = S->ms_cnt[k]; }
+    return LBDEM_OK;
+}
+
+int lbdem_tile_info(lbdem_set *S, int32_t lattice, int32_t *tile_x, int32_t *tile_y, int32_t *z_per_thread)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    const MemberDev &M = S->G.mem[lattice];
+    if (tile_x) *tile_x = M.bx;
+    if (tile_y) *tile_y = M.by;
+    if (z_per_thread) *z_per_thread = S->G.nzt;
+    return LBDEM_OK;
+}
+
+} // extern "C"

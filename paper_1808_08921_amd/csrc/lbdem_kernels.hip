@@ -1,0 +1,1112 @@
+// lbdem_kernels.hip -- gfx950 kernels of the coupled lattice-Boltzmann / DEM step.
+//
+// Method: Cheng, Luding, Rivas, Harting, Magnanimo, "Hydro-micromechanical modeling of
+// wave propagation in saturated granular media", arXiv 1808.08921, Sec. 2.
+//
+// Three kernels make one time step t -> t+1 of every lattice of a set:
+//   k_fluid      one thread per (x, y) column of a tile, nzt planes deep: pull streaming
+//                (Eq. stream), half-way bounce-back on moving particle surfaces
+//                (Eq. mem), stationary walls, the density faces (Sec. 2.4), BGK collision
+//                (Eqs. bgk, BGKequili, rhoAndU), probe partial sums, and the link forces
+//                and torques (Eqs. fFS, coupleT) reduced per wavefront into a few
+//                (particle, F, T) slots.
+//   k_particles  one workgroup per particle: gathers the wavefront slots that can hold
+//                its links (a fixed, geometry-derived order: deterministic), adds the
+//                conversion impulses of the previous re-projection (Eqs. coupleF,
+//                coupleT), Hertz / Mindlin contacts (Eqs. fdLawn, fdLaws), and advances
+//                V, Omega, X by symplectic Euler (Eqs. translate, rotate).  Extra
+//                workgroups reduce the probe partials of each probe plane.
+//   k_remap      one workgroup per particle: re-projects the particle on the lattice
+//                (Sec. 2.3) where its motion can have changed a node, converts covered
+//                and uncovered nodes (Eqs. convertFS, convertSF) and records the
+//                impulses that act in the next step; the last workgroup advances the
+//                step counter.
+// The population layout is SoA [19][nz][ny][nx] per lattice; the fluid kernel is
+// bound by HBM bandwidth (about 1.5 flop per byte at FP32) and uses no MFMA.
+#include "lbdem_internal.hpp"
+
+namespace lbdem {
+
+// D3Q19 velocity set in the paper's order (Eq. 3d19q); index = paper index - 1.
+constexpr int kCX[kQ] = {1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0, 0};
+constexpr int kCY[kQ] = {0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0};
+constexpr int kCZ[kQ] = {0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1, 0};
+constexpr int kOPP[kQ] = {1, 0, 3, 2, 5, 4, 11, 10, 13, 12, 7, 6, 9, 8, 17, 16, 15, 14, 18};
+__device__ __forceinline__ int kCXr(int e) { return (e == 0 || (e >= 6 && e <= 9)) ? 1 : ((e == 1 || (e >= 10 && e <= 13)) ? -1 : 0); }
+__device__ __forceinline__ int kCYr(int e)
+{
+    return (e == 2 || e == 6 || e == 10 || e == 14 || e == 15) ? 1 : ((e == 3 || e == 7 || e == 11 || e == 16 || e == 17) ? -1 : 0);
+}
+__device__ __forceinline__ int kCZr(int e)
+{
+    return (e == 4 || e == 8 || e == 12 || e == 14 || e == 16) ? 1 : ((e == 5 || e == 9 || e == 13 || e == 15 || e == 17) ? -1 : 0);
+}
+// lattice weights (Sec. 2.1): 1/18 along the axes, 1/36 on the diagonals, 1/3 at rest
+constexpr double kWd[kQ] = {1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 3};
+constexpr double kCS2 = 1.0 / 3.0;
+// 2 w_d / c_s^2 of the moving-wall term of Eq. (mem)
+constexpr double kMW[kQ] = {2.0 * kWd[0] / kCS2, 2.0 * kWd[1] / kCS2, 2.0 * kWd[2] / kCS2, 2.0 * kWd[3] / kCS2,
+                            2.0 * kWd[4] / kCS2, 2.0 * kWd[5] / kCS2, 2.0 * kWd[6] / kCS2, 2.0 * kWd[7] / kCS2,
+                            2.0 * kWd[8] / kCS2, 2.0 * kWd[9] / kCS2, 2.0 * kWd[10] / kCS2, 2.0 * kWd[11] / kCS2,
+                            2.0 * kWd[12] / kCS2, 2.0 * kWd[13] / kCS2, 2.0 * kWd[14] / kCS2, 2.0 * kWd[15] / kCS2,
+                            2.0 * kWd[16] / kCS2, 2.0 * kWd[17] / kCS2, 2.0 * kWd[18] / kCS2};
+// 1 / w_d (exact) for the 16-bit deviation codec
+constexpr float kInvW[kQ] = {18, 18, 18, 18, 18, 18, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 3};
+
+// ---------------------------------------------------------------------------
+// storage precisions
+// ---------------------------------------------------------------------------
+template <int P> struct Prec;
+template <> struct Prec<PREC_FP64> { using S = double; using C = double; };
+template <> struct Prec<PREC_FP32> { using S = float; using C = float; };
+template <> struct Prec<PREC_FP16DEV> { using S = _Float16; using C = float; };
+template <> struct Prec<PREC_BF16DEV> { using S = uint16_t; using C = float; };
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u); // round to nearest even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// element idx of an array whose byte size stays below 4 GiB: a 32-bit byte offset from a
+// base that is the same in every lane (scalar base + vector offset addressing)
+template <typename T>
+__device__ __forceinline__ T ldo(const T *base, unsigned idx)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *base, unsigned idx, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (unsigned)sizeof(T)) = v;
+}
+
+// decode population d from storage
+template <int P>
+__device__ __forceinline__ typename Prec<P>::C ld(const typename Prec<P>::S *a, unsigned idx, int d, float rho_f)
+{
+    if constexpr (P == PREC_FP64 || P == PREC_FP32) {
+        return ldo(a, idx);
+    } else if constexpr (P == PREC_FP16DEV) {
+        return (float)kWd[d] * (rho_f + (float)ldo(a, idx));
+    } else {
+        return (float)kWd[d] * (rho_f + bf16_to_f32(ldo(a, idx)));
+    }
+}
+// encode population d to storage: 16-bit forms hold q = f / w_d - rho_f
+template <int P>
+__device__ __forceinline__ void st(typename Prec<P>::S *a, unsigned idx, int d, typename Prec<P>::C f, float rho_f)
+{
+    using S = typename Prec<P>::S;
+    if constexpr (P == PREC_FP64 || P == PREC_FP32) {
+        sto(a, idx, (S)f);
+    } else if constexpr (P == PREC_FP16DEV) {
+        sto(a, idx, (S)(f * kInvW[d] - rho_f));
+    } else {
+        sto(a, idx, f32_to_bf16(f * kInvW[d] - rho_f));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_swizzle(int b, int G)
+{
+    // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous tile range
+    const int q = G >> 3, r = G & 7, x = b & 7, k = b >> 3;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+__device__ __forceinline__ double mimg(double dx, int per, double n)
+{
+    if (per) {
+        if (dx > 0.5 * n) dx -= n;
+        else if (dx < -0.5 * n) dx += n;
+    }
+    return dx;
+}
+
+__device__ __forceinline__ double dist2(const MemberDev *M, int i, int j, int k, double X0, double X1, double X2)
+{
+    const double dx = mimg((double)i - X0, M->per[0], M->box[0]);
+    const double dy = mimg((double)j - X1, M->per[1], M->box[1]);
+    const double dz = mimg((double)k - X2, M->per[2], M->box[2]);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_i(int v, int old)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xf, false);
+}
+
+// Sum over the 64 lanes in a fixed order; the total lands in lane 63.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_d<0xB1, 0xF>(v);  // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E, 0xF>(v);  // quad_perm [2,3,0,1]
+    v += dpp_d<0x141, 0xF>(v); // row_half_mirror
+    v += dpp_d<0x140, 0xF>(v); // row_mirror
+    v += dpp_d<0x142, 0xA>(v); // row_bcast:15 into rows 1, 3
+    v += dpp_d<0x143, 0xC>(v); // row_bcast:31 into rows 2, 3
+    return v;
+}
+// Minimum over the 64 lanes, returned to every lane.
+__device__ __forceinline__ int wave_min(int v)
+{
+    v = min(v, dpp_i<0xB1, 0xF>(v, v));
+    v = min(v, dpp_i<0x4E, 0xF>(v, v));
+    v = min(v, dpp_i<0x141, 0xF>(v, v));
+    v = min(v, dpp_i<0x140, 0xF>(v, v));
+    v = min(v, dpp_i<0x142, 0xA>(v, v));
+    v = min(v, dpp_i<0x143, 0xC>(v, v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ double wave_min_d(double v)
+{
+    // values are non-negative here: the bit patterns order like the values
+    long long b = __double_as_longlong(v);
+    int hi = (int)(b >> 32);
+    unsigned lo = (unsigned)b;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int ohi = __shfl_xor(hi, off, 64);
+        const unsigned olo = (unsigned)__shfl_xor((int)lo, off, 64);
+        if (ohi < hi || (ohi == hi && olo < lo)) { hi = ohi; lo = olo; }
+    }
+    return __longlong_as_double(((long long)hi << 32) | lo);
+}
+
+// Block-wide (256 threads) sums of N doubles in a fixed order; result valid in thread 0.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = wave_sum(v[c]);
+    if (lane == 63)
+#pragma unroll
+        for (int c = 0; c < N; ++c) red[wv][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < N; ++c) v[c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    __syncthreads();
+}
+
+// values that are the same in every lane, moved to scalar registers
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni(long long v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double uni(double v) { return __longlong_as_double(uni((long long)__double_as_longlong(v))); }
+
+__device__ __forceinline__ const MemberDev *member_of_tile(const DevSet &s, int g)
+{
+    int lo = 0, hi = s.nmem - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.mem[mid].tile_off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return s.mem + uni(lo);
+}
+
+__device__ __forceinline__ int wrap_axis(int c, int n, int bclo, int bchi, int &kind)
+{
+    if (c < 0) { kind = max(kind, bclo); return c + n; }
+    if (c >= n) { kind = max(kind, bchi); return c - n; }
+    return c;
+}
+
+struct LinkSlot {
+    int pid;
+    double fx, fy, fz, tx, ty, tz;
+};
+
+__device__ __forceinline__ void slot_clear(LinkSlot &a)
+{
+    a.pid = kEmpty;
+    a.fx = a.fy = a.fz = a.tx = a.ty = a.tz = 0.0;
+}
+__device__ __forceinline__ void slot_acc(LinkSlot &a, double fx, double fy, double fz, double tx, double ty, double tz)
+{
+    a.fx += fx; a.fy += fy; a.fz += fz;
+    a.tx += tx; a.ty += ty; a.tz += tz;
+}
+
+// Density boundary on a z face: non-equilibrium bounce-back (Sec. 2.4) with zero
+// tangential velocity; the velocity normal to the face follows from the density.
+template <typename C>
+__device__ __forceinline__ void zou_he(C (&f)[kQ], C rho, bool top)
+{
+    // paper indices k -> f[k-1]
+    const C s0 = f[0] + f[1] + f[2] + f[3] + f[6] + f[7] + f[10] + f[11] + f[18];
+    const C nxc = C(0.5) * (f[0] + f[6] + f[7] - f[1] - f[10] - f[11]);
+    const C nyc = C(0.5) * (f[2] + f[6] + f[10] - f[3] - f[7] - f[11]);
+    if (!top) {
+        const C sm = f[5] + f[9] + f[13] + f[15] + f[17];
+        const C ruz = rho - (s0 + C(2) * sm);
+        f[4] = f[5] + ruz / C(3);
+        f[8] = f[13] + ruz / C(6) - nxc;
+        f[12] = f[9] + ruz / C(6) + nxc;
+        f[14] = f[17] + ruz / C(6) - nyc;
+        f[16] = f[15] + ruz / C(6) + nyc;
+    } else {
+        const C sp = f[4] + f[8] + f[12] + f[14] + f[16];
+        const C ruz = (s0 + C(2) * sp) - rho;
+        f[5] = f[4] - ruz / C(3);
+        f[13] = f[8] - ruz / C(6) + nxc;
+        f[9] = f[12] - ruz / C(6) - nxc;
+        f[17] = f[14] - ruz / C(6) + nyc;
+        f[15] = f[16] - ruz / C(6) - nyc;
+    }
+}
+
+// rho = sum f, j = sum f c (Eq. rhoAndU), summed in direction order
+template <typename C>
+__device__ __forceinline__ void moments(const C (&f)[kQ], C &rho, C &jx, C &jy, C &jz)
+{
+    C r = C(0), x = C(0), y = C(0), z = C(0);
+#pragma unroll
+    for (int d = 0; d < kQ; ++d) {
+        r += f[d];
+        if (kCX[d] > 0) x += f[d]; else if (kCX[d] < 0) x -= f[d];
+        if (kCY[d] > 0) y += f[d]; else if (kCY[d] < 0) y -= f[d];
+        if (kCZ[d] > 0) z += f[d]; else if (kCZ[d] < 0) z -= f[d];
+    }
+    rho = r; jx = x; jy = y; jz = z;
+}
+
+// f^eq_d(rho, u), Eq. (BGKequili)
+template <typename C>
+__device__ __forceinline__ C feq(int d, C rho, C ux, C uy, C uz, C uu)
+{
+    C cu = C(0);
+    if (kCX[d] > 0) cu += ux; else if (kCX[d] < 0) cu -= ux;
+    if (kCY[d] > 0) cu += uy; else if (kCY[d] < 0) cu -= uy;
+    if (kCZ[d] > 0) cu += uz; else if (kCZ[d] < 0) cu -= uz;
+    if constexpr (sizeof(C) == 8) {
+        const double cs2 = kCS2;
+        return kWd[d] * rho * (1.0 + cu / cs2 + (cu * cu) / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+    } else {
+        return (C)kWd[d] * rho * (C(1) + C(3) * cu + C(4.5) * (cu * cu) - C(1.5) * uu);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fluid kernel
+// ---------------------------------------------------------------------------
+// Transposed butterfly over the 64 lanes for 8 values at once (fixed order, so the
+// result is reproducible): on return lane l holds the 64-lane total of value
+// 4*bit5(l) + 2*bit4(l) + bit3(l).
+__device__ __forceinline__ double wave_reduce8(const double (&a)[8])
+{
+    const int lane = threadIdx.x & 63;
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+    double s1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        // lanes 32..63 of a[k] trade places with lanes 0..31 of a[k+4]
+        const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a[k]), __double2loint(a[k + 4]), false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a[k]), __double2hiint(a[k + 4]), false, false);
+        const double nd = __hiloint2double((int)hi[0], (int)lo[0]); // a[k+4] of lane - 32 (upper half)
+        const double ns = __hiloint2double((int)hi[1], (int)lo[1]); // a[k] of lane + 32 (lower half)
+        s1[k] = b5 ? (a[k + 4] + nd) : (a[k] + ns);
+    }
+    double s2[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(s1[k]), __double2loint(s1[k + 2]), false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(s1[k]), __double2hiint(s1[k + 2]), false, false);
+        const double nd = __hiloint2double((int)hi[0], (int)lo[0]);
+        const double ns = __hiloint2double((int)hi[1], (int)lo[1]);
+        s2[k] = b4 ? (s1[k + 2] + nd) : (s1[k] + ns);
+    }
+    const double y = b3 ? s2[0] : s2[1];       // what the lane 8 apart keeps
+    double r = (b3 ? s2[1] : s2[0]) + dpp_d<0x128, 0xF>(y); // row_ror:8 = lane ^ 8 within a row
+    r += dpp_d<0xB1, 0xF>(r);                  // lane ^ 1
+    r += dpp_d<0x4E, 0xF>(r);                  // lane ^ 2
+    r += dpp_d<0x141, 0xF>(r);                 // the other quad of the 8-lane group
+    return r;
+}
+
+// Moving half-way bounce-back (Eq. mem) and link force / torque (Eqs. fFS, coupleT) for
+// the links of node (i,j,z) whose solid end belongs to particle p (bit e of m set: the
+// source x - c_e of direction e lies in p).  With d = e* pointing into the particle,
+//   f_e = f~_d - 2 (w_d / c_s^2) rho_f V_b . c_d,   V_b = V_p + Omega_p x (x_b - X_p),
+//   F = c_d f~_d(x,t) - c_e f_e(x,t+1),   T = (x_b - X_p) x F,   x_b = x + c_d / 2.
+// Because x_b - X_p = (x - X_p) + c_d/2, V_b . c_d = c_d . (V_p + Omega_p x (x - X_p)) and
+// (c_d / 2) x F = 0 (F is parallel to c_d), so the rigid velocity and the torque arm are
+// evaluated once at the node.  f[e] holds f~_d(x,t) on entry and f_e(x,t+1) on exit.
+template <typename C>
+__device__ __forceinline__ void moving_links(C (&f)[kQ], unsigned m, int p, int i, int j, int z, double rho_f,
+                                             const DevSet &s, const double *PX, const double *PV, const double *PW,
+                                             int per0, int per1, int per2, double box0, double box1, double box2,
+                                             LinkSlot &L0, LinkSlot &L1)
+{
+    const double r0 = mimg((double)i - PX[3 * p], per0, box0);
+    const double r1 = mimg((double)j - PX[3 * p + 1], per1, box1);
+    const double r2 = mimg((double)z - PX[3 * p + 2], per2, box2);
+    const double w0 = PW[3 * p], w1 = PW[3 * p + 1], w2 = PW[3 * p + 2];
+    const double u0 = PV[3 * p] + (w1 * r2 - w2 * r1);
+    const double u1 = PV[3 * p + 1] + (w2 * r0 - w0 * r2);
+    const double u2 = PV[3 * p + 2] + (w0 * r1 - w1 * r0);
+    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < kQ - 1; ++e) {
+        if (m & (1u << e)) {
+            const int d = kOPP[e];
+            double cu = 0.0;
+            if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
+            if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
+            if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
+            const C fo = f[e];
+            const C v = fo - (C)(kMW[d] * rho_f * cu);
+            f[e] = v;
+            const double sl = (double)fo + (double)v; // F = c_d (f~_d + f_e)
+            if (kCX[d] > 0) F0 += sl; else if (kCX[d] < 0) F0 -= sl;
+            if (kCY[d] > 0) F1 += sl; else if (kCY[d] < 0) F1 -= sl;
+            if (kCZ[d] > 0) F2 += sl; else if (kCZ[d] < 0) F2 -= sl;
+        }
+    }
+    const double T0 = r1 * F2 - r2 * F1, T1 = r2 * F0 - r0 * F2, T2 = r0 * F1 - r1 * F0;
+    if (L0.pid == p || L0.pid == kEmpty) { L0.pid = p; slot_acc(L0, F0, F1, F2, T0, T1, T2); }
+    else if (L1.pid == p || L1.pid == kEmpty) { L1.pid = p; slot_acc(L1, F0, F1, F2, T0, T1, T2); }
+    else {
+        double *o6 = s.ovf + 6 * (long long)p;
+        atomicAdd(o6 + 0, F0); atomicAdd(o6 + 1, F1); atomicAdd(o6 + 2, F2);
+        atomicAdd(o6 + 3, T0); atomicAdd(o6 + 4, T1); atomicAdd(o6 + 5, T2);
+        atomicOr(s.flags, 0x20u);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_fluid(DevSet s)
+{
+    using S = typename Prec<P>::S;
+    using C = typename Prec<P>::C;
+    __shared__ double red[4][8];
+
+    const long long t = *s.tstep;
+    const int par = (int)(t & 1);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+    // bring the other node map up to date with the previous step's changes
+    const int prev_cnt = s.chgcnt[par ^ 1];
+    const bool full_copy = prev_cnt > s.chg_cap;
+    if (!full_copy) {
+        const int *lst = s.chg[par ^ 1];
+        int *nmap = s.own[par ^ 1];
+        const long long nthr = (long long)gridDim.x * blockDim.x;
+        for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < prev_cnt; e += nthr)
+            nmap[lst[2 * e]] = lst[2 * e + 1];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.chgcnt[par] = 0;
+
+    const int g = xcd_swizzle(blockIdx.x, gridDim.x);
+    const MemberDev *M = member_of_tile(s, g);
+    const int bxl = uni(M->bx_log2);
+    const int lx = threadIdx.x & ((1 << bxl) - 1), ly = threadIdx.x >> bxl;
+    const int tl = g - uni(M->tile_off);
+    const int ntx = uni(M->ntx), nty = uni(M->nty);
+    const int tx = tl % ntx, trem = tl / ntx, ty = trem % nty, tz = trem / nty;
+    const int nx = uni(M->nx), ny = uni(M->ny), nz = uni(M->nz);
+    const int i = (tx << bxl) + lx, j = ty * uni(M->by) + ly;
+    const bool vij = (i < nx) && (j < ny);
+    const int z0 = tz * s.nzt, z1 = min(z0 + s.nzt, nz);
+    const int nc = (int)uni(M->ncell);
+    const int nxy = nx * ny;
+    const long long pop_off = uni(M->pop_off), cell_off = uni(M->cell_off);
+    const S *A = (const S *)(par ? s.popB : s.popA) + pop_off;
+    S *B = (S *)(par ? s.popA : s.popB) + pop_off;
+    const int *own = s.own[par] + cell_off;
+    int *nmap = s.own[par ^ 1] + cell_off;
+    const double rho_fd = uni(M->rho_f);
+    const float rho_ff = (float)rho_fd;
+    const C omega = (C)uni(M->omega);
+    const int bc4 = uni(M->bc[4]), bc5 = uni(M->bc[5]);
+    const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
+    const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
+    const long long t_n = uni(M->t_n);
+    long long ti = t + 1;
+    if (ti > t_n + 1) ti = t_n + 1;
+    const C rho_in = (C)s.wave[uni(M->wave_off) + ti];
+    const C rho_out = (C)rho_fd;
+    const int pz_off = uni(M->pz_off);
+    const double *PX = s.X[par], *PV = s.V[par], *PW = s.W[par];
+
+    // offsets to the x-1 / x+1 / y-1 / y+1 neighbours (wrapped on periodic axes) and the
+    // kind of face crossed to reach them (0 inside or periodic, 1 wall, 2 density face)
+    int oxm = (i > 0) ? -1 : (nx - 1), oxp = (i < nx - 1) ? 1 : -(nx - 1);
+    int kxm = (i > 0) ? 0 : uni(M->bc[0]), kxp = (i < nx - 1) ? 0 : uni(M->bc[1]);
+    int oym = (j > 0) ? -nx : (ny - 1) * nx, oyp = (j < ny - 1) ? nx : -(ny - 1) * nx;
+    int kym = (j > 0) ? 0 : uni(M->bc[2]), kyp = (j < ny - 1) ? 0 : uni(M->bc[3]);
+
+    LinkSlot L0, L1;
+    slot_clear(L0); slot_clear(L1);
+
+    for (int z = z0; z < z1; ++z) {
+        // keep the per-direction offsets from being hoisted out of the loop (they are cheap
+        // to recompute, and 36 of them held live would cost occupancy)
+        asm volatile("" : "+v"(oxm), "+v"(oxp), "+v"(oym), "+v"(oyp), "+v"(kxm), "+v"(kxp), "+v"(kym), "+v"(kyp));
+        const int cell = (z * ny + j) * nx + i;
+        bool fl = false;
+        if (vij) {
+            const int o = ldo(own, (unsigned)cell);
+            fl = (o < 0);
+            if (full_copy) nmap[cell] = o;
+        }
+        double pr0 = 0.0, pr1 = 0.0, pr2 = 0.0, pr3 = 0.0;
+        if (fl) {
+            const int ozm = (z > 0) ? -nxy : (nz - 1) * nxy, ozp = (z < nz - 1) ? nxy : -(nz - 1) * nxy;
+            const int kzm = (z > 0) ? 0 : bc4, kzp = (z < nz - 1) ? 0 : bc5;
+            C f[kQ];
+            int pa = -1;
+            unsigned ma = 0u, mo = 0u;
+            // Eq. (stream) in pull form: f_e(x, t+1) = f~_e(x - c_e, t).  A source across a
+            // wall or inside a particle gives the bounced f~_{e*}(x, t) (the moving-wall term
+            // follows), a source across a density face is left for the boundary rule.
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                int off = 0, kind = 0;
+                if (kCX[e] > 0) { off += oxm; kind = max(kind, kxm); } else if (kCX[e] < 0) { off += oxp; kind = max(kind, kxp); }
+                if (kCY[e] > 0) { off += oym; kind = max(kind, kym); } else if (kCY[e] < 0) { off += oyp; kind = max(kind, kyp); }
+                if (kCZ[e] > 0) { off += ozm; kind = max(kind, kzm); } else if (kCZ[e] < 0) { off += ozp; kind = max(kind, kzp); }
+                const unsigned sc = (kind == 0) ? (unsigned)(cell + off) : (unsigned)cell;
+                const int os = ldo(own, sc);
+                const bool bb = (kind != 0) || (os >= 0);
+                const C v = ld<P>(A, bb ? (unsigned)(kOPP[e] * nc) + (unsigned)cell : (unsigned)(e * nc) + sc, e, rho_ff);
+                f[e] = (kind == BC_PRESSURE) ? C(0) : v;
+                if (kind == 0 && os >= 0) {
+                    if (pa < 0) pa = os;
+                    if (os == pa) ma |= 1u << e; else mo |= 1u << e;
+                }
+            }
+            f[18] = ld<P>(A, (unsigned)(18 * nc) + (unsigned)cell, 18, rho_ff);
+
+            if (ma) moving_links<C>(f, ma, pa, i, j, z, rho_fd, s, PX, PV, PW, per0, per1, per2, box0, box1, box2, L0, L1);
+            while (mo) {
+                // links to further particles (rare): one particle at a time
+                const int e0 = __builtin_ctz(mo);
+                int off0 = 0;
+                off0 += (kCXr(e0) > 0) ? oxm : (kCXr(e0) < 0 ? oxp : 0);
+                off0 += (kCYr(e0) > 0) ? oym : (kCYr(e0) < 0 ? oyp : 0);
+                off0 += (kCZr(e0) > 0) ? ozm : (kCZr(e0) < 0 ? ozp : 0);
+                const int pc = ldo(own, (unsigned)(cell + off0));
+                unsigned mc = 0u;
+#pragma unroll
+                for (int e = 0; e < kQ - 1; ++e) {
+                    if (mo & (1u << e)) {
+                        int off = 0;
+                        if (kCX[e] > 0) off += oxm; else if (kCX[e] < 0) off += oxp;
+                        if (kCY[e] > 0) off += oym; else if (kCY[e] < 0) off += oyp;
+                        if (kCZ[e] > 0) off += ozm; else if (kCZ[e] < 0) off += ozp;
+                        if (ldo(own, (unsigned)(cell + off)) == pc) mc |= 1u << e;
+                    }
+                }
+                moving_links<C>(f, mc, pc, i, j, z, rho_fd, s, PX, PV, PW, per0, per1, per2, box0, box1, box2, L0, L1);
+                mo &= ~mc;
+            }
+
+            if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, rho_in, false);
+            if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, rho_out, true);
+
+            C rho, jx, jy, jz;
+            moments<C>(f, rho, jx, jy, jz);
+            pr0 = 1.0;
+            pr1 = (double)rho - rho_fd;
+            pr2 = (double)jz;
+            pr3 = (double)rho;
+            const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
+            const C uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+            for (int d = 0; d < kQ; ++d) {
+                const C fe = feq<C>(d, rho, ux, uy, uz, uu);
+                st<P>(B, (unsigned)(d * nc) + (unsigned)cell, d, f[d] + omega * (fe - f[d]), rho_ff);
+            }
+        }
+        const int pidx = s.pzmap[pz_off + z];
+        if (pidx >= 0) {
+            double v[4] = {pr0, pr1, pr2, pr3};
+            block_sum<4>(v, red);
+            if (threadIdx.x == 0) {
+                double *o = s.pprt + ((long long)g * s.nzt + (z - z0)) * 4;
+                o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+            }
+        }
+    }
+
+    // link partials: one (particle, F, T) slot per distinct particle of this wavefront,
+    // in increasing particle order, each summed over the lanes in a fixed order
+    const long long WT = (long long)g * 4 + wv;
+    const int vi = (lane >> 3) & 7;
+    int k = 0;
+    for (;;) {
+        const int mn = min(L0.pid, L1.pid);
+        const int pm = wave_min(mn);
+        if (pm == kEmpty) break;
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (L0.pid == pm) { v[0] = L0.fx; v[1] = L0.fy; v[2] = L0.fz; v[3] = L0.tx; v[4] = L0.ty; v[5] = L0.tz; L0.pid = kEmpty; }
+        else if (L1.pid == pm) { v[0] = L1.fx; v[1] = L1.fy; v[2] = L1.fz; v[3] = L1.tx; v[4] = L1.ty; v[5] = L1.tz; L1.pid = kEmpty; }
+        const double r = wave_reduce8(v);
+        if ((lane & 7) == 0 && vi < 6) {
+            if (k < kWaveSlots) {
+                const long long o = WT * kWaveSlots + k;
+                s.wval[o * 6 + vi] = r;
+                if (vi == 0) s.wpid[o] = pm;
+            } else {
+                atomicAdd(s.ovf + 6 * (long long)pm + vi, r);
+                if (vi == 0) atomicOr(s.flags, 0x1u);
+            }
+        }
+        ++k;
+    }
+    if (lane == 0) s.wcnt[WT] = min(k, kWaveSlots);
+}
+
+// ---------------------------------------------------------------------------
+// particle kernel: link-force gather, contacts, motion; probe reduction
+// ---------------------------------------------------------------------------
+// Units (tiles along x, wavefront rows along y, tile layers along z) that can hold a
+// node within R + 2 of coordinate c, as a start unit and a count on a ring of nun units.
+__device__ __forceinline__ void axis_units(double c, double R, int n, int unit, int per, int &u0, int &L, int &nun)
+{
+    nun = (n + unit - 1) / unit;
+    int lo = (int)floor(c - R) - 2, hi = (int)ceil(c + R) + 2;
+    if (!per) {
+        lo = max(lo, 0);
+        hi = min(hi, n - 1);
+        if (lo > hi) { u0 = 0; L = 0; return; }
+        u0 = lo / unit;
+        L = hi / unit - u0 + 1;
+        return;
+    }
+    if (hi - lo + 1 > n - unit) { u0 = 0; L = nun; return; }
+    const int lw = ((lo % n) + n) % n, hw = ((hi % n) + n) % n;
+    const int ul = lw / unit, uh = hw / unit;
+    u0 = ul;
+    L = ((uh - ul) % nun + nun) % nun + 1;
+}
+
+__device__ __forceinline__ int block_rank(bool pred, int &total, int *cnt4)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long bal = __ballot(pred);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) cnt4[wv] = __popcll(bal);
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wv; ++w) off += cnt4[w];
+    total = cnt4[0] + cnt4[1] + cnt4[2] + cnt4[3];
+    __syncthreads();
+    return off + before;
+}
+
+__global__ __launch_bounds__(256) void k_particles(DevSet s, int mode, int only)
+{
+    __shared__ double red[4][8];
+    __shared__ int cnt4[4];
+    const long long t = *s.tstep;
+    const int par = (int)(t & 1);
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+
+    if (b >= s.ptot) {
+        // probe plane reduction, one workgroup per (lattice, probe)
+        if (mode != 0) return;
+        const int q = b - s.ptot;
+        if (q >= s.nprobe_total) return;
+        int m = 0;
+        while (m + 1 < s.nmem && s.mem[m + 1].plist_off <= q) ++m;
+        while (s.mem[m].n_probe == 0 || q - s.mem[m].plist_off >= s.mem[m].n_probe) ++m;
+        const MemberDev *M = s.mem + m;
+        const int k = q - M->plist_off;
+        const int z = s.plist[M->plist_off + k];
+        const int tz = z / s.nzt, dz = z - tz * s.nzt;
+        const int ntile = M->ntx * M->nty;
+        double v[4] = {0, 0, 0, 0};
+        for (int c = tid; c < ntile; c += 256) {
+            const long long gt = M->tile_off + (long long)tz * ntile + c;
+            const double *pp = s.pprt + (gt * s.nzt + dz) * 4;
+            v[0] += pp[0]; v[1] += pp[1]; v[2] += pp[2]; v[3] += pp[3];
+        }
+        block_sum<4>(v, red);
+        if (tid == 0) {
+            double *o = s.ring + M->ring_off + ((t % s.ring_len) * M->n_probe + k) * 4;
+            o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+        }
+        return;
+    }
+
+    const int p = b;
+    const int m = s.pmem[p];
+    const MemberDev *M = s.mem + m;
+    if (p - M->p_off >= M->np) return;
+    if (only >= 0 && m != only) return;
+
+    const double *Xo = s.X[par], *Vo = s.V[par], *Wo = s.W[par];
+    const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
+    const double R = s.R[p];
+
+    // (1) hydrodynamic force and torque from the wavefront link slots
+    double hyd[6] = {0, 0, 0, 0, 0, 0};
+    if (mode == 0) {
+        const int bx = M->bx, rowh = 64 / bx;
+        int ux0, Lx, nux, uy0, Ly, nuy, uz0, Lz, nuz;
+        axis_units(X0, R, M->nx, bx, M->per[0], ux0, Lx, nux);
+        axis_units(X1, R, M->ny, rowh, M->per[1], uy0, Ly, nuy);
+        axis_units(X2, R, M->nz, s.nzt, M->per[2], uz0, Lz, nuz);
+        const int tot = Lx * Ly * Lz;
+        for (int c = tid; c < tot; c += 256) {
+            const int cx = c % Lx, cr = c / Lx, cy = cr % Ly, cz = cr / Ly;
+            int ux = ux0 + cx; if (ux >= nux) ux -= nux;
+            int uy = uy0 + cy; if (uy >= nuy) uy -= nuy;
+            int uz = uz0 + cz; if (uz >= nuz) uz -= nuz;
+            const long long gt = M->tile_off + ((long long)uz * M->nty + (uy >> 2)) * M->ntx + ux;
+            const long long WT = gt * 4 + (uy & 3);
+            const int cnt = s.wcnt[WT];
+            for (int k = 0; k < cnt; ++k) {
+                if (s.wpid[WT * kWaveSlots + k] == p) {
+                    const double *w6 = s.wval + (WT * kWaveSlots + k) * 6;
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) hyd[e] += w6[e];
+                }
+            }
+        }
+        block_sum<6>(hyd, red);
+    }
+
+    // (2) contacts, near-neighbour list, tangential history
+    const int q0 = M->p_off, nq = M->np;
+    const double E = M->E, nu = M->nu, mu = M->mu;
+    const int *hjo = s.hj[par] + (long long)p * kHistCap;
+    const double *hfo = s.hf[par] + (long long)p * kHistCap * 3;
+    const int hno = s.hn[par][p];
+    int *hjn = s.hj[par ^ 1] + (long long)p * kHistCap;
+    double *hfn = s.hf[par ^ 1] + (long long)p * kHistCap * 3;
+    double con[6] = {0, 0, 0, 0, 0, 0};
+    int near_total = 0, hist_total = 0;
+    for (int base = 0; base < nq; base += 256) {
+        const int jj = base + tid;
+        const int q = q0 + jj;
+        bool isnear = false, keep = false;
+        double ftn[3] = {0, 0, 0};
+        if (jj < nq && q != p) {
+            const double Y0 = Xo[3 * q], Y1 = Xo[3 * q + 1], Y2 = Xo[3 * q + 2], Rq = s.R[q];
+            const double d0 = mimg(Y0 - X0, M->per[0], M->box[0]);
+            const double d1 = mimg(Y1 - X1, M->per[1], M->box[1]);
+            const double d2 = mimg(Y2 - X2, M->per[2], M->box[2]);
+            const double dist = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+            isnear = dist <= R + Rq + kNearMargin;
+            const double un = R + Rq - dist;
+            if (mode == 0 && un > 0.0) {
+                // Eq. (fdLawn): Hertz normal force, pushing p away from q
+                const double n0 = d0 / dist, n1 = d1 / dist, n2 = d2 / dist;
+                const double rstar = 1.0 / (1.0 / R + 1.0 / Rq);
+                const double fn = 2.0 * E * un * sqrt(rstar * un) / (3.0 * (1.0 - nu * nu));
+                con[0] += -fn * n0; con[1] += -fn * n1; con[2] += -fn * n2;
+                if (mu > 0.0) {
+                    // Eq. (fdLaws): incremental Mindlin spring, Coulomb cap
+                    double fo[3] = {0, 0, 0};
+                    for (int h = 0; h < hno; ++h)
+                        if (hjo[h] == q) { fo[0] = hfo[3 * h]; fo[1] = hfo[3 * h + 1]; fo[2] = hfo[3 * h + 2]; }
+                    const double a0 = (R - 0.5 * un) * n0, a1 = (R - 0.5 * un) * n1, a2 = (R - 0.5 * un) * n2;
+                    const double b0 = -(Rq - 0.5 * un) * n0, b1 = -(Rq - 0.5 * un) * n1, b2 = -(Rq - 0.5 * un) * n2;
+                    const double *Vq = Vo + 3 * q, *Wq = Wo + 3 * q, *Vp = Vo + 3 * p, *Wp = Wo + 3 * p;
+                    const double wa0 = Wp[1] * a2 - Wp[2] * a1, wa1 = Wp[2] * a0 - Wp[0] * a2, wa2 = Wp[0] * a1 - Wp[1] * a0;
+                    const double wb0 = Wq[1] * b2 - Wq[2] * b1, wb1 = Wq[2] * b0 - Wq[0] * b2, wb2 = Wq[0] * b1 - Wq[1] * b0;
+                    const double v0 = (Vp[0] + wa0) - (Vq[0] + wb0);
+                    const double v1 = (Vp[1] + wa1) - (Vq[1] + wb1);
+                    const double v2 = (Vp[2] + wa2) - (Vq[2] + wb2);
+                    const double vn = v0 * n0 + v1 * n1 + v2 * n2;
+                    const double fon = fo[0] * n0 + fo[1] * n1 + fo[2] * n2;
+                    const double kt = 2.0 * E * sqrt(rstar * un) / ((1.0 + nu) * (2.0 - nu));
+                    ftn[0] = (fo[0] - fon * n0) - kt * (v0 - vn * n0);
+                    ftn[1] = (fo[1] - fon * n1) - kt * (v1 - vn * n1);
+                    ftn[2] = (fo[2] - fon * n2) - kt * (v2 - vn * n2);
+                    const double fm = sqrt(ftn[0] * ftn[0] + ftn[1] * ftn[1] + ftn[2] * ftn[2]);
+                    if (fm > mu * fn) { const double sc = mu * fn / fm; ftn[0] *= sc; ftn[1] *= sc; ftn[2] *= sc; }
+                    con[0] += ftn[0]; con[1] += ftn[1]; con[2] += ftn[2];
+                    con[3] += a1 * ftn[2] - a2 * ftn[1];
+                    con[4] += a2 * ftn[0] - a0 * ftn[2];
+                    con[5] += a0 * ftn[1] - a1 * ftn[0];
+                    keep = true;
+                }
+            }
+        }
+        int tot = 0;
+        const int rk = block_rank(isnear, tot, cnt4);
+        if (isnear) {
+            const int slot = near_total + rk;
+            if (slot < kNearCap) s.nearl[(long long)p * kNearCap + slot] = q;
+            else atomicOr(s.flags, 0x2u);
+        }
+        near_total += tot;
+        if (mode == 0 && mu > 0.0) {
+            int ht = 0;
+            const int hr = block_rank(keep, ht, cnt4);
+            if (keep) {
+                const int slot = hist_total + hr;
+                if (slot < kHistCap) {
+                    hjn[slot] = q;
+                    hfn[3 * slot] = ftn[0]; hfn[3 * slot + 1] = ftn[1]; hfn[3 * slot + 2] = ftn[2];
+                } else {
+                    atomicOr(s.flags, 0x8u);
+                }
+            }
+            hist_total += ht;
+        }
+    }
+    if (tid == 0) {
+        s.nnear[p] = min(near_total, kNearCap);
+        s.hn[par ^ 1][p] = min(hist_total, kHistCap);
+    }
+    if (mode != 0) return;
+    block_sum<6>(con, red);
+
+    // (3) Eqs. (coupleF), (coupleT), (translate), (rotate): symplectic Euler, dt = 1
+    if (tid == 0) {
+        double *ov = s.ovf + 6 * (long long)p;
+        double Fh[3], Th[3];
+        for (int a = 0; a < 3; ++a) {
+            Fh[a] = (hyd[a] + ov[a]) + s.Ph[3 * p + a];
+            Th[a] = (hyd[3 + a] + ov[3 + a]) + s.Lh[3 * p + a];
+            ov[a] = 0.0;
+            ov[3 + a] = 0.0;
+            s.Fh[3 * p + a] = Fh[a];
+            s.Th[3 * p + a] = Th[a];
+        }
+        double *Xn = s.X[par ^ 1], *Vn = s.V[par ^ 1], *Wn = s.W[par ^ 1];
+        const double Xc[3] = {X0, X1, X2};
+        if (s.fixed[p]) {
+            for (int a = 0; a < 3; ++a) { Xn[3 * p + a] = Xc[a]; Vn[3 * p + a] = 0.0; Wn[3 * p + a] = 0.0; }
+        } else {
+            const double mass = s.m[p], inert = s.I[p];
+            for (int a = 0; a < 3; ++a) {
+                const double Ft = (Fh[a] + s.Fg[3 * p + a]) + con[a];
+                const double Tt = Th[a] + con[3 + a];
+                const double v = Vo[3 * p + a] + Ft / mass;
+                Vn[3 * p + a] = v;
+                Wn[3 * p + a] = Wo[3 * p + a] + Tt / inert;
+                double x = Xc[a] + v;
+                if (M->per[a]) {
+                    if (x >= M->box[a]) x -= M->box[a];
+                    else if (x < 0.0) x += M->box[a];
+                }
+                Xn[3 * p + a] = x;
+                if (fabs(v) > 0.25) atomicOr(s.flags, 0x10u);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// re-projection kernel
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
+{
+    using S = typename Prec<P>::S;
+    __shared__ double red[4][8];
+    __shared__ double nb[kNearCap][4];
+    __shared__ int nbid[kNearCap];
+    const long long t = *s.tstep;
+    const int par = (int)(t & 1);
+    const int tid = threadIdx.x;
+    const int p = blockIdx.x;
+
+    bool active = p < s.ptot;
+    const MemberDev *M = nullptr;
+    if (active) {
+        const int m = s.pmem[p];
+        M = s.mem + m;
+        active = (p - M->p_off < M->np) && (only < 0 || m == only);
+    }
+    if (active) {
+        // positions after this step's motion (mode 0) or the current ones (mode 1)
+        const int sp = (mode == 1) ? par : (par ^ 1);
+        const double *Xs = s.X[sp], *Vs = s.V[sp], *Ws = s.W[sp];
+        const double X[3] = {Xs[3 * p], Xs[3 * p + 1], Xs[3 * p + 2]};
+        const double R = s.R[p], R2 = R * R;
+        const double Xr[3] = {mode == 1 ? X[0] : s.Xref[3 * p], mode == 1 ? X[1] : s.Xref[3 * p + 1],
+                              mode == 1 ? X[2] : s.Xref[3 * p + 2]};
+        const int nn = min(s.nnear[p], kNearCap);
+        if (tid < nn) {
+            const int q = s.nearl[(long long)p * kNearCap + tid];
+            nbid[tid] = q;
+            nb[tid][0] = Xs[3 * q]; nb[tid][1] = Xs[3 * q + 1]; nb[tid][2] = Xs[3 * q + 2];
+            nb[tid][3] = s.R[q];
+        }
+        __syncthreads();
+        double dmax = 0.0, disp2 = 0.0;
+        for (int k = 0; k < nn; ++k) {
+            const double d0 = mimg(nb[k][0] - X[0], M->per[0], M->box[0]);
+            const double d1 = mimg(nb[k][1] - X[1], M->per[1], M->box[1]);
+            const double d2 = mimg(nb[k][2] - X[2], M->per[2], M->box[2]);
+            dmax = fmax(dmax, R + nb[k][3] - sqrt((d0 * d0 + d1 * d1) + d2 * d2));
+        }
+        double xr[3];
+        for (int a = 0; a < 3; ++a) {
+            const double d = mimg(X[a] - Xr[a], M->per[a], M->box[a]);
+            disp2 += d * d;
+            xr[a] = X[a] - d; // reference centre unwrapped next to X
+        }
+        // a node can change owner only if |d_ref - R| <= displacement (membership) or
+        // it lies in an overlap lens of depth <= dmax (ordering between two spheres)
+        const double thr = sqrt(disp2) + dmax + 1e-9;
+        const bool scan = (mode == 1) || (thr >= s.margin[p]);
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        double mrg = kMarginCap;
+        if (scan) {
+            const int sn = par ^ 1; // population buffer holding f~(t+1)
+            S *Bn = (S *)(sn ? s.popB : s.popA) + M->pop_off;
+            const int *cur = s.own[par] + M->cell_off;
+            int *nxt = s.own[par ^ 1] + M->cell_off;
+            const int nc = (int)M->ncell;
+            const float rho_ff = (float)M->rho_f;
+            int lo[3], ext[3];
+            const int dims[3] = {M->nx, M->ny, M->nz};
+            for (int a = 0; a < 3; ++a) {
+                int l = (int)floor(fmin(X[a], xr[a]) - R) - 1;
+                int h = (int)ceil(fmax(X[a], xr[a]) + R) + 1;
+                if (!M->per[a]) { l = max(l, 0); h = min(h, dims[a] - 1); }
+                else if (h - l + 1 > dims[a]) { l = 0; h = dims[a] - 1; } // visit each node once
+                lo[a] = l;
+                ext[a] = max(h - l + 1, 0);
+            }
+            const int tot = ext[0] * ext[1] * ext[2];
+            for (int idx = tid; idx < tot; idx += 256) {
+                int ii = lo[0] + idx % ext[0];
+                int jj = lo[1] + (idx / ext[0]) % ext[1];
+                int kk = lo[2] + idx / (ext[0] * ext[1]);
+                if (ii < 0) ii += dims[0]; else if (ii >= dims[0]) ii -= dims[0];
+                if (jj < 0) jj += dims[1]; else if (jj >= dims[1]) jj -= dims[1];
+                if (kk < 0) kk += dims[2]; else if (kk >= dims[2]) kk -= dims[2];
+                const int cell = (kk * dims[1] + jj) * dims[0] + ii;
+                const double d2n = dist2(M, ii, jj, kk, X[0], X[1], X[2]);
+                mrg = fmin(mrg, fabs(sqrt(d2n) - R));
+                bool ev;
+                if (mode == 1) ev = d2n <= R2;
+                else ev = fabs(sqrt(dist2(M, ii, jj, kk, Xr[0], Xr[1], Xr[2])) - R) <= thr;
+                if (!ev) continue;
+                // owner: smallest d^2, then smallest index, among the spheres containing the node
+                int best = -1;
+                double bd = 0.0;
+                if (d2n <= R2) { best = p; bd = d2n; }
+                for (int k = 0; k < nn; ++k) {
+                    const double dq = dist2(M, ii, jj, kk, nb[k][0], nb[k][1], nb[k][2]);
+                    if (dq <= nb[k][3] * nb[k][3]) {
+                        const int q = nbid[k];
+                        if (best < 0 || dq < bd || (dq == bd && q < best)) { best = q; bd = dq; }
+                    }
+                }
+                if (mode == 1) {
+                    if (best >= 0) { s.own[0][M->cell_off + cell] = best; s.own[1][M->cell_off + cell] = best; }
+                    continue;
+                }
+                const int was = cur[cell];
+                if (best == was) continue;
+                nxt[cell] = best;
+                const int slot = atomicAdd(s.chgcnt + par, 1);
+                if (slot < s.chg_cap) {
+                    s.chg[par][2 * slot] = (int)(M->cell_off + cell);
+                    s.chg[par][2 * slot + 1] = best;
+                } else {
+                    atomicOr(s.flags, 0x4u);
+                }
+                const double r0 = mimg((double)ii - X[0], M->per[0], M->box[0]);
+                const double r1 = mimg((double)jj - X[1], M->per[1], M->box[1]);
+                const double r2 = mimg((double)kk - X[2], M->per[2], M->box[2]);
+                if (was < 0 && best == p) {
+                    // Eq. (convertFS): a covered node hands its momentum to the particle
+                    double f[kQ];
+#pragma unroll
+                    for (int d = 0; d < kQ; ++d) f[d] = (double)ld<P>(Bn, d * nc + cell, d, rho_ff);
+                    double rho, j0, j1, j2;
+                    moments<double>(f, rho, j0, j1, j2);
+                    acc[0] += j0; acc[1] += j1; acc[2] += j2;
+                    acc[3] += r1 * j2 - r2 * j1;
+                    acc[4] += r2 * j0 - r0 * j2;
+                    acc[5] += r0 * j1 - r1 * j0;
+                } else if (was == p && best < 0) {
+                    // Eq. (convertSF): an uncovered node is refilled with f^eq(rho_bar, V_b)
+                    // and takes rho_bar V_b from the particle; rho_bar averages the
+                    // neighbours that are fluid before and after the re-projection
+                    double sum = 0.0;
+                    int cnt = 0;
+#pragma unroll 1
+                    for (int e = 0; e < kQ - 1; ++e) {
+                        int c[3] = {ii + kCX[e], jj + kCY[e], kk + kCZ[e]};
+                        bool ok = true;
+                        for (int a = 0; a < 3; ++a) {
+                            if (c[a] < 0 || c[a] >= dims[a]) {
+                                if (M->per[a]) c[a] = c[a] < 0 ? c[a] + dims[a] : c[a] - dims[a];
+                                else ok = false;
+                            }
+                        }
+                        if (!ok) continue;
+                        const int yc = (c[2] * dims[1] + c[1]) * dims[0] + c[0];
+                        if (cur[yc] >= 0) continue;
+                        bool inside = dist2(M, c[0], c[1], c[2], X[0], X[1], X[2]) <= R2;
+                        for (int k = 0; k < nn && !inside; ++k)
+                            inside = dist2(M, c[0], c[1], c[2], nb[k][0], nb[k][1], nb[k][2]) <= nb[k][3] * nb[k][3];
+                        if (inside) continue;
+                        double rr = 0.0;
+                        for (int d = 0; d < kQ; ++d) rr += (double)ld<P>(Bn, d * nc + yc, d, rho_ff);
+                        sum += rr;
+                        cnt += 1;
+                    }
+                    const double rbar = cnt > 0 ? sum / cnt : M->rho_f;
+                    const double *Vp = Vs + 3 * p, *Wp = Ws + 3 * p;
+                    const double vb0 = Vp[0] + (Wp[1] * r2 - Wp[2] * r1);
+                    const double vb1 = Vp[1] + (Wp[2] * r0 - Wp[0] * r2);
+                    const double vb2 = Vp[2] + (Wp[0] * r1 - Wp[1] * r0);
+                    const double uu = vb0 * vb0 + vb1 * vb1 + vb2 * vb2;
+#pragma unroll
+                    for (int d = 0; d < kQ; ++d)
+                        st<P>(Bn, d * nc + cell, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
+                    const double m0 = rbar * vb0, m1 = rbar * vb1, m2 = rbar * vb2;
+                    acc[0] -= m0; acc[1] -= m1; acc[2] -= m2;
+                    acc[3] -= r1 * m2 - r2 * m1;
+                    acc[4] -= r2 * m0 - r0 * m2;
+                    acc[5] -= r0 * m1 - r1 * m0;
+                }
+            }
+            // margin: distance of the closest node to the sphere surface
+            double mv = wave_min_d(mrg);
+            if ((tid & 63) == 0) red[tid >> 6][7] = mv;
+            __syncthreads();
+            if (tid == 0) {
+                mv = fmin(fmin(red[0][7], red[1][7]), fmin(red[2][7], red[3][7]));
+                s.margin[p] = mv;
+                s.Xref[3 * p] = X[0]; s.Xref[3 * p + 1] = X[1]; s.Xref[3 * p + 2] = X[2];
+            }
+            __syncthreads();
+            if (mode == 0) block_sum<6>(acc, red);
+        }
+        if (mode == 0 && tid == 0) {
+            for (int a = 0; a < 3; ++a) { s.Ph[3 * p + a] = acc[a]; s.Lh[3 * p + a] = acc[3 + a]; }
+        }
+    }
+    if (mode == 0) {
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            const unsigned v = atomicAdd(s.k3done, 1u);
+            if (v == gridDim.x - 1) {
+                *s.k3done = 0u;
+                *s.tstep = t + 1;
+                __threadfence();
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initial populations f = w_d rho_f in both buffers
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_init_pops(DevSet s, long long total_cells)
+{
+    using S = typename Prec<P>::S;
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= total_cells) return;
+    int lo = 0, hi = s.nmem - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.mem[mid].cell_off <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    const MemberDev *M = s.mem + lo;
+    const int cell = (int)(c - M->cell_off);
+    const int nc = (int)M->ncell;
+    S *A = (S *)s.popA + M->pop_off, *B = (S *)s.popB + M->pop_off;
+    const float rho_ff = (float)M->rho_f;
+    for (int d = 0; d < kQ; ++d) {
+        const typename Prec<P>::C v = (typename Prec<P>::C)(kWd[d] * M->rho_f);
+        st<P>(A, d * nc + cell, d, v, rho_ff);
+        st<P>(B, d * nc + cell, d, v, rho_ff);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void *fluid_kernel_ptr(int prec)
+{
+    switch (prec) {
+    case PREC_FP64: return (void *)&k_fluid<PREC_FP64>;
+    case PREC_FP32: return (void *)&k_fluid<PREC_FP32>;
+    case PREC_FP16DEV: return (void *)&k_fluid<PREC_FP16DEV>;
+    default: return (void *)&k_fluid<PREC_BF16DEV>;
+    }
+}
+void *particles_kernel_ptr() { return (void *)&k_particles; }
+void *remap_kernel_ptr_prec(int prec)
+{
+    switch (prec) {
+    case PREC_FP64: return (void *)&k_remap<PREC_FP64>;
+    case PREC_FP32: return (void *)&k_remap<PREC_FP32>;
+    case PREC_FP16DEV: return (void *)&k_remap<PREC_FP16DEV>;
+    default: return (void *)&k_remap<PREC_BF16DEV>;
+    }
+}
+int particles_grid(const DevSet &s) { return max(s.ptot + s.nprobe_total, 1); }
+int remap_grid(const DevSet &s) { return max(s.ptot, 1); }
+
+hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st)
+{
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL(k_fluid<PREC_FP64>, dim3(s.tiles_total), dim3(256), 0, st, s); break;
+    case PREC_FP32: hipLaunchKernelGGL(k_fluid<PREC_FP32>, dim3(s.tiles_total), dim3(256), 0, st, s); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL(k_fluid<PREC_FP16DEV>, dim3(s.tiles_total), dim3(256), 0, st, s); break;
+    default: hipLaunchKernelGGL(k_fluid<PREC_BF16DEV>, dim3(s.tiles_total), dim3(256), 0, st, s); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_particles(const DevSet &s, int mode, int only_member, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_particles, dim3(particles_grid(s)), dim3(256), 0, st, s, mode, only_member);
+    return hipGetLastError();
+}
+
+hipError_t launch_remap_prec(int prec, const DevSet &s, int mode, int only_member, hipStream_t st)
+{
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL(k_remap<PREC_FP64>, dim3(remap_grid(s)), dim3(256), 0, st, s, mode, only_member); break;
+    case PREC_FP32: hipLaunchKernelGGL(k_remap<PREC_FP32>, dim3(remap_grid(s)), dim3(256), 0, st, s, mode, only_member); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL(k_remap<PREC_FP16DEV>, dim3(remap_grid(s)), dim3(256), 0, st, s, mode, only_member); break;
+    default: hipLaunchKernelGGL(k_remap<PREC_BF16DEV>, dim3(remap_grid(s)), dim3(256), 0, st, s, mode, only_member); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init_pops(int prec, const DevSet &s, long long total_cells, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((total_cells + 255) / 256);
+    if (grid == 0) return hipSuccess;
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL(k_init_pops<PREC_FP64>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
+    case PREC_FP32: hipLaunchKernelGGL(k_init_pops<PREC_FP32>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL(k_init_pops<PREC_FP16DEV>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
+    default: hipLaunchKernelGGL(k_init_pops<PREC_BF16DEV>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
+    }
+    return hipGetLastError();
+}
+
+} // namespace lbdem

@@ -1,0 +1,256 @@
+"""ctypes binding of the C interface in ``include/lbdem.h``.
+
+Argument marshalling only: every step of the coupled lattice-Boltzmann / DEM method runs
+in the HIP kernels of ``liblbdem.so``.  PyTorch supplies the device workspace (one
+``torch.uint8`` allocation) and the HIP stream (torch's current stream).  The library
+must have been built (``paper_1808_08921_amd.build``); a missing library raises, there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbdem.so")
+
+OK, EINVAL, EDEVICE, ECAPACITY, ENOMEM, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5, -6
+PERIODIC, WALL, PRESSURE = 0, 1, 2
+WAVE_NONE, WAVE_SINE, WAVE_COSINE, WAVE_STEP = 0, 1, 2, 3
+FP64, FP32, FP16DEV, BF16DEV = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16DEV, "fp16dev": FP16DEV, "bf16": BF16DEV, "bf16dev": BF16DEV}
+MAX_PROBES = 64
+
+STATUS_WAVE_SLOT_OVERFLOW = 0x1
+STATUS_NEAR_OVERFLOW = 0x2
+STATUS_CHANGE_OVERFLOW = 0x4
+STATUS_HISTORY_OVERFLOW = 0x8
+STATUS_TOO_FAST = 0x10
+STATUS_NODE_SLOT_OVERFLOW = 0x20
+
+
+class LbdemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbdem error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("face_bc", ctypes.c_int32 * 6),
+        ("tau", ctypes.c_double), ("rho_f", ctypes.c_double),
+        ("wave", ctypes.c_int32), ("rho_amp", ctypes.c_double), ("omega", ctypes.c_double),
+        ("t_n", ctypes.c_int64),
+        ("young_E", ctypes.c_double), ("poisson_nu", ctypes.c_double), ("friction_mu", ctypes.c_double),
+        ("rho_p", ctypes.c_double),
+        ("n_probe", ctypes.c_int32), ("probe_z", ctypes.c_int32 * MAX_PROBES),
+        ("max_particles", ctypes.c_int32),
+    ]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("probe_ring", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("z_per_thread", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbdem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1808_08921_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, VP, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.lbdem_last_error.restype = ctypes.c_char_p
+        L.lbdem_default_config.argtypes = [ctypes.POINTER(Config)]
+        L.lbdem_workspace_size.argtypes = [I32, ctypes.POINTER(Params), ctypes.POINTER(Config), ctypes.POINTER(SZ)]
+        L.lbdem_create.argtypes = [I32, ctypes.POINTER(Params), ctypes.POINTER(Config), VP, SZ, VP, ctypes.POINTER(P)]
+        L.lbdem_destroy.argtypes = [P]
+        L.lbdem_set_stream.argtypes = [P, VP]
+        L.lbdem_particles_set.argtypes = [P, I32, I32, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_uint8)]
+        L.lbdem_particles_get.argtypes = [P, I32, I32, dp, dp, dp, dp, dp]
+        L.lbdem_step.argtypes = [P, I64]
+        L.lbdem_time.argtypes = [P, ctypes.POINTER(I64)]
+        L.lbdem_synchronize.argtypes = [P]
+        L.lbdem_status.argtypes = [P, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int]
+        L.lbdem_probe_read.argtypes = [P, I32, I64, I64, dp]
+        L.lbdem_populations_get.argtypes = [P, I32, dp]
+        L.lbdem_populations_set.argtypes = [P, I32, dp]
+        L.lbdem_owner_get.argtypes = [P, I32, ctypes.POINTER(ctypes.c_int32)]
+        L.lbdem_timing_enable.argtypes = [P, ctypes.c_int]
+        L.lbdem_timing_read.argtypes = [P, dp, ctypes.POINTER(I64)]
+        L.lbdem_tile_info.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        for name in ("lbdem_default_config", "lbdem_workspace_size", "lbdem_create", "lbdem_destroy",
+                     "lbdem_set_stream", "lbdem_particles_set", "lbdem_particles_get", "lbdem_step", "lbdem_time",
+                     "lbdem_synchronize", "lbdem_status", "lbdem_probe_read", "lbdem_populations_get",
+                     "lbdem_populations_set", "lbdem_owner_get", "lbdem_timing_enable", "lbdem_timing_read",
+                     "lbdem_tile_info"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise LbdemError(rc, lib().lbdem_last_error().decode())
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
+
+
+def make_params(nx, ny, nz, tau=1.0, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), wave=WAVE_NONE, amp=0.0, omega=0.0,
+                t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=1.0, probe_z=(), max_particles=0, **_ignored):
+    p = Params()
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    for k in range(6):
+        p.face_bc[k] = int(bc[k])
+    p.tau, p.rho_f = float(tau), float(rho_f)
+    p.wave, p.rho_amp, p.omega, p.t_n = int(wave), float(amp), float(omega), int(t_n)
+    p.young_E, p.poisson_nu, p.friction_mu, p.rho_p = float(E), float(nu), float(mu), float(rho_p)
+    pz = list(probe_z)
+    if len(pz) > MAX_PROBES:
+        raise ValueError("too many probe planes")
+    p.n_probe = len(pz)
+    for k, z in enumerate(pz):
+        p.probe_z[k] = int(z)
+    p.max_particles = int(max_particles)
+    return p
+
+
+class LatticeSet:
+    """A set of lattices advanced together on one GPU (one lattice, or a batched ensemble).
+
+    ``lattices``: list of dicts with the keys of :func:`make_params`.
+    """
+
+    def __init__(self, lattices, precision="fp32", probe_ring=4096, tile_x=0, z_per_thread=0, graph_steps=8,
+                 device="cuda"):
+        import torch
+
+        self._torch = torch
+        L = lib()
+        n = len(lattices)
+        arr = (Params * n)()
+        for k, d in enumerate(lattices):
+            arr[k] = make_params(**d)
+        self.shapes = [(d["nz"], d["ny"], d["nx"]) for d in lattices]
+        self.n_probe = [len(d.get("probe_z", ())) for d in lattices]
+        self.n_particles = [0] * n
+        cfg = Config()
+        _check(L.lbdem_default_config(ctypes.byref(cfg)))
+        cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        cfg.probe_ring, cfg.tile_x, cfg.z_per_thread, cfg.graph_steps = probe_ring, tile_x, z_per_thread, graph_steps
+        nbytes = ctypes.c_size_t()
+        _check(L.lbdem_workspace_size(n, arr, ctypes.byref(cfg), ctypes.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self.device = torch.device(device)
+        self._ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        self._stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(L.lbdem_create(n, arr, ctypes.byref(cfg), ctypes.c_void_p(self._ws.data_ptr()), nbytes.value,
+                              ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._arr = arr
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().lbdem_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def particles_set(self, lattice, x, radius, v=None, w=None, fg=None, fixed=None):
+        x = _f64(x, (-1, 3))
+        n = x.shape[0]
+        r = _f64(radius, (n,))
+        v = None if v is None else _f64(v, (n, 3))
+        w = None if w is None else _f64(w, (n, 3))
+        fg = None if fg is None else _f64(fg, (n, 3))
+        fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, dtype=np.uint8).reshape(n))
+        fxp = None if fx is None else fx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        _check(lib().lbdem_particles_set(self._h, lattice, n, _dp(x), _dp(v), _dp(w), _dp(r), _dp(fg), fxp))
+        self.n_particles[lattice] = n
+
+    def particles_get(self, lattice):
+        n = self.n_particles[lattice]
+        out = {k: np.zeros((n, 3)) for k in ("x", "v", "w", "force", "torque")}
+        _check(lib().lbdem_particles_get(self._h, lattice, n, *[_dp(out[k]) for k in ("x", "v", "w", "force", "torque")]))
+        return out
+
+    def step(self, n=1):
+        _check(lib().lbdem_step(self._h, int(n)))
+
+    def synchronize(self):
+        _check(lib().lbdem_synchronize(self._h))
+
+    @property
+    def t(self):
+        t = ctypes.c_int64()
+        _check(lib().lbdem_time(self._h, ctypes.byref(t)))
+        return t.value
+
+    def status(self, clear=False):
+        b = ctypes.c_uint32()
+        rc = lib().lbdem_status(self._h, ctypes.byref(b), 1 if clear else 0)
+        if rc not in (OK, ECAPACITY):
+            _check(rc)
+        return b.value
+
+    def probes(self, lattice, first=0, n=None):
+        if n is None:
+            n = self.t - first
+        out = np.zeros((n, max(self.n_probe[lattice], 1), 4))
+        _check(lib().lbdem_probe_read(self._h, lattice, int(first), int(n), _dp(out)))
+        return out[:, : self.n_probe[lattice], :]
+
+    def populations(self, lattice):
+        f = np.zeros((19,) + self.shapes[lattice])
+        _check(lib().lbdem_populations_get(self._h, lattice, _dp(f)))
+        return f
+
+    def set_populations(self, lattice, f):
+        f = _f64(f, (19,) + self.shapes[lattice])
+        _check(lib().lbdem_populations_set(self._h, lattice, _dp(f)))
+
+    def owner(self, lattice):
+        o = np.zeros(self.shapes[lattice], dtype=np.int32)
+        _check(lib().lbdem_owner_get(self._h, lattice, o.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return o
+
+    def timing_enable(self, on=True):
+        _check(lib().lbdem_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self):
+        ms = np.zeros(3)
+        cnt = np.zeros(3, dtype=np.int64)
+        _check(lib().lbdem_timing_read(self._h, _dp(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return ms, cnt
+
+    def tile_info(self, lattice=0):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbdem_tile_info(self._h, lattice, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value

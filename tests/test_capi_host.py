@@ -1,0 +1,90 @@
+"""Host-side checks of the C interface that need no GPU: the library loads, exports every
+function include/lbdem.h declares, and rejects invalid parameters before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbdem.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(lbdem_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lb():
+    from paper_1808_08921_amd import lbdem
+
+    if not os.path.exists(lbdem.LIB_PATH):
+        from paper_1808_08921_amd import build
+
+        build.build()
+    return lbdem
+
+
+def test_library_exports_every_declared_function(lb):
+    names = _declared()
+    assert len(names) >= 18
+    out = subprocess.run(["nm", "-D", "--defined-only", lb.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (lbdem_[a-z_]+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = lb.lib()
+    for n in names:
+        assert getattr(L, n) is not None
+
+
+def _size(lb, params, cfg=None):
+    arr = (lb.Params * len(params))(*params)
+    n = ctypes.c_size_t()
+    rc = lb.lib().lbdem_workspace_size(len(params), arr, None if cfg is None else ctypes.byref(cfg), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_size_and_validation(lb):
+    ok = lb.make_params(96, 96, 384, tau=1.0, bc=(0, 0, 0, 0, 2, 2), wave=lb.WAVE_COSINE, amp=1e-3, omega=0.0314,
+                        t_n=200, probe_z=range(0, 384, 16), max_particles=1024)
+    rc, n = _size(lb, [ok])
+    assert rc == lb.OK
+    # FP32 populations (2 x 19 x 4 B per cell) dominate the workspace
+    assert 2 * 19 * 4 * 96 * 96 * 384 < n < 1.3 * 2 * 19 * 4 * 96 * 96 * 384
+    bad = [
+        lb.make_params(8, 8, 8, tau=0.5),                         # tau must exceed 1/2
+        lb.make_params(8, 8, 8, bc=(0, 1, 0, 0, 0, 0)),            # periodic paired with a wall
+        lb.make_params(8, 8, 8, bc=(2, 2, 0, 0, 0, 0)),            # density faces only on z
+        lb.make_params(8, 8, 8, probe_z=(9,)),                     # probe outside
+        lb.make_params(8, 8, 8, probe_z=(3, 3)),                   # duplicate probe
+        lb.make_params(0, 8, 8),                                   # empty axis
+        lb.make_params(8, 8, 8, max_particles=-1),
+        lb.make_params(8, 8, 1, bc=(0, 0, 0, 0, 2, 2)),            # density faces need nz >= 2
+    ]
+    for p in bad:
+        rc, _ = _size(lb, [p])
+        assert rc == lb.EINVAL, lb.lib().lbdem_last_error()
+    assert lb.lib().lbdem_last_error().decode()
+    # a set of several lattices needs about the sum of their sizes
+    rc1, n1 = _size(lb, [lb.make_params(48, 48, 192, max_particles=256)])
+    rc2, n2 = _size(lb, [lb.make_params(48, 48, 192, max_particles=256)] * 3)
+    assert rc1 == rc2 == lb.OK and 2.9 * n1 < n2 < 3.1 * n1
+    # FP64 populations over 4 GiB per lattice are refused
+    cfg = lb.Config()
+    lb.lib().lbdem_default_config(ctypes.byref(cfg))
+    cfg.precision = lb.FP64
+    rc, _ = _size(lb, [lb.make_params(512, 512, 256)], cfg)
+    assert rc == lb.EINVAL
+    cfg.precision = 7
+    rc, _ = _size(lb, [ok], cfg)
+    assert rc == lb.EINVAL
+
+
+def test_null_arguments_are_rejected(lb):
+    L = lb.lib()
+    assert L.lbdem_step(None, 1) == lb.EINVAL
+    assert L.lbdem_synchronize(None) == lb.EINVAL
+    assert L.lbdem_destroy(None) == lb.OK
+    assert L.lbdem_default_config(None) == lb.EINVAL
