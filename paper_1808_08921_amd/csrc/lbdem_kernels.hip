@@ -151,16 +151,22 @@ __device__ __forceinline__ int dpp_i(int v, int old)
     return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xf, false);
 }
 
-// Sum over the 64 lanes in a fixed order; the total lands in lane 63.
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes in a fixed order, returned to every lane: DPP sums within each
+// row of 16 lanes, then the four row sums are added in row order.
 __device__ __forceinline__ double wave_sum(double v)
 {
     v += dpp_d<0xB1, 0xF>(v);  // quad_perm [1,0,3,2]
     v += dpp_d<0x4E, 0xF>(v);  // quad_perm [2,3,0,1]
     v += dpp_d<0x141, 0xF>(v); // row_half_mirror
     v += dpp_d<0x140, 0xF>(v); // row_mirror
-    v += dpp_d<0x142, 0xA>(v); // row_bcast:15 into rows 1, 3
-    v += dpp_d<0x143, 0xC>(v); // row_bcast:31 into rows 2, 3
-    return v;
+    return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
 }
 // Minimum over the 64 lanes, returned to every lane.
 __device__ __forceinline__ int wave_min(int v)
@@ -169,9 +175,8 @@ __device__ __forceinline__ int wave_min(int v)
     v = min(v, dpp_i<0x4E, 0xF>(v, v));
     v = min(v, dpp_i<0x141, 0xF>(v, v));
     v = min(v, dpp_i<0x140, 0xF>(v, v));
-    v = min(v, dpp_i<0x142, 0xA>(v, v));
-    v = min(v, dpp_i<0x143, 0xC>(v, v));
-    return __builtin_amdgcn_readlane(v, 63);
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 __device__ __forceinline__ double wave_min_d(double v)
 {
@@ -194,7 +199,7 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double (*red)[8])
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int c = 0; c < N; ++c) v[c] = wave_sum(v[c]);
-    if (lane == 63)
+    if (lane == 0)
 #pragma unroll
         for (int c = 0; c < N; ++c) red[wv][c] = v[c];
     __syncthreads();
