@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled D3Q19 lattice-Boltzmann / DEM step on one MI355X.
+
+Workload (the FCC wave-propagation case): a 4 x 4 x 16 FCC packing of 1024 spheres (cell
+edge 24 lu, touching radius plus a seed-jittered 1e-3 overlap) in a 96 x 96 x 384
+lattice, periodic in x and y, density inlet at z = 0 driven by a single-period cosine
+(amplitude 1e-3, period 200 steps), constant density at z = 383, probes every 16 lu,
+tau = 1, Hertz-Mindlin spheres with E* = 10.37, nu = 0.2, mu = 0, rho_p* = 2.466.
+
+One step = one pass of the whole coupled path (fluid kernel, particle kernel,
+re-projection kernel).  ``value`` is fluid-node updates per second (millions) over K
+timed steps with all data resident in HBM; ``roofline`` prices the fluid kernel's
+algorithmic bytes (19 populations read and written per fluid node) against 8 TB/s.
+The FP16 / BF16 deviation-storage variants and their errors against the FP64 path are
+reported beside it, and the FP64 CPU oracle is timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_VALUE = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _case(seed=0):
+    from paper_1808_08921_amd import inputs
+
+    params, pk = inputs.wave_fcc_case(seed=seed)
+    params["max_particles"] = len(pk["x"])
+    return params, pk
+
+
+def _make(params, pk, precision, graph_steps=8):
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    gs = LatticeSet([params], precision=precision, graph_steps=graph_steps, probe_ring=4096)
+    gs.particles_set(0, pk["x"], pk["radius"], fixed=pk["fixed"])
+    return gs
+
+
+def _fluid_nodes(gs):
+    return int((gs.owner(0) < 0).sum())
+
+
+def time_steps(gs, steps, warmup):
+    import torch
+
+    gs.step(warmup)
+    gs.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gs.step(steps)
+    gs.synchronize()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def kernel_times(gs, steps):
+    """Average duration of each kernel over `steps` eager steps, from HIP events recorded
+    on the library's stream around every launch."""
+    gs.timing_enable(True)
+    gs.step(steps)
+    ms, cnt = gs.timing_read()
+    gs.timing_enable(False)
+    return ms / np.maximum(cnt, 1)
+
+
+def arrival_velocity(probes, zs, tmax):
+    """P-wave speed from the arrival time of the peak cross-section momentum
+    sum(rho u_z)/sum(rho) at each probe plane (3-point parabolic refinement of the
+    argmax), fitted by least squares over the planes."""
+    mom = probes[:tmax, :, 2] / probes[:tmax, :, 3]
+    times = []
+    for k in range(mom.shape[1]):
+        s = mom[:, k]
+        i = int(np.argmax(s))
+        if 0 < i < len(s) - 1:
+            a, b, c = s[i - 1], s[i], s[i + 1]
+            den = a - 2 * b + c
+            i = i + (0.5 * (a - c) / den if den != 0 else 0.0)
+        times.append(i + 1.0)
+    slope = np.polyfit(np.asarray(times), np.asarray(zs, float), 1)[0]
+    return float(slope), times
+
+
+def precision_errors(params, pk, steps=900, planes=12):
+    """Error of each storage precision against the FP64 GPU path (itself checked against
+    the FP64 CPU oracle to 1e-10 by the test-suite) on the same workload."""
+    out = {}
+    ref = None
+    zs = list(params["probe_z"])[1:planes + 1]
+    for prec in ("fp64", "fp32", "fp16", "bf16"):
+        gs = _make(params, pk, prec, graph_steps=8)
+        vs = []
+        for _ in range(steps // 100):
+            gs.step(100)
+            vs.append(gs.particles_get(0)["v"])
+        probes = gs.probes(0, 0, steps)[:, 1:planes + 1, :]
+        vel, _ = arrival_velocity(probes, zs, steps)
+        vs = np.stack(vs)
+        gs.close()
+        if prec == "fp64":
+            ref = (vel, vs, probes)
+            out[prec] = {"p_wave_velocity": vel}
+            continue
+        rho_ref = ref[2][..., 1] / ref[2][..., 0]
+        rho = probes[..., 1] / probes[..., 0]
+        out[prec] = {
+            "p_wave_velocity": vel,
+            "p_wave_velocity_rel_err": abs(vel - ref[0]) / abs(ref[0]),
+            "particle_velocity_rel_err": float(np.linalg.norm(vs - ref[1]) / np.linalg.norm(ref[1])),
+            "probe_rho_prime_rel_err": float(np.abs(rho - rho_ref).max() / np.abs(rho_ref).max()),
+        }
+    return out
+
+
+def cpu_baseline(params, pk, budget_s=20.0):
+    """The FP64 oracle on the host (single thread) on the same workload: steps of the
+    full 96 x 96 x 384 lattice until about `budget_s` seconds have passed."""
+    import oracle
+
+    oracle.build()
+    p = params
+    s = oracle.Sim(p["nx"], p["ny"], p["nz"], tau=p["tau"], bc=p["bc"], wave=p["wave"], amp=p["amp"],
+                   omega=p["omega"], t_n=p["t_n"], E=p["E"], nu=p["nu"], mu=p["mu"], rho_p=p["rho_p"],
+                   probe_z=p["probe_z"])
+    s.set_particles(pk["x"], pk["radius"], fixed=pk["fixed"])
+    nfl = int((s.owner() < 0).sum())
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        s.step(1)
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 50:
+            break
+    dt = time.perf_counter() - t0
+    s.close()
+    return {"value": nfl * n / dt / 1e6, "unit": "MLUPS (fluid nodes)", "cores": 1, "kind": "oracle",
+            "sample": f"{n} full steps of the 96x96x384 FCC case (oracle, FP64, one host thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--kernel-steps", type=int, default=300, help="eager steps timed per kernel with HIP events")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip FP16/BF16 timing and the error study")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab decomposition is "
+              "a design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    params, pk = _case(seed=0)
+    results = {}
+    kt = None
+    nfl = None
+    for prec in (("fp32",) if args.no_variants else ("fp32", "fp16", "bf16")):
+        gs = _make(params, pk, prec)
+        if nfl is None:
+            nfl = _fluid_nodes(gs)
+        dt = time_steps(gs, args.steps, args.warmup)
+        k = kernel_times(gs, args.kernel_steps)
+        status = gs.status()
+        gs.close()
+        torch.cuda.empty_cache()
+        results[prec] = {"ms_per_step": 1e3 * dt / args.steps, "mlups": nfl * args.steps / dt / 1e6,
+                         "kernel_ms": [float(x) for x in k], "status": status}
+        _log(f"{prec}: {results[prec]}")
+        if prec == "fp32":
+            kt = k
+    ncell = params["nx"] * params["ny"] * params["nz"]
+    r32 = results["fp32"]
+    alg_bytes = 2 * 19 * BYTES_PER_VALUE["fp32"] * nfl
+    achieved = alg_bytes / (kt[2] * 1e-3) / 1e9
+    line = {
+        "metric": "coupled D3Q19 MLUPS + % HBM roofline; FP16-stored vs FP32 at stated error",
+        "value": r32["mlups"],
+        "unit": "MLUPS (fluid-node updates/s, millions)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "FCC wave propagation, 4x4x16 FCC cells, 1024 spheres, 96x96x384 D3Q19, FP32 "
+                               "populations, cosine inlet 1e-3 / 200 steps, probes every 16 lu",
+                   "cells": ncell, "fluid_nodes": nfl, "solid_fraction": 1 - nfl / ncell,
+                   "mlups_all_cells": ncell * args.steps / (r32["ms_per_step"] * 1e-3 * args.steps) / 1e6,
+                   "kernel_ms": {"links": kt[0], "motion": kt[1], "fluid": kt[2], "remap": kt[3]}},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_fluid<FP32>", "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_variants:
+        line["variants"] = {}
+        for prec in ("fp16", "bf16"):
+            r = results[prec]
+            ab = 2 * 19 * BYTES_PER_VALUE[prec] * nfl
+            line["variants"][prec] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"],
+                                      "speedup_vs_fp32": r32["ms_per_step"] / r["ms_per_step"],
+                                      "fluid_kernel_ms": r["kernel_ms"][2],
+                                      "fluid_kernel_speedup_vs_fp32": kt[2] / r["kernel_ms"][2],
+                                      "roofline_frac": ab / (r["kernel_ms"][2] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        _log("error study against the FP64 path")
+        line["errors_vs_fp64"] = precision_errors(params, pk)
+    if not args.no_cpu:
+        _log("CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(params, pk)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

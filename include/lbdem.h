@@ -66,12 +66,11 @@ extern "C" {
 #define LBDEM_MAX_PROBES 64
 
 /* status bits returned by lbdem_status */
-#define LBDEM_STATUS_WAVE_SLOT_OVERFLOW 0x1u /* link partials spilled to atomics (results valid, order not fixed) */
 #define LBDEM_STATUS_NEAR_OVERFLOW 0x2u      /* a particle had more near neighbours than the table holds (error) */
 #define LBDEM_STATUS_CHANGE_OVERFLOW 0x4u    /* node-change list spilled; a full map copy was used (results valid) */
 #define LBDEM_STATUS_HISTORY_OVERFLOW 0x8u   /* tangential contact history table full (error) */
 #define LBDEM_STATUS_TOO_FAST 0x10u          /* a particle moved more than 0.25 lu in one step (error) */
-#define LBDEM_STATUS_NODE_SLOT_OVERFLOW 0x20u /* a fluid node touched more particles than its slots (results valid) */
+#define LBDEM_STATUS_SHELL_OVERFLOW 0x40u    /* a particle's surface-shell table overflowed (error) */
 
 /* One lattice and its physics (Sec. 2; Table 1 "tab:params" for the FCC runs). */
 typedef struct lbdem_params {
@@ -90,6 +89,7 @@ typedef struct lbdem_params {
     int32_t n_probe;         /* number of probe planes (0..LBDEM_MAX_PROBES) */
     int32_t probe_z[LBDEM_MAX_PROBES]; /* z index of each probe plane */
     int32_t max_particles;   /* particle capacity of this lattice (>= 0) */
+    double max_radius;       /* largest particle radius this lattice will hold (sizes per-particle tables) */
 } lbdem_params;
 
 /* Settings shared by all lattices of a set. */
@@ -137,7 +137,7 @@ int lbdem_set_stream(lbdem_set *set, void *hip_stream);
  * constant external force added in Eq. translate); radius is n; fixed is n (1 = the
  * particle never moves and has V = Omega = 0).  v, w, fg and fixed may be NULL (zeros).
  * Populations are not modified.  Errors: LBDEM_EINVAL when n exceeds max_particles, a
- * radius is not positive, a centre lies outside a non-periodic extent, or a periodic
+ * radius is not positive or exceeds max_radius, a centre lies outside a non-periodic extent, or a periodic
  * axis is shorter than 2 R + 4. */
 int lbdem_particles_set(lbdem_set *set, int32_t lattice, int32_t n, const double *x, const double *v,
                         const double *w, const double *radius, const double *fg, const uint8_t *fixed);
@@ -149,11 +149,11 @@ int lbdem_particles_set(lbdem_set *set, int32_t lattice, int32_t n, const double
 int lbdem_particles_get(lbdem_set *set, int32_t lattice, int32_t n, double *x, double *v, double *w,
                         double *force, double *torque);
 
-/* Queue nsteps coupled time steps of every lattice of the set.  Each step: pull
- * streaming with moving-surface bounce-back and link forces, the density faces, BGK
- * collision and probes (one fused kernel); link-force finalisation, contacts and
- * symplectic-Euler motion (one kernel); re-projection with refill / emptying (one
- * kernel).  Asynchronous; errors found on the device are reported by lbdem_status. */
+/* Queue nsteps coupled time steps of every lattice of the set.  Each step: the links of
+ * every particle (moving-surface bounce-back values and link forces); contacts and
+ * symplectic-Euler motion of the particles; pull streaming, density faces, BGK collision
+ * and probes (one fused kernel); re-projection with refill / emptying.  Asynchronous;
+ * errors found on the device are reported by lbdem_status. */
 int lbdem_step(lbdem_set *set, int64_t nsteps);
 
 /* Number of steps taken so far (synchronises). */
@@ -186,8 +186,9 @@ int lbdem_owner_get(lbdem_set *set, int32_t lattice, int32_t *owner);
 
 /* Kernel timing with HIP events on the set's stream.  While enabled, lbdem_step launches
  * kernels one by one and brackets every launch with a pair of events.  lbdem_timing_read
- * synchronises and returns, for kernel k = 0 (fluid), 1 (particles), 2 (re-projection),
- * the summed milliseconds ms[k] and the number of launches count[k] since enabling. */
+ * synchronises and returns, for kernel k = 0 (links), 1 (particle motion), 2 (fluid),
+ * 3 (re-projection), the summed milliseconds ms[k] and the number of launches count[k]
+ * since enabling (ms and count hold 4 entries). */
 int lbdem_timing_enable(lbdem_set *set, int enable);
 int lbdem_timing_read(lbdem_set *set, double *ms, int64_t *count);
 

@@ -72,6 +72,7 @@ struct Geometry {
     int nzt = 4;
     int ring_len = 1;
     int chg_cap = 0;
+    int lcap = 1;
     int prec = PREC_FP32;
 };
 
@@ -113,6 +114,8 @@ int validate(int32_t n, const lbdem_params *lat, const lbdem_config *cfg)
                 if (p.probe_z[k2] == p.probe_z[k]) return fail(LBDEM_EINVAL, "lattice %d: duplicate probe plane", m);
         }
         if (p.max_particles < 0 || p.max_particles > (1 << 20)) return fail(LBDEM_EINVAL, "lattice %d: max_particles", m);
+        if (p.max_particles > 0 && !(p.max_radius > 0.0 && p.max_radius < 1024.0))
+            return fail(LBDEM_EINVAL, "lattice %d: max_radius must be positive when particles are allowed", m);
         if (!(p.young_E >= 0.0) || !(p.poisson_nu > -1.0 && p.poisson_nu < 1.0) || !(p.friction_mu >= 0.0) ||
             !(p.rho_p > 0.0))
             return fail(LBDEM_EINVAL, "lattice %d: material constants out of range", m);
@@ -191,6 +194,15 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
     G.wave_doubles = wave;
     G.pz = pz;
     G.chg_cap = (int)std::min<long long>(std::max<long long>(65536, 256LL * pt), 1LL << 26);
+    // shell-list capacity: lattice nodes with -kShell < d - R <= sqrt(2) + kShell are within
+    // the shell thickened by half a cell diagonal on both sides
+    double rmax = 0.0;
+    for (int m = 0; m < n; ++m)
+        if (lat[m].max_particles > 0) rmax = std::max(rmax, lat[m].max_radius);
+    if (rmax > 0.0) {
+        const double ro = rmax + std::sqrt(2.0) + kShell + 0.8661, ri = std::max(0.0, rmax - kShell - 0.8661);
+        G.lcap = (int)std::ceil(4.0 / 3.0 * M_PI * (ro * ro * ro - ri * ri * ri)) + 64;
+    }
 }
 
 // Lays out (or sizes, when base is null) every device buffer; fills the pointers of s.
@@ -212,9 +224,6 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.chg[0] = c.take<int>(2 * (size_t)G.chg_cap);
     s.chg[1] = c.take<int>(2 * (size_t)G.chg_cap);
     s.chgcnt = c.take<int>(2);
-    s.wcnt = c.take<int>((size_t)G.tiles * 4);
-    s.wpid = c.take<int>((size_t)G.tiles * 4 * kWaveSlots);
-    s.wval = c.take<double>((size_t)G.tiles * 4 * kWaveSlots * 6);
     s.pprt = c.take<double>((size_t)G.tiles * G.nzt * 4);
     s.ring = c.take<double>(G.ring_doubles);
     s.ring_len = G.ring_len;
@@ -238,18 +247,23 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.Lh = c.take<double>(3 * (size_t)P);
     s.Xref = c.take<double>(3 * (size_t)P);
     s.margin = c.take<double>(P);
-    s.ovf = c.take<double>(6 * (size_t)P);
     s.fixed = c.take<int>(P);
     s.pmem = c.take<int>(P);
+    s.ppart = c.take<double>((size_t)P * kChunks * 6);
     s.nearl = c.take<int>((size_t)P * kNearCap);
     s.nnear = c.take<int>(P);
+    s.lcap = G.lcap;
+    s.lcell = c.take<int>((size_t)P * G.lcap);
+    s.ldr = c.take<float>((size_t)P * G.lcap);
+    s.lmask = c.take<unsigned>((size_t)P * G.lcap);
+    s.lcnt = c.take<int>(P);
     for (int k = 0; k < 2; ++k) {
         s.hj[k] = c.take<int>((size_t)P * kHistCap);
         s.hf[k] = c.take<double>((size_t)P * kHistCap * 3);
         s.hn[k] = c.take<int>(P);
     }
     s.tstep = c.take<long long>(1);
-    s.k3done = c.take<unsigned int>(1);
+    s.tcopy = c.take<long long>(1);
     s.flags = c.take<unsigned int>(1);
     return (c.off + 255) & ~size_t(255);
 }
@@ -274,6 +288,8 @@ const double kWh[kQ] = {1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 
                         1.0 / 36, 1.0 / 36, 1.0 / 3};
 const float kInvWh[kQ] = {18, 18, 18, 18, 18, 18, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 3};
 
+constexpr int kKernels = 4; // links, motion, fluid, re-projection
+
 } // namespace
 
 struct lbdem_set {
@@ -292,9 +308,9 @@ struct lbdem_set {
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, int>> ev_pending[3];
-    double ms_acc[3] = {0, 0, 0};
-    int64_t ms_cnt[3] = {0, 0, 0};
+    std::vector<std::pair<int, int>> ev_pending[kKernels];
+    double ms_acc[kKernels] = {0, 0, 0, 0};
+    int64_t ms_cnt[kKernels] = {0, 0, 0, 0};
     size_t ev_next = 0;
 };
 
@@ -329,17 +345,20 @@ int build_graph(lbdem_set *S, int steps)
     hipGraphNode_t prev = nullptr;
     for (int k = 0; k < steps; ++k) {
         hipKernelNodeParams kp{};
-        hipGraphNode_t n1, n2, n3;
-        kp.func = fluid_kernel_ptr(S->G.prec);
-        kp.gridDim = dim3(S->ds.tiles_total);
+        hipGraphNode_t n0, n1, n2, n3;
         kp.blockDim = dim3(256);
         kp.sharedMemBytes = 0;
-        kp.kernelParams = fluid_args;
         kp.extra = nullptr;
-        HIPCHK(hipGraphAddKernelNode(&n1, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
-        kp.func = particles_kernel_ptr();
-        kp.gridDim = dim3(particles_grid(S->ds));
+        kp.func = links_kernel_ptr(S->G.prec);
+        kp.gridDim = dim3(links_grid(S->ds));
         kp.kernelParams = part_args;
+        HIPCHK(hipGraphAddKernelNode(&n0, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        kp.func = motion_kernel_ptr();
+        kp.gridDim = dim3(motion_grid(S->ds));
+        HIPCHK(hipGraphAddKernelNode(&n1, S->graph, &n0, 1, &kp));
+        kp.func = fluid_kernel_ptr(S->G.prec);
+        kp.gridDim = dim3(S->ds.tiles_total);
+        kp.kernelParams = fluid_args;
         HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n1, 1, &kp));
         kp.func = remap_kernel_ptr_prec(S->G.prec);
         kp.gridDim = dim3(remap_grid(S->ds));
@@ -354,7 +373,7 @@ int build_graph(lbdem_set *S, int steps)
 
 int harvest_events(lbdem_set *S)
 {
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kKernels; ++k) {
         for (auto &pr : S->ev_pending[k]) {
             float ms = 0.0f;
             HIPCHK(hipEventSynchronize(S->ev_pool[pr.second]));
@@ -370,7 +389,7 @@ int harvest_events(lbdem_set *S)
 
 int launch_step_eager(lbdem_set *S)
 {
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kKernels; ++k) {
         int e0 = -1, e1 = -1;
         if (S->timing) {
             if (S->ev_next + 2 > S->ev_pool.size()) {
@@ -382,8 +401,9 @@ int launch_step_eager(lbdem_set *S)
             HIPCHK(hipEventRecord(S->ev_pool[e0], S->stream));
         }
         hipError_t err;
-        if (k == 0) err = launch_fluid(S->G.prec, S->ds, S->stream);
-        else if (k == 1) err = launch_particles(S->ds, 0, -1, S->stream);
+        if (k == 0) err = launch_links(S->G.prec, S->ds, S->stream);
+        else if (k == 1) err = launch_motion(S->ds, 0, -1, S->stream);
+        else if (k == 2) err = launch_fluid(S->G.prec, S->ds, S->stream);
         else err = launch_remap_prec(S->G.prec, S->ds, 0, -1, S->stream);
         if (err != hipSuccess) return fail(LBDEM_EDEVICE, "kernel launch %d: %s", k, hipGetErrorString(err));
         if (S->timing) {
@@ -516,7 +536,6 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     CHK(hipMemsetAsync(s.own[0], 0xff, sizeof(int) * S->G.cells, st));
     CHK(hipMemsetAsync(s.own[1], 0xff, sizeof(int) * S->G.cells, st));
     CHK(hipMemsetAsync(s.chgcnt, 0, sizeof(int) * 2, st));
-    CHK(hipMemsetAsync(s.wcnt, 0, sizeof(int) * S->G.tiles * 4, st));
     CHK(hipMemsetAsync(s.pprt, 0, sizeof(double) * S->G.tiles * S->G.nzt * 4, st));
     CHK(hipMemsetAsync(s.ring, 0, sizeof(double) * S->G.ring_doubles, st));
     for (int k = 0; k < 2; ++k) {
@@ -527,11 +546,11 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     }
     double *zero3[] = {s.Fg, s.Fh, s.Th, s.Ph, s.Lh, s.Xref};
     for (double *z : zero3) CHK(hipMemsetAsync(z, 0, sizeof(double) * 3 * P, st));
-    CHK(hipMemsetAsync(s.ovf, 0, sizeof(double) * 6 * P, st));
     CHK(hipMemsetAsync(s.margin, 0, sizeof(double) * P, st));
     CHK(hipMemsetAsync(s.nnear, 0, sizeof(int) * P, st));
+    CHK(hipMemsetAsync(s.lcnt, 0, sizeof(int) * P, st));
     CHK(hipMemsetAsync(s.tstep, 0, sizeof(long long), st));
-    CHK(hipMemsetAsync(s.k3done, 0, sizeof(unsigned), st));
+    CHK(hipMemsetAsync(s.tcopy, 0, sizeof(long long), st));
     CHK(hipMemsetAsync(s.flags, 0, sizeof(unsigned), st));
     CHK(launch_init_pops(S->G.prec, s, S->G.cells, st));
     CHK(hipStreamSynchronize(st));
@@ -584,6 +603,8 @@ int lbdem_particles_set(lbdem_set *S, int32_t lattice, int32_t n, const double *
     for (int q = 0; q < n; ++q) {
         const double R = radius[q];
         if (!(R > 0.0) || !std::isfinite(R)) return fail(LBDEM_EINVAL, "particle %d: radius must be positive", q);
+        if (R > S->params[lattice].max_radius)
+            return fail(LBDEM_EINVAL, "particle %d: radius %g exceeds max_radius %g", q, R, S->params[lattice].max_radius);
         for (int a = 0; a < 3; ++a) {
             double c = x[3 * q + a];
             if (!std::isfinite(c)) return fail(LBDEM_EINVAL, "particle %d: non-finite position", q);
@@ -631,7 +652,6 @@ int lbdem_particles_set(lbdem_set *S, int32_t lattice, int32_t n, const double *
         HIPCHK(hipMemsetAsync(s.Th + o3, 0, 8 * 3 * n, st));
         HIPCHK(hipMemsetAsync(s.Ph + o3, 0, 8 * 3 * n, st));
         HIPCHK(hipMemsetAsync(s.Lh + o3, 0, 8 * 3 * n, st));
-        HIPCHK(hipMemsetAsync(s.ovf + 6 * o1, 0, 8 * 6 * n, st));
         HIPCHK(hipMemsetAsync(s.hn[0] + o1, 0, 4 * n, st));
         HIPCHK(hipMemsetAsync(s.hn[1] + o1, 0, 4 * n, st));
     }
@@ -641,7 +661,7 @@ int lbdem_particles_set(lbdem_set *S, int32_t lattice, int32_t n, const double *
     M.np = n;
     rc = upload_member(S, lattice);
     if (rc) return rc;
-    hipError_t e = launch_particles(s, 1, lattice, st);
+    hipError_t e = launch_motion(s, 1, lattice, st);
     if (e != hipSuccess) return fail(LBDEM_EDEVICE, "near-list kernel: %s", hipGetErrorString(e));
     e = launch_remap_prec(S->G.prec, s, 1, lattice, st);
     if (e != hipSuccess) return fail(LBDEM_EDEVICE, "projection kernel: %s", hipGetErrorString(e));
@@ -722,7 +742,8 @@ int lbdem_status(lbdem_set *S, uint32_t *bits, int clear)
     HIPCHK(hipMemcpy(&f, S->ds.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
     *bits = f;
     if (clear) HIPCHK(hipMemset(S->ds.flags, 0, sizeof(unsigned)));
-    const unsigned errs = LBDEM_STATUS_NEAR_OVERFLOW | LBDEM_STATUS_HISTORY_OVERFLOW | LBDEM_STATUS_TOO_FAST;
+    const unsigned errs = LBDEM_STATUS_NEAR_OVERFLOW | LBDEM_STATUS_HISTORY_OVERFLOW | LBDEM_STATUS_TOO_FAST |
+                          LBDEM_STATUS_SHELL_OVERFLOW;
     if (f & errs) return fail(LBDEM_ECAPACITY, "device status 0x%x", f);
     return LBDEM_OK;
 }
@@ -823,7 +844,7 @@ int lbdem_timing_enable(lbdem_set *S, int enable)
     rc = harvest_events(S);
     if (rc) return rc;
     S->timing = enable != 0;
-    for (int k = 0; k < 3; ++k) { S->ms_acc[k] = 0.0; S->ms_cnt[k] = 0; }
+    for (int k = 0; k < kKernels; ++k) { S->ms_acc[k] = 0.0; S->ms_cnt[k] = 0; }
     return LBDEM_OK;
 }
 
@@ -834,7 +855,7 @@ int lbdem_timing_read(lbdem_set *S, double *ms, int64_t *count)
     if (rc) return rc;
     rc = harvest_events(S);
     if (rc) return rc;
-    for (int k = 0; k < 3; ++k) { ms[k] = S->ms_acc[k]; count[k] = S->ms_cnt[k]; }
+    for (int k = 0; k < kKernels; ++k) { ms[k] = S->ms_acc[k]; count[k] = S->ms_cnt[k]; }
     return LBDEM_OK;
 }
 

@@ -17,7 +17,8 @@ constexpr int kWaveSlots = 12;     // link-force partial slots per wavefront til
 constexpr int kNearCap = 32;       // near-neighbour table per particle
 constexpr int kHistCap = 16;       // tangential contact history per particle
 constexpr double kNearMargin = 3.0; // near list: |X_p - X_q| <= R_p + R_q + margin
-constexpr double kMarginCap = 0.5;  // re-projection margin cap (lattice units)
+constexpr double kShell = 0.5;      // skin of the per-particle shell lists (lattice units)
+constexpr int kChunks = 8;          // workgroups per particle in the particle kernel
 constexpr int kEmpty = 0x7fffffff;
 
 // Per-lattice constants (one entry per lattice of the set).
@@ -57,10 +58,6 @@ struct DevSet {
     int *chg[2];
     int chg_cap;
     int *chgcnt;              // [2]
-    // link-force partials per wavefront tile
-    int *wcnt;                // [tiles_total*4]
-    int *wpid;                // [tiles_total*4*kWaveSlots]
-    double *wval;             // [tiles_total*4*kWaveSlots*6]
     // probes
     double *pprt;             // [tiles_total*nzt*4]
     double *ring;
@@ -72,15 +69,21 @@ struct DevSet {
     // particles
     int ptot;
     double *X[2], *V[2], *W[2];
-    double *R, *m, *I, *Fg, *Fh, *Th, *Ph, *Lh, *Xref, *margin, *ovf;
+    double *R, *m, *I, *Fg, *Fh, *Th, *Ph, *Lh, *Xref, *margin;
     int *fixed, *pmem;
+    double *ppart;            // link-force partials per (particle, chunk) [ptot*kChunks*6]
     int *nearl, *nnear;       // [ptot*kNearCap], [ptot]
+    // shell list per particle around X_ref: node, d_ref - R, link-candidate directions
+    int lcap;
+    int *lcell, *lcnt;
+    float *ldr;
+    unsigned *lmask;
     int *hj[2];               // tangential history partner ids [ptot*kHistCap]
     double *hf[2];            // tangential history forces [ptot*kHistCap*3]
     int *hn[2];               // history counts [ptot]
     // counters
-    long long *tstep;
-    unsigned int *k3done;
+    long long *tstep;         // steps completed
+    long long *tcopy;         // step in progress, for the re-projection kernel
     unsigned int *flags;
 };
 
@@ -88,15 +91,18 @@ enum { BC_PERIODIC = 0, BC_WALL = 1, BC_PRESSURE = 2 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16DEV = 2, PREC_BF16DEV = 3 };
 
 // kernel launchers (lbdem_kernels.hip)
+hipError_t launch_links(int prec, const DevSet &s, hipStream_t st);
+hipError_t launch_motion(const DevSet &s, int mode, int only_member, hipStream_t st);
 hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st);
-hipError_t launch_particles(const DevSet &s, int mode, int only_member, hipStream_t st);
 hipError_t launch_remap_prec(int prec, const DevSet &s, int mode, int only_member, hipStream_t st);
 hipError_t launch_init_pops(int prec, const DevSet &s, long long total_cells, hipStream_t st);
 // kernel entry points and grid sizes, for building HIP graphs
+void *links_kernel_ptr(int prec);
+void *motion_kernel_ptr();
 void *fluid_kernel_ptr(int prec);
-void *particles_kernel_ptr();
 void *remap_kernel_ptr_prec(int prec);
-int particles_grid(const DevSet &s);
+int links_grid(const DevSet &s);
+int motion_grid(const DevSet &s);
 int remap_grid(const DevSet &s);
 
 } // namespace lbdem

@@ -3,24 +3,23 @@
 // Method: Cheng, Luding, Rivas, Harting, Magnanimo, "Hydro-micromechanical modeling of
 // wave propagation in saturated granular media", arXiv 1808.08921, Sec. 2.
 //
-// Three kernels make one time step t -> t+1 of every lattice of a set:
+// Four kernels make one time step t -> t+1 of every lattice of a set:
+//   k_links      kChunks workgroups per particle: find the particle's links (fluid node
+//                x, direction e, source x - c_e inside the particle) on its shell list,
+//                write the bounced moving-wall population of Eq. (mem) into the solid
+//                source's slot of direction e, and sum the link forces and torques
+//                (Eq. fFS) in a fixed order.
+//   k_motion     one workgroup per particle: Eqs. (coupleF), (coupleT) with the
+//                conversion impulses of the previous re-projection, Hertz / Mindlin
+//                contacts (Eqs. fdLawn, fdLaws), symplectic Euler (Eqs. translate, rotate).
 //   k_fluid      one thread per (x, y) column of a tile, nzt planes deep: pull streaming
-//                (Eq. stream), half-way bounce-back on moving particle surfaces
-//                (Eq. mem), stationary walls, the density faces (Sec. 2.4), BGK collision
-//                (Eqs. bgk, BGKequili, rhoAndU), probe partial sums, and the link forces
-//                and torques (Eqs. fFS, coupleT) reduced per wavefront into a few
-//                (particle, F, T) slots.
-//   k_particles  one workgroup per particle: gathers the wavefront slots that can hold
-//                its links (a fixed, geometry-derived order: deterministic), adds the
-//                conversion impulses of the previous re-projection (Eqs. coupleF,
-//                coupleT), Hertz / Mindlin contacts (Eqs. fdLawn, fdLaws), and advances
-//                V, Omega, X by symplectic Euler (Eqs. translate, rotate).  Extra
-//                workgroups reduce the probe partials of each probe plane.
+//                (Eq. stream), stationary walls, the density faces (Sec. 2.4), BGK
+//                collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.
 //   k_remap      one workgroup per particle: re-projects the particle on the lattice
 //                (Sec. 2.3) where its motion can have changed a node, converts covered
 //                and uncovered nodes (Eqs. convertFS, convertSF) and records the
-//                impulses that act in the next step; the last workgroup advances the
-//                step counter.
+//                impulses that act in the next step; extra workgroups reduce the probe
+//                planes; the step counter advances.
 // The population layout is SoA [19][nz][ny][nx] per lattice; the fluid kernel is
 // bound by HBM bandwidth (about 1.5 flop per byte at FP32) and uses no MFMA.
 #include "lbdem_internal.hpp"
@@ -32,15 +31,6 @@ constexpr int kCX[kQ] = {1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0,
 constexpr int kCY[kQ] = {0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0};
 constexpr int kCZ[kQ] = {0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1, 0};
 constexpr int kOPP[kQ] = {1, 0, 3, 2, 5, 4, 11, 10, 13, 12, 7, 6, 9, 8, 17, 16, 15, 14, 18};
-__device__ __forceinline__ int kCXr(int e) { return (e == 0 || (e >= 6 && e <= 9)) ? 1 : ((e == 1 || (e >= 10 && e <= 13)) ? -1 : 0); }
-__device__ __forceinline__ int kCYr(int e)
-{
-    return (e == 2 || e == 6 || e == 10 || e == 14 || e == 15) ? 1 : ((e == 3 || e == 7 || e == 11 || e == 16 || e == 17) ? -1 : 0);
-}
-__device__ __forceinline__ int kCZr(int e)
-{
-    return (e == 4 || e == 8 || e == 12 || e == 14 || e == 16) ? 1 : ((e == 5 || e == 9 || e == 13 || e == 15 || e == 17) ? -1 : 0);
-}
 // lattice weights (Sec. 2.1): 1/18 along the axes, 1/36 on the diagonals, 1/3 at rest
 constexpr double kWd[kQ] = {1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
@@ -237,22 +227,6 @@ __device__ __forceinline__ int wrap_axis(int c, int n, int bclo, int bchi, int &
     return c;
 }
 
-struct LinkSlot {
-    int pid;
-    double fx, fy, fz, tx, ty, tz;
-};
-
-__device__ __forceinline__ void slot_clear(LinkSlot &a)
-{
-    a.pid = kEmpty;
-    a.fx = a.fy = a.fz = a.tx = a.ty = a.tz = 0.0;
-}
-__device__ __forceinline__ void slot_acc(LinkSlot &a, double fx, double fy, double fz, double tx, double ty, double tz)
-{
-    a.fx += fx; a.fy += fy; a.fz += fz;
-    a.tx += tx; a.ty += ty; a.tz += tz;
-}
-
 // Density boundary on a z face: non-equilibrium bounce-back (Sec. 2.4) with zero
 // tangential velocity; the velocity normal to the face follows from the density.
 template <typename C>
@@ -315,90 +289,11 @@ __device__ __forceinline__ C feq(int d, C rho, C ux, C uy, C uz, C uu)
 // ---------------------------------------------------------------------------
 // fluid kernel
 // ---------------------------------------------------------------------------
-// Transposed butterfly over the 64 lanes for 8 values at once (fixed order, so the
-// result is reproducible): on return lane l holds the 64-lane total of value
-// 4*bit5(l) + 2*bit4(l) + bit3(l).
-__device__ __forceinline__ double wave_reduce8(const double (&a)[8])
-{
-    const int lane = threadIdx.x & 63;
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
-    double s1[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        // lanes 32..63 of a[k] trade places with lanes 0..31 of a[k+4]
-        const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a[k]), __double2loint(a[k + 4]), false, false);
-        const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a[k]), __double2hiint(a[k + 4]), false, false);
-        const double nd = __hiloint2double((int)hi[0], (int)lo[0]); // a[k+4] of lane - 32 (upper half)
-        const double ns = __hiloint2double((int)hi[1], (int)lo[1]); // a[k] of lane + 32 (lower half)
-        s1[k] = b5 ? (a[k + 4] + nd) : (a[k] + ns);
-    }
-    double s2[2];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(s1[k]), __double2loint(s1[k + 2]), false, false);
-        const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(s1[k]), __double2hiint(s1[k + 2]), false, false);
-        const double nd = __hiloint2double((int)hi[0], (int)lo[0]);
-        const double ns = __hiloint2double((int)hi[1], (int)lo[1]);
-        s2[k] = b4 ? (s1[k + 2] + nd) : (s1[k] + ns);
-    }
-    const double y = b3 ? s2[0] : s2[1];       // what the lane 8 apart keeps
-    double r = (b3 ? s2[1] : s2[0]) + dpp_d<0x128, 0xF>(y); // row_ror:8 = lane ^ 8 within a row
-    r += dpp_d<0xB1, 0xF>(r);                  // lane ^ 1
-    r += dpp_d<0x4E, 0xF>(r);                  // lane ^ 2
-    r += dpp_d<0x141, 0xF>(r);                 // the other quad of the 8-lane group
-    return r;
-}
-
-// Moving half-way bounce-back (Eq. mem) and link force / torque (Eqs. fFS, coupleT) for
-// the links of node (i,j,z) whose solid end belongs to particle p (bit e of m set: the
-// source x - c_e of direction e lies in p).  With d = e* pointing into the particle,
-//   f_e = f~_d - 2 (w_d / c_s^2) rho_f V_b . c_d,   V_b = V_p + Omega_p x (x_b - X_p),
-//   F = c_d f~_d(x,t) - c_e f_e(x,t+1),   T = (x_b - X_p) x F,   x_b = x + c_d / 2.
-// Because x_b - X_p = (x - X_p) + c_d/2, V_b . c_d = c_d . (V_p + Omega_p x (x - X_p)) and
-// (c_d / 2) x F = 0 (F is parallel to c_d), so the rigid velocity and the torque arm are
-// evaluated once at the node.  f[e] holds f~_d(x,t) on entry and f_e(x,t+1) on exit.
-template <typename C>
-__device__ __forceinline__ void moving_links(C (&f)[kQ], unsigned m, int p, int i, int j, int z, double rho_f,
-                                             const DevSet &s, const double *PX, const double *PV, const double *PW,
-                                             int per0, int per1, int per2, double box0, double box1, double box2,
-                                             LinkSlot &L0, LinkSlot &L1)
-{
-    const double r0 = mimg((double)i - PX[3 * p], per0, box0);
-    const double r1 = mimg((double)j - PX[3 * p + 1], per1, box1);
-    const double r2 = mimg((double)z - PX[3 * p + 2], per2, box2);
-    const double w0 = PW[3 * p], w1 = PW[3 * p + 1], w2 = PW[3 * p + 2];
-    const double u0 = PV[3 * p] + (w1 * r2 - w2 * r1);
-    const double u1 = PV[3 * p + 1] + (w2 * r0 - w0 * r2);
-    const double u2 = PV[3 * p + 2] + (w0 * r1 - w1 * r0);
-    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
-#pragma unroll
-    for (int e = 0; e < kQ - 1; ++e) {
-        if (m & (1u << e)) {
-            const int d = kOPP[e];
-            double cu = 0.0;
-            if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
-            if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
-            if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
-            const C fo = f[e];
-            const C v = fo - (C)(kMW[d] * rho_f * cu);
-            f[e] = v;
-            const double sl = (double)fo + (double)v; // F = c_d (f~_d + f_e)
-            if (kCX[d] > 0) F0 += sl; else if (kCX[d] < 0) F0 -= sl;
-            if (kCY[d] > 0) F1 += sl; else if (kCY[d] < 0) F1 -= sl;
-            if (kCZ[d] > 0) F2 += sl; else if (kCZ[d] < 0) F2 -= sl;
-        }
-    }
-    const double T0 = r1 * F2 - r2 * F1, T1 = r2 * F0 - r0 * F2, T2 = r0 * F1 - r1 * F0;
-    if (L0.pid == p || L0.pid == kEmpty) { L0.pid = p; slot_acc(L0, F0, F1, F2, T0, T1, T2); }
-    else if (L1.pid == p || L1.pid == kEmpty) { L1.pid = p; slot_acc(L1, F0, F1, F2, T0, T1, T2); }
-    else {
-        double *o6 = s.ovf + 6 * (long long)p;
-        atomicAdd(o6 + 0, F0); atomicAdd(o6 + 1, F1); atomicAdd(o6 + 2, F2);
-        atomicAdd(o6 + 3, T0); atomicAdd(o6 + 4, T1); atomicAdd(o6 + 5, T2);
-        atomicOr(s.flags, 0x20u);
-    }
-}
-
+// Pull streaming (Eq. stream), stationary half-way walls, the density faces (Sec. 2.4),
+// BGK collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.  A source node
+// inside a particle needs no special case here: the particle kernel of the same step
+// has already written the bounced, moving-wall population f_e (Eq. mem) into that
+// solid node's own slot of direction e, which is read by this node only.
 template <int P>
 __global__ __launch_bounds__(256) void k_fluid(DevSet s)
 {
@@ -408,7 +303,6 @@ __global__ __launch_bounds__(256) void k_fluid(DevSet s)
 
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
     // bring the other node map up to date with the previous step's changes
     const int prev_cnt = s.chgcnt[par ^ 1];
@@ -420,7 +314,10 @@ __global__ __launch_bounds__(256) void k_fluid(DevSet s)
         for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < prev_cnt; e += nthr)
             nmap[lst[2 * e]] = lst[2 * e + 1];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) s.chgcnt[par] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.chgcnt[par] = 0;
+        *s.tcopy = t; // the re-projection kernel of this step reads the step from here
+    }
 
     const int g = xcd_swizzle(blockIdx.x, gridDim.x);
     const MemberDev *M = member_of_tile(s, g);
@@ -444,15 +341,12 @@ __global__ __launch_bounds__(256) void k_fluid(DevSet s)
     const float rho_ff = (float)rho_fd;
     const C omega = (C)uni(M->omega);
     const int bc4 = uni(M->bc[4]), bc5 = uni(M->bc[5]);
-    const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
-    const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
     const long long t_n = uni(M->t_n);
     long long ti = t + 1;
     if (ti > t_n + 1) ti = t_n + 1;
     const C rho_in = (C)s.wave[uni(M->wave_off) + ti];
     const C rho_out = (C)rho_fd;
     const int pz_off = uni(M->pz_off);
-    const double *PX = s.X[par], *PV = s.V[par], *PW = s.W[par];
 
     // offsets to the x-1 / x+1 / y-1 / y+1 neighbours (wrapped on periodic axes) and the
     // kind of face crossed to reach them (0 inside or periodic, 1 wall, 2 density face)
@@ -461,12 +355,9 @@ __global__ __launch_bounds__(256) void k_fluid(DevSet s)
     int oym = (j > 0) ? -nx : (ny - 1) * nx, oyp = (j < ny - 1) ? nx : -(ny - 1) * nx;
     int kym = (j > 0) ? 0 : uni(M->bc[2]), kyp = (j < ny - 1) ? 0 : uni(M->bc[3]);
 
-    LinkSlot L0, L1;
-    slot_clear(L0); slot_clear(L1);
-
     for (int z = z0; z < z1; ++z) {
-        // keep the per-direction offsets from being hoisted out of the loop (they are cheap
-        // to recompute, and 36 of them held live would cost occupancy)
+        // keep the 18 per-direction offsets from being hoisted out of the loop: they are
+        // cheap to recompute and would otherwise stay live in 36 registers
         asm volatile("" : "+v"(oxm), "+v"(oxp), "+v"(oym), "+v"(oyp), "+v"(kxm), "+v"(kxp), "+v"(kym), "+v"(kyp));
         const int cell = (z * ny + j) * nx + i;
         bool fl = false;
@@ -480,52 +371,20 @@ __global__ __launch_bounds__(256) void k_fluid(DevSet s)
             const int ozm = (z > 0) ? -nxy : (nz - 1) * nxy, ozp = (z < nz - 1) ? nxy : -(nz - 1) * nxy;
             const int kzm = (z > 0) ? 0 : bc4, kzp = (z < nz - 1) ? 0 : bc5;
             C f[kQ];
-            int pa = -1;
-            unsigned ma = 0u, mo = 0u;
-            // Eq. (stream) in pull form: f_e(x, t+1) = f~_e(x - c_e, t).  A source across a
-            // wall or inside a particle gives the bounced f~_{e*}(x, t) (the moving-wall term
-            // follows), a source across a density face is left for the boundary rule.
 #pragma unroll
             for (int e = 0; e < kQ - 1; ++e) {
                 int off = 0, kind = 0;
                 if (kCX[e] > 0) { off += oxm; kind = max(kind, kxm); } else if (kCX[e] < 0) { off += oxp; kind = max(kind, kxp); }
                 if (kCY[e] > 0) { off += oym; kind = max(kind, kym); } else if (kCY[e] < 0) { off += oyp; kind = max(kind, kyp); }
                 if (kCZ[e] > 0) { off += ozm; kind = max(kind, kzm); } else if (kCZ[e] < 0) { off += ozp; kind = max(kind, kzp); }
-                const unsigned sc = (kind == 0) ? (unsigned)(cell + off) : (unsigned)cell;
-                const int os = ldo(own, sc);
-                const bool bb = (kind != 0) || (os >= 0);
-                const C v = ld<P>(A, bb ? (unsigned)(kOPP[e] * nc) + (unsigned)cell : (unsigned)(e * nc) + sc, e, rho_ff);
+                // f_e(x, t+1) = f~_e(x - c_e, t); across a wall the population comes back
+                // from this node, f~_{e*}(x, t); across a density face it is unknown
+                const unsigned idx = (kind == 0) ? (unsigned)(e * nc) + (unsigned)(cell + off)
+                                                 : (unsigned)(kOPP[e] * nc) + (unsigned)cell;
+                const C v = ld<P>(A, idx, e, rho_ff);
                 f[e] = (kind == BC_PRESSURE) ? C(0) : v;
-                if (kind == 0 && os >= 0) {
-                    if (pa < 0) pa = os;
-                    if (os == pa) ma |= 1u << e; else mo |= 1u << e;
-                }
             }
             f[18] = ld<P>(A, (unsigned)(18 * nc) + (unsigned)cell, 18, rho_ff);
-
-            if (ma) moving_links<C>(f, ma, pa, i, j, z, rho_fd, s, PX, PV, PW, per0, per1, per2, box0, box1, box2, L0, L1);
-            while (mo) {
-                // links to further particles (rare): one particle at a time
-                const int e0 = __builtin_ctz(mo);
-                int off0 = 0;
-                off0 += (kCXr(e0) > 0) ? oxm : (kCXr(e0) < 0 ? oxp : 0);
-                off0 += (kCYr(e0) > 0) ? oym : (kCYr(e0) < 0 ? oyp : 0);
-                off0 += (kCZr(e0) > 0) ? ozm : (kCZr(e0) < 0 ? ozp : 0);
-                const int pc = ldo(own, (unsigned)(cell + off0));
-                unsigned mc = 0u;
-#pragma unroll
-                for (int e = 0; e < kQ - 1; ++e) {
-                    if (mo & (1u << e)) {
-                        int off = 0;
-                        if (kCX[e] > 0) off += oxm; else if (kCX[e] < 0) off += oxp;
-                        if (kCY[e] > 0) off += oym; else if (kCY[e] < 0) off += oyp;
-                        if (kCZ[e] > 0) off += ozm; else if (kCZ[e] < 0) off += ozp;
-                        if (ldo(own, (unsigned)(cell + off)) == pc) mc |= 1u << e;
-                    }
-                }
-                moving_links<C>(f, mc, pc, i, j, z, rho_fd, s, PX, PV, PW, per0, per1, per2, box0, box1, box2, L0, L1);
-                mo &= ~mc;
-            }
 
             if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, rho_in, false);
             if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, rho_out, true);
@@ -554,59 +413,11 @@ __global__ __launch_bounds__(256) void k_fluid(DevSet s)
             }
         }
     }
-
-    // link partials: one (particle, F, T) slot per distinct particle of this wavefront,
-    // in increasing particle order, each summed over the lanes in a fixed order
-    const long long WT = (long long)g * 4 + wv;
-    const int vi = (lane >> 3) & 7;
-    int k = 0;
-    for (;;) {
-        const int mn = min(L0.pid, L1.pid);
-        const int pm = wave_min(mn);
-        if (pm == kEmpty) break;
-        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (L0.pid == pm) { v[0] = L0.fx; v[1] = L0.fy; v[2] = L0.fz; v[3] = L0.tx; v[4] = L0.ty; v[5] = L0.tz; L0.pid = kEmpty; }
-        else if (L1.pid == pm) { v[0] = L1.fx; v[1] = L1.fy; v[2] = L1.fz; v[3] = L1.tx; v[4] = L1.ty; v[5] = L1.tz; L1.pid = kEmpty; }
-        const double r = wave_reduce8(v);
-        if ((lane & 7) == 0 && vi < 6) {
-            if (k < kWaveSlots) {
-                const long long o = WT * kWaveSlots + k;
-                s.wval[o * 6 + vi] = r;
-                if (vi == 0) s.wpid[o] = pm;
-            } else {
-                atomicAdd(s.ovf + 6 * (long long)pm + vi, r);
-                if (vi == 0) atomicOr(s.flags, 0x1u);
-            }
-        }
-        ++k;
-    }
-    if (lane == 0) s.wcnt[WT] = min(k, kWaveSlots);
 }
 
 // ---------------------------------------------------------------------------
-// particle kernel: link-force gather, contacts, motion; probe reduction
+// particle kernel: links, contacts, motion
 // ---------------------------------------------------------------------------
-// Units (tiles along x, wavefront rows along y, tile layers along z) that can hold a
-// node within R + 2 of coordinate c, as a start unit and a count on a ring of nun units.
-__device__ __forceinline__ void axis_units(double c, double R, int n, int unit, int per, int &u0, int &L, int &nun)
-{
-    nun = (n + unit - 1) / unit;
-    int lo = (int)floor(c - R) - 2, hi = (int)ceil(c + R) + 2;
-    if (!per) {
-        lo = max(lo, 0);
-        hi = min(hi, n - 1);
-        if (lo > hi) { u0 = 0; L = 0; return; }
-        u0 = lo / unit;
-        L = hi / unit - u0 + 1;
-        return;
-    }
-    if (hi - lo + 1 > n - unit) { u0 = 0; L = nun; return; }
-    const int lw = ((lo % n) + n) % n, hw = ((hi % n) + n) % n;
-    const int ul = lw / unit, uh = hw / unit;
-    u0 = ul;
-    L = ((uh - ul) % nun + nun) % nun + 1;
-}
-
 __device__ __forceinline__ int block_rank(bool pred, int &total, int *cnt4)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -621,83 +432,151 @@ __device__ __forceinline__ int block_rank(bool pred, int &total, int *cnt4)
     return off + before;
 }
 
-__global__ __launch_bounds__(256) void k_particles(DevSet s, int mode, int only)
+// Node range [lo, lo + ext) along one axis covering [c - h, c + h]: clipped on a bounded
+// axis, at most one full period on a periodic one.
+__device__ __forceinline__ void axis_range(double c, double h, int n, int per, int &lo, int &ext)
+{
+    int l = (int)floor(c - h), u = (int)ceil(c + h);
+    if (!per) { l = max(l, 0); u = min(u, n - 1); }
+    else if (u - l + 1 > n) { l = 0; u = n - 1; }
+    lo = l;
+    ext = max(u - l + 1, 0);
+}
+
+__device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+// Workgroups (particle p, chunk of p's shell list): the links of p, i.e. every fluid
+// node x and direction e whose source x - c_e lies in p.  Eq. (mem) gives the population
+// that returns to x, f_e = f~_d(x,t) - 2 (w_d / c_s^2) rho_f V_b . c_d with d = e*
+// pointing into p and V_b = V_p + Omega_p x (x_b - X_p) at x_b = x + c_d / 2; it is
+// stored in the solid source's slot of direction e for the fluid kernel to pull.  Since
+// x_b - X_p = (x - X_p) + c_d / 2, V_b . c_d = c_d . (V_p + Omega_p x (x - X_p)).
+// Eq. (fFS): F = c_d f~_d(x,t) - c_e f_e(x,t+1) = c_d (f~_d + f_e), torque
+// (x_b - X_p) x F = (x - X_p) x F, summed in FP64 in a fixed order per chunk.
+template <int P>
+__global__ __launch_bounds__(256) void k_links(DevSet s, int mode, int only)
+{
+    using S = typename Prec<P>::S;
+    using C = typename Prec<P>::C;
+    __shared__ double red[4][8];
+    const long long t = *s.tstep;
+    const int par = (int)(t & 1);
+    const int tid = threadIdx.x;
+    // workgroup = (particle, chunk of its shell list)
+    const int p = blockIdx.x / kChunks, chunk = blockIdx.x - p * kChunks;
+    if (p >= s.ptot || mode != 0) return;
+    const int m = uni(s.pmem[p]);
+    const MemberDev *M = s.mem + m;
+    if (p - uni(M->p_off) >= uni(M->np)) return;
+    if (only >= 0 && m != only) return;
+
+    const double *Xo = s.X[par], *Vo = s.V[par], *Wo = s.W[par];
+    const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
+    const double R = s.R[p];
+    const int nx = uni(M->nx), ny = uni(M->ny), nz = uni(M->nz);
+    const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
+    const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
+
+    // (1) links of this chunk of the shell list
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (mode == 0) {
+        const int nc = (int)uni(M->ncell);
+        const long long pop_off = uni(M->pop_off), cell_off = uni(M->cell_off);
+        S *A = (S *)(par ? s.popB : s.popA) + pop_off;
+        const int *own = s.own[par] + cell_off;
+        const double rho_f = uni(M->rho_f);
+        const float rho_ff = (float)rho_f;
+        const double V0 = Vo[3 * p], V1 = Vo[3 * p + 1], V2 = Vo[3 * p + 2];
+        const double W0 = Wo[3 * p], W1 = Wo[3 * p + 1], W2 = Wo[3 * p + 2];
+        const int nxy = nx * ny;
+        const long long lbase = (long long)p * s.lcap;
+        const int n = s.lcnt[p];
+        const int k0 = (int)((long long)n * chunk / kChunks), k1 = (int)((long long)n * (chunk + 1) / kChunks);
+        for (int k = k0 + tid; k < k1; k += 256) {
+            const unsigned mask = s.lmask[lbase + k];
+            if (mask == 0u) continue;
+            const int cell = s.lcell[lbase + k];
+            const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx, ii = rem - jj * nx;
+            // the node's own flag and the owners of the candidate sources: independent loads
+            int sc[kQ - 1], os[kQ - 1];
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                sc[e] = (wrapc(kk - kCZ[e], nz) * ny + wrapc(jj - kCY[e], ny)) * nx + wrapc(ii - kCX[e], nx);
+                os[e] = (mask & (1u << e)) ? ldo(own, (unsigned)sc[e]) : -1;
+            }
+            if (ldo(own, (unsigned)cell) >= 0) continue; // x is not fluid
+            const double r0 = mimg((double)ii - X0, per0, box0);
+            const double r1 = mimg((double)jj - X1, per1, box1);
+            const double r2 = mimg((double)kk - X2, per2, box2);
+            const double u0 = V0 + (W1 * r2 - W2 * r1);
+            const double u1 = V1 + (W2 * r0 - W0 * r2);
+            const double u2 = V2 + (W0 * r1 - W1 * r0);
+            // populations leaving x toward p (independent loads), then the bounced values
+            C fo[kQ - 1];
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e)
+                fo[e] = (os[e] == p) ? ld<P>(A, (unsigned)(kOPP[e] * nc) + (unsigned)cell, kOPP[e], rho_ff) : C(0);
+            double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                if (os[e] != p) continue;
+                const int d = kOPP[e];
+                double cu = 0.0;
+                if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
+                if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
+                if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
+                const C fe = fo[e] - (C)(kMW[d] * rho_f * cu);
+                st<P>(A, (unsigned)(e * nc) + (unsigned)sc[e], e, fe, rho_ff);
+                const double sl = (double)fo[e] + (double)fe;
+                if (kCX[d] > 0) F0 += sl; else if (kCX[d] < 0) F0 -= sl;
+                if (kCY[d] > 0) F1 += sl; else if (kCY[d] < 0) F1 -= sl;
+                if (kCZ[d] > 0) F2 += sl; else if (kCZ[d] < 0) F2 -= sl;
+            }
+            acc[0] += F0; acc[1] += F1; acc[2] += F2;
+            acc[3] += r1 * F2 - r2 * F1;
+            acc[4] += r2 * F0 - r0 * F2;
+            acc[5] += r0 * F1 - r1 * F0;
+        }
+        block_sum<6>(acc, red);
+        if (tid == 0) {
+            double *pp = s.ppart + ((long long)p * kChunks + chunk) * 6;
+            for (int c = 0; c < 6; ++c) pp[c] = acc[c];
+        }
+    }
+}
+
+// One workgroup per particle p.
+// mode 0: Eqs. (coupleF), (coupleT): the link force and torque (chunk partials summed in
+//         chunk order) plus the conversion impulses of the previous re-projection; Hertz /
+//         Mindlin contacts (Eqs. fdLawn, fdLaws) and the external force; symplectic Euler
+//         (Eqs. translate, rotate), dt = 1; fixed particles stay.
+// mode 1: near-neighbour lists only (set-up).
+__global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
 {
     __shared__ double red[4][8];
     __shared__ int cnt4[4];
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
     const int tid = threadIdx.x;
-    const int b = blockIdx.x;
-
-    if (b >= s.ptot) {
-        // probe plane reduction, one workgroup per (lattice, probe)
-        if (mode != 0) return;
-        const int q = b - s.ptot;
-        if (q >= s.nprobe_total) return;
-        int m = 0;
-        while (m + 1 < s.nmem && s.mem[m + 1].plist_off <= q) ++m;
-        while (s.mem[m].n_probe == 0 || q - s.mem[m].plist_off >= s.mem[m].n_probe) ++m;
-        const MemberDev *M = s.mem + m;
-        const int k = q - M->plist_off;
-        const int z = s.plist[M->plist_off + k];
-        const int tz = z / s.nzt, dz = z - tz * s.nzt;
-        const int ntile = M->ntx * M->nty;
-        double v[4] = {0, 0, 0, 0};
-        for (int c = tid; c < ntile; c += 256) {
-            const long long gt = M->tile_off + (long long)tz * ntile + c;
-            const double *pp = s.pprt + (gt * s.nzt + dz) * 4;
-            v[0] += pp[0]; v[1] += pp[1]; v[2] += pp[2]; v[3] += pp[3];
-        }
-        block_sum<4>(v, red);
-        if (tid == 0) {
-            double *o = s.ring + M->ring_off + ((t % s.ring_len) * M->n_probe + k) * 4;
-            o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
-        }
-        return;
-    }
-
-    const int p = b;
-    const int m = s.pmem[p];
+    const int p = blockIdx.x;
+    if (p >= s.ptot) return;
+    const int m = uni(s.pmem[p]);
     const MemberDev *M = s.mem + m;
-    if (p - M->p_off >= M->np) return;
+    if (p - uni(M->p_off) >= uni(M->np)) return;
     if (only >= 0 && m != only) return;
-
     const double *Xo = s.X[par], *Vo = s.V[par], *Wo = s.W[par];
     const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
     const double R = s.R[p];
-
-    // (1) hydrodynamic force and torque from the wavefront link slots
-    double hyd[6] = {0, 0, 0, 0, 0, 0};
-    if (mode == 0) {
-        const int bx = M->bx, rowh = 64 / bx;
-        int ux0, Lx, nux, uy0, Ly, nuy, uz0, Lz, nuz;
-        axis_units(X0, R, M->nx, bx, M->per[0], ux0, Lx, nux);
-        axis_units(X1, R, M->ny, rowh, M->per[1], uy0, Ly, nuy);
-        axis_units(X2, R, M->nz, s.nzt, M->per[2], uz0, Lz, nuz);
-        const int tot = Lx * Ly * Lz;
-        for (int c = tid; c < tot; c += 256) {
-            const int cx = c % Lx, cr = c / Lx, cy = cr % Ly, cz = cr / Ly;
-            int ux = ux0 + cx; if (ux >= nux) ux -= nux;
-            int uy = uy0 + cy; if (uy >= nuy) uy -= nuy;
-            int uz = uz0 + cz; if (uz >= nuz) uz -= nuz;
-            const long long gt = M->tile_off + ((long long)uz * M->nty + (uy >> 2)) * M->ntx + ux;
-            const long long WT = gt * 4 + (uy & 3);
-            const int cnt = s.wcnt[WT];
-            for (int k = 0; k < cnt; ++k) {
-                if (s.wpid[WT * kWaveSlots + k] == p) {
-                    const double *w6 = s.wval + (WT * kWaveSlots + k) * 6;
-#pragma unroll
-                    for (int e = 0; e < 6; ++e) hyd[e] += w6[e];
-                }
-            }
-        }
-        block_sum<6>(hyd, red);
-    }
+    const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
+    const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (mode == 0)
+        for (int q = 0; q < kChunks; ++q)
+            for (int c = 0; c < 6; ++c) acc[c] += s.ppart[((long long)p * kChunks + q) * 6 + c];
 
     // (2) contacts, near-neighbour list, tangential history
-    const int q0 = M->p_off, nq = M->np;
-    const double E = M->E, nu = M->nu, mu = M->mu;
+    const int q0 = uni(M->p_off), nq = uni(M->np);
+    const double E = uni(M->E), nu = uni(M->nu), mu = uni(M->mu);
     const int *hjo = s.hj[par] + (long long)p * kHistCap;
     const double *hfo = s.hf[par] + (long long)p * kHistCap * 3;
     const int hno = s.hn[par][p];
@@ -712,9 +591,9 @@ __global__ __launch_bounds__(256) void k_particles(DevSet s, int mode, int only)
         double ftn[3] = {0, 0, 0};
         if (jj < nq && q != p) {
             const double Y0 = Xo[3 * q], Y1 = Xo[3 * q + 1], Y2 = Xo[3 * q + 2], Rq = s.R[q];
-            const double d0 = mimg(Y0 - X0, M->per[0], M->box[0]);
-            const double d1 = mimg(Y1 - X1, M->per[1], M->box[1]);
-            const double d2 = mimg(Y2 - X2, M->per[2], M->box[2]);
+            const double d0 = mimg(Y0 - X0, per0, box0);
+            const double d1 = mimg(Y1 - X1, per1, box1);
+            const double d2 = mimg(Y2 - X2, per2, box2);
             const double dist = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
             isnear = dist <= R + Rq + kNearMargin;
             const double un = R + Rq - dist;
@@ -778,25 +657,24 @@ __global__ __launch_bounds__(256) void k_particles(DevSet s, int mode, int only)
     }
     if (tid == 0) {
         s.nnear[p] = min(near_total, kNearCap);
-        s.hn[par ^ 1][p] = min(hist_total, kHistCap);
+        if (mode == 0) s.hn[par ^ 1][p] = min(hist_total, kHistCap);
     }
     if (mode != 0) return;
     block_sum<6>(con, red);
 
-    // (3) Eqs. (coupleF), (coupleT), (translate), (rotate): symplectic Euler, dt = 1
+    // (3) motion
     if (tid == 0) {
-        double *ov = s.ovf + 6 * (long long)p;
         double Fh[3], Th[3];
         for (int a = 0; a < 3; ++a) {
-            Fh[a] = (hyd[a] + ov[a]) + s.Ph[3 * p + a];
-            Th[a] = (hyd[3 + a] + ov[3 + a]) + s.Lh[3 * p + a];
-            ov[a] = 0.0;
-            ov[3 + a] = 0.0;
+            Fh[a] = acc[a] + s.Ph[3 * p + a];
+            Th[a] = acc[3 + a] + s.Lh[3 * p + a];
             s.Fh[3 * p + a] = Fh[a];
             s.Th[3 * p + a] = Th[a];
         }
         double *Xn = s.X[par ^ 1], *Vn = s.V[par ^ 1], *Wn = s.W[par ^ 1];
         const double Xc[3] = {X0, X1, X2};
+        const int per[3] = {per0, per1, per2};
+        const double box[3] = {box0, box1, box2};
         if (s.fixed[p]) {
             for (int a = 0; a < 3; ++a) { Xn[3 * p + a] = Xc[a]; Vn[3 * p + a] = 0.0; Wn[3 * p + a] = 0.0; }
         } else {
@@ -808,9 +686,9 @@ __global__ __launch_bounds__(256) void k_particles(DevSet s, int mode, int only)
                 Vn[3 * p + a] = v;
                 Wn[3 * p + a] = Wo[3 * p + a] + Tt / inert;
                 double x = Xc[a] + v;
-                if (M->per[a]) {
-                    if (x >= M->box[a]) x -= M->box[a];
-                    else if (x < 0.0) x += M->box[a];
+                if (per[a]) {
+                    if (x >= box[a]) x -= box[a];
+                    else if (x < 0.0) x += box[a];
                 }
                 Xn[3 * p + a] = x;
                 if (fabs(v) > 0.25) atomicOr(s.flags, 0x10u);
@@ -829,10 +707,41 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
     __shared__ double red[4][8];
     __shared__ double nb[kNearCap][4];
     __shared__ int nbid[kNearCap];
-    const long long t = *s.tstep;
+    __shared__ int cnt4[4];
+    // the step being completed: copied by the fluid kernel (mode 0); the counter itself is
+    // advanced here and read by no workgroup of this kernel
+    const long long t = (mode == 0) ? *s.tcopy : *s.tstep;
     const int par = (int)(t & 1);
     const int tid = threadIdx.x;
     const int p = blockIdx.x;
+    if (mode == 0 && p == 0 && tid == 0) *s.tstep = t + 1;
+
+    if (p >= s.ptot) {
+        // probe plane reduction, one workgroup per (lattice, probe), tiles in fixed order
+        if (mode != 0) return;
+        const int q = p - s.ptot;
+        if (q >= s.nprobe_total) return;
+        int m = 0;
+        while (m + 1 < s.nmem && s.mem[m + 1].plist_off <= q) ++m;
+        while (s.mem[m].n_probe == 0 || q - s.mem[m].plist_off >= s.mem[m].n_probe) ++m;
+        const MemberDev *Mq = s.mem + m;
+        const int k = q - Mq->plist_off;
+        const int z = s.plist[Mq->plist_off + k];
+        const int tz = z / s.nzt, dz = z - tz * s.nzt;
+        const int ntile = Mq->ntx * Mq->nty;
+        double v[4] = {0, 0, 0, 0};
+        for (int c = tid; c < ntile; c += 256) {
+            const long long gt = Mq->tile_off + (long long)tz * ntile + c;
+            const double *pp = s.pprt + (gt * s.nzt + dz) * 4;
+            v[0] += pp[0]; v[1] += pp[1]; v[2] += pp[2]; v[3] += pp[3];
+        }
+        block_sum<4>(v, red);
+        if (tid == 0) {
+            double *o = s.ring + Mq->ring_off + ((t % s.ring_len) * Mq->n_probe + k) * 4;
+            o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+        }
+        return;
+    }
 
     bool active = p < s.ptot;
     const MemberDev *M = nullptr;
@@ -873,150 +782,198 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
         // a node can change owner only if |d_ref - R| <= displacement (membership) or
         // it lies in an overlap lens of depth <= dmax (ordering between two spheres)
         const double thr = sqrt(disp2) + dmax + 1e-9;
-        const bool scan = (mode == 1) || (thr >= s.margin[p]);
+        // the shell list around X_ref holds every node with |d_ref - R| < kShell: while
+        // thr stays below kShell the candidates are in it, else it is rebuilt at X
+        const bool rebuild = (mode == 1) || (thr >= kShell - 1e-6);
+        const bool use_list = !rebuild && (thr >= s.margin[p]);
         double acc[6] = {0, 0, 0, 0, 0, 0};
-        double mrg = kMarginCap;
-        if (scan) {
-            const int sn = par ^ 1; // population buffer holding f~(t+1)
-            S *Bn = (S *)(sn ? s.popB : s.popA) + M->pop_off;
-            const int *cur = s.own[par] + M->cell_off;
-            int *nxt = s.own[par ^ 1] + M->cell_off;
-            const int nc = (int)M->ncell;
-            const float rho_ff = (float)M->rho_f;
+        const int sn = par ^ 1; // population buffer holding f~(t+1)
+        S *Bn = (S *)(sn ? s.popB : s.popA) + M->pop_off;
+        const int *cur = s.own[par] + M->cell_off;
+        int *nxt = s.own[par ^ 1] + M->cell_off;
+        const int nc = (int)M->ncell;
+        const float rho_ff = (float)M->rho_f;
+        const int dims[3] = {M->nx, M->ny, M->nz};
+        const long long lbase = (long long)p * s.lcap;
+
+        // owner of one node after the motion; conversions of covered / uncovered nodes
+        auto evaluate = [&](int ii, int jj, int kk, int cell, double d2n) {
+            // owner: smallest d^2, then smallest index, among the spheres containing the node
+            int best = -1;
+            double bd = 0.0;
+            if (d2n <= R2) { best = p; bd = d2n; }
+            for (int k = 0; k < nn; ++k) {
+                const double dq = dist2(M, ii, jj, kk, nb[k][0], nb[k][1], nb[k][2]);
+                if (dq <= nb[k][3] * nb[k][3]) {
+                    const int q = nbid[k];
+                    if (best < 0 || dq < bd || (dq == bd && q < best)) { best = q; bd = dq; }
+                }
+            }
+            if (mode == 1) {
+                if (best >= 0) { s.own[0][M->cell_off + cell] = best; s.own[1][M->cell_off + cell] = best; }
+                return;
+            }
+            const int was = cur[cell];
+            if (best == was) return;
+            nxt[cell] = best;
+            const int slot = atomicAdd(s.chgcnt + par, 1);
+            if (slot < s.chg_cap) {
+                s.chg[par][2 * slot] = (int)(M->cell_off + cell);
+                s.chg[par][2 * slot + 1] = best;
+            } else {
+                atomicOr(s.flags, 0x4u);
+            }
+            const double r0 = mimg((double)ii - X[0], M->per[0], M->box[0]);
+            const double r1 = mimg((double)jj - X[1], M->per[1], M->box[1]);
+            const double r2 = mimg((double)kk - X[2], M->per[2], M->box[2]);
+            if (was < 0 && best == p) {
+                // Eq. (convertFS): a covered node hands its momentum to the particle
+                double f[kQ];
+#pragma unroll
+                for (int d = 0; d < kQ; ++d) f[d] = (double)ld<P>(Bn, d * nc + cell, d, rho_ff);
+                double rho, j0, j1, j2;
+                moments<double>(f, rho, j0, j1, j2);
+                acc[0] += j0; acc[1] += j1; acc[2] += j2;
+                acc[3] += r1 * j2 - r2 * j1;
+                acc[4] += r2 * j0 - r0 * j2;
+                acc[5] += r0 * j1 - r1 * j0;
+            } else if (was == p && best < 0) {
+                // Eq. (convertSF): an uncovered node is refilled with f^eq(rho_bar, V_b)
+                // and takes rho_bar V_b from the particle; rho_bar averages the
+                // neighbours that are fluid before and after the re-projection
+                double sum = 0.0;
+                int cnt = 0;
+#pragma unroll 1
+                for (int e = 0; e < kQ - 1; ++e) {
+                    int c[3] = {ii + kCX[e], jj + kCY[e], kk + kCZ[e]};
+                    bool ok = true;
+                    for (int a = 0; a < 3; ++a) {
+                        if (c[a] < 0 || c[a] >= dims[a]) {
+                            if (M->per[a]) c[a] = c[a] < 0 ? c[a] + dims[a] : c[a] - dims[a];
+                            else ok = false;
+                        }
+                    }
+                    if (!ok) continue;
+                    const int yc = (c[2] * dims[1] + c[1]) * dims[0] + c[0];
+                    if (cur[yc] >= 0) continue;
+                    bool inside = dist2(M, c[0], c[1], c[2], X[0], X[1], X[2]) <= R2;
+                    for (int k = 0; k < nn && !inside; ++k)
+                        inside = dist2(M, c[0], c[1], c[2], nb[k][0], nb[k][1], nb[k][2]) <= nb[k][3] * nb[k][3];
+                    if (inside) continue;
+                    double rr = 0.0;
+                    for (int d = 0; d < kQ; ++d) rr += (double)ld<P>(Bn, d * nc + yc, d, rho_ff);
+                    sum += rr;
+                    cnt += 1;
+                }
+                const double rbar = cnt > 0 ? sum / cnt : M->rho_f;
+                const double *Vp = Vs + 3 * p, *Wp = Ws + 3 * p;
+                const double vb0 = Vp[0] + (Wp[1] * r2 - Wp[2] * r1);
+                const double vb1 = Vp[1] + (Wp[2] * r0 - Wp[0] * r2);
+                const double vb2 = Vp[2] + (Wp[0] * r1 - Wp[1] * r0);
+                const double uu = vb0 * vb0 + vb1 * vb1 + vb2 * vb2;
+#pragma unroll
+                for (int d = 0; d < kQ; ++d)
+                    st<P>(Bn, d * nc + cell, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
+                const double m0 = rbar * vb0, m1 = rbar * vb1, m2 = rbar * vb2;
+                acc[0] -= m0; acc[1] -= m1; acc[2] -= m2;
+                acc[3] -= r1 * m2 - r2 * m1;
+                acc[4] -= r2 * m0 - r0 * m2;
+                acc[5] -= r0 * m1 - r1 * m0;
+            }
+        };
+
+        if (rebuild) {
+            // scan the boxes around X and X_ref, evaluate the candidates, and rebuild the
+            // shell list at X: nodes with -kShell < d - R <= sqrt(2) + kShell, with the
+            // directions e whose source x - c_e lies within R + kShell (link candidates)
+            const double hout = R + 1.5 + kShell + thr;
+            const double Rin = R - kShell, Rin2 = Rin > 0.0 ? Rin * Rin : -1.0, Rout2 = hout * hout;
+            const double Rl2 = (R + kShell) * (R + kShell);
             int lo[3], ext[3];
-            const int dims[3] = {M->nx, M->ny, M->nz};
             for (int a = 0; a < 3; ++a) {
-                int l = (int)floor(fmin(X[a], xr[a]) - R) - 1;
-                int h = (int)ceil(fmax(X[a], xr[a]) + R) + 1;
+                int l = (int)floor(fmin(X[a], xr[a]) - hout) - 1;
+                int h = (int)ceil(fmax(X[a], xr[a]) + hout) + 1;
                 if (!M->per[a]) { l = max(l, 0); h = min(h, dims[a] - 1); }
                 else if (h - l + 1 > dims[a]) { l = 0; h = dims[a] - 1; } // visit each node once
                 lo[a] = l;
                 ext[a] = max(h - l + 1, 0);
             }
             const int tot = ext[0] * ext[1] * ext[2];
-            for (int idx = tid; idx < tot; idx += 256) {
-                int ii = lo[0] + idx % ext[0];
-                int jj = lo[1] + (idx / ext[0]) % ext[1];
-                int kk = lo[2] + idx / (ext[0] * ext[1]);
-                if (ii < 0) ii += dims[0]; else if (ii >= dims[0]) ii -= dims[0];
-                if (jj < 0) jj += dims[1]; else if (jj >= dims[1]) jj -= dims[1];
-                if (kk < 0) kk += dims[2]; else if (kk >= dims[2]) kk -= dims[2];
-                const int cell = (kk * dims[1] + jj) * dims[0] + ii;
-                const double d2n = dist2(M, ii, jj, kk, X[0], X[1], X[2]);
-                mrg = fmin(mrg, fabs(sqrt(d2n) - R));
-                bool ev;
-                if (mode == 1) ev = d2n <= R2;
-                else ev = fabs(sqrt(dist2(M, ii, jj, kk, Xr[0], Xr[1], Xr[2])) - R) <= thr;
-                if (!ev) continue;
-                // owner: smallest d^2, then smallest index, among the spheres containing the node
-                int best = -1;
-                double bd = 0.0;
-                if (d2n <= R2) { best = p; bd = d2n; }
-                for (int k = 0; k < nn; ++k) {
-                    const double dq = dist2(M, ii, jj, kk, nb[k][0], nb[k][1], nb[k][2]);
-                    if (dq <= nb[k][3] * nb[k][3]) {
-                        const int q = nbid[k];
-                        if (best < 0 || dq < bd || (dq == bd && q < best)) { best = q; bd = dq; }
-                    }
-                }
-                if (mode == 1) {
-                    if (best >= 0) { s.own[0][M->cell_off + cell] = best; s.own[1][M->cell_off + cell] = best; }
-                    continue;
-                }
-                const int was = cur[cell];
-                if (best == was) continue;
-                nxt[cell] = best;
-                const int slot = atomicAdd(s.chgcnt + par, 1);
-                if (slot < s.chg_cap) {
-                    s.chg[par][2 * slot] = (int)(M->cell_off + cell);
-                    s.chg[par][2 * slot + 1] = best;
-                } else {
-                    atomicOr(s.flags, 0x4u);
-                }
-                const double r0 = mimg((double)ii - X[0], M->per[0], M->box[0]);
-                const double r1 = mimg((double)jj - X[1], M->per[1], M->box[1]);
-                const double r2 = mimg((double)kk - X[2], M->per[2], M->box[2]);
-                if (was < 0 && best == p) {
-                    // Eq. (convertFS): a covered node hands its momentum to the particle
-                    double f[kQ];
+            double mrg = kShell;
+            int lcount = 0;
+            for (int base = 0; base < tot; base += 256) {
+                const int idx = base + tid;
+                bool in_list = false;
+                int cell = 0;
+                unsigned mask = 0u;
+                float dref = 0.0f;
+                if (idx < tot) {
+                    int ii = lo[0] + idx % ext[0];
+                    int jj = lo[1] + (idx / ext[0]) % ext[1];
+                    int kk = lo[2] + idx / (ext[0] * ext[1]);
+                    ii = wrapc(ii, dims[0]); jj = wrapc(jj, dims[1]); kk = wrapc(kk, dims[2]);
+                    cell = (kk * dims[1] + jj) * dims[0] + ii;
+                    const double d2n = dist2(M, ii, jj, kk, X[0], X[1], X[2]);
+                    bool ev;
+                    if (mode == 1) ev = d2n <= R2;
+                    else ev = fabs(sqrt(dist2(M, ii, jj, kk, Xr[0], Xr[1], Xr[2])) - R) <= thr;
+                    if (ev) evaluate(ii, jj, kk, cell, d2n);
+                    if (d2n > Rin2 && d2n <= Rout2) {
+                        const double dn = sqrt(d2n) - R;
+                        if (dn > -kShell && dn <= 1.4142135623730951 + kShell) {
+                            in_list = true;
+                            dref = (float)dn;
+                            mrg = fmin(mrg, fabs(dn));
 #pragma unroll
-                    for (int d = 0; d < kQ; ++d) f[d] = (double)ld<P>(Bn, d * nc + cell, d, rho_ff);
-                    double rho, j0, j1, j2;
-                    moments<double>(f, rho, j0, j1, j2);
-                    acc[0] += j0; acc[1] += j1; acc[2] += j2;
-                    acc[3] += r1 * j2 - r2 * j1;
-                    acc[4] += r2 * j0 - r0 * j2;
-                    acc[5] += r0 * j1 - r1 * j0;
-                } else if (was == p && best < 0) {
-                    // Eq. (convertSF): an uncovered node is refilled with f^eq(rho_bar, V_b)
-                    // and takes rho_bar V_b from the particle; rho_bar averages the
-                    // neighbours that are fluid before and after the re-projection
-                    double sum = 0.0;
-                    int cnt = 0;
-#pragma unroll 1
-                    for (int e = 0; e < kQ - 1; ++e) {
-                        int c[3] = {ii + kCX[e], jj + kCY[e], kk + kCZ[e]};
-                        bool ok = true;
-                        for (int a = 0; a < 3; ++a) {
-                            if (c[a] < 0 || c[a] >= dims[a]) {
-                                if (M->per[a]) c[a] = c[a] < 0 ? c[a] + dims[a] : c[a] - dims[a];
-                                else ok = false;
+                            for (int e = 0; e < kQ - 1; ++e) {
+                                const int si = ii - kCX[e], sj = jj - kCY[e], sk = kk - kCZ[e];
+                                if ((!M->per[0] && (si < 0 || si >= dims[0])) || (!M->per[1] && (sj < 0 || sj >= dims[1])) ||
+                                    (!M->per[2] && (sk < 0 || sk >= dims[2])))
+                                    continue;
+                                if (dist2(M, wrapc(si, dims[0]), wrapc(sj, dims[1]), wrapc(sk, dims[2]), X[0], X[1], X[2]) <= Rl2)
+                                    mask |= 1u << e;
                             }
                         }
-                        if (!ok) continue;
-                        const int yc = (c[2] * dims[1] + c[1]) * dims[0] + c[0];
-                        if (cur[yc] >= 0) continue;
-                        bool inside = dist2(M, c[0], c[1], c[2], X[0], X[1], X[2]) <= R2;
-                        for (int k = 0; k < nn && !inside; ++k)
-                            inside = dist2(M, c[0], c[1], c[2], nb[k][0], nb[k][1], nb[k][2]) <= nb[k][3] * nb[k][3];
-                        if (inside) continue;
-                        double rr = 0.0;
-                        for (int d = 0; d < kQ; ++d) rr += (double)ld<P>(Bn, d * nc + yc, d, rho_ff);
-                        sum += rr;
-                        cnt += 1;
                     }
-                    const double rbar = cnt > 0 ? sum / cnt : M->rho_f;
-                    const double *Vp = Vs + 3 * p, *Wp = Ws + 3 * p;
-                    const double vb0 = Vp[0] + (Wp[1] * r2 - Wp[2] * r1);
-                    const double vb1 = Vp[1] + (Wp[2] * r0 - Wp[0] * r2);
-                    const double vb2 = Vp[2] + (Wp[0] * r1 - Wp[1] * r0);
-                    const double uu = vb0 * vb0 + vb1 * vb1 + vb2 * vb2;
-#pragma unroll
-                    for (int d = 0; d < kQ; ++d)
-                        st<P>(Bn, d * nc + cell, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
-                    const double m0 = rbar * vb0, m1 = rbar * vb1, m2 = rbar * vb2;
-                    acc[0] -= m0; acc[1] -= m1; acc[2] -= m2;
-                    acc[3] -= r1 * m2 - r2 * m1;
-                    acc[4] -= r2 * m0 - r0 * m2;
-                    acc[5] -= r0 * m1 - r1 * m0;
                 }
+                int tcount = 0;
+                const int rk = block_rank(in_list, tcount, cnt4);
+                if (in_list) {
+                    const int slot = lcount + rk;
+                    if (slot < s.lcap) {
+                        s.lcell[lbase + slot] = cell;
+                        s.ldr[lbase + slot] = dref;
+                        s.lmask[lbase + slot] = mask;
+                    } else {
+                        atomicOr(s.flags, 0x40u);
+                    }
+                }
+                lcount += tcount;
             }
-            // margin: distance of the closest node to the sphere surface
             double mv = wave_min_d(mrg);
             if ((tid & 63) == 0) red[tid >> 6][7] = mv;
             __syncthreads();
             if (tid == 0) {
                 mv = fmin(fmin(red[0][7], red[1][7]), fmin(red[2][7], red[3][7]));
                 s.margin[p] = mv;
+                s.lcnt[p] = min(lcount, s.lcap);
                 s.Xref[3 * p] = X[0]; s.Xref[3 * p + 1] = X[1]; s.Xref[3 * p + 2] = X[2];
             }
             __syncthreads();
-            if (mode == 0) block_sum<6>(acc, red);
+        } else if (use_list) {
+            const int n = s.lcnt[p];
+            for (int k = tid; k < n; k += 256) {
+                if (fabs((double)s.ldr[lbase + k]) > thr + 1e-6) continue;
+                const int cell = s.lcell[lbase + k];
+                const int kk = cell / (dims[0] * dims[1]);
+                const int rem = cell - kk * dims[0] * dims[1];
+                const int jj = rem / dims[0], ii = rem - jj * dims[0];
+                evaluate(ii, jj, kk, cell, dist2(M, ii, jj, kk, X[0], X[1], X[2]));
+            }
         }
+        if (mode == 0) block_sum<6>(acc, red);
         if (mode == 0 && tid == 0) {
             for (int a = 0; a < 3; ++a) { s.Ph[3 * p + a] = acc[a]; s.Lh[3 * p + a] = acc[3 + a]; }
-        }
-    }
-    if (mode == 0) {
-        __syncthreads();
-        if (tid == 0) {
-            __threadfence();
-            const unsigned v = atomicAdd(s.k3done, 1u);
-            if (v == gridDim.x - 1) {
-                *s.k3done = 0u;
-                *s.tstep = t + 1;
-                __threadfence();
-            }
         }
     }
 }
@@ -1060,7 +1017,16 @@ void *fluid_kernel_ptr(int prec)
     default: return (void *)&k_fluid<PREC_BF16DEV>;
     }
 }
-void *particles_kernel_ptr() { return (void *)&k_particles; }
+void *links_kernel_ptr(int prec)
+{
+    switch (prec) {
+    case PREC_FP64: return (void *)&k_links<PREC_FP64>;
+    case PREC_FP32: return (void *)&k_links<PREC_FP32>;
+    case PREC_FP16DEV: return (void *)&k_links<PREC_FP16DEV>;
+    default: return (void *)&k_links<PREC_BF16DEV>;
+    }
+}
+void *motion_kernel_ptr() { return (void *)&k_motion; }
 void *remap_kernel_ptr_prec(int prec)
 {
     switch (prec) {
@@ -1070,8 +1036,9 @@ void *remap_kernel_ptr_prec(int prec)
     default: return (void *)&k_remap<PREC_BF16DEV>;
     }
 }
-int particles_grid(const DevSet &s) { return max(s.ptot + s.nprobe_total, 1); }
-int remap_grid(const DevSet &s) { return max(s.ptot, 1); }
+int links_grid(const DevSet &s) { return max(s.ptot * kChunks, 1); }
+int motion_grid(const DevSet &s) { return max(s.ptot, 1); }
+int remap_grid(const DevSet &s) { return max(s.ptot + s.nprobe_total, 1); }
 
 hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st)
 {
@@ -1084,9 +1051,22 @@ hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_particles(const DevSet &s, int mode, int only_member, hipStream_t st)
+hipError_t launch_links(int prec, const DevSet &s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_particles, dim3(particles_grid(s)), dim3(256), 0, st, s, mode, only_member);
+    const dim3 g(links_grid(s));
+    const int mode = 0, only = -1;
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL(k_links<PREC_FP64>, g, dim3(256), 0, st, s, mode, only); break;
+    case PREC_FP32: hipLaunchKernelGGL(k_links<PREC_FP32>, g, dim3(256), 0, st, s, mode, only); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL(k_links<PREC_FP16DEV>, g, dim3(256), 0, st, s, mode, only); break;
+    default: hipLaunchKernelGGL(k_links<PREC_BF16DEV>, g, dim3(256), 0, st, s, mode, only); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_motion(const DevSet &s, int mode, int only_member, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_motion, dim3(motion_grid(s)), dim3(256), 0, st, s, mode, only_member);
     return hipGetLastError();
 }
 

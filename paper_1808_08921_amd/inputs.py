@@ -81,7 +81,7 @@ def wave_fcc_case(seed: int = 0, ncx: int = 4, ncy: int = 4, ncz: int = 16, a: f
                   bc=(PERIODIC, PERIODIC, PERIODIC, PERIODIC, PRESSURE, PRESSURE),
                   wave=WAVE_COSINE, amp=amp, omega=2.0 * math.pi / period, t_n=int(round(period)),
                   E=10.37, nu=0.2, mu=0.0, rho_p=2.466,
-                  probe_z=tuple(range(0, nz, 16)))
+                  probe_z=tuple(range(0, nz, 16)), max_radius=float(np.ceil(pk["radius"].max())))
     return params, pk
 
 
@@ -95,7 +95,8 @@ def settling_case(n: int = 32, radius: float = 6.0, density_ratio: float = 2.0, 
     vol = 4.0 / 3.0 * math.pi * radius ** 3
     fg = np.array([[0.0, 0.0, -(density_ratio - 1.0) * vol * g]])
     params = dict(nx=n, ny=n, nz=n, tau=tau, rho_f=1.0, bc=(WALL,) * 6, wave=WAVE_NONE, amp=0.0,
-                  omega=0.0, t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=density_ratio, probe_z=())
+                  omega=0.0, t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=density_ratio, probe_z=(),
+                  max_radius=float(radius))
     pk = {"x": np.array([centre], dtype=np.float64), "radius": np.array([radius]),
           "fixed": np.zeros(1, np.uint8), "fg": fg, "shape": (n, n, n)}
     return params, pk

@@ -23,12 +23,11 @@ FP64, FP32, FP16DEV, BF16DEV = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16DEV, "fp16dev": FP16DEV, "bf16": BF16DEV, "bf16dev": BF16DEV}
 MAX_PROBES = 64
 
-STATUS_WAVE_SLOT_OVERFLOW = 0x1
 STATUS_NEAR_OVERFLOW = 0x2
 STATUS_CHANGE_OVERFLOW = 0x4
 STATUS_HISTORY_OVERFLOW = 0x8
 STATUS_TOO_FAST = 0x10
-STATUS_NODE_SLOT_OVERFLOW = 0x20
+STATUS_SHELL_OVERFLOW = 0x40
 
 
 class LbdemError(RuntimeError):
@@ -48,6 +47,7 @@ class Params(ctypes.Structure):
         ("rho_p", ctypes.c_double),
         ("n_probe", ctypes.c_int32), ("probe_z", ctypes.c_int32 * MAX_PROBES),
         ("max_particles", ctypes.c_int32),
+        ("max_radius", ctypes.c_double),
     ]
 
 
@@ -111,7 +111,7 @@ def _f64(a, shape):
 
 
 def make_params(nx, ny, nz, tau=1.0, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), wave=WAVE_NONE, amp=0.0, omega=0.0,
-                t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=1.0, probe_z=(), max_particles=0, **_ignored):
+                t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=1.0, probe_z=(), max_particles=0, max_radius=12.0, **_ignored):
     p = Params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     for k in range(6):
@@ -126,6 +126,7 @@ def make_params(nx, ny, nz, tau=1.0, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), wave=WAVE
     for k, z in enumerate(pz):
         p.probe_z[k] = int(z)
     p.max_particles = int(max_particles)
+    p.max_radius = float(max_radius)
     return p
 
 
@@ -245,8 +246,9 @@ class LatticeSet:
         _check(lib().lbdem_timing_enable(self._h, 1 if on else 0))
 
     def timing_read(self):
-        ms = np.zeros(3)
-        cnt = np.zeros(3, dtype=np.int64)
+        """Summed milliseconds and launch counts of the kernels: links, motion, fluid, remap."""
+        ms = np.zeros(4)
+        cnt = np.zeros(4, dtype=np.int64)
         _check(lib().lbdem_timing_read(self._h, _dp(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return ms, cnt
 
