@@ -71,6 +71,7 @@ extern "C" {
 #define LBDEM_STATUS_HISTORY_OVERFLOW 0x8u   /* tangential contact history table full (error) */
 #define LBDEM_STATUS_TOO_FAST 0x10u          /* a particle moved more than 0.25 lu in one step (error) */
 #define LBDEM_STATUS_SHELL_OVERFLOW 0x40u    /* a particle's surface-shell table overflowed (error) */
+#define LBDEM_STATUS_LINK_OVERFLOW 0x80u     /* a fluid node had links to more than four particles (error) */
 
 /* One lattice and its physics (Sec. 2; Table 1 "tab:params" for the FCC runs). */
 typedef struct lbdem_params {
@@ -88,7 +89,7 @@ typedef struct lbdem_params {
     double rho_p;            /* particle density; m = rho_p 4/3 pi R^3, I = 2/5 m R^2 */
     int32_t n_probe;         /* number of probe planes (0..LBDEM_MAX_PROBES) */
     int32_t probe_z[LBDEM_MAX_PROBES]; /* z index of each probe plane */
-    int32_t max_particles;   /* particle capacity of this lattice (>= 0) */
+    int32_t max_particles;   /* particle capacity of this lattice (0 .. 8191) */
     double max_radius;       /* largest particle radius this lattice will hold (sizes per-particle tables) */
 } lbdem_params;
 

@@ -73,6 +73,7 @@ struct Geometry {
     int ring_len = 1;
     int chg_cap = 0;
     int lcap = 1;
+    int bcap = 1;
     int prec = PREC_FP32;
 };
 
@@ -113,7 +114,7 @@ int validate(int32_t n, const lbdem_params *lat, const lbdem_config *cfg)
             for (int k2 = 0; k2 < k; ++k2)
                 if (p.probe_z[k2] == p.probe_z[k]) return fail(LBDEM_EINVAL, "lattice %d: duplicate probe plane", m);
         }
-        if (p.max_particles < 0 || p.max_particles > (1 << 20)) return fail(LBDEM_EINVAL, "lattice %d: max_particles", m);
+        if (p.max_particles < 0 || p.max_particles > kMaxLocal) return fail(LBDEM_EINVAL, "lattice %d: max_particles", m);
         if (p.max_particles > 0 && !(p.max_radius > 0.0 && p.max_radius < 1024.0))
             return fail(LBDEM_EINVAL, "lattice %d: max_radius must be positive when particles are allowed", m);
         if (!(p.young_E >= 0.0) || !(p.poisson_nu > -1.0 && p.poisson_nu < 1.0) || !(p.friction_mu >= 0.0) ||
@@ -202,6 +203,8 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
     if (rmax > 0.0) {
         const double ro = rmax + std::sqrt(2.0) + kShell + 0.8661, ri = std::max(0.0, rmax - kShell - 0.8661);
         G.lcap = (int)std::ceil(4.0 / 3.0 * M_PI * (ro * ro * ro - ri * ri * ri)) + 64;
+        const double bo = rmax + kBand + 0.8661, bi = std::max(0.0, rmax - kBand - 0.8661);
+        G.bcap = (int)std::ceil(4.0 / 3.0 * M_PI * (bo * bo * bo - bi * bi * bi)) + 64;
     }
 }
 
@@ -220,6 +223,9 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.popB = c.take<char>(es * kQ * (size_t)G.cells);
     s.own[0] = c.take<int>(G.cells);
     s.own[1] = c.take<int>(G.cells);
+    s.lw = c.take<unsigned long long>(2 * (size_t)G.cells);
+    s.ncell_total = G.cells;
+    for (int k = 0; k < 4; ++k) s.fnode[k] = c.take<double>(4 * (size_t)G.cells);
     s.chg_cap = G.chg_cap;
     s.chg[0] = c.take<int>(2 * (size_t)G.chg_cap);
     s.chg[1] = c.take<int>(2 * (size_t)G.chg_cap);
@@ -246,6 +252,8 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.Ph = c.take<double>(3 * (size_t)P);
     s.Lh = c.take<double>(3 * (size_t)P);
     s.Xref = c.take<double>(3 * (size_t)P);
+    s.pf[0] = c.take<float>(12 * (size_t)P);
+    s.pf[1] = c.take<float>(12 * (size_t)P);
     s.margin = c.take<double>(P);
     s.fixed = c.take<int>(P);
     s.pmem = c.take<int>(P);
@@ -257,6 +265,16 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.ldr = c.take<float>((size_t)P * G.lcap);
     s.lmask = c.take<unsigned>((size_t)P * G.lcap);
     s.lcnt = c.take<int>(P);
+    s.xcell = c.take<int>((size_t)P * G.lcap);
+    s.xcnt = c.take<int>((size_t)P * kChunks);
+    s.lreb = c.take<long long>(P);
+    s.ldirty = c.take<long long>((size_t)P * kChunks);
+    s.lzr = c.take<int>(2 * (size_t)P);
+    s.lchunk = c.take<int>((size_t)P * (kChunks + 1));
+    s.bcap = G.bcap;
+    s.bcell = c.take<int>((size_t)P * G.bcap);
+    s.bdr = c.take<float>((size_t)P * G.bcap);
+    s.bcnt = c.take<int>(P);
     for (int k = 0; k < 2; ++k) {
         s.hj[k] = c.take<int>((size_t)P * kHistCap);
         s.hf[k] = c.take<double>((size_t)P * kHistCap * 3);
@@ -349,21 +367,21 @@ int build_graph(lbdem_set *S, int steps)
         kp.blockDim = dim3(256);
         kp.sharedMemBytes = 0;
         kp.extra = nullptr;
-        kp.func = links_kernel_ptr(S->G.prec);
-        kp.gridDim = dim3(links_grid(S->ds));
-        kp.kernelParams = part_args;
-        HIPCHK(hipGraphAddKernelNode(&n0, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
-        kp.func = motion_kernel_ptr();
-        kp.gridDim = dim3(motion_grid(S->ds));
-        HIPCHK(hipGraphAddKernelNode(&n1, S->graph, &n0, 1, &kp));
+        // fluid -> links -> motion -> re-projection
         kp.func = fluid_kernel_ptr(S->G.prec);
         kp.gridDim = dim3(S->ds.tiles_total);
         kp.kernelParams = fluid_args;
-        HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n1, 1, &kp));
+        HIPCHK(hipGraphAddKernelNode(&n2, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        kp.func = links_kernel_ptr(S->G.prec);
+        kp.gridDim = dim3(links_grid(S->ds));
+        kp.kernelParams = part_args;
+        HIPCHK(hipGraphAddKernelNode(&n0, S->graph, &n2, 1, &kp));
+        kp.func = motion_kernel_ptr();
+        kp.gridDim = dim3(motion_grid(S->ds));
+        HIPCHK(hipGraphAddKernelNode(&n1, S->graph, &n0, 1, &kp));
         kp.func = remap_kernel_ptr_prec(S->G.prec);
         kp.gridDim = dim3(remap_grid(S->ds));
-        kp.kernelParams = part_args;
-        HIPCHK(hipGraphAddKernelNode(&n3, S->graph, &n2, 1, &kp));
+        HIPCHK(hipGraphAddKernelNode(&n3, S->graph, &n1, 1, &kp));
         prev = n3;
     }
     HIPCHK(hipGraphInstantiate(&S->gexec, S->graph, nullptr, nullptr, 0));
@@ -389,7 +407,11 @@ int harvest_events(lbdem_set *S)
 
 int launch_step_eager(lbdem_set *S)
 {
-    for (int k = 0; k < kKernels; ++k) {
+    // launch order fluid, links, motion, re-projection; timing slots keep the order
+    // links, motion, fluid, re-projection of lbdem_timing_read
+    static const int order[kKernels] = {2, 0, 1, 3};
+    for (int o = 0; o < kKernels; ++o) {
+        const int k = order[o];
         int e0 = -1, e1 = -1;
         if (S->timing) {
             if (S->ev_next + 2 > S->ev_pool.size()) {
@@ -535,6 +557,7 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     const int P = std::max(S->G.ptot, 1);
     CHK(hipMemsetAsync(s.own[0], 0xff, sizeof(int) * S->G.cells, st));
     CHK(hipMemsetAsync(s.own[1], 0xff, sizeof(int) * S->G.cells, st));
+    CHK(hipMemsetAsync(s.lw, 0, sizeof(unsigned long long) * 2 * S->G.cells, st));
     CHK(hipMemsetAsync(s.chgcnt, 0, sizeof(int) * 2, st));
     CHK(hipMemsetAsync(s.pprt, 0, sizeof(double) * S->G.tiles * S->G.nzt * 4, st));
     CHK(hipMemsetAsync(s.ring, 0, sizeof(double) * S->G.ring_doubles, st));
@@ -547,8 +570,16 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     double *zero3[] = {s.Fg, s.Fh, s.Th, s.Ph, s.Lh, s.Xref};
     for (double *z : zero3) CHK(hipMemsetAsync(z, 0, sizeof(double) * 3 * P, st));
     CHK(hipMemsetAsync(s.margin, 0, sizeof(double) * P, st));
+    CHK(hipMemsetAsync(s.pf[0], 0, sizeof(float) * 12 * P, st));
+    CHK(hipMemsetAsync(s.pf[1], 0, sizeof(float) * 12 * P, st));
     CHK(hipMemsetAsync(s.nnear, 0, sizeof(int) * P, st));
     CHK(hipMemsetAsync(s.lcnt, 0, sizeof(int) * P, st));
+    CHK(hipMemsetAsync(s.xcnt, 0, sizeof(int) * P * kChunks, st));
+    CHK(hipMemsetAsync(s.bcnt, 0, sizeof(int) * P, st));
+    CHK(hipMemsetAsync(s.lreb, 0xff, sizeof(long long) * P, st));
+    CHK(hipMemsetAsync(s.ldirty, 0xff, sizeof(long long) * P * kChunks, st));
+    CHK(hipMemsetAsync(s.lzr, 0, sizeof(int) * 2 * P, st));
+    CHK(hipMemsetAsync(s.lchunk, 0, sizeof(int) * P * (kChunks + 1), st));
     CHK(hipMemsetAsync(s.tstep, 0, sizeof(long long), st));
     CHK(hipMemsetAsync(s.tcopy, 0, sizeof(long long), st));
     CHK(hipMemsetAsync(s.flags, 0, sizeof(unsigned), st));
@@ -743,7 +774,7 @@ int lbdem_status(lbdem_set *S, uint32_t *bits, int clear)
     *bits = f;
     if (clear) HIPCHK(hipMemset(S->ds.flags, 0, sizeof(unsigned)));
     const unsigned errs = LBDEM_STATUS_NEAR_OVERFLOW | LBDEM_STATUS_HISTORY_OVERFLOW | LBDEM_STATUS_TOO_FAST |
-                          LBDEM_STATUS_SHELL_OVERFLOW;
+                          LBDEM_STATUS_SHELL_OVERFLOW | LBDEM_STATUS_LINK_OVERFLOW;
     if (f & errs) return fail(LBDEM_ECAPACITY, "device status 0x%x", f);
     return LBDEM_OK;
 }

@@ -13,13 +13,20 @@
 namespace lbdem {
 
 constexpr int kQ = 19;
-constexpr int kWaveSlots = 12;     // link-force partial slots per wavefront tile
 constexpr int kNearCap = 32;       // near-neighbour table per particle
 constexpr int kHistCap = 16;       // tangential contact history per particle
 constexpr double kNearMargin = 3.0; // near list: |X_p - X_q| <= R_p + R_q + margin
 constexpr double kShell = 0.5;      // skin of the per-particle shell lists (lattice units)
+constexpr double kBand = 0.15;      // half-width of the surface band list (lattice units)
 constexpr int kChunks = 8;          // workgroups per particle in the particle kernel
 constexpr int kEmpty = 0x7fffffff;
+// Link words of a fluid node x (two 64-bit words per node: lw[c] and lw[ncell_total + c]).
+// Word 0: bits 0-17 the directions e whose source x - c_e is inside a particle, bits 18-35
+// the low bit of the slot (0..3) of the particle owning that source, bits 36-48 and 49-61
+// the local indices of the particles in slots 0 and 1, bit 62 set when slots 2 or 3 are
+// used, bit 63 when more than four particles border x.  Word 1: bits 0-17 the high slot
+// bit per direction, bits 18-30 and 31-43 the local indices in slots 2 and 3.
+constexpr int kMaxLocal = 8191;     // particles per lattice (13-bit local indices)
 
 // Per-lattice constants (one entry per lattice of the set).
 struct MemberDev {
@@ -55,6 +62,11 @@ struct DevSet {
     void *popA, *popB;
     // node maps (index = parity), change lists (pairs cell, owner) and counts
     int *own[2];
+    unsigned long long *lw;   // link words, two per node (all lattices) [2*ncell_total]
+    long long ncell_total;
+    // link force sum c_d (f~_d + f_e) over a fluid node's links to the particle in each
+    // slot of its link words: FP64 records (x, y, z, unused) [ncell_total][4] per slot
+    double *fnode[4];
     int *chg[2];
     int chg_cap;
     int *chgcnt;              // [2]
@@ -70,6 +82,7 @@ struct DevSet {
     int ptot;
     double *X[2], *V[2], *W[2];
     double *R, *m, *I, *Fg, *Fh, *Th, *Ph, *Lh, *Xref, *margin;
+    float *pf[2];             // FP32 copy of X, V, Omega per particle (12 floats), by parity
     int *fixed, *pmem;
     double *ppart;            // link-force partials per (particle, chunk) [ptot*kChunks*6]
     int *nearl, *nnear;       // [ptot*kNearCap], [ptot]
@@ -78,6 +91,19 @@ struct DevSet {
     int *lcell, *lcnt;
     float *ldr;
     unsigned *lmask;
+    // the shell-list entries that hold links of the particle: each chunk of a list keeps
+    // its own compacted run [ptot*lcap], counts [ptot*kChunks]
+    int *xcell, *xcnt;
+    long long *lreb;          // step after which the shell list was last rebuilt [ptot]
+    long long *ldirty;        // last step in which a node of a chunk's z-slab, or next to
+                              // it, changed owner [ptot*kChunks]
+    // chunks are z-slabs of the list's scan box: first z (unwrapped), slab height, and
+    // the list offset where each chunk starts [ptot*2], [ptot*(kChunks+1)]
+    int *lzr, *lchunk;
+    // surface band: shell-list entries with |d_ref - R| <= kBand [ptot*bcap], [ptot]
+    int bcap;
+    int *bcell, *bcnt;
+    float *bdr;
     int *hj[2];               // tangential history partner ids [ptot*kHistCap]
     double *hf[2];            // tangential history forces [ptot*kHistCap*3]
     int *hn[2];               // history counts [ptot]

@@ -3,18 +3,19 @@
 // Method: Cheng, Luding, Rivas, Harting, Magnanimo, "Hydro-micromechanical modeling of
 // wave propagation in saturated granular media", arXiv 1808.08921, Sec. 2.
 //
-// Four kernels make one time step t -> t+1 of every lattice of a set:
-//   k_links      kChunks workgroups per particle: find the particle's links (fluid node
-//                x, direction e, source x - c_e inside the particle) on its shell list,
-//                write the bounced moving-wall population of Eq. (mem) into the solid
-//                source's slot of direction e, and sum the link forces and torques
-//                (Eq. fFS) in a fixed order.
+// Four kernels make one time step t -> t+1 of every lattice of a set, in this order:
+//   k_fluid      one thread per (x, y) column of a tile, nzt planes deep: refreshes the
+//                tile's link words from the previous step's node changes, then pull
+//                streaming (Eq. stream) with stationary walls and, from each link of a
+//                fluid node to a particle, the moving-wall bounce-back of Eq. (mem); the
+//                density faces (Sec. 2.4), BGK collision (Eqs. bgk, BGKequili, rhoAndU),
+//                probe partial sums, and per node and particle the sum c_d f~_d over its
+//                links for the momentum exchange.
+//   k_links      kChunks workgroups per particle: the link force and torque of Eq. (fFS)
+//                over the particle's shell list, summed in a fixed order.
 //   k_motion     one workgroup per particle: Eqs. (coupleF), (coupleT) with the
 //                conversion impulses of the previous re-projection, Hertz / Mindlin
 //                contacts (Eqs. fdLawn, fdLaws), symplectic Euler (Eqs. translate, rotate).
-//   k_fluid      one thread per (x, y) column of a tile, nzt planes deep: pull streaming
-//                (Eq. stream), stationary walls, the density faces (Sec. 2.4), BGK
-//                collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.
 //   k_remap      one workgroup per particle: re-projects the particle on the lattice
 //                (Sec. 2.3) where its motion can have changed a node, converts covered
 //                and uncovered nodes (Eqs. convertFS, convertSF) and records the
@@ -31,6 +32,10 @@ constexpr int kCX[kQ] = {1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0,
 constexpr int kCY[kQ] = {0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0};
 constexpr int kCZ[kQ] = {0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1, 0};
 constexpr int kOPP[kQ] = {1, 0, 3, 2, 5, 4, 11, 10, 13, 12, 7, 6, 9, 8, 17, 16, 15, 14, 18};
+// the same components in device memory, for a direction known only at run time
+__constant__ int kCXd[kQ] = {1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0, 0};
+__constant__ int kCYd[kQ] = {0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0};
+__constant__ int kCZd[kQ] = {0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1, 0};
 // lattice weights (Sec. 2.1): 1/18 along the axes, 1/36 on the diagonals, 1/3 at rest
 constexpr double kWd[kQ] = {1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
@@ -87,6 +92,15 @@ __device__ __forceinline__ typename Prec<P>::C ld(const typename Prec<P>::S *a, 
         return (float)kWd[d] * (rho_f + bf16_to_f32(ldo(a, idx)));
     }
 }
+// decode a stored value of population d
+template <int P>
+__device__ __forceinline__ typename Prec<P>::C decode(typename Prec<P>::S v, int d, float rho_f)
+{
+    if constexpr (P == PREC_FP64 || P == PREC_FP32) return v;
+    else if constexpr (P == PREC_FP16DEV) return (float)kWd[d] * (rho_f + (float)v);
+    else return (float)kWd[d] * (rho_f + bf16_to_f32(v));
+}
+
 // encode population d to storage: 16-bit forms hold q = f / w_d - rho_f
 template <int P>
 __device__ __forceinline__ void st(typename Prec<P>::S *a, unsigned idx, int d, typename Prec<P>::C f, float rho_f)
@@ -110,6 +124,8 @@ __device__ __forceinline__ int xcd_swizzle(int b, int G)
     const int q = G >> 3, r = G & 7, x = b & 7, k = b >> 3;
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
+
+__device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
 __device__ __forceinline__ double mimg(double dx, int per, double n)
 {
@@ -287,15 +303,178 @@ __device__ __forceinline__ C feq(int d, C rho, C ux, C uy, C uz, C uu)
 }
 
 // ---------------------------------------------------------------------------
+// link words
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ const MemberDev *member_of_cell(const DevSet &s, long long c)
+{
+    int lo = 0, hi = s.nmem - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.mem[mid].cell_off <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    return s.mem + lo;
+}
+
+// Link words of node (i, j, k) of lattice M from the node map own (this lattice's part):
+// for a fluid node x, the directions e whose source x - c_e lies inside a particle and the
+// slot (0..3, in the order the particles are met) of the particle owning each source.
+__device__ void link_words(const MemberDev *M, const int *own, int i, int j, int k, unsigned long long &w0,
+                           unsigned long long &w1)
+{
+    const int nx = M->nx, ny = M->ny, nz = M->nz;
+    w0 = 0ull;
+    w1 = 0ull;
+    if (own[(k * ny + j) * nx + i] >= 0) return;
+    unsigned mask = 0u, lo = 0u, hi = 0u;
+    int id[4] = {-1, -1, -1, -1};
+    int nid = 0;
+    bool over = false;
+#pragma unroll 1
+    for (int e = 0; e < kQ - 1; ++e) {
+        int c[3] = {i - kCXd[e], j - kCYd[e], k - kCZd[e]};
+        const int dims[3] = {nx, ny, nz};
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            if (c[a] < 0 || c[a] >= dims[a]) {
+                if (M->per[a]) c[a] = c[a] < 0 ? c[a] + dims[a] : c[a] - dims[a];
+                else ok = false;
+            }
+        }
+        if (!ok) continue;
+        const int o = own[(c[2] * ny + c[1]) * nx + c[0]];
+        if (o < 0) continue;
+        const int q = o - M->p_off;
+        int sl = 0;
+        while (sl < nid && id[sl] != q) ++sl;
+        if (sl == nid) {
+            if (nid == 4) { over = true; continue; }
+            id[nid++] = q;
+        }
+        mask |= 1u << e;
+        if (sl & 1) lo |= 1u << e;
+        if (sl & 2) hi |= 1u << e;
+    }
+    if (mask == 0u && !over) return;
+    w0 = (unsigned long long)mask | ((unsigned long long)lo << 18) |
+         ((unsigned long long)max(id[0], 0) << 36) | ((unsigned long long)max(id[1], 0) << 49) |
+         ((unsigned long long)(nid > 2) << 62) | ((unsigned long long)over << 63);
+    w1 = (unsigned long long)hi | ((unsigned long long)max(id[2], 0) << 18) | ((unsigned long long)max(id[3], 0) << 31);
+}
+
+// Directions of slot g and the slot's local particle index, from the two link words.
+__device__ __forceinline__ unsigned slot_dirs(unsigned long long w0, unsigned long long w1, int g, int &id)
+{
+    const unsigned mask = (unsigned)w0 & 0x3ffffu, lo = (unsigned)(w0 >> 18) & 0x3ffffu;
+    const unsigned hi = (unsigned)w1 & 0x3ffffu;
+    id = (g == 0) ? (int)(w0 >> 36) & 0x1fff : (g == 1) ? (int)(w0 >> 49) & 0x1fff
+       : (g == 2) ? (int)(w1 >> 18) & 0x1fff : (int)(w1 >> 31) & 0x1fff;
+    return mask & ((g & 1) ? lo : ~lo) & ((g & 2) ? hi : ~hi);
+}
+
+// ---------------------------------------------------------------------------
 // fluid kernel
 // ---------------------------------------------------------------------------
-// Pull streaming (Eq. stream), stationary half-way walls, the density faces (Sec. 2.4),
-// BGK collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.  A source node
-// inside a particle needs no special case here: the particle kernel of the same step
-// has already written the bounced, moving-wall population f_e (Eq. mem) into that
-// solid node's own slot of direction e, which is read by this node only.
+// FP32 copy of a particle's state for the fluid kernel: X, V, Omega, padding
+__device__ __forceinline__ void pack_state(float *o, const double *X, const double *V, const double *W)
+{
+    for (int a = 0; a < 3; ++a) { o[a] = (float)X[a]; o[4 + a] = (float)V[a]; o[8 + a] = (float)W[a]; }
+    o[3] = o[7] = o[11] = 0.0f;
+}
+
+__device__ __forceinline__ float mimg_f(float dx, int per, float n)
+{
+    if (per) {
+        if (dx > 0.5f * n) dx -= n;
+        else if (dx < -0.5f * n) dx += n;
+    }
+    return dx;
+}
+
+// V_b = V + Omega x r at node (i, j, k) from a packed FP32 state q (X, V, Omega)
+__device__ __forceinline__ void wall_velocity_f(const MemberDev *M, const float4 (&q)[3], int i, int j, int k,
+                                                float &u0, float &u1, float &u2)
+{
+    const float r0 = mimg_f((float)i - q[0].x, M->per[0], (float)M->box[0]);
+    const float r1 = mimg_f((float)j - q[0].y, M->per[1], (float)M->box[1]);
+    const float r2 = mimg_f((float)k - q[0].z, M->per[2], (float)M->box[2]);
+    u0 = q[1].x + (q[2].y * r2 - q[2].z * r1);
+    u1 = q[1].y + (q[2].z * r0 - q[2].x * r2);
+    u2 = q[1].z + (q[2].x * r1 - q[2].y * r0);
+}
+
+// Velocity of particle q's surface point nearest to node (i, j, k), V_b = V + Omega x r
+// with r = x - X (minimum image), in the collision precision C; used with c_d . V_b for
+// the link (x, d).
+template <typename C>
+__device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *M, int q, int i, int j, int k,
+                                              int par, C &u0, C &u1, C &u2)
+{
+    const double *X = s.X[par] + 3 * q, *V = s.V[par] + 3 * q, *W = s.W[par] + 3 * q;
+    const C r0 = (C)mimg((double)i - X[0], M->per[0], M->box[0]);
+    const C r1 = (C)mimg((double)j - X[1], M->per[1], M->box[1]);
+    const C r2 = (C)mimg((double)k - X[2], M->per[2], M->box[2]);
+    const C w0 = (C)W[0], w1 = (C)W[1], w2 = (C)W[2];
+    u0 = (C)V[0] + (w1 * r2 - w2 * r1);
+    u1 = (C)V[1] + (w2 * r0 - w0 * r2);
+    u2 = (C)V[2] + (w0 * r1 - w1 * r0);
+}
+
+// Eq. (mem) for the links of a fluid node: f_e = f~_d(x,t) - 2 (w_d / c_s^2) rho_f V_b . c_d,
+// d = e*, for every direction e whose source is inside a particle; f[e] holds f~_d(x,t).
+// For the momentum exchange of Eq. (fFS), F = sum c_d (f~_d + f_e) = 2 G - K V_b with
+// G = sum c_d f~_d over the node's links to one particle and K = sum 2 (w_d / c_s^2) rho_f
+// c_d c_d^T; the node stores G per slot of its link words (collision precision) and the
+// link kernel adds the wall-velocity part.
+template <typename C>
+__device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M, C (&f)[kQ], unsigned long long w0,
+                                            int i, int j, int k, int par, double rho_f, long long gc)
+{
+    const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + gc] : 0ull;
+    const int ng = (w0 >> 62) ? 4 : 2;
+#pragma unroll 1
+    for (int g = 0; g < ng; ++g) {
+        int q;
+        const unsigned grp = slot_dirs(w0, w1, g, q);
+        if (grp == 0u) continue;
+        C u0, u1, u2;
+        if constexpr (sizeof(C) == 4) {
+            const float4 *pq = reinterpret_cast<const float4 *>(s.pf[par] + 12 * (M->p_off + q));
+            const float4 qq[3] = {pq[0], pq[1], pq[2]};
+            wall_velocity_f(M, qq, i, j, k, u0, u1, u2);
+        } else {
+            wall_velocity<C>(s, M, M->p_off + q, i, j, k, par, u0, u1, u2);
+        }
+        C G0 = C(0), G1 = C(0), G2 = C(0);
+#pragma unroll
+        for (int e = 0; e < kQ - 1; ++e) {
+            if (!((grp >> e) & 1u)) continue;
+            const int d = kOPP[e];
+            C cu = C(0);
+            if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
+            if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
+            if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
+            const C fo = f[e];
+            f[e] = fo - (C)(kMW[d] * rho_f) * cu;
+            if (kCX[d] > 0) G0 += fo; else if (kCX[d] < 0) G0 -= fo;
+            if (kCY[d] > 0) G1 += fo; else if (kCY[d] < 0) G1 -= fo;
+            if (kCZ[d] > 0) G2 += fo; else if (kCZ[d] < 0) G2 -= fo;
+        }
+        if constexpr (sizeof(C) == 4) {
+            reinterpret_cast<float4 *>(s.fnode[g])[gc] = make_float4(G0, G1, G2, 0.0f);
+        } else {
+            double2 *fn = reinterpret_cast<double2 *>(s.fnode[g] + 4 * gc);
+            fn[0] = make_double2(G0, G1);
+            fn[1] = make_double2(G2, 0.0);
+        }
+    }
+}
+
+// Pull streaming (Eq. stream), stationary half-way walls, moving half-way walls on the
+// particles (Eq. mem, from the node's link words), the density faces (Sec. 2.4), BGK
+// collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.
 template <int P>
-__global__ __launch_bounds__(256) void k_fluid(DevSet s)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 3 : 5))) void k_fluid(DevSet s)
 {
     using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
@@ -348,6 +527,48 @@ __global__ __launch_bounds__(256) void k_fluid(DevSet s)
     const C rho_out = (C)rho_fd;
     const int pz_off = uni(M->pz_off);
 
+    // link words of this tile from the node map of step t: all of them after a set-up or
+    // an overflowed change list, else those of the previous step's changed nodes and
+    // their neighbours (each word belongs to the one tile holding its node)
+    {
+        const int x0 = tx << bxl, y0 = ty * uni(M->by);
+        const int *ownm = s.own[par] + cell_off;
+        bool over = false;
+        if (full_copy) {
+            if (vij)
+                for (int z = z0; z < z1; ++z) {
+                    const long long gc = cell_off + (z * ny + j) * nx + i;
+                    unsigned long long w0, w1;
+                    link_words(M, ownm, i, j, z, w0, w1);
+                    s.lw[gc] = w0;
+                    s.lw[s.ncell_total + gc] = w1;
+                    over |= (w0 >> 63) != 0ull;
+                }
+        } else if (prev_cnt > 0) {
+            const int *lst = s.chg[par ^ 1];
+            for (int e = threadIdx.x; e < prev_cnt; e += blockDim.x) {
+                const long long gcell = lst[2 * e];
+                if (gcell < cell_off || gcell >= cell_off + nc) continue;
+                const int c0 = (int)(gcell - cell_off);
+                const int k0 = c0 / nxy, rem = c0 - k0 * nxy, j0 = rem / nx, i0 = rem - j0 * nx;
+                for (int q = 0; q < kQ; ++q) {
+                    const int ci = wrapc(i0 + kCX[q], nx), cj = wrapc(j0 + kCY[q], ny), ck = wrapc(k0 + kCZ[q], nz);
+                    if (ci < x0 || ci >= x0 + (1 << bxl) || cj < y0 || cj >= y0 + uni(M->by) || ck < z0 || ck >= z1)
+                        continue;
+                    const long long gc = cell_off + (ck * ny + cj) * nx + ci;
+                    unsigned long long w0, w1;
+                    link_words(M, ownm, ci, cj, ck, w0, w1);
+                    s.lw[gc] = w0;
+                    s.lw[s.ncell_total + gc] = w1;
+                    over |= (w0 >> 63) != 0ull;
+                }
+            }
+        }
+        if (over) atomicOr(s.flags, 0x80u);
+        __threadfence_block();
+        __syncthreads();
+    }
+
     // offsets to the x-1 / x+1 / y-1 / y+1 neighbours (wrapped on periodic axes) and the
     // kind of face crossed to reach them (0 inside or periodic, 1 wall, 2 density face)
     int oxm = (i > 0) ? -1 : (nx - 1), oxp = (i < nx - 1) ? 1 : -(nx - 1);
@@ -367,34 +588,58 @@ __global__ __launch_bounds__(256) void k_fluid(DevSet s)
             if (full_copy) nmap[cell] = o;
         }
         double pr0 = 0.0, pr1 = 0.0, pr2 = 0.0, pr3 = 0.0;
-        if (fl) {
+        // With 4- and 8-byte storage every node of the row is written, so each store
+        // covers whole cache lines: a solid node loads nothing and stores the rest state
+        // w_d, a value that is never read (its slots are refilled by the link kernel or on
+        // uncovering).  16-bit storage measured faster with solid nodes left out.
+        constexpr bool kWholeRows = sizeof(S) >= 4;
+        if (kWholeRows ? vij : fl) {
             const int ozm = (z > 0) ? -nxy : (nz - 1) * nxy, ozp = (z < nz - 1) ? nxy : -(nz - 1) * nxy;
             const int kzm = (z > 0) ? 0 : bc4, kzp = (z < nz - 1) ? 0 : bc5;
+            // Loads are issued for every lane, a solid lane reading the first element of the
+            // array (one shared line) instead of branching around each load.
+            const unsigned long long lwr = s.lw[fl ? cell_off + cell : 0];
+            const unsigned long long lwv = fl ? lwr : 0ull;
+            const unsigned lmask = (unsigned)lwv & 0x3ffffu;
             C f[kQ];
+            S raw[kQ];
+            unsigned unk = 0u;
 #pragma unroll
             for (int e = 0; e < kQ - 1; ++e) {
                 int off = 0, kind = 0;
                 if (kCX[e] > 0) { off += oxm; kind = max(kind, kxm); } else if (kCX[e] < 0) { off += oxp; kind = max(kind, kxp); }
                 if (kCY[e] > 0) { off += oym; kind = max(kind, kym); } else if (kCY[e] < 0) { off += oyp; kind = max(kind, kyp); }
                 if (kCZ[e] > 0) { off += ozm; kind = max(kind, kzm); } else if (kCZ[e] < 0) { off += ozp; kind = max(kind, kzp); }
-                // f_e(x, t+1) = f~_e(x - c_e, t); across a wall the population comes back
-                // from this node, f~_{e*}(x, t); across a density face it is unknown
-                const unsigned idx = (kind == 0) ? (unsigned)(e * nc) + (unsigned)(cell + off)
-                                                 : (unsigned)(kOPP[e] * nc) + (unsigned)cell;
-                const C v = ld<P>(A, idx, e, rho_ff);
-                f[e] = (kind == BC_PRESSURE) ? C(0) : v;
+                // f_e(x, t+1) = f~_e(x - c_e, t); from a wall or a particle the population
+                // comes back from this node, f~_{e*}(x, t); across a density face it is unknown
+                const bool back = (kind != 0) || ((lmask >> e) & 1u);
+                const unsigned idx = back ? (unsigned)(kOPP[e] * nc) + (unsigned)cell
+                                          : (unsigned)(e * nc) + (unsigned)(cell + off);
+                raw[e] = ldo(A, fl ? idx : 0u);
+                unk |= (kind == BC_PRESSURE) ? (1u << e) : 0u;
             }
-            f[18] = ld<P>(A, (unsigned)(18 * nc) + (unsigned)cell, 18, rho_ff);
+            raw[18] = ldo(A, fl ? (unsigned)(18 * nc) + (unsigned)cell : 0u);
+            // every load is in flight before the first use (no branch between them)
+            asm volatile("" : "+v"(raw[0]), "+v"(raw[1]), "+v"(raw[2]), "+v"(raw[3]), "+v"(raw[4]), "+v"(raw[5]),
+                              "+v"(raw[6]), "+v"(raw[7]), "+v"(raw[8]), "+v"(raw[9]), "+v"(raw[10]), "+v"(raw[11]),
+                              "+v"(raw[12]), "+v"(raw[13]), "+v"(raw[14]), "+v"(raw[15]), "+v"(raw[16]),
+                              "+v"(raw[17]), "+v"(raw[18]));
+#pragma unroll
+            for (int e = 0; e < kQ; ++e)
+                f[e] = fl ? (((unk >> e) & 1u) ? C(0) : decode<P>(raw[e], e, rho_ff)) : (C)kWd[e];
+            if (lmask != 0u) moving_wall<C>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell);
 
             if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, rho_in, false);
             if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, rho_out, true);
 
             C rho, jx, jy, jz;
             moments<C>(f, rho, jx, jy, jz);
-            pr0 = 1.0;
-            pr1 = (double)rho - rho_fd;
-            pr2 = (double)jz;
-            pr3 = (double)rho;
+            if (fl) {
+                pr0 = 1.0;
+                pr1 = (double)rho - rho_fd;
+                pr2 = (double)jz;
+                pr3 = (double)rho;
+            }
             const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
             const C uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
@@ -443,22 +688,22 @@ __device__ __forceinline__ void axis_range(double c, double h, int n, int per, i
     ext = max(u - l + 1, 0);
 }
 
-__device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-// Workgroups (particle p, chunk of p's shell list): the links of p, i.e. every fluid
-// node x and direction e whose source x - c_e lies in p.  Eq. (mem) gives the population
-// that returns to x, f_e = f~_d(x,t) - 2 (w_d / c_s^2) rho_f V_b . c_d with d = e*
-// pointing into p and V_b = V_p + Omega_p x (x_b - X_p) at x_b = x + c_d / 2; it is
-// stored in the solid source's slot of direction e for the fluid kernel to pull.  Since
-// x_b - X_p = (x - X_p) + c_d / 2, V_b . c_d = c_d . (V_p + Omega_p x (x - X_p)).
-// Eq. (fFS): F = c_d f~_d(x,t) - c_e f_e(x,t+1) = c_d (f~_d + f_e), torque
-// (x_b - X_p) x F = (x - X_p) x F, summed in FP64 in a fixed order per chunk.
+// Workgroups (particle p, chunk of p's shell list): the momentum exchange of p's links,
+// i.e. of every fluid node x and direction e whose source x - c_e lies in p.  With d = e*
+// pointing into p, Eq. (fFS) gives F = c_d f~_d(x,t) - c_e f_e(x,t+1) = c_d (f~_d + f_e),
+// and Eq. (mem) f_e = f~_d - 2 (w_d / c_s^2) rho_f V_b . c_d, V_b = V_p + Omega_p x
+// (x_b - X_p) at x_b = x + c_d / 2.  Since x_b - X_p = (x - X_p) + c_d / 2, V_b . c_d =
+// c_d . (V_p + Omega_p x (x - X_p)), and the torque (x_b - X_p) x F = (x - X_p) x F.  The
+// fluid kernel of the step has stored G = sum c_d f~_d over the node's links to p; here
+// F = 2 G - sum 2 (w_d / c_s^2) rho_f c_d (c_d . V_b), summed in FP64 in a fixed order per
+// chunk (Eqs. coupleF, coupleT).
 template <int P>
 __global__ __launch_bounds__(256) void k_links(DevSet s, int mode, int only)
 {
-    using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
     __shared__ double red[4][8];
+    __shared__ int cnt4[4];
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
     const int tid = threadIdx.x;
@@ -467,81 +712,124 @@ __global__ __launch_bounds__(256) void k_links(DevSet s, int mode, int only)
     if (p >= s.ptot || mode != 0) return;
     const int m = uni(s.pmem[p]);
     const MemberDev *M = s.mem + m;
-    if (p - uni(M->p_off) >= uni(M->np)) return;
+    const int pl = p - uni(M->p_off);
+    if (pl >= uni(M->np)) return;
     if (only >= 0 && m != only) return;
 
     const double *Xo = s.X[par], *Vo = s.V[par], *Wo = s.W[par];
     const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
-    const double R = s.R[p];
-    const int nx = uni(M->nx), ny = uni(M->ny), nz = uni(M->nz);
+    const int nx = uni(M->nx), ny = uni(M->ny);
     const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
     const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
+    const long long cell_off = uni(M->cell_off);
+    const double rho_f = uni(M->rho_f);
+    const int nxy = nx * ny;
+    const long long lbase = (long long)p * s.lcap;
+    const int k0 = s.lchunk[p * (kChunks + 1) + chunk], k1 = s.lchunk[p * (kChunks + 1) + chunk + 1];
+    int *xc = s.xcell + lbase + k0;
 
-    // (1) links of this chunk of the shell list
+    // Links of p at a fluid node x: the link words of x (refreshed by this step's fluid
+    // kernel) give p's slot at x, whose link-force sum the fluid kernel has stored.
+    auto links_of_p = [&](int cell, int &slot) -> unsigned {
+        const unsigned long long w0 = s.lw[cell_off + cell];
+        slot = -1;
+        if (((unsigned)w0 & 0x3ffffu) == 0u) return 0u;
+        const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + cell_off + cell] : 0ull;
+        const int ng = (w0 >> 62) ? 4 : 2;
+        for (int g = 0; g < ng; ++g) {
+            int q;
+            const unsigned grp = slot_dirs(w0, w1, g, q);
+            if (grp != 0u && q == pl) { slot = g; return grp; }
+        }
+        return 0u;
+    };
+
+    // (1) the chunk's shell-list entries that hold links of p, compacted in list order;
+    // kept from the previous step unless the list was rebuilt or a node within one plane
+    // of the chunk's slab changed owner in the previous step
+    const bool fresh = (s.lreb[p] == t - 1) || (s.ldirty[p * kChunks + chunk] == t - 1);
+    int cntx;
+    if (fresh) {
+        cntx = 0;
+        for (int base = k0; base < k1; base += 256) {
+            const int k = base + tid;
+            bool has = false;
+            int cell = 0, slot = -1;
+            if (k < k1 && s.lmask[lbase + k] != 0u) {
+                cell = s.lcell[lbase + k];
+                has = links_of_p(cell, slot) != 0u;
+            }
+            int tot = 0;
+            const int rk = block_rank(has, tot, cnt4);
+            if (has) xc[cntx + rk] = cell | (slot << 30);
+            cntx += tot;
+        }
+        if (tid == 0) s.xcnt[p * kChunks + chunk] = cntx;
+        __threadfence_block();
+        __syncthreads();
+    } else {
+        cntx = s.xcnt[p * kChunks + chunk];
+    }
+
+    // (2) Eqs. (fFS), (coupleF), (coupleT): force and torque (x - X_p) x F over the links.
+    // An entry holds the node and p's slot when the entry was made; the slot is checked
+    // against the current link words (another particle's links at the node can move p to
+    // another slot) while the record of the expected slot is already being read.
+    const double V0 = Vo[3 * p], V1 = Vo[3 * p + 1], V2 = Vo[3 * p + 2];
+    const double W0 = Wo[3 * p], W1 = Wo[3 * p + 1], W2 = Wo[3 * p + 2];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    if (mode == 0) {
-        const int nc = (int)uni(M->ncell);
-        const long long pop_off = uni(M->pop_off), cell_off = uni(M->cell_off);
-        S *A = (S *)(par ? s.popB : s.popA) + pop_off;
-        const int *own = s.own[par] + cell_off;
-        const double rho_f = uni(M->rho_f);
-        const float rho_ff = (float)rho_f;
-        const double V0 = Vo[3 * p], V1 = Vo[3 * p + 1], V2 = Vo[3 * p + 2];
-        const double W0 = Wo[3 * p], W1 = Wo[3 * p + 1], W2 = Wo[3 * p + 2];
-        const int nxy = nx * ny;
-        const long long lbase = (long long)p * s.lcap;
-        const int n = s.lcnt[p];
-        const int k0 = (int)((long long)n * chunk / kChunks), k1 = (int)((long long)n * (chunk + 1) / kChunks);
-        for (int k = k0 + tid; k < k1; k += 256) {
-            const unsigned mask = s.lmask[lbase + k];
-            if (mask == 0u) continue;
-            const int cell = s.lcell[lbase + k];
-            const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx, ii = rem - jj * nx;
-            // the node's own flag and the owners of the candidate sources: independent loads
-            int sc[kQ - 1], os[kQ - 1];
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e) {
-                sc[e] = (wrapc(kk - kCZ[e], nz) * ny + wrapc(jj - kCY[e], ny)) * nx + wrapc(ii - kCX[e], nx);
-                os[e] = (mask & (1u << e)) ? ldo(own, (unsigned)sc[e]) : -1;
+    for (int k = tid; k < cntx; k += 256) {
+        const int ent = xc[k];
+        const int cell = ent & 0x3fffffff, pred = (int)((unsigned)ent >> 30);
+        double G0, G1, G2;
+        auto read_g = [&](int sl) {
+            if constexpr (sizeof(C) == 4) {
+                const float4 v = reinterpret_cast<const float4 *>(s.fnode[sl])[cell_off + cell];
+                G0 = v.x; G1 = v.y; G2 = v.z;
+            } else {
+                const double2 *fp = reinterpret_cast<const double2 *>(s.fnode[sl] + 4 * (cell_off + cell));
+                const double2 a = fp[0], b = fp[1];
+                G0 = a.x; G1 = a.y; G2 = b.x;
             }
-            if (ldo(own, (unsigned)cell) >= 0) continue; // x is not fluid
-            const double r0 = mimg((double)ii - X0, per0, box0);
-            const double r1 = mimg((double)jj - X1, per1, box1);
-            const double r2 = mimg((double)kk - X2, per2, box2);
-            const double u0 = V0 + (W1 * r2 - W2 * r1);
-            const double u1 = V1 + (W2 * r0 - W0 * r2);
-            const double u2 = V2 + (W0 * r1 - W1 * r0);
-            // populations leaving x toward p (independent loads), then the bounced values
-            C fo[kQ - 1];
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e)
-                fo[e] = (os[e] == p) ? ld<P>(A, (unsigned)(kOPP[e] * nc) + (unsigned)cell, kOPP[e], rho_ff) : C(0);
-            double F0 = 0.0, F1 = 0.0, F2 = 0.0;
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e) {
-                if (os[e] != p) continue;
-                const int d = kOPP[e];
-                double cu = 0.0;
-                if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
-                if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
-                if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
-                const C fe = fo[e] - (C)(kMW[d] * rho_f * cu);
-                st<P>(A, (unsigned)(e * nc) + (unsigned)sc[e], e, fe, rho_ff);
-                const double sl = (double)fo[e] + (double)fe;
-                if (kCX[d] > 0) F0 += sl; else if (kCX[d] < 0) F0 -= sl;
-                if (kCY[d] > 0) F1 += sl; else if (kCY[d] < 0) F1 -= sl;
-                if (kCZ[d] > 0) F2 += sl; else if (kCZ[d] < 0) F2 -= sl;
-            }
-            acc[0] += F0; acc[1] += F1; acc[2] += F2;
-            acc[3] += r1 * F2 - r2 * F1;
-            acc[4] += r2 * F0 - r0 * F2;
-            acc[5] += r0 * F1 - r1 * F0;
+        };
+        read_g(pred);
+        int slot;
+        const unsigned grp = links_of_p(cell, slot);
+        if (slot != pred) {
+            if (slot >= 0) read_g(slot);
+            else { G0 = 0.0; G1 = 0.0; G2 = 0.0; }
         }
-        block_sum<6>(acc, red);
-        if (tid == 0) {
-            double *pp = s.ppart + ((long long)p * kChunks + chunk) * 6;
-            for (int c = 0; c < 6; ++c) pp[c] = acc[c];
+        const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx, ii = rem - jj * nx;
+        const double r0 = mimg((double)ii - X0, per0, box0);
+        const double r1 = mimg((double)jj - X1, per1, box1);
+        const double r2 = mimg((double)kk - X2, per2, box2);
+        // F = 2 G - sum_d 2 (w_d / c_s^2) rho_f c_d (c_d . V_b) over p's links at the node
+        const double u0 = V0 + (W1 * r2 - W2 * r1);
+        const double u1 = V1 + (W2 * r0 - W0 * r2);
+        const double u2 = V2 + (W0 * r1 - W1 * r0);
+        double F0 = 2.0 * G0, F1 = 2.0 * G1, F2 = 2.0 * G2;
+#pragma unroll
+        for (int e = 0; e < kQ - 1; ++e) {
+            if (!((grp >> e) & 1u)) continue;
+            const int d = kOPP[e];
+            double cu = 0.0;
+            if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
+            if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
+            if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
+            const double m = kMW[d] * rho_f * cu;
+            if (kCX[d] > 0) F0 -= m; else if (kCX[d] < 0) F0 += m;
+            if (kCY[d] > 0) F1 -= m; else if (kCY[d] < 0) F1 += m;
+            if (kCZ[d] > 0) F2 -= m; else if (kCZ[d] < 0) F2 += m;
         }
+        acc[0] += F0; acc[1] += F1; acc[2] += F2;
+        acc[3] += r1 * F2 - r2 * F1;
+        acc[4] += r2 * F0 - r0 * F2;
+        acc[5] += r0 * F1 - r1 * F0;
+    }
+    block_sum<6>(acc, red);
+    if (tid == 0) {
+        double *pp = s.ppart + ((long long)p * kChunks + chunk) * 6;
+        for (int c = 0; c < 6; ++c) pp[c] = acc[c];
     }
 }
 
@@ -659,7 +947,10 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
         s.nnear[p] = min(near_total, kNearCap);
         if (mode == 0) s.hn[par ^ 1][p] = min(hist_total, kHistCap);
     }
-    if (mode != 0) return;
+    if (mode != 0) {
+        if (tid == 0) pack_state(s.pf[par] + 12 * p, Xo + 3 * p, Vo + 3 * p, Wo + 3 * p);
+        return;
+    }
     block_sum<6>(con, red);
 
     // (3) motion
@@ -694,12 +985,27 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
                 if (fabs(v) > 0.25) atomicOr(s.flags, 0x10u);
             }
         }
+        pack_state(s.pf[par ^ 1] + 12 * p, Xn + 3 * p, Vn + 3 * p, Wn + 3 * p);
     }
 }
 
 // ---------------------------------------------------------------------------
 // re-projection kernel
 // ---------------------------------------------------------------------------
+// Marks the chunks of q's shell list whose z-slab lies within one plane of z.
+__device__ __forceinline__ void mark_dirty(const DevSet &s, const MemberDev *M, int q, int z, long long t)
+{
+    if (q < 0) return;
+    const int z0 = s.lzr[2 * q], hz = s.lzr[2 * q + 1];
+    if (hz <= 0) return;
+    int dz = z - z0;
+    if (M->per[2]) dz = ((dz % M->nz) + M->nz) % M->nz;
+    for (int w = dz - 1; w <= dz + 1; ++w) {
+        const int c = (w >= 0) ? w / hz : -1;
+        if (c >= 0 && c < kChunks) s.ldirty[q * kChunks + c] = t;
+    }
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
 {
@@ -708,6 +1014,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
     __shared__ double nb[kNearCap][4];
     __shared__ int nbid[kNearCap];
     __shared__ int cnt4[4];
+    __shared__ int cstart[kChunks + 1];
     // the step being completed: copied by the fluid kernel (mode 0); the counter itself is
     // advanced here and read by no workgroup of this kernel
     const long long t = (mode == 0) ? *s.tcopy : *s.tstep;
@@ -816,6 +1123,23 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             const int was = cur[cell];
             if (best == was) return;
             nxt[cell] = best;
+            // links of the old and new owner and of the neighbours' owners can change, at
+            // list nodes of the z-slabs within one plane of this node
+            mark_dirty(s, M, was, kk, t);
+            mark_dirty(s, M, best, kk, t);
+#pragma unroll 1
+            for (int e = 0; e < kQ - 1; ++e) {
+                int c[3] = {ii + kCX[e], jj + kCY[e], kk + kCZ[e]};
+                bool ok = true;
+                for (int a = 0; a < 3; ++a) {
+                    if (c[a] < 0 || c[a] >= dims[a]) {
+                        if (M->per[a]) c[a] = c[a] < 0 ? c[a] + dims[a] : c[a] - dims[a];
+                        else ok = false;
+                    }
+                }
+                if (!ok) continue;
+                mark_dirty(s, M, cur[(c[2] * dims[1] + c[1]) * dims[0] + c[0]], kk, t);
+            }
             const int slot = atomicAdd(s.chgcnt + par, 1);
             if (slot < s.chg_cap) {
                 s.chg[par][2 * slot] = (int)(M->cell_off + cell);
@@ -900,7 +1224,12 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             }
             const int tot = ext[0] * ext[1] * ext[2];
             double mrg = kShell;
-            int lcount = 0;
+            int lcount = 0, bcount = 0;
+            const long long bbase = (long long)p * s.bcap;
+            // chunks of the list are z-slabs of hz planes of the scan box
+            const int hz = (ext[2] + kChunks - 1) / kChunks;
+            if (tid <= kChunks) cstart[tid] = 0;
+            __syncthreads();
             for (int base = 0; base < tot; base += 256) {
                 const int idx = base + tid;
                 bool in_list = false;
@@ -938,6 +1267,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 }
                 int tcount = 0;
                 const int rk = block_rank(in_list, tcount, cnt4);
+                if (in_list && hz > 0) atomicAdd(&cstart[idx / (ext[0] * ext[1]) / hz + 1], 1);
                 if (in_list) {
                     const int slot = lcount + rk;
                     if (slot < s.lcap) {
@@ -949,6 +1279,19 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                     }
                 }
                 lcount += tcount;
+                // the surface band, a sub-list for small displacements
+                const bool in_band = in_list && fabs((double)dref) <= kBand;
+                const int bk = block_rank(in_band, tcount, cnt4);
+                if (in_band) {
+                    const int slot = bcount + bk;
+                    if (slot < s.bcap) {
+                        s.bcell[bbase + slot] = cell;
+                        s.bdr[bbase + slot] = dref;
+                    } else {
+                        atomicOr(s.flags, 0x40u);
+                    }
+                }
+                bcount += tcount;
             }
             double mv = wave_min_d(mrg);
             if ((tid & 63) == 0) red[tid >> 6][7] = mv;
@@ -957,14 +1300,28 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 mv = fmin(fmin(red[0][7], red[1][7]), fmin(red[2][7], red[3][7]));
                 s.margin[p] = mv;
                 s.lcnt[p] = min(lcount, s.lcap);
+                s.bcnt[p] = min(bcount, s.bcap);
+                s.lreb[p] = (mode == 1) ? t - 1 : t; // the next link pass recomputes its links
+                s.lzr[2 * p] = lo[2];
+                s.lzr[2 * p + 1] = hz;
+                int acc_c = 0;
+                for (int c = 0; c <= kChunks; ++c) {
+                    acc_c += cstart[c];
+                    s.lchunk[p * (kChunks + 1) + c] = min(acc_c, s.lcap);
+                }
                 s.Xref[3 * p] = X[0]; s.Xref[3 * p + 1] = X[1]; s.Xref[3 * p + 2] = X[2];
             }
             __syncthreads();
         } else if (use_list) {
-            const int n = s.lcnt[p];
+            // candidates have |d_ref - R| <= thr: the band list holds them all while
+            // thr <= kBand, the whole shell list otherwise
+            const bool band = thr + 1e-6 <= kBand;
+            const int n = band ? s.bcnt[p] : s.lcnt[p];
+            const int *lc = band ? s.bcell + (long long)p * s.bcap : s.lcell + lbase;
+            const float *dl = band ? s.bdr + (long long)p * s.bcap : s.ldr + lbase;
             for (int k = tid; k < n; k += 256) {
-                if (fabs((double)s.ldr[lbase + k]) > thr + 1e-6) continue;
-                const int cell = s.lcell[lbase + k];
+                if (fabs((double)dl[k]) > thr + 1e-6) continue;
+                const int cell = lc[k];
                 const int kk = cell / (dims[0] * dims[1]);
                 const int rem = cell - kk * dims[0] * dims[1];
                 const int jj = rem / dims[0], ii = rem - jj * dims[0];
@@ -987,13 +1344,7 @@ __global__ __launch_bounds__(256) void k_init_pops(DevSet s, long long total_cel
     using S = typename Prec<P>::S;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= total_cells) return;
-    int lo = 0, hi = s.nmem - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s.mem[mid].cell_off <= c) lo = mid;
-        else hi = mid - 1;
-    }
-    const MemberDev *M = s.mem + lo;
+    const MemberDev *M = member_of_cell(s, c);
     const int cell = (int)(c - M->cell_off);
     const int nc = (int)M->ncell;
     S *A = (S *)s.popA + M->pop_off, *B = (S *)s.popB + M->pop_off;

@@ -48,11 +48,15 @@ def _size(lb, params, cfg=None):
 
 def test_workspace_size_and_validation(lb):
     ok = lb.make_params(96, 96, 384, tau=1.0, bc=(0, 0, 0, 0, 2, 2), wave=lb.WAVE_COSINE, amp=1e-3, omega=0.0314,
-                        t_n=200, probe_z=range(0, 384, 16), max_particles=1024)
+                        t_n=200, probe_z=range(0, 384, 16), max_particles=1024, max_radius=9.0)
     rc, n = _size(lb, [ok])
     assert rc == lb.OK
-    # FP32 populations (2 x 19 x 4 B per cell) dominate the workspace
-    assert 2 * 19 * 4 * 96 * 96 * 384 < n < 1.3 * 2 * 19 * 4 * 96 * 96 * 384
+    # per node: FP32 populations (2 x 19 x 4 B), two node maps (8 B), two link words (16 B)
+    # and four 32-byte FP64 link-force records (128 B); then the per-particle shell lists
+    # (16 B per entry, about 5.6 k entries per sphere of radius 9)
+    cells = 96 * 96 * 384
+    per_node = 2 * 19 * 4 + 8 + 16 + 128
+    assert per_node * cells < n < per_node * cells + 1024 * 5600 * 16 * 1.5 + (64 << 20)
     bad = [
         lb.make_params(8, 8, 8, tau=0.5),                         # tau must exceed 1/2
         lb.make_params(8, 8, 8, bc=(0, 1, 0, 0, 0, 0)),            # periodic paired with a wall
