@@ -1123,11 +1123,9 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             const int was = cur[cell];
             if (best == was) return;
             nxt[cell] = best;
-            // links of the old and new owner and of the neighbours' owners can change, at
-            // list nodes of the z-slabs within one plane of this node
-            mark_dirty(s, M, was, kk, t);
-            mark_dirty(s, M, best, kk, t);
-#pragma unroll 1
+            // the 18 neighbours and their owners before the re-projection (loads together)
+            int nbc[kQ - 1], ow[kQ - 1];
+#pragma unroll
             for (int e = 0; e < kQ - 1; ++e) {
                 int c[3] = {ii + kCX[e], jj + kCY[e], kk + kCZ[e]};
                 bool ok = true;
@@ -1137,8 +1135,22 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                         else ok = false;
                     }
                 }
-                if (!ok) continue;
-                mark_dirty(s, M, cur[(c[2] * dims[1] + c[1]) * dims[0] + c[0]], kk, t);
+                nbc[e] = ok ? (c[2] * dims[1] + c[1]) * dims[0] + c[0] : -1;
+            }
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) ow[e] = nbc[e] >= 0 ? cur[nbc[e]] : -1;
+            // links of the old and new owner and of the neighbours' owners can change, at
+            // list nodes of the z-slabs within one plane of this node
+            mark_dirty(s, M, was, kk, t);
+            mark_dirty(s, M, best, kk, t);
+            int m1 = -1, m2 = -1;
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                const int q = ow[e];
+                if (q < 0 || q == was || q == best || q == m1 || q == m2) continue;
+                mark_dirty(s, M, q, kk, t);
+                m2 = m1;
+                m1 = q;
             }
             const int slot = atomicAdd(s.chgcnt + par, 1);
             if (slot < s.chg_cap) {
@@ -1165,25 +1177,27 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 // Eq. (convertSF): an uncovered node is refilled with f^eq(rho_bar, V_b)
                 // and takes rho_bar V_b from the particle; rho_bar averages the
                 // neighbours that are fluid before and after the re-projection
+                unsigned use = 0u;
+#pragma unroll
+                for (int e = 0; e < kQ - 1; ++e) {
+                    if (nbc[e] < 0 || ow[e] >= 0) continue;
+                    const int yc = nbc[e];
+                    const int zc = yc / (dims[0] * dims[1]), rc = yc - zc * dims[0] * dims[1];
+                    const int yy = rc / dims[0], xx = rc - yy * dims[0];
+                    bool inside = dist2(M, xx, yy, zc, X[0], X[1], X[2]) <= R2;
+                    for (int k = 0; k < nn && !inside; ++k)
+                        inside = dist2(M, xx, yy, zc, nb[k][0], nb[k][1], nb[k][2]) <= nb[k][3] * nb[k][3];
+                    if (!inside) use |= 1u << e;
+                }
                 double sum = 0.0;
                 int cnt = 0;
 #pragma unroll 1
                 for (int e = 0; e < kQ - 1; ++e) {
-                    int c[3] = {ii + kCX[e], jj + kCY[e], kk + kCZ[e]};
-                    bool ok = true;
-                    for (int a = 0; a < 3; ++a) {
-                        if (c[a] < 0 || c[a] >= dims[a]) {
-                            if (M->per[a]) c[a] = c[a] < 0 ? c[a] + dims[a] : c[a] - dims[a];
-                            else ok = false;
-                        }
-                    }
-                    if (!ok) continue;
-                    const int yc = (c[2] * dims[1] + c[1]) * dims[0] + c[0];
-                    if (cur[yc] >= 0) continue;
-                    bool inside = dist2(M, c[0], c[1], c[2], X[0], X[1], X[2]) <= R2;
-                    for (int k = 0; k < nn && !inside; ++k)
-                        inside = dist2(M, c[0], c[1], c[2], nb[k][0], nb[k][1], nb[k][2]) <= nb[k][3] * nb[k][3];
-                    if (inside) continue;
+                    if (!((use >> e) & 1u)) continue;
+                    int yc = 0;
+#pragma unroll
+                    for (int q = 0; q < kQ - 1; ++q)
+                        if (q == e) yc = nbc[q];
                     double rr = 0.0;
                     for (int d = 0; d < kQ; ++d) rr += (double)ld<P>(Bn, d * nc + yc, d, rho_ff);
                     sum += rr;
