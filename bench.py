@@ -7,10 +7,15 @@ lattice, periodic in x and y, density inlet at z = 0 driven by a single-period c
 (amplitude 1e-3, period 200 steps), constant density at z = 383, probes every 16 lu,
 tau = 1, Hertz-Mindlin spheres with E* = 10.37, nu = 0.2, mu = 0, rho_p* = 2.466.
 
-One step = one pass of the whole coupled path (fluid kernel, particle kernel,
-re-projection kernel).  ``value`` is fluid-node updates per second (millions) over K
-timed steps with all data resident in HBM; ``roofline`` prices the fluid kernel's
-algorithmic bytes (19 populations read and written per fluid node) against 8 TB/s.
+One step = one pass of the whole coupled path (fluid, link, motion and re-projection
+kernels, replayed from a HIP graph).  ``value`` is fluid-node updates per second
+(millions) over K timed steps with all data resident in HBM; ``roofline`` prices the
+fluid kernel's algorithmic bytes (19 populations read and written per fluid node)
+against 8 TB/s, using its average duration from HIP events recorded around each launch
+on the library's stream in eager steps of the same set.  ``traffic`` is the HBM bytes
+per launch of that kernel from the committed rocprofv3 counter summary (FETCH_SIZE and
+WRITE_SIZE scaled by a calibration copy), reported only while the kernel source is the
+one the counters were taken on.
 The FP16 / BF16 deviation-storage variants and their errors against the FP64 path are
 reported beside it, and the FP64 CPU oracle is timed on a bounded sample.
 """
@@ -153,6 +158,85 @@ def cpu_baseline(params, pk, budget_s=20.0):
             "sample": f"{n} full steps of the 96x96x384 FCC case (oracle, FP64, one host thread)"}
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1808_08921_amd", "csrc", "lbdem_kernels.hip")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_fluid_fcc96x96x384_fp32_counters.txt")
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read and 1 GiB written
+
+
+def kernel_source_hash():
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def counters_workload(steps):
+    """Workload for the rocprofv3 counter passes: `steps` eager steps of the FP32 FCC case,
+    then a plain device-to-device copy of COPY_BYTES that calibrates the counters."""
+    import torch
+
+    params, pk = _case(seed=0)
+    gs = _make(params, pk, "fp32", graph_steps=0)
+    gs.step(steps)
+    gs.synchronize()
+    gs.close()
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    _log("counter workload done")
+
+
+def summarize_counters(fetch_csv, write_csv, out_path, command):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of each kernel from two rocprofv3 --pmc
+    passes, scaled by the same counters' reading for the calibration copy (COPY_BYTES read
+    and written), written as a text summary with the kernel source hash."""
+    import csv
+
+    def load(path, counter):
+        rows = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return rows
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    copy_name = max((k for k in fetch if "copy" in k.lower()), key=lambda k: max(fetch[k]))
+    f_scale = COPY_BYTES / (max(fetch[copy_name]) * 1024.0)
+    w_scale = COPY_BYTES / (max(write[copy_name]) * 1024.0)
+    lines = [f"# rocprofv3 counters, FCC 96x96x384 FP32 (1024 spheres), per dispatch",
+             f"# command: {command}",
+             f"# kernel source sha256[:16]: {kernel_source_hash()}",
+             f"# calibration: {copy_name} copying {COPY_BYTES} B reads FETCH_SIZE {max(fetch[copy_name]):.0f} KiB, "
+             f"WRITE_SIZE {max(write[copy_name]):.0f} KiB -> scale fetch {f_scale:.4f}, write {w_scale:.4f}",
+             "kernel | dispatches | FETCH_SIZE KiB (mean) | WRITE_SIZE KiB (mean) | HBM bytes per dispatch (scaled)"]
+    for k in sorted(fetch):
+        if k == copy_name or k not in write:
+            continue
+        fm, wm = float(np.mean(fetch[k])), float(np.mean(write[k]))
+        lines.append(f"{k} | {len(fetch[k])} | {fm:.1f} | {wm:.1f} | {(fm * f_scale + wm * w_scale) * 1024.0:.0f}")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def measured_traffic(kernel_prefix="_ZN5lbdem7k_fluidILi1E"):
+    """HBM bytes per dispatch of the FP32 fluid kernel from the committed counter summary,
+    or None when it is missing or was taken on another version of the kernel source."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    txt = open(COUNTERS_FILE).read()
+    if f"sha256[:16]: {kernel_source_hash()}" not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith(kernel_prefix):
+            return float(line.split("|")[-1])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,7 +245,17 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=300, help="eager steps timed per kernel with HIP events")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip FP16/BF16 timing and the error study")
+    ap.add_argument("--counters", type=int, default=0, metavar="STEPS",
+                    help="only run the workload of the rocprofv3 counter passes (STEPS eager steps + a copy)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="write the counter summary from two rocprofv3 --pmc CSV files")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, COUNTERS_FILE)
+        return
+    if args.counters:
+        counters_workload(args.counters)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab decomposition is "
               "a design note, not part of this build", file=sys.stderr)
@@ -210,8 +304,9 @@ def main():
                    "mlups_all_cells": ncell * args.steps / (r32["ms_per_step"] * 1e-3 * args.steps) / 1e6,
                    "kernel_ms": {"links": kt[0], "motion": kt[1], "fluid": kt[2], "remap": kt[3]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_fluid<FP32>", "algorithmic_bytes_per_launch": alg_bytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "k_fluid<FP32>", "algorithmic_bytes_per_launch": alg_bytes,
+                     "step_frac": alg_bytes / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_variants:
         line["variants"] = {}

@@ -92,15 +92,6 @@ __device__ __forceinline__ typename Prec<P>::C ld(const typename Prec<P>::S *a, 
         return (float)kWd[d] * (rho_f + bf16_to_f32(ldo(a, idx)));
     }
 }
-// decode a stored value of population d
-template <int P>
-__device__ __forceinline__ typename Prec<P>::C decode(typename Prec<P>::S v, int d, float rho_f)
-{
-    if constexpr (P == PREC_FP64 || P == PREC_FP32) return v;
-    else if constexpr (P == PREC_FP16DEV) return (float)kWd[d] * (rho_f + (float)v);
-    else return (float)kWd[d] * (rho_f + bf16_to_f32(v));
-}
-
 // encode population d to storage: 16-bit forms hold q = f / w_d - rho_f
 template <int P>
 __device__ __forceinline__ void st(typename Prec<P>::S *a, unsigned idx, int d, typename Prec<P>::C f, float rho_f)
@@ -302,6 +293,47 @@ __device__ __forceinline__ C feq(int d, C rho, C ux, C uy, C uz, C uu)
     }
 }
 
+// f^eq_d(rho, u) - w_d rho_f with rho = rho_f + drho, Eq. (BGKequili) written for the
+// deviation from the rest state: w_d (drho + rho (c.u / c_s^2 + (c.u)^2 / (2 c_s^4) - u.u /
+// (2 c_s^2)))
+template <typename C>
+__device__ __forceinline__ C feq_dev(int d, C drho, C rho, C ux, C uy, C uz, C uu)
+{
+    C cu = C(0);
+    if (kCX[d] > 0) cu += ux; else if (kCX[d] < 0) cu -= ux;
+    if (kCY[d] > 0) cu += uy; else if (kCY[d] < 0) cu -= uy;
+    if (kCZ[d] > 0) cu += uz; else if (kCZ[d] < 0) cu -= uz;
+    if constexpr (sizeof(C) == 8) {
+        const double cs2 = kCS2;
+        return kWd[d] * (drho + rho * (cu / cs2 + (cu * cu) / (2.0 * cs2 * cs2) - uu / (2.0 * cs2)));
+    } else {
+        return (C)kWd[d] * (drho + rho * (C(3) * cu + C(4.5) * (cu * cu) - C(1.5) * uu));
+    }
+}
+
+// stored value of population d -> deviation f_d - w_d rho_f (the 16-bit forms store
+// q = f / w_d - rho_f, so the deviation is w_d q)
+template <int P>
+__device__ __forceinline__ typename Prec<P>::C decode_dev(typename Prec<P>::S v, int d, double rho_f)
+{
+    using C = typename Prec<P>::C;
+    if constexpr (P == PREC_FP64 || P == PREC_FP32) return v - (C)(kWd[d] * rho_f);
+    else if constexpr (P == PREC_FP16DEV) return (float)kWd[d] * (float)v;
+    else return (float)kWd[d] * bf16_to_f32(v);
+}
+
+// deviation f_d - w_d rho_f -> stored value of population d
+template <int P>
+__device__ __forceinline__ void store_dev(typename Prec<P>::S *a, unsigned idx, int d, typename Prec<P>::C df,
+                                          double rho_f)
+{
+    using S = typename Prec<P>::S;
+    using C = typename Prec<P>::C;
+    if constexpr (P == PREC_FP64 || P == PREC_FP32) sto(a, idx, (S)((C)(kWd[d] * rho_f) + df));
+    else if constexpr (P == PREC_FP16DEV) sto(a, idx, (S)(df * kInvW[d]));
+    else sto(a, idx, f32_to_bf16(df * kInvW[d]));
+}
+
 // ---------------------------------------------------------------------------
 // link words
 // ---------------------------------------------------------------------------
@@ -421,11 +453,12 @@ __device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *
 }
 
 // Eq. (mem) for the links of a fluid node: f_e = f~_d(x,t) - 2 (w_d / c_s^2) rho_f V_b . c_d,
-// d = e*, for every direction e whose source is inside a particle; f[e] holds f~_d(x,t).
-// For the momentum exchange of Eq. (fFS), F = sum c_d (f~_d + f_e) = 2 G - K V_b with
-// G = sum c_d f~_d over the node's links to one particle and K = sum 2 (w_d / c_s^2) rho_f
-// c_d c_d^T; the node stores G per slot of its link words (collision precision) and the
-// link kernel adds the wall-velocity part.
+// d = e*, for every direction e whose source is inside a particle; f[e] holds the deviation
+// f~_d(x,t) - w_d rho_f (the same relation holds for deviations since w_e = w_d).  For the
+// momentum exchange of Eq. (fFS), F = sum c_d (f~_d + f_e) = 2 (G + rho_f sum c_d w_d) - K V_b
+// with G = sum c_d (f~_d - w_d rho_f) over the node's links to one particle and K = sum
+// 2 (w_d / c_s^2) rho_f c_d c_d^T; the node stores G per slot of its link words (collision
+// precision) and the link kernel adds the rest-state and wall-velocity parts in FP64.
 template <typename C>
 __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M, C (&f)[kQ], unsigned long long w0,
                                             int i, int j, int k, int par, double rho_f, long long gc)
@@ -517,14 +550,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     const int *own = s.own[par] + cell_off;
     int *nmap = s.own[par ^ 1] + cell_off;
     const double rho_fd = uni(M->rho_f);
-    const float rho_ff = (float)rho_fd;
     const C omega = (C)uni(M->omega);
     const int bc4 = uni(M->bc[4]), bc5 = uni(M->bc[5]);
     const long long t_n = uni(M->t_n);
     long long ti = t + 1;
     if (ti > t_n + 1) ti = t_n + 1;
-    const C rho_in = (C)s.wave[uni(M->wave_off) + ti];
-    const C rho_out = (C)rho_fd;
+    const C drho_in = (C)(s.wave[uni(M->wave_off) + ti] - rho_fd);
     const int pz_off = uni(M->pz_off);
 
     // link words of this tile from the node map of step t: all of them after a set-up or
@@ -624,28 +655,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                               "+v"(raw[6]), "+v"(raw[7]), "+v"(raw[8]), "+v"(raw[9]), "+v"(raw[10]), "+v"(raw[11]),
                               "+v"(raw[12]), "+v"(raw[13]), "+v"(raw[14]), "+v"(raw[15]), "+v"(raw[16]),
                               "+v"(raw[17]), "+v"(raw[18]));
+            // the arithmetic works on deviations f_d - w_d rho_f from the rest state: Eqs.
+            // (stream), (mem) and the density faces are affine with the same coefficients
+            // for f and its deviation (w_d = w_{d*}; the weights of each Zou-He closure sum
+            // to one), and the deviations keep the small density and momentum signals
+            // clear of the rounding of the O(1) rest populations
 #pragma unroll
             for (int e = 0; e < kQ; ++e)
-                f[e] = fl ? (((unk >> e) & 1u) ? C(0) : decode<P>(raw[e], e, rho_ff)) : (C)kWd[e];
+                f[e] = (fl && !((unk >> e) & 1u)) ? decode_dev<P>(raw[e], e, rho_fd) : C(0);
             if (lmask != 0u) moving_wall<C>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell);
 
-            if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, rho_in, false);
-            if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, rho_out, true);
+            if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, drho_in, false);
+            if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, C(0), true);
 
-            C rho, jx, jy, jz;
-            moments<C>(f, rho, jx, jy, jz);
+            C drho, jx, jy, jz;
+            moments<C>(f, drho, jx, jy, jz);
+            const C rho = (C)rho_fd + drho;
             if (fl) {
                 pr0 = 1.0;
-                pr1 = (double)rho - rho_fd;
+                pr1 = (double)drho;
                 pr2 = (double)jz;
-                pr3 = (double)rho;
+                pr3 = rho_fd + (double)drho;
             }
             const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
             const C uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
             for (int d = 0; d < kQ; ++d) {
-                const C fe = feq<C>(d, rho, ux, uy, uz, uu);
-                st<P>(B, (unsigned)(d * nc) + (unsigned)cell, d, f[d] + omega * (fe - f[d]), rho_ff);
+                const C fe = feq_dev<C>(d, drho, rho, ux, uy, uz, uu);
+                store_dev<P>(B, (unsigned)(d * nc) + (unsigned)cell, d, f[d] + omega * (fe - f[d]), rho_fd);
             }
         }
         const int pidx = s.pzmap[pz_off + z];
@@ -803,7 +840,7 @@ __global__ __launch_bounds__(256) void k_links(DevSet s, int mode, int only)
         const double r0 = mimg((double)ii - X0, per0, box0);
         const double r1 = mimg((double)jj - X1, per1, box1);
         const double r2 = mimg((double)kk - X2, per2, box2);
-        // F = 2 G - sum_d 2 (w_d / c_s^2) rho_f c_d (c_d . V_b) over p's links at the node
+        // F = 2 G + sum_d c_d (2 w_d rho_f - 2 (w_d / c_s^2) rho_f c_d . V_b) over p's links
         const double u0 = V0 + (W1 * r2 - W2 * r1);
         const double u1 = V1 + (W2 * r0 - W0 * r2);
         const double u2 = V2 + (W0 * r1 - W1 * r0);
@@ -816,10 +853,11 @@ __global__ __launch_bounds__(256) void k_links(DevSet s, int mode, int only)
             if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
             if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
             if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
-            const double m = kMW[d] * rho_f * cu;
-            if (kCX[d] > 0) F0 -= m; else if (kCX[d] < 0) F0 += m;
-            if (kCY[d] > 0) F1 -= m; else if (kCY[d] < 0) F1 += m;
-            if (kCZ[d] > 0) F2 -= m; else if (kCZ[d] < 0) F2 += m;
+            // 2 w_d rho_f c_d (rest state) - 2 (w_d / c_s^2) rho_f c_d (c_d . V_b)
+            const double m = 2.0 * kWd[d] * rho_f - kMW[d] * rho_f * cu;
+            if (kCX[d] > 0) F0 += m; else if (kCX[d] < 0) F0 -= m;
+            if (kCY[d] > 0) F1 += m; else if (kCY[d] < 0) F1 -= m;
+            if (kCZ[d] > 0) F2 += m; else if (kCZ[d] < 0) F2 -= m;
         }
         acc[0] += F0; acc[1] += F1; acc[2] += F2;
         acc[3] += r1 * F2 - r2 * F1;
