@@ -302,7 +302,7 @@ def main():
                                "populations, cosine inlet 1e-3 / 200 steps, probes every 16 lu",
                    "cells": ncell, "fluid_nodes": nfl, "solid_fraction": 1 - nfl / ncell,
                    "mlups_all_cells": ncell * args.steps / (r32["ms_per_step"] * 1e-3 * args.steps) / 1e6,
-                   "kernel_ms": {"links": kt[0], "motion": kt[1], "fluid": kt[2], "remap": kt[3]}},
+                   "kernel_ms": {"refresh": kt[4], "fluid": kt[2], "links": kt[0], "motion": kt[1], "remap": kt[3]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_fluid<FP32>", "algorithmic_bytes_per_launch": alg_bytes,

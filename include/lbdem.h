@@ -188,8 +188,8 @@ int lbdem_owner_get(lbdem_set *set, int32_t lattice, int32_t *owner);
 /* Kernel timing with HIP events on the set's stream.  While enabled, lbdem_step launches
  * kernels one by one and brackets every launch with a pair of events.  lbdem_timing_read
  * synchronises and returns, for kernel k = 0 (links), 1 (particle motion), 2 (fluid),
- * 3 (re-projection), the summed milliseconds ms[k] and the number of launches count[k]
- * since enabling (ms and count hold 4 entries). */
+ * 3 (re-projection), 4 (start-of-step node-map refresh), the summed milliseconds ms[k] and
+ * the number of launches count[k] since enabling (ms and count hold 5 entries). */
 int lbdem_timing_enable(lbdem_set *set, int enable);
 int lbdem_timing_read(lbdem_set *set, double *ms, int64_t *count);
 

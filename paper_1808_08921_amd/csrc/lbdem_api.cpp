@@ -306,7 +306,7 @@ const double kWh[kQ] = {1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 
                         1.0 / 36, 1.0 / 36, 1.0 / 3};
 const float kInvWh[kQ] = {18, 18, 18, 18, 18, 18, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 36, 3};
 
-constexpr int kKernels = 4; // links, motion, fluid, re-projection
+constexpr int kKernels = 5; // links, motion, fluid, re-projection, refresh
 
 } // namespace
 
@@ -327,8 +327,8 @@ struct lbdem_set {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, int>> ev_pending[kKernels];
-    double ms_acc[kKernels] = {0, 0, 0, 0};
-    int64_t ms_cnt[kKernels] = {0, 0, 0, 0};
+    double ms_acc[kKernels] = {0, 0, 0, 0, 0};
+    int64_t ms_cnt[kKernels] = {0, 0, 0, 0, 0};
     size_t ev_next = 0;
 };
 
@@ -363,15 +363,19 @@ int build_graph(lbdem_set *S, int steps)
     hipGraphNode_t prev = nullptr;
     for (int k = 0; k < steps; ++k) {
         hipKernelNodeParams kp{};
-        hipGraphNode_t n0, n1, n2, n3;
+        hipGraphNode_t n0, n1, n2, n3, n4;
         kp.blockDim = dim3(256);
         kp.sharedMemBytes = 0;
         kp.extra = nullptr;
-        // fluid -> links -> motion -> re-projection
+        // refresh -> fluid -> links -> motion -> re-projection
+        kp.func = refresh_kernel_ptr();
+        kp.gridDim = dim3(refresh_grid(S->ds));
+        kp.kernelParams = fluid_args;
+        HIPCHK(hipGraphAddKernelNode(&n4, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
         kp.func = fluid_kernel_ptr(S->G.prec);
         kp.gridDim = dim3(S->ds.tiles_total);
         kp.kernelParams = fluid_args;
-        HIPCHK(hipGraphAddKernelNode(&n2, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n4, 1, &kp));
         kp.func = links_kernel_ptr(S->G.prec);
         kp.gridDim = dim3(links_grid(S->ds));
         kp.kernelParams = part_args;
@@ -407,9 +411,9 @@ int harvest_events(lbdem_set *S)
 
 int launch_step_eager(lbdem_set *S)
 {
-    // launch order fluid, links, motion, re-projection; timing slots keep the order
-    // links, motion, fluid, re-projection of lbdem_timing_read
-    static const int order[kKernels] = {2, 0, 1, 3};
+    // launch order refresh, fluid, links, motion, re-projection; timing slots keep the
+    // order links, motion, fluid, re-projection, refresh of lbdem_timing_read
+    static const int order[kKernels] = {4, 2, 0, 1, 3};
     for (int o = 0; o < kKernels; ++o) {
         const int k = order[o];
         int e0 = -1, e1 = -1;
@@ -423,7 +427,8 @@ int launch_step_eager(lbdem_set *S)
             HIPCHK(hipEventRecord(S->ev_pool[e0], S->stream));
         }
         hipError_t err;
-        if (k == 0) err = launch_links(S->G.prec, S->ds, S->stream);
+        if (k == 4) err = launch_refresh(S->ds, S->stream);
+        else if (k == 0) err = launch_links(S->G.prec, S->ds, S->stream);
         else if (k == 1) err = launch_motion(S->ds, 0, -1, S->stream);
         else if (k == 2) err = launch_fluid(S->G.prec, S->ds, S->stream);
         else err = launch_remap_prec(S->G.prec, S->ds, 0, -1, S->stream);

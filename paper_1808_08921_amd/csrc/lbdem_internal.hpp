@@ -27,6 +27,7 @@ constexpr int kEmpty = 0x7fffffff;
 // used, bit 63 when more than four particles border x.  Word 1: bits 0-17 the high slot
 // bit per direction, bits 18-30 and 31-43 the local indices in slots 2 and 3.
 constexpr int kMaxLocal = 8191;     // particles per lattice (13-bit local indices)
+constexpr int kRefreshBlocks = 512; // workgroups of the start-of-step refresh kernel
 
 // Per-lattice constants (one entry per lattice of the set).
 struct MemberDev {
@@ -117,16 +118,19 @@ enum { BC_PERIODIC = 0, BC_WALL = 1, BC_PRESSURE = 2 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16DEV = 2, PREC_BF16DEV = 3 };
 
 // kernel launchers (lbdem_kernels.hip)
+hipError_t launch_refresh(const DevSet &s, hipStream_t st);
 hipError_t launch_links(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_motion(const DevSet &s, int mode, int only_member, hipStream_t st);
 hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_remap_prec(int prec, const DevSet &s, int mode, int only_member, hipStream_t st);
 hipError_t launch_init_pops(int prec, const DevSet &s, long long total_cells, hipStream_t st);
 // kernel entry points and grid sizes, for building HIP graphs
+void *refresh_kernel_ptr();
 void *links_kernel_ptr(int prec);
 void *motion_kernel_ptr();
 void *fluid_kernel_ptr(int prec);
 void *remap_kernel_ptr_prec(int prec);
+int refresh_grid(const DevSet &s);
 int links_grid(const DevSet &s);
 int motion_grid(const DevSet &s);
 int remap_grid(const DevSet &s);

@@ -503,6 +503,60 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
     }
 }
 
+// Start of step t: brings the other node map up to date with the re-projection of step
+// t-1 (its change list, or a full copy after an overflow or a particle set-up), refreshes
+// the link words of the changed nodes and their neighbours (all of them after a full
+// copy) from the node map of step t, and opens the change list of step t.
+__global__ __launch_bounds__(256) void k_refresh(DevSet s)
+{
+    const long long t = *s.tstep;
+    const int par = (int)(t & 1);
+    const int cnt = s.chgcnt[par ^ 1];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool over = false;
+    if (cnt > s.chg_cap) {
+        for (long long c = t0; c < s.ncell_total; c += stride) {
+            s.own[par ^ 1][c] = s.own[par][c];
+            const MemberDev *M = member_of_cell(s, c);
+            const int cell = (int)(c - M->cell_off);
+            const int nxy = M->nx * M->ny;
+            const int k = cell / nxy, rem = cell - k * nxy, j = rem / M->nx, i = rem - j * M->nx;
+            unsigned long long w0, w1;
+            link_words(M, s.own[par] + M->cell_off, i, j, k, w0, w1);
+            s.lw[c] = w0;
+            s.lw[s.ncell_total + c] = w1;
+            over |= (w0 >> 63) != 0ull;
+        }
+    } else {
+        const int *lst = s.chg[par ^ 1];
+        for (long long e = t0; e < cnt; e += stride) s.own[par ^ 1][lst[2 * e]] = lst[2 * e + 1];
+        for (long long w = t0; w < (long long)cnt * kQ; w += stride) {
+            const long long ch = w / kQ;
+            const int q = (int)(w - ch * kQ); // 18: the changed node itself
+            const long long gcell = lst[2 * ch];
+            const MemberDev *M = member_of_cell(s, gcell);
+            const int nx = M->nx, ny = M->ny, nz = M->nz;
+            const int c0 = (int)(gcell - M->cell_off);
+            const int k0 = c0 / (nx * ny), rem = c0 - k0 * nx * ny, j0 = rem / nx, i0 = rem - j0 * nx;
+            // a neighbour across a bounded face wraps to a node whose words are unchanged;
+            // recomputing them is harmless
+            const int ci = wrapc(i0 + kCXd[q], nx), cj = wrapc(j0 + kCYd[q], ny), ck = wrapc(k0 + kCZd[q], nz);
+            const long long gc = M->cell_off + (ck * ny + cj) * nx + ci;
+            unsigned long long w0, w1;
+            link_words(M, s.own[par] + M->cell_off, ci, cj, ck, w0, w1);
+            s.lw[gc] = w0;
+            s.lw[s.ncell_total + gc] = w1;
+            over |= (w0 >> 63) != 0ull;
+        }
+    }
+    if (over) atomicOr(s.flags, 0x80u);
+    if (t0 == 0) {
+        s.chgcnt[par] = 0;
+        *s.tcopy = t; // the re-projection kernel of this step reads the step from here
+    }
+}
+
 // Pull streaming (Eq. stream), stationary half-way walls, moving half-way walls on the
 // particles (Eq. mem, from the node's link words), the density faces (Sec. 2.4), BGK
 // collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.
@@ -515,21 +569,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
 
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
-
-    // bring the other node map up to date with the previous step's changes
-    const int prev_cnt = s.chgcnt[par ^ 1];
-    const bool full_copy = prev_cnt > s.chg_cap;
-    if (!full_copy) {
-        const int *lst = s.chg[par ^ 1];
-        int *nmap = s.own[par ^ 1];
-        const long long nthr = (long long)gridDim.x * blockDim.x;
-        for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < prev_cnt; e += nthr)
-            nmap[lst[2 * e]] = lst[2 * e + 1];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        s.chgcnt[par] = 0;
-        *s.tcopy = t; // the re-projection kernel of this step reads the step from here
-    }
 
     const int g = xcd_swizzle(blockIdx.x, gridDim.x);
     const MemberDev *M = member_of_tile(s, g);
@@ -548,7 +587,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     const S *A = (const S *)(par ? s.popB : s.popA) + pop_off;
     S *B = (S *)(par ? s.popA : s.popB) + pop_off;
     const int *own = s.own[par] + cell_off;
-    int *nmap = s.own[par ^ 1] + cell_off;
     const double rho_fd = uni(M->rho_f);
     const C omega = (C)uni(M->omega);
     const int bc4 = uni(M->bc[4]), bc5 = uni(M->bc[5]);
@@ -557,48 +595,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     if (ti > t_n + 1) ti = t_n + 1;
     const C drho_in = (C)(s.wave[uni(M->wave_off) + ti] - rho_fd);
     const int pz_off = uni(M->pz_off);
-
-    // link words of this tile from the node map of step t: all of them after a set-up or
-    // an overflowed change list, else those of the previous step's changed nodes and
-    // their neighbours (each word belongs to the one tile holding its node)
-    {
-        const int x0 = tx << bxl, y0 = ty * uni(M->by);
-        const int *ownm = s.own[par] + cell_off;
-        bool over = false;
-        if (full_copy) {
-            if (vij)
-                for (int z = z0; z < z1; ++z) {
-                    const long long gc = cell_off + (z * ny + j) * nx + i;
-                    unsigned long long w0, w1;
-                    link_words(M, ownm, i, j, z, w0, w1);
-                    s.lw[gc] = w0;
-                    s.lw[s.ncell_total + gc] = w1;
-                    over |= (w0 >> 63) != 0ull;
-                }
-        } else if (prev_cnt > 0) {
-            const int *lst = s.chg[par ^ 1];
-            for (int e = threadIdx.x; e < prev_cnt; e += blockDim.x) {
-                const long long gcell = lst[2 * e];
-                if (gcell < cell_off || gcell >= cell_off + nc) continue;
-                const int c0 = (int)(gcell - cell_off);
-                const int k0 = c0 / nxy, rem = c0 - k0 * nxy, j0 = rem / nx, i0 = rem - j0 * nx;
-                for (int q = 0; q < kQ; ++q) {
-                    const int ci = wrapc(i0 + kCX[q], nx), cj = wrapc(j0 + kCY[q], ny), ck = wrapc(k0 + kCZ[q], nz);
-                    if (ci < x0 || ci >= x0 + (1 << bxl) || cj < y0 || cj >= y0 + uni(M->by) || ck < z0 || ck >= z1)
-                        continue;
-                    const long long gc = cell_off + (ck * ny + cj) * nx + ci;
-                    unsigned long long w0, w1;
-                    link_words(M, ownm, ci, cj, ck, w0, w1);
-                    s.lw[gc] = w0;
-                    s.lw[s.ncell_total + gc] = w1;
-                    over |= (w0 >> 63) != 0ull;
-                }
-            }
-        }
-        if (over) atomicOr(s.flags, 0x80u);
-        __threadfence_block();
-        __syncthreads();
-    }
 
     // offsets to the x-1 / x+1 / y-1 / y+1 neighbours (wrapped on periodic axes) and the
     // kind of face crossed to reach them (0 inside or periodic, 1 wall, 2 density face)
@@ -613,11 +609,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
         asm volatile("" : "+v"(oxm), "+v"(oxp), "+v"(oym), "+v"(oyp), "+v"(kxm), "+v"(kxp), "+v"(kym), "+v"(kyp));
         const int cell = (z * ny + j) * nx + i;
         bool fl = false;
-        if (vij) {
-            const int o = ldo(own, (unsigned)cell);
-            fl = (o < 0);
-            if (full_copy) nmap[cell] = o;
-        }
+        if (vij) fl = ldo(own, (unsigned)cell) < 0;
         double pr0 = 0.0, pr1 = 0.0, pr2 = 0.0, pr3 = 0.0;
         // With 4- and 8-byte storage every node of the row is written, so each store
         // covers whole cache lines: a solid node loads nothing and stores the rest state
@@ -1440,6 +1432,14 @@ void *remap_kernel_ptr_prec(int prec)
     }
 }
 int links_grid(const DevSet &s) { return max(s.ptot * kChunks, 1); }
+int refresh_grid(const DevSet &) { return kRefreshBlocks; }
+void *refresh_kernel_ptr() { return reinterpret_cast<void *>(k_refresh); }
+
+hipError_t launch_refresh(const DevSet &s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_refresh, dim3(refresh_grid(s)), dim3(256), 0, st, s);
+    return hipGetLastError();
+}
 int motion_grid(const DevSet &s) { return max(s.ptot, 1); }
 int remap_grid(const DevSet &s) { return max(s.ptot + s.nprobe_total, 1); }
 

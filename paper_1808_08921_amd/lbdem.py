@@ -246,9 +246,10 @@ class LatticeSet:
         _check(lib().lbdem_timing_enable(self._h, 1 if on else 0))
 
     def timing_read(self):
-        """Summed milliseconds and launch counts of the kernels: links, motion, fluid, remap."""
-        ms = np.zeros(4)
-        cnt = np.zeros(4, dtype=np.int64)
+        """Summed milliseconds and launch counts of the kernels: links, motion, fluid, remap,
+        refresh."""
+        ms = np.zeros(5)
+        cnt = np.zeros(5, dtype=np.int64)
         _check(lib().lbdem_timing_read(self._h, _dp(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return ms, cnt
 
