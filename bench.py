@@ -237,6 +237,53 @@ def measured_traffic(kernel_prefix="_ZN5lbdem7k_fluidILi1E"):
     return None
 
 
+def ensemble_bench(n_members, steps, warmup, kernel_steps, precision="fp32"):
+    """The batched-ensemble workload: n_members uneven FCC samples (2x2x8 to 4x4x16 cubic
+    cells, overlaps 1e-4..1e-2 R0, inlet periods 50..400 steps) advanced together, one
+    launch per kernel per step, graph-replayed; fluid tiles chosen by the autotuner."""
+    import torch
+    from paper_1808_08921_amd import inputs
+    from paper_1808_08921_amd.autotune import autotune
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    members = inputs.ensemble_members(n_members)
+    lats, parts = [], []
+    for params, pk in members:
+        lats.append(dict(params, max_particles=len(pk["x"])))
+        parts.append(pk)
+    _log(f"ensemble: {n_members} lattices, {sum(d['nx'] * d['ny'] * d['nz'] for d in lats)} cells")
+    tuned, nzt, report = autotune(lats, parts, precision=precision)
+    _log(f"autotune: z_per_thread {nzt}, tiles " +
+         str(sorted({(d['nx'], d['tile_x']) for d in tuned})))
+    out = {}
+    for label, lset, z in (("autotuned", tuned, nzt), ("default_tiles", lats, 0)):
+        gs = LatticeSet(lset, precision=precision, z_per_thread=z, graph_steps=8, probe_ring=64)
+        for k, pk in enumerate(parts):
+            gs.particles_set(k, pk["x"], pk["radius"], fixed=pk["fixed"])
+        nfl = sum(int((gs.owner(k) < 0).sum()) for k in range(len(lset)))
+        dt = time_steps(gs, steps, warmup)
+        kt = kernel_times(gs, kernel_steps)
+        status = gs.status()
+        gs.close()
+        torch.cuda.empty_cache()
+        alg = 2 * 19 * BYTES_PER_VALUE[precision] * nfl
+        out[label] = {"ms_per_step": 1e3 * dt / steps, "mlups": nfl * steps / dt / 1e6, "fluid_nodes": nfl,
+                      "kernel_ms": {"refresh": kt[4], "fluid": kt[2], "links": kt[0], "motion": kt[1], "remap": kt[3]},
+                      "fluid_roofline_frac": alg / (kt[2] * 1e-3) / 1e9 / HBM_PEAK_GBS, "status": status}
+        _log(f"{label}: {out[label]}")
+    cells = sum(d["nx"] * d["ny"] * d["nz"] for d in lats)
+    line = {"metric": "batched ensemble, fluid-node MLUPS", "value": out["autotuned"]["mlups"],
+            "unit": "MLUPS (fluid-node updates/s, millions)", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": out["autotuned"]["ms_per_step"], "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"{n_members} uneven FCC samples (seeds 1000..{999 + n_members}), one launch "
+                                   "per kernel per step", "cells": cells, "precision": precision,
+                       "z_per_thread": nzt, "tile_x_by_nx": {str(k): v for k, v in sorted(
+                           {d["nx"]: d["tile_x"] for d in tuned}.items())}},
+            "results": out, "autotune_report": report}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,7 +298,12 @@ def main():
                     help="only run the workload of the rocprofv3 counter passes (STEPS eager steps + a copy)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="write the counter summary from two rocprofv3 --pmc CSV files")
+    ap.add_argument("--ensemble", type=int, default=0, metavar="N",
+                    help="run the batched-ensemble workload with N lattices instead of the main line")
     args = ap.parse_args()
+    if args.ensemble:
+        ensemble_bench(args.ensemble, args.steps, args.warmup, args.kernel_steps)
+        return
     if args.summarize_counters:
         fetch_csv, write_csv, command = args.summarize_counters
         summarize_counters(fetch_csv, write_csv, COUNTERS_FILE, command)

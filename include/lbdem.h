@@ -91,6 +91,8 @@ typedef struct lbdem_params {
     int32_t probe_z[LBDEM_MAX_PROBES]; /* z index of each probe plane */
     int32_t max_particles;   /* particle capacity of this lattice (0 .. 8191) */
     double max_radius;       /* largest particle radius this lattice will hold (sizes per-particle tables) */
+    int32_t tile_x;          /* fluid-kernel tile x extent for this lattice: 8, 16, 32, 64, or 0 = the
+                                set's lbdem_config.tile_x (chosen per lattice by an autotuner) */
 } lbdem_params;
 
 /* Settings shared by all lattices of a set. */

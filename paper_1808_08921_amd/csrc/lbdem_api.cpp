@@ -114,6 +114,7 @@ int validate(int32_t n, const lbdem_params *lat, const lbdem_config *cfg)
             for (int k2 = 0; k2 < k; ++k2)
                 if (p.probe_z[k2] == p.probe_z[k]) return fail(LBDEM_EINVAL, "lattice %d: duplicate probe plane", m);
         }
+        if (p.tile_x != 0 && !is_pow2_tile(p.tile_x)) return fail(LBDEM_EINVAL, "lattice %d: tile_x must be 0, 8, 16, 32 or 64", m);
         if (p.max_particles < 0 || p.max_particles > kMaxLocal) return fail(LBDEM_EINVAL, "lattice %d: max_particles", m);
         if (p.max_particles > 0 && !(p.max_radius > 0.0 && p.max_radius < 1024.0))
             return fail(LBDEM_EINVAL, "lattice %d: max_radius must be positive when particles are allowed", m);
@@ -151,7 +152,7 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
         const lbdem_params &p = lat[m];
         MemberDev &M = G.mem[m];
         M.nx = p.nx; M.ny = p.ny; M.nz = p.nz;
-        M.bx = choose_tile_x(p.nx, cfg->tile_x);
+        M.bx = choose_tile_x(p.nx, p.tile_x ? p.tile_x : cfg->tile_x);
         M.bx_log2 = (int)std::lround(std::log2((double)M.bx));
         M.by = 256 / M.bx;
         M.ntx = (p.nx + M.bx - 1) / M.bx;

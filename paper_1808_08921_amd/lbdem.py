@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("n_probe", ctypes.c_int32), ("probe_z", ctypes.c_int32 * MAX_PROBES),
         ("max_particles", ctypes.c_int32),
         ("max_radius", ctypes.c_double),
+        ("tile_x", ctypes.c_int32),
     ]
 
 
@@ -111,7 +112,8 @@ def _f64(a, shape):
 
 
 def make_params(nx, ny, nz, tau=1.0, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), wave=WAVE_NONE, amp=0.0, omega=0.0,
-                t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=1.0, probe_z=(), max_particles=0, max_radius=12.0, **_ignored):
+                t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=1.0, probe_z=(), max_particles=0, max_radius=12.0, tile_x=0,
+                **_ignored):
     p = Params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     for k in range(6):
@@ -127,6 +129,7 @@ def make_params(nx, ny, nz, tau=1.0, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), wave=WAVE
         p.probe_z[k] = int(z)
     p.max_particles = int(max_particles)
     p.max_radius = float(max_radius)
+    p.tile_x = int(tile_x)
     return p
 
 
