@@ -67,6 +67,10 @@ def lib():
         L.orc_zou_he.argtypes = [dp, D, I]
         L.orc_rho_in_value.restype = D
         L.orc_rho_in_value.argtypes = [I, D, D, D, L64, L64]
+        L.orc_set_frozen.argtypes = [P, I]
+        L.orc_set_velocities.argtypes = [P, dp, dp]
+        L.orc_adjoint.restype = I
+        L.orc_adjoint.argtypes = [P, L64, D, D, dp, dp, dp, dp, dp]
         L.orc_contact.restype = I
         L.orc_contact.argtypes = [dp, dp, D, D, dp, dp, dp, dp, D, D, D, dp, dp, dp, dp, dp]
         _lib = L
@@ -74,7 +78,7 @@ def lib():
 
 
 def _dp(a):
-    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 def _ip(a):
@@ -167,6 +171,29 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+    def set_frozen(self, frozen=True):
+        """Frozen geometry: particles keep X, V, Omega; no DEM and no re-projection."""
+        lib().orc_set_frozen(self._h, 1 if frozen else 0)
+
+    def set_velocities(self, v=None, w=None):
+        v = None if v is None else _f64(v).reshape(self.np, 3)
+        w = None if w is None else _f64(w).reshape(self.np, 3)
+        lib().orc_set_velocities(self._h, _dp(v), _dp(w))
+
+    def adjoint(self, nsteps, tau, amp, dLdP):
+        """Forward nsteps over frozen geometry from the current state (probe signals P,
+        plane averages of rho - rho_f), then the discrete adjoint for the loss gradient
+        dLdP [nsteps][n_probe]: returns (P, dL/dtau, dL/damp, dL/dV [np][3])."""
+        dLdP = _f64(dLdP).reshape(nsteps, self.n_probe)
+        P = np.zeros((nsteps, max(self.n_probe, 1)))
+        gt, ga = ctypes.c_double(), ctypes.c_double()
+        gv = np.zeros((max(self.np, 1), 3))
+        rc = lib().orc_adjoint(self._h, int(nsteps), float(tau), float(amp), _dp(dLdP), _dp(P), ctypes.byref(gt),
+                               ctypes.byref(ga), _dp(gv))
+        if rc != 0:
+            raise MemoryError("oracle adjoint: out of memory")
+        return P[:, : self.n_probe], gt.value, ga.value, gv[: self.np]
 
     def set_particles(self, x, radius, v=None, w=None, fg=None, fixed=None):
         x = _f64(x).reshape(-1, 3)

@@ -174,6 +174,7 @@ typedef struct {
     /* probes: [t][n_probe][4] = n_fluid, sum rho', sum rho u_z, sum rho */
     double *probe;
     long probe_cap;
+    int frozen;     /* 1: particles keep X, V, Omega; no DEM and no re-projection */
 } orc_sim;
 
 static int axis_n(const orc_sim *s, int a) { return a == 0 ? s->p.nx : (a == 1 ? s->p.ny : s->p.nz); }
@@ -630,8 +631,10 @@ void orc_step(void *h, long nsteps)
     for (long it = 0; it < nsteps; ++it) {
         stream(s);
         boundary_collide_probe(s);
-        dem(s);
-        remap(s);
+        if (!s->frozen) {
+            dem(s);
+            remap(s);
+        }
         s->t += 1;
     }
 }
@@ -710,3 +713,214 @@ void orc_velocity_set(int *c, double *w, int *opp)
 void orc_equilibrium(double rho, const double *u, double *feq) { equilibrium(rho, u, feq); }
 void orc_collide_node(const double *f, double tau, double *out) { collide(f, tau, out); }
 void orc_zou_he(double *f, double rho, int outlet) { zou_he(f, rho, outlet); }
+
+/* ------------------------------------------------------------------------- */
+/* Adjoint of the fluid step over frozen particle geometry.                  */
+/* ------------------------------------------------------------------------- */
+/* Frozen geometry: the particles keep their position, velocity and angular velocity,
+ * the node map does not change, and one step is streaming with the walls of Eq. (mem),
+ * the density faces and the collision (steps 1-3 above).  The probe signal of step n is
+ * the plane average of rho - rho_f over the fluid nodes of each probe plane, taken from
+ * the pre-collision moments of time level n+1.  For a loss L(P) the discrete adjoint
+ * lambda^n = (dS/df^n)^T lambda^{n+1} + dL/df^n is propagated backwards through the
+ * stored forward states, and dL/dtau, dL/dA (the waveform amplitude) and dL/dV (particle
+ * velocities, through the moving-wall term) are accumulated.  Each transpose is taken of
+ * the plain definition: the collision Jacobian differentiated term by term, the density
+ * faces through the columns of their affine map, streaming by following every
+ * population to its single consumer. */
+void orc_set_frozen(void *h, int frozen) { ((orc_sim *)h)->frozen = frozen; }
+
+void orc_set_velocities(void *h, const double *V, const double *W)
+{
+    orc_sim *s = (orc_sim *)h;
+    for (int q = 0; q < 3 * s->np; ++q) {
+        if (V) s->V[q] = V[q];
+        if (W) s->W[q] = W[q];
+    }
+}
+
+/* d f~_d / d f_e of the BGK collision at one node, from Eqs. (bgk), (BGKequili),
+ * (rhoAndU): (1 - 1/tau) delta_de + (1/tau) d f^eq_d / d f_e, with d rho / d f_e = 1 and
+ * d u / d f_e = (c_e - u) / rho. */
+static void collide_jacobian(const double f[Q], double tau, double J[Q][Q])
+{
+    double rho, j[3], u[3];
+    moments(f, &rho, j);
+    for (int a = 0; a < 3; ++a) u[a] = j[a] / rho;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int d = 0; d < Q; ++d) {
+        double cu = CX[d] * u[0] + CY[d] * u[1] + CZ[d] * u[2];
+        double base = 1.0 + cu / CS2 + (cu * cu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2);
+        for (int e = 0; e < Q; ++e) {
+            double du[3] = {(CX[e] - u[0]) / rho, (CY[e] - u[1]) / rho, (CZ[e] - u[2]) / rho};
+            double cdu = CX[d] * du[0] + CY[d] * du[1] + CZ[d] * du[2];
+            double udu = u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+            double dfeq = weight(d) * (base + rho * (cdu / CS2 + cu * cdu / (CS2 * CS2) - udu / CS2));
+            J[d][e] = (d == e ? 1.0 - 1.0 / tau : 0.0) + dfeq / tau;
+        }
+    }
+}
+
+/* The density face as an affine map g = M f + b rho: column e of M is the face applied to
+ * the unit vector e with rho = 0, b is the face applied to zero with rho = 1. */
+static void zou_he_affine(int outlet, double M[Q][Q], double b[Q])
+{
+    for (int e = 0; e < Q; ++e) {
+        double v[Q] = {0};
+        v[e] = 1.0;
+        zou_he(v, 0.0, outlet);
+        for (int d = 0; d < Q; ++d) M[d][e] = v[d];
+    }
+    double z[Q] = {0};
+    zou_he(z, 1.0, outlet);
+    for (int d = 0; d < Q; ++d) b[d] = z[d];
+}
+
+/* Forward nsteps from the current state with relaxation time tau, waveform amplitude amp
+ * and the current particle velocities; P[n * n_probe + k] receives the probe signals.
+ * Then, for the loss gradient dLdP (same layout), g_tau, g_amp and g_v[np][3] receive
+ * dL/dtau, dL/damp and dL/dV.  The simulation ends at time t + nsteps.  Returns 0, or -1
+ * when memory runs out. */
+int orc_adjoint(void *h, long nsteps, double tau, double amp, const double *dLdP, double *P, double *g_tau,
+                double *g_amp, double *g_v)
+{
+    orc_sim *s = (orc_sim *)h;
+    const int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz, np = s->p.n_probe;
+    const long N = s->ncell;
+    const long t0 = s->t;
+    s->p.tau = tau;
+    s->p.amp = amp;
+    int frozen = s->frozen;
+    s->frozen = 1;
+    double *traj = (double *)malloc(sizeof(double) * Q * N * (size_t)(nsteps > 0 ? nsteps : 1));
+    double *lam = (double *)calloc((size_t)Q * N, sizeof(double));
+    double *lam_prev = (double *)calloc((size_t)Q * N, sizeof(double));
+    double *mu = (double *)calloc((size_t)Q * N, sizeof(double));
+    double *nfl = (double *)calloc((size_t)(np > 0 ? np : 1), sizeof(double));
+    if (!traj || !lam || !lam_prev || !mu || !nfl) {
+        free(traj); free(lam); free(lam_prev); free(mu); free(nfl);
+        s->frozen = frozen;
+        return -1;
+    }
+    /* forward, keeping every state f^n */
+    for (long n = 0; n < nsteps; ++n) {
+        memcpy(traj + (size_t)Q * N * n, s->f, sizeof(double) * Q * N);
+        orc_step(s, 1);
+        const double *pr = s->probe + 4 * (np > 0 ? np : 1) * (t0 + n);
+        for (int k = 0; k < np; ++k) {
+            P[n * np + k] = pr[4 * k + 1] / pr[4 * k + 0];
+            nfl[k] = pr[4 * k + 0];
+        }
+    }
+    double Mz[2][Q][Q], bz[2][Q];
+    zou_he_affine(0, Mz[0], bz[0]);
+    zou_he_affine(1, Mz[1], bz[1]);
+    double gw = 0.0, ga = 0.0;
+    for (int q = 0; q < 3 * s->np; ++q) g_v[q] = 0.0;
+    /* backward: lambda holds dL/df^{n+1} (zero after the last step) */
+    for (long n = nsteps - 1; n >= 0; --n) {
+        const double *fn = traj + (size_t)Q * N * n;
+        const double shape = orc_rho_in_value(s->p.wave, 0.0, 1.0, s->p.omega, s->p.t_n, t0 + n + 1);
+        const double rho_in = s->p.rho_f + amp * shape;
+        for (long q = 0; q < (long)Q * N; ++q) mu[q] = 0.0;
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    long x = ((long)k * ny + j) * nx + i;
+                    if (s->owner[x] >= 0) continue;
+                    /* pre-face populations: streaming and walls from f^n */
+                    double g0[Q], g[Q];
+                    for (int e = 0; e < Q; ++e) {
+                        if (e == 18) { g0[e] = fn[e * N + x]; continue; }
+                        int si, sj, sk;
+                        int kind = source_of(s, i, j, k, e, &si, &sj, &sk);
+                        int d = opposite(e);
+                        if (kind == 2) { g0[e] = 0.0; continue; }
+                        if (kind == 1) { g0[e] = fn[d * N + x]; continue; }
+                        long sn = ((long)sk * ny + sj) * nx + si;
+                        int q = s->owner[sn];
+                        if (q < 0) { g0[e] = fn[e * N + sn]; continue; }
+                        double xb[3] = {i + 0.5 * CX[d], j + 0.5 * CY[d], k + 0.5 * CZ[d]};
+                        double r[3], wr[3];
+                        for (int a = 0; a < 3; ++a) r[a] = min_image(s, a, xb[a] - s->X[3 * q + a]);
+                        cross(s->W + 3 * q, r, wr);
+                        double vbc = (s->V[3 * q] + wr[0]) * CX[d] + (s->V[3 * q + 1] + wr[1]) * CY[d] +
+                                     (s->V[3 * q + 2] + wr[2]) * CZ[d];
+                        g0[e] = fn[d * N + x] - 2.0 * weight(d) / CS2 * s->p.rho_f * vbc;
+                    }
+                    int face = -1;
+                    if (k == 0 && s->p.bc[4] == BC_PRESSURE) face = 0;
+                    if (k == nz - 1 && s->p.bc[5] == BC_PRESSURE) face = 1;
+                    for (int e = 0; e < Q; ++e) g[e] = g0[e];
+                    if (face >= 0) zou_he(g, face == 0 ? rho_in : s->p.rho_f, face);
+                    /* dL/dg: collision transpose and the probe term */
+                    double J[Q][Q], rho, jm[3], u[3], feq[Q];
+                    collide_jacobian(g, tau, J);
+                    moments(g, &rho, jm);
+                    for (int a = 0; a < 3; ++a) u[a] = jm[a] / rho;
+                    equilibrium(rho, u, feq);
+                    double dg[Q];
+                    for (int e = 0; e < Q; ++e) {
+                        double acc = 0.0;
+                        for (int d = 0; d < Q; ++d) acc += lam[d * N + x] * J[d][e];
+                        dg[e] = acc;
+                    }
+                    for (int pz = 0; pz < np; ++pz)
+                        if (s->p.probe_z[pz] == k)
+                            for (int e = 0; e < Q; ++e) dg[e] += dLdP[n * np + pz] / nfl[pz];
+                    /* d f~ / d(1/tau) = f^eq - f */
+                    for (int d = 0; d < Q; ++d) gw += lam[d * N + x] * (feq[d] - g[d]);
+                    /* through the density face */
+                    double dg0[Q];
+                    if (face >= 0) {
+                        for (int e = 0; e < Q; ++e) {
+                            double acc = 0.0;
+                            for (int d = 0; d < Q; ++d) acc += dg[d] * Mz[face][d][e];
+                            dg0[e] = acc;
+                        }
+                        if (face == 0)
+                            for (int d = 0; d < Q; ++d) ga += dg[d] * bz[0][d] * shape;
+                    } else {
+                        for (int e = 0; e < Q; ++e) dg0[e] = dg[e];
+                    }
+                    /* moving walls: d g0_e / dV_q = -2 (w_d / cs^2) rho_f c_d */
+                    for (int e = 0; e < 18; ++e) {
+                        int si, sj, sk;
+                        if (source_of(s, i, j, k, e, &si, &sj, &sk) != 0) continue;
+                        int q = s->owner[((long)sk * ny + sj) * nx + si];
+                        if (q < 0) continue;
+                        int d = opposite(e);
+                        double c = -2.0 * weight(d) / CS2 * s->p.rho_f;
+                        g_v[3 * q + 0] += dg0[e] * c * CX[d];
+                        g_v[3 * q + 1] += dg0[e] * c * CY[d];
+                        g_v[3 * q + 2] += dg0[e] * c * CZ[d];
+                    }
+                    for (int e = 0; e < Q; ++e) mu[e * N + x] = dg0[e];
+                }
+        /* streaming transpose: every f~_e(y) has one consumer */
+        for (long q = 0; q < (long)Q * N; ++q) lam_prev[q] = 0.0;
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    long x = ((long)k * ny + j) * nx + i;
+                    if (s->owner[x] >= 0) continue;
+                    for (int e = 0; e < Q; ++e) {
+                        if (e == 18) { lam_prev[e * N + x] += mu[e * N + x]; continue; }
+                        int si, sj, sk;
+                        int kind = source_of(s, i, j, k, e, &si, &sj, &sk);
+                        if (kind == 2) continue;
+                        int d = opposite(e);
+                        if (kind == 1) { lam_prev[d * N + x] += mu[e * N + x]; continue; }
+                        long sn = ((long)sk * ny + sj) * nx + si;
+                        if (s->owner[sn] >= 0) lam_prev[d * N + x] += mu[e * N + x];
+                        else lam_prev[e * N + sn] += mu[e * N + x];
+                    }
+                }
+        double *tmp = lam; lam = lam_prev; lam_prev = tmp;
+    }
+    *g_tau = gw * (-1.0 / (tau * tau));
+    *g_amp = ga;
+    free(traj); free(lam); free(lam_prev); free(mu); free(nfl);
+    s->frozen = frozen;
+    return 0;
+}
