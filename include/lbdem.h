@@ -198,6 +198,49 @@ int lbdem_timing_read(lbdem_set *set, double *ms, int64_t *count);
 /* Tile geometry actually used for lattice `lattice`: tile_x, tile_y, z_per_thread. */
 int lbdem_tile_info(lbdem_set *set, int32_t lattice, int32_t *tile_x, int32_t *tile_y, int32_t *z_per_thread);
 
+/* ---- Adjoint of the fluid step over frozen particle geometry ----------------------------
+ * An adjoint window binds to one lattice of a set and freezes its current geometry: node
+ * map, particle positions, angular velocities and radii.  Its forward map is nsteps fluid
+ * steps from the lattice's current populations: pull streaming with stationary walls and
+ * the moving walls of Eq. (mem) (particle velocities V chosen per forward), the density
+ * faces (Sec. 2.4) with rho_in = rho_f + A s(t+1) for the lattice's waveform s of unit
+ * amplitude (Eq. source), and the BGK collision with relaxation time tau (Eqs. bgk,
+ * BGKequili, rhoAndU).  The probe signal of step n is the plane average of rho - rho_f
+ * over the fluid nodes of each probe plane, from the pre-collision moments of time level
+ * t0+n+1.  lbdem_adj_backward returns the vector-Jacobian product of that map: for a loss
+ * gradient dL/dP it propagates the discrete adjoint backwards through the window,
+ * recomputing the forward states segment by segment from checkpoints taken every
+ * ckpt_every steps, and returns dL/dtau, dL/dA and dL/dV.  Gradient sums are FP64; the
+ * adjoint fields use the set's arithmetic precision (FP64 or FP32).
+ * The set must not be stepped or given new particles while a window is bound to it. */
+typedef struct lbdem_adj lbdem_adj;
+
+/* Device bytes for a window of nsteps (>= 1) with a checkpoint every ckpt_every (>= 1)
+ * steps: populations for the checkpoints and one segment, three adjoint fields, 18 FP64
+ * values per node for the particle-velocity gradient, and small tables. */
+int lbdem_adj_workspace_size(lbdem_set *set, int32_t lattice, int64_t nsteps, int32_t ckpt_every, size_t *bytes);
+
+/* Bind a window to lattice `lattice` of `set` (synchronises the set's stream).  workspace:
+ * caller-owned device memory of at least lbdem_adj_workspace_size bytes, 256-byte aligned,
+ * kept alive until lbdem_adj_destroy.  Errors: LBDEM_EINVAL, LBDEM_ENOMEM (workspace too
+ * small), LBDEM_EDEVICE. */
+int lbdem_adj_create(lbdem_set *set, int32_t lattice, int64_t nsteps, int32_t ckpt_every, void *workspace,
+                     size_t workspace_bytes, lbdem_adj **out);
+
+/* Run the window's forward map with relaxation time tau (> 1/2), waveform amplitude amp and
+ * particle velocities v (n x 3, the lattice's particle order; NULL = the velocities held
+ * when the window was created).  probes (NULL allowed): [nsteps][n_probe] signals.
+ * Synchronous.  The set's own populations are not modified. */
+int lbdem_adj_forward(lbdem_adj *adj, double tau, double amp, const double *v, double *probes);
+
+/* Vector-Jacobian product of the last forward: dL_dP [nsteps][n_probe] in, dL/dtau,
+ * dL/dA and dL/dV (n x 3) out (any output may be NULL).  Synchronous.  LBDEM_ESTATE if no
+ * forward has run. */
+int lbdem_adj_backward(lbdem_adj *adj, const double *dL_dP, double *dL_dtau, double *dL_damp, double *dL_dv);
+
+/* Release the window (its workspace stays with the caller). */
+int lbdem_adj_destroy(lbdem_adj *adj);
+
 #ifdef __cplusplus
 }
 #endif

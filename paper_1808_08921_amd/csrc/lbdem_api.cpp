@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -904,6 +905,236 @@ int lbdem_tile_info(lbdem_set *S, int32_t lattice, int32_t *tile_x, int32_t *til
     if (tile_x) *tile_x = M.bx;
     if (tile_y) *tile_y = M.by;
     if (z_per_thread) *z_per_thread = S->G.nzt;
+    return LBDEM_OK;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint window over frozen geometry
+// ---------------------------------------------------------------------------
+struct lbdem_adj {
+    lbdem_set *set = nullptr;
+    int lattice = 0, prec = 0;
+    size_t es = 0, cs = 0;      // storage / arithmetic element sizes
+    int64_t nsteps = 0;
+    int ck = 1, nck = 0;
+    int64_t t0 = 0;
+    double tau = 1.0;
+    bool have_forward = false;
+    AdjDev a{};
+    hipStream_t stream = nullptr;
+    char *f0 = nullptr, *ckp = nullptr, *seg = nullptr, *lam0 = nullptr, *lam1 = nullptr, *mu = nullptr;
+    double *vdev = nullptr, *shape = nullptr, *P = nullptr, *dLdP = nullptr, *accw = nullptr, *acca = nullptr;
+    double *macc = nullptr, *gv = nullptr, *nfl = nullptr, *X = nullptr, *W = nullptr, *R = nullptr;
+    int *own = nullptr, *pz = nullptr;
+    std::vector<double> v_host;
+};
+
+extern "C" {
+
+static size_t adj_layout(lbdem_adj *J, int64_t ncell, int64_t np, int nprobe, int nblk, int64_t nsteps, int ck,
+                         size_t es, size_t cs, char *base)
+{
+    Carver c;
+    c.base = base;
+    const size_t st = (size_t)kQ * ncell;
+    const int nck = (int)((nsteps + ck - 1) / ck);
+    char *f0 = c.take<char>(es * st);
+    char *ckp = c.take<char>(es * st * (size_t)nck);
+    char *seg = c.take<char>(es * st * (size_t)std::max(ck, 2));
+    char *lam0 = c.take<char>(cs * st), *lam1 = c.take<char>(cs * st), *mu = c.take<char>(cs * st);
+    double *macc = c.take<double>((size_t)(kQ - 1) * ncell);
+    int *own = c.take<int>((size_t)ncell);
+    double *X = c.take<double>(3 * (size_t)std::max<int64_t>(np, 1));
+    double *W = c.take<double>(3 * (size_t)std::max<int64_t>(np, 1));
+    double *R = c.take<double>((size_t)std::max<int64_t>(np, 1));
+    double *V = c.take<double>(3 * (size_t)std::max<int64_t>(np, 1));
+    double *gv = c.take<double>(3 * (size_t)std::max<int64_t>(np, 1));
+    double *shape = c.take<double>((size_t)std::max<int64_t>(nsteps, 1));
+    double *P = c.take<double>((size_t)std::max<int64_t>(nsteps * nprobe, 1));
+    double *dLdP = c.take<double>((size_t)std::max<int64_t>(nsteps * nprobe, 1));
+    double *accw = c.take<double>((size_t)nblk), *acca = c.take<double>((size_t)nblk);
+    double *nfl = c.take<double>((size_t)std::max(nprobe, 1));
+    int *pz = c.take<int>((size_t)std::max(nprobe, 1));
+    if (J) {
+        J->f0 = f0; J->ckp = ckp; J->seg = seg; J->lam0 = lam0; J->lam1 = lam1; J->mu = mu; J->macc = macc;
+        J->own = own; J->X = X; J->W = W; J->R = R; J->vdev = V; J->gv = gv; J->shape = shape; J->P = P;
+        J->dLdP = dLdP; J->accw = accw; J->acca = acca; J->nfl = nfl; J->pz = pz; J->nck = nck;
+    }
+    return (c.off + 255) & ~size_t(255);
+}
+
+int lbdem_adj_workspace_size(lbdem_set *S, int32_t lattice, int64_t nsteps, int32_t ckpt_every, size_t *bytes)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    if (!bytes) return fail(LBDEM_EINVAL, "null argument");
+    if (nsteps < 1 || ckpt_every < 1) return fail(LBDEM_EINVAL, "nsteps and ckpt_every must be >= 1");
+    const MemberDev &M = S->G.mem[lattice];
+    const size_t es = elem_size(S->G.prec), cs = S->G.prec == PREC_FP64 ? 8 : 4;
+    const int nblk = (int)((M.ncell + 255) / 256);
+    *bytes = adj_layout(nullptr, M.ncell, M.np, S->params[lattice].n_probe, nblk, nsteps, ckpt_every, es, cs, nullptr);
+    return LBDEM_OK;
+}
+
+int lbdem_adj_create(lbdem_set *S, int32_t lattice, int64_t nsteps, int32_t ckpt_every, void *workspace,
+                     size_t workspace_bytes, lbdem_adj **out)
+{
+    if (!out) return fail(LBDEM_EINVAL, "null output");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = lbdem_adj_workspace_size(S, lattice, nsteps, ckpt_every, &need);
+    if (rc) return rc;
+    if (!workspace || workspace_bytes < need) return fail(LBDEM_ENOMEM, "adjoint workspace needs %zu bytes", need);
+    if (((uintptr_t)workspace & 255) != 0) return fail(LBDEM_EINVAL, "workspace must be 256-byte aligned");
+    const MemberDev &M = S->G.mem[lattice];
+    const lbdem_params &p = S->params[lattice];
+    if (M.ncell > (1LL << 31) / kQ) return fail(LBDEM_EINVAL, "lattice too large for the adjoint window");
+    std::unique_ptr<lbdem_adj> J(new lbdem_adj());
+    J->set = S;
+    J->lattice = lattice;
+    J->prec = S->G.prec;
+    J->es = elem_size(S->G.prec);
+    J->cs = S->G.prec == PREC_FP64 ? 8 : 4;
+    J->nsteps = nsteps;
+    J->ck = ckpt_every;
+    J->stream = S->stream;
+    const int nblk = (int)((M.ncell + 255) / 256);
+    adj_layout(J.get(), M.ncell, M.np, p.n_probe, nblk, nsteps, ckpt_every, J->es, J->cs, (char *)workspace);
+    rc = lbdem_time(S, &J->t0);
+    if (rc) return rc;
+    rc = sync_set(S);
+    if (rc) return rc;
+    // frozen geometry: node map (local particle indices), particle state, start populations
+    std::vector<int32_t> own((size_t)M.ncell);
+    rc = lbdem_owner_get(S, lattice, own.data());
+    if (rc) return rc;
+    const int np = M.np;
+    std::vector<double> x(3 * (size_t)std::max(np, 1)), v(x.size()), w(x.size()), fh(x.size()), th(x.size());
+    rc = lbdem_particles_get(S, lattice, np, x.data(), v.data(), w.data(), fh.data(), th.data());
+    if (rc) return rc;
+    J->v_host.assign(v.begin(), v.begin() + 3 * np);
+    HIPCHK(hipMemcpy(J->own, own.data(), sizeof(int32_t) * own.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(J->X, x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(J->W, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice));
+    if (np > 0) HIPCHK(hipMemcpy(J->R, S->ds.R + M.p_off, sizeof(double) * np, hipMemcpyDeviceToDevice));
+    const char *src = (const char *)((J->t0 & 1) ? S->ds.popB : S->ds.popA) + J->es * M.pop_off;
+    HIPCHK(hipMemcpy(J->f0, src, J->es * kQ * M.ncell, hipMemcpyDeviceToDevice));
+    // unit-amplitude waveform at the time levels t0+1 .. t0+nsteps, Eq. (source)
+    std::vector<double> shape((size_t)nsteps);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        const int64_t tt = J->t0 + n + 1;
+        double sv = 0.0;
+        if (p.wave != LBDEM_WAVE_NONE && tt <= p.t_n) {
+            const double wt = p.omega * (double)tt;
+            sv = p.wave == LBDEM_WAVE_SINE ? sin(wt) : (p.wave == LBDEM_WAVE_COSINE ? 1.0 - cos(wt) : 1.0);
+        }
+        shape[(size_t)n] = sv;
+    }
+    HIPCHK(hipMemcpy(J->shape, shape.data(), sizeof(double) * shape.size(), hipMemcpyHostToDevice));
+    if (p.n_probe > 0) HIPCHK(hipMemcpy(J->pz, p.probe_z, sizeof(int) * p.n_probe, hipMemcpyHostToDevice));
+    AdjDev &a = J->a;
+    a.M = M;
+    a.ncell = (int)M.ncell;
+    a.own = J->own;
+    a.X = J->X; a.W = J->W; a.R = J->R; a.V = J->vdev;
+    a.np = np;
+    a.rho_f = p.rho_f;
+    a.omega = 1.0 / p.tau;
+    a.amp = p.rho_amp;
+    a.shape = J->shape;
+    a.n_probe = p.n_probe;
+    a.probe_z = J->pz;
+    a.probe_nfl = J->nfl;
+    a.P = J->P;
+    a.dLdP = J->dLdP;
+    a.acc_w = J->accw; a.acc_a = J->acca;
+    a.macc = J->macc;
+    a.gv = J->gv;
+    HIPCHK(launch_adj_nfl(a, J->nfl, J->stream));
+    HIPCHK(hipStreamSynchronize(J->stream));
+    *out = J.release();
+    return LBDEM_OK;
+}
+
+int lbdem_adj_forward(lbdem_adj *J, double tau, double amp, const double *v, double *probes)
+{
+    if (!J) return fail(LBDEM_EINVAL, "null adjoint window");
+    if (!(tau > 0.5)) return fail(LBDEM_EINVAL, "tau must exceed 1/2");
+    AdjDev &a = J->a;
+    const size_t st = (size_t)kQ * a.ncell * J->es;
+    J->tau = tau;
+    a.omega = 1.0 / tau;
+    a.amp = amp;
+    const std::vector<double> &vv = v ? std::vector<double>(v, v + 3 * a.np) : J->v_host;
+    if (a.np > 0) HIPCHK(hipMemcpyAsync(J->vdev, vv.data(), sizeof(double) * 3 * a.np, hipMemcpyHostToDevice, J->stream));
+    char *cur = J->seg, *nxt = J->seg + st;
+    HIPCHK(hipMemcpyAsync(cur, J->f0, st, hipMemcpyDeviceToDevice, J->stream));
+    for (int64_t n = 0; n < J->nsteps; ++n) {
+        if (n % J->ck == 0)
+            HIPCHK(hipMemcpyAsync(J->ckp + st * (size_t)(n / J->ck), cur, st, hipMemcpyDeviceToDevice, J->stream));
+        if (a.n_probe > 0) HIPCHK(launch_adj_probe(J->prec, a, cur, (int)n, J->stream));
+        HIPCHK(launch_adj_step(J->prec, a, cur, nxt, (int)n, J->stream));
+        std::swap(cur, nxt);
+    }
+    if (probes && a.n_probe > 0)
+        HIPCHK(hipMemcpyAsync(probes, J->P, sizeof(double) * J->nsteps * a.n_probe, hipMemcpyDeviceToHost, J->stream));
+    HIPCHK(hipStreamSynchronize(J->stream));
+    J->have_forward = true;
+    return LBDEM_OK;
+}
+
+int lbdem_adj_backward(lbdem_adj *J, const double *dL_dP, double *dL_dtau, double *dL_damp, double *dL_dv)
+{
+    if (!J) return fail(LBDEM_EINVAL, "null adjoint window");
+    if (!J->have_forward) return fail(LBDEM_ESTATE, "lbdem_adj_forward must run first");
+    AdjDev &a = J->a;
+    const size_t st = (size_t)kQ * a.ncell * J->es, sl = (size_t)kQ * a.ncell * J->cs;
+    const int nblk = adj_blocks(a);
+    if (a.n_probe > 0) {
+        if (!dL_dP) return fail(LBDEM_EINVAL, "null loss gradient");
+        HIPCHK(hipMemcpyAsync(J->dLdP, dL_dP, sizeof(double) * J->nsteps * a.n_probe, hipMemcpyHostToDevice, J->stream));
+    }
+    HIPCHK(hipMemsetAsync(J->lam0, 0, sl, J->stream));
+    HIPCHK(hipMemsetAsync(J->accw, 0, sizeof(double) * nblk, J->stream));
+    HIPCHK(hipMemsetAsync(J->acca, 0, sizeof(double) * nblk, J->stream));
+    HIPCHK(hipMemsetAsync(J->macc, 0, sizeof(double) * (kQ - 1) * (size_t)a.ncell, J->stream));
+    char *lam = J->lam0, *lam_next = J->lam1;
+    for (int s = J->nck - 1; s >= 0; --s) {
+        const int64_t start = (int64_t)s * J->ck;
+        const int64_t len = std::min<int64_t>(J->ck, J->nsteps - start);
+        // recompute the segment's states from its checkpoint
+        HIPCHK(hipMemcpyAsync(J->seg, J->ckp + st * (size_t)s, st, hipMemcpyDeviceToDevice, J->stream));
+        for (int64_t m = 0; m + 1 < len; ++m)
+            HIPCHK(launch_adj_step(J->prec, a, J->seg + st * (size_t)m, J->seg + st * (size_t)(m + 1), (int)(start + m),
+                                   J->stream));
+        for (int64_t m = len - 1; m >= 0; --m) {
+            HIPCHK(launch_adj_mu(J->prec, a, J->seg + st * (size_t)m, lam, J->mu, (int)(start + m), J->stream));
+            HIPCHK(launch_adj_pull(J->prec, a, J->mu, lam_next, J->stream));
+            std::swap(lam, lam_next);
+        }
+    }
+    HIPCHK(launch_adj_vgrad(a, J->stream));
+    std::vector<double> aw(nblk), aa(nblk);
+    HIPCHK(hipMemcpyAsync(aw.data(), J->accw, sizeof(double) * nblk, hipMemcpyDeviceToHost, J->stream));
+    HIPCHK(hipMemcpyAsync(aa.data(), J->acca, sizeof(double) * nblk, hipMemcpyDeviceToHost, J->stream));
+    if (dL_dv && a.np > 0)
+        HIPCHK(hipMemcpyAsync(dL_dv, J->gv, sizeof(double) * 3 * a.np, hipMemcpyDeviceToHost, J->stream));
+    HIPCHK(hipStreamSynchronize(J->stream));
+    double gw = 0.0, ga = 0.0;
+    for (int b = 0; b < nblk; ++b) { gw += aw[b]; ga += aa[b]; }
+    // omega = 1/tau
+    if (dL_dtau) *dL_dtau = gw * (-1.0 / (J->tau * J->tau));
+    if (dL_damp) *dL_damp = ga;
+    return LBDEM_OK;
+}
+
+int lbdem_adj_destroy(lbdem_adj *J)
+{
+    if (!J) return LBDEM_OK;
+    (void)hipStreamSynchronize(J->stream);
+    delete J;
     return LBDEM_OK;
 }
 

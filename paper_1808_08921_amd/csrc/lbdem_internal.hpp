@@ -114,6 +114,26 @@ struct DevSet {
     unsigned int *flags;
 };
 
+// Adjoint window over frozen geometry (one lattice): device view.
+struct AdjDev {
+    MemberDev M;              // the lattice's constants (offsets relative to this lattice)
+    int ncell;
+    const int *own;           // frozen node map, local particle indices [ncell]
+    const double *X, *W, *R;  // particle positions, angular velocities [np*3], radii [np]
+    const double *V;          // particle velocities of the window [np*3]
+    int np;
+    double rho_f, omega, amp; // omega = 1/tau and the waveform amplitude of the window
+    const double *shape;      // unit-amplitude waveform at time level t0+n+1 [nsteps]
+    int n_probe;
+    const int *probe_z;       // [n_probe]
+    const double *probe_nfl;  // fluid nodes per probe plane [n_probe]
+    double *P;                // probe signals [nsteps][n_probe]
+    const double *dLdP;       // loss gradient [nsteps][n_probe]
+    double *acc_w, *acc_a;    // per-workgroup sums of dL/domega and dL/dA [nblk]
+    double *macc;             // summed dL/dg of every direction whose source is a particle [18][ncell]
+    double *gv;               // dL/dV [np*3]
+};
+
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_PRESSURE = 2 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16DEV = 2, PREC_BF16DEV = 3 };
 
@@ -134,5 +154,13 @@ int refresh_grid(const DevSet &s);
 int links_grid(const DevSet &s);
 int motion_grid(const DevSet &s);
 int remap_grid(const DevSet &s);
+// adjoint window kernels (lbdem_kernels.hip)
+hipError_t launch_adj_step(int prec, const AdjDev &a, const void *fin, void *fout, int n, hipStream_t st);
+hipError_t launch_adj_probe(int prec, const AdjDev &a, const void *fin, int n, hipStream_t st);
+hipError_t launch_adj_mu(int prec, const AdjDev &a, const void *fin, const void *lam, void *mu, int n, hipStream_t st);
+hipError_t launch_adj_pull(int prec, const AdjDev &a, const void *mu, void *lam, hipStream_t st);
+hipError_t launch_adj_vgrad(const AdjDev &a, hipStream_t st);
+hipError_t launch_adj_nfl(const AdjDev &a, double *nfl, hipStream_t st);
+int adj_blocks(const AdjDev &a);
 
 } // namespace lbdem

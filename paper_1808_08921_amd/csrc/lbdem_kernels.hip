@@ -1401,6 +1401,335 @@ __global__ __launch_bounds__(256) void k_init_pops(DevSet s, long long total_cel
 }
 
 // ---------------------------------------------------------------------------
+// adjoint of the fluid step over frozen particle geometry
+// ---------------------------------------------------------------------------
+// The window's forward map is the fluid step with the node map and the particles frozen
+// (positions, angular velocities; prescribed velocities V): pull streaming with
+// stationary walls and the moving walls of Eq. (mem), the density faces (Sec. 2.4) with
+// rho_in = rho_f + A s(t+1), and the BGK collision, all on deviations from the rest
+// state as in the coupled fluid kernel.  Its discrete adjoint propagates a loss gradient
+// on the probe signals backwards: lambda^n = (dS/df^n)^T lambda^{n+1} + dL/df^n.
+
+// Pre-face populations g0 (deviation form) of fluid node (i, j, k) from the state fin,
+// and the unknown directions of a density face; the moving-wall term of Eq. (mem) uses
+// V_b . c_d = c_d . (V + Omega x (x - X)) of the source's particle.
+template <int P>
+__device__ __forceinline__ unsigned adj_gather(const AdjDev &a, const typename Prec<P>::S *fin, int i, int j, int k,
+                                               int cell, typename Prec<P>::C (&g)[kQ])
+{
+    using C = typename Prec<P>::C;
+    const MemberDev &M = a.M;
+    const int nx = M.nx, ny = M.ny, nz = M.nz, nc = a.ncell;
+    const int dims[3] = {nx, ny, nz};
+    unsigned unk = 0u;
+#pragma unroll
+    for (int e = 0; e < kQ - 1; ++e) {
+        int c[3] = {i - kCX[e], j - kCY[e], k - kCZ[e]};
+        int kind = 0; // 0 node, 1 wall, 2 unknown
+        for (int ax = 0; ax < 3; ++ax) {
+            if (c[ax] < 0 || c[ax] >= dims[ax]) {
+                const int f = M.bc[2 * ax + (c[ax] >= dims[ax] ? 1 : 0)];
+                if (f == BC_PRESSURE) kind = 2;
+                else if (f == BC_WALL) kind = max(kind, 1);
+                else c[ax] = c[ax] < 0 ? c[ax] + dims[ax] : c[ax] - dims[ax];
+            }
+        }
+        const int d = kOPP[e];
+        if (kind == 2) { g[e] = C(0); unk |= 1u << e; continue; }
+        if (kind == 1) { g[e] = decode_dev<P>(fin[d * nc + cell], d, a.rho_f); continue; }
+        const int sc = (c[2] * ny + c[1]) * nx + c[0];
+        const int q = a.own[sc];
+        if (q < 0) { g[e] = decode_dev<P>(fin[e * nc + sc], e, a.rho_f); continue; }
+        const double r0 = mimg((double)i - a.X[3 * q], M.per[0], M.box[0]);
+        const double r1 = mimg((double)j - a.X[3 * q + 1], M.per[1], M.box[1]);
+        const double r2 = mimg((double)k - a.X[3 * q + 2], M.per[2], M.box[2]);
+        const double *V = a.V + 3 * q, *W = a.W + 3 * q;
+        const double u0 = V[0] + (W[1] * r2 - W[2] * r1);
+        const double u1 = V[1] + (W[2] * r0 - W[0] * r2);
+        const double u2 = V[2] + (W[0] * r1 - W[1] * r0);
+        const double cu = (double)kCX[d] * u0 + (double)kCY[d] * u1 + (double)kCZ[d] * u2;
+        g[e] = decode_dev<P>(fin[d * nc + cell], d, a.rho_f) - (C)(kMW[d] * a.rho_f) * (C)cu;
+    }
+    g[18] = decode_dev<P>(fin[18 * nc + cell], 18, a.rho_f);
+    return unk;
+}
+
+__device__ __forceinline__ void adj_coords(const AdjDev &a, int cell, int &i, int &j, int &k)
+{
+    const int nxy = a.M.nx * a.M.ny;
+    k = cell / nxy;
+    const int rem = cell - k * nxy;
+    j = rem / a.M.nx;
+    i = rem - j * a.M.nx;
+}
+
+// One frozen forward step fin -> fout.
+template <int P>
+__global__ __launch_bounds__(256) void k_adj_step(AdjDev a, const typename Prec<P>::S *fin, typename Prec<P>::S *fout, int n)
+{
+    const double drho_in = a.amp * a.shape[n];
+    using C = typename Prec<P>::C;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= a.ncell || a.own[cell] >= 0) return;
+    int i, j, k;
+    adj_coords(a, cell, i, j, k);
+    C f[kQ];
+    adj_gather<P>(a, fin, i, j, k, cell, f);
+    if (k == 0 && a.M.bc[4] == BC_PRESSURE) zou_he<C>(f, (C)drho_in, false);
+    if (k == a.M.nz - 1 && a.M.bc[5] == BC_PRESSURE) zou_he<C>(f, C(0), true);
+    C drho, jx, jy, jz;
+    moments<C>(f, drho, jx, jy, jz);
+    const C rho = (C)a.rho_f + drho;
+    const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    const C uu = ux * ux + uy * uy + uz * uz;
+    const C om = (C)a.omega;
+#pragma unroll
+    for (int d = 0; d < kQ; ++d) {
+        const C fe = feq_dev<C>(d, drho, rho, ux, uy, uz, uu);
+        store_dev<P>(fout, (unsigned)(d * a.ncell + cell), d, f[d] + om * (fe - f[d]), a.rho_f);
+    }
+}
+
+// Probe signals of step n from the state f^n: one workgroup per probe plane, the plane
+// average of rho - rho_f over its fluid nodes (pre-collision, after the density faces).
+template <int P>
+__global__ __launch_bounds__(256) void k_adj_probe(AdjDev a, const typename Prec<P>::S *fin, int n)
+{
+    using C = typename Prec<P>::C;
+    __shared__ double red[4][8];
+    const int kp = blockIdx.x;
+    if (kp >= a.n_probe) return;
+    const int k = a.probe_z[kp];
+    const int nxy = a.M.nx * a.M.ny;
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < nxy; t += blockDim.x) {
+        const int cell = k * nxy + t;
+        if (a.own[cell] >= 0) continue;
+        const int j = t / a.M.nx, i = t - j * a.M.nx;
+        C f[kQ];
+        adj_gather<P>(a, fin, i, j, k, cell, f);
+        if (k == 0 && a.M.bc[4] == BC_PRESSURE) zou_he<C>(f, (C)(a.amp * a.shape[n]), false);
+        if (k == a.M.nz - 1 && a.M.bc[5] == BC_PRESSURE) zou_he<C>(f, C(0), true);
+        C drho, jx, jy, jz;
+        moments<C>(f, drho, jx, jy, jz);
+        v[0] += (double)drho;
+    }
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) a.P[(long long)n * a.n_probe + kp] = v[0] / a.probe_nfl[kp];
+}
+
+// Fluid nodes of each probe plane (one workgroup per plane).
+__global__ __launch_bounds__(256) void k_adj_nfl(AdjDev a, double *nfl)
+{
+    __shared__ double red[4][8];
+    const int kp = blockIdx.x;
+    if (kp >= a.n_probe) return;
+    const int nxy = a.M.nx * a.M.ny;
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < nxy; t += blockDim.x)
+        if (a.own[a.probe_z[kp] * nxy + t] < 0) v[0] += 1.0;
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) nfl[kp] = v[0];
+}
+
+// Adjoint through step n at every fluid node: from lambda^{n+1} (dL/d of the post-collision
+// state) and the probe term, mu = dL/dg0 of the pre-face populations g0 of time level
+// n+1.  Collision transpose: with A = sum lambda_d w_d, B = sum lambda_d w_d c_d,
+// Cm = sum lambda_d w_d (c_d.u) c_d, D = sum lambda_d w_d (c_d.u)^2 (lattice units,
+// 1/c_s^2 = 3), sum_d lambda_d df^eq_d/dg_e = A (1 + 1.5 u.u) - 4.5 D + (3 B + 9 Cm - 3 A u).c_e.
+// The density faces are transposed by hand from their closure formulas.  Also collected:
+// dL/domega = sum lambda_d (f^eq_d - g_d), dL/drho_in, and per node dL/dg0_e of every
+// direction whose source is a particle (for dL/dV).
+template <int P>
+__global__ __launch_bounds__(256) void k_adj_mu(AdjDev a, const typename Prec<P>::S *fin,
+                                                const typename Prec<P>::C *lam, typename Prec<P>::C *mu, int n)
+{
+    using C = typename Prec<P>::C;
+    __shared__ double red[4][8];
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = a.ncell;
+    double acc[2] = {0.0, 0.0}; // dL/domega, dL/drho_in
+    if (cell < nc && a.own[cell] < 0) {
+        int i, j, k;
+        adj_coords(a, cell, i, j, k);
+        C g[kQ];
+        const unsigned unk = adj_gather<P>(a, fin, i, j, k, cell, g);
+        const int face = (k == 0 && a.M.bc[4] == BC_PRESSURE) ? 0 : ((k == a.M.nz - 1 && a.M.bc[5] == BC_PRESSURE) ? 1 : -1);
+        if (face == 0) zou_he<C>(g, (C)(a.amp * a.shape[n]), false);
+        if (face == 1) zou_he<C>(g, C(0), true);
+        C drho, jx, jy, jz;
+        moments<C>(g, drho, jx, jy, jz);
+        const C rho = (C)a.rho_f + drho;
+        const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
+        const C uu = ux * ux + uy * uy + uz * uz;
+        C l[kQ];
+#pragma unroll
+        for (int d = 0; d < kQ; ++d) l[d] = lam[d * nc + cell];
+        C A = C(0), B0 = C(0), B1 = C(0), B2 = C(0), C0 = C(0), C1 = C(0), C2 = C(0), D = C(0);
+        double gw = 0.0;
+#pragma unroll
+        for (int d = 0; d < kQ; ++d) {
+            const C wl = (C)kWd[d] * l[d];
+            const C cu = (C)kCX[d] * ux + (C)kCY[d] * uy + (C)kCZ[d] * uz;
+            A += wl;
+            B0 += wl * (C)kCX[d]; B1 += wl * (C)kCY[d]; B2 += wl * (C)kCZ[d];
+            C0 += wl * cu * (C)kCX[d]; C1 += wl * cu * (C)kCY[d]; C2 += wl * cu * (C)kCZ[d];
+            D += wl * cu * cu;
+            gw += (double)l[d] * (double)(feq_dev<C>(d, drho, rho, ux, uy, uz, uu) - g[d]);
+        }
+        acc[0] = gw;
+        const C om = (C)a.omega;
+        const C base = A * (C(1) + C(1.5) * uu) - C(4.5) * D;
+        const C v0 = C(3) * B0 + C(9) * C0 - C(3) * A * ux;
+        const C v1 = C(3) * B1 + C(9) * C1 - C(3) * A * uy;
+        const C v2 = C(3) * B2 + C(9) * C2 - C(3) * A * uz;
+        C pt = C(0);
+        for (int kp = 0; kp < a.n_probe; ++kp)
+            if (a.probe_z[kp] == k) pt += (C)(a.dLdP[(long long)n * a.n_probe + kp] / a.probe_nfl[kp]);
+        C m[kQ];
+#pragma unroll
+        for (int e = 0; e < kQ; ++e)
+            m[e] = (C(1) - om) * l[e] + om * (base + (C)kCX[e] * v0 + (C)kCY[e] * v1 + (C)kCZ[e] * v2) + pt;
+        // density faces (paper index p -> m[p-1]); unknowns end with no dependence on g0
+        if (face == 0) {
+            const C av = m[4], bv = m[8], cv = m[12], dv = m[14], ev = m[16];
+            const C R = av / C(3) + (bv + cv + dv + ev) / C(6), X = cv - bv, Y = ev - dv;
+            acc[1] = (double)R * a.shape[n]; // d rho_in / dA = s(t+1)
+            m[4] = m[8] = m[12] = m[14] = m[16] = C(0);
+            const int s0[9] = {0, 1, 2, 3, 6, 7, 10, 11, 18}, sm[5] = {5, 9, 13, 15, 17};
+#pragma unroll
+            for (int q = 0; q < 9; ++q) m[s0[q]] -= R;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) m[sm[q]] -= C(2) * R;
+            m[0] += C(0.5) * X; m[6] += C(0.5) * X; m[7] += C(0.5) * X;
+            m[1] -= C(0.5) * X; m[10] -= C(0.5) * X; m[11] -= C(0.5) * X;
+            m[2] += C(0.5) * Y; m[6] += C(0.5) * Y; m[10] += C(0.5) * Y;
+            m[3] -= C(0.5) * Y; m[7] -= C(0.5) * Y; m[11] -= C(0.5) * Y;
+            m[5] += av; m[13] += bv; m[9] += cv; m[17] += dv; m[15] += ev;
+        } else if (face == 1) {
+            const C av = m[5], bv = m[13], cv = m[9], dv = m[17], ev = m[15];
+            const C R = -av / C(3) - (bv + cv + dv + ev) / C(6), X = bv - cv, Y = dv - ev;
+            m[5] = m[13] = m[9] = m[17] = m[15] = C(0);
+            const int s0[9] = {0, 1, 2, 3, 6, 7, 10, 11, 18}, sp[5] = {4, 8, 12, 14, 16};
+#pragma unroll
+            for (int q = 0; q < 9; ++q) m[s0[q]] += R;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) m[sp[q]] += C(2) * R;
+            m[0] += C(0.5) * X; m[6] += C(0.5) * X; m[7] += C(0.5) * X;
+            m[1] -= C(0.5) * X; m[10] -= C(0.5) * X; m[11] -= C(0.5) * X;
+            m[2] += C(0.5) * Y; m[6] += C(0.5) * Y; m[10] += C(0.5) * Y;
+            m[3] -= C(0.5) * Y; m[7] -= C(0.5) * Y; m[11] -= C(0.5) * Y;
+            m[4] += av; m[8] += bv; m[12] += cv; m[14] += dv; m[16] += ev;
+        }
+        (void)unk;
+        // moving walls: the directions whose source is a particle
+        const int dims[3] = {a.M.nx, a.M.ny, a.M.nz};
+#pragma unroll
+        for (int e = 0; e < kQ - 1; ++e) {
+            int c[3] = {i - kCX[e], j - kCY[e], k - kCZ[e]};
+            bool ok = true;
+            for (int ax = 0; ax < 3; ++ax)
+                if (c[ax] < 0 || c[ax] >= dims[ax]) {
+                    if (a.M.per[ax]) c[ax] = c[ax] < 0 ? c[ax] + dims[ax] : c[ax] - dims[ax];
+                    else ok = false;
+                }
+            if (ok && a.own[(c[2] * dims[1] + c[1]) * dims[0] + c[0]] >= 0)
+                a.macc[(long long)e * nc + cell] += (double)m[e];
+        }
+#pragma unroll
+        for (int e = 0; e < kQ; ++e) mu[e * nc + cell] = m[e];
+    }
+    block_sum<2>(acc, red);
+    if (threadIdx.x == 0) {
+        a.acc_w[blockIdx.x] += acc[0];
+        a.acc_a[blockIdx.x] += acc[1];
+    }
+}
+
+// lambda^n from mu: every post-collision population f~_e(y) has one consumer, the node
+// y + c_e pulling direction e, or y itself bouncing it back from a wall or a particle;
+// populations leaving through a density face have none.
+template <int P>
+__global__ __launch_bounds__(256) void k_adj_pull(AdjDev a, const typename Prec<P>::C *mu, typename Prec<P>::C *lam)
+{
+    using C = typename Prec<P>::C;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = a.ncell;
+    if (cell >= nc) return;
+    if (a.own[cell] >= 0) {
+#pragma unroll
+        for (int e = 0; e < kQ; ++e) lam[e * nc + cell] = C(0);
+        return;
+    }
+    int i, j, k;
+    adj_coords(a, cell, i, j, k);
+    const int dims[3] = {a.M.nx, a.M.ny, a.M.nz};
+#pragma unroll
+    for (int e = 0; e < kQ - 1; ++e) {
+        int c[3] = {i + kCX[e], j + kCY[e], k + kCZ[e]};
+        int kind = 0;
+        for (int ax = 0; ax < 3; ++ax) {
+            if (c[ax] < 0 || c[ax] >= dims[ax]) {
+                const int f = a.M.bc[2 * ax + (c[ax] >= dims[ax] ? 1 : 0)];
+                if (f == BC_PRESSURE) kind = 2;
+                else if (f == BC_WALL) kind = max(kind, 1);
+                else c[ax] = c[ax] < 0 ? c[ax] + dims[ax] : c[ax] - dims[ax];
+            }
+        }
+        C v = C(0);
+        if (kind == 1) v = mu[kOPP[e] * nc + cell];
+        else if (kind == 0) {
+            const int x = (c[2] * dims[1] + c[1]) * dims[0] + c[0];
+            v = (a.own[x] >= 0) ? mu[kOPP[e] * nc + cell] : mu[e * nc + x];
+        }
+        lam[e * nc + cell] = v;
+    }
+    lam[18 * nc + cell] = mu[18 * nc + cell];
+}
+
+// dL/dV_q = sum over q's links (x, e) of -2 (w_d / c_s^2) rho_f c_d dL/dg0_e(x), d = e*:
+// one workgroup per particle over the nodes within R_q + 2 of X_q, in a fixed order.
+__global__ __launch_bounds__(256) void k_adj_vgrad(AdjDev a)
+{
+    __shared__ double red[4][8];
+    const int q = blockIdx.x;
+    if (q >= a.np) return;
+    const MemberDev &M = a.M;
+    const int dims[3] = {M.nx, M.ny, M.nz};
+    int lo[3], ext[3];
+    for (int ax = 0; ax < 3; ++ax) axis_range(a.X[3 * q + ax], a.R[q] + 2.0, dims[ax], M.per[ax], lo[ax], ext[ax]);
+    const int tot = ext[0] * ext[1] * ext[2];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int ii = wrapc(lo[0] + idx % ext[0], dims[0]);
+        const int jj = wrapc(lo[1] + (idx / ext[0]) % ext[1], dims[1]);
+        const int kk = wrapc(lo[2] + idx / (ext[0] * ext[1]), dims[2]);
+        const int x = (kk * dims[1] + jj) * dims[0] + ii;
+        if (a.own[x] >= 0) continue;
+        for (int e = 0; e < kQ - 1; ++e) {
+            int c[3] = {ii - kCXd[e], jj - kCYd[e], kk - kCZd[e]};
+            bool ok = true;
+            for (int ax = 0; ax < 3; ++ax)
+                if (c[ax] < 0 || c[ax] >= dims[ax]) {
+                    if (M.per[ax]) c[ax] = c[ax] < 0 ? c[ax] + dims[ax] : c[ax] - dims[ax];
+                    else ok = false;
+                }
+            if (!ok || a.own[(c[2] * dims[1] + c[1]) * dims[0] + c[0]] != q) continue;
+            // d g0_e / dV = -2 (w_d / c_s^2) rho_f c_d with c_d = -c_e and w_d = w_e
+            const int c2 = kCXd[e] * kCXd[e] + kCYd[e] * kCYd[e] + kCZd[e] * kCZd[e];
+            const double w = (c2 == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
+            const double f = 2.0 * w / kCS2 * a.rho_f * a.macc[(long long)e * a.ncell + x];
+            acc[0] += f * kCXd[e];
+            acc[1] += f * kCYd[e];
+            acc[2] += f * kCZd[e];
+        }
+    }
+    block_sum<3>(acc, red);
+    if (threadIdx.x == 0)
+        for (int ax = 0; ax < 3; ++ax) a.gv[3 * q + ax] = acc[ax];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 void *fluid_kernel_ptr(int prec)
@@ -1481,6 +1810,90 @@ hipError_t launch_remap_prec(int prec, const DevSet &s, int mode, int only_membe
     case PREC_FP16DEV: hipLaunchKernelGGL(k_remap<PREC_FP16DEV>, dim3(remap_grid(s)), dim3(256), 0, st, s, mode, only_member); break;
     default: hipLaunchKernelGGL(k_remap<PREC_BF16DEV>, dim3(remap_grid(s)), dim3(256), 0, st, s, mode, only_member); break;
     }
+    return hipGetLastError();
+}
+
+int adj_blocks(const AdjDev &a) { return (a.ncell + 255) / 256; }
+
+template <int P> using StoreT = typename Prec<P>::S;
+template <int P> using CompT = typename Prec<P>::C;
+
+hipError_t launch_adj_step(int prec, const AdjDev &a, const void *fin, void *fout, int n, hipStream_t st)
+{
+    switch (prec) {
+    case PREC_FP64:
+        hipLaunchKernelGGL(k_adj_step<PREC_FP64>, dim3(adj_blocks(a)), dim3(256), 0, st, a,
+                           (const StoreT<PREC_FP64> *)fin, (StoreT<PREC_FP64> *)fout, n);
+        break;
+    case PREC_FP32:
+        hipLaunchKernelGGL(k_adj_step<PREC_FP32>, dim3(adj_blocks(a)), dim3(256), 0, st, a,
+                           (const StoreT<PREC_FP32> *)fin, (StoreT<PREC_FP32> *)fout, n);
+        break;
+    case PREC_FP16DEV:
+        hipLaunchKernelGGL(k_adj_step<PREC_FP16DEV>, dim3(adj_blocks(a)), dim3(256), 0, st, a,
+                           (const StoreT<PREC_FP16DEV> *)fin, (StoreT<PREC_FP16DEV> *)fout, n);
+        break;
+    default:
+        hipLaunchKernelGGL(k_adj_step<PREC_BF16DEV>, dim3(adj_blocks(a)), dim3(256), 0, st, a,
+                           (const StoreT<PREC_BF16DEV> *)fin, (StoreT<PREC_BF16DEV> *)fout, n);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_probe(int prec, const AdjDev &a, const void *fin, int n, hipStream_t st)
+{
+    const int g = a.n_probe > 0 ? a.n_probe : 1;
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL(k_adj_probe<PREC_FP64>, dim3(g), dim3(256), 0, st, a, (const StoreT<PREC_FP64> *)fin, n); break;
+    case PREC_FP32: hipLaunchKernelGGL(k_adj_probe<PREC_FP32>, dim3(g), dim3(256), 0, st, a, (const StoreT<PREC_FP32> *)fin, n); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL(k_adj_probe<PREC_FP16DEV>, dim3(g), dim3(256), 0, st, a, (const StoreT<PREC_FP16DEV> *)fin, n); break;
+    default: hipLaunchKernelGGL(k_adj_probe<PREC_BF16DEV>, dim3(g), dim3(256), 0, st, a, (const StoreT<PREC_BF16DEV> *)fin, n); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_mu(int prec, const AdjDev &a, const void *fin, const void *lam, void *mu, int n, hipStream_t st)
+{
+    switch (prec) {
+    case PREC_FP64:
+        hipLaunchKernelGGL(k_adj_mu<PREC_FP64>, dim3(adj_blocks(a)), dim3(256), 0, st, a, (const StoreT<PREC_FP64> *)fin,
+                           (const CompT<PREC_FP64> *)lam, (CompT<PREC_FP64> *)mu, n);
+        break;
+    case PREC_FP32:
+        hipLaunchKernelGGL(k_adj_mu<PREC_FP32>, dim3(adj_blocks(a)), dim3(256), 0, st, a, (const StoreT<PREC_FP32> *)fin,
+                           (const CompT<PREC_FP32> *)lam, (CompT<PREC_FP32> *)mu, n);
+        break;
+    case PREC_FP16DEV:
+        hipLaunchKernelGGL(k_adj_mu<PREC_FP16DEV>, dim3(adj_blocks(a)), dim3(256), 0, st, a, (const StoreT<PREC_FP16DEV> *)fin,
+                           (const CompT<PREC_FP16DEV> *)lam, (CompT<PREC_FP16DEV> *)mu, n);
+        break;
+    default:
+        hipLaunchKernelGGL(k_adj_mu<PREC_BF16DEV>, dim3(adj_blocks(a)), dim3(256), 0, st, a, (const StoreT<PREC_BF16DEV> *)fin,
+                           (const CompT<PREC_BF16DEV> *)lam, (CompT<PREC_BF16DEV> *)mu, n);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_pull(int prec, const AdjDev &a, const void *mu, void *lam, hipStream_t st)
+{
+    if (prec == PREC_FP64)
+        hipLaunchKernelGGL(k_adj_pull<PREC_FP64>, dim3(adj_blocks(a)), dim3(256), 0, st, a, (const double *)mu, (double *)lam);
+    else
+        hipLaunchKernelGGL(k_adj_pull<PREC_FP32>, dim3(adj_blocks(a)), dim3(256), 0, st, a, (const float *)mu, (float *)lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_vgrad(const AdjDev &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_vgrad, dim3(a.np > 0 ? a.np : 1), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_nfl(const AdjDev &a, double *nfl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_nfl, dim3(a.n_probe > 0 ? a.n_probe : 1), dim3(256), 0, st, a, nfl);
     return hipGetLastError();
 }
 

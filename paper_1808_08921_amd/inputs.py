@@ -113,6 +113,33 @@ def chain_case(n_spheres: int = 60, r0: float = 5.0, overlap: float = 0.01, side
             "fixed": np.full(n_spheres, 1 if fixed else 0, np.uint8), "shape": (side, side, length)}
 
 
+def adjoint_fcc_case(n_xy: int = 64, nz: int = 256, radius: float = 8.0, offset: float = 8.0,
+                     period: float = 200.0, amp: float = 1e-3):
+    """Frozen packing of the adjoint workload: touching FCC spheres of radius R (cubic cell
+    a = 2 sqrt(2) R) in an n_xy x n_xy x nz lattice with walls on the x and y faces and
+    density faces in z; FCC sites shifted by `offset` on every axis, keeping the spheres
+    whose centres lie at least R inside the lattice on every axis (275 spheres for the
+    defaults).  Returns (params, packing) like wave_fcc_case."""
+    a = 2.0 * math.sqrt(2.0) * radius
+    hi = (n_xy - 1 - radius, n_xy - 1 - radius, nz - 1 - radius)
+    sites = []
+    for k in range(int(nz / a) + 2):
+        for j in range(int(n_xy / a) + 2):
+            for i in range(int(n_xy / a) + 2):
+                for b in _FCC_BASIS:
+                    p = ((i + b[0]) * a + offset, (j + b[1]) * a + offset, (k + b[2]) * a + offset)
+                    if all(radius <= p[ax] <= hi[ax] for ax in range(3)):
+                        sites.append(p)
+    x = np.array(sites, dtype=np.float64)
+    x = x[np.lexsort((x[:, 0], x[:, 1], x[:, 2]))]
+    n = x.shape[0]
+    params = dict(nx=n_xy, ny=n_xy, nz=nz, tau=1.0, rho_f=1.0, bc=(WALL, WALL, WALL, WALL, PRESSURE, PRESSURE),
+                  wave=WAVE_COSINE, amp=amp, omega=2.0 * math.pi / period, t_n=int(round(period)),
+                  E=10.37, nu=0.2, mu=0.0, rho_p=2.466, probe_z=tuple(range(16, nz, 16)), max_radius=radius + 1.0)
+    pk = {"x": x, "radius": np.full(n, radius), "fixed": np.ones(n, np.uint8), "shape": (n_xy, n_xy, nz)}
+    return params, pk
+
+
 def ensemble_members(n: int = 64, base_seed: int = 1000, a: float = 24.0):
     """Uneven FCC samples for the batched ensemble: sample s draws, from
     default_rng(base_seed + s), n_xy in {2,3,4}, n_z in {8..16}, overlap

@@ -88,11 +88,17 @@ def lib():
         L.lbdem_timing_enable.argtypes = [P, ctypes.c_int]
         L.lbdem_timing_read.argtypes = [P, dp, ctypes.POINTER(I64)]
         L.lbdem_tile_info.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        L.lbdem_adj_workspace_size.argtypes = [P, I32, I64, I32, ctypes.POINTER(SZ)]
+        L.lbdem_adj_create.argtypes = [P, I32, I64, I32, VP, SZ, ctypes.POINTER(P)]
+        L.lbdem_adj_forward.argtypes = [P, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.lbdem_adj_backward.argtypes = [P, dp, dp, dp, dp]
+        L.lbdem_adj_destroy.argtypes = [P]
         for name in ("lbdem_default_config", "lbdem_workspace_size", "lbdem_create", "lbdem_destroy",
                      "lbdem_set_stream", "lbdem_particles_set", "lbdem_particles_get", "lbdem_step", "lbdem_time",
                      "lbdem_synchronize", "lbdem_status", "lbdem_probe_read", "lbdem_populations_get",
                      "lbdem_populations_set", "lbdem_owner_get", "lbdem_timing_enable", "lbdem_timing_read",
-                     "lbdem_tile_info"):
+                     "lbdem_tile_info", "lbdem_adj_workspace_size", "lbdem_adj_create", "lbdem_adj_forward",
+                     "lbdem_adj_backward", "lbdem_adj_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -260,3 +266,86 @@ class LatticeSet:
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().lbdem_tile_info(self._h, lattice, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+
+class AdjointWindow:
+    """Adjoint of ``nsteps`` fluid steps of one lattice of a set over its current (frozen)
+    particle geometry, with checkpoints every ``ckpt_every`` steps (C ABI lbdem_adj_*).
+
+    forward(tau, amp, v) returns the probe signals [nsteps][n_probe] (plane averages of
+    rho - rho_f); backward(dL_dP) returns (dL/dtau, dL/dA, dL/dV [n][3]) for the last
+    forward.  The set must not be stepped while the window is in use."""
+
+    def __init__(self, lset, lattice=0, nsteps=2000, ckpt_every=100):
+        import torch
+
+        self._set = lset
+        self.nsteps = int(nsteps)
+        self.n_probe = lset.n_probe[lattice]
+        self.n_particles = lset.n_particles[lattice]
+        nbytes = ctypes.c_size_t()
+        _check(lib().lbdem_adj_workspace_size(lset._h, lattice, self.nsteps, int(ckpt_every), ctypes.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self._ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=lset.device)
+        h = ctypes.c_void_p()
+        _check(lib().lbdem_adj_create(lset._h, lattice, self.nsteps, int(ckpt_every), ctypes.c_void_p(self._ws.data_ptr()),
+                                      nbytes.value, ctypes.byref(h)))
+        self._h = h
+        self.generation = 0
+
+    def forward(self, tau, amp, v=None):
+        out = np.zeros((self.nsteps, max(self.n_probe, 1)))
+        vv = None if v is None else _f64(v, (self.n_particles, 3))
+        _check(lib().lbdem_adj_forward(self._h, float(tau), float(amp), _dp(vv), _dp(out)))
+        self.generation += 1
+        return out[:, : self.n_probe]
+
+    def backward(self, dL_dP):
+        g = _f64(dL_dP, (self.nsteps, self.n_probe))
+        gt, ga = ctypes.c_double(), ctypes.c_double()
+        gv = np.zeros((max(self.n_particles, 1), 3))
+        _check(lib().lbdem_adj_backward(self._h, _dp(g), ctypes.byref(gt), ctypes.byref(ga), _dp(gv)))
+        return gt.value, ga.value, gv[: self.n_particles]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().lbdem_adj_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _probe_function():
+    import torch
+
+    class ProbeSignals(torch.autograd.Function):
+        """Probe signals of an AdjointWindow as a differentiable function of (tau, A, V);
+        the backward pass is the window's discrete adjoint (checkpointed)."""
+
+        @staticmethod
+        def forward(ctx, tau, amp, v, window):
+            P = window.forward(float(tau), float(amp), v.detach().cpu().numpy())
+            ctx.window = window
+            ctx.generation = window.generation
+            return torch.from_numpy(P).to(torch.float64)
+
+        @staticmethod
+        def backward(ctx, grad_P):
+            w = ctx.window
+            if w.generation != ctx.generation:
+                raise RuntimeError("the adjoint window ran another forward since this one")
+            gt, ga, gv = w.backward(grad_P.detach().cpu().numpy())
+            return (torch.tensor(gt, dtype=torch.float64), torch.tensor(ga, dtype=torch.float64),
+                    torch.from_numpy(gv).to(torch.float64), None)
+
+    return ProbeSignals
+
+
+def probe_signals(window, tau, amp, v):
+    """Differentiable probe signals [nsteps][n_probe] for float64 tensors tau, amp (scalars)
+    and v [n][3]."""
+    return _probe_function().apply(tau, amp, v, window)
