@@ -284,6 +284,81 @@ def ensemble_bench(n_members, steps, warmup, kernel_steps, precision="fp32"):
     print(json.dumps(line), flush=True)
 
 
+def adjoint_bench(nsteps=2000, ckpt=100):
+    """The adjoint workload: 64x64x256 lattice, frozen touching FCC packing of 275 spheres of
+    radius 8 (walls in x and y, density faces in z), a 2000-step window with checkpoints
+    every 100 steps.  Loss: L2 misfit of the probe signals against a twin target made by
+    the FP64 window at (tau + 0.01, 1.1 A); gradients w.r.t. tau, A and the velocities of
+    the first 256 spheres, FP32 and FP64 windows, checked against central differences of
+    the FP64 forward (relative step 1e-4 for tau and A, 1e-6 lu/step for a velocity)."""
+    import torch
+    from paper_1808_08921_amd import inputs
+    from paper_1808_08921_amd.lbdem import AdjointWindow, LatticeSet
+
+    params, pk = inputs.adjoint_fcc_case()
+    params = dict(params, max_particles=len(pk["x"]))
+    n = len(pk["x"])
+    tau0, amp0 = params["tau"], params["amp"]
+    v0 = np.zeros((n, 3))
+    out = {}
+    wins = {}
+    for prec in ("fp64", "fp32"):
+        gs = LatticeSet([params], precision=prec, graph_steps=0, probe_ring=64)
+        gs.particles_set(0, pk["x"], pk["radius"], fixed=pk["fixed"])
+        win = AdjointWindow(gs, 0, nsteps=nsteps, ckpt_every=ckpt)
+        wins[prec] = (gs, win)
+    win64 = wins["fp64"][1]
+    target = win64.forward(tau0 + 0.01, 1.1 * amp0, v0)
+
+    def loss(win, tau=tau0, amp=amp0, v=v0):
+        P = win.forward(tau, amp, v)
+        return float(((P - target) ** 2).sum()), P
+
+    for prec in ("fp64", "fp32"):
+        win = wins[prec][1]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L, P = loss(win)
+        t1 = time.perf_counter()
+        gt, ga, gv = win.backward(2.0 * (P - target))
+        t2 = time.perf_counter()
+        out[prec] = {"loss": L, "forward_s": t1 - t0, "backward_s": t2 - t1, "dL_dtau": gt, "dL_damp": ga,
+                     "dL_dv_first256_norm": float(np.linalg.norm(gv[:256])), "gv": gv}
+        _log(f"adjoint {prec}: L={L:.6e} fwd {t1 - t0:.2f}s bwd {t2 - t1:.2f}s dtau {gt:.6e} damp {ga:.6e}")
+    # central differences on the FP64 forward
+    h = 1e-4
+    fd = {"dL_dtau": (loss(win64, tau=tau0 * (1 + h))[0] - loss(win64, tau=tau0 * (1 - h))[0]) / (2 * h * tau0),
+          "dL_damp": (loss(win64, amp=amp0 * (1 + h))[0] - loss(win64, amp=amp0 * (1 - h))[0]) / (2 * h * amp0)}
+    g64 = out["fp64"]["gv"]
+    comps = [tuple(int(c) for c in np.unravel_index(np.argmax(np.abs(g64[:256])), (256, 3)))]
+    hv = 1e-6  # velocities enter the collision's u^2 terms: a step far below the flow speed
+    for (q, a) in comps:
+        vp, vm = v0.copy(), v0.copy()
+        vp[q, a] += hv
+        vm[q, a] -= hv
+        fd[f"dL_dv[{q},{a}]"] = (loss(win64, v=vp)[0] - loss(win64, v=vm)[0]) / (2 * hv)
+    checks = {}
+    for prec in ("fp64", "fp32"):
+        r = out[prec]
+        checks[prec] = {"dL_dtau_rel_err_vs_fd": abs(r["dL_dtau"] - fd["dL_dtau"]) / abs(fd["dL_dtau"]),
+                        "dL_damp_rel_err_vs_fd": abs(r["dL_damp"] - fd["dL_damp"]) / abs(fd["dL_damp"])}
+        for (q, a) in comps:
+            key = f"dL_dv[{q},{a}]"
+            checks[prec][key + "_rel_err_vs_fd"] = abs(r["gv"][q, a] - fd[key]) / abs(fd[key])
+    checks["fp32_vs_fp64_dL_dv_rel"] = float(np.linalg.norm(out["fp32"]["gv"][:256] - g64[:256]) / np.linalg.norm(g64[:256]))
+    for prec in out:
+        out[prec].pop("gv")
+    for gs, win in wins.values():
+        win.close()
+        gs.close()
+    torch.cuda.empty_cache()
+    line = {"metric": "adjoint window: forward + backward seconds, gradient errors vs central differences",
+            "config": {"workload": f"64x64x256 frozen FCC, {n} spheres R=8, {nsteps} steps, checkpoint every {ckpt}",
+                       "loss": "L2 probe misfit vs twin target (tau+0.01, 1.1 A)"},
+            "results": out, "finite_differences_fp64": fd, "checks": checks}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,7 +375,11 @@ def main():
                     help="write the counter summary from two rocprofv3 --pmc CSV files")
     ap.add_argument("--ensemble", type=int, default=0, metavar="N",
                     help="run the batched-ensemble workload with N lattices instead of the main line")
+    ap.add_argument("--adjoint", action="store_true", help="run the adjoint-window workload instead of the main line")
     args = ap.parse_args()
+    if args.adjoint:
+        adjoint_bench()
+        return
     if args.ensemble:
         ensemble_bench(args.ensemble, args.steps, args.warmup, args.kernel_steps)
         return
