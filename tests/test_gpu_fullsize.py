@@ -1,0 +1,97 @@
+"""Parity at the benchmark's full size and launch configuration, and the settling-sphere
+workload over a long window.
+
+The FCC wave case is run at 96 x 96 x 384 (1024 spheres) exactly as bench.py launches it
+(HIP graphs of 8 steps, automatic tiles) for a few steps, which the oracle can afford:
+FP64 to the 1e-10 bar with bit-exact node maps; FP32 against the same FP64 oracle state.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_08921_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(params, pk):
+    p = params
+    s = oracle.Sim(p["nx"], p["ny"], p["nz"], tau=p["tau"], rho_f=p["rho_f"], bc=p["bc"], wave=p["wave"],
+                   amp=p["amp"], omega=p["omega"], t_n=p["t_n"], E=p["E"], nu=p["nu"], mu=p["mu"], rho_p=p["rho_p"],
+                   probe_z=p["probe_z"])
+    s.set_particles(pk["x"], pk["radius"], v=pk.get("v"), w=pk.get("w"), fg=pk.get("fg"), fixed=pk.get("fixed"))
+    return s
+
+
+@pytest.fixture(scope="module")
+def fcc_oracle():
+    params, pk = inputs.wave_fcc_case(seed=0)
+    params["max_particles"] = len(pk["x"])
+    s = _oracle(params, pk)
+    s.step(8)
+    yield params, pk, s
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol_f,tol_probe,tol_v", [("fp64", 1e-10, 1e-10, 1e-10),
+                                                             ("fp32", 5e-8, 1e-4, 1e-4)])
+def test_full_size_fcc_bench_configuration(fcc_oracle, precision, tol_f, tol_probe, tol_v):
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    params, pk, s = fcc_oracle
+    with LatticeSet([params], precision=precision, graph_steps=8, probe_ring=4096) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], fixed=pk["fixed"])
+        gs.step(8)
+        own_g, own_o = gs.owner(0), s.owner()
+        diff = own_g != own_o
+        if precision == "fp64":
+            assert not diff.any(), f"{int(diff.sum())} nodes differ"
+        else:
+            # FP32 particle forces differ from FP64 at ~1e-7 relative, so a node within
+            # that distance of a surface may change owner a step apart: count them
+            assert int(diff.sum()) <= 16, f"{int(diff.sum())} nodes differ"
+        near = diff.copy()
+        for ax in range(3):
+            near |= np.roll(diff, 1, axis=ax) | np.roll(diff, -1, axis=ax)
+        fl = (own_o < 0) & (own_g < 0) & ~near
+        df = np.abs(gs.populations(0)[:, fl] - s.populations()[:, fl]).max()
+        assert df <= tol_f, f"populations differ by {df:.3e}"
+        pg, po = gs.probes(0, 0, 8), s.probes(0, 8)
+        if precision == "fp64":
+            assert np.array_equal(pg[..., 0], po[..., 0])       # fluid-node counts per plane
+        # plane averages of rho - rho_f; the oracle forms rho - rho_f from the full
+        # populations, so its values carry an absolute rounding floor of ~1e-16
+        rg, ro = pg[..., 1] / pg[..., 0], po[..., 1] / po[..., 0]
+        assert np.abs(rg - ro).max() <= tol_probe * np.abs(ro).max() + 1e-15
+        g, o = gs.particles_get(0), s.particles()
+        assert np.abs(g["x"] - o["x"]).max() <= 1e-10 * 384
+        # the hydrodynamic force is a sum over ~4.8k links of terms ~0.1 that cancel to
+        # ~1e-3; its rounding floor per step (~1e-12 in FP64, ~4.8k x 4e-9 ~ 2e-5 with
+        # FP32 populations, any summation order) bounds how well two codes can agree on
+        # velocities this early (|v| ~ 1e-6)
+        m_min = params["rho_p"] * 4.0 / 3.0 * np.pi * float(np.min(pk["radius"])) ** 3
+        floor = (1e-12 if precision == "fp64" else 2e-5) * 8 / m_min
+        assert np.abs(g["v"] - o["v"]).max() <= tol_v * np.abs(o["v"]).max() + floor
+        assert gs.status() == 0
+
+
+def test_settling_sphere_long_window_fp64():
+    """Config 1 (32^3 walls, R = 6, density ratio 2, g = 1e-5, tau = 0.8): trajectory
+    parity over 400 steps, sampled every 50 steps."""
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    params, pk = inputs.settling_case()
+    params["max_particles"] = 1
+    s = _oracle(params, pk)
+    with LatticeSet([params], precision="fp64", graph_steps=8) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], fg=pk["fg"], fixed=pk["fixed"])
+        for _ in range(8):
+            gs.step(50)
+            s.step(50)
+            g, o = gs.particles_get(0), s.particles()
+            assert np.abs(g["x"] - o["x"]).max() <= 1e-10 * 32
+            assert np.abs(g["v"] - o["v"]).max() <= 1e-10 * np.abs(o["v"]).max()
+            assert np.array_equal(gs.owner(0), s.owner())
+        # falling: V_z < 0 and growing in magnitude toward the terminal velocity
+        assert g["v"][0, 2] < 0.0
+    s.close()
