@@ -252,12 +252,12 @@ def ensemble_bench(n_members, steps, warmup, kernel_steps, precision="fp32"):
         lats.append(dict(params, max_particles=len(pk["x"])))
         parts.append(pk)
     _log(f"ensemble: {n_members} lattices, {sum(d['nx'] * d['ny'] * d['nz'] for d in lats)} cells")
-    tuned, nzt, report = autotune(lats, parts, precision=precision)
-    _log(f"autotune: z_per_thread {nzt}, tiles " +
+    tuned, nzt, lists, report = autotune(lats, parts, precision=precision)
+    _log(f"autotune: node lists {lists}, z_per_thread {nzt}, tiles " +
          str(sorted({(d['nx'], d['tile_x']) for d in tuned})))
     out = {}
-    for label, lset, z in (("autotuned", tuned, nzt), ("default_tiles", lats, 0)):
-        gs = LatticeSet(lset, precision=precision, z_per_thread=z, graph_steps=8, probe_ring=64)
+    for label, lset, z, nl in (("autotuned", tuned, nzt, lists), ("default_tiles", lats, 0, 0)):
+        gs = LatticeSet(lset, precision=precision, z_per_thread=z, graph_steps=8, probe_ring=64, node_lists=nl)
         for k, pk in enumerate(parts):
             gs.particles_set(k, pk["x"], pk["radius"], fixed=pk["fixed"])
         nfl = sum(int((gs.owner(k) < 0).sum()) for k in range(len(lset)))
@@ -278,7 +278,7 @@ def ensemble_bench(n_members, steps, warmup, kernel_steps, precision="fp32"):
             "data": "synthetic",
             "config": {"workload": f"{n_members} uneven FCC samples (seeds 1000..{999 + n_members}), one launch "
                                    "per kernel per step", "cells": cells, "precision": precision,
-                       "z_per_thread": nzt, "tile_x_by_nx": {str(k): v for k, v in sorted(
+                       "node_lists": lists, "z_per_thread": nzt, "tile_x_by_nx": {str(k): v for k, v in sorted(
                            {d["nx"]: d["tile_x"] for d in tuned}.items())}},
             "results": out, "autotune_report": report}
     print(json.dumps(line), flush=True)

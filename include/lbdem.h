@@ -102,6 +102,11 @@ typedef struct lbdem_config {
     int32_t tile_x;       /* x extent of a fluid-kernel tile: 8, 16, 32, 64, or 0 = automatic */
     int32_t z_per_thread; /* z planes per fluid-kernel thread: 1..16, or 0 = automatic */
     int32_t graph_steps;  /* steps per replayed HIP graph: 1..64, or 0 = no graph (eager launches) */
+    int32_t node_lists;   /* fluid-kernel mapping: 1 = one thread per listed node (fluid nodes and
+                             solid nodes within 0.25 of a particle surface, per z plane, rebuilt
+                             when a particle has moved that far); 0 = dense tiles of
+                             tile_x * (256 / tile_x) nodes, z_per_thread planes deep; -1 =
+                             automatic (lists for 16-bit storage, dense tiles otherwise) */
 } lbdem_config;
 
 typedef struct lbdem_set lbdem_set;
@@ -109,7 +114,8 @@ typedef struct lbdem_set lbdem_set;
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbdem_last_error(void);
 
-/* Fill *cfg with the defaults (FP32, automatic tiles, 4096-step probe ring, graphs of 8 steps). */
+/* Fill *cfg with the defaults (FP32, automatic fluid mapping and tiles, 4096-step probe ring,
+ * graphs of 8 steps). */
 int lbdem_default_config(lbdem_config *cfg);
 
 /* Bytes of device workspace needed by lbdem_create for n_lat lattices.

@@ -17,11 +17,12 @@ TILE_X = (8, 16, 32, 64)
 Z_PER_THREAD = (1, 2, 4)
 
 
-def _time_fluid(lattices, particles, precision, tile_x=0, nzt=0, steps=20, warmup=5):
+def _time_fluid(lattices, particles, precision, tile_x=0, nzt=0, steps=20, warmup=5, node_lists=0):
     """Average fluid-kernel milliseconds of one set (HIP events, eager steps)."""
     import torch
 
-    gs = LatticeSet(lattices, precision=precision, tile_x=tile_x, z_per_thread=nzt, graph_steps=0, probe_ring=64)
+    gs = LatticeSet(lattices, precision=precision, tile_x=tile_x, z_per_thread=nzt, graph_steps=0, probe_ring=64,
+                    node_lists=node_lists)
     try:
         for k, pk in enumerate(particles):
             if pk is not None:
@@ -37,11 +38,12 @@ def _time_fluid(lattices, particles, precision, tile_x=0, nzt=0, steps=20, warmu
 
 
 def autotune(lattices, particles, precision="fp32", tile_x=TILE_X, z_per_thread=Z_PER_THREAD, steps=20):
-    """Choose a fluid-kernel tile per lattice shape and the planes per thread of the set.
+    """Choose the fluid-kernel mapping of a set: dense tiles (a tile width per lattice shape
+    and the planes per thread of the set) or per-plane node lists, whichever is faster.
 
     lattices: parameter dicts (as for LatticeSet); particles: matching list of particle
     dicts (x, radius, fixed) or None.  Returns (tuned lattices with a ``tile_x`` key,
-    z_per_thread, report) where report lists every timing taken.
+    z_per_thread, node_lists, report) where report lists every timing taken.
     """
     shapes = {}
     for k, d in enumerate(lattices):
@@ -64,4 +66,7 @@ def autotune(lattices, particles, precision="fp32", tile_x=TILE_X, z_per_thread=
     for nzt in z_per_thread:
         zt[nzt] = _time_fluid(sample, sample_p, precision, nzt=nzt, steps=steps)
         report.append({"shape": "sample", "tile_x": "tuned", "z_per_thread": nzt, "fluid_ms": zt[nzt]})
-    return tuned, min(zt, key=zt.get), report
+    best_nzt = min(zt, key=zt.get)
+    t_lists = _time_fluid(sample, sample_p, precision, steps=steps, node_lists=1)
+    report.append({"shape": "sample", "node_lists": 1, "fluid_ms": t_lists})
+    return tuned, best_nzt, int(t_lists < zt[best_nzt]), report

@@ -71,6 +71,7 @@ struct Geometry {
     long long wave_doubles = 0;
     long long pz = 0;
     int nzt = 4;
+    int listmode = 1;
     int ring_len = 1;
     int chg_cap = 0;
     int lcap = 1;
@@ -142,10 +143,14 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
 {
     G.mem.assign(n, MemberDev{});
     G.prec = cfg->precision;
+    // automatic: node lists for 16-bit storage, where partial-line writes cost less than
+    // the idle lanes of dense tiles; dense tiles with whole-line writes otherwise
+    G.listmode = cfg->node_lists < 0 ? (cfg->precision == LBDEM_FP16DEV || cfg->precision == LBDEM_BF16DEV)
+                                     : (cfg->node_lists ? 1 : 0);
     int nzt = cfg->z_per_thread ? cfg->z_per_thread : 2;
     int nzmin = lat[0].nz;
     for (int m = 1; m < n; ++m) nzmin = std::min(nzmin, lat[m].nz);
-    G.nzt = std::max(1, std::min(nzt, nzmin));
+    G.nzt = G.listmode ? 1 : std::max(1, std::min(nzt, nzmin));
     G.ring_len = cfg->probe_ring;
     long long cells = 0, ring = 0, wave = 0, pz = 0;
     int tiles = 0, pt = 0, npr = 0;
@@ -156,9 +161,16 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
         M.bx = choose_tile_x(p.nx, p.tile_x ? p.tile_x : cfg->tile_x);
         M.bx_log2 = (int)std::lround(std::log2((double)M.bx));
         M.by = 256 / M.bx;
-        M.ntx = (p.nx + M.bx - 1) / M.bx;
-        M.nty = (p.ny + M.by - 1) / M.by;
-        M.ntz = (p.nz + G.nzt - 1) / G.nzt;
+        if (G.listmode) {
+            // one workgroup per 256 listed nodes of a z plane (at most nx*ny of them)
+            M.ntx = (int)(((long long)p.nx * p.ny + 255) / 256);
+            M.nty = 1;
+            M.ntz = p.nz;
+        } else {
+            M.ntx = (p.nx + M.bx - 1) / M.bx;
+            M.nty = (p.ny + M.by - 1) / M.by;
+            M.ntz = (p.nz + G.nzt - 1) / G.nzt;
+        }
         M.tile_off = tiles;
         tiles += M.ntx * M.nty * M.ntz;
         for (int f = 0; f < 6; ++f) M.bc[f] = p.face_bc[f];
@@ -221,6 +233,11 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.mem = c.take<MemberDev>(G.mem.size());
     s.tiles_total = G.tiles;
     s.nzt = G.nzt;
+    s.listmode = G.listmode;
+    s.nplanes = (int)G.pz;
+    s.clist = c.take<int>((size_t)G.cells);
+    s.ccnt = c.take<int>((size_t)std::max<long long>(G.pz, 1));
+    s.relist_at = c.take<long long>(1);
     s.popA = c.take<char>(es * kQ * (size_t)G.cells);
     s.popB = c.take<char>(es * kQ * (size_t)G.cells);
     s.own[0] = c.take<int>(G.cells);
@@ -254,6 +271,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.Ph = c.take<double>(3 * (size_t)P);
     s.Lh = c.take<double>(3 * (size_t)P);
     s.Xref = c.take<double>(3 * (size_t)P);
+    s.Xl = c.take<double>(3 * (size_t)P);
     s.pf[0] = c.take<float>(12 * (size_t)P);
     s.pf[1] = c.take<float>(12 * (size_t)P);
     s.margin = c.take<double>(P);
@@ -462,6 +480,7 @@ int lbdem_default_config(lbdem_config *cfg)
     cfg->precision = LBDEM_FP32;
     cfg->probe_ring = 4096;
     cfg->tile_x = 0;
+    cfg->node_lists = -1;
     cfg->z_per_thread = 0;
     cfg->graph_steps = 8;
     return LBDEM_OK;
@@ -565,6 +584,8 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     CHK(hipMemsetAsync(s.own[0], 0xff, sizeof(int) * S->G.cells, st));
     CHK(hipMemsetAsync(s.own[1], 0xff, sizeof(int) * S->G.cells, st));
     CHK(hipMemsetAsync(s.lw, 0, sizeof(unsigned long long) * 2 * S->G.cells, st));
+    CHK(hipMemsetAsync(s.relist_at, 0, sizeof(long long), st)); // lists are built by the first step
+    CHK(hipMemsetAsync(s.ccnt, 0, sizeof(int) * std::max<long long>(S->G.pz, 1), st));
     CHK(hipMemsetAsync(s.chgcnt, 0, sizeof(int) * 2, st));
     CHK(hipMemsetAsync(s.pprt, 0, sizeof(double) * S->G.tiles * S->G.nzt * 4, st));
     CHK(hipMemsetAsync(s.ring, 0, sizeof(double) * S->G.ring_doubles, st));

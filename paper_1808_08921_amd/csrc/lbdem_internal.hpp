@@ -18,6 +18,7 @@ constexpr int kHistCap = 16;       // tangential contact history per particle
 constexpr double kNearMargin = 3.0; // near list: |X_p - X_q| <= R_p + R_q + margin
 constexpr double kShell = 0.5;      // skin of the per-particle shell lists (lattice units)
 constexpr double kBand = 0.15;      // half-width of the surface band list (lattice units)
+constexpr double kListSkin = 0.25;  // solid nodes this close to a surface stay in the node lists
 constexpr int kChunks = 8;          // workgroups per particle in the particle kernel
 constexpr int kEmpty = 0x7fffffff;
 // Link words of a fluid node x (two 64-bit words per node: lw[c] and lw[ncell_total + c]).
@@ -59,6 +60,14 @@ struct DevSet {
     const MemberDev *mem;
     int tiles_total;
     int nzt;                  // z planes per fluid-kernel thread
+    // node lists: per lattice and z plane, the listed nodes in x-fastest order at
+    // [cell_off + z*nx*ny, +count); the fluid kernel then runs one thread per listed node
+    int listmode;
+    int nplanes;              // sum of nz over the lattices
+    int *clist;               // [ncell_total]
+    int *ccnt;                // [sum of nz], indexed like the z -> probe map
+    double *Xl;               // particle positions when the lists were built [ptot*3]
+    long long *relist_at;     // step whose refresh rebuilds the lists
     // populations
     void *popA, *popB;
     // node maps (index = parity), change lists (pairs cell, owner) and counts

@@ -334,6 +334,21 @@ __device__ __forceinline__ void store_dev(typename Prec<P>::S *a, unsigned idx, 
     else sto(a, idx, f32_to_bf16(df * kInvW[d]));
 }
 
+// Rank of a true predicate among the workgroup's threads (thread order) and the total.
+__device__ __forceinline__ int block_rank(bool pred, int &total, int *cnt4)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long bal = __ballot(pred);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) cnt4[wv] = __popcll(bal);
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wv; ++w) off += cnt4[w];
+    total = cnt4[0] + cnt4[1] + cnt4[2] + cnt4[3];
+    __syncthreads();
+    return off + before;
+}
+
 // ---------------------------------------------------------------------------
 // link words
 // ---------------------------------------------------------------------------
@@ -551,6 +566,51 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
         }
     }
     if (over) atomicOr(s.flags, 0x80u);
+
+    // node lists, when a particle has moved kListSkin since they were built (or after a
+    // set-up): per z plane, in x-fastest order, every fluid node and every solid node
+    // less than kListSkin inside its particle's surface.  Only such a node can become
+    // fluid before a particle has moved kListSkin.
+    if (s.listmode && *s.relist_at == t) {
+        __shared__ int cnt4[4];
+        for (long long q = t0; q < s.ptot; q += stride)
+            for (int ax = 0; ax < 3; ++ax) s.Xl[3 * q + ax] = s.X[par][3 * q + ax];
+        for (int pl = blockIdx.x; pl < s.nplanes; pl += gridDim.x) {
+            int lo = 0, hi = s.nmem - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s.mem[mid].pz_off <= pl) lo = mid;
+                else hi = mid - 1;
+            }
+            const MemberDev *M = s.mem + lo;
+            const int z = pl - M->pz_off, nx = M->nx, nxy = M->nx * M->ny;
+            const int *own = s.own[par] + M->cell_off;
+            int *lst = s.clist + M->cell_off + (long long)z * nxy;
+            int count = 0;
+            for (int c0 = 0; c0 < nxy; c0 += blockDim.x) {
+                const int c = c0 + threadIdx.x;
+                bool listed = false;
+                int cell = 0;
+                if (c < nxy) {
+                    cell = z * nxy + c;
+                    const int o = own[cell];
+                    if (o < 0) {
+                        listed = true;
+                    } else {
+                        const double rr = s.R[o] - kListSkin;
+                        const int j = c / nx, i = c - j * nx;
+                        const double *Xq = s.X[par] + 3 * o;
+                        listed = rr <= 0.0 || dist2(M, i, j, z, Xq[0], Xq[1], Xq[2]) > rr * rr;
+                    }
+                }
+                int tot = 0;
+                const int rk = block_rank(listed, tot, cnt4);
+                if (listed) lst[count + rk] = cell;
+                count += tot;
+            }
+            if (threadIdx.x == 0) s.ccnt[pl] = count;
+        }
+    }
     if (t0 == 0) {
         s.chgcnt[par] = 0;
         *s.tcopy = t; // the re-projection kernel of this step reads the step from here
@@ -572,18 +632,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
 
     const int g = xcd_swizzle(blockIdx.x, gridDim.x);
     const MemberDev *M = member_of_tile(s, g);
-    const int bxl = uni(M->bx_log2);
-    const int lx = threadIdx.x & ((1 << bxl) - 1), ly = threadIdx.x >> bxl;
     const int tl = g - uni(M->tile_off);
     const int ntx = uni(M->ntx), nty = uni(M->nty);
-    const int tx = tl % ntx, trem = tl / ntx, ty = trem % nty, tz = trem / nty;
     const int nx = uni(M->nx), ny = uni(M->ny), nz = uni(M->nz);
-    const int i = (tx << bxl) + lx, j = ty * uni(M->by) + ly;
-    const bool vij = (i < nx) && (j < ny);
-    const int z0 = tz * s.nzt, z1 = min(z0 + s.nzt, nz);
     const int nc = (int)uni(M->ncell);
     const int nxy = nx * ny;
     const long long pop_off = uni(M->pop_off), cell_off = uni(M->cell_off);
+    const int pz_off = uni(M->pz_off);
+    int i, j, z0, z1;
+    bool vij;
+    const bool lists = s.listmode != 0;
+    if (lists) {
+        // workgroup = 256 consecutive listed nodes of one z plane
+        const int lb = tl % ntx, z = tl / ntx;
+        const int cnt = s.ccnt[pz_off + z];
+        if (lb * 256 >= cnt) {
+            if (s.pzmap[pz_off + z] >= 0 && threadIdx.x == 0) {
+                double *o = s.pprt + (long long)g * s.nzt * 4;
+                o[0] = 0.0; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0;
+            }
+            return;
+        }
+        const int k = lb * 256 + (int)threadIdx.x;
+        vij = k < cnt;
+        const int c = vij ? s.clist[cell_off + (long long)z * nxy + k] - z * nxy : 0;
+        j = c / nx;
+        i = c - j * nx;
+        z0 = z;
+        z1 = z + 1;
+    } else {
+        const int bxl = uni(M->bx_log2);
+        const int lx = threadIdx.x & ((1 << bxl) - 1), ly = threadIdx.x >> bxl;
+        const int tx = tl % ntx, trem = tl / ntx, ty = trem % nty, tz = trem / nty;
+        i = (tx << bxl) + lx;
+        j = ty * uni(M->by) + ly;
+        vij = (i < nx) && (j < ny);
+        z0 = tz * s.nzt;
+        z1 = min(z0 + s.nzt, nz);
+    }
     const S *A = (const S *)(par ? s.popB : s.popA) + pop_off;
     S *B = (S *)(par ? s.popA : s.popB) + pop_off;
     const int *own = s.own[par] + cell_off;
@@ -594,7 +680,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     long long ti = t + 1;
     if (ti > t_n + 1) ti = t_n + 1;
     const C drho_in = (C)(s.wave[uni(M->wave_off) + ti] - rho_fd);
-    const int pz_off = uni(M->pz_off);
 
     // offsets to the x-1 / x+1 / y-1 / y+1 neighbours (wrapped on periodic axes) and the
     // kind of face crossed to reach them (0 inside or periodic, 1 wall, 2 density face)
@@ -611,12 +696,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
         bool fl = false;
         if (vij) fl = ldo(own, (unsigned)cell) < 0;
         double pr0 = 0.0, pr1 = 0.0, pr2 = 0.0, pr3 = 0.0;
-        // With 4- and 8-byte storage every node of the row is written, so each store
+        // Dense tiles with 4- and 8-byte storage write every node of a row, so each store
         // covers whole cache lines: a solid node loads nothing and stores the rest state
-        // w_d, a value that is never read (its slots are refilled by the link kernel or on
-        // uncovering).  16-bit storage measured faster with solid nodes left out.
+        // w_d, a value that is never read (a node is refilled on uncovering).  16-bit
+        // storage measured faster with solid nodes left out; with node lists only the
+        // fluid nodes work.
         constexpr bool kWholeRows = sizeof(S) >= 4;
-        if (kWholeRows ? vij : fl) {
+        if ((kWholeRows && !lists) ? vij : fl) {
             const int ozm = (z > 0) ? -nxy : (nz - 1) * nxy, ozp = (z < nz - 1) ? nxy : -(nz - 1) * nxy;
             const int kzm = (z > 0) ? 0 : bc4, kzp = (z < nz - 1) ? 0 : bc5;
             // Loads are issued for every lane, a solid lane reading the first element of the
@@ -692,19 +778,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
 // ---------------------------------------------------------------------------
 // particle kernel: links, contacts, motion
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int block_rank(bool pred, int &total, int *cnt4)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long bal = __ballot(pred);
-    const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) cnt4[wv] = __popcll(bal);
-    __syncthreads();
-    int off = 0;
-    for (int w = 0; w < wv; ++w) off += cnt4[w];
-    total = cnt4[0] + cnt4[1] + cnt4[2] + cnt4[3];
-    __syncthreads();
-    return off + before;
-}
 
 // Node range [lo, lo + ext) along one axis covering [c - h, c + h]: clipped on a bounded
 // axis, at most one full period on a periodic one.
@@ -1115,6 +1188,19 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             const double d = mimg(X[a] - Xr[a], M->per[a], M->box[a]);
             disp2 += d * d;
             xr[a] = X[a] - d; // reference centre unwrapped next to X
+        }
+        // node lists: rebuilt at the start of the next step once p has moved kListSkin
+        if (s.listmode) {
+            if (mode == 1) {
+                if (tid == 0) *s.relist_at = t;
+            } else {
+                double dl = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double d = mimg(X[a] - s.Xl[3 * p + a], M->per[a], M->box[a]);
+                    dl += d * d;
+                }
+                if (tid == 0 && dl >= (kListSkin - 1e-9) * (kListSkin - 1e-9)) *s.relist_at = t + 1;
+            }
         }
         // a node can change owner only if |d_ref - R| <= displacement (membership) or
         // it lies in an overlap lens of depth <= dmax (ordering between two spheres)

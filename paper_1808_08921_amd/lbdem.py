@@ -54,7 +54,7 @@ class Params(ctypes.Structure):
 
 class Config(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("probe_ring", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("z_per_thread", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
+                ("z_per_thread", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("node_lists", ctypes.c_int32)]
 
 
 _lib = None
@@ -146,7 +146,7 @@ class LatticeSet:
     """
 
     def __init__(self, lattices, precision="fp32", probe_ring=4096, tile_x=0, z_per_thread=0, graph_steps=8,
-                 device="cuda"):
+                 device="cuda", node_lists=None):
         import torch
 
         self._torch = torch
@@ -162,6 +162,8 @@ class LatticeSet:
         _check(L.lbdem_default_config(ctypes.byref(cfg)))
         cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         cfg.probe_ring, cfg.tile_x, cfg.z_per_thread, cfg.graph_steps = probe_ring, tile_x, z_per_thread, graph_steps
+        if node_lists is not None:
+            cfg.node_lists = 1 if node_lists else 0
         nbytes = ctypes.c_size_t()
         _check(L.lbdem_workspace_size(n, arr, ctypes.byref(cfg), ctypes.byref(nbytes)))
         self.workspace_bytes = nbytes.value

@@ -137,13 +137,15 @@ def test_projection_bitexact_fcc(seed):
 # ---------------------------------------------------------------------------
 # coupled steps
 # ---------------------------------------------------------------------------
-def test_coupled_moving_sphere_with_conversions_fp64():
-    """A fast sphere in a periodic box: links, cover/uncover conversions every step."""
+@pytest.mark.parametrize("node_lists", [0, 1])
+def test_coupled_moving_sphere_with_conversions_fp64(node_lists):
+    """A fast sphere in a periodic box: links, cover/uncover conversions every step; with
+    node lists, the lists are rebuilt every few steps as the sphere moves."""
     params = dict(nx=16, ny=15, nz=17, tau=0.8, bc=(0,) * 6, rho_p=1.2, max_particles=2)
     pk = {"x": np.array([[7.3, 6.9, 8.6]]), "radius": np.array([3.2]), "v": np.array([[0.03, -0.02, 0.025]]),
           "w": np.array([[0.0, 0.01, -0.02]])}
     s = _oracle(params, pk)
-    with _gpu_set([params], graph_steps=0) as gs:
+    with _gpu_set([params], graph_steps=0, node_lists=node_lists) as gs:
         _set_particles(gs, 0, pk)
         for _ in range(4):
             gs.step(15)
@@ -153,11 +155,12 @@ def test_coupled_moving_sphere_with_conversions_fp64():
         assert gs.status() & 0x12 == 0
 
 
-def test_coupled_fcc_wave_fp64():
+@pytest.mark.parametrize("node_lists", [0, 1])
+def test_coupled_fcc_wave_fp64(node_lists):
     params, pk = inputs.wave_fcc_case(seed=2, ncx=2, ncy=2, ncz=3, a=24.0, overlap_rel=1e-2, period=40.0, amp=5e-3)
     params["max_particles"] = len(pk["x"])
     s = _oracle(params, pk)
-    with _gpu_set([params], graph_steps=4) as gs:
+    with _gpu_set([params], graph_steps=4, node_lists=node_lists) as gs:
         _set_particles(gs, 0, pk)
         gs.step(60)
         s.step(60)
