@@ -280,6 +280,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.ppart = c.take<double>((size_t)P * kChunks * 6);
     s.nearl = c.take<int>((size_t)P * kNearCap);
     s.nnear = c.take<int>(P);
+    s.near_at = c.take<long long>(P);
     s.lcap = G.lcap;
     s.lcell = c.take<int>((size_t)P * G.lcap);
     s.ldr = c.take<float>((size_t)P * G.lcap);
@@ -601,6 +602,7 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     CHK(hipMemsetAsync(s.pf[0], 0, sizeof(float) * 12 * P, st));
     CHK(hipMemsetAsync(s.pf[1], 0, sizeof(float) * 12 * P, st));
     CHK(hipMemsetAsync(s.nnear, 0, sizeof(int) * P, st));
+    CHK(hipMemsetAsync(s.near_at, 0xff, sizeof(long long) * P, st)); // -1: build at the first step
     CHK(hipMemsetAsync(s.lcnt, 0, sizeof(int) * P, st));
     CHK(hipMemsetAsync(s.xcnt, 0, sizeof(int) * P * kChunks, st));
     CHK(hipMemsetAsync(s.bcnt, 0, sizeof(int) * P, st));

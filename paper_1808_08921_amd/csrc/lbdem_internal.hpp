@@ -16,6 +16,7 @@ constexpr int kQ = 19;
 constexpr int kNearCap = 32;       // near-neighbour table per particle
 constexpr int kHistCap = 16;       // tangential contact history per particle
 constexpr double kNearMargin = 3.0; // near list: |X_p - X_q| <= R_p + R_q + margin
+constexpr int kNearEvery = 5;       // steps between near-list builds (approach < 0.5 lu per step)
 constexpr double kShell = 0.5;      // skin of the per-particle shell lists (lattice units)
 constexpr double kBand = 0.15;      // half-width of the surface band list (lattice units)
 constexpr double kListSkin = 0.25;  // solid nodes this close to a surface stay in the node lists
@@ -96,6 +97,7 @@ struct DevSet {
     int *fixed, *pmem;
     double *ppart;            // link-force partials per (particle, chunk) [ptot*kChunks*6]
     int *nearl, *nnear;       // [ptot*kNearCap], [ptot]
+    long long *near_at;       // step at which each near list was built [ptot]
     // shell list per particle around X_ref: node, d_ref - R, link-candidate directions
     int lcap;
     int *lcell, *lcnt;

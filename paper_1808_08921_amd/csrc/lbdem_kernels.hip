@@ -546,7 +546,13 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
     } else {
         const int *lst = s.chg[par ^ 1];
         for (long long e = t0; e < cnt; e += stride) s.own[par ^ 1][lst[2 * e]] = lst[2 * e + 1];
-        for (long long w = t0; w < (long long)cnt * kQ; w += stride) {
+        // the words of the changed nodes and their neighbours: one group of 32 lanes per
+        // word, lane e < 18 reading the owner of source e and lane 18 the node's own (one
+        // round of loads), every lane assembling the word from the group's values as
+        // link_words does, lane 0 storing it
+        const int lane = threadIdx.x & 31;
+        const long long grp = t0 >> 5, ngrp = stride >> 5;
+        for (long long w = grp; w < (long long)cnt * kQ; w += ngrp) {
             const long long ch = w / kQ;
             const int q = (int)(w - ch * kQ); // 18: the changed node itself
             const long long gcell = lst[2 * ch];
@@ -557,12 +563,50 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
             // a neighbour across a bounded face wraps to a node whose words are unchanged;
             // recomputing them is harmless
             const int ci = wrapc(i0 + kCXd[q], nx), cj = wrapc(j0 + kCYd[q], ny), ck = wrapc(k0 + kCZd[q], nz);
-            const long long gc = M->cell_off + (ck * ny + cj) * nx + ci;
-            unsigned long long w0, w1;
-            link_words(M, s.own[par] + M->cell_off, ci, cj, ck, w0, w1);
-            s.lw[gc] = w0;
-            s.lw[s.ncell_total + gc] = w1;
-            over |= (w0 >> 63) != 0ull;
+            const int *own = s.own[par] + M->cell_off;
+            int o = -1;
+            if (lane < kQ - 1) {
+                const int si = ci - kCXd[lane], sj = cj - kCYd[lane], sk = ck - kCZd[lane];
+                const bool ok = (M->per[0] || (si >= 0 && si < nx)) && (M->per[1] || (sj >= 0 && sj < ny)) &&
+                                (M->per[2] || (sk >= 0 && sk < nz));
+                if (ok) o = own[(wrapc(sk, nz) * ny + wrapc(sj, ny)) * nx + wrapc(si, nx)];
+            } else if (lane == kQ - 1) {
+                o = own[(ck * ny + cj) * nx + ci];
+            }
+            const int self = __shfl(o, kQ - 1, 32);
+            unsigned mask = 0u, slo = 0u, shi = 0u;
+            int id0 = -1, id1 = -1, id2 = -1, id3 = -1;
+            bool ov = false;
+            if (self < 0) {
+                for (int e = 0; e < kQ - 1; ++e) {
+                    const int oe = __shfl(o, e, 32);
+                    if (oe < 0) continue;
+                    const int pq = oe - M->p_off;
+                    int sl;
+                    if (id0 < 0 || id0 == pq) { id0 = pq; sl = 0; }
+                    else if (id1 < 0 || id1 == pq) { id1 = pq; sl = 1; }
+                    else if (id2 < 0 || id2 == pq) { id2 = pq; sl = 2; }
+                    else if (id3 < 0 || id3 == pq) { id3 = pq; sl = 3; }
+                    else { ov = true; continue; }
+                    mask |= 1u << e;
+                    if (sl & 1) slo |= 1u << e;
+                    if (sl & 2) shi |= 1u << e;
+                }
+            }
+            unsigned long long w0 = 0ull, w1 = 0ull;
+            if (mask != 0u || ov) {
+                w0 = (unsigned long long)mask | ((unsigned long long)slo << 18) |
+                     ((unsigned long long)max(id0, 0) << 36) | ((unsigned long long)max(id1, 0) << 49) |
+                     ((unsigned long long)(id2 >= 0) << 62) | ((unsigned long long)ov << 63);
+                w1 = (unsigned long long)shi | ((unsigned long long)max(id2, 0) << 18) |
+                     ((unsigned long long)max(id3, 0) << 31);
+            }
+            if (lane == 0) {
+                const long long gc = M->cell_off + (ck * ny + cj) * nx + ci;
+                s.lw[gc] = w0;
+                s.lw[s.ncell_total + gc] = w1;
+                over |= ov;
+            }
         }
     }
     if (over) atomicOr(s.flags, 0x80u);
@@ -975,12 +1019,20 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
     double *hfn = s.hf[par ^ 1] + (long long)p * kHistCap * 3;
     double con[6] = {0, 0, 0, 0, 0, 0};
     int near_total = 0, hist_total = 0;
-    for (int base = 0; base < nq; base += 256) {
+    // Candidates: every particle of the lattice when the near list is (re)built (set-up,
+    // or kNearEvery steps after the last build), else the near list, which holds every
+    // particle within R_p + R_q + kNearMargin at its build; with each particle moving
+    // less than 0.25 per step, contacts stay among them until the next build.
+    const long long nat = s.near_at[p];
+    const bool build = (mode != 0) || nat < 0 || t - nat >= kNearEvery;
+    const int ncand = build ? nq : min(s.nnear[p], kNearCap);
+    const int *nl = s.nearl + (long long)p * kNearCap;
+    for (int base = 0; base < ncand; base += 256) {
         const int jj = base + tid;
-        const int q = q0 + jj;
+        const int q = (jj < ncand) ? (build ? q0 + jj : nl[jj]) : -1;
         bool isnear = false, keep = false;
         double ftn[3] = {0, 0, 0};
-        if (jj < nq && q != p) {
+        if (jj < ncand && q != p) {
             const double Y0 = Xo[3 * q], Y1 = Xo[3 * q + 1], Y2 = Xo[3 * q + 2], Rq = s.R[q];
             const double d0 = mimg(Y0 - X0, per0, box0);
             const double d1 = mimg(Y1 - X1, per1, box1);
@@ -1023,14 +1075,16 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
                 }
             }
         }
-        int tot = 0;
-        const int rk = block_rank(isnear, tot, cnt4);
-        if (isnear) {
-            const int slot = near_total + rk;
-            if (slot < kNearCap) s.nearl[(long long)p * kNearCap + slot] = q;
-            else atomicOr(s.flags, 0x2u);
+        if (build) {
+            int tot = 0;
+            const int rk = block_rank(isnear, tot, cnt4);
+            if (isnear) {
+                const int slot = near_total + rk;
+                if (slot < kNearCap) s.nearl[(long long)p * kNearCap + slot] = q;
+                else atomicOr(s.flags, 0x2u);
+            }
+            near_total += tot;
         }
-        near_total += tot;
         if (mode == 0 && mu > 0.0) {
             int ht = 0;
             const int hr = block_rank(keep, ht, cnt4);
@@ -1047,7 +1101,10 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
         }
     }
     if (tid == 0) {
-        s.nnear[p] = min(near_total, kNearCap);
+        if (build) {
+            s.nnear[p] = min(near_total, kNearCap);
+            s.near_at[p] = t;
+        }
         if (mode == 0) s.hn[par ^ 1][p] = min(hist_total, kHistCap);
     }
     if (mode != 0) {
