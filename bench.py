@@ -223,7 +223,7 @@ def summarize_counters(fetch_csv, write_csv, out_path, command):
     print("\n".join(lines))
 
 
-def measured_traffic(kernel_prefix="_ZN5lbdem7k_fluidILi1E"):
+def measured_traffic(kernel_name="lbdem::k_fluid<1>("):
     """HBM bytes per dispatch of the FP32 fluid kernel from the committed counter summary,
     or None when it is missing or was taken on another version of the kernel source."""
     if not os.path.exists(COUNTERS_FILE):
@@ -232,7 +232,7 @@ def measured_traffic(kernel_prefix="_ZN5lbdem7k_fluidILi1E"):
     if f"sha256[:16]: {kernel_source_hash()}" not in txt:
         return None
     for line in txt.splitlines():
-        if line.startswith(kernel_prefix):
+        if kernel_name in line.split("|")[0]:
             return float(line.split("|")[-1])
     return None
 
