@@ -72,6 +72,7 @@ extern "C" {
 #define LBDEM_STATUS_TOO_FAST 0x10u          /* a particle moved more than 0.25 lu in one step (error) */
 #define LBDEM_STATUS_SHELL_OVERFLOW 0x40u    /* a particle's surface-shell table overflowed (error) */
 #define LBDEM_STATUS_LINK_OVERFLOW 0x80u     /* a fluid node had links to more than four particles (error) */
+#define LBDEM_STATUS_LIST_MISS 0x100u        /* compact storage: a node turned fluid outside the node lists (error) */
 
 /* One lattice and its physics (Sec. 2; Table 1 "tab:params" for the FCC runs). */
 typedef struct lbdem_params {
@@ -105,8 +106,13 @@ typedef struct lbdem_config {
     int32_t node_lists;   /* fluid-kernel mapping: 1 = one thread per listed node (fluid nodes and
                              solid nodes within 0.25 of a particle surface, per z plane, rebuilt
                              when a particle has moved that far); 0 = dense tiles of
-                             tile_x * (256 / tile_x) nodes, z_per_thread planes deep; -1 =
-                             automatic (lists for 16-bit storage, dense tiles otherwise) */
+                             tile_x * (256 / tile_x) nodes, z_per_thread planes deep; 2 = node
+                             lists with compact storage (only listed nodes hold populations,
+                             per plane in list order; moved when the lists are rebuilt; needs
+                             ny * ceil(nx / 32) <= 8192; a third population buffer); -1 =
+                             automatic (2 where every plane fits, else 1 for 16-bit storage
+                             and 0 otherwise).  Host access to populations, particle set-up
+                             and adjoint windows see the node layout either way. */
 } lbdem_config;
 
 typedef struct lbdem_set lbdem_set;

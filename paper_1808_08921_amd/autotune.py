@@ -39,7 +39,8 @@ def _time_fluid(lattices, particles, precision, tile_x=0, nzt=0, steps=20, warmu
 
 def autotune(lattices, particles, precision="fp32", tile_x=TILE_X, z_per_thread=Z_PER_THREAD, steps=20):
     """Choose the fluid-kernel mapping of a set: dense tiles (a tile width per lattice shape
-    and the planes per thread of the set) or per-plane node lists, whichever is faster.
+    and the planes per thread of the set), per-plane node lists, or node lists with compact
+    storage, whichever is fastest.
 
     lattices: parameter dicts (as for LatticeSet); particles: matching list of particle
     dicts (x, radius, fixed) or None.  Returns (tuned lattices with a ``tile_x`` key,
@@ -67,6 +68,8 @@ def autotune(lattices, particles, precision="fp32", tile_x=TILE_X, z_per_thread=
         zt[nzt] = _time_fluid(sample, sample_p, precision, nzt=nzt, steps=steps)
         report.append({"shape": "sample", "tile_x": "tuned", "z_per_thread": nzt, "fluid_ms": zt[nzt]})
     best_nzt = min(zt, key=zt.get)
-    t_lists = _time_fluid(sample, sample_p, precision, steps=steps, node_lists=1)
-    report.append({"shape": "sample", "node_lists": 1, "fluid_ms": t_lists})
-    return tuned, best_nzt, int(t_lists < zt[best_nzt]), report
+    modes = {0: zt[best_nzt]}
+    for nl in (1, 2):
+        modes[nl] = _time_fluid(sample, sample_p, precision, steps=steps, node_lists=nl)
+        report.append({"shape": "sample", "node_lists": nl, "fluid_ms": modes[nl]})
+    return tuned, best_nzt, min(modes, key=modes.get), report

@@ -72,6 +72,8 @@ struct Geometry {
     long long pz = 0;
     int nzt = 4;
     int listmode = 1;
+    int compact = 0;
+    long long rt_words = 0;
     int ring_len = 1;
     int chg_cap = 0;
     int lcap = 1;
@@ -89,8 +91,11 @@ int validate(int32_t n, const lbdem_params *lat, const lbdem_config *cfg)
     if (cfg->tile_x != 0 && !is_pow2_tile(cfg->tile_x)) return fail(LBDEM_EINVAL, "tile_x must be 0, 8, 16, 32 or 64");
     if (cfg->z_per_thread < 0 || cfg->z_per_thread > 16) return fail(LBDEM_EINVAL, "z_per_thread must be 0..16");
     if (cfg->graph_steps < 0 || cfg->graph_steps > 64) return fail(LBDEM_EINVAL, "graph_steps must be 0..64");
+    if (cfg->node_lists < -1 || cfg->node_lists > 2) return fail(LBDEM_EINVAL, "node_lists must be -1, 0, 1 or 2");
     for (int m = 0; m < n; ++m) {
         const lbdem_params &p = lat[m];
+        if (cfg->node_lists == 2 && (long long)p.ny * ((p.nx + 31) / 32) > kMaxPlaneWords)
+            return fail(LBDEM_EINVAL, "lattice %d: an x-y plane is too large for compact storage", m);
         if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(LBDEM_EINVAL, "lattice %d: sizes must be >= 1", m);
         const long long nc = (long long)p.nx * p.ny * p.nz;
         if (nc * kQ >= (1LL << 31)) return fail(LBDEM_EINVAL, "lattice %d: more than 113M cells", m);
@@ -143,10 +148,18 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
 {
     G.mem.assign(n, MemberDev{});
     G.prec = cfg->precision;
-    // automatic: node lists for 16-bit storage, where partial-line writes cost less than
-    // the idle lanes of dense tiles; dense tiles with whole-line writes otherwise
-    G.listmode = cfg->node_lists < 0 ? (cfg->precision == LBDEM_FP16DEV || cfg->precision == LBDEM_BF16DEV)
-                                     : (cfg->node_lists ? 1 : 0);
+    // automatic: node lists with compact storage (the fastest mapping measured at every
+    // precision), unless an x-y plane has too many row-table words for it; then node lists
+    // for 16-bit storage, where partial-line writes cost less than the idle lanes of dense
+    // tiles, and dense tiles with whole-line writes otherwise
+    int mode = cfg->node_lists;
+    if (mode < 0) {
+        bool fits = true;
+        for (int m = 0; m < n; ++m) fits = fits && (long long)lat[m].ny * ((lat[m].nx + 31) / 32) <= kMaxPlaneWords;
+        mode = fits ? 2 : ((cfg->precision == LBDEM_FP16DEV || cfg->precision == LBDEM_BF16DEV) ? 1 : 0);
+    }
+    G.listmode = mode != 0 ? 1 : 0;
+    G.compact = mode == 2 ? 1 : 0;
     int nzt = cfg->z_per_thread ? cfg->z_per_thread : 2;
     int nzmin = lat[0].nz;
     for (int m = 1; m < n; ++m) nzmin = std::min(nzmin, lat[m].nz);
@@ -190,6 +203,9 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
         wave += p.t_n + 2;
         M.pz_off = (int)pz;
         pz += p.nz;
+        M.nw = (p.nx + 31) / 32;
+        M.rt_off = G.rt_words;
+        G.rt_words += (long long)p.nz * p.ny * M.nw;
         M.plist_off = npr;
         M.n_probe = p.n_probe;
         npr += p.n_probe;
@@ -234,6 +250,10 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.tiles_total = G.tiles;
     s.nzt = G.nzt;
     s.listmode = G.listmode;
+    s.compact = G.compact;
+    s.es = (int)es;
+    s.rt = c.take<uint2>((size_t)std::max<long long>(G.compact ? G.rt_words : 1, 1));
+    s.popC = c.take<char>(G.compact ? es * kQ * (size_t)G.cells : 1);
     s.nplanes = (int)G.pz;
     s.clist = c.take<int>((size_t)G.cells);
     s.ccnt = c.take<int>((size_t)std::max<long long>(G.pz, 1));
@@ -340,6 +360,9 @@ struct lbdem_set {
     void *ws = nullptr;
     bool owns_ws = false;
     int64_t t_host = 0;
+    // compact storage: populations currently held at their nodes (after creation or an
+    // expansion, until the next step's list rebuild compacts them again)
+    bool node_layout = true;
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -359,6 +382,20 @@ int sync_set(lbdem_set *S)
 {
     HIPCHK(hipStreamSynchronize(S->stream));
     return LBDEM_OK;
+}
+
+// Compact storage: moves the populations of every lattice back to their nodes (the row
+// tables become the identity) and has the next step rebuild the lists, which compacts
+// them again.  Host access to populations and particle set-up work on the node layout.
+int node_layout(lbdem_set *S)
+{
+    if (!S->G.compact || S->node_layout) return LBDEM_OK;
+    int rc = sync_set(S);
+    if (rc) return rc;
+    HIPCHK(launch_expand(S->G.prec, S->ds, S->stream));
+    HIPCHK(hipMemcpyAsync(S->ds.relist_at, S->ds.tstep, sizeof(long long), hipMemcpyDeviceToDevice, S->stream));
+    S->node_layout = true;
+    return sync_set(S);
 }
 
 int upload_member(lbdem_set *S, int m)
@@ -393,7 +430,7 @@ int build_graph(lbdem_set *S, int steps)
         kp.gridDim = dim3(refresh_grid(S->ds));
         kp.kernelParams = fluid_args;
         HIPCHK(hipGraphAddKernelNode(&n4, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
-        kp.func = fluid_kernel_ptr(S->G.prec);
+        kp.func = fluid_kernel_ptr(S->G.prec, S->G.compact);
         kp.gridDim = dim3(S->ds.tiles_total);
         kp.kernelParams = fluid_args;
         HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n4, 1, &kp));
@@ -580,6 +617,23 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     CHK(hipMemcpyAsync((void *)s.plist, plist.data(), sizeof(int) * plist.size(), hipMemcpyHostToDevice, st));
     CHK(hipMemcpyAsync((void *)s.wave, wave.data(), sizeof(double) * wave.size(), hipMemcpyHostToDevice, st));
     CHK(hipMemcpyAsync(s.pmem, pmem.data(), sizeof(int) * pmem.size(), hipMemcpyHostToDevice, st));
+    if (S->G.compact) {
+        // before the first list build every node is listed: slot = cell
+        std::vector<uint2> rt((size_t)S->G.rt_words);
+        for (int m = 0; m < n_lat; ++m) {
+            const MemberDev &M = S->G.mem[m];
+            for (int k = 0; k < M.nz; ++k)
+                for (int j = 0; j < M.ny; ++j)
+                    for (int w = 0; w < M.nw; ++w) {
+                        const int lo = 32 * w, n_in = std::min(32, M.nx - lo);
+                        const unsigned bits = n_in == 32 ? 0xffffffffu : ((1u << n_in) - 1u);
+                        rt[(size_t)(M.rt_off + ((long long)k * M.ny + j) * M.nw + w)] =
+                            make_uint2(bits, (unsigned)(j * M.nx + lo));
+                    }
+        }
+        CHK(hipMemcpyAsync(s.rt, rt.data(), sizeof(uint2) * rt.size(), hipMemcpyHostToDevice, st));
+        CHK(hipStreamSynchronize(st)); // rt is a local vector
+    }
     // state
     const int P = std::max(S->G.ptot, 1);
     CHK(hipMemsetAsync(s.own[0], 0xff, sizeof(int) * S->G.cells, st));
@@ -691,6 +745,8 @@ int lbdem_particles_set(lbdem_set *S, int32_t lattice, int32_t n, const double *
         mv[q] = M.rho_p * (4.0 / 3.0) * M_PI * R * R * R;
         Iv[q] = 0.4 * mv[q] * R * R;
     }
+    rc = node_layout(S);
+    if (rc) return rc;
     rc = sync_set(S);
     if (rc) return rc;
     long long t = 0;
@@ -774,6 +830,7 @@ int lbdem_step(lbdem_set *S, int64_t nsteps)
         if (rc) return rc;
     }
     S->t_host += nsteps;
+    if (nsteps > 0) S->node_layout = false;
     return LBDEM_OK;
 }
 
@@ -804,7 +861,7 @@ int lbdem_status(lbdem_set *S, uint32_t *bits, int clear)
     *bits = f;
     if (clear) HIPCHK(hipMemset(S->ds.flags, 0, sizeof(unsigned)));
     const unsigned errs = LBDEM_STATUS_NEAR_OVERFLOW | LBDEM_STATUS_HISTORY_OVERFLOW | LBDEM_STATUS_TOO_FAST |
-                          LBDEM_STATUS_SHELL_OVERFLOW | LBDEM_STATUS_LINK_OVERFLOW;
+                          LBDEM_STATUS_SHELL_OVERFLOW | LBDEM_STATUS_LINK_OVERFLOW | LBDEM_STATUS_LIST_MISS;
     if (f & errs) return fail(LBDEM_ECAPACITY, "device status 0x%x", f);
     return LBDEM_OK;
 }
@@ -835,6 +892,8 @@ int lbdem_populations_get(lbdem_set *S, int32_t lattice, double *f)
     int rc = check_lattice(S, lattice);
     if (rc) return rc;
     if (!f) return fail(LBDEM_EINVAL, "null output");
+    rc = node_layout(S);
+    if (rc) return rc;
     int64_t t = 0;
     rc = lbdem_time(S, &t);
     if (rc) return rc;
@@ -861,6 +920,8 @@ int lbdem_populations_set(lbdem_set *S, int32_t lattice, const double *f)
     int rc = check_lattice(S, lattice);
     if (rc) return rc;
     if (!f) return fail(LBDEM_EINVAL, "null input");
+    rc = node_layout(S);
+    if (rc) return rc;
     int64_t t = 0;
     rc = lbdem_time(S, &t);
     if (rc) return rc;
@@ -1026,6 +1087,8 @@ int lbdem_adj_create(lbdem_set *S, int32_t lattice, int64_t nsteps, int32_t ckpt
     const int nblk = (int)((M.ncell + 255) / 256);
     adj_layout(J.get(), M.ncell, M.np, p.n_probe, nblk, nsteps, ckpt_every, J->es, J->cs, (char *)workspace);
     rc = lbdem_time(S, &J->t0);
+    if (rc) return rc;
+    rc = node_layout(S);
     if (rc) return rc;
     rc = sync_set(S);
     if (rc) return rc;

@@ -30,6 +30,7 @@ constexpr int kEmpty = 0x7fffffff;
 // bit per direction, bits 18-30 and 31-43 the local indices in slots 2 and 3.
 constexpr int kMaxLocal = 8191;     // particles per lattice (13-bit local indices)
 constexpr int kRefreshBlocks = 512; // workgroups of the start-of-step refresh kernel
+constexpr int kMaxPlaneWords = 8192; // row-table words of one x-y plane held in LDS (compact storage)
 
 // Per-lattice constants (one entry per lattice of the set).
 struct MemberDev {
@@ -53,6 +54,8 @@ struct MemberDev {
     long long ring_off;       // offset (doubles) of this lattice's probe ring
     int p_off, p_cap, np;     // particles: global offset, capacity, current count
     double E, nu, mu, rho_p;
+    int nw;                   // 32-node words per x row (compact storage)
+    long long rt_off;         // offset of this lattice's row tables (compact storage)
 };
 
 // Everything a kernel needs, passed by value.
@@ -64,6 +67,13 @@ struct DevSet {
     // node lists: per lattice and z plane, the listed nodes in x-fastest order at
     // [cell_off + z*nx*ny, +count); the fluid kernel then runs one thread per listed node
     int listmode;
+    // compact storage (with node lists): populations of the listed nodes of plane z at
+    // slots z*nx*ny + rank (rank in list order); row tables give, per x row and 32-node
+    // word, the listed-node bits and the rank of the word's first listed node
+    int compact;
+    int es;                   // bytes per stored population value
+    uint2 *rt;                // [sum over lattices of nz*ny*nw]
+    void *popC;               // scratch population buffer for re-layouts
     int nplanes;              // sum of nz over the lattices
     int *clist;               // [ncell_total]
     int *ccnt;                // [sum of nz], indexed like the z -> probe map
@@ -155,11 +165,12 @@ hipError_t launch_motion(const DevSet &s, int mode, int only_member, hipStream_t
 hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_remap_prec(int prec, const DevSet &s, int mode, int only_member, hipStream_t st);
 hipError_t launch_init_pops(int prec, const DevSet &s, long long total_cells, hipStream_t st);
+hipError_t launch_expand(int prec, const DevSet &s, hipStream_t st);
 // kernel entry points and grid sizes, for building HIP graphs
 void *refresh_kernel_ptr();
 void *links_kernel_ptr(int prec);
 void *motion_kernel_ptr();
-void *fluid_kernel_ptr(int prec);
+void *fluid_kernel_ptr(int prec, int compact);
 void *remap_kernel_ptr_prec(int prec);
 int refresh_grid(const DevSet &s);
 int links_grid(const DevSet &s);

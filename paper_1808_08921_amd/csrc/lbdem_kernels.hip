@@ -363,6 +363,29 @@ __device__ __forceinline__ const MemberDev *member_of_cell(const DevSet &s, long
     return s.mem + lo;
 }
 
+// Storage slot of node (i, j, k) under compact storage: its rank among the listed nodes
+// of plane k, from the row table of its 32-node word; -1 when the node is not listed.
+__device__ __forceinline__ int slot_of(const DevSet &s, const MemberDev *M, int i, int j, int k)
+{
+    const uint2 r = s.rt[M->rt_off + ((long long)k * M->ny + j) * M->nw + (i >> 5)];
+    const unsigned b = 1u << (i & 31);
+    return (r.x & b) ? k * (M->nx * M->ny) + (int)r.y + __popc(r.x & (b - 1u)) : -1;
+}
+
+// Storage slot of local node `cell` = (i, j, k): the node itself, or its compact slot.
+__device__ __forceinline__ int node_slot(const DevSet &s, const MemberDev *M, int cell, int i, int j, int k)
+{
+    return s.compact ? slot_of(s, M, i, j, k) : cell;
+}
+
+template <typename T>
+__device__ __forceinline__ void move_values(const char *src, long long from, char *dst, long long to, long long stride)
+{
+    const T *a = reinterpret_cast<const T *>(src);
+    T *b = reinterpret_cast<T *>(dst);
+    for (int d = 0; d < kQ; ++d) b[d * stride + to] = a[d * stride + from];
+}
+
 // Link words of node (i, j, k) of lattice M from the node map own (this lattice's part):
 // for a fluid node x, the directions e whose source x - c_e lies inside a particle and the
 // slot (0..3, in the order the particles are met) of the particle owning each source.
@@ -653,6 +676,60 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
                 count += tot;
             }
             if (threadIdx.x == 0) s.ccnt[pl] = count;
+            if (s.compact) {
+                // compact storage: move the plane's populations to the new list order
+                // (through the scratch buffer), then rewrite the plane's row tables
+                __shared__ unsigned tab[kMaxPlaneWords];
+                __threadfence_block();
+                __syncthreads();
+                const long long nc = M->ncell, po = M->pop_off * (long long)s.es;
+                char *A = (char *)(par ? s.popB : s.popA) + po;
+                char *Cb = (char *)s.popC + po;
+                const int ny = M->ny, nw = M->nw;
+                for (int k = threadIdx.x; k < count; k += blockDim.x) {
+                    const int c = lst[k] - z * nxy, j = c / nx, i = c - j * nx;
+                    const int old = slot_of(s, M, i, j, z);
+                    const long long to = (long long)z * nxy + k;
+                    if (old < 0) {
+                        // not listed before: a solid node, given the rest state w_d rho_f
+                        // (zero deviation in 16-bit storage) until it is refilled
+                        for (int d = 0; d < kQ; ++d) {
+                            const double r = kWd[d] * M->rho_f;
+                            if (s.es == 8) reinterpret_cast<double *>(Cb)[d * nc + to] = r;
+                            else if (s.es == 4) reinterpret_cast<float *>(Cb)[d * nc + to] = (float)r;
+                            else reinterpret_cast<unsigned short *>(Cb)[d * nc + to] = 0;
+                        }
+                        continue;
+                    }
+                    if (s.es == 8) move_values<unsigned long long>(A, old, Cb, to, nc);
+                    else if (s.es == 4) move_values<unsigned>(A, old, Cb, to, nc);
+                    else move_values<unsigned short>(A, old, Cb, to, nc);
+                }
+                for (int w = threadIdx.x; w < ny * nw; w += blockDim.x) tab[w] = 0u;
+                __threadfence_block();
+                __syncthreads();
+                for (int k = threadIdx.x; k < count; k += blockDim.x) {
+                    const int c = lst[k] - z * nxy, j = c / nx, i = c - j * nx;
+                    atomicOr(&tab[j * nw + (i >> 5)], 1u << (i & 31));
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    unsigned run = 0u;
+                    uint2 *rtp = s.rt + M->rt_off + (long long)z * ny * nw;
+                    for (int w = 0; w < ny * nw; ++w) {
+                        rtp[w] = make_uint2(tab[w], run);
+                        run += __popc(tab[w]);
+                    }
+                }
+                for (int k = threadIdx.x; k < count; k += blockDim.x) {
+                    const long long at = (long long)z * nxy + k;
+                    if (s.es == 8) move_values<unsigned long long>(Cb, at, A, at, nc);
+                    else if (s.es == 4) move_values<unsigned>(Cb, at, A, at, nc);
+                    else move_values<unsigned short>(Cb, at, A, at, nc);
+                }
+                __threadfence_block();
+                __syncthreads();
+            }
         }
     }
     if (t0 == 0) {
@@ -664,7 +741,7 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
 // Pull streaming (Eq. stream), stationary half-way walls, moving half-way walls on the
 // particles (Eq. mem, from the node's link words), the density faces (Sec. 2.4), BGK
 // collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.
-template <int P>
+template <int P, bool CMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 3 : 5))) void k_fluid(DevSet s)
 {
     using S = typename Prec<P>::S;
@@ -683,9 +760,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     const int nxy = nx * ny;
     const long long pop_off = uni(M->pop_off), cell_off = uni(M->cell_off);
     const int pz_off = uni(M->pz_off);
-    int i, j, z0, z1;
+    int i, j, z0, z1, me0 = 0;
     bool vij;
-    const bool lists = s.listmode != 0;
+    // CMP: compact storage (node lists, populations at the nodes' ranks in the lists)
+    const bool lists = CMP || s.listmode != 0;
+    constexpr bool compact = CMP;
     if (lists) {
         // workgroup = 256 consecutive listed nodes of one z plane
         const int lb = tl % ntx, z = tl / ntx;
@@ -702,6 +781,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
         const int c = vij ? s.clist[cell_off + (long long)z * nxy + k] - z * nxy : 0;
         j = c / nx;
         i = c - j * nx;
+        me0 = z * nxy + k; // the node's slot under compact storage
         z0 = z;
         z1 = z + 1;
     } else {
@@ -754,6 +834,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
             const unsigned long long lwr = s.lw[fl ? cell_off + cell : 0];
             const unsigned long long lwv = fl ? lwr : 0ull;
             const unsigned lmask = (unsigned)lwv & 0x3ffffu;
+            // storage slot of this node: the node itself, or its rank in the plane's list
+            // (as an offset from the node that the compiler cannot see through: it keeps
+            // the register allocation of the node-layout kernel, which has no spills)
+            int dlt = compact ? me0 - cell : 0;
+            if (compact) asm volatile("" : "+v"(dlt));
+            const int me = cell + dlt;
+            // compact storage: slots of the sources from the row tables of the 9 source rows
+            // (y - c_y, z - c_z).  Along a row the listed nodes hold consecutive slots, so
+            // the source x - 1 sits one slot below the node's rank in that row and x + 1
+            // one above it (plus one when x itself is listed); a source across a periodic
+            // x face reads the table word at the other end of the row.
+            int src[kQ - 1];
+            if (compact) {
+                const uint2 *rtab = s.rt + uni(M->rt_off);
+                const int nw = uni(M->nw), per_x = uni(M->per[0]);
+                const unsigned b = 1u << (i & 31);
+                const int wx = (i == 0) ? nx - 1 : 0;
+                const unsigned bw = 1u << (wx & 31);
+                uint2 wv[9], ww[9];
+#pragma unroll
+                for (int r = 0; r < 9; ++r) {
+                    const int jj = wrapc(j + r / 3 - 1, ny), zz = wrapc(z + r % 3 - 1, nz);
+                    const long long row = ((long long)zz * ny + jj) * nw;
+                    wv[r] = rtab[row + (i >> 5)];
+                    ww[r] = per_x ? rtab[row + (wx >> 5)] : make_uint2(0u, 0u);
+                }
+#pragma unroll
+                for (int e = 0; e < kQ - 1; ++e) {
+                    const int r = (1 - kCY[e]) * 3 + (1 - kCZ[e]);
+                    const int zb = wrapc(z - kCZ[e], nz) * nxy;
+                    const int rk = zb + (int)wv[r].y + __popc(wv[r].x & (b - 1u));
+                    const int rwr = zb + (int)ww[r].y + __popc(ww[r].x & (bw - 1u));
+                    int v;
+                    if (kCX[e] == 0) v = rk;
+                    else if (kCX[e] < 0) v = (i < nx - 1) ? rk + ((wv[r].x & b) ? 1 : 0) : rwr;
+                    else v = (i > 0) ? rk - 1 : rwr;
+                    src[e] = max(v, 0);
+                }
+            }
             C f[kQ];
             S raw[kQ];
             unsigned unk = 0u;
@@ -766,12 +885,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                 // f_e(x, t+1) = f~_e(x - c_e, t); from a wall or a particle the population
                 // comes back from this node, f~_{e*}(x, t); across a density face it is unknown
                 const bool back = (kind != 0) || ((lmask >> e) & 1u);
-                const unsigned idx = back ? (unsigned)(kOPP[e] * nc) + (unsigned)cell
-                                          : (unsigned)(e * nc) + (unsigned)(cell + off);
+                const unsigned idx = back ? (unsigned)(kOPP[e] * nc) + (unsigned)me
+                                          : (unsigned)(e * nc) + (unsigned)(compact ? src[e] : cell + off);
                 raw[e] = ldo(A, fl ? idx : 0u);
                 unk |= (kind == BC_PRESSURE) ? (1u << e) : 0u;
             }
-            raw[18] = ldo(A, fl ? (unsigned)(18 * nc) + (unsigned)cell : 0u);
+            raw[18] = ldo(A, fl ? (unsigned)(18 * nc) + (unsigned)me : 0u);
             // every load is in flight before the first use (no branch between them)
             asm volatile("" : "+v"(raw[0]), "+v"(raw[1]), "+v"(raw[2]), "+v"(raw[3]), "+v"(raw[4]), "+v"(raw[5]),
                               "+v"(raw[6]), "+v"(raw[7]), "+v"(raw[8]), "+v"(raw[9]), "+v"(raw[10]), "+v"(raw[11]),
@@ -804,7 +923,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
 #pragma unroll
             for (int d = 0; d < kQ; ++d) {
                 const C fe = feq_dev<C>(d, drho, rho, ux, uy, uz, uu);
-                store_dev<P>(B, (unsigned)(d * nc) + (unsigned)cell, d, f[d] + omega * (fe - f[d]), rho_fd);
+                store_dev<P>(B, (unsigned)(d * nc) + (unsigned)me, d, f[d] + omega * (fe - f[d]), rho_fd);
             }
         }
         const int pidx = s.pzmap[pz_off + z];
@@ -1251,12 +1370,18 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             if (mode == 1) {
                 if (tid == 0) *s.relist_at = t;
             } else {
-                double dl = 0.0;
+                double dl = 0.0, ds = 0.0;
                 for (int a = 0; a < 3; ++a) {
                     const double d = mimg(X[a] - s.Xl[3 * p + a], M->per[a], M->box[a]);
+                    const double v = mimg(X[a] - s.X[par][3 * p + a], M->per[a], M->box[a]);
                     dl += d * d;
+                    ds += v * v;
                 }
-                if (tid == 0 && dl >= (kListSkin - 1e-9) * (kListSkin - 1e-9)) *s.relist_at = t + 1;
+                // compact storage: a node uncovered by the next re-projection needs a slot
+                // in the current lists, so they are rebuilt while the particle stays within
+                // kListSkin after one more step of up to twice this step's displacement
+                const double reach = sqrt(dl) + (s.compact ? 2.0 * sqrt(ds) : 0.0);
+                if (tid == 0 && reach >= kListSkin - 1e-9) *s.relist_at = t + 1;
             }
         }
         // a node can change owner only if |d_ref - R| <= displacement (membership) or
@@ -1337,9 +1462,11 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             const double r2 = mimg((double)kk - X[2], M->per[2], M->box[2]);
             if (was < 0 && best == p) {
                 // Eq. (convertFS): a covered node hands its momentum to the particle
+                const int sl = node_slot(s, M, cell, ii, jj, kk);
+                if (sl < 0) { atomicOr(s.flags, 0x100u); return; }
                 double f[kQ];
 #pragma unroll
-                for (int d = 0; d < kQ; ++d) f[d] = (double)ld<P>(Bn, d * nc + cell, d, rho_ff);
+                for (int d = 0; d < kQ; ++d) f[d] = (double)ld<P>(Bn, d * nc + sl, d, rho_ff);
                 double rho, j0, j1, j2;
                 moments<double>(f, rho, j0, j1, j2);
                 acc[0] += j0; acc[1] += j1; acc[2] += j2;
@@ -1362,6 +1489,8 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                         inside = dist2(M, xx, yy, zc, nb[k][0], nb[k][1], nb[k][2]) <= nb[k][3] * nb[k][3];
                     if (!inside) use |= 1u << e;
                 }
+                const int sl = node_slot(s, M, cell, ii, jj, kk);
+                if (sl < 0) { atomicOr(s.flags, 0x100u); return; }
                 double sum = 0.0;
                 int cnt = 0;
 #pragma unroll 1
@@ -1371,6 +1500,12 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
 #pragma unroll
                     for (int q = 0; q < kQ - 1; ++q)
                         if (q == e) yc = nbc[q];
+                    if (s.compact) {
+                        const int zc = yc / (dims[0] * dims[1]), rc = yc - zc * dims[0] * dims[1];
+                        const int yy = rc / dims[0];
+                        yc = slot_of(s, M, rc - yy * dims[0], yy, zc);
+                        if (yc < 0) { atomicOr(s.flags, 0x100u); continue; }
+                    }
                     double rr = 0.0;
                     for (int d = 0; d < kQ; ++d) rr += (double)ld<P>(Bn, d * nc + yc, d, rho_ff);
                     sum += rr;
@@ -1384,7 +1519,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 const double uu = vb0 * vb0 + vb1 * vb1 + vb2 * vb2;
 #pragma unroll
                 for (int d = 0; d < kQ; ++d)
-                    st<P>(Bn, d * nc + cell, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
+                    st<P>(Bn, d * nc + sl, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
                 const double m0 = rbar * vb0, m1 = rbar * vb1, m2 = rbar * vb2;
                 acc[0] -= m0; acc[1] -= m1; acc[2] -= m2;
                 acc[3] -= r1 * m2 - r2 * m1;
@@ -1540,6 +1675,60 @@ __global__ __launch_bounds__(256) void k_init_pops(DevSet s, long long total_cel
         const typename Prec<P>::C v = (typename Prec<P>::C)(kWd[d] * M->rho_f);
         st<P>(A, d * nc + cell, d, v, rho_ff);
         st<P>(B, d * nc + cell, d, v, rho_ff);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// compact storage back to the node layout (before the host reads or writes populations,
+// or replaces particles): per plane, listed nodes move from their slots to their nodes,
+// every other node takes the rest state w_d rho_f, and the row tables become the identity
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_expand(DevSet s)
+{
+    using S = typename Prec<P>::S;
+    const long long t = *s.tstep;
+    const int par = (int)(t & 1);
+    for (int pl = blockIdx.x; pl < s.nplanes; pl += gridDim.x) {
+        int lo = 0, hi = s.nmem - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s.mem[mid].pz_off <= pl) lo = mid;
+            else hi = mid - 1;
+        }
+        const MemberDev *M = s.mem + lo;
+        const int z = pl - M->pz_off, nx = M->nx, ny = M->ny, nxy = nx * ny, nw = M->nw;
+        const long long nc = M->ncell;
+        S *A = (S *)(par ? s.popB : s.popA) + M->pop_off;
+        S *Cb = (S *)s.popC + M->pop_off;
+        const float rho_ff = (float)M->rho_f;
+        const long long z0 = (long long)z * nxy;
+        // the list of this plane is the one the row tables were built from
+        for (int c = threadIdx.x; c < nxy; c += blockDim.x) {
+            const int j = c / nx, i = c - j * nx;
+            const int sl = slot_of(s, M, i, j, z);
+            if (sl >= 0)
+                for (int d = 0; d < kQ; ++d) Cb[d * nc + z0 + c] = A[d * nc + sl];
+        }
+        __threadfence_block();
+        __syncthreads();
+        for (int c = threadIdx.x; c < nxy; c += blockDim.x) {
+            const int j = c / nx, i = c - j * nx;
+            if (slot_of(s, M, i, j, z) >= 0) {
+                for (int d = 0; d < kQ; ++d) A[d * nc + z0 + c] = Cb[d * nc + z0 + c];
+            } else {
+                for (int d = 0; d < kQ; ++d)
+                    st<P>(A, (unsigned)(d * nc + z0 + c), d, (typename Prec<P>::C)(kWd[d] * M->rho_f), rho_ff);
+            }
+        }
+        __syncthreads();
+        uint2 *rtp = s.rt + M->rt_off + (long long)z * ny * nw;
+        for (int w = threadIdx.x; w < ny * nw; w += blockDim.x) {
+            const int j = w / nw, x0 = (w - j * nw) * 32;
+            const int nb = min(32, nx - x0);
+            rtp[w] = make_uint2(nb == 32 ? 0xffffffffu : ((1u << nb) - 1u), (unsigned)(j * nx + x0));
+        }
+        __syncthreads();
     }
 }
 
@@ -1875,15 +2064,17 @@ __global__ __launch_bounds__(256) void k_adj_vgrad(AdjDev a)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-void *fluid_kernel_ptr(int prec)
+template <bool CMP>
+void *fluid_ptr(int prec)
 {
     switch (prec) {
-    case PREC_FP64: return (void *)&k_fluid<PREC_FP64>;
-    case PREC_FP32: return (void *)&k_fluid<PREC_FP32>;
-    case PREC_FP16DEV: return (void *)&k_fluid<PREC_FP16DEV>;
-    default: return (void *)&k_fluid<PREC_BF16DEV>;
+    case PREC_FP64: return (void *)&k_fluid<PREC_FP64, CMP>;
+    case PREC_FP32: return (void *)&k_fluid<PREC_FP32, CMP>;
+    case PREC_FP16DEV: return (void *)&k_fluid<PREC_FP16DEV, CMP>;
+    default: return (void *)&k_fluid<PREC_BF16DEV, CMP>;
     }
 }
+void *fluid_kernel_ptr(int prec, int compact) { return compact ? fluid_ptr<true>(prec) : fluid_ptr<false>(prec); }
 void *links_kernel_ptr(int prec)
 {
     switch (prec) {
@@ -1915,14 +2106,20 @@ hipError_t launch_refresh(const DevSet &s, hipStream_t st)
 int motion_grid(const DevSet &s) { return max(s.ptot, 1); }
 int remap_grid(const DevSet &s) { return max(s.ptot + s.nprobe_total, 1); }
 
-hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st)
+template <bool CMP>
+void launch_fluid_t(int prec, const DevSet &s, hipStream_t st)
 {
     switch (prec) {
-    case PREC_FP64: hipLaunchKernelGGL(k_fluid<PREC_FP64>, dim3(s.tiles_total), dim3(256), 0, st, s); break;
-    case PREC_FP32: hipLaunchKernelGGL(k_fluid<PREC_FP32>, dim3(s.tiles_total), dim3(256), 0, st, s); break;
-    case PREC_FP16DEV: hipLaunchKernelGGL(k_fluid<PREC_FP16DEV>, dim3(s.tiles_total), dim3(256), 0, st, s); break;
-    default: hipLaunchKernelGGL(k_fluid<PREC_BF16DEV>, dim3(s.tiles_total), dim3(256), 0, st, s); break;
+    case PREC_FP64: hipLaunchKernelGGL((k_fluid<PREC_FP64, CMP>), dim3(s.tiles_total), dim3(256), 0, st, s); break;
+    case PREC_FP32: hipLaunchKernelGGL((k_fluid<PREC_FP32, CMP>), dim3(s.tiles_total), dim3(256), 0, st, s); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL((k_fluid<PREC_FP16DEV, CMP>), dim3(s.tiles_total), dim3(256), 0, st, s); break;
+    default: hipLaunchKernelGGL((k_fluid<PREC_BF16DEV, CMP>), dim3(s.tiles_total), dim3(256), 0, st, s); break;
     }
+}
+hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st)
+{
+    if (s.compact) launch_fluid_t<true>(prec, s, st);
+    else launch_fluid_t<false>(prec, s, st);
     return hipGetLastError();
 }
 
@@ -2049,6 +2246,18 @@ hipError_t launch_init_pops(int prec, const DevSet &s, long long total_cells, hi
     case PREC_FP32: hipLaunchKernelGGL(k_init_pops<PREC_FP32>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
     case PREC_FP16DEV: hipLaunchKernelGGL(k_init_pops<PREC_FP16DEV>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
     default: hipLaunchKernelGGL(k_init_pops<PREC_BF16DEV>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_expand(int prec, const DevSet &s, hipStream_t st)
+{
+    const dim3 g(max(s.nplanes, 1));
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL(k_expand<PREC_FP64>, g, dim3(256), 0, st, s); break;
+    case PREC_FP32: hipLaunchKernelGGL(k_expand<PREC_FP32>, g, dim3(256), 0, st, s); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL(k_expand<PREC_FP16DEV>, g, dim3(256), 0, st, s); break;
+    default: hipLaunchKernelGGL(k_expand<PREC_BF16DEV>, g, dim3(256), 0, st, s); break;
     }
     return hipGetLastError();
 }

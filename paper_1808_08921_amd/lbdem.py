@@ -163,7 +163,8 @@ class LatticeSet:
         cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         cfg.probe_ring, cfg.tile_x, cfg.z_per_thread, cfg.graph_steps = probe_ring, tile_x, z_per_thread, graph_steps
         if node_lists is not None:
-            cfg.node_lists = 1 if node_lists else 0
+            # 0 dense tiles, 1 node lists, 2 node lists with compact storage
+            cfg.node_lists = int(node_lists)
         nbytes = ctypes.c_size_t()
         _check(L.lbdem_workspace_size(n, arr, ctypes.byref(cfg), ctypes.byref(nbytes)))
         self.workspace_bytes = nbytes.value

@@ -55,7 +55,9 @@ def test_workspace_size_and_validation(lb):
     # and four 32-byte FP64 link-force records (128 B); then the per-particle shell lists
     # (16 B per entry, about 5.6 k entries per sphere of radius 9)
     cells = 96 * 96 * 384
-    per_node = 2 * 19 * 4 + 8 + 16 + 128
+    # two population buffers and the scratch buffer of compact storage (the default
+    # mapping), node maps, link words, per-node wall records
+    per_node = 3 * 19 * 4 + 8 + 16 + 128
     assert per_node * cells < n < per_node * cells + 1024 * 5600 * 16 * 1.5 + (64 << 20)
     bad = [
         lb.make_params(8, 8, 8, tau=0.5),                         # tau must exceed 1/2

@@ -137,10 +137,12 @@ def test_projection_bitexact_fcc(seed):
 # ---------------------------------------------------------------------------
 # coupled steps
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("node_lists", [0, 1])
+@pytest.mark.parametrize("node_lists", [0, 1, 2])
 def test_coupled_moving_sphere_with_conversions_fp64(node_lists):
     """A fast sphere in a periodic box: links, cover/uncover conversions every step; with
-    node lists, the lists are rebuilt every few steps as the sphere moves."""
+    node lists, the lists are rebuilt every few steps as the sphere moves (with compact
+    storage the populations move with them, and every comparison reads them back through
+    the node layout)."""
     params = dict(nx=16, ny=15, nz=17, tau=0.8, bc=(0,) * 6, rho_p=1.2, max_particles=2)
     pk = {"x": np.array([[7.3, 6.9, 8.6]]), "radius": np.array([3.2]), "v": np.array([[0.03, -0.02, 0.025]]),
           "w": np.array([[0.0, 0.01, -0.02]])}
@@ -152,10 +154,10 @@ def test_coupled_moving_sphere_with_conversions_fp64(node_lists):
             s.step(15)
             _compare_state(gs, 0, s, pk)
         ph_o, lh_o = s.pending()
-        assert gs.status() & 0x12 == 0
+        assert gs.status() & 0x192 == 0
 
 
-@pytest.mark.parametrize("node_lists", [0, 1])
+@pytest.mark.parametrize("node_lists", [0, 1, 2])
 def test_coupled_fcc_wave_fp64(node_lists):
     params, pk = inputs.wave_fcc_case(seed=2, ncx=2, ncy=2, ncz=3, a=24.0, overlap_rel=1e-2, period=40.0, amp=5e-3)
     params["max_particles"] = len(pk["x"])
@@ -167,6 +169,7 @@ def test_coupled_fcc_wave_fp64(node_lists):
         _compare_state(gs, 0, s, pk)
         pg, po = gs.probes(0, 0, 60), s.probes()
         assert np.abs(pg - po).max() <= 1e-12 * np.abs(po).max()
+        assert gs.status() & 0x180 == 0
 
 
 def test_settling_sphere_walls_fp64():
