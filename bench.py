@@ -223,7 +223,7 @@ def summarize_counters(fetch_csv, write_csv, out_path, command):
     print("\n".join(lines))
 
 
-def measured_traffic(kernel_name="lbdem::k_fluid<1>("):
+def measured_traffic(kernel_name="lbdem::k_fluid<1, true>("):
     """HBM bytes per dispatch of the FP32 fluid kernel from the committed counter summary,
     or None when it is missing or was taken on another version of the kernel source."""
     if not os.path.exists(COUNTERS_FILE):
@@ -435,11 +435,12 @@ def main():
         "config": {"workload": "FCC wave propagation, 4x4x16 FCC cells, 1024 spheres, 96x96x384 D3Q19, FP32 "
                                "populations, cosine inlet 1e-3 / 200 steps, probes every 16 lu",
                    "cells": ncell, "fluid_nodes": nfl, "solid_fraction": 1 - nfl / ncell,
+                   "fluid_mapping": "per-plane node lists, compact population storage",
                    "mlups_all_cells": ncell * args.steps / (r32["ms_per_step"] * 1e-3 * args.steps) / 1e6,
                    "kernel_ms": {"refresh": kt[4], "fluid": kt[2], "links": kt[0], "motion": kt[1], "remap": kt[3]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_fluid<FP32>", "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel": "k_fluid<FP32, compact>", "algorithmic_bytes_per_launch": alg_bytes,
                      "step_frac": alg_bytes / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_variants:
