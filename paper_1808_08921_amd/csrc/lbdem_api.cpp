@@ -233,7 +233,7 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
     if (rmax > 0.0) {
         const double ro = rmax + std::sqrt(2.0) + kShell + 0.8661, ri = std::max(0.0, rmax - kShell - 0.8661);
         G.lcap = (int)std::ceil(4.0 / 3.0 * M_PI * (ro * ro * ro - ri * ri * ri)) + 64;
-        const double bo = rmax + kBand + 0.8661, bi = std::max(0.0, rmax - kBand - 0.8661);
+        const double bo = rmax + kBandOut + 0.8661, bi = std::max(0.0, rmax - kBandIn - 0.8661);
         G.bcap = (int)std::ceil(4.0 / 3.0 * M_PI * (bo * bo * bo - bi * bi * bi)) + 64;
     }
 }
@@ -312,6 +312,8 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.ldirty = c.take<long long>((size_t)P * kChunks);
     s.lzr = c.take<int>(2 * (size_t)P);
     s.lchunk = c.take<int>((size_t)P * (kChunks + 1));
+    s.rdisp = c.take<double>((size_t)P);
+    s.rlens = c.take<double>((size_t)P);
     s.bcap = G.bcap;
     s.bcell = c.take<int>((size_t)P * G.bcap);
     s.bdr = c.take<float>((size_t)P * G.bcap);
@@ -436,8 +438,10 @@ int build_graph(lbdem_set *S, int steps)
         HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n4, 1, &kp));
         kp.func = links_kernel_ptr(S->G.prec);
         kp.gridDim = dim3(links_grid(S->ds));
+        kp.blockDim = dim3(links_block());
         kp.kernelParams = part_args;
         HIPCHK(hipGraphAddKernelNode(&n0, S->graph, &n2, 1, &kp));
+        kp.blockDim = dim3(256);
         kp.func = motion_kernel_ptr();
         kp.gridDim = dim3(motion_grid(S->ds));
         HIPCHK(hipGraphAddKernelNode(&n1, S->graph, &n0, 1, &kp));
@@ -653,6 +657,8 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     double *zero3[] = {s.Fg, s.Fh, s.Th, s.Ph, s.Lh, s.Xref};
     for (double *z : zero3) CHK(hipMemsetAsync(z, 0, sizeof(double) * 3 * P, st));
     CHK(hipMemsetAsync(s.margin, 0, sizeof(double) * P, st));
+    CHK(hipMemsetAsync(s.rdisp, 0, sizeof(double) * P, st));
+    CHK(hipMemsetAsync(s.rlens, 0, sizeof(double) * P, st));
     CHK(hipMemsetAsync(s.pf[0], 0, sizeof(float) * 12 * P, st));
     CHK(hipMemsetAsync(s.pf[1], 0, sizeof(float) * 12 * P, st));
     CHK(hipMemsetAsync(s.nnear, 0, sizeof(int) * P, st));

@@ -18,7 +18,8 @@ constexpr int kHistCap = 16;       // tangential contact history per particle
 constexpr double kNearMargin = 3.0; // near list: |X_p - X_q| <= R_p + R_q + margin
 constexpr int kNearEvery = 5;       // steps between near-list builds (approach < 0.5 lu per step)
 constexpr double kShell = 0.5;      // skin of the per-particle shell lists (lattice units)
-constexpr double kBand = 0.15;      // half-width of the surface band list (lattice units)
+constexpr double kBandIn = 0.15;    // surface band list: nodes with -kBandIn <= d - R <= kBandOut
+constexpr double kBandOut = 0.1;    // (lattice units)
 constexpr double kListSkin = 0.25;  // solid nodes this close to a surface stay in the node lists
 constexpr int kChunks = 8;          // workgroups per particle in the particle kernel
 constexpr int kEmpty = 0x7fffffff;
@@ -122,7 +123,10 @@ struct DevSet {
     // chunks are z-slabs of the list's scan box: first z (unwrapped), slab height, and
     // the list offset where each chunk starts [ptot*2], [ptot*(kChunks+1)]
     int *lzr, *lchunk;
-    // surface band: shell-list entries with |d_ref - R| <= kBand [ptot*bcap], [ptot]
+    // running maxima since the last shell-list rebuild of |X - X_ref| and of |X - X_ref|
+    // plus the overlap depth with the near neighbours [ptot] each
+    double *rdisp, *rlens;
+    // surface band: shell-list entries with -kBandIn <= d_ref - R <= kBandOut [ptot*bcap], [ptot]
     int bcap;
     int *bcell, *bcnt;
     float *bdr;
@@ -174,6 +178,7 @@ void *fluid_kernel_ptr(int prec, int compact);
 void *remap_kernel_ptr_prec(int prec);
 int refresh_grid(const DevSet &s);
 int links_grid(const DevSet &s);
+int links_block();
 int motion_grid(const DevSet &s);
 int remap_grid(const DevSet &s);
 // adjoint window kernels (lbdem_kernels.hip)

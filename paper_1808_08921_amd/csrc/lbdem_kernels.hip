@@ -442,6 +442,35 @@ __device__ __forceinline__ unsigned slot_dirs(unsigned long long w0, unsigned lo
     return mask & ((g & 1) ? lo : ~lo) & ((g & 2) ? hi : ~hi);
 }
 
+// Marks the chunks of q's shell list whose z-slab lies within one plane of z.
+__device__ __forceinline__ void mark_dirty(const DevSet &s, const MemberDev *M, int q, int z, long long t)
+{
+    if (q < 0) return;
+    const int z0 = s.lzr[2 * q], hz = s.lzr[2 * q + 1];
+    if (hz <= 0) return;
+    int dz = z - z0;
+    if (M->per[2]) dz = ((dz % M->nz) + M->nz) % M->nz;
+    for (int w = dz - 1; w <= dz + 1; ++w) {
+        const int c = (w >= 0) ? w / hz : -1;
+        if (c >= 0 && c < kChunks) s.ldirty[q * kChunks + c] = t;
+    }
+}
+
+// Link words of a node changed (re-projection of the previous step): the cached link
+// entries of every particle named in the old or the new words are stale in the chunks
+// around the node's plane z (a particle's slot at the node can move even when its own
+// links there do not change).
+__device__ __forceinline__ void mark_words(const DevSet &s, const MemberDev *M, unsigned long long o0,
+                                           unsigned long long o1, unsigned long long n0, unsigned long long n1,
+                                           int z, long long stamp)
+{
+    for (int g = 0; g < 4; ++g) {
+        int q;
+        if (slot_dirs(o0, o1, g, q) != 0u) mark_dirty(s, M, M->p_off + q, z, stamp);
+        if (slot_dirs(n0, n1, g, q) != 0u) mark_dirty(s, M, M->p_off + q, z, stamp);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // fluid kernel
 // ---------------------------------------------------------------------------
@@ -493,10 +522,10 @@ __device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *
 // Eq. (mem) for the links of a fluid node: f_e = f~_d(x,t) - 2 (w_d / c_s^2) rho_f V_b . c_d,
 // d = e*, for every direction e whose source is inside a particle; f[e] holds the deviation
 // f~_d(x,t) - w_d rho_f (the same relation holds for deviations since w_e = w_d).  For the
-// momentum exchange of Eq. (fFS), F = sum c_d (f~_d + f_e) = 2 (G + rho_f sum c_d w_d) - K V_b
-// with G = sum c_d (f~_d - w_d rho_f) over the node's links to one particle and K = sum
-// 2 (w_d / c_s^2) rho_f c_d c_d^T; the node stores G per slot of its link words (collision
-// precision) and the link kernel adds the rest-state and wall-velocity parts in FP64.
+// momentum exchange of Eq. (fFS), F = sum c_d (f~_d + f_e) over the node's links to one
+// particle = D + 2 rho_f sum c_d w_d with the deviation part D = sum c_d (df~_d + df_e); the
+// node stores D (collision precision) and the link directions per slot of its link words,
+// and the link kernel adds the rest-state part in FP64.
 template <typename C>
 __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M, C (&f)[kQ], unsigned long long w0,
                                             int i, int j, int k, int par, double rho_f, long long gc)
@@ -526,17 +555,20 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
             if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
             if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
             const C fo = f[e];
-            f[e] = fo - (C)(kMW[d] * rho_f) * cu;
-            if (kCX[d] > 0) G0 += fo; else if (kCX[d] < 0) G0 -= fo;
-            if (kCY[d] > 0) G1 += fo; else if (kCY[d] < 0) G1 -= fo;
-            if (kCZ[d] > 0) G2 += fo; else if (kCZ[d] < 0) G2 -= fo;
+            const C fe = fo - (C)(kMW[d] * rho_f) * cu;
+            f[e] = fe;
+            const C fs = fo + fe;
+            if (kCX[d] > 0) G0 += fs; else if (kCX[d] < 0) G0 -= fs;
+            if (kCY[d] > 0) G1 += fs; else if (kCY[d] < 0) G1 -= fs;
+            if (kCZ[d] > 0) G2 += fs; else if (kCZ[d] < 0) G2 -= fs;
         }
+        // the record: the deviation part of F and the link directions (bit pattern)
         if constexpr (sizeof(C) == 4) {
-            reinterpret_cast<float4 *>(s.fnode[g])[gc] = make_float4(G0, G1, G2, 0.0f);
+            reinterpret_cast<float4 *>(s.fnode[g])[gc] = make_float4(G0, G1, G2, __uint_as_float(grp));
         } else {
             double2 *fn = reinterpret_cast<double2 *>(s.fnode[g] + 4 * gc);
             fn[0] = make_double2(G0, G1);
-            fn[1] = make_double2(G2, 0.0);
+            fn[1] = make_double2(G2, __longlong_as_double((long long)grp));
         }
     }
 }
@@ -562,6 +594,8 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
             const int k = cell / nxy, rem = cell - k * nxy, j = rem / M->nx, i = rem - j * M->nx;
             unsigned long long w0, w1;
             link_words(M, s.own[par] + M->cell_off, i, j, k, w0, w1);
+            const unsigned long long o0 = s.lw[c], o1 = s.lw[s.ncell_total + c];
+            if (o0 != w0 || o1 != w1) mark_words(s, M, o0, o1, w0, w1, k, t - 1);
             s.lw[c] = w0;
             s.lw[s.ncell_total + c] = w1;
             over |= (w0 >> 63) != 0ull;
@@ -626,6 +660,8 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
             }
             if (lane == 0) {
                 const long long gc = M->cell_off + (ck * ny + cj) * nx + ci;
+                const unsigned long long o0 = s.lw[gc], o1 = s.lw[s.ncell_total + gc];
+                if (o0 != w0 || o1 != w1) mark_words(s, M, o0, o1, w0, w1, ck, t - 1);
                 s.lw[gc] = w0;
                 s.lw[s.ncell_total + gc] = w1;
                 over |= ov;
@@ -954,7 +990,7 @@ __device__ __forceinline__ void axis_range(double c, double h, int n, int per, i
 }
 
 
-// Workgroups (particle p, chunk of p's shell list): the momentum exchange of p's links,
+// One wave per (particle p, chunk of p's shell list): the momentum exchange of p's links,
 // i.e. of every fluid node x and direction e whose source x - c_e lies in p.  With d = e*
 // pointing into p, Eq. (fFS) gives F = c_d f~_d(x,t) - c_e f_e(x,t+1) = c_d (f~_d + f_e),
 // and Eq. (mem) f_e = f~_d - 2 (w_d / c_s^2) rho_f V_b . c_d, V_b = V_p + Omega_p x
@@ -962,17 +998,17 @@ __device__ __forceinline__ void axis_range(double c, double h, int n, int per, i
 // c_d . (V_p + Omega_p x (x - X_p)), and the torque (x_b - X_p) x F = (x - X_p) x F.  The
 // fluid kernel of the step has stored G = sum c_d f~_d over the node's links to p; here
 // F = 2 G - sum 2 (w_d / c_s^2) rho_f c_d (c_d . V_b), summed in FP64 in a fixed order per
-// chunk (Eqs. coupleF, coupleT).
+// chunk (Eqs. coupleF, coupleT).  A chunk holds ~100-200 links, so a single wave serves it
+// with its loads batched kLinkBatch entries deep, and the whole grid is resident at once.
+constexpr int kLinksBlock = 64;
+constexpr int kLinkBatch = 4;
 template <int P>
-__global__ __launch_bounds__(256) void k_links(DevSet s, int mode, int only)
+__global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int only)
 {
     using C = typename Prec<P>::C;
-    __shared__ double red[4][8];
-    __shared__ int cnt4[4];
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
-    const int tid = threadIdx.x;
-    // workgroup = (particle, chunk of its shell list)
+    const int lane = threadIdx.x;
     const int p = blockIdx.x / kChunks, chunk = blockIdx.x - p * kChunks;
     if (p >= s.ptot || mode != 0) return;
     const int m = uni(s.pmem[p]);
@@ -981,7 +1017,7 @@ __global__ __launch_bounds__(256) void k_links(DevSet s, int mode, int only)
     if (pl >= uni(M->np)) return;
     if (only >= 0 && m != only) return;
 
-    const double *Xo = s.X[par], *Vo = s.V[par], *Wo = s.W[par];
+    const double *Xo = s.X[par];
     const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
     const int nx = uni(M->nx), ny = uni(M->ny);
     const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
@@ -991,6 +1027,8 @@ __global__ __launch_bounds__(256) void k_links(DevSet s, int mode, int only)
     const int nxy = nx * ny;
     const long long lbase = (long long)p * s.lcap;
     const int k0 = s.lchunk[p * (kChunks + 1) + chunk], k1 = s.lchunk[p * (kChunks + 1) + chunk + 1];
+    const bool fresh = (s.lreb[p] == t - 1) || (s.ldirty[p * kChunks + chunk] == t - 1);
+    const int cnt_old = s.xcnt[p * kChunks + chunk];
     int *xc = s.xcell + lbase + k0;
 
     // Links of p at a fluid node x: the link words of x (refreshed by this step's fluid
@@ -1012,88 +1050,87 @@ __global__ __launch_bounds__(256) void k_links(DevSet s, int mode, int only)
     // (1) the chunk's shell-list entries that hold links of p, compacted in list order;
     // kept from the previous step unless the list was rebuilt or a node within one plane
     // of the chunk's slab changed owner in the previous step
-    const bool fresh = (s.lreb[p] == t - 1) || (s.ldirty[p * kChunks + chunk] == t - 1);
     int cntx;
     if (fresh) {
         cntx = 0;
-        for (int base = k0; base < k1; base += 256) {
-            const int k = base + tid;
+        for (int base = k0; base < k1; base += kLinksBlock) {
+            const int k = base + lane;
             bool has = false;
             int cell = 0, slot = -1;
             if (k < k1 && s.lmask[lbase + k] != 0u) {
                 cell = s.lcell[lbase + k];
                 has = links_of_p(cell, slot) != 0u;
             }
-            int tot = 0;
-            const int rk = block_rank(has, tot, cnt4);
-            if (has) xc[cntx + rk] = cell | (slot << 30);
-            cntx += tot;
+            const unsigned long long bal = __ballot(has);
+            if (has) xc[cntx + __popcll(bal & ((1ull << lane) - 1ull))] = cell | (slot << 30);
+            cntx += __popcll(bal);
         }
-        if (tid == 0) s.xcnt[p * kChunks + chunk] = cntx;
+        if (lane == 0) s.xcnt[p * kChunks + chunk] = cntx;
         __threadfence_block();
         __syncthreads();
     } else {
-        cntx = s.xcnt[p * kChunks + chunk];
+        cntx = cnt_old;
     }
 
     // (2) Eqs. (fFS), (coupleF), (coupleT): force and torque (x - X_p) x F over the links.
-    // An entry holds the node and p's slot when the entry was made; the slot is checked
-    // against the current link words (another particle's links at the node can move p to
-    // another slot) while the record of the expected slot is already being read.
-    const double V0 = Vo[3 * p], V1 = Vo[3 * p + 1], V2 = Vo[3 * p + 2];
-    const double W0 = Wo[3 * p], W1 = Wo[3 * p + 1], W2 = Wo[3 * p + 2];
+    // An entry holds the node and p's slot in its link words; both are current, since a
+    // change of the words at a node marks the chunk for rebuilding.  The fluid kernel has
+    // stored the deviation part D of F and the link directions in the slot's record.
+    auto read_rec = [&](int sl, int cell, double &D0, double &D1, double &D2, unsigned &grp) {
+        if constexpr (sizeof(C) == 4) {
+            const float4 v = reinterpret_cast<const float4 *>(s.fnode[sl])[cell_off + cell];
+            D0 = v.x; D1 = v.y; D2 = v.z;
+            grp = __float_as_uint(v.w);
+        } else {
+            const double2 *fp = reinterpret_cast<const double2 *>(s.fnode[sl] + 4 * (cell_off + cell));
+            const double2 a = fp[0], b = fp[1];
+            D0 = a.x; D1 = a.y; D2 = b.x;
+            grp = (unsigned)__double_as_longlong(b.y);
+        }
+    };
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = tid; k < cntx; k += 256) {
-        const int ent = xc[k];
-        const int cell = ent & 0x3fffffff, pred = (int)((unsigned)ent >> 30);
-        double G0, G1, G2;
-        auto read_g = [&](int sl) {
-            if constexpr (sizeof(C) == 4) {
-                const float4 v = reinterpret_cast<const float4 *>(s.fnode[sl])[cell_off + cell];
-                G0 = v.x; G1 = v.y; G2 = v.z;
-            } else {
-                const double2 *fp = reinterpret_cast<const double2 *>(s.fnode[sl] + 4 * (cell_off + cell));
-                const double2 a = fp[0], b = fp[1];
-                G0 = a.x; G1 = a.y; G2 = b.x;
-            }
-        };
-        read_g(pred);
-        int slot;
-        const unsigned grp = links_of_p(cell, slot);
-        if (slot != pred) {
-            if (slot >= 0) read_g(slot);
-            else { G0 = 0.0; G1 = 0.0; G2 = 0.0; }
-        }
-        const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx, ii = rem - jj * nx;
-        const double r0 = mimg((double)ii - X0, per0, box0);
-        const double r1 = mimg((double)jj - X1, per1, box1);
-        const double r2 = mimg((double)kk - X2, per2, box2);
-        // F = 2 G + sum_d c_d (2 w_d rho_f - 2 (w_d / c_s^2) rho_f c_d . V_b) over p's links
-        const double u0 = V0 + (W1 * r2 - W2 * r1);
-        const double u1 = V1 + (W2 * r0 - W0 * r2);
-        const double u2 = V2 + (W0 * r1 - W1 * r0);
-        double F0 = 2.0 * G0, F1 = 2.0 * G1, F2 = 2.0 * G2;
+    for (int base = 0; base < cntx; base += kLinksBlock * kLinkBatch) {
+        int ent[kLinkBatch];
 #pragma unroll
-        for (int e = 0; e < kQ - 1; ++e) {
-            if (!((grp >> e) & 1u)) continue;
-            const int d = kOPP[e];
-            double cu = 0.0;
-            if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
-            if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
-            if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
-            // 2 w_d rho_f c_d (rest state) - 2 (w_d / c_s^2) rho_f c_d (c_d . V_b)
-            const double m = 2.0 * kWd[d] * rho_f - kMW[d] * rho_f * cu;
-            if (kCX[d] > 0) F0 += m; else if (kCX[d] < 0) F0 -= m;
-            if (kCY[d] > 0) F1 += m; else if (kCY[d] < 0) F1 -= m;
-            if (kCZ[d] > 0) F2 += m; else if (kCZ[d] < 0) F2 -= m;
+        for (int b = 0; b < kLinkBatch; ++b) {
+            const int k = base + b * kLinksBlock + lane;
+            ent[b] = (k < cntx) ? xc[k] : -1;
         }
-        acc[0] += F0; acc[1] += F1; acc[2] += F2;
-        acc[3] += r1 * F2 - r2 * F1;
-        acc[4] += r2 * F0 - r0 * F2;
-        acc[5] += r0 * F1 - r1 * F0;
+        double D[kLinkBatch][3];
+        unsigned grp[kLinkBatch];
+#pragma unroll
+        for (int b = 0; b < kLinkBatch; ++b) {
+            const int cell = ent[b] < 0 ? 0 : (ent[b] & 0x3fffffff), sl = ent[b] < 0 ? 0 : (int)((unsigned)ent[b] >> 30);
+            read_rec(sl, cell, D[b][0], D[b][1], D[b][2], grp[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < kLinkBatch; ++b) {
+            if (ent[b] < 0) continue;
+            const int cell = ent[b] & 0x3fffffff;
+            const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx, ii = rem - jj * nx;
+            const double r0 = mimg((double)ii - X0, per0, box0);
+            const double r1 = mimg((double)jj - X1, per1, box1);
+            const double r2 = mimg((double)kk - X2, per2, box2);
+            // F = D + 2 rho_f sum_d w_d c_d over p's links at the node (d pointing into p)
+            double F0 = D[b][0], F1 = D[b][1], F2 = D[b][2];
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                if (!((grp[b] >> e) & 1u)) continue;
+                const int d = kOPP[e];
+                const double mm = 2.0 * kWd[d] * rho_f;
+                if (kCX[d] > 0) F0 += mm; else if (kCX[d] < 0) F0 -= mm;
+                if (kCY[d] > 0) F1 += mm; else if (kCY[d] < 0) F1 -= mm;
+                if (kCZ[d] > 0) F2 += mm; else if (kCZ[d] < 0) F2 -= mm;
+            }
+            acc[0] += F0; acc[1] += F1; acc[2] += F2;
+            acc[3] += r1 * F2 - r2 * F1;
+            acc[4] += r2 * F0 - r0 * F2;
+            acc[5] += r0 * F1 - r1 * F0;
+        }
     }
-    block_sum<6>(acc, red);
-    if (tid == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] = wave_sum(acc[c]);
+    if (lane == 0) {
         double *pp = s.ppart + ((long long)p * kChunks + chunk) * 6;
         for (int c = 0; c < 6; ++c) pp[c] = acc[c];
     }
@@ -1268,23 +1305,10 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
     }
 }
 
+
 // ---------------------------------------------------------------------------
 // re-projection kernel
 // ---------------------------------------------------------------------------
-// Marks the chunks of q's shell list whose z-slab lies within one plane of z.
-__device__ __forceinline__ void mark_dirty(const DevSet &s, const MemberDev *M, int q, int z, long long t)
-{
-    if (q < 0) return;
-    const int z0 = s.lzr[2 * q], hz = s.lzr[2 * q + 1];
-    if (hz <= 0) return;
-    int dz = z - z0;
-    if (M->per[2]) dz = ((dz % M->nz) + M->nz) % M->nz;
-    for (int w = dz - 1; w <= dz + 1; ++w) {
-        const int c = (w >= 0) ? w / hz : -1;
-        if (c >= 0 && c < kChunks) s.ldirty[q * kChunks + c] = t;
-    }
-}
-
 template <int P>
 __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
 {
@@ -1329,39 +1353,67 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
         return;
     }
 
+    // Per-particle values that depend on nothing else are loaded together, before any
+    // branch (index clamped for the probe workgroups): the member, the near list, the
+    // reference state and the first band entries of each thread, and p's position in both
+    // buffers (the parity comes from the step counter, read in the same round).
     bool active = p < s.ptot;
+    const int pc = active ? p : 0;
+    const int m = s.pmem[pc];
+    const int nn_raw = s.nnear[pc];
+    const int q_raw = s.nearl[(long long)pc * kNearCap + (tid & (kNearCap - 1))];
+    const double Rp = s.R[pc];
+    const double Xr_ld[3] = {s.Xref[3 * pc], s.Xref[3 * pc + 1], s.Xref[3 * pc + 2]};
+    const double Xb0[3] = {s.X[0][3 * pc], s.X[0][3 * pc + 1], s.X[0][3 * pc + 2]};
+    const double Xb1[3] = {s.X[1][3 * pc], s.X[1][3 * pc + 1], s.X[1][3 * pc + 2]};
+    const double Xl_ld[3] = {s.Xl[3 * pc], s.Xl[3 * pc + 1], s.Xl[3 * pc + 2]};
+    const double mg_ld = s.margin[pc], rdisp_ld = s.rdisp[pc], rlens_ld = s.rlens[pc];
+    const int bnum = min(s.bcnt[pc], s.bcap);
+    const bool spec = tid < bnum;
+    const int bcell0 = spec ? s.bcell[(long long)pc * s.bcap + tid] : 0;
+    const float bdr0 = spec ? s.bdr[(long long)pc * s.bcap + tid] : 0.0f;
     const MemberDev *M = nullptr;
     if (active) {
-        const int m = s.pmem[p];
         M = s.mem + m;
         active = (p - M->p_off < M->np) && (only < 0 || m == only);
     }
     if (active) {
+        // the lattice's periodicity and extents, held in registers for the distance loops
+        const int perh[3] = {uni(M->per[0]), uni(M->per[1]), uni(M->per[2])};
+        const double boxh[3] = {uni(M->box[0]), uni(M->box[1]), uni(M->box[2])};
+        auto dist2h = [&](int i, int j, int k, double X0, double X1, double X2) {
+            const double dx = mimg((double)i - X0, perh[0], boxh[0]);
+            const double dy = mimg((double)j - X1, perh[1], boxh[1]);
+            const double dz = mimg((double)k - X2, perh[2], boxh[2]);
+            return (dx * dx + dy * dy) + dz * dz;
+        };
         // positions after this step's motion (mode 0) or the current ones (mode 1)
         const int sp = (mode == 1) ? par : (par ^ 1);
         const double *Xs = s.X[sp], *Vs = s.V[sp], *Ws = s.W[sp];
-        const double X[3] = {Xs[3 * p], Xs[3 * p + 1], Xs[3 * p + 2]};
-        const double R = s.R[p], R2 = R * R;
-        const double Xr[3] = {mode == 1 ? X[0] : s.Xref[3 * p], mode == 1 ? X[1] : s.Xref[3 * p + 1],
-                              mode == 1 ? X[2] : s.Xref[3 * p + 2]};
-        const int nn = min(s.nnear[p], kNearCap);
+        const double X[3] = {sp ? Xb1[0] : Xb0[0], sp ? Xb1[1] : Xb0[1], sp ? Xb1[2] : Xb0[2]};
+        const double R = Rp, R2 = R * R;
+        const double Xr[3] = {mode == 1 ? X[0] : Xr_ld[0], mode == 1 ? X[1] : Xr_ld[1], mode == 1 ? X[2] : Xr_ld[2]};
+        const int nn = min(nn_raw, kNearCap);
         if (tid < nn) {
-            const int q = s.nearl[(long long)p * kNearCap + tid];
+            const int q = q_raw;
             nbid[tid] = q;
             nb[tid][0] = Xs[3 * q]; nb[tid][1] = Xs[3 * q + 1]; nb[tid][2] = Xs[3 * q + 2];
             nb[tid][3] = s.R[q];
         }
+        // owner of this thread's first band entry (the candidates of a small step)
+        const int *cur = s.own[par] + M->cell_off;
+        const int was0 = spec ? cur[bcell0] : -1;
         __syncthreads();
         double dmax = 0.0, disp2 = 0.0;
         for (int k = 0; k < nn; ++k) {
-            const double d0 = mimg(nb[k][0] - X[0], M->per[0], M->box[0]);
-            const double d1 = mimg(nb[k][1] - X[1], M->per[1], M->box[1]);
-            const double d2 = mimg(nb[k][2] - X[2], M->per[2], M->box[2]);
+            const double d0 = mimg(nb[k][0] - X[0], perh[0], boxh[0]);
+            const double d1 = mimg(nb[k][1] - X[1], perh[1], boxh[1]);
+            const double d2 = mimg(nb[k][2] - X[2], perh[2], boxh[2]);
             dmax = fmax(dmax, R + nb[k][3] - sqrt((d0 * d0 + d1 * d1) + d2 * d2));
         }
         double xr[3];
         for (int a = 0; a < 3; ++a) {
-            const double d = mimg(X[a] - Xr[a], M->per[a], M->box[a]);
+            const double d = mimg(X[a] - Xr[a], perh[a], boxh[a]);
             disp2 += d * d;
             xr[a] = X[a] - d; // reference centre unwrapped next to X
         }
@@ -1372,8 +1424,8 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             } else {
                 double dl = 0.0, ds = 0.0;
                 for (int a = 0; a < 3; ++a) {
-                    const double d = mimg(X[a] - s.Xl[3 * p + a], M->per[a], M->box[a]);
-                    const double v = mimg(X[a] - s.X[par][3 * p + a], M->per[a], M->box[a]);
+                    const double d = mimg(X[a] - Xl_ld[a], perh[a], boxh[a]);
+                    const double v = mimg(X[a] - (sp ? Xb0[a] : Xb1[a]), perh[a], boxh[a]);
                     dl += d * d;
                     ds += v * v;
                 }
@@ -1384,17 +1436,25 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 if (tid == 0 && reach >= kListSkin - 1e-9) *s.relist_at = t + 1;
             }
         }
-        // a node can change owner only if |d_ref - R| <= displacement (membership) or
-        // it lies in an overlap lens of depth <= dmax (ordering between two spheres)
-        const double thr = sqrt(disp2) + dmax + 1e-9;
+        // Candidates, with d_ref = |x - X_ref| and maxima over this projection and every
+        // one since the shell list was built at X_ref (the node map being replaced comes
+        // from the previous one): a node enters or leaves p only if |d_ref - R| <= dr,
+        // dr = max |X - X_ref|; the order between p and an overlapping sphere changes only
+        // at nodes inside p within the overlap depth, d_ref - R >= -lr, lr = max(|X -
+        // X_ref| + overlap depth).  A node with d_ref - R > dr is outside p at both
+        // projections, so its owner is settled by the other spheres' workgroups.
+        const double disp = sqrt(disp2);
+        const double rd = (mode == 1) ? disp : fmax(rdisp_ld, disp);
+        const double rl = (mode == 1) ? disp + dmax : fmax(rlens_ld, disp + dmax);
+        const double dr = rd + 1e-9, lr = rl + 1e-9;
         // the shell list around X_ref holds every node with |d_ref - R| < kShell: while
-        // thr stays below kShell the candidates are in it, else it is rebuilt at X
-        const bool rebuild = (mode == 1) || (thr >= kShell - 1e-6);
-        const bool use_list = !rebuild && (thr >= s.margin[p]);
+        // lr stays below kShell the candidates are in it, else it is rebuilt at X
+        const bool rebuild = (mode == 1) || (lr >= kShell - 1e-6);
+        const bool use_list = !rebuild && (lr >= mg_ld);
         double acc[6] = {0, 0, 0, 0, 0, 0};
+        int conv = 0; // this thread converted a node (its momentum is in acc)
         const int sn = par ^ 1; // population buffer holding f~(t+1)
         S *Bn = (S *)(sn ? s.popB : s.popA) + M->pop_off;
-        const int *cur = s.own[par] + M->cell_off;
         int *nxt = s.own[par ^ 1] + M->cell_off;
         const int nc = (int)M->ncell;
         const float rho_ff = (float)M->rho_f;
@@ -1402,13 +1462,13 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
         const long long lbase = (long long)p * s.lcap;
 
         // owner of one node after the motion; conversions of covered / uncovered nodes
-        auto evaluate = [&](int ii, int jj, int kk, int cell, double d2n) {
+        auto evaluate = [&](int ii, int jj, int kk, int cell, double d2n, int was_pre) {
             // owner: smallest d^2, then smallest index, among the spheres containing the node
             int best = -1;
             double bd = 0.0;
             if (d2n <= R2) { best = p; bd = d2n; }
             for (int k = 0; k < nn; ++k) {
-                const double dq = dist2(M, ii, jj, kk, nb[k][0], nb[k][1], nb[k][2]);
+                const double dq = dist2h(ii, jj, kk, nb[k][0], nb[k][1], nb[k][2]);
                 if (dq <= nb[k][3] * nb[k][3]) {
                     const int q = nbid[k];
                     if (best < 0 || dq < bd || (dq == bd && q < best)) { best = q; bd = dq; }
@@ -1418,7 +1478,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 if (best >= 0) { s.own[0][M->cell_off + cell] = best; s.own[1][M->cell_off + cell] = best; }
                 return;
             }
-            const int was = cur[cell];
+            const int was = (was_pre >= -1) ? was_pre : cur[cell];
             if (best == was) return;
             nxt[cell] = best;
             // the 18 neighbours and their owners before the re-projection (loads together)
@@ -1457,9 +1517,9 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             } else {
                 atomicOr(s.flags, 0x4u);
             }
-            const double r0 = mimg((double)ii - X[0], M->per[0], M->box[0]);
-            const double r1 = mimg((double)jj - X[1], M->per[1], M->box[1]);
-            const double r2 = mimg((double)kk - X[2], M->per[2], M->box[2]);
+            const double r0 = mimg((double)ii - X[0], perh[0], boxh[0]);
+            const double r1 = mimg((double)jj - X[1], perh[1], boxh[1]);
+            const double r2 = mimg((double)kk - X[2], perh[2], boxh[2]);
             if (was < 0 && best == p) {
                 // Eq. (convertFS): a covered node hands its momentum to the particle
                 const int sl = node_slot(s, M, cell, ii, jj, kk);
@@ -1469,6 +1529,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 for (int d = 0; d < kQ; ++d) f[d] = (double)ld<P>(Bn, d * nc + sl, d, rho_ff);
                 double rho, j0, j1, j2;
                 moments<double>(f, rho, j0, j1, j2);
+                conv = 1;
                 acc[0] += j0; acc[1] += j1; acc[2] += j2;
                 acc[3] += r1 * j2 - r2 * j1;
                 acc[4] += r2 * j0 - r0 * j2;
@@ -1484,9 +1545,9 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                     const int yc = nbc[e];
                     const int zc = yc / (dims[0] * dims[1]), rc = yc - zc * dims[0] * dims[1];
                     const int yy = rc / dims[0], xx = rc - yy * dims[0];
-                    bool inside = dist2(M, xx, yy, zc, X[0], X[1], X[2]) <= R2;
+                    bool inside = dist2h(xx, yy, zc, X[0], X[1], X[2]) <= R2;
                     for (int k = 0; k < nn && !inside; ++k)
-                        inside = dist2(M, xx, yy, zc, nb[k][0], nb[k][1], nb[k][2]) <= nb[k][3] * nb[k][3];
+                        inside = dist2h(xx, yy, zc, nb[k][0], nb[k][1], nb[k][2]) <= nb[k][3] * nb[k][3];
                     if (!inside) use |= 1u << e;
                 }
                 const int sl = node_slot(s, M, cell, ii, jj, kk);
@@ -1520,6 +1581,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
 #pragma unroll
                 for (int d = 0; d < kQ; ++d)
                     st<P>(Bn, d * nc + sl, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
+                conv = 1;
                 const double m0 = rbar * vb0, m1 = rbar * vb1, m2 = rbar * vb2;
                 acc[0] -= m0; acc[1] -= m1; acc[2] -= m2;
                 acc[3] -= r1 * m2 - r2 * m1;
@@ -1532,7 +1594,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             // scan the boxes around X and X_ref, evaluate the candidates, and rebuild the
             // shell list at X: nodes with -kShell < d - R <= sqrt(2) + kShell, with the
             // directions e whose source x - c_e lies within R + kShell (link candidates)
-            const double hout = R + 1.5 + kShell + thr;
+            const double hout = R + 1.5 + kShell + lr;
             const double Rin = R - kShell, Rin2 = Rin > 0.0 ? Rin * Rin : -1.0, Rout2 = hout * hout;
             const double Rl2 = (R + kShell) * (R + kShell);
             int lo[3], ext[3];
@@ -1564,11 +1626,15 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                     int kk = lo[2] + idx / (ext[0] * ext[1]);
                     ii = wrapc(ii, dims[0]); jj = wrapc(jj, dims[1]); kk = wrapc(kk, dims[2]);
                     cell = (kk * dims[1] + jj) * dims[0] + ii;
-                    const double d2n = dist2(M, ii, jj, kk, X[0], X[1], X[2]);
+                    const double d2n = dist2h(ii, jj, kk, X[0], X[1], X[2]);
                     bool ev;
-                    if (mode == 1) ev = d2n <= R2;
-                    else ev = fabs(sqrt(dist2(M, ii, jj, kk, Xr[0], Xr[1], Xr[2])) - R) <= thr;
-                    if (ev) evaluate(ii, jj, kk, cell, d2n);
+                    if (mode == 1) {
+                        ev = d2n <= R2;
+                    } else {
+                        const double dd = sqrt(dist2h(ii, jj, kk, Xr[0], Xr[1], Xr[2])) - R;
+                        ev = dd >= -lr && dd <= dr;
+                    }
+                    if (ev) evaluate(ii, jj, kk, cell, d2n, -2);
                     if (d2n > Rin2 && d2n <= Rout2) {
                         const double dn = sqrt(d2n) - R;
                         if (dn > -kShell && dn <= 1.4142135623730951 + kShell) {
@@ -1581,7 +1647,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                                 if ((!M->per[0] && (si < 0 || si >= dims[0])) || (!M->per[1] && (sj < 0 || sj >= dims[1])) ||
                                     (!M->per[2] && (sk < 0 || sk >= dims[2])))
                                     continue;
-                                if (dist2(M, wrapc(si, dims[0]), wrapc(sj, dims[1]), wrapc(sk, dims[2]), X[0], X[1], X[2]) <= Rl2)
+                                if (dist2h(wrapc(si, dims[0]), wrapc(sj, dims[1]), wrapc(sk, dims[2]), X[0], X[1], X[2]) <= Rl2)
                                     mask |= 1u << e;
                             }
                         }
@@ -1602,7 +1668,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 }
                 lcount += tcount;
                 // the surface band, a sub-list for small displacements
-                const bool in_band = in_list && fabs((double)dref) <= kBand;
+                const bool in_band = in_list && (double)dref >= -kBandIn && (double)dref <= kBandOut;
                 const int bk = block_rank(in_band, tcount, cnt4);
                 if (in_band) {
                     const int slot = bcount + bk;
@@ -1632,27 +1698,39 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                     s.lchunk[p * (kChunks + 1) + c] = min(acc_c, s.lcap);
                 }
                 s.Xref[3 * p] = X[0]; s.Xref[3 * p + 1] = X[1]; s.Xref[3 * p + 2] = X[2];
+                // maxima restart at the new reference, where this projection has
+                // displacement 0 and overlap depth dmax
+                s.rdisp[p] = 0.0;
+                s.rlens[p] = dmax;
             }
             __syncthreads();
         } else if (use_list) {
-            // candidates have |d_ref - R| <= thr: the band list holds them all while
-            // thr <= kBand, the whole shell list otherwise
-            const bool band = thr + 1e-6 <= kBand;
-            const int n = band ? s.bcnt[p] : s.lcnt[p];
+            // candidates have -lr <= d_ref - R <= dr: the band list holds them all while
+            // lr <= kBandIn and dr <= kBandOut, the whole shell list otherwise
+            const bool band = lr + 1e-6 <= kBandIn && dr + 1e-6 <= kBandOut;
+            const int n = band ? bnum : s.lcnt[p];
             const int *lc = band ? s.bcell + (long long)p * s.bcap : s.lcell + lbase;
             const float *dl = band ? s.bdr + (long long)p * s.bcap : s.ldr + lbase;
             for (int k = tid; k < n; k += 256) {
-                if (fabs((double)dl[k]) > thr + 1e-6) continue;
-                const int cell = lc[k];
+                // the first band entry of each thread and its owner are loaded already
+                const bool pre = band && k == tid;
+                const int cell = pre ? bcell0 : lc[k];
+                const double dk = pre ? (double)bdr0 : (double)dl[k];
+                if (dk < -lr - 1e-6 || dk > dr + 1e-6) continue;
                 const int kk = cell / (dims[0] * dims[1]);
                 const int rem = cell - kk * dims[0] * dims[1];
                 const int jj = rem / dims[0], ii = rem - jj * dims[0];
-                evaluate(ii, jj, kk, cell, dist2(M, ii, jj, kk, X[0], X[1], X[2]));
+                evaluate(ii, jj, kk, cell, dist2h(ii, jj, kk, X[0], X[1], X[2]), pre ? was0 : -2);
             }
         }
-        if (mode == 0) block_sum<6>(acc, red);
+        // the momentum of conversions, summed only when some thread made one
+        if (mode == 0 && __syncthreads_or(conv)) block_sum<6>(acc, red);
         if (mode == 0 && tid == 0) {
             for (int a = 0; a < 3; ++a) { s.Ph[3 * p + a] = acc[a]; s.Lh[3 * p + a] = acc[3 + a]; }
+            if (!rebuild) {
+                s.rdisp[p] = rd;
+                s.rlens[p] = rl;
+            }
         }
     }
 }
@@ -2123,15 +2201,17 @@ hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st)
     return hipGetLastError();
 }
 
+int links_block() { return kLinksBlock; }
+
 hipError_t launch_links(int prec, const DevSet &s, hipStream_t st)
 {
-    const dim3 g(links_grid(s));
+    const dim3 g(links_grid(s)), b(kLinksBlock);
     const int mode = 0, only = -1;
     switch (prec) {
-    case PREC_FP64: hipLaunchKernelGGL(k_links<PREC_FP64>, g, dim3(256), 0, st, s, mode, only); break;
-    case PREC_FP32: hipLaunchKernelGGL(k_links<PREC_FP32>, g, dim3(256), 0, st, s, mode, only); break;
-    case PREC_FP16DEV: hipLaunchKernelGGL(k_links<PREC_FP16DEV>, g, dim3(256), 0, st, s, mode, only); break;
-    default: hipLaunchKernelGGL(k_links<PREC_BF16DEV>, g, dim3(256), 0, st, s, mode, only); break;
+    case PREC_FP64: hipLaunchKernelGGL(k_links<PREC_FP64>, g, b, 0, st, s, mode, only); break;
+    case PREC_FP32: hipLaunchKernelGGL(k_links<PREC_FP32>, g, b, 0, st, s, mode, only); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL(k_links<PREC_FP16DEV>, g, b, 0, st, s, mode, only); break;
+    default: hipLaunchKernelGGL(k_links<PREC_BF16DEV>, g, b, 0, st, s, mode, only); break;
     }
     return hipGetLastError();
 }

@@ -157,6 +157,24 @@ def test_coupled_moving_sphere_with_conversions_fp64(node_lists):
         assert gs.status() & 0x192 == 0
 
 
+@pytest.mark.parametrize("node_lists", [0, 2])
+def test_head_on_collision_fp64(node_lists):
+    """Two spheres driven into each other: the overlap grows to ~0.75 lu (lens nodes change
+    owner, shell lists are rebuilt) and the Hertz contact reverses the motion, so the
+    displacement from a shell list's reference shrinks again while nodes keep changing."""
+    params = dict(nx=40, ny=20, nz=20, tau=0.8, bc=(0,) * 6, E=10.0, nu=0.2, mu=0.3, rho_p=1.5, max_particles=2)
+    pk = {"x": np.array([[12.0, 10.0, 10.2], [22.4, 9.8, 9.9]]), "radius": np.array([5.0, 5.0]),
+          "v": np.array([[0.04, 0.0, 0.01], [-0.04, 0.005, 0.0]])}
+    s = _oracle(params, pk)
+    with _gpu_set([params], graph_steps=0, node_lists=node_lists) as gs:
+        _set_particles(gs, 0, pk)
+        for _ in range(6):
+            gs.step(10)
+            s.step(10)
+            _compare_state(gs, 0, s, pk)
+        assert gs.status() & 0x1da == 0
+
+
 @pytest.mark.parametrize("node_lists", [0, 1, 2])
 def test_coupled_fcc_wave_fp64(node_lists):
     params, pk = inputs.wave_fcc_case(seed=2, ncx=2, ncy=2, ncz=3, a=24.0, overlap_rel=1e-2, period=40.0, amp=5e-3)
