@@ -72,7 +72,10 @@ extern "C" {
 #define LBDEM_STATUS_TOO_FAST 0x10u          /* a particle moved more than 0.25 lu in one step (error) */
 #define LBDEM_STATUS_SHELL_OVERFLOW 0x40u    /* a particle's surface-shell table overflowed (error) */
 #define LBDEM_STATUS_LINK_OVERFLOW 0x80u     /* a fluid node had links to more than four particles (error) */
-#define LBDEM_STATUS_LIST_MISS 0x100u        /* compact storage: a node turned fluid outside the node lists (error) */
+#define LBDEM_STATUS_LIST_MISS 0x100u        /* compact storage: more than 16384 refills awaited a list rebuild (error) */
+#define LBDEM_STATUS_LIST_PARKED 0x200u      /* compact storage: a node turned fluid outside the node lists; its refill
+                                                waited for the next step's list rebuild (results valid; a larger
+                                                list_margin avoids it) */
 
 /* One lattice and its physics (Sec. 2; Table 1 "tab:params" for the FCC runs). */
 typedef struct lbdem_params {
@@ -113,6 +116,12 @@ typedef struct lbdem_config {
                              automatic (2 where every plane fits, else 1 for 16-bit storage
                              and 0 otherwise).  Host access to populations, particle set-up
                              and adjoint windows see the node layout either way. */
+    int32_t list_margin;  /* node lists: a lattice's lists are rebuilt once a particle's
+                             displacement since the last rebuild plus list_margin times its
+                             last step reaches the skin (12 times the lattice's largest last
+                             step, within [0.05, 0.25] lu); 0..8, default 2.  Under compact
+                             storage a node uncovered outside the lists anyway has its refill
+                             kept until the rebuild that follows at the next step. */
 } lbdem_config;
 
 typedef struct lbdem_set lbdem_set;

@@ -73,6 +73,7 @@ struct Geometry {
     int nzt = 4;
     int listmode = 1;
     int compact = 0;
+    int list_margin = 2;
     long long rt_words = 0;
     int ring_len = 1;
     int chg_cap = 0;
@@ -92,6 +93,7 @@ int validate(int32_t n, const lbdem_params *lat, const lbdem_config *cfg)
     if (cfg->z_per_thread < 0 || cfg->z_per_thread > 16) return fail(LBDEM_EINVAL, "z_per_thread must be 0..16");
     if (cfg->graph_steps < 0 || cfg->graph_steps > 64) return fail(LBDEM_EINVAL, "graph_steps must be 0..64");
     if (cfg->node_lists < -1 || cfg->node_lists > 2) return fail(LBDEM_EINVAL, "node_lists must be -1, 0, 1 or 2");
+    if (cfg->list_margin < 0 || cfg->list_margin > 8) return fail(LBDEM_EINVAL, "list_margin must be 0..8");
     for (int m = 0; m < n; ++m) {
         const lbdem_params &p = lat[m];
         if (cfg->node_lists == 2 && (long long)p.ny * ((p.nx + 31) / 32) > kMaxPlaneWords)
@@ -160,6 +162,7 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
     }
     G.listmode = mode != 0 ? 1 : 0;
     G.compact = mode == 2 ? 1 : 0;
+    G.list_margin = cfg->list_margin;
     int nzt = cfg->z_per_thread ? cfg->z_per_thread : 2;
     int nzmin = lat[0].nz;
     for (int m = 1; m < n; ++m) nzmin = std::min(nzmin, lat[m].nz);
@@ -251,6 +254,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.nzt = G.nzt;
     s.listmode = G.listmode;
     s.compact = G.compact;
+    s.list_margin = (double)G.list_margin;
     s.es = (int)es;
     s.rt = c.take<uint2>((size_t)std::max<long long>(G.compact ? G.rt_words : 1, 1));
     s.popC = c.take<char>(G.compact ? es * kQ * (size_t)G.cells : 1);
@@ -258,6 +262,11 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.clist = c.take<int>((size_t)G.cells);
     s.ccnt = c.take<int>((size_t)std::max<long long>(G.pz, 1));
     s.relist_at = c.take<long long>(1);
+    s.skin = c.take<double>(G.mem.size());
+    s.pend = c.take<int>((size_t)G.cells);
+    s.pbuf[0] = c.take<double>(4 * (size_t)kPendCap);
+    s.pbuf[1] = c.take<double>(4 * (size_t)kPendCap);
+    s.pcnt = c.take<int>(2);
     s.popA = c.take<char>(es * kQ * (size_t)G.cells);
     s.popB = c.take<char>(es * kQ * (size_t)G.cells);
     s.own[0] = c.take<int>(G.cells);
@@ -292,6 +301,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.Lh = c.take<double>(3 * (size_t)P);
     s.Xref = c.take<double>(3 * (size_t)P);
     s.Xl = c.take<double>(3 * (size_t)P);
+    s.pspd = c.take<double>((size_t)P);
     s.pf[0] = c.take<float>(12 * (size_t)P);
     s.pf[1] = c.take<float>(12 * (size_t)P);
     s.margin = c.take<double>(P);
@@ -428,7 +438,7 @@ int build_graph(lbdem_set *S, int steps)
         kp.sharedMemBytes = 0;
         kp.extra = nullptr;
         // refresh -> fluid -> links -> motion -> re-projection
-        kp.func = refresh_kernel_ptr();
+        kp.func = refresh_kernel_ptr(S->G.prec);
         kp.gridDim = dim3(refresh_grid(S->ds));
         kp.kernelParams = fluid_args;
         HIPCHK(hipGraphAddKernelNode(&n4, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
@@ -489,7 +499,7 @@ int launch_step_eager(lbdem_set *S)
             HIPCHK(hipEventRecord(S->ev_pool[e0], S->stream));
         }
         hipError_t err;
-        if (k == 4) err = launch_refresh(S->ds, S->stream);
+        if (k == 4) err = launch_refresh(S->G.prec, S->ds, S->stream);
         else if (k == 0) err = launch_links(S->G.prec, S->ds, S->stream);
         else if (k == 1) err = launch_motion(S->ds, 0, -1, S->stream);
         else if (k == 2) err = launch_fluid(S->G.prec, S->ds, S->stream);
@@ -523,6 +533,7 @@ int lbdem_default_config(lbdem_config *cfg)
     cfg->probe_ring = 4096;
     cfg->tile_x = 0;
     cfg->node_lists = -1;
+    cfg->list_margin = 2;
     cfg->z_per_thread = 0;
     cfg->graph_steps = 8;
     return LBDEM_OK;
@@ -644,7 +655,15 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     CHK(hipMemsetAsync(s.own[1], 0xff, sizeof(int) * S->G.cells, st));
     CHK(hipMemsetAsync(s.lw, 0, sizeof(unsigned long long) * 2 * S->G.cells, st));
     CHK(hipMemsetAsync(s.relist_at, 0, sizeof(long long), st)); // lists are built by the first step
-    CHK(hipMemsetAsync(s.ccnt, 0, sizeof(int) * std::max<long long>(S->G.pz, 1), st));
+    {
+        std::vector<double> sk(S->G.mem.size(), kListSkin);
+        CHK(hipMemcpyAsync(s.skin, sk.data(), sizeof(double) * sk.size(), hipMemcpyHostToDevice, st));
+        CHK(hipStreamSynchronize(st)); // sk is a local vector
+    }
+    CHK(hipMemsetAsync(s.pend, 0xff, sizeof(int) * S->G.cells, st));
+    CHK(hipMemsetAsync(s.pcnt, 0, sizeof(int) * 2, st));
+    // -1: no list yet, so the first rebuild lays out every plane
+    CHK(hipMemsetAsync(s.ccnt, 0xff, sizeof(int) * std::max<long long>(S->G.pz, 1), st));
     CHK(hipMemsetAsync(s.chgcnt, 0, sizeof(int) * 2, st));
     CHK(hipMemsetAsync(s.pprt, 0, sizeof(double) * S->G.tiles * S->G.nzt * 4, st));
     CHK(hipMemsetAsync(s.ring, 0, sizeof(double) * S->G.ring_doubles, st));
@@ -657,6 +676,7 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     double *zero3[] = {s.Fg, s.Fh, s.Th, s.Ph, s.Lh, s.Xref};
     for (double *z : zero3) CHK(hipMemsetAsync(z, 0, sizeof(double) * 3 * P, st));
     CHK(hipMemsetAsync(s.margin, 0, sizeof(double) * P, st));
+    CHK(hipMemsetAsync(s.pspd, 0, sizeof(double) * P, st));
     CHK(hipMemsetAsync(s.rdisp, 0, sizeof(double) * P, st));
     CHK(hipMemsetAsync(s.rlens, 0, sizeof(double) * P, st));
     CHK(hipMemsetAsync(s.pf[0], 0, sizeof(float) * 12 * P, st));

@@ -20,7 +20,12 @@ constexpr int kNearEvery = 5;       // steps between near-list builds (approach 
 constexpr double kShell = 0.5;      // skin of the per-particle shell lists (lattice units)
 constexpr double kBandIn = 0.15;    // surface band list: nodes with -kBandIn <= d - R <= kBandOut
 constexpr double kBandOut = 0.1;    // (lattice units)
-constexpr double kListSkin = 0.25;  // solid nodes this close to a surface stay in the node lists
+// node lists keep the solid nodes within a skin of a surface; the skin of a rebuild is
+// kSkinSteps times the largest particle step of the lattice, within [kSkinMin, kListSkin]
+constexpr double kListSkin = 0.25;
+constexpr double kSkinMin = 0.05;
+constexpr double kSkinSteps = 12.0;
+constexpr int kPendCap = 16384;     // refills of unlisted nodes awaiting the next list rebuild
 constexpr int kChunks = 8;          // workgroups per particle in the particle kernel
 constexpr int kEmpty = 0x7fffffff;
 // Link words of a fluid node x (two 64-bit words per node: lw[c] and lw[ncell_total + c]).
@@ -80,14 +85,24 @@ struct DevSet {
     int *ccnt;                // [sum of nz], indexed like the z -> probe map
     double *Xl;               // particle positions when the lists were built [ptot*3]
     long long *relist_at;     // step whose refresh rebuilds the lists
+    double *skin;             // skin of each lattice's current lists [nmem]
+    double list_margin;       // look-ahead of the rebuild trigger, in particle steps
+    double *pspd;             // each particle's displacement in its last step [ptot]
+    // compact storage: a node uncovered outside the lists has its refill (rho_bar, V_b)
+    // parked until the next step's list rebuild: record index per node (-1 none)
+    // [ncell_total], records [2][kPendCap*4] and counts [2] by the parity of the step
+    int *pend;
+    double *pbuf[2];
+    int *pcnt;
     // populations
     void *popA, *popB;
     // node maps (index = parity), change lists (pairs cell, owner) and counts
     int *own[2];
     unsigned long long *lw;   // link words, two per node (all lattices) [2*ncell_total]
     long long ncell_total;
-    // link force sum c_d (f~_d + f_e) over a fluid node's links to the particle in each
-    // slot of its link words: FP64 records (x, y, z, unused) [ncell_total][4] per slot
+    // per slot of a fluid node's link words: the deviation part of the link force
+    // sum c_d (df~_d + df_e) over its links to that particle and the link directions
+    // (bit pattern of the last component); FP64 (or FP32) records [ncell_total][4] per slot
     double *fnode[4];
     int *chg[2];
     int chg_cap;
@@ -163,7 +178,7 @@ enum { BC_PERIODIC = 0, BC_WALL = 1, BC_PRESSURE = 2 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16DEV = 2, PREC_BF16DEV = 3 };
 
 // kernel launchers (lbdem_kernels.hip)
-hipError_t launch_refresh(const DevSet &s, hipStream_t st);
+hipError_t launch_refresh(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_links(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_motion(const DevSet &s, int mode, int only_member, hipStream_t st);
 hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st);
@@ -171,7 +186,7 @@ hipError_t launch_remap_prec(int prec, const DevSet &s, int mode, int only_membe
 hipError_t launch_init_pops(int prec, const DevSet &s, long long total_cells, hipStream_t st);
 hipError_t launch_expand(int prec, const DevSet &s, hipStream_t st);
 // kernel entry points and grid sizes, for building HIP graphs
-void *refresh_kernel_ptr();
+void *refresh_kernel_ptr(int prec);
 void *links_kernel_ptr(int prec);
 void *motion_kernel_ptr();
 void *fluid_kernel_ptr(int prec, int compact);

@@ -577,8 +577,10 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
 // t-1 (its change list, or a full copy after an overflow or a particle set-up), refreshes
 // the link words of the changed nodes and their neighbours (all of them after a full
 // copy) from the node map of step t, and opens the change list of step t.
+template <int P>
 __global__ __launch_bounds__(256) void k_refresh(DevSet s)
 {
+    using S = typename Prec<P>::S;
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
     const int cnt = s.chgcnt[par ^ 1];
@@ -670,12 +672,14 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
     }
     if (over) atomicOr(s.flags, 0x80u);
 
-    // node lists, when a particle has moved kListSkin since they were built (or after a
+    // node lists, when a particle has moved the skin since they were built (or after a
     // set-up): per z plane, in x-fastest order, every fluid node and every solid node
-    // less than kListSkin inside its particle's surface.  Only such a node can become
-    // fluid before a particle has moved kListSkin.
+    // less than the skin inside its particle's surface.  Only such a node can become
+    // fluid before a particle has moved the skin.  The skin follows the lattice's
+    // fastest particle (kSkinSteps of its last step, within [kSkinMin, kListSkin]).
     if (s.listmode && *s.relist_at == t) {
         __shared__ int cnt4[4];
+        __shared__ double vred[4];
         for (long long q = t0; q < s.ptot; q += stride)
             for (int ax = 0; ax < 3; ++ax) s.Xl[3 * q + ax] = s.X[par][3 * q + ax];
         for (int pl = blockIdx.x; pl < s.nplanes; pl += gridDim.x) {
@@ -689,7 +693,19 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
             const int z = pl - M->pz_off, nx = M->nx, nxy = M->nx * M->ny;
             const int *own = s.own[par] + M->cell_off;
             int *lst = s.clist + M->cell_off + (long long)z * nxy;
+            // the lattice's largest particle step (non-negative: bit patterns order)
+            double vm = 0.0;
+            for (int q = threadIdx.x; q < M->np; q += blockDim.x) vm = fmax(vm, s.pspd[M->p_off + q]);
+            for (int off = 32; off >= 1; off >>= 1) vm = fmax(vm, __shfl_xor(vm, off, 64));
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) vred[threadIdx.x >> 6] = vm;
+            __syncthreads();
+            vm = fmax(fmax(vred[0], vred[1]), fmax(vred[2], vred[3]));
+            const double skin = fmin(fmax(kSkinSteps * vm, kSkinMin), kListSkin);
+            if (threadIdx.x == 0) s.skin[lo] = skin;
+            const int oldcnt = s.ccnt[pl];
             int count = 0;
+            int chg = 0; // the plane's list differs from the previous one
             for (int c0 = 0; c0 < nxy; c0 += blockDim.x) {
                 const int c = c0 + threadIdx.x;
                 bool listed = false;
@@ -700,7 +716,7 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
                     if (o < 0) {
                         listed = true;
                     } else {
-                        const double rr = s.R[o] - kListSkin;
+                        const double rr = s.R[o] - skin;
                         const int j = c / nx, i = c - j * nx;
                         const double *Xq = s.X[par] + 3 * o;
                         listed = rr <= 0.0 || dist2(M, i, j, z, Xq[0], Xq[1], Xq[2]) > rr * rr;
@@ -708,11 +724,16 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
                 }
                 int tot = 0;
                 const int rk = block_rank(listed, tot, cnt4);
-                if (listed) lst[count + rk] = cell;
+                if (listed) {
+                    chg |= (count + rk >= oldcnt || lst[count + rk] != cell) ? 1 : 0;
+                    lst[count + rk] = cell;
+                }
                 count += tot;
             }
+            // compact storage: an unchanged list keeps its slots, nothing moves
+            const bool moved = __syncthreads_or(chg) || count != oldcnt;
             if (threadIdx.x == 0) s.ccnt[pl] = count;
-            if (s.compact) {
+            if (s.compact && moved) {
                 // compact storage: move the plane's populations to the new list order
                 // (through the scratch buffer), then rewrite the plane's row tables
                 __shared__ unsigned tab[kMaxPlaneWords];
@@ -727,14 +748,22 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
                     const int old = slot_of(s, M, i, j, z);
                     const long long to = (long long)z * nxy + k;
                     if (old < 0) {
-                        // not listed before: a solid node, given the rest state w_d rho_f
-                        // (zero deviation in 16-bit storage) until it is refilled
-                        for (int d = 0; d < kQ; ++d) {
-                            const double r = kWd[d] * M->rho_f;
-                            if (s.es == 8) reinterpret_cast<double *>(Cb)[d * nc + to] = r;
-                            else if (s.es == 4) reinterpret_cast<float *>(Cb)[d * nc + to] = (float)r;
-                            else reinterpret_cast<unsigned short *>(Cb)[d * nc + to] = 0;
+                        // not listed before: a node uncovered in the last re-projection
+                        // takes its parked refill f^eq(rho_bar, V_b) (Eq. convertSF); any
+                        // other is solid and takes the rest state w_d rho_f until refilled
+                        const long long gcell = M->cell_off + lst[k];
+                        const int pi = s.pend[gcell];
+                        double rb = M->rho_f, u0 = 0.0, u1 = 0.0, u2 = 0.0;
+                        if (pi >= 0) {
+                            const double *rec = s.pbuf[par ^ 1] + 4 * pi;
+                            rb = rec[0]; u0 = rec[1]; u1 = rec[2]; u2 = rec[3];
+                            s.pend[gcell] = -1;
                         }
+                        const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+                        S *CbS = reinterpret_cast<S *>(Cb);
+                        for (int d = 0; d < kQ; ++d)
+                            st<P>(CbS, (unsigned)(d * nc + to), d, (typename Prec<P>::C)feq<double>(d, rb, u0, u1, u2, uu),
+                                  (float)M->rho_f);
                         continue;
                     }
                     if (s.es == 8) move_values<unsigned long long>(A, old, Cb, to, nc);
@@ -770,6 +799,7 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
     }
     if (t0 == 0) {
         s.chgcnt[par] = 0;
+        s.pcnt[par] = 0; // parked refills of this step's re-projection
         *s.tcopy = t; // the re-projection kernel of this step reads the step from here
     }
 }
@@ -1417,10 +1447,14 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             disp2 += d * d;
             xr[a] = X[a] - d; // reference centre unwrapped next to X
         }
-        // node lists: rebuilt at the start of the next step once p has moved kListSkin
+        // node lists: rebuilt at the start of the next step once p may have moved the skin
         if (s.listmode) {
             if (mode == 1) {
-                if (tid == 0) *s.relist_at = t;
+                if (tid == 0) {
+                    *s.relist_at = t;
+                    const double *Vp = Vs + 3 * p;
+                    s.pspd[p] = sqrt(Vp[0] * Vp[0] + Vp[1] * Vp[1] + Vp[2] * Vp[2]);
+                }
             } else {
                 double dl = 0.0, ds = 0.0;
                 for (int a = 0; a < 3; ++a) {
@@ -1429,11 +1463,16 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                     dl += d * d;
                     ds += v * v;
                 }
-                // compact storage: a node uncovered by the next re-projection needs a slot
-                // in the current lists, so they are rebuilt while the particle stays within
-                // kListSkin after one more step of up to twice this step's displacement
-                const double reach = sqrt(dl) + (s.compact ? 2.0 * sqrt(ds) : 0.0);
-                if (tid == 0 && reach >= kListSkin - 1e-9) *s.relist_at = t + 1;
+                // a node uncovered by the next re-projection should have a slot in the
+                // current lists, so they are rebuilt while the particle stays within the
+                // skin after one more step of up to list_margin times this step's
+                // displacement (under compact storage a node uncovered outside them is
+                // parked until the rebuild)
+                const double reach = sqrt(dl) + s.list_margin * sqrt(ds);
+                if (tid == 0) {
+                    s.pspd[p] = sqrt(ds);
+                    if (reach >= s.skin[m] - 1e-9) *s.relist_at = t + 1;
+                }
             }
         }
         // Candidates, with d_ref = |x - X_ref| and maxima over this projection and every
@@ -1537,7 +1576,9 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             } else if (was == p && best < 0) {
                 // Eq. (convertSF): an uncovered node is refilled with f^eq(rho_bar, V_b)
                 // and takes rho_bar V_b from the particle; rho_bar averages the
-                // neighbours that are fluid before and after the re-projection
+                // neighbours that are fluid before and after the re-projection.  Under
+                // compact storage a node outside the lists has its refill parked for the
+                // list rebuild at the start of the next step.
                 unsigned use = 0u;
 #pragma unroll
                 for (int e = 0; e < kQ - 1; ++e) {
@@ -1551,7 +1592,6 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                     if (!inside) use |= 1u << e;
                 }
                 const int sl = node_slot(s, M, cell, ii, jj, kk);
-                if (sl < 0) { atomicOr(s.flags, 0x100u); return; }
                 double sum = 0.0;
                 int cnt = 0;
 #pragma unroll 1
@@ -1578,9 +1618,22 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 const double vb1 = Vp[1] + (Wp[2] * r0 - Wp[0] * r2);
                 const double vb2 = Vp[2] + (Wp[0] * r1 - Wp[1] * r0);
                 const double uu = vb0 * vb0 + vb1 * vb1 + vb2 * vb2;
+                if (sl >= 0) {
 #pragma unroll
-                for (int d = 0; d < kQ; ++d)
-                    st<P>(Bn, d * nc + sl, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
+                    for (int d = 0; d < kQ; ++d)
+                        st<P>(Bn, d * nc + sl, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
+                } else {
+                    const int pi = atomicAdd(s.pcnt + par, 1);
+                    if (pi < kPendCap) {
+                        double *rec = s.pbuf[par] + 4 * pi;
+                        rec[0] = rbar; rec[1] = vb0; rec[2] = vb1; rec[3] = vb2;
+                        s.pend[M->cell_off + cell] = pi;
+                        *s.relist_at = t + 1;
+                        atomicOr(s.flags, 0x200u);
+                    } else {
+                        atomicOr(s.flags, 0x100u);
+                    }
+                }
                 conv = 1;
                 const double m0 = rbar * vb0, m1 = rbar * vb1, m2 = rbar * vb2;
                 acc[0] -= m0; acc[1] -= m1; acc[2] -= m2;
@@ -1795,8 +1848,18 @@ __global__ __launch_bounds__(256) void k_expand(DevSet s)
             if (slot_of(s, M, i, j, z) >= 0) {
                 for (int d = 0; d < kQ; ++d) A[d * nc + z0 + c] = Cb[d * nc + z0 + c];
             } else {
+                // a parked refill of the last re-projection, else the rest state
+                const long long gcell = M->cell_off + z0 + c;
+                const int pi = s.pend[gcell];
+                double rb = M->rho_f, u0 = 0.0, u1 = 0.0, u2 = 0.0;
+                if (pi >= 0) {
+                    const double *rec = s.pbuf[par ^ 1] + 4 * pi;
+                    rb = rec[0]; u0 = rec[1]; u1 = rec[2]; u2 = rec[3];
+                    s.pend[gcell] = -1;
+                }
+                const double uu = u0 * u0 + u1 * u1 + u2 * u2;
                 for (int d = 0; d < kQ; ++d)
-                    st<P>(A, (unsigned)(d * nc + z0 + c), d, (typename Prec<P>::C)(kWd[d] * M->rho_f), rho_ff);
+                    st<P>(A, (unsigned)(d * nc + z0 + c), d, (typename Prec<P>::C)feq<double>(d, rb, u0, u1, u2, uu), rho_ff);
             }
         }
         __syncthreads();
@@ -1806,6 +1869,8 @@ __global__ __launch_bounds__(256) void k_expand(DevSet s)
             const int nb = min(32, nx - x0);
             rtp[w] = make_uint2(nb == 32 ? 0xffffffffu : ((1u << nb) - 1u), (unsigned)(j * nx + x0));
         }
+        // the plane's list no longer describes the layout: the next rebuild lays it out
+        if (threadIdx.x == 0) s.ccnt[pl] = -1;
         __syncthreads();
     }
 }
@@ -2174,11 +2239,25 @@ void *remap_kernel_ptr_prec(int prec)
 }
 int links_grid(const DevSet &s) { return max(s.ptot * kChunks, 1); }
 int refresh_grid(const DevSet &) { return kRefreshBlocks; }
-void *refresh_kernel_ptr() { return reinterpret_cast<void *>(k_refresh); }
-
-hipError_t launch_refresh(const DevSet &s, hipStream_t st)
+void *refresh_kernel_ptr(int prec)
 {
-    hipLaunchKernelGGL(k_refresh, dim3(refresh_grid(s)), dim3(256), 0, st, s);
+    switch (prec) {
+    case PREC_FP64: return reinterpret_cast<void *>(&k_refresh<PREC_FP64>);
+    case PREC_FP32: return reinterpret_cast<void *>(&k_refresh<PREC_FP32>);
+    case PREC_FP16DEV: return reinterpret_cast<void *>(&k_refresh<PREC_FP16DEV>);
+    default: return reinterpret_cast<void *>(&k_refresh<PREC_BF16DEV>);
+    }
+}
+
+hipError_t launch_refresh(int prec, const DevSet &s, hipStream_t st)
+{
+    const dim3 g(refresh_grid(s)), b(256);
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL(k_refresh<PREC_FP64>, g, b, 0, st, s); break;
+    case PREC_FP32: hipLaunchKernelGGL(k_refresh<PREC_FP32>, g, b, 0, st, s); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL(k_refresh<PREC_FP16DEV>, g, b, 0, st, s); break;
+    default: hipLaunchKernelGGL(k_refresh<PREC_BF16DEV>, g, b, 0, st, s); break;
+    }
     return hipGetLastError();
 }
 int motion_grid(const DevSet &s) { return max(s.ptot, 1); }

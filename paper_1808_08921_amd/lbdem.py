@@ -54,7 +54,8 @@ class Params(ctypes.Structure):
 
 class Config(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("probe_ring", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("z_per_thread", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("node_lists", ctypes.c_int32)]
+                ("z_per_thread", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("node_lists", ctypes.c_int32),
+                ("list_margin", ctypes.c_int32)]
 
 
 _lib = None
@@ -146,7 +147,7 @@ class LatticeSet:
     """
 
     def __init__(self, lattices, precision="fp32", probe_ring=4096, tile_x=0, z_per_thread=0, graph_steps=8,
-                 device="cuda", node_lists=None):
+                 device="cuda", node_lists=None, list_margin=None):
         import torch
 
         self._torch = torch
@@ -165,6 +166,8 @@ class LatticeSet:
         if node_lists is not None:
             # 0 dense tiles, 1 node lists, 2 node lists with compact storage
             cfg.node_lists = int(node_lists)
+        if list_margin is not None:
+            cfg.list_margin = int(list_margin)
         nbytes = ctypes.c_size_t()
         _check(L.lbdem_workspace_size(n, arr, ctypes.byref(cfg), ctypes.byref(nbytes)))
         self.workspace_bytes = nbytes.value

@@ -157,6 +157,29 @@ def test_coupled_moving_sphere_with_conversions_fp64(node_lists):
         assert gs.status() & 0x192 == 0
 
 
+@pytest.mark.parametrize("margin", [0, 2])
+def test_moving_sphere_parked_refills_fp64(margin):
+    """Compact storage with the list rebuild trigger's look-ahead switched off: nodes turn
+    fluid outside the lists, their refills wait for the next step's rebuild (status bit
+    0x200), and the state still matches the oracle step for step."""
+    params = dict(nx=18, ny=16, nz=17, tau=0.8, bc=(0,) * 6, rho_p=3.0, max_particles=2)
+    pk = {"x": np.array([[7.3, 6.9, 8.6]]), "radius": np.array([3.2]), "v": np.array([[0.09, -0.06, 0.07]]),
+          "w": np.array([[0.0, 0.01, -0.02]])}
+    s = _oracle(params, pk)
+    with _gpu_set([params], graph_steps=0, node_lists=2, list_margin=margin) as gs:
+        _set_particles(gs, 0, pk)
+        gs.step(23)
+        s.step(23)
+        _compare_state(gs, 0, s, pk)
+        gs.step(37)
+        s.step(37)
+        _compare_state(gs, 0, s, pk)
+        st = gs.status()
+        assert st & 0x1da == 0
+        if margin == 0:
+            assert st & 0x200, "no refill was parked"
+
+
 @pytest.mark.parametrize("node_lists", [0, 2])
 def test_head_on_collision_fp64(node_lists):
     """Two spheres driven into each other: the overlap grows to ~0.75 lu (lens nodes change
