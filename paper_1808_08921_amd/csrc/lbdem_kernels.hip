@@ -808,7 +808,7 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
 // particles (Eq. mem, from the node's link words), the density faces (Sec. 2.4), BGK
 // collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.
 template <int P, bool CMP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 3 : 5))) void k_fluid(DevSet s)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 3 : (CMP ? 6 : 5)))) void k_fluid(DevSet s)
 {
     using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
