@@ -1166,38 +1166,40 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     }
 }
 
-// One workgroup per particle p.
+// One wave per particle, kMotionWaves particles per workgroup.
 // mode 0: Eqs. (coupleF), (coupleT): the link force and torque (chunk partials summed in
 //         chunk order) plus the conversion impulses of the previous re-projection; Hertz /
-//         Mindlin contacts (Eqs. fdLawn, fdLaws) and the external force; symplectic Euler
-//         (Eqs. translate, rotate), dt = 1; fixed particles stay.
-// mode 1: near-neighbour lists only (set-up).
-__global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
+//         Mindlin contacts (Eqs. fdLawn, fdLaws) with the particles of the near list and
+//         the external force; symplectic Euler (Eqs. translate, rotate), dt = 1; fixed
+//         particles stay.
+// mode 1: near-neighbour list (every particle within R_p + R_q + kNearMargin) and the FP32
+//         state copy (set-up); later lists are built by the re-projection kernel.
+constexpr int kMotionWaves = 4;
+__global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode, int only)
 {
-    __shared__ double red[4][8];
-    __shared__ int cnt4[4];
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
-    const int tid = threadIdx.x;
-    const int p = blockIdx.x;
-    if (p >= s.ptot) return;
-    const int m = uni(s.pmem[p]);
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * kMotionWaves + (int)(threadIdx.x >> 6);
+    if (p >= s.ptot) return; // the whole wave: waves never synchronise here
+    const int m = s.pmem[p];
     const MemberDev *M = s.mem + m;
-    if (p - uni(M->p_off) >= uni(M->np)) return;
+    if (p - M->p_off >= M->np) return;
     if (only >= 0 && m != only) return;
     const double *Xo = s.X[par], *Vo = s.V[par], *Wo = s.W[par];
     const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
     const double R = s.R[p];
-    const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
-    const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
+    const int per0 = M->per[0], per1 = M->per[1], per2 = M->per[2];
+    const double box0 = M->box[0], box1 = M->box[1], box2 = M->box[2];
+    // the link kernel's chunk sums, in chunk order
     double acc[6] = {0, 0, 0, 0, 0, 0};
     if (mode == 0)
         for (int q = 0; q < kChunks; ++q)
             for (int c = 0; c < 6; ++c) acc[c] += s.ppart[((long long)p * kChunks + q) * 6 + c];
 
-    // (2) contacts, near-neighbour list, tangential history
-    const int q0 = uni(M->p_off), nq = uni(M->np);
-    const double E = uni(M->E), nu = uni(M->nu), mu = uni(M->mu);
+    // contacts over the near list (mode 0) or the near-list build (mode 1)
+    const int q0 = M->p_off, nq = M->np;
+    const double E = M->E, nu = M->nu, mu = M->mu;
     const int *hjo = s.hj[par] + (long long)p * kHistCap;
     const double *hfo = s.hf[par] + (long long)p * kHistCap * 3;
     const int hno = s.hn[par][p];
@@ -1205,16 +1207,12 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
     double *hfn = s.hf[par ^ 1] + (long long)p * kHistCap * 3;
     double con[6] = {0, 0, 0, 0, 0, 0};
     int near_total = 0, hist_total = 0;
-    // Candidates: every particle of the lattice when the near list is (re)built (set-up,
-    // or kNearEvery steps after the last build), else the near list, which holds every
-    // particle within R_p + R_q + kNearMargin at its build; with each particle moving
-    // less than 0.25 per step, contacts stay among them until the next build.
-    const long long nat = s.near_at[p];
-    const bool build = (mode != 0) || nat < 0 || t - nat >= kNearEvery;
+    const bool build = mode != 0;
     const int ncand = build ? nq : min(s.nnear[p], kNearCap);
     const int *nl = s.nearl + (long long)p * kNearCap;
-    for (int base = 0; base < ncand; base += 256) {
-        const int jj = base + tid;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int base = 0; base < ncand; base += 64) {
+        const int jj = base + lane;
         const int q = (jj < ncand) ? (build ? q0 + jj : nl[jj]) : -1;
         bool isnear = false, keep = false;
         double ftn[3] = {0, 0, 0};
@@ -1262,20 +1260,18 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
             }
         }
         if (build) {
-            int tot = 0;
-            const int rk = block_rank(isnear, tot, cnt4);
+            const unsigned long long bal = __ballot(isnear);
             if (isnear) {
-                const int slot = near_total + rk;
+                const int slot = near_total + __popcll(bal & below);
                 if (slot < kNearCap) s.nearl[(long long)p * kNearCap + slot] = q;
                 else atomicOr(s.flags, 0x2u);
             }
-            near_total += tot;
+            near_total += __popcll(bal);
         }
         if (mode == 0 && mu > 0.0) {
-            int ht = 0;
-            const int hr = block_rank(keep, ht, cnt4);
+            const unsigned long long bal = __ballot(keep);
             if (keep) {
-                const int slot = hist_total + hr;
+                const int slot = hist_total + __popcll(bal & below);
                 if (slot < kHistCap) {
                     hjn[slot] = q;
                     hfn[3 * slot] = ftn[0]; hfn[3 * slot + 1] = ftn[1]; hfn[3 * slot + 2] = ftn[2];
@@ -1283,10 +1279,10 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
                     atomicOr(s.flags, 0x8u);
                 }
             }
-            hist_total += ht;
+            hist_total += __popcll(bal);
         }
     }
-    if (tid == 0) {
+    if (lane == 0) {
         if (build) {
             s.nnear[p] = min(near_total, kNearCap);
             s.near_at[p] = t;
@@ -1294,13 +1290,14 @@ __global__ __launch_bounds__(256) void k_motion(DevSet s, int mode, int only)
         if (mode == 0) s.hn[par ^ 1][p] = min(hist_total, kHistCap);
     }
     if (mode != 0) {
-        if (tid == 0) pack_state(s.pf[par] + 12 * p, Xo + 3 * p, Vo + 3 * p, Wo + 3 * p);
+        if (lane == 0) pack_state(s.pf[par] + 12 * p, Xo + 3 * p, Vo + 3 * p, Wo + 3 * p);
         return;
     }
-    block_sum<6>(con, red);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) con[c] = wave_sum(con[c]);
 
-    // (3) motion
-    if (tid == 0) {
+    // symplectic Euler: V and Omega from the total force and torque, then X from the new V
+    if (lane == 0) {
         double Fh[3], Th[3];
         for (int a = 0; a < 3; ++a) {
             Fh[a] = acc[a] + s.Ph[3 * p + a];
@@ -1398,6 +1395,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
     const double Xb1[3] = {s.X[1][3 * pc], s.X[1][3 * pc + 1], s.X[1][3 * pc + 2]};
     const double Xl_ld[3] = {s.Xl[3 * pc], s.Xl[3 * pc + 1], s.Xl[3 * pc + 2]};
     const double mg_ld = s.margin[pc], rdisp_ld = s.rdisp[pc], rlens_ld = s.rlens[pc];
+    const long long nat_ld = s.near_at[pc];
     const int bnum = min(s.bcnt[pc], s.bcap);
     const bool spec = tid < bnum;
     const int bcell0 = spec ? s.bcell[(long long)pc * s.bcap + tid] : 0;
@@ -1774,6 +1772,37 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 const int rem = cell - kk * dims[0] * dims[1];
                 const int jj = rem / dims[0], ii = rem - jj * dims[0];
                 evaluate(ii, jj, kk, cell, dist2h(ii, jj, kk, X[0], X[1], X[2]), pre ? was0 : -2);
+            }
+        }
+        // the near list for the next kNearEvery steps, from the positions after this
+        // step's motion: every particle within R_p + R_q + kNearMargin (each particle
+        // moves less than 0.25 per step, so the contacts and the spheres that can own a
+        // node of p stay among them until the next build)
+        if (mode == 0 && t + 1 - nat_ld >= kNearEvery) {
+            const int q0 = M->p_off, nq = M->np;
+            int near_total = 0;
+            for (int base = 0; base < nq; base += 256) {
+                const int jj = base + tid;
+                bool isnear = false;
+                if (jj < nq && q0 + jj != p) {
+                    const int q = q0 + jj;
+                    const double d0 = mimg(Xs[3 * q] - X[0], perh[0], boxh[0]);
+                    const double d1 = mimg(Xs[3 * q + 1] - X[1], perh[1], boxh[1]);
+                    const double d2 = mimg(Xs[3 * q + 2] - X[2], perh[2], boxh[2]);
+                    isnear = sqrt((d0 * d0 + d1 * d1) + d2 * d2) <= R + s.R[q] + kNearMargin;
+                }
+                int tot = 0;
+                const int rk = block_rank(isnear, tot, cnt4);
+                if (isnear) {
+                    const int slot = near_total + rk;
+                    if (slot < kNearCap) s.nearl[(long long)p * kNearCap + slot] = q0 + jj;
+                    else atomicOr(s.flags, 0x2u);
+                }
+                near_total += tot;
+            }
+            if (tid == 0) {
+                s.nnear[p] = min(near_total, kNearCap);
+                s.near_at[p] = t + 1;
             }
         }
         // the momentum of conversions, summed only when some thread made one
@@ -2260,7 +2289,7 @@ hipError_t launch_refresh(int prec, const DevSet &s, hipStream_t st)
     }
     return hipGetLastError();
 }
-int motion_grid(const DevSet &s) { return max(s.ptot, 1); }
+int motion_grid(const DevSet &s) { return max((s.ptot + kMotionWaves - 1) / kMotionWaves, 1); }
 int remap_grid(const DevSet &s) { return max(s.ptot + s.nprobe_total, 1); }
 
 template <bool CMP>
