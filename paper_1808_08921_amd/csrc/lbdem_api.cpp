@@ -317,6 +317,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.lmask = c.take<unsigned>((size_t)P * G.lcap);
     s.lcnt = c.take<int>(P);
     s.xcell = c.take<int>((size_t)P * G.lcap);
+    s.xslot = c.take<int>((size_t)P * G.lcap);
     s.xcnt = c.take<int>((size_t)P * kChunks);
     s.lreb = c.take<long long>(P);
     s.ldirty = c.take<long long>((size_t)P * kChunks);

@@ -102,7 +102,8 @@ struct DevSet {
     long long ncell_total;
     // per slot of a fluid node's link words: the deviation part of the link force
     // sum c_d (df~_d + df_e) over its links to that particle and the link directions
-    // (bit pattern of the last component); FP64 (or FP32) records [ncell_total][4] per slot
+    // (bit pattern of the last component); FP64 (or FP32) records [ncell_total][4] per
+    // slot, at the node's storage slot (its rank in the lists under compact storage)
     double *fnode[4];
     int *chg[2];
     int chg_cap;
@@ -132,6 +133,7 @@ struct DevSet {
     // the shell-list entries that hold links of the particle: each chunk of a list keeps
     // its own compacted run [ptot*lcap], counts [ptot*kChunks]
     int *xcell, *xcnt;
+    int *xslot;               // storage slot of each cached entry's node [ptot*lcap]
     long long *lreb;          // step after which the shell list was last rebuilt [ptot]
     long long *ldirty;        // last step in which a node of a chunk's z-slab, or next to
                               // it, changed owner [ptot*kChunks]

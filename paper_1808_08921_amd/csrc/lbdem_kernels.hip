@@ -528,7 +528,7 @@ __device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *
 // and the link kernel adds the rest-state part in FP64.
 template <typename C>
 __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M, C (&f)[kQ], unsigned long long w0,
-                                            int i, int j, int k, int par, double rho_f, long long gc)
+                                            int i, int j, int k, int par, double rho_f, long long gc, long long gr)
 {
     const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + gc] : 0ull;
     const int ng = (w0 >> 62) ? 4 : 2;
@@ -564,9 +564,9 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
         }
         // the record: the deviation part of F and the link directions (bit pattern)
         if constexpr (sizeof(C) == 4) {
-            reinterpret_cast<float4 *>(s.fnode[g])[gc] = make_float4(G0, G1, G2, __uint_as_float(grp));
+            reinterpret_cast<float4 *>(s.fnode[g])[gr] = make_float4(G0, G1, G2, __uint_as_float(grp));
         } else {
-            double2 *fn = reinterpret_cast<double2 *>(s.fnode[g] + 4 * gc);
+            double2 *fn = reinterpret_cast<double2 *>(s.fnode[g] + 4 * gr);
             fn[0] = make_double2(G0, G1);
             fn[1] = make_double2(G2, __longlong_as_double((long long)grp));
         }
@@ -970,7 +970,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
 #pragma unroll
             for (int e = 0; e < kQ; ++e)
                 f[e] = (fl && !((unk >> e) & 1u)) ? decode_dev<P>(raw[e], e, rho_fd) : C(0);
-            if (lmask != 0u) moving_wall<C>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell);
+            if (lmask != 0u) moving_wall<C>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell, cell_off + me);
 
             if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, drho_in, false);
             if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, C(0), true);
@@ -1057,9 +1057,12 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     const int nxy = nx * ny;
     const long long lbase = (long long)p * s.lcap;
     const int k0 = s.lchunk[p * (kChunks + 1) + chunk], k1 = s.lchunk[p * (kChunks + 1) + chunk + 1];
-    const bool fresh = (s.lreb[p] == t - 1) || (s.ldirty[p * kChunks + chunk] == t - 1);
+    // (a list rebuild under compact storage moves the nodes' storage slots)
+    const bool fresh = (s.lreb[p] == t - 1) || (s.ldirty[p * kChunks + chunk] == t - 1) ||
+                       (s.compact && *s.relist_at == t);
     const int cnt_old = s.xcnt[p * kChunks + chunk];
     int *xc = s.xcell + lbase + k0;
+    int *xs = s.xslot + lbase + k0;
 
     // Links of p at a fluid node x: the link words of x (refreshed by this step's fluid
     // kernel) give p's slot at x, whose link-force sum the fluid kernel has stored.
@@ -1092,7 +1095,12 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
                 has = links_of_p(cell, slot) != 0u;
             }
             const unsigned long long bal = __ballot(has);
-            if (has) xc[cntx + __popcll(bal & ((1ull << lane) - 1ull))] = cell | (slot << 30);
+            if (has) {
+                const int at = cntx + __popcll(bal & ((1ull << lane) - 1ull));
+                const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
+                xc[at] = cell | (slot << 30);
+                xs[at] = node_slot(s, M, cell, rem - jj * nx, jj, kk);
+            }
             cntx += __popcll(bal);
         }
         if (lane == 0) s.xcnt[p * kChunks + chunk] = cntx;
@@ -1106,13 +1114,13 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     // An entry holds the node and p's slot in its link words; both are current, since a
     // change of the words at a node marks the chunk for rebuilding.  The fluid kernel has
     // stored the deviation part D of F and the link directions in the slot's record.
-    auto read_rec = [&](int sl, int cell, double &D0, double &D1, double &D2, unsigned &grp) {
+    auto read_rec = [&](int sl, int at, double &D0, double &D1, double &D2, unsigned &grp) {
         if constexpr (sizeof(C) == 4) {
-            const float4 v = reinterpret_cast<const float4 *>(s.fnode[sl])[cell_off + cell];
+            const float4 v = reinterpret_cast<const float4 *>(s.fnode[sl])[cell_off + at];
             D0 = v.x; D1 = v.y; D2 = v.z;
             grp = __float_as_uint(v.w);
         } else {
-            const double2 *fp = reinterpret_cast<const double2 *>(s.fnode[sl] + 4 * (cell_off + cell));
+            const double2 *fp = reinterpret_cast<const double2 *>(s.fnode[sl] + 4 * (cell_off + at));
             const double2 a = fp[0], b = fp[1];
             D0 = a.x; D1 = a.y; D2 = b.x;
             grp = (unsigned)__double_as_longlong(b.y);
@@ -1120,18 +1128,19 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     };
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int base = 0; base < cntx; base += kLinksBlock * kLinkBatch) {
-        int ent[kLinkBatch];
+        int ent[kLinkBatch], at[kLinkBatch];
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b) {
             const int k = base + b * kLinksBlock + lane;
             ent[b] = (k < cntx) ? xc[k] : -1;
+            at[b] = (k < cntx) ? xs[k] : 0;
         }
         double D[kLinkBatch][3];
         unsigned grp[kLinkBatch];
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b) {
-            const int cell = ent[b] < 0 ? 0 : (ent[b] & 0x3fffffff), sl = ent[b] < 0 ? 0 : (int)((unsigned)ent[b] >> 30);
-            read_rec(sl, cell, D[b][0], D[b][1], D[b][2], grp[b]);
+            const int sl = ent[b] < 0 ? 0 : (int)((unsigned)ent[b] >> 30);
+            read_rec(sl, ent[b] < 0 ? 0 : max(at[b], 0), D[b][0], D[b][1], D[b][2], grp[b]);
         }
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b) {
