@@ -65,6 +65,7 @@ struct Geometry {
     std::vector<MemberDev> mem;
     long long cells = 0;
     int tiles = 0;
+    int tiles_max = 0;        // the fluid grid's largest size (probe partials are sized for it)
     int ptot = 0;
     int nprobe = 0;
     long long ring_doubles = 0;
@@ -222,6 +223,7 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
     }
     G.cells = cells;
     G.tiles = tiles;
+    G.tiles_max = tiles;
     G.ptot = pt;
     G.nprobe = npr;
     G.ring_doubles = ring;
@@ -278,7 +280,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.chg[0] = c.take<int>(2 * (size_t)G.chg_cap);
     s.chg[1] = c.take<int>(2 * (size_t)G.chg_cap);
     s.chgcnt = c.take<int>(2);
-    s.pprt = c.take<double>((size_t)G.tiles * G.nzt * 4);
+    s.pprt = c.take<double>((size_t)G.tiles_max * G.nzt * 4);
     s.ring = c.take<double>(G.ring_doubles);
     s.ring_len = G.ring_len;
     s.pzmap = c.take<short>(G.pz);
@@ -414,6 +416,51 @@ int node_layout(lbdem_set *S)
 int upload_member(lbdem_set *S, int m)
 {
     HIPCHK(hipMemcpyAsync((void *)(S->ds.mem + m), &S->G.mem[m], sizeof(MemberDev), hipMemcpyHostToDevice, S->stream));
+    return LBDEM_OK;
+}
+
+int build_graph(lbdem_set *S, int steps);
+
+// Node lists: workgroups per plane of a lattice from the listed nodes its particles leave.
+// A plane's cross-sections of the spheres shrunk by the widest list skin and half a node
+// bound its solid non-listed area from below (overlaps aside), so nx*ny minus that area
+// bounds its listed nodes from above.  The fluid kernel gives a plane with more listed
+// nodes than its workgroups hold further chunks per workgroup, so the estimate sets the
+// speed (no idle workgroups), never the result.
+int retile_lists(lbdem_set *S, int lattice, int n, const double *X, const double *Rv)
+{
+    if (!S->G.listmode) return LBDEM_OK;
+    MemberDev &M = S->G.mem[lattice];
+    const long long nxy = (long long)M.nx * M.ny;
+    std::vector<double> solid((size_t)M.nz, 0.0);
+    for (int q = 0; q < n; ++q) {
+        const double r = Rv[q] - kListSkin - 0.5, zc = X[3 * q + 2];
+        if (r <= 0.0) continue;
+        for (int z = (int)std::ceil(zc - r); z <= (int)std::floor(zc + r); ++z) {
+            int zz = z;
+            if (M.per[2]) zz = ((z % M.nz) + M.nz) % M.nz;
+            else if (z < 0 || z >= M.nz) continue;
+            const double h = (double)z - zc;
+            solid[(size_t)zz] += M_PI * std::max(r * r - h * h, 0.0);
+        }
+    }
+    double worst = 0.0;
+    for (int z = 0; z < M.nz; ++z) worst = std::max(worst, (double)nxy - solid[(size_t)z]);
+    const int full = (int)((nxy + 255) / 256);
+    const int ntx = std::min(std::max((int)std::ceil(worst / 256.0) + 1, 1), full);
+    if (ntx == M.ntx) return LBDEM_OK;
+    M.ntx = ntx;
+    int tiles = 0;
+    for (MemberDev &Mm : S->G.mem) {
+        Mm.tile_off = tiles;
+        tiles += Mm.ntx * Mm.nty * Mm.ntz;
+    }
+    S->G.tiles = tiles;
+    S->ds.tiles_total = tiles;
+    HIPCHK(hipMemcpyAsync((void *)S->ds.mem, S->G.mem.data(), sizeof(MemberDev) * S->G.mem.size(),
+                          hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));
+    if (S->gexec) return build_graph(S, S->graph_steps);
     return LBDEM_OK;
 }
 
@@ -666,7 +713,7 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     // -1: no list yet, so the first rebuild lays out every plane
     CHK(hipMemsetAsync(s.ccnt, 0xff, sizeof(int) * std::max<long long>(S->G.pz, 1), st));
     CHK(hipMemsetAsync(s.chgcnt, 0, sizeof(int) * 2, st));
-    CHK(hipMemsetAsync(s.pprt, 0, sizeof(double) * S->G.tiles * S->G.nzt * 4, st));
+    CHK(hipMemsetAsync(s.pprt, 0, sizeof(double) * S->G.tiles_max * S->G.nzt * 4, st));
     CHK(hipMemsetAsync(s.ring, 0, sizeof(double) * S->G.ring_doubles, st));
     for (int k = 0; k < 2; ++k) {
         CHK(hipMemsetAsync(s.X[k], 0, sizeof(double) * 3 * P, st));
@@ -804,6 +851,8 @@ int lbdem_particles_set(lbdem_set *S, int32_t lattice, int32_t n, const double *
     HIPCHK(hipMemsetAsync(s.own[1] + M.cell_off, 0xff, sizeof(int) * M.ncell, st));
     M.np = n;
     rc = upload_member(S, lattice);
+    if (rc) return rc;
+    rc = retile_lists(S, lattice, n, X.data(), Rv.data());
     if (rc) return rc;
     hipError_t e = launch_motion(s, 1, lattice, st);
     if (e != hipSuccess) return fail(LBDEM_EDEVICE, "near-list kernel: %s", hipGetErrorString(e));

@@ -826,40 +826,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     const int nxy = nx * ny;
     const long long pop_off = uni(M->pop_off), cell_off = uni(M->cell_off);
     const int pz_off = uni(M->pz_off);
-    int i, j, z0, z1, me0 = 0;
-    bool vij;
-    // CMP: compact storage (node lists, populations at the nodes' ranks in the lists)
-    const bool lists = CMP || s.listmode != 0;
-    constexpr bool compact = CMP;
-    if (lists) {
-        // workgroup = 256 consecutive listed nodes of one z plane
-        const int lb = tl % ntx, z = tl / ntx;
-        const int cnt = s.ccnt[pz_off + z];
-        if (lb * 256 >= cnt) {
-            if (s.pzmap[pz_off + z] >= 0 && threadIdx.x == 0) {
-                double *o = s.pprt + (long long)g * s.nzt * 4;
-                o[0] = 0.0; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0;
-            }
-            return;
-        }
-        const int k = lb * 256 + (int)threadIdx.x;
-        vij = k < cnt;
-        const int c = vij ? s.clist[cell_off + (long long)z * nxy + k] - z * nxy : 0;
-        j = c / nx;
-        i = c - j * nx;
-        me0 = z * nxy + k; // the node's slot under compact storage
-        z0 = z;
-        z1 = z + 1;
-    } else {
-        const int bxl = uni(M->bx_log2);
-        const int lx = threadIdx.x & ((1 << bxl) - 1), ly = threadIdx.x >> bxl;
-        const int tx = tl % ntx, trem = tl / ntx, ty = trem % nty, tz = trem / nty;
-        i = (tx << bxl) + lx;
-        j = ty * uni(M->by) + ly;
-        vij = (i < nx) && (j < ny);
-        z0 = tz * s.nzt;
-        z1 = min(z0 + s.nzt, nz);
-    }
     const S *A = (const S *)(par ? s.popB : s.popA) + pop_off;
     S *B = (S *)(par ? s.popA : s.popB) + pop_off;
     const int *own = s.own[par] + cell_off;
@@ -871,136 +837,176 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     if (ti > t_n + 1) ti = t_n + 1;
     const C drho_in = (C)(s.wave[uni(M->wave_off) + ti] - rho_fd);
 
-    // offsets to the x-1 / x+1 / y-1 / y+1 neighbours (wrapped on periodic axes) and the
-    // kind of face crossed to reach them (0 inside or periodic, 1 wall, 2 density face)
-    int oxm = (i > 0) ? -1 : (nx - 1), oxp = (i < nx - 1) ? 1 : -(nx - 1);
-    int kxm = (i > 0) ? 0 : uni(M->bc[0]), kxp = (i < nx - 1) ? 0 : uni(M->bc[1]);
-    int oym = (j > 0) ? -nx : (ny - 1) * nx, oyp = (j < ny - 1) ? nx : -(ny - 1) * nx;
-    int kym = (j > 0) ? 0 : uni(M->bc[2]), kyp = (j < ny - 1) ? 0 : uni(M->bc[3]);
+    // CMP: compact storage (node lists, populations at the nodes' ranks in the lists)
+    const bool lists = CMP || s.listmode != 0;
+    constexpr bool compact = CMP;
 
-    for (int z = z0; z < z1; ++z) {
-        // keep the 18 per-direction offsets from being hoisted out of the loop: they are
-        // cheap to recompute and would otherwise stay live in 36 registers
-        asm volatile("" : "+v"(oxm), "+v"(oxp), "+v"(oym), "+v"(oyp), "+v"(kxm), "+v"(kxp), "+v"(kym), "+v"(kyp));
-        const int cell = (z * ny + j) * nx + i;
-        bool fl = false;
-        if (vij) fl = ldo(own, (unsigned)cell) < 0;
-        double pr0 = 0.0, pr1 = 0.0, pr2 = 0.0, pr3 = 0.0;
-        // Dense tiles with 4- and 8-byte storage write every node of a row, so each store
-        // covers whole cache lines: a solid node loads nothing and stores the rest state
-        // w_d, a value that is never read (a node is refilled on uncovering).  16-bit
-        // storage measured faster with solid nodes left out; with node lists only the
-        // fluid nodes work.
-        constexpr bool kWholeRows = sizeof(S) >= 4;
-        if ((kWholeRows && !lists) ? vij : fl) {
-            const int ozm = (z > 0) ? -nxy : (nz - 1) * nxy, ozp = (z < nz - 1) ? nxy : -(nz - 1) * nxy;
-            const int kzm = (z > 0) ? 0 : bc4, kzp = (z < nz - 1) ? 0 : bc5;
-            // Loads are issued for every lane, a solid lane reading the first element of the
-            // array (one shared line) instead of branching around each load.
-            const unsigned long long lwr = s.lw[fl ? cell_off + cell : 0];
-            const unsigned long long lwv = fl ? lwr : 0ull;
-            const unsigned lmask = (unsigned)lwv & 0x3ffffu;
-            // storage slot of this node: the node itself, or its rank in the plane's list
-            // (as an offset from the node that the compiler cannot see through: it keeps
-            // the register allocation of the node-layout kernel, which has no spills)
-            int dlt = compact ? me0 - cell : 0;
-            if (compact) asm volatile("" : "+v"(dlt));
-            const int me = cell + dlt;
-            // compact storage: slots of the sources from the row tables of the 9 source rows
-            // (y - c_y, z - c_z).  Along a row the listed nodes hold consecutive slots, so
-            // the source x - 1 sits one slot below the node's rank in that row and x + 1
-            // one above it (plus one when x itself is listed); a source across a periodic
-            // x face reads the table word at the other end of the row.
-            int src[kQ - 1];
-            if (compact) {
-                const uint2 *rtab = s.rt + uni(M->rt_off);
-                const int nw = uni(M->nw), per_x = uni(M->per[0]);
-                const unsigned b = 1u << (i & 31);
-                const int wx = (i == 0) ? nx - 1 : 0;
-                const unsigned bw = 1u << (wx & 31);
-                uint2 wv[9], ww[9];
-#pragma unroll
-                for (int r = 0; r < 9; ++r) {
-                    const int jj = wrapc(j + r / 3 - 1, ny), zz = wrapc(z + r % 3 - 1, nz);
-                    const long long row = ((long long)zz * ny + jj) * nw;
-                    wv[r] = rtab[row + (i >> 5)];
-                    ww[r] = per_x ? rtab[row + (wx >> 5)] : make_uint2(0u, 0u);
+    // one chunk of the work: the nodes (i, j) of planes z0 .. z1-1 (dense tiles), or one
+    // listed node of plane z0 at slot me0 (node lists); accum adds the probe partial sums
+    // to those of an earlier chunk of the same workgroup
+    auto run = [&](int i, int j, int z0, int z1, int me0, bool vij, bool accum) {
+        // offsets to the x-1 / x+1 / y-1 / y+1 neighbours (wrapped on periodic axes) and the
+        // kind of face crossed to reach them (0 inside or periodic, 1 wall, 2 density face)
+        int oxm = (i > 0) ? -1 : (nx - 1), oxp = (i < nx - 1) ? 1 : -(nx - 1);
+        int kxm = (i > 0) ? 0 : uni(M->bc[0]), kxp = (i < nx - 1) ? 0 : uni(M->bc[1]);
+        int oym = (j > 0) ? -nx : (ny - 1) * nx, oyp = (j < ny - 1) ? nx : -(ny - 1) * nx;
+        int kym = (j > 0) ? 0 : uni(M->bc[2]), kyp = (j < ny - 1) ? 0 : uni(M->bc[3]);
+
+        for (int z = z0; z < z1; ++z) {
+            // keep the 18 per-direction offsets from being hoisted out of the loop: they are
+            // cheap to recompute and would otherwise stay live in 36 registers
+            asm volatile("" : "+v"(oxm), "+v"(oxp), "+v"(oym), "+v"(oyp), "+v"(kxm), "+v"(kxp), "+v"(kym), "+v"(kyp));
+            const int cell = (z * ny + j) * nx + i;
+            bool fl = false;
+            if (vij) fl = ldo(own, (unsigned)cell) < 0;
+            double pr0 = 0.0, pr1 = 0.0, pr2 = 0.0, pr3 = 0.0;
+            // Dense tiles with 4- and 8-byte storage write every node of a row, so each store
+            // covers whole cache lines: a solid node loads nothing and stores the rest state
+            // w_d, a value that is never read (a node is refilled on uncovering).  16-bit
+            // storage measured faster with solid nodes left out; with node lists only the
+            // fluid nodes work.
+            constexpr bool kWholeRows = sizeof(S) >= 4;
+            if ((kWholeRows && !lists) ? vij : fl) {
+                const int ozm = (z > 0) ? -nxy : (nz - 1) * nxy, ozp = (z < nz - 1) ? nxy : -(nz - 1) * nxy;
+                const int kzm = (z > 0) ? 0 : bc4, kzp = (z < nz - 1) ? 0 : bc5;
+                // Loads are issued for every lane, a solid lane reading the first element of the
+                // array (one shared line) instead of branching around each load.
+                const unsigned long long lwr = s.lw[fl ? cell_off + cell : 0];
+                const unsigned long long lwv = fl ? lwr : 0ull;
+                const unsigned lmask = (unsigned)lwv & 0x3ffffu;
+                // storage slot of this node: the node itself, or its rank in the plane's list
+                // (as an offset from the node that the compiler cannot see through: it keeps
+                // the register allocation of the node-layout kernel, which has no spills)
+                int dlt = compact ? me0 - cell : 0;
+                if (compact) asm volatile("" : "+v"(dlt));
+                const int me = cell + dlt;
+                // compact storage: slots of the sources from the row tables of the 9 source rows
+                // (y - c_y, z - c_z).  Along a row the listed nodes hold consecutive slots, so
+                // the source x - 1 sits one slot below the node's rank in that row and x + 1
+                // one above it (plus one when x itself is listed); a source across a periodic
+                // x face reads the table word at the other end of the row.
+                int src[kQ - 1];
+                if (compact) {
+                    const uint2 *rtab = s.rt + uni(M->rt_off);
+                    const int nw = uni(M->nw), per_x = uni(M->per[0]);
+                    const unsigned b = 1u << (i & 31);
+                    const int wx = (i == 0) ? nx - 1 : 0;
+                    const unsigned bw = 1u << (wx & 31);
+                    uint2 wv[9], ww[9];
+    #pragma unroll
+                    for (int r = 0; r < 9; ++r) {
+                        const int jj = wrapc(j + r / 3 - 1, ny), zz = wrapc(z + r % 3 - 1, nz);
+                        const long long row = ((long long)zz * ny + jj) * nw;
+                        wv[r] = rtab[row + (i >> 5)];
+                        ww[r] = per_x ? rtab[row + (wx >> 5)] : make_uint2(0u, 0u);
+                    }
+    #pragma unroll
+                    for (int e = 0; e < kQ - 1; ++e) {
+                        const int r = (1 - kCY[e]) * 3 + (1 - kCZ[e]);
+                        const int zb = wrapc(z - kCZ[e], nz) * nxy;
+                        const int rk = zb + (int)wv[r].y + __popc(wv[r].x & (b - 1u));
+                        const int rwr = zb + (int)ww[r].y + __popc(ww[r].x & (bw - 1u));
+                        int v;
+                        if (kCX[e] == 0) v = rk;
+                        else if (kCX[e] < 0) v = (i < nx - 1) ? rk + ((wv[r].x & b) ? 1 : 0) : rwr;
+                        else v = (i > 0) ? rk - 1 : rwr;
+                        src[e] = max(v, 0);
+                    }
                 }
-#pragma unroll
+                C f[kQ];
+                S raw[kQ];
+                unsigned unk = 0u;
+    #pragma unroll
                 for (int e = 0; e < kQ - 1; ++e) {
-                    const int r = (1 - kCY[e]) * 3 + (1 - kCZ[e]);
-                    const int zb = wrapc(z - kCZ[e], nz) * nxy;
-                    const int rk = zb + (int)wv[r].y + __popc(wv[r].x & (b - 1u));
-                    const int rwr = zb + (int)ww[r].y + __popc(ww[r].x & (bw - 1u));
-                    int v;
-                    if (kCX[e] == 0) v = rk;
-                    else if (kCX[e] < 0) v = (i < nx - 1) ? rk + ((wv[r].x & b) ? 1 : 0) : rwr;
-                    else v = (i > 0) ? rk - 1 : rwr;
-                    src[e] = max(v, 0);
+                    int off = 0, kind = 0;
+                    if (kCX[e] > 0) { off += oxm; kind = max(kind, kxm); } else if (kCX[e] < 0) { off += oxp; kind = max(kind, kxp); }
+                    if (kCY[e] > 0) { off += oym; kind = max(kind, kym); } else if (kCY[e] < 0) { off += oyp; kind = max(kind, kyp); }
+                    if (kCZ[e] > 0) { off += ozm; kind = max(kind, kzm); } else if (kCZ[e] < 0) { off += ozp; kind = max(kind, kzp); }
+                    // f_e(x, t+1) = f~_e(x - c_e, t); from a wall or a particle the population
+                    // comes back from this node, f~_{e*}(x, t); across a density face it is unknown
+                    const bool back = (kind != 0) || ((lmask >> e) & 1u);
+                    const unsigned idx = back ? (unsigned)(kOPP[e] * nc) + (unsigned)me
+                                              : (unsigned)(e * nc) + (unsigned)(compact ? src[e] : cell + off);
+                    raw[e] = ldo(A, fl ? idx : 0u);
+                    unk |= (kind == BC_PRESSURE) ? (1u << e) : 0u;
+                }
+                raw[18] = ldo(A, fl ? (unsigned)(18 * nc) + (unsigned)me : 0u);
+                // every load is in flight before the first use (no branch between them)
+                asm volatile("" : "+v"(raw[0]), "+v"(raw[1]), "+v"(raw[2]), "+v"(raw[3]), "+v"(raw[4]), "+v"(raw[5]),
+                                  "+v"(raw[6]), "+v"(raw[7]), "+v"(raw[8]), "+v"(raw[9]), "+v"(raw[10]), "+v"(raw[11]),
+                                  "+v"(raw[12]), "+v"(raw[13]), "+v"(raw[14]), "+v"(raw[15]), "+v"(raw[16]),
+                                  "+v"(raw[17]), "+v"(raw[18]));
+                // the arithmetic works on deviations f_d - w_d rho_f from the rest state: Eqs.
+                // (stream), (mem) and the density faces are affine with the same coefficients
+                // for f and its deviation (w_d = w_{d*}; the weights of each Zou-He closure sum
+                // to one), and the deviations keep the small density and momentum signals
+                // clear of the rounding of the O(1) rest populations
+    #pragma unroll
+                for (int e = 0; e < kQ; ++e)
+                    f[e] = (fl && !((unk >> e) & 1u)) ? decode_dev<P>(raw[e], e, rho_fd) : C(0);
+                if (lmask != 0u) moving_wall<C>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell, cell_off + me);
+
+                if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, drho_in, false);
+                if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, C(0), true);
+
+                C drho, jx, jy, jz;
+                moments<C>(f, drho, jx, jy, jz);
+                const C rho = (C)rho_fd + drho;
+                if (fl) {
+                    pr0 = 1.0;
+                    pr1 = (double)drho;
+                    pr2 = (double)jz;
+                    pr3 = rho_fd + (double)drho;
+                }
+                const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
+                const C uu = ux * ux + uy * uy + uz * uz;
+    #pragma unroll
+                for (int d = 0; d < kQ; ++d) {
+                    const C fe = feq_dev<C>(d, drho, rho, ux, uy, uz, uu);
+                    store_dev<P>(B, (unsigned)(d * nc) + (unsigned)me, d, f[d] + omega * (fe - f[d]), rho_fd);
                 }
             }
-            C f[kQ];
-            S raw[kQ];
-            unsigned unk = 0u;
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e) {
-                int off = 0, kind = 0;
-                if (kCX[e] > 0) { off += oxm; kind = max(kind, kxm); } else if (kCX[e] < 0) { off += oxp; kind = max(kind, kxp); }
-                if (kCY[e] > 0) { off += oym; kind = max(kind, kym); } else if (kCY[e] < 0) { off += oyp; kind = max(kind, kyp); }
-                if (kCZ[e] > 0) { off += ozm; kind = max(kind, kzm); } else if (kCZ[e] < 0) { off += ozp; kind = max(kind, kzp); }
-                // f_e(x, t+1) = f~_e(x - c_e, t); from a wall or a particle the population
-                // comes back from this node, f~_{e*}(x, t); across a density face it is unknown
-                const bool back = (kind != 0) || ((lmask >> e) & 1u);
-                const unsigned idx = back ? (unsigned)(kOPP[e] * nc) + (unsigned)me
-                                          : (unsigned)(e * nc) + (unsigned)(compact ? src[e] : cell + off);
-                raw[e] = ldo(A, fl ? idx : 0u);
-                unk |= (kind == BC_PRESSURE) ? (1u << e) : 0u;
-            }
-            raw[18] = ldo(A, fl ? (unsigned)(18 * nc) + (unsigned)me : 0u);
-            // every load is in flight before the first use (no branch between them)
-            asm volatile("" : "+v"(raw[0]), "+v"(raw[1]), "+v"(raw[2]), "+v"(raw[3]), "+v"(raw[4]), "+v"(raw[5]),
-                              "+v"(raw[6]), "+v"(raw[7]), "+v"(raw[8]), "+v"(raw[9]), "+v"(raw[10]), "+v"(raw[11]),
-                              "+v"(raw[12]), "+v"(raw[13]), "+v"(raw[14]), "+v"(raw[15]), "+v"(raw[16]),
-                              "+v"(raw[17]), "+v"(raw[18]));
-            // the arithmetic works on deviations f_d - w_d rho_f from the rest state: Eqs.
-            // (stream), (mem) and the density faces are affine with the same coefficients
-            // for f and its deviation (w_d = w_{d*}; the weights of each Zou-He closure sum
-            // to one), and the deviations keep the small density and momentum signals
-            // clear of the rounding of the O(1) rest populations
-#pragma unroll
-            for (int e = 0; e < kQ; ++e)
-                f[e] = (fl && !((unk >> e) & 1u)) ? decode_dev<P>(raw[e], e, rho_fd) : C(0);
-            if (lmask != 0u) moving_wall<C>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell, cell_off + me);
-
-            if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, drho_in, false);
-            if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, C(0), true);
-
-            C drho, jx, jy, jz;
-            moments<C>(f, drho, jx, jy, jz);
-            const C rho = (C)rho_fd + drho;
-            if (fl) {
-                pr0 = 1.0;
-                pr1 = (double)drho;
-                pr2 = (double)jz;
-                pr3 = rho_fd + (double)drho;
-            }
-            const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
-            const C uu = ux * ux + uy * uy + uz * uz;
-#pragma unroll
-            for (int d = 0; d < kQ; ++d) {
-                const C fe = feq_dev<C>(d, drho, rho, ux, uy, uz, uu);
-                store_dev<P>(B, (unsigned)(d * nc) + (unsigned)me, d, f[d] + omega * (fe - f[d]), rho_fd);
+            const int pidx = s.pzmap[pz_off + z];
+            if (pidx >= 0) {
+                double v[4] = {pr0, pr1, pr2, pr3};
+                block_sum<4>(v, red);
+                if (threadIdx.x == 0) {
+                    double *o = s.pprt + ((long long)g * s.nzt + (z - z0)) * 4;
+                    if (accum) { o[0] += v[0]; o[1] += v[1]; o[2] += v[2]; o[3] += v[3]; }
+                    else { o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3]; }
+                }
             }
         }
-        const int pidx = s.pzmap[pz_off + z];
-        if (pidx >= 0) {
-            double v[4] = {pr0, pr1, pr2, pr3};
-            block_sum<4>(v, red);
-            if (threadIdx.x == 0) {
-                double *o = s.pprt + ((long long)g * s.nzt + (z - z0)) * 4;
-                o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+    };
+
+    if (lists) {
+        // workgroup = 256 consecutive listed nodes of one z plane; a plane with more than
+        // ntx * 256 listed nodes gives each of its workgroups further chunks, ntx apart
+        const int lb = tl % ntx, z = tl / ntx;
+        const int cnt = s.ccnt[pz_off + z];
+        if (lb * 256 >= cnt) {
+            if (s.pzmap[pz_off + z] >= 0 && threadIdx.x == 0) {
+                double *o = s.pprt + (long long)g * s.nzt * 4;
+                o[0] = 0.0; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0;
             }
+            return;
         }
+        for (int lbx = lb; lbx * 256 < cnt; lbx += ntx) {
+            const int kk = lbx * 256 + (int)threadIdx.x;
+            const bool v = kk < cnt;
+            const int c = v ? s.clist[cell_off + (long long)z * nxy + kk] - z * nxy : 0;
+            const int jj = c / nx;
+            // the node's slot under compact storage
+            run(c - jj * nx, jj, z, z + 1, z * nxy + kk, v, lbx != lb);
+        }
+    } else {
+        const int bxl = uni(M->bx_log2);
+        const int lx = threadIdx.x & ((1 << bxl) - 1), ly = threadIdx.x >> bxl;
+        const int tx = tl % ntx, trem = tl / ntx, ty = trem % nty, tz = trem / nty;
+        const int i = (tx << bxl) + lx;
+        const int j = ty * uni(M->by) + ly;
+        const int z0 = tz * s.nzt;
+        run(i, j, z0, min(z0 + s.nzt, nz), 0, (i < nx) && (j < ny), false);
     }
 }
 
@@ -1098,7 +1104,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
             if (has) {
                 const int at = cntx + __popcll(bal & ((1ull << lane) - 1ull));
                 const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
-                xc[at] = cell | (slot << 30);
+                xc[at] = (int)((unsigned)cell | ((unsigned)slot << 30));
                 xs[at] = node_slot(s, M, cell, rem - jj * nx, jj, kk);
             }
             cntx += __popcll(bal);
@@ -1128,24 +1134,27 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     };
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int base = 0; base < cntx; base += kLinksBlock * kLinkBatch) {
-        int ent[kLinkBatch], at[kLinkBatch];
+        // an entry is cell | slot << 30: slots 2 and 3 set the sign bit, so validity is
+        // kept apart from the entry's value
+        unsigned ent[kLinkBatch];
+        int at[kLinkBatch];
+        bool val[kLinkBatch];
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b) {
             const int k = base + b * kLinksBlock + lane;
-            ent[b] = (k < cntx) ? xc[k] : -1;
-            at[b] = (k < cntx) ? xs[k] : 0;
+            val[b] = k < cntx;
+            ent[b] = val[b] ? (unsigned)xc[k] : 0u;
+            at[b] = val[b] ? xs[k] : 0;
         }
         double D[kLinkBatch][3];
         unsigned grp[kLinkBatch];
 #pragma unroll
-        for (int b = 0; b < kLinkBatch; ++b) {
-            const int sl = ent[b] < 0 ? 0 : (int)((unsigned)ent[b] >> 30);
-            read_rec(sl, ent[b] < 0 ? 0 : max(at[b], 0), D[b][0], D[b][1], D[b][2], grp[b]);
-        }
+        for (int b = 0; b < kLinkBatch; ++b)
+            read_rec((int)(ent[b] >> 30), max(at[b], 0), D[b][0], D[b][1], D[b][2], grp[b]);
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b) {
-            if (ent[b] < 0) continue;
-            const int cell = ent[b] & 0x3fffffff;
+            if (!val[b]) continue;
+            const int cell = (int)(ent[b] & 0x3fffffffu);
             const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx, ii = rem - jj * nx;
             const double r0 = mimg((double)ii - X0, per0, box0);
             const double r1 = mimg((double)jj - X1, per1, box1);

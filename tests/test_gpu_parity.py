@@ -157,6 +157,27 @@ def test_coupled_moving_sphere_with_conversions_fp64(node_lists):
         assert gs.status() & 0x192 == 0
 
 
+def test_compact_planes_beyond_the_grid_estimate_fp64():
+    """Three heavily overlapping large spheres: the fluid grid's estimate (sphere
+    cross-sections summed, overlaps counted twice) leaves one workgroup per plane, so
+    every plane's second chunk of listed nodes is done by a further pass of the same
+    workgroup; the state and the probe sums still match the oracle."""
+    params = dict(nx=32, ny=32, nz=12, tau=0.9, bc=(0, 0, 0, 0, 1, 1), rho_p=1.5, E=1e-9, max_particles=3,
+                  max_radius=14.0, probe_z=[2, 6, 9])
+    pk = {"x": np.array([[15.6, 16.2, 5.5], [16.4, 15.7, 5.9], [16.0, 16.5, 5.2]]),
+          "radius": np.array([13.5, 13.2, 13.4]),
+          "v": np.array([[0.01, -0.004, 0.002], [-0.006, 0.008, -0.003], [0.002, 0.003, 0.004]])}
+    s = _oracle(params, pk)
+    with _gpu_set([params], graph_steps=4, node_lists=2) as gs:
+        _set_particles(gs, 0, pk)
+        gs.step(24)
+        s.step(24)
+        _compare_state(gs, 0, s, pk)
+        pg, po = gs.probes(0, 0, 24), s.probes()
+        assert np.abs(pg - po).max() <= 1e-12 * np.abs(po).max()
+        assert gs.status() & 0x1da == 0
+
+
 @pytest.mark.parametrize("margin", [0, 2])
 def test_moving_sphere_parked_refills_fp64(margin):
     """Compact storage with the list rebuild trigger's look-ahead switched off: nodes turn
