@@ -69,7 +69,9 @@ extern "C" {
 #define LBDEM_STATUS_NEAR_OVERFLOW 0x2u      /* a particle had more near neighbours than the table holds (error) */
 #define LBDEM_STATUS_CHANGE_OVERFLOW 0x4u    /* node-change list spilled; a full map copy was used (results valid) */
 #define LBDEM_STATUS_HISTORY_OVERFLOW 0x8u   /* tangential contact history table full (error) */
-#define LBDEM_STATUS_TOO_FAST 0x10u          /* a particle moved more than 0.25 lu in one step (error) */
+#define LBDEM_STATUS_TOO_FAST 0x10u          /* a particle moved more than 0.25 lu in one step, its state became
+                                                non-finite, or its centre left a bounded axis (error; the particle
+                                                is then held to 0.25 lu per step and inside the lattice) */
 #define LBDEM_STATUS_SHELL_OVERFLOW 0x40u    /* a particle's surface-shell table overflowed (error) */
 #define LBDEM_STATUS_LINK_OVERFLOW 0x80u     /* a fluid node had links to more than four particles (error) */
 #define LBDEM_STATUS_LIST_MISS 0x100u        /* compact storage: more than 16384 refills awaited a list rebuild (error) */

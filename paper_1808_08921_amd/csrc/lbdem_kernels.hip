@@ -1334,16 +1334,27 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
             for (int a = 0; a < 3; ++a) {
                 const double Ft = (Fh[a] + s.Fg[3 * p + a]) + con[a];
                 const double Tt = Th[a] + con[3 + a];
-                const double v = Vo[3 * p + a] + Ft / mass;
+                double v = Vo[3 * p + a] + Ft / mass;
+                double w = Wo[3 * p + a] + Tt / inert;
+                // a step beyond 0.25 lu (or a non-finite state) is an error (status 0x10);
+                // the particle is then held to that step and inside the lattice, so that
+                // every index derived from its position stays in range
+                if (!(fabs(v) <= 0.25) || !isfinite(w)) {
+                    atomicOr(s.flags, 0x10u);
+                    if (!isfinite(v) || !isfinite(w)) { v = 0.0; w = 0.0; }
+                    else v = fmin(fmax(v, -0.25), 0.25);
+                }
                 Vn[3 * p + a] = v;
-                Wn[3 * p + a] = Wo[3 * p + a] + Tt / inert;
+                Wn[3 * p + a] = w;
                 double x = Xc[a] + v;
                 if (per[a]) {
                     if (x >= box[a]) x -= box[a];
                     else if (x < 0.0) x += box[a];
+                } else {
+                    if (x < 0.0 || x > box[a] - 1.0) atomicOr(s.flags, 0x10u);
+                    x = fmin(fmax(x, 0.0), box[a] - 1.0);
                 }
                 Xn[3 * p + a] = x;
-                if (fabs(v) > 0.25) atomicOr(s.flags, 0x10u);
             }
         }
         pack_state(s.pf[par ^ 1] + 12 * p, Xn + 3 * p, Vn + 3 * p, Wn + 3 * p);
@@ -1552,19 +1563,8 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             }
 #pragma unroll
             for (int e = 0; e < kQ - 1; ++e) ow[e] = nbc[e] >= 0 ? cur[nbc[e]] : -1;
-            // links of the old and new owner and of the neighbours' owners can change, at
-            // list nodes of the z-slabs within one plane of this node
-            mark_dirty(s, M, was, kk, t);
-            mark_dirty(s, M, best, kk, t);
-            int m1 = -1, m2 = -1;
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e) {
-                const int q = ow[e];
-                if (q < 0 || q == was || q == best || q == m1 || q == m2) continue;
-                mark_dirty(s, M, q, kk, t);
-                m2 = m1;
-                m1 = q;
-            }
+            // (the cached link entries that this change makes stale are marked by the next
+            // refresh, which sees which link words actually change)
             const int slot = atomicAdd(s.chgcnt + par, 1);
             if (slot < s.chg_cap) {
                 s.chg[par][2 * slot] = (int)(M->cell_off + cell);
@@ -1693,7 +1693,11 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                     int ii = lo[0] + idx % ext[0];
                     int jj = lo[1] + (idx / ext[0]) % ext[1];
                     int kk = lo[2] + idx / (ext[0] * ext[1]);
-                    ii = wrapc(ii, dims[0]); jj = wrapc(jj, dims[1]); kk = wrapc(kk, dims[2]);
+                    // (positions stay within one period of the lattice, so one wrap suffices;
+                    // a true modulo keeps every index in range regardless)
+                    ii = ((ii % dims[0]) + dims[0]) % dims[0];
+                    jj = ((jj % dims[1]) + dims[1]) % dims[1];
+                    kk = ((kk % dims[2]) + dims[2]) % dims[2];
                     cell = (kk * dims[1] + jj) * dims[0] + ii;
                     const double d2n = dist2h(ii, jj, kk, X[0], X[1], X[2]);
                     bool ev;
