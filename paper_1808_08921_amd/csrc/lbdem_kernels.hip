@@ -1365,27 +1365,48 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
 // ---------------------------------------------------------------------------
 // re-projection kernel
 // ---------------------------------------------------------------------------
+// Per-particle context of the re-projection: the particle, its lattice, its position
+// after this step's motion (mode 0) or now (mode 1), and its near neighbours (staged in
+// the workgroup's shared memory, slot w).
+struct RemapCtx {
+    int p, w, nn;
+    const MemberDev *M;
+    double X[3], R, R2;
+    int per[3];
+    double box[3];
+};
+
+constexpr int kRemapWaves = 4; // particles per workgroup of the re-projection kernel
+
+// Re-projection (Sec. 2.3), one wave per particle for the common case: the candidates of
+// a small step, from the particle's surface band or shell list, evaluated by the wave's
+// 64 lanes.  A particle that needs its shell list rebuilt (set-up, or motion beyond the
+// shell) and the periodic near-list build use the whole workgroup, one particle after the
+// other.  Workgroups past the particles reduce the probe planes.
 template <int P>
 __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
 {
     using S = typename Prec<P>::S;
     __shared__ double red[4][8];
-    __shared__ double nb[kNearCap][4];
-    __shared__ int nbid[kNearCap];
+    __shared__ double nbw[kRemapWaves][kNearCap][4];
+    __shared__ int nbidw[kRemapWaves][kNearCap];
     __shared__ int cnt4[4];
     __shared__ int cstart[kChunks + 1];
+    __shared__ double accw[kRemapWaves][6];
+    __shared__ double ctxw[kRemapWaves][9]; // x, x_ref unwrapped next to x, lr, dr, overlap depth
+    __shared__ int flagw[kRemapWaves];
     // the step being completed: copied by the fluid kernel (mode 0); the counter itself is
     // advanced here and read by no workgroup of this kernel
     const long long t = (mode == 0) ? *s.tcopy : *s.tstep;
     const int par = (int)(t & 1);
-    const int tid = threadIdx.x;
-    const int p = blockIdx.x;
-    if (mode == 0 && p == 0 && tid == 0) *s.tstep = t + 1;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int npw = (s.ptot + kRemapWaves - 1) / kRemapWaves;
+    if (mode == 0 && blockIdx.x == 0 && tid == 0) *s.tstep = t + 1;
 
-    if (p >= s.ptot) {
+    if ((int)blockIdx.x >= npw) {
         // probe plane reduction, one workgroup per (lattice, probe), tiles in fixed order
         if (mode != 0) return;
-        const int q = p - s.ptot;
+        const int q = blockIdx.x - npw;
         if (q >= s.nprobe_total) return;
         int m = 0;
         while (m + 1 < s.nmem && s.mem[m + 1].plist_off <= q) ++m;
@@ -1409,15 +1430,171 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
         return;
     }
 
+    const int sp = (mode == 1) ? par : (par ^ 1); // buffers of the positions after the motion
+    const double *Xs = s.X[sp], *Vs = s.V[sp], *Ws = s.W[sp];
+    const int sn = par ^ 1;                       // population buffer holding f~(t+1)
+
+    auto dist2c = [&](const RemapCtx &c, int i, int j, int k, double X0, double X1, double X2) {
+        const double dx = mimg((double)i - X0, c.per[0], c.box[0]);
+        const double dy = mimg((double)j - X1, c.per[1], c.box[1]);
+        const double dz = mimg((double)k - X2, c.per[2], c.box[2]);
+        return (dx * dx + dy * dy) + dz * dz;
+    };
+
+    // owner of one node after the motion; conversions of covered / uncovered nodes
+    auto evaluate = [&](const RemapCtx &c, int ii, int jj, int kk, int cell, double d2n, int was_pre,
+                        double (&acc)[6], int &conv) {
+        const MemberDev *M = c.M;
+        const int p = c.p;
+        const int dims[3] = {M->nx, M->ny, M->nz};
+        const int *cur = s.own[par] + M->cell_off;
+        // owner: smallest d^2, then smallest index, among the spheres containing the node
+        int best = -1;
+        double bd = 0.0;
+        if (d2n <= c.R2) { best = p; bd = d2n; }
+        for (int k = 0; k < c.nn; ++k) {
+            const double dq = dist2c(c, ii, jj, kk, nbw[c.w][k][0], nbw[c.w][k][1], nbw[c.w][k][2]);
+            if (dq <= nbw[c.w][k][3] * nbw[c.w][k][3]) {
+                const int q = nbidw[c.w][k];
+                if (best < 0 || dq < bd || (dq == bd && q < best)) { best = q; bd = dq; }
+            }
+        }
+        if (mode == 1) {
+            if (best >= 0) { s.own[0][M->cell_off + cell] = best; s.own[1][M->cell_off + cell] = best; }
+            return;
+        }
+        const int was = (was_pre >= -1) ? was_pre : cur[cell];
+        if (best == was) return;
+        s.own[par ^ 1][M->cell_off + cell] = best;
+        // the 18 neighbours and their owners before the re-projection (loads together)
+        int nbc[kQ - 1], ow[kQ - 1];
+#pragma unroll
+        for (int e = 0; e < kQ - 1; ++e) {
+            int cc[3] = {ii + kCX[e], jj + kCY[e], kk + kCZ[e]};
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+                if (cc[a] < 0 || cc[a] >= dims[a]) {
+                    if (c.per[a]) cc[a] = cc[a] < 0 ? cc[a] + dims[a] : cc[a] - dims[a];
+                    else ok = false;
+                }
+            }
+            nbc[e] = ok ? (cc[2] * dims[1] + cc[1]) * dims[0] + cc[0] : -1;
+        }
+#pragma unroll
+        for (int e = 0; e < kQ - 1; ++e) ow[e] = nbc[e] >= 0 ? cur[nbc[e]] : -1;
+        // (the cached link entries that this change makes stale are marked by the next
+        // refresh, which sees which link words actually change)
+        const int slot = atomicAdd(s.chgcnt + par, 1);
+        if (slot < s.chg_cap) {
+            s.chg[par][2 * slot] = (int)(M->cell_off + cell);
+            s.chg[par][2 * slot + 1] = best;
+        } else {
+            atomicOr(s.flags, 0x4u);
+        }
+        const double r0 = mimg((double)ii - c.X[0], c.per[0], c.box[0]);
+        const double r1 = mimg((double)jj - c.X[1], c.per[1], c.box[1]);
+        const double r2 = mimg((double)kk - c.X[2], c.per[2], c.box[2]);
+        S *Bn = (S *)(sn ? s.popB : s.popA) + M->pop_off;
+        const int nc = (int)M->ncell;
+        const float rho_ff = (float)M->rho_f;
+        if (was < 0 && best == p) {
+            // Eq. (convertFS): a covered node hands its momentum to the particle
+            const int sl = node_slot(s, M, cell, ii, jj, kk);
+            if (sl < 0) { atomicOr(s.flags, 0x100u); return; }
+            double f[kQ];
+#pragma unroll
+            for (int d = 0; d < kQ; ++d) f[d] = (double)ld<P>(Bn, d * nc + sl, d, rho_ff);
+            double rho, j0, j1, j2;
+            moments<double>(f, rho, j0, j1, j2);
+            conv = 1;
+            acc[0] += j0; acc[1] += j1; acc[2] += j2;
+            acc[3] += r1 * j2 - r2 * j1;
+            acc[4] += r2 * j0 - r0 * j2;
+            acc[5] += r0 * j1 - r1 * j0;
+        } else if (was == p && best < 0) {
+            // Eq. (convertSF): an uncovered node is refilled with f^eq(rho_bar, V_b)
+            // and takes rho_bar V_b from the particle; rho_bar averages the
+            // neighbours that are fluid before and after the re-projection.  Under
+            // compact storage a node outside the lists has its refill parked for the
+            // list rebuild at the start of the next step.
+            unsigned use = 0u;
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                if (nbc[e] < 0 || ow[e] >= 0) continue;
+                const int yc = nbc[e];
+                const int zc = yc / (dims[0] * dims[1]), rc = yc - zc * dims[0] * dims[1];
+                const int yy = rc / dims[0], xx = rc - yy * dims[0];
+                bool inside = dist2c(c, xx, yy, zc, c.X[0], c.X[1], c.X[2]) <= c.R2;
+                for (int k = 0; k < c.nn && !inside; ++k)
+                    inside = dist2c(c, xx, yy, zc, nbw[c.w][k][0], nbw[c.w][k][1], nbw[c.w][k][2]) <=
+                             nbw[c.w][k][3] * nbw[c.w][k][3];
+                if (!inside) use |= 1u << e;
+            }
+            const int sl = node_slot(s, M, cell, ii, jj, kk);
+            double sum = 0.0;
+            int cnt = 0;
+#pragma unroll 1
+            for (int e = 0; e < kQ - 1; ++e) {
+                if (!((use >> e) & 1u)) continue;
+                int yc = 0;
+#pragma unroll
+                for (int q = 0; q < kQ - 1; ++q)
+                    if (q == e) yc = nbc[q];
+                if (s.compact) {
+                    const int zc = yc / (dims[0] * dims[1]), rc = yc - zc * dims[0] * dims[1];
+                    const int yy = rc / dims[0];
+                    yc = slot_of(s, M, rc - yy * dims[0], yy, zc);
+                    if (yc < 0) { atomicOr(s.flags, 0x100u); continue; }
+                }
+                double rr = 0.0;
+                for (int d = 0; d < kQ; ++d) rr += (double)ld<P>(Bn, d * nc + yc, d, rho_ff);
+                sum += rr;
+                cnt += 1;
+            }
+            const double rbar = cnt > 0 ? sum / cnt : M->rho_f;
+            const double *Vp = Vs + 3 * p, *Wp = Ws + 3 * p;
+            const double vb0 = Vp[0] + (Wp[1] * r2 - Wp[2] * r1);
+            const double vb1 = Vp[1] + (Wp[2] * r0 - Wp[0] * r2);
+            const double vb2 = Vp[2] + (Wp[0] * r1 - Wp[1] * r0);
+            const double uu = vb0 * vb0 + vb1 * vb1 + vb2 * vb2;
+            if (sl >= 0) {
+#pragma unroll
+                for (int d = 0; d < kQ; ++d)
+                    st<P>(Bn, d * nc + sl, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
+            } else {
+                const int pi = atomicAdd(s.pcnt + par, 1);
+                if (pi < kPendCap) {
+                    double *rec = s.pbuf[par] + 4 * pi;
+                    rec[0] = rbar; rec[1] = vb0; rec[2] = vb1; rec[3] = vb2;
+                    s.pend[M->cell_off + cell] = pi;
+                    *s.relist_at = t + 1;
+                    atomicOr(s.flags, 0x200u);
+                } else {
+                    atomicOr(s.flags, 0x100u);
+                }
+            }
+            conv = 1;
+            const double m0 = rbar * vb0, m1 = rbar * vb1, m2 = rbar * vb2;
+            acc[0] -= m0; acc[1] -= m1; acc[2] -= m2;
+            acc[3] -= r1 * m2 - r2 * m1;
+            acc[4] -= r2 * m0 - r0 * m2;
+            acc[5] -= r0 * m1 - r1 * m0;
+        }
+    };
+
+    // ------------------------------------------------------------------------------
+    // phase A: one wave per particle
+    // ------------------------------------------------------------------------------
+    const int p = blockIdx.x * kRemapWaves + wv;
     // Per-particle values that depend on nothing else are loaded together, before any
-    // branch (index clamped for the probe workgroups): the member, the near list, the
-    // reference state and the first band entries of each thread, and p's position in both
-    // buffers (the parity comes from the step counter, read in the same round).
+    // branch (index clamped past the particles): the member, the near list, the reference
+    // state, the first band entries of each lane, and p's position in both buffers.
+    constexpr int kPre = 4; // band entries preloaded per lane
     bool active = p < s.ptot;
     const int pc = active ? p : 0;
     const int m = s.pmem[pc];
     const int nn_raw = s.nnear[pc];
-    const int q_raw = s.nearl[(long long)pc * kNearCap + (tid & (kNearCap - 1))];
+    const int q_raw = s.nearl[(long long)pc * kNearCap + (lane & (kNearCap - 1))];
     const double Rp = s.R[pc];
     const double Xr_ld[3] = {s.Xref[3 * pc], s.Xref[3 * pc + 1], s.Xref[3 * pc + 2]};
     const double Xb0[3] = {s.X[0][3 * pc], s.X[0][3 * pc + 1], s.X[0][3 * pc + 2]};
@@ -1426,58 +1603,67 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
     const double mg_ld = s.margin[pc], rdisp_ld = s.rdisp[pc], rlens_ld = s.rlens[pc];
     const long long nat_ld = s.near_at[pc];
     const int bnum = min(s.bcnt[pc], s.bcap);
-    const bool spec = tid < bnum;
-    const int bcell0 = spec ? s.bcell[(long long)pc * s.bcap + tid] : 0;
-    const float bdr0 = spec ? s.bdr[(long long)pc * s.bcap + tid] : 0.0f;
-    const MemberDev *M = nullptr;
-    if (active) {
-        M = s.mem + m;
-        active = (p - M->p_off < M->np) && (only < 0 || m == only);
+    int bc[kPre];
+    float bd[kPre];
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+        const int k = lane + 64 * i;
+        bc[i] = (k < bnum) ? s.bcell[(long long)pc * s.bcap + k] : 0;
+        bd[i] = (k < bnum) ? s.bdr[(long long)pc * s.bcap + k] : 0.0f;
     }
+    const MemberDev *Mp = nullptr;
     if (active) {
-        // the lattice's periodicity and extents, held in registers for the distance loops
-        const int perh[3] = {uni(M->per[0]), uni(M->per[1]), uni(M->per[2])};
-        const double boxh[3] = {uni(M->box[0]), uni(M->box[1]), uni(M->box[2])};
-        auto dist2h = [&](int i, int j, int k, double X0, double X1, double X2) {
-            const double dx = mimg((double)i - X0, perh[0], boxh[0]);
-            const double dy = mimg((double)j - X1, perh[1], boxh[1]);
-            const double dz = mimg((double)k - X2, perh[2], boxh[2]);
-            return (dx * dx + dy * dy) + dz * dz;
-        };
-        // positions after this step's motion (mode 0) or the current ones (mode 1)
-        const int sp = (mode == 1) ? par : (par ^ 1);
-        const double *Xs = s.X[sp], *Vs = s.V[sp], *Ws = s.W[sp];
-        const double X[3] = {sp ? Xb1[0] : Xb0[0], sp ? Xb1[1] : Xb0[1], sp ? Xb1[2] : Xb0[2]};
-        const double R = Rp, R2 = R * R;
-        const double Xr[3] = {mode == 1 ? X[0] : Xr_ld[0], mode == 1 ? X[1] : Xr_ld[1], mode == 1 ? X[2] : Xr_ld[2]};
-        const int nn = min(nn_raw, kNearCap);
-        if (tid < nn) {
-            const int q = q_raw;
-            nbid[tid] = q;
-            nb[tid][0] = Xs[3 * q]; nb[tid][1] = Xs[3 * q + 1]; nb[tid][2] = Xs[3 * q + 2];
-            nb[tid][3] = s.R[q];
-        }
-        // owner of this thread's first band entry (the candidates of a small step)
-        const int *cur = s.own[par] + M->cell_off;
-        const int was0 = spec ? cur[bcell0] : -1;
-        __syncthreads();
-        double dmax = 0.0, disp2 = 0.0;
-        for (int k = 0; k < nn; ++k) {
-            const double d0 = mimg(nb[k][0] - X[0], perh[0], boxh[0]);
-            const double d1 = mimg(nb[k][1] - X[1], perh[1], boxh[1]);
-            const double d2 = mimg(nb[k][2] - X[2], perh[2], boxh[2]);
-            dmax = fmax(dmax, R + nb[k][3] - sqrt((d0 * d0 + d1 * d1) + d2 * d2));
-        }
-        double xr[3];
+        Mp = s.mem + m;
+        active = (p - Mp->p_off < Mp->np) && (only < 0 || m == only);
+    }
+    int flag = 0; // 1 active, 2 shell rebuild, 4 near-list build
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    int conv = 0;
+    if (active) {
+        RemapCtx c;
+        c.p = p; c.w = wv; c.M = Mp;
         for (int a = 0; a < 3; ++a) {
-            const double d = mimg(X[a] - Xr[a], perh[a], boxh[a]);
+            c.per[a] = Mp->per[a];
+            c.box[a] = Mp->box[a];
+            c.X[a] = sp ? Xb1[a] : Xb0[a];
+        }
+        c.R = Rp; c.R2 = Rp * Rp;
+        c.nn = min(nn_raw, kNearCap);
+        const double Xr[3] = {mode == 1 ? c.X[0] : Xr_ld[0], mode == 1 ? c.X[1] : Xr_ld[1], mode == 1 ? c.X[2] : Xr_ld[2]};
+        if (lane < c.nn) {
+            const int q = q_raw;
+            nbidw[wv][lane] = q;
+            nbw[wv][lane][0] = Xs[3 * q]; nbw[wv][lane][1] = Xs[3 * q + 1]; nbw[wv][lane][2] = Xs[3 * q + 2];
+            nbw[wv][lane][3] = s.R[q];
+        }
+        // owners of the preloaded band entries (the candidates of a small step)
+        const int *cur = s.own[par] + Mp->cell_off;
+        int was[kPre];
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) was[i] = (lane + 64 * i < bnum) ? cur[bc[i]] : -1;
+        // the wave's staged neighbours are visible to all its lanes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // overlap depth with the near neighbours (one lane each), maximum over the wave
+        double dmax = 0.0;
+        if (lane < c.nn) {
+            const double d0 = mimg(nbw[wv][lane][0] - c.X[0], c.per[0], c.box[0]);
+            const double d1 = mimg(nbw[wv][lane][1] - c.X[1], c.per[1], c.box[1]);
+            const double d2 = mimg(nbw[wv][lane][2] - c.X[2], c.per[2], c.box[2]);
+            dmax = fmax(0.0, c.R + nbw[wv][lane][3] - sqrt((d0 * d0 + d1 * d1) + d2 * d2));
+        }
+        for (int off = 32; off >= 1; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+        double disp2 = 0.0, xr[3];
+        for (int a = 0; a < 3; ++a) {
+            const double d = mimg(c.X[a] - Xr[a], c.per[a], c.box[a]);
             disp2 += d * d;
-            xr[a] = X[a] - d; // reference centre unwrapped next to X
+            xr[a] = c.X[a] - d; // reference centre unwrapped next to X
         }
         // node lists: rebuilt at the start of the next step once p may have moved the skin
         if (s.listmode) {
             if (mode == 1) {
-                if (tid == 0) {
+                if (lane == 0) {
                     *s.relist_at = t;
                     const double *Vp = Vs + 3 * p;
                     s.pspd[p] = sqrt(Vp[0] * Vp[0] + Vp[1] * Vp[1] + Vp[2] * Vp[2]);
@@ -1485,8 +1671,8 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             } else {
                 double dl = 0.0, ds = 0.0;
                 for (int a = 0; a < 3; ++a) {
-                    const double d = mimg(X[a] - Xl_ld[a], perh[a], boxh[a]);
-                    const double v = mimg(X[a] - (sp ? Xb0[a] : Xb1[a]), perh[a], boxh[a]);
+                    const double d = mimg(c.X[a] - Xl_ld[a], c.per[a], c.box[a]);
+                    const double v = mimg(c.X[a] - (sp ? Xb0[a] : Xb1[a]), c.per[a], c.box[a]);
                     dl += d * d;
                     ds += v * v;
                 }
@@ -1496,7 +1682,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 // displacement (under compact storage a node uncovered outside them is
                 // parked until the rebuild)
                 const double reach = sqrt(dl) + s.list_margin * sqrt(ds);
-                if (tid == 0) {
+                if (lane == 0) {
                     s.pspd[p] = sqrt(ds);
                     if (reach >= s.skin[m] - 1e-9) *s.relist_at = t + 1;
                 }
@@ -1517,160 +1703,91 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
         // lr stays below kShell the candidates are in it, else it is rebuilt at X
         const bool rebuild = (mode == 1) || (lr >= kShell - 1e-6);
         const bool use_list = !rebuild && (lr >= mg_ld);
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        int conv = 0; // this thread converted a node (its momentum is in acc)
-        const int sn = par ^ 1; // population buffer holding f~(t+1)
-        S *Bn = (S *)(sn ? s.popB : s.popA) + M->pop_off;
-        int *nxt = s.own[par ^ 1] + M->cell_off;
-        const int nc = (int)M->ncell;
-        const float rho_ff = (float)M->rho_f;
+        if (use_list) {
+            // candidates have -lr <= d_ref - R <= dr: the band list holds them all while
+            // lr <= kBandIn and dr <= kBandOut, the whole shell list otherwise
+            const bool band = lr + 1e-6 <= kBandIn && dr + 1e-6 <= kBandOut;
+            const long long lbase = (long long)p * s.lcap;
+            const int n = band ? bnum : s.lcnt[p];
+            const int *lc = band ? s.bcell + (long long)p * s.bcap : s.lcell + lbase;
+            const float *dl = band ? s.bdr + (long long)p * s.bcap : s.ldr + lbase;
+            const int dxy = Mp->nx * Mp->ny, dx = Mp->nx;
+            for (int k = lane, i = 0; k < n; k += 64, ++i) {
+                // the first kPre band entries of each lane and their owners are loaded already
+                int cell = 0, wpre = -2;
+                double dk = 0.0;
+                bool pre = false;
+#pragma unroll
+                for (int u = 0; u < kPre; ++u)
+                    if (band && i == u) { cell = bc[u]; dk = (double)bd[u]; wpre = was[u]; pre = true; }
+                if (!pre) { cell = lc[k]; dk = (double)dl[k]; }
+                if (dk < -lr - 1e-6 || dk > dr + 1e-6) continue;
+                const int kk = cell / dxy;
+                const int rem = cell - kk * dxy;
+                const int jj = rem / dx, ii = rem - jj * dx;
+                evaluate(c, ii, jj, kk, cell, dist2c(c, ii, jj, kk, c.X[0], c.X[1], c.X[2]), wpre, acc, conv);
+            }
+        }
+        flag = 1 | (rebuild ? 2 : 0) | ((mode == 0 && t + 1 - nat_ld >= kNearEvery) ? 4 : 0);
+        if (lane == 0) {
+            ctxw[wv][0] = c.X[0]; ctxw[wv][1] = c.X[1]; ctxw[wv][2] = c.X[2];
+            ctxw[wv][3] = xr[0]; ctxw[wv][4] = xr[1]; ctxw[wv][5] = xr[2];
+            ctxw[wv][6] = lr; ctxw[wv][7] = dr; ctxw[wv][8] = dmax;
+            if (mode == 0 && !rebuild) {
+                s.rdisp[p] = rd;
+                s.rlens[p] = rl;
+            }
+        }
+    }
+    // the wave's conversion momentum (summed only when a lane made a conversion)
+    if (__ballot(conv) != 0ull) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] = wave_sum(acc[k]);
+    }
+    if (lane == 0) {
+        flagw[wv] = flag;
+        for (int k = 0; k < 6; ++k) accw[wv][k] = acc[k];
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------------------------
+    // phase B: shell-list rebuilds and near-list builds, the whole workgroup per particle
+    // ------------------------------------------------------------------------------
+    for (int w = 0; w < kRemapWaves; ++w) {
+        const int fw = flagw[w];
+        if ((fw & 6) == 0) continue;
+        const int pw = blockIdx.x * kRemapWaves + w;
+        RemapCtx c;
+        c.p = pw; c.w = w; c.M = s.mem + s.pmem[pw];
+        const MemberDev *M = c.M;
+        for (int a = 0; a < 3; ++a) {
+            c.per[a] = M->per[a];
+            c.box[a] = M->box[a];
+            c.X[a] = ctxw[w][a];
+        }
+        c.R = s.R[pw]; c.R2 = c.R * c.R;
+        c.nn = min(s.nnear[pw], kNearCap);
+        const double xr[3] = {ctxw[w][3], ctxw[w][4], ctxw[w][5]};
+        const double lr = ctxw[w][6], dr = ctxw[w][7], dmax = ctxw[w][8];
+        const double R = c.R, R2 = c.R2;
         const int dims[3] = {M->nx, M->ny, M->nz};
-        const long long lbase = (long long)p * s.lcap;
-
-        // owner of one node after the motion; conversions of covered / uncovered nodes
-        auto evaluate = [&](int ii, int jj, int kk, int cell, double d2n, int was_pre) {
-            // owner: smallest d^2, then smallest index, among the spheres containing the node
-            int best = -1;
-            double bd = 0.0;
-            if (d2n <= R2) { best = p; bd = d2n; }
-            for (int k = 0; k < nn; ++k) {
-                const double dq = dist2h(ii, jj, kk, nb[k][0], nb[k][1], nb[k][2]);
-                if (dq <= nb[k][3] * nb[k][3]) {
-                    const int q = nbid[k];
-                    if (best < 0 || dq < bd || (dq == bd && q < best)) { best = q; bd = dq; }
-                }
-            }
-            if (mode == 1) {
-                if (best >= 0) { s.own[0][M->cell_off + cell] = best; s.own[1][M->cell_off + cell] = best; }
-                return;
-            }
-            const int was = (was_pre >= -1) ? was_pre : cur[cell];
-            if (best == was) return;
-            nxt[cell] = best;
-            // the 18 neighbours and their owners before the re-projection (loads together)
-            int nbc[kQ - 1], ow[kQ - 1];
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e) {
-                int c[3] = {ii + kCX[e], jj + kCY[e], kk + kCZ[e]};
-                bool ok = true;
-                for (int a = 0; a < 3; ++a) {
-                    if (c[a] < 0 || c[a] >= dims[a]) {
-                        if (M->per[a]) c[a] = c[a] < 0 ? c[a] + dims[a] : c[a] - dims[a];
-                        else ok = false;
-                    }
-                }
-                nbc[e] = ok ? (c[2] * dims[1] + c[1]) * dims[0] + c[0] : -1;
-            }
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e) ow[e] = nbc[e] >= 0 ? cur[nbc[e]] : -1;
-            // (the cached link entries that this change makes stale are marked by the next
-            // refresh, which sees which link words actually change)
-            const int slot = atomicAdd(s.chgcnt + par, 1);
-            if (slot < s.chg_cap) {
-                s.chg[par][2 * slot] = (int)(M->cell_off + cell);
-                s.chg[par][2 * slot + 1] = best;
-            } else {
-                atomicOr(s.flags, 0x4u);
-            }
-            const double r0 = mimg((double)ii - X[0], perh[0], boxh[0]);
-            const double r1 = mimg((double)jj - X[1], perh[1], boxh[1]);
-            const double r2 = mimg((double)kk - X[2], perh[2], boxh[2]);
-            if (was < 0 && best == p) {
-                // Eq. (convertFS): a covered node hands its momentum to the particle
-                const int sl = node_slot(s, M, cell, ii, jj, kk);
-                if (sl < 0) { atomicOr(s.flags, 0x100u); return; }
-                double f[kQ];
-#pragma unroll
-                for (int d = 0; d < kQ; ++d) f[d] = (double)ld<P>(Bn, d * nc + sl, d, rho_ff);
-                double rho, j0, j1, j2;
-                moments<double>(f, rho, j0, j1, j2);
-                conv = 1;
-                acc[0] += j0; acc[1] += j1; acc[2] += j2;
-                acc[3] += r1 * j2 - r2 * j1;
-                acc[4] += r2 * j0 - r0 * j2;
-                acc[5] += r0 * j1 - r1 * j0;
-            } else if (was == p && best < 0) {
-                // Eq. (convertSF): an uncovered node is refilled with f^eq(rho_bar, V_b)
-                // and takes rho_bar V_b from the particle; rho_bar averages the
-                // neighbours that are fluid before and after the re-projection.  Under
-                // compact storage a node outside the lists has its refill parked for the
-                // list rebuild at the start of the next step.
-                unsigned use = 0u;
-#pragma unroll
-                for (int e = 0; e < kQ - 1; ++e) {
-                    if (nbc[e] < 0 || ow[e] >= 0) continue;
-                    const int yc = nbc[e];
-                    const int zc = yc / (dims[0] * dims[1]), rc = yc - zc * dims[0] * dims[1];
-                    const int yy = rc / dims[0], xx = rc - yy * dims[0];
-                    bool inside = dist2h(xx, yy, zc, X[0], X[1], X[2]) <= R2;
-                    for (int k = 0; k < nn && !inside; ++k)
-                        inside = dist2h(xx, yy, zc, nb[k][0], nb[k][1], nb[k][2]) <= nb[k][3] * nb[k][3];
-                    if (!inside) use |= 1u << e;
-                }
-                const int sl = node_slot(s, M, cell, ii, jj, kk);
-                double sum = 0.0;
-                int cnt = 0;
-#pragma unroll 1
-                for (int e = 0; e < kQ - 1; ++e) {
-                    if (!((use >> e) & 1u)) continue;
-                    int yc = 0;
-#pragma unroll
-                    for (int q = 0; q < kQ - 1; ++q)
-                        if (q == e) yc = nbc[q];
-                    if (s.compact) {
-                        const int zc = yc / (dims[0] * dims[1]), rc = yc - zc * dims[0] * dims[1];
-                        const int yy = rc / dims[0];
-                        yc = slot_of(s, M, rc - yy * dims[0], yy, zc);
-                        if (yc < 0) { atomicOr(s.flags, 0x100u); continue; }
-                    }
-                    double rr = 0.0;
-                    for (int d = 0; d < kQ; ++d) rr += (double)ld<P>(Bn, d * nc + yc, d, rho_ff);
-                    sum += rr;
-                    cnt += 1;
-                }
-                const double rbar = cnt > 0 ? sum / cnt : M->rho_f;
-                const double *Vp = Vs + 3 * p, *Wp = Ws + 3 * p;
-                const double vb0 = Vp[0] + (Wp[1] * r2 - Wp[2] * r1);
-                const double vb1 = Vp[1] + (Wp[2] * r0 - Wp[0] * r2);
-                const double vb2 = Vp[2] + (Wp[0] * r1 - Wp[1] * r0);
-                const double uu = vb0 * vb0 + vb1 * vb1 + vb2 * vb2;
-                if (sl >= 0) {
-#pragma unroll
-                    for (int d = 0; d < kQ; ++d)
-                        st<P>(Bn, d * nc + sl, d, (typename Prec<P>::C)feq<double>(d, rbar, vb0, vb1, vb2, uu), rho_ff);
-                } else {
-                    const int pi = atomicAdd(s.pcnt + par, 1);
-                    if (pi < kPendCap) {
-                        double *rec = s.pbuf[par] + 4 * pi;
-                        rec[0] = rbar; rec[1] = vb0; rec[2] = vb1; rec[3] = vb2;
-                        s.pend[M->cell_off + cell] = pi;
-                        *s.relist_at = t + 1;
-                        atomicOr(s.flags, 0x200u);
-                    } else {
-                        atomicOr(s.flags, 0x100u);
-                    }
-                }
-                conv = 1;
-                const double m0 = rbar * vb0, m1 = rbar * vb1, m2 = rbar * vb2;
-                acc[0] -= m0; acc[1] -= m1; acc[2] -= m2;
-                acc[3] -= r1 * m2 - r2 * m1;
-                acc[4] -= r2 * m0 - r0 * m2;
-                acc[5] -= r0 * m1 - r1 * m0;
-            }
-        };
-
-        if (rebuild) {
+        const double Xr[3] = {mode == 1 ? c.X[0] : s.Xref[3 * pw], mode == 1 ? c.X[1] : s.Xref[3 * pw + 1],
+                              mode == 1 ? c.X[2] : s.Xref[3 * pw + 2]};
+        if (fw & 2) {
+            double acc2[6] = {0, 0, 0, 0, 0, 0};
+            int conv2 = 0;
             // scan the boxes around X and X_ref, evaluate the candidates, and rebuild the
             // shell list at X: nodes with -kShell < d - R <= sqrt(2) + kShell, with the
             // directions e whose source x - c_e lies within R + kShell (link candidates)
             const double hout = R + 1.5 + kShell + lr;
             const double Rin = R - kShell, Rin2 = Rin > 0.0 ? Rin * Rin : -1.0, Rout2 = hout * hout;
             const double Rl2 = (R + kShell) * (R + kShell);
+            const long long lbase = (long long)pw * s.lcap;
             int lo[3], ext[3];
             for (int a = 0; a < 3; ++a) {
-                int l = (int)floor(fmin(X[a], xr[a]) - hout) - 1;
-                int h = (int)ceil(fmax(X[a], xr[a]) + hout) + 1;
-                if (!M->per[a]) { l = max(l, 0); h = min(h, dims[a] - 1); }
+                int l = (int)floor(fmin(c.X[a], xr[a]) - hout) - 1;
+                int h = (int)ceil(fmax(c.X[a], xr[a]) + hout) + 1;
+                if (!c.per[a]) { l = max(l, 0); h = min(h, dims[a] - 1); }
                 else if (h - l + 1 > dims[a]) { l = 0; h = dims[a] - 1; } // visit each node once
                 lo[a] = l;
                 ext[a] = max(h - l + 1, 0);
@@ -1678,7 +1795,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             const int tot = ext[0] * ext[1] * ext[2];
             double mrg = kShell;
             int lcount = 0, bcount = 0;
-            const long long bbase = (long long)p * s.bcap;
+            const long long bbase = (long long)pw * s.bcap;
             // chunks of the list are z-slabs of hz planes of the scan box
             const int hz = (ext[2] + kChunks - 1) / kChunks;
             if (tid <= kChunks) cstart[tid] = 0;
@@ -1699,15 +1816,15 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                     jj = ((jj % dims[1]) + dims[1]) % dims[1];
                     kk = ((kk % dims[2]) + dims[2]) % dims[2];
                     cell = (kk * dims[1] + jj) * dims[0] + ii;
-                    const double d2n = dist2h(ii, jj, kk, X[0], X[1], X[2]);
+                    const double d2n = dist2c(c, ii, jj, kk, c.X[0], c.X[1], c.X[2]);
                     bool ev;
                     if (mode == 1) {
                         ev = d2n <= R2;
                     } else {
-                        const double dd = sqrt(dist2h(ii, jj, kk, Xr[0], Xr[1], Xr[2])) - R;
+                        const double dd = sqrt(dist2c(c, ii, jj, kk, Xr[0], Xr[1], Xr[2])) - R;
                         ev = dd >= -lr && dd <= dr;
                     }
-                    if (ev) evaluate(ii, jj, kk, cell, d2n, -2);
+                    if (ev) evaluate(c, ii, jj, kk, cell, d2n, -2, acc2, conv2);
                     if (d2n > Rin2 && d2n <= Rout2) {
                         const double dn = sqrt(d2n) - R;
                         if (dn > -kShell && dn <= 1.4142135623730951 + kShell) {
@@ -1717,10 +1834,11 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
 #pragma unroll
                             for (int e = 0; e < kQ - 1; ++e) {
                                 const int si = ii - kCX[e], sj = jj - kCY[e], sk = kk - kCZ[e];
-                                if ((!M->per[0] && (si < 0 || si >= dims[0])) || (!M->per[1] && (sj < 0 || sj >= dims[1])) ||
-                                    (!M->per[2] && (sk < 0 || sk >= dims[2])))
+                                if ((!c.per[0] && (si < 0 || si >= dims[0])) || (!c.per[1] && (sj < 0 || sj >= dims[1])) ||
+                                    (!c.per[2] && (sk < 0 || sk >= dims[2])))
                                     continue;
-                                if (dist2h(wrapc(si, dims[0]), wrapc(sj, dims[1]), wrapc(sk, dims[2]), X[0], X[1], X[2]) <= Rl2)
+                                if (dist2c(c, wrapc(si, dims[0]), wrapc(sj, dims[1]), wrapc(sk, dims[2]), c.X[0], c.X[1],
+                                           c.X[2]) <= Rl2)
                                     mask |= 1u << e;
                             }
                         }
@@ -1759,83 +1877,68 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             __syncthreads();
             if (tid == 0) {
                 mv = fmin(fmin(red[0][7], red[1][7]), fmin(red[2][7], red[3][7]));
-                s.margin[p] = mv;
-                s.lcnt[p] = min(lcount, s.lcap);
-                s.bcnt[p] = min(bcount, s.bcap);
-                s.lreb[p] = (mode == 1) ? t - 1 : t; // the next link pass recomputes its links
-                s.lzr[2 * p] = lo[2];
-                s.lzr[2 * p + 1] = hz;
+                s.margin[pw] = mv;
+                s.lcnt[pw] = min(lcount, s.lcap);
+                s.bcnt[pw] = min(bcount, s.bcap);
+                s.lreb[pw] = (mode == 1) ? t - 1 : t; // the next link pass recomputes its links
+                s.lzr[2 * pw] = lo[2];
+                s.lzr[2 * pw + 1] = hz;
                 int acc_c = 0;
-                for (int c = 0; c <= kChunks; ++c) {
-                    acc_c += cstart[c];
-                    s.lchunk[p * (kChunks + 1) + c] = min(acc_c, s.lcap);
+                for (int k = 0; k <= kChunks; ++k) {
+                    acc_c += cstart[k];
+                    s.lchunk[pw * (kChunks + 1) + k] = min(acc_c, s.lcap);
                 }
-                s.Xref[3 * p] = X[0]; s.Xref[3 * p + 1] = X[1]; s.Xref[3 * p + 2] = X[2];
+                s.Xref[3 * pw] = c.X[0]; s.Xref[3 * pw + 1] = c.X[1]; s.Xref[3 * pw + 2] = c.X[2];
                 // maxima restart at the new reference, where this projection has
                 // displacement 0 and overlap depth dmax
-                s.rdisp[p] = 0.0;
-                s.rlens[p] = dmax;
+                s.rdisp[pw] = 0.0;
+                s.rlens[pw] = dmax;
+            }
+            // the momentum of this rebuild's conversions
+            if (mode == 0 && __syncthreads_or(conv2)) {
+                block_sum<6>(acc2, red);
+                if (tid == 0)
+                    for (int k = 0; k < 6; ++k) accw[w][k] += acc2[k];
             }
             __syncthreads();
-        } else if (use_list) {
-            // candidates have -lr <= d_ref - R <= dr: the band list holds them all while
-            // lr <= kBandIn and dr <= kBandOut, the whole shell list otherwise
-            const bool band = lr + 1e-6 <= kBandIn && dr + 1e-6 <= kBandOut;
-            const int n = band ? bnum : s.lcnt[p];
-            const int *lc = band ? s.bcell + (long long)p * s.bcap : s.lcell + lbase;
-            const float *dl = band ? s.bdr + (long long)p * s.bcap : s.ldr + lbase;
-            for (int k = tid; k < n; k += 256) {
-                // the first band entry of each thread and its owner are loaded already
-                const bool pre = band && k == tid;
-                const int cell = pre ? bcell0 : lc[k];
-                const double dk = pre ? (double)bdr0 : (double)dl[k];
-                if (dk < -lr - 1e-6 || dk > dr + 1e-6) continue;
-                const int kk = cell / (dims[0] * dims[1]);
-                const int rem = cell - kk * dims[0] * dims[1];
-                const int jj = rem / dims[0], ii = rem - jj * dims[0];
-                evaluate(ii, jj, kk, cell, dist2h(ii, jj, kk, X[0], X[1], X[2]), pre ? was0 : -2);
-            }
         }
-        // the near list for the next kNearEvery steps, from the positions after this
-        // step's motion: every particle within R_p + R_q + kNearMargin (each particle
-        // moves less than 0.25 per step, so the contacts and the spheres that can own a
-        // node of p stay among them until the next build)
-        if (mode == 0 && t + 1 - nat_ld >= kNearEvery) {
+        if (fw & 4) {
+            // the near list for the next kNearEvery steps, from the positions after this
+            // step's motion: every particle within R_p + R_q + kNearMargin (each particle
+            // moves less than 0.25 per step, so the contacts and the spheres that can own
+            // a node of p stay among them until the next build)
             const int q0 = M->p_off, nq = M->np;
             int near_total = 0;
             for (int base = 0; base < nq; base += 256) {
                 const int jj = base + tid;
                 bool isnear = false;
-                if (jj < nq && q0 + jj != p) {
+                if (jj < nq && q0 + jj != pw) {
                     const int q = q0 + jj;
-                    const double d0 = mimg(Xs[3 * q] - X[0], perh[0], boxh[0]);
-                    const double d1 = mimg(Xs[3 * q + 1] - X[1], perh[1], boxh[1]);
-                    const double d2 = mimg(Xs[3 * q + 2] - X[2], perh[2], boxh[2]);
+                    const double d0 = mimg(Xs[3 * q] - c.X[0], c.per[0], c.box[0]);
+                    const double d1 = mimg(Xs[3 * q + 1] - c.X[1], c.per[1], c.box[1]);
+                    const double d2 = mimg(Xs[3 * q + 2] - c.X[2], c.per[2], c.box[2]);
                     isnear = sqrt((d0 * d0 + d1 * d1) + d2 * d2) <= R + s.R[q] + kNearMargin;
                 }
                 int tot = 0;
                 const int rk = block_rank(isnear, tot, cnt4);
                 if (isnear) {
                     const int slot = near_total + rk;
-                    if (slot < kNearCap) s.nearl[(long long)p * kNearCap + slot] = q0 + jj;
+                    if (slot < kNearCap) s.nearl[(long long)pw * kNearCap + slot] = q0 + jj;
                     else atomicOr(s.flags, 0x2u);
                 }
                 near_total += tot;
             }
             if (tid == 0) {
-                s.nnear[p] = min(near_total, kNearCap);
-                s.near_at[p] = t + 1;
+                s.nnear[pw] = min(near_total, kNearCap);
+                s.near_at[pw] = t + 1;
             }
+            __syncthreads();
         }
-        // the momentum of conversions, summed only when some thread made one
-        if (mode == 0 && __syncthreads_or(conv)) block_sum<6>(acc, red);
-        if (mode == 0 && tid == 0) {
-            for (int a = 0; a < 3; ++a) { s.Ph[3 * p + a] = acc[a]; s.Lh[3 * p + a] = acc[3 + a]; }
-            if (!rebuild) {
-                s.rdisp[p] = rd;
-                s.rlens[p] = rl;
-            }
-        }
+    }
+    // the conversion momentum of each particle of the workgroup
+    if (mode == 0 && tid < kRemapWaves && (flagw[tid] & 1)) {
+        const int pw = blockIdx.x * kRemapWaves + tid;
+        for (int a = 0; a < 3; ++a) { s.Ph[3 * pw + a] = accw[tid][a]; s.Lh[3 * pw + a] = accw[tid][3 + a]; }
     }
 }
 
@@ -2312,7 +2415,7 @@ hipError_t launch_refresh(int prec, const DevSet &s, hipStream_t st)
     return hipGetLastError();
 }
 int motion_grid(const DevSet &s) { return max((s.ptot + kMotionWaves - 1) / kMotionWaves, 1); }
-int remap_grid(const DevSet &s) { return max(s.ptot + s.nprobe_total, 1); }
+int remap_grid(const DevSet &s) { return max((s.ptot + kRemapWaves - 1) / kRemapWaves + s.nprobe_total, 1); }
 
 template <bool CMP>
 void launch_fluid_t(int prec, const DevSet &s, hipStream_t st)
