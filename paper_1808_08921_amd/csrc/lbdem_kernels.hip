@@ -1038,6 +1038,18 @@ __device__ __forceinline__ void axis_range(double c, double h, int n, int per, i
 // with its loads batched kLinkBatch entries deep, and the whole grid is resident at once.
 constexpr int kLinksBlock = 64;
 constexpr int kLinkBatch = 4;
+// Link-direction masks for the rest-state part of a link force, 2 rho_f sum_d w_d c_d over
+// the links e (d = e*, so c_d = -c_e): per axis and weight class (w = 1/18 on the axes,
+// e < 6; 1/36 on the diagonals), the links whose c_d component is +1 or -1.
+constexpr unsigned link_mask(int axis, int sign, bool diag)
+{
+    unsigned m = 0u;
+    for (int e = 0; e < kQ - 1; ++e) {
+        const int c = -(axis == 0 ? kCX[e] : axis == 1 ? kCY[e] : kCZ[e]);
+        if (c == sign && (e >= 6) == diag) m |= 1u << e;
+    }
+    return m;
+}
 template <int P>
 __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int only)
 {
@@ -1133,6 +1145,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         }
     };
     double acc[6] = {0, 0, 0, 0, 0, 0};
+    const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;
     for (int base = 0; base < cntx; base += kLinksBlock * kLinkBatch) {
         // an entry is cell | slot << 30: slots 2 and 3 set the sign bit, so validity is
         // kept apart from the entry's value
@@ -1159,17 +1172,15 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
             const double r0 = mimg((double)ii - X0, per0, box0);
             const double r1 = mimg((double)jj - X1, per1, box1);
             const double r2 = mimg((double)kk - X2, per2, box2);
-            // F = D + 2 rho_f sum_d w_d c_d over p's links at the node (d pointing into p)
-            double F0 = D[b][0], F1 = D[b][1], F2 = D[b][2];
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e) {
-                if (!((grp[b] >> e) & 1u)) continue;
-                const int d = kOPP[e];
-                const double mm = 2.0 * kWd[d] * rho_f;
-                if (kCX[d] > 0) F0 += mm; else if (kCX[d] < 0) F0 -= mm;
-                if (kCY[d] > 0) F1 += mm; else if (kCY[d] < 0) F1 -= mm;
-                if (kCZ[d] > 0) F2 += mm; else if (kCZ[d] < 0) F2 -= mm;
-            }
+            // F = D + 2 rho_f sum_d w_d c_d over p's links at the node (d pointing into p),
+            // the sum taken as counts of links per direction class
+            const unsigned g = grp[b];
+            auto rest = [&](int axis) {
+                const int na = __popc(g & link_mask(axis, 1, false)) - __popc(g & link_mask(axis, -1, false));
+                const int nd = __popc(g & link_mask(axis, 1, true)) - __popc(g & link_mask(axis, -1, true));
+                return a18 * (double)na + a36 * (double)nd;
+            };
+            const double F0 = D[b][0] + rest(0), F1 = D[b][1] + rest(1), F2 = D[b][2] + rest(2);
             acc[0] += F0; acc[1] += F1; acc[2] += F2;
             acc[3] += r1 * F2 - r2 * F1;
             acc[4] += r2 * F0 - r0 * F2;
