@@ -1036,6 +1036,17 @@ __device__ __forceinline__ void axis_range(double c, double h, int n, int per, i
 // F = 2 G - sum 2 (w_d / c_s^2) rho_f c_d (c_d . V_b), summed in FP64 in a fixed order per
 // chunk (Eqs. coupleF, coupleT).  A chunk holds ~100-200 links, so a single wave serves it
 // with its loads batched kLinkBatch entries deep, and the whole grid is resident at once.
+// n / d for 0 <= n < 2^31 and a divisor d > 0 that every lane shares, through the FP64
+// reciprocal (rounded within one unit of the quotient, then corrected)
+__device__ __forceinline__ int div_uni(int n, int d, double inv)
+{
+    int q = (int)((double)n * inv);
+    const int r = n - q * d;
+    if (r < 0) q -= 1;
+    else if (r >= d) q += 1;
+    return q;
+}
+
 constexpr int kLinksBlock = 64;
 constexpr int kLinkBatch = 4;
 // Link-direction masks for the rest-state part of a link force, 2 rho_f sum_d w_d c_d over
@@ -1146,6 +1157,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     };
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;
+    const double inv_nxy = 1.0 / (double)nxy, inv_nx = 1.0 / (double)nx;
     for (int base = 0; base < cntx; base += kLinksBlock * kLinkBatch) {
         // an entry is cell | slot << 30: slots 2 and 3 set the sign bit, so validity is
         // kept apart from the entry's value
@@ -1168,7 +1180,8 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         for (int b = 0; b < kLinkBatch; ++b) {
             if (!val[b]) continue;
             const int cell = (int)(ent[b] & 0x3fffffffu);
-            const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx, ii = rem - jj * nx;
+            const int kk = div_uni(cell, nxy, inv_nxy), rem = cell - kk * nxy;
+            const int jj = div_uni(rem, nx, inv_nx), ii = rem - jj * nx;
             const double r0 = mimg((double)ii - X0, per0, box0);
             const double r1 = mimg((double)jj - X1, per1, box1);
             const double r2 = mimg((double)kk - X2, per2, box2);
@@ -1220,11 +1233,22 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
     const double R = s.R[p];
     const int per0 = M->per[0], per1 = M->per[1], per2 = M->per[2];
     const double box0 = M->box[0], box1 = M->box[1], box2 = M->box[2];
-    // the link kernel's chunk sums, in chunk order
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    if (mode == 0)
-        for (int q = 0; q < kChunks; ++q)
-            for (int c = 0; c < 6; ++c) acc[c] += s.ppart[((long long)p * kChunks + q) * 6 + c];
+    // the link kernel's chunk sums (lane c * kChunks + q holds component c of chunk q) and
+    // the rest of p's state for the update, loaded up front
+    static_assert(6 * kChunks <= 64, "one lane per chunk-sum component");
+    double ppv = 0.0;
+    if (mode == 0 && lane < 6 * kChunks)
+        ppv = s.ppart[((long long)p * kChunks + lane % kChunks) * 6 + lane / kChunks];
+    double Phv[3], Lhv[3], Fgv[3], Vpv[3], Wpv[3];
+    for (int a = 0; a < 3; ++a) {
+        Phv[a] = s.Ph[3 * p + a];
+        Lhv[a] = s.Lh[3 * p + a];
+        Fgv[a] = s.Fg[3 * p + a];
+        Vpv[a] = Vo[3 * p + a];
+        Wpv[a] = Wo[3 * p + a];
+    }
+    const double mass = s.m[p], inert = s.I[p];
+    const int fixed_p = s.fixed[p];
 
     // contacts over the near list (mode 0) or the near-list build (mode 1)
     const int q0 = M->p_off, nq = M->np;
@@ -1325,12 +1349,21 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
 #pragma unroll
     for (int c = 0; c < 6; ++c) con[c] = wave_sum(con[c]);
 
+    // the chunk sums in chunk order (every lane takes the same values)
+    double acc[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < kChunks; ++q) v += readlane_d(ppv, c * kChunks + q);
+        acc[c] = v;
+    }
     // symplectic Euler: V and Omega from the total force and torque, then X from the new V
     if (lane == 0) {
         double Fh[3], Th[3];
         for (int a = 0; a < 3; ++a) {
-            Fh[a] = acc[a] + s.Ph[3 * p + a];
-            Th[a] = acc[3 + a] + s.Lh[3 * p + a];
+            Fh[a] = acc[a] + Phv[a];
+            Th[a] = acc[3 + a] + Lhv[a];
             s.Fh[3 * p + a] = Fh[a];
             s.Th[3 * p + a] = Th[a];
         }
@@ -1338,15 +1371,14 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
         const double Xc[3] = {X0, X1, X2};
         const int per[3] = {per0, per1, per2};
         const double box[3] = {box0, box1, box2};
-        if (s.fixed[p]) {
+        if (fixed_p) {
             for (int a = 0; a < 3; ++a) { Xn[3 * p + a] = Xc[a]; Vn[3 * p + a] = 0.0; Wn[3 * p + a] = 0.0; }
         } else {
-            const double mass = s.m[p], inert = s.I[p];
             for (int a = 0; a < 3; ++a) {
-                const double Ft = (Fh[a] + s.Fg[3 * p + a]) + con[a];
+                const double Ft = (Fh[a] + Fgv[a]) + con[a];
                 const double Tt = Th[a] + con[3 + a];
-                double v = Vo[3 * p + a] + Ft / mass;
-                double w = Wo[3 * p + a] + Tt / inert;
+                double v = Vpv[a] + Ft / mass;
+                double w = Wpv[a] + Tt / inert;
                 // a step beyond 0.25 lu (or a non-finite state) is an error (status 0x10);
                 // the particle is then held to that step and inside the lattice, so that
                 // every index derived from its position stays in range
