@@ -623,6 +623,10 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
             // recomputing them is harmless
             const int ci = wrapc(i0 + kCXd[q], nx), cj = wrapc(j0 + kCYd[q], ny), ck = wrapc(k0 + kCZd[q], nz);
             const int *own = s.own[par] + M->cell_off;
+            // the node's current words, loaded with the owners (lane 0 compares and stores)
+            const long long gc = M->cell_off + (ck * ny + cj) * nx + ci;
+            unsigned long long o0 = 0ull, o1 = 0ull;
+            if (lane == 0) { o0 = s.lw[gc]; o1 = s.lw[s.ncell_total + gc]; }
             int o = -1;
             if (lane < kQ - 1) {
                 const int si = ci - kCXd[lane], sj = cj - kCYd[lane], sk = ck - kCZd[lane];
@@ -661,8 +665,6 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
                      ((unsigned long long)max(id3, 0) << 31);
             }
             if (lane == 0) {
-                const long long gc = M->cell_off + (ck * ny + cj) * nx + ci;
-                const unsigned long long o0 = s.lw[gc], o1 = s.lw[s.ncell_total + gc];
                 if (o0 != w0 || o1 != w1) mark_words(s, M, o0, o1, w0, w1, ck, t - 1);
                 s.lw[gc] = w0;
                 s.lw[s.ncell_total + gc] = w1;
