@@ -166,3 +166,17 @@ def random_populations(shape, rho_f: float = 1.0, amp: float = 1e-3, seed: int =
     nx, ny, nz = shape
     noise = amp * (2.0 * rng.random((19, nz, ny, nx)) - 1.0)
     return w[:, None, None, None] * (rho_f + noise)
+
+
+def probe_signal(n_t: int, zpos, omega: float, amp: complex, alpha: float, k: float, t0: float = 0.0,
+                 offset: float = 0.0, harmonic: float = 0.0, noise: float = 0.0, seed: int = 0):
+    """Synthetic probe record x[t, z] (float64, [n_t, len(zpos)]) for the dispersion analysis:
+    a damped harmonic wave Re[amp exp(-alpha z) exp(j (omega (t0 + t) - k z))] travelling
+    towards +z, plus a constant offset, a second harmonic of relative size `harmonic` and
+    seeded Gaussian noise of standard deviation `noise`."""
+    z = np.asarray(zpos, dtype=np.float64)[None, :]
+    t = (t0 + np.arange(n_t, dtype=np.float64))[:, None]
+    base = np.real(amp * np.exp(-alpha * z) * np.exp(1j * (omega * t - k * z)))
+    sec = harmonic * np.real(amp * np.exp(-2 * alpha * z) * np.exp(2j * (omega * t - k * z)))
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(base + sec + offset + noise * rng.standard_normal((n_t, z.shape[1])))
