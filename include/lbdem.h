@@ -264,6 +264,51 @@ int lbdem_adj_backward(lbdem_adj *adj, const double *dL_dP, double *dL_dtau, dou
 /* Release the window (its workspace stays with the caller). */
 int lbdem_adj_destroy(lbdem_adj *adj);
 
+/* ---- Dispersion analysis of probe records (Sec. 3.2) ----
+ * The cross-section averaged density signal rho'(t, x3) of a wave experiment is analysed in
+ * two ways: its discrete Fourier transform over space and time, whose ridge gives the
+ * dispersion relation and, at the inserted frequency, the sound speed c_s = omega / k; and a
+ * fit of the stationary solution of the one-dimensional lossy wave equation, Eq. (1Dwave),
+ * rho' = A exp(-alpha_s x) exp(j (omega t - k x)), which gives A, alpha_s and c_s = omega / k.
+ * All arrays of these calls are device memory (FP64, row-major), the calls are asynchronous
+ * on `stream` (a hipStream_t; NULL is the null stream) and the caller owns every buffer.
+ * Errors: LBDEM_EINVAL for a null pointer or a size out of range, LBDEM_ENOMEM for a
+ * workspace smaller than the size query returns, LBDEM_EDEVICE for a launch failure. */
+
+/* Plane-averaged density signal of lattice `lattice` for steps [first, first + n):
+ * x[n][n_probe] = (sum of rho - rho_f) / (node count) of each probe plane (0 for a plane
+ * without fluid nodes), the same records lbdem_probe_read returns, gathered on the device
+ * from the probe ring on the set's stream (x must hold n * n_probe doubles).  The record of
+ * step s is taken at time level s + 1.  Errors: LBDEM_ERANGE as for lbdem_probe_read. */
+int lbdem_probe_signal(lbdem_set *set, int32_t lattice, int64_t first, int64_t n, double *x);
+
+/* Device workspace bytes for lbdem_st_dft and lbdem_wave_fit with these sizes. */
+int lbdem_dft_workspace_size(int64_t nt, int32_t nz, int32_t nw, int32_t nk, size_t *bytes);
+
+/* Space-time DFT: F[m][n] = sum_t sum_z x[t][z] exp(-j (omega_m (t0 + t) - kappa_n zpos[z]))
+ * for omega_m = w0 + m dw (m < nw) and kappa_n = k0 + n dk (n < nk); the sign pair of
+ * Eq. (1Dwave), so a wave running towards +x3 peaks at omega > 0, kappa > 0.
+ * x: [nt][nz] signal, row t taken at time t0 + t; zpos: [nz] positions of the columns along
+ * x3; F: [nw][nk][2] (real, imaginary).  ridge (NULL allowed): [nw] int32, for each row m the
+ * index n of the largest |F|^2 = re^2 + im^2, the smallest index among equal values (-1
+ * for a row of NaN).  work: device workspace of at least lbdem_dft_workspace_size(nt, nz,
+ * nw, nk) bytes, 256-byte aligned.  Limits: 1 <= nt <= 2^31, 1 <= nz <= 65536,
+ * 1 <= nw, nk <= 2^20, and each of nw nz, nz nk, nw nk at most 2^28. */
+int lbdem_st_dft(const double *x, int64_t nt, int32_t nz, const double *zpos, double t0, double w0, double dw,
+                 int32_t nw, double k0, double dk, int32_t nk, double *F, int32_t *ridge, void *work,
+                 size_t work_bytes, void *stream);
+
+/* Fit of Eq. (1Dwave) at the inserted frequency omega (!= 0): at every column z the complex
+ * amplitude P[z] = (2 / nt) sum_t x[t][z] exp(-j omega (t0 + t)) (exact for a stationary
+ * wave sampled over whole periods), then least-squares straight lines through log |P[z]| and
+ * through the phase of P[z] unwrapped along the columns (steps larger than pi taken modulo
+ * 2 pi), against zpos: slopes -alpha_s and -k, intercepts log |A| and arg A.
+ * out: [6] = A real, A imaginary, alpha_s, k, c_s = omega / k, and the number of columns
+ * used.  Columns with P[z] = 0 are left out; fewer than two left gives NaN fits.
+ * work: at least lbdem_dft_workspace_size(nt, nz, 1, 1) bytes.  Limits as for lbdem_st_dft. */
+int lbdem_wave_fit(const double *x, int64_t nt, int32_t nz, const double *zpos, double t0, double omega,
+                   double *out, void *work, size_t work_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

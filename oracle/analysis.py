@@ -37,9 +37,10 @@ def space_time_dft(x, t0, zpos, omegas, kappas):
 
 
 def ridge(F):
-    """For every frequency row, the index of the wavenumber with the largest |F|^2
-    (the first one among equal values)."""
-    a = np.abs(F) ** 2
+    """For every frequency row, the index of the wavenumber with the largest
+    |F|^2 = re^2 + im^2 (the first one among equal values)."""
+    F = np.asarray(F)
+    a = F.real ** 2 + F.imag ** 2
     return np.argmax(a, axis=1)
 
 
@@ -60,10 +61,13 @@ def harmonic_amplitudes(x, t0, omega):
 def wave_fit(x, t0, zpos, omega):
     """Fit of Eq. (1Dwave) to the stationary signal x[t, z] at the inserted frequency omega.
 
-    Returns (A, alpha_s, k, c_s) with c_s = omega / k.
+    Returns (A, alpha_s, k, c_s) with c_s = omega / k.  Columns whose amplitude is exactly
+    zero (a probe plane without fluid nodes records 0) carry no phase and are left out.
     """
     P = harmonic_amplitudes(x, t0, omega)
     z = np.asarray(zpos, np.float64)
+    keep = P != 0
+    P, z = P[keep], z[keep]
     mag = np.log(np.abs(P))
     ph = np.unwrap(np.angle(P))
     s_mag, i_mag = np.polyfit(z, mag, 1)

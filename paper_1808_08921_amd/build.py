@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbdem.so")
-SOURCES = [os.path.join(CSRC, "lbdem_kernels.hip"), os.path.join(CSRC, "lbdem_api.cpp")]
+SOURCES = [os.path.join(CSRC, "lbdem_kernels.hip"), os.path.join(CSRC, "lbdem_analysis.hip"),
+           os.path.join(CSRC, "lbdem_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -963,6 +963,81 @@ int lbdem_probe_read(lbdem_set *S, int32_t lattice, int64_t first, int64_t n, do
     return LBDEM_OK;
 }
 
+int lbdem_probe_signal(lbdem_set *S, int32_t lattice, int64_t first, int64_t n, double *x)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && !x)) return fail(LBDEM_EINVAL, "bad output");
+    int64_t t = 0;
+    rc = lbdem_time(S, &t);
+    if (rc) return rc;
+    const MemberDev &M = S->G.mem[lattice];
+    if (first < 0 || first + n > t || first < t - S->G.ring_len)
+        return fail(LBDEM_ERANGE, "steps [%lld, %lld) not held (t = %lld, ring %d)", (long long)first,
+                    (long long)(first + n), (long long)t, S->G.ring_len);
+    if (M.n_probe == 0 || n == 0) return LBDEM_OK;
+    HIPCHK(launch_probe_signal(S->ds.ring + M.ring_off, S->G.ring_len, M.n_probe, first, n, x, S->stream));
+    return LBDEM_OK;
+}
+
+namespace {
+
+int check_dft_sizes(int64_t nt, int32_t nz, int32_t nw, int32_t nk)
+{
+    const long long lim = 1ll << 28;
+    if (nt < 1 || nt > (1ll << 31) || nz < 1 || nz > 65536 || nw < 1 || nw > (1 << 20) || nk < 1 || nk > (1 << 20))
+        return fail(LBDEM_EINVAL, "sizes out of range (nt %lld, nz %d, nw %d, nk %d)", (long long)nt, nz, nw, nk);
+    if ((long long)nw * nz > lim || (long long)nz * nk > lim || (long long)nw * nk > lim)
+        return fail(LBDEM_EINVAL, "spectrum too large (nw %d, nz %d, nk %d)", nw, nz, nk);
+    return LBDEM_OK;
+}
+
+size_t dft_bytes(int64_t nt, int32_t nz, int32_t nw, int32_t nk)
+{
+    const DftPlan p = dft_plan(nt, nz, nw, nk);
+    return p.part_bytes + p.g_bytes + p.e_bytes;
+}
+
+}  // namespace
+
+int lbdem_dft_workspace_size(int64_t nt, int32_t nz, int32_t nw, int32_t nk, size_t *bytes)
+{
+    if (!bytes) return fail(LBDEM_EINVAL, "null output");
+    int rc = check_dft_sizes(nt, nz, nw, nk);
+    if (rc) return rc;
+    *bytes = dft_bytes(nt, nz, nw, nk);
+    return LBDEM_OK;
+}
+
+int lbdem_st_dft(const double *x, int64_t nt, int32_t nz, const double *zpos, double t0, double w0, double dw,
+                 int32_t nw, double k0, double dk, int32_t nk, double *F, int32_t *ridge, void *work,
+                 size_t work_bytes, void *stream)
+{
+    int rc = check_dft_sizes(nt, nz, nw, nk);
+    if (rc) return rc;
+    if (!x || !zpos || !F || !work) return fail(LBDEM_EINVAL, "null pointer");
+    if ((uintptr_t)work % 256) return fail(LBDEM_EINVAL, "workspace not 256-byte aligned");
+    const DftPlan p = dft_plan(nt, nz, nw, nk);
+    if (work_bytes < p.part_bytes + p.g_bytes + p.e_bytes)
+        return fail(LBDEM_ENOMEM, "workspace of %zu bytes, %zu needed", work_bytes, p.part_bytes + p.g_bytes + p.e_bytes);
+    HIPCHK(launch_st_dft(p, x, nt, nz, zpos, t0, w0, dw, nw, k0, dk, nk, F, ridge, work, (hipStream_t)stream));
+    return LBDEM_OK;
+}
+
+int lbdem_wave_fit(const double *x, int64_t nt, int32_t nz, const double *zpos, double t0, double omega,
+                   double *out, void *work, size_t work_bytes, void *stream)
+{
+    int rc = check_dft_sizes(nt, nz, 1, 1);
+    if (rc) return rc;
+    if (!x || !zpos || !out || !work) return fail(LBDEM_EINVAL, "null pointer");
+    if (!(omega != 0.0) || !std::isfinite(omega)) return fail(LBDEM_EINVAL, "omega must be finite and non-zero");
+    if ((uintptr_t)work % 256) return fail(LBDEM_EINVAL, "workspace not 256-byte aligned");
+    if (work_bytes < dft_bytes(nt, nz, 1, 1))
+        return fail(LBDEM_ENOMEM, "workspace of %zu bytes, %zu needed", work_bytes, dft_bytes(nt, nz, 1, 1));
+    HIPCHK(launch_wave_fit(x, nt, nz, zpos, t0, omega, out, work, (hipStream_t)stream));
+    return LBDEM_OK;
+}
+
 int lbdem_populations_get(lbdem_set *S, int32_t lattice, double *f)
 {
     int rc = check_lattice(S, lattice);

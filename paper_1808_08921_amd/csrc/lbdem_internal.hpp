@@ -207,4 +207,20 @@ hipError_t launch_adj_vgrad(const AdjDev &a, hipStream_t st);
 hipError_t launch_adj_nfl(const AdjDev &a, double *nfl, hipStream_t st);
 int adj_blocks(const AdjDev &a);
 
+
+// dispersion analysis (lbdem_analysis.hip)
+struct DftPlan {
+    int nwb, nzb, threads, nchunk;   // frequency blocks of 64, column blocks, threads per block, time chunks
+    long long chunk;                  // steps per time chunk
+    size_t part_bytes, g_bytes, e_bytes;  // workspace: chunk partials, time-stage sums, phase table
+};
+DftPlan dft_plan(long long nt, int nz, int nw, int nk);
+hipError_t launch_st_dft(const DftPlan &p, const double *x, long long nt, int nz, const double *zpos, double t0,
+                         double w0, double dw, int nw, double k0, double dk, int nk, double *F, int *ridge,
+                         void *work, hipStream_t st);
+hipError_t launch_wave_fit(const double *x, long long nt, int nz, const double *zpos, double t0, double omega,
+                           double *out, void *work, hipStream_t st);
+hipError_t launch_probe_signal(const double *ring, int ring_len, int nprobe, long long first, long long n, double *x,
+                               hipStream_t st);
+
 } // namespace lbdem

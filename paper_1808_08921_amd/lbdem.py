@@ -94,12 +94,18 @@ def lib():
         L.lbdem_adj_forward.argtypes = [P, ctypes.c_double, ctypes.c_double, dp, dp]
         L.lbdem_adj_backward.argtypes = [P, dp, dp, dp, dp]
         L.lbdem_adj_destroy.argtypes = [P]
+        D = ctypes.c_double
+        L.lbdem_probe_signal.argtypes = [P, I32, I64, I64, VP]
+        L.lbdem_dft_workspace_size.argtypes = [I64, I32, I32, I32, ctypes.POINTER(SZ)]
+        L.lbdem_st_dft.argtypes = [VP, I64, I32, VP, D, D, D, I32, D, D, I32, VP, VP, VP, SZ, VP]
+        L.lbdem_wave_fit.argtypes = [VP, I64, I32, VP, D, D, VP, VP, SZ, VP]
         for name in ("lbdem_default_config", "lbdem_workspace_size", "lbdem_create", "lbdem_destroy",
                      "lbdem_set_stream", "lbdem_particles_set", "lbdem_particles_get", "lbdem_step", "lbdem_time",
                      "lbdem_synchronize", "lbdem_status", "lbdem_probe_read", "lbdem_populations_get",
                      "lbdem_populations_set", "lbdem_owner_get", "lbdem_timing_enable", "lbdem_timing_read",
                      "lbdem_tile_info", "lbdem_adj_workspace_size", "lbdem_adj_create", "lbdem_adj_forward",
-                     "lbdem_adj_backward", "lbdem_adj_destroy"):
+                     "lbdem_adj_backward", "lbdem_adj_destroy", "lbdem_probe_signal", "lbdem_dft_workspace_size",
+                     "lbdem_st_dft", "lbdem_wave_fit"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -243,6 +249,16 @@ class LatticeSet:
         _check(lib().lbdem_probe_read(self._h, lattice, int(first), int(n), _dp(out)))
         return out[:, : self.n_probe[lattice], :]
 
+    def probe_signal(self, lattice, first=0, n=None):
+        """Plane-averaged rho' of every probe plane for steps [first, first + n) as a device
+        tensor [n][n_probe] (float64), gathered from the probe ring on the set's stream."""
+        torch = self._torch
+        if n is None:
+            n = self.t - first
+        x = torch.zeros((n, self.n_probe[lattice]), dtype=torch.float64, device=self.device)
+        _check(lib().lbdem_probe_signal(self._h, lattice, int(first), int(n), ctypes.c_void_p(x.data_ptr())))
+        return x
+
     def populations(self, lattice):
         f = np.zeros((19,) + self.shapes[lattice])
         _check(lib().lbdem_populations_get(self._h, lattice, _dp(f)))
@@ -355,3 +371,61 @@ def probe_signals(window, tau, amp, v):
     """Differentiable probe signals [nsteps][n_probe] for float64 tensors tau, amp (scalars)
     and v [n][3]."""
     return _probe_function().apply(tau, amp, v, window)
+
+
+# ---------------------------------------------------------------------------
+# dispersion analysis of probe records (Sec. 3.2)
+# ---------------------------------------------------------------------------
+def _analysis_args(x, zpos):
+    import torch
+
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.dim() == 2):
+        raise TypeError("x must be a 2-D float64 CUDA tensor [nt, nz]")
+    x = x.contiguous()
+    zpos = torch.as_tensor(zpos, dtype=torch.float64, device=x.device).contiguous()
+    if zpos.numel() != x.shape[1]:
+        raise ValueError("zpos must hold one position per column of x")
+    return torch, x, zpos
+
+
+def _workspace(torch, nt, nz, nw, nk, device):
+    nb = ctypes.c_size_t()
+    _check(lib().lbdem_dft_workspace_size(int(nt), int(nz), int(nw), int(nk), ctypes.byref(nb)))
+    return torch.empty(max(nb.value, 256), dtype=torch.uint8, device=device), nb.value
+
+
+def st_dft(x, zpos, t0, w0, dw, nw, k0, dk, nk, ridge=True, work=None):
+    """Space-time DFT of the record x[t][z] (float64 CUDA tensor), row t at time t0 + t:
+    F[m][n] = sum_t sum_z x[t][z] exp(-j (omega_m (t0 + t) - kappa_n zpos[z])) with
+    omega_m = w0 + m dw and kappa_n = k0 + n dk.  Returns the complex128 tensor F [nw][nk]
+    and, with ridge=True, the int32 tensor of the wavenumber index of each row's maximum."""
+    torch, x, zpos = _analysis_args(x, zpos)
+    nt, nz = x.shape
+    if work is None:
+        work, nb = _workspace(torch, nt, nz, nw, nk, x.device)
+    else:
+        nb = work.numel()
+    F = torch.empty((nw, nk, 2), dtype=torch.float64, device=x.device)
+    r = torch.empty(nw, dtype=torch.int32, device=x.device) if ridge else None
+    st = torch.cuda.current_stream(x.device).cuda_stream
+    _check(lib().lbdem_st_dft(ctypes.c_void_p(x.data_ptr()), int(nt), int(nz), ctypes.c_void_p(zpos.data_ptr()),
+                              float(t0), float(w0), float(dw), int(nw), float(k0), float(dk), int(nk),
+                              ctypes.c_void_p(F.data_ptr()), None if r is None else ctypes.c_void_p(r.data_ptr()),
+                              ctypes.c_void_p(work.data_ptr()), nb, ctypes.c_void_p(st)))
+    F = torch.view_as_complex(F)
+    return (F, r) if ridge else F
+
+
+def wave_fit(x, zpos, t0, omega):
+    """Fit of Eq. (1Dwave) to the stationary record x[t][z] at the inserted frequency omega.
+    Returns dict(A=complex, alpha=alpha_s, k=k, c=omega / k, n_used=columns used)."""
+    torch, x, zpos = _analysis_args(x, zpos)
+    nt, nz = x.shape
+    work, nb = _workspace(torch, nt, nz, 1, 1, x.device)
+    out = torch.empty(6, dtype=torch.float64, device=x.device)
+    st = torch.cuda.current_stream(x.device).cuda_stream
+    _check(lib().lbdem_wave_fit(ctypes.c_void_p(x.data_ptr()), int(nt), int(nz), ctypes.c_void_p(zpos.data_ptr()),
+                                float(t0), float(omega), ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(work.data_ptr()), nb, ctypes.c_void_p(st)))
+    o = out.cpu().numpy()
+    return {"A": complex(o[0], o[1]), "alpha": float(o[2]), "k": float(o[3]), "c": float(o[4]), "n_used": int(o[5])}

@@ -94,3 +94,18 @@ def test_null_arguments_are_rejected(lb):
     assert L.lbdem_synchronize(None) == lb.EINVAL
     assert L.lbdem_destroy(None) == lb.OK
     assert L.lbdem_default_config(None) == lb.EINVAL
+
+
+def test_dft_workspace_size_and_validation(lb):
+    L = lb.lib()
+    n = ctypes.c_size_t()
+    assert L.lbdem_dft_workspace_size(20000, 24, 512, 512, ctypes.byref(n)) == lb.OK
+    # at least the time-stage sums, the phase table and one chunk of partials (16 B each)
+    assert n.value >= 16 * (512 * 24 + 24 * 512 + 512 * 24)
+    assert n.value % 256 == 0
+    for bad in [(0, 24, 8, 8), (10, 0, 8, 8), (10, 4, 0, 8), (10, 4, 8, 0), (10, 70000, 8, 8),
+                (10, 4, 1 << 20, 1 << 20)]:
+        assert L.lbdem_dft_workspace_size(*bad, ctypes.byref(n)) == lb.EINVAL, bad
+    # null pointers are rejected before any device work
+    assert L.lbdem_st_dft(None, 10, 4, None, 0.0, 0.0, 0.1, 4, 0.0, 0.1, 4, None, None, None, 0, None) == lb.EINVAL
+    assert L.lbdem_wave_fit(None, 10, 4, None, 0.0, 0.3, None, None, 0, None) == lb.EINVAL
