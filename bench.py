@@ -103,6 +103,14 @@ def arrival_velocity(probes, zs, tmax):
     return float(slope), times
 
 
+def front_velocity(probes, zs, tmax):
+    """Front speed from the first step at which the cross-section momentum reaches half of
+    its largest value at each probe plane, fitted by least squares over the planes."""
+    mom = probes[:tmax, :, 2] / probes[:tmax, :, 3]
+    times = [float(np.argmax(mom[:, k] >= 0.5 * mom[:, k].max()) + 1) for k in range(mom.shape[1])]
+    return float(np.polyfit(np.asarray(times), np.asarray(zs, float), 1)[0])
+
+
 def precision_errors(params, pk, steps=900, planes=12):
     """Error of each storage precision against the FP64 GPU path (itself checked against
     the FP64 CPU oracle to 1e-10 by the test-suite) on the same workload."""
@@ -360,6 +368,57 @@ def adjoint_bench(nsteps=2000, ckpt=100):
     print(json.dumps(line), flush=True)
 
 
+def sweep_bench(steps, warmup, kernel_steps, precision="fp32"):
+    """The source sweep of Table tab:source as a batched ensemble: the FCC wave case
+    (96 x 96 x 384, 1024 spheres) driven by each of the six sources (single-period step,
+    cosine and sine at 6.50 MHz; cosine at 1.30, 3.25 and 13.0 MHz; rho' = 2e-4), advanced
+    together, one launch per kernel per step.  Reports the ensemble's fluid-node MLUPS and
+    each member's P-wave arrival speed from its momentum probes."""
+    import torch
+    from paper_1808_08921_amd import inputs
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    members = inputs.source_sweep_fcc()
+    rows = inputs.source_table_rows()
+    lats = [dict(p, max_particles=len(pk["x"])) for p, pk in members]
+    gs = LatticeSet(lats, precision=precision, graph_steps=8, probe_ring=4096)
+    for k, (_, pk) in enumerate(members):
+        gs.particles_set(k, pk["x"], pk["radius"], fixed=pk["fixed"])
+    nfl = sum(int((gs.owner(k) < 0).sum()) for k in range(len(lats)))
+    dt = time_steps(gs, steps, warmup)
+    tmax = min(steps + warmup, 1200)
+    speeds = []
+    for k, r in enumerate(rows):
+        pr = gs.probes(k, 0, tmax)
+        zs = lats[k]["probe_z"]
+        # planes beyond the inlet that the pulse reaches within the record; a step source
+        # has no momentum peak, its front is timed where the momentum first reaches half
+        # of its largest value
+        if r["wave"] == inputs.WAVE_STEP:
+            c = front_velocity(pr[:, 2:12, :], zs[2:12], tmax)
+        else:
+            c, _ = arrival_velocity(pr[:, 2:12, :], zs[2:12], tmax)
+        speeds.append({"f_mhz": r["f_mhz"], "wave": {1: "sine", 2: "cosine", 3: "step"}[r["wave"]],
+                       "p_wave_velocity": c})
+    kt = kernel_times(gs, kernel_steps)
+    status = gs.status()
+    gs.close()
+    torch.cuda.empty_cache()
+    cells = sum(d["nx"] * d["ny"] * d["nz"] for d in lats)
+    alg = 2 * 19 * BYTES_PER_VALUE[precision] * nfl
+    line = {"metric": "source sweep ensemble (Table tab:source), fluid-node MLUPS", "value": nfl * steps / dt / 1e6,
+            "unit": "MLUPS (fluid-node updates/s, millions)", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": 1e3 * dt / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": {"fp32": "f32", "fp64": "f64"}.get(precision, precision), "data": "synthetic",
+            "config": {"workload": "six FCC wave cases (4x4x16 cells, 96x96x384, 1024 spheres) driven by the six "
+                                   "sources of Table tab:source, one launch per kernel per step",
+                       "cells": cells, "fluid_nodes": nfl, "status": status,
+                       "kernel_ms": {"refresh": kt[4], "fluid": kt[2], "links": kt[0], "motion": kt[1], "remap": kt[3]},
+                       "fluid_roofline_frac": alg / (kt[2] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "p_wave_velocity_by_source": speeds}}
+    print(json.dumps(line), flush=True)
+
+
 def dispersion_bench(calls=50, warmup=5):
     """The dispersion-analysis workload (Sec. 3.2): a probe record of 20000 steps x 24 planes
     (the FCC wave case's probes every 16 lu) through the space-time DFT on a 1024 x 1024
@@ -442,12 +501,17 @@ def main():
                     help="write the counter summary from two rocprofv3 --pmc CSV files")
     ap.add_argument("--ensemble", type=int, default=0, metavar="N",
                     help="run the batched-ensemble workload with N lattices instead of the main line")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run the Table tab:source sweep (six FCC cases, one per source) as a batched ensemble")
     ap.add_argument("--dispersion", action="store_true",
                     help="run the dispersion-analysis workload (space-time DFT of a probe record) instead")
     ap.add_argument("--adjoint", action="store_true", help="run the adjoint-window workload instead of the main line")
     args = ap.parse_args()
     if args.dispersion:
         dispersion_bench()
+        return
+    if args.sweep:
+        sweep_bench(args.steps, args.warmup, args.kernel_steps)
         return
     if args.adjoint:
         adjoint_bench()

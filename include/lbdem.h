@@ -275,12 +275,14 @@ int lbdem_adj_destroy(lbdem_adj *adj);
  * Errors: LBDEM_EINVAL for a null pointer or a size out of range, LBDEM_ENOMEM for a
  * workspace smaller than the size query returns, LBDEM_EDEVICE for a launch failure. */
 
-/* Plane-averaged density signal of lattice `lattice` for steps [first, first + n):
- * x[n][n_probe] = (sum of rho - rho_f) / (node count) of each probe plane (0 for a plane
- * without fluid nodes), the same records lbdem_probe_read returns, gathered on the device
- * from the probe ring on the set's stream (x must hold n * n_probe doubles).  The record of
- * step s is taken at time level s + 1.  Errors: LBDEM_ERANGE as for lbdem_probe_read. */
-int lbdem_probe_signal(lbdem_set *set, int32_t lattice, int64_t first, int64_t n, double *x);
+/* Cross-section averages of lattice `lattice` for steps [first, first + n), gathered on the
+ * device from the probe ring on the set's stream into x[n][n_probe] (n * n_probe doubles):
+ * quantity 0 gives the averaged density signal (sum of rho - rho_f) / (node count) of each
+ * probe plane (Sec. 3.2), quantity 1 the averaged momentum sum(rho u_z) / sum(rho)
+ * (Sec. 4.1); a plane without fluid nodes gives 0.  The values are those of the records
+ * lbdem_probe_read returns; the record of step s is taken at time level s + 1.
+ * Errors: LBDEM_EINVAL for another quantity, LBDEM_ERANGE as for lbdem_probe_read. */
+int lbdem_probe_signal(lbdem_set *set, int32_t lattice, int64_t first, int64_t n, int32_t quantity, double *x);
 
 /* Device workspace bytes for lbdem_st_dft and lbdem_wave_fit with these sizes. */
 int lbdem_dft_workspace_size(int64_t nt, int32_t nz, int32_t nw, int32_t nk, size_t *bytes);

@@ -299,9 +299,11 @@ __global__ __launch_bounds__(256) void k_wave_fit(const double2 *__restrict__ ph
     out[5] = (double)cnt;
 }
 
-// x[i][p] = mean rho' of probe plane p at step first + i, from the probe ring
+// x[i][p] = mean rho' (quantity 0) or sum rho u_z / sum rho (quantity 1) of probe plane p at
+// step first + i, from the probe ring records (count, sum rho', sum rho u_z, sum rho)
 __global__ __launch_bounds__(256) void k_probe_signal(const double *__restrict__ ring, int ring_len, int nprobe,
-                                                      long long first, long long n, double *__restrict__ x)
+                                                      long long first, long long n, int quantity,
+                                                      double *__restrict__ x)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * nprobe) return;
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(256) void k_probe_signal(const double *__restrict__
     const long long slot = (first + s) % ring_len;
     const double *rec = ring + (slot * nprobe + p) * 4;
     const double cnt = rec[0];
-    x[i] = cnt > 0.0 ? rec[1] / cnt : 0.0;
+    x[i] = cnt > 0.0 ? (quantity == 0 ? rec[1] / cnt : rec[2] / rec[3]) : 0.0;
 }
 
 inline long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
@@ -373,13 +375,13 @@ hipError_t launch_wave_fit(const double *x, long long nt, int nz, const double *
     return hipGetLastError();
 }
 
-hipError_t launch_probe_signal(const double *ring, int ring_len, int nprobe, long long first, long long n, double *x,
-                               hipStream_t st)
+hipError_t launch_probe_signal(const double *ring, int ring_len, int nprobe, long long first, long long n,
+                               int quantity, double *x, hipStream_t st)
 {
     const long long tot = n * nprobe;
     if (tot == 0) return hipSuccess;
     hipLaunchKernelGGL(k_probe_signal, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, ring, ring_len, nprobe,
-                       first, n, x);
+                       first, n, quantity, x);
     return hipGetLastError();
 }
 

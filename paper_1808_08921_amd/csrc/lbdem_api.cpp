@@ -963,11 +963,12 @@ int lbdem_probe_read(lbdem_set *S, int32_t lattice, int64_t first, int64_t n, do
     return LBDEM_OK;
 }
 
-int lbdem_probe_signal(lbdem_set *S, int32_t lattice, int64_t first, int64_t n, double *x)
+int lbdem_probe_signal(lbdem_set *S, int32_t lattice, int64_t first, int64_t n, int32_t quantity, double *x)
 {
     int rc = check_lattice(S, lattice);
     if (rc) return rc;
     if (n < 0 || (n > 0 && !x)) return fail(LBDEM_EINVAL, "bad output");
+    if (quantity != 0 && quantity != 1) return fail(LBDEM_EINVAL, "quantity must be 0 (density) or 1 (momentum)");
     int64_t t = 0;
     rc = lbdem_time(S, &t);
     if (rc) return rc;
@@ -976,7 +977,7 @@ int lbdem_probe_signal(lbdem_set *S, int32_t lattice, int64_t first, int64_t n, 
         return fail(LBDEM_ERANGE, "steps [%lld, %lld) not held (t = %lld, ring %d)", (long long)first,
                     (long long)(first + n), (long long)t, S->G.ring_len);
     if (M.n_probe == 0 || n == 0) return LBDEM_OK;
-    HIPCHK(launch_probe_signal(S->ds.ring + M.ring_off, S->G.ring_len, M.n_probe, first, n, x, S->stream));
+    HIPCHK(launch_probe_signal(S->ds.ring + M.ring_off, S->G.ring_len, M.n_probe, first, n, quantity, x, S->stream));
     return LBDEM_OK;
 }
 

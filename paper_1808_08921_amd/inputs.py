@@ -180,3 +180,57 @@ def probe_signal(n_t: int, zpos, omega: float, amp: complex, alpha: float, k: fl
     sec = harmonic * np.real(amp * np.exp(-2 * alpha * z) * np.exp(2j * (omega * t - k * z)))
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(base + sec + offset + noise * rng.standard_normal((n_t, z.shape[1])))
+
+
+# Table tab:source of the paper: (input frequency in MHz, waveform) of the oscillating
+# density boundary; the density amplitude is 0.2 kg/m^3 against rho_f = 1e3 kg/m^3, and
+# the waveform acts for a single period.  Table 1 fixes the time unit, 1.54e-6 ms.
+SOURCE_TABLE = ((6.50, WAVE_STEP), (6.50, WAVE_COSINE), (6.50, WAVE_SINE),
+                (1.30, WAVE_COSINE), (3.25, WAVE_COSINE), (13.0, WAVE_COSINE))
+TIME_UNIT_S = 1.54e-9
+SOURCE_AMP = 0.2 / 1.0e3
+
+
+def source_omega(f_mhz: float) -> float:
+    """Angular frequency in lattice units (rad per step) of an input frequency in MHz."""
+    return 2.0 * math.pi * f_mhz * 1.0e6 * TIME_UNIT_S
+
+
+def source_table_rows():
+    """The six sources of Table tab:source as lattice parameters (wave, amp, omega, t_n),
+    each acting for one period (t_n = the period rounded to whole steps)."""
+    rows = []
+    for f, wave in SOURCE_TABLE:
+        om = source_omega(f)
+        rows.append(dict(wave=wave, amp=SOURCE_AMP, omega=om, t_n=int(round(2.0 * math.pi / om)), f_mhz=f))
+    return rows
+
+
+def source_sweep_fcc(seed: int = 0, **kw):
+    """The Table tab:source sweep as a batched ensemble: the FCC wave case (same packing
+    for every member) driven by each of the six sources."""
+    out = []
+    for row in source_table_rows():
+        params, pk = wave_fcc_case(seed=seed, **kw)
+        params.update({k: row[k] for k in ("wave", "amp", "omega", "t_n")})
+        out.append((params, pk))
+    return out
+
+
+def impulse_fcc_case(seed: int = 0, ncx: int = 2, ncy: int = 2, ncz: int = 6, a: float = 12.0,
+                     overlap_rel: float = 1e-3, push: float = 5.0):
+    """Mechanically agitated impulse (Sec. 4.2): the FCC case without an acoustic source
+    (both density faces held at rho_f), the first mobile layer of spheres moved towards the
+    fixed layer at z = 0 by `push` times the mean overlap, so that its contacts with the
+    fixed layer start with overlaps larger than elsewhere."""
+    params, pk = wave_fcc_case(seed=seed, ncx=ncx, ncy=ncy, ncz=ncz, a=a, overlap_rel=overlap_rel)
+    params.update(wave=WAVE_NONE, amp=0.0, omega=0.0, t_n=0)
+    z = pk["x"][:, 2]
+    zl = np.unique(np.round(z, 6))
+    first_free = np.isclose(z, zl[1], atol=1e-5)
+    r0 = a / (2.0 * math.sqrt(2.0))
+    mean_overlap = float(np.mean(2.0 * (pk["radius"] - r0)))
+    x = pk["x"].copy()
+    x[first_free, 2] -= push * mean_overlap
+    pk = dict(pk, x=x)
+    return params, pk

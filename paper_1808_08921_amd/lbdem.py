@@ -95,7 +95,7 @@ def lib():
         L.lbdem_adj_backward.argtypes = [P, dp, dp, dp, dp]
         L.lbdem_adj_destroy.argtypes = [P]
         D = ctypes.c_double
-        L.lbdem_probe_signal.argtypes = [P, I32, I64, I64, VP]
+        L.lbdem_probe_signal.argtypes = [P, I32, I64, I64, I32, VP]
         L.lbdem_dft_workspace_size.argtypes = [I64, I32, I32, I32, ctypes.POINTER(SZ)]
         L.lbdem_st_dft.argtypes = [VP, I64, I32, VP, D, D, D, I32, D, D, I32, VP, VP, VP, SZ, VP]
         L.lbdem_wave_fit.argtypes = [VP, I64, I32, VP, D, D, VP, VP, SZ, VP]
@@ -249,14 +249,16 @@ class LatticeSet:
         _check(lib().lbdem_probe_read(self._h, lattice, int(first), int(n), _dp(out)))
         return out[:, : self.n_probe[lattice], :]
 
-    def probe_signal(self, lattice, first=0, n=None):
-        """Plane-averaged rho' of every probe plane for steps [first, first + n) as a device
-        tensor [n][n_probe] (float64), gathered from the probe ring on the set's stream."""
+    def probe_signal(self, lattice, first=0, n=None, quantity="density"):
+        """Cross-section averages of every probe plane for steps [first, first + n) as a device
+        tensor [n][n_probe] (float64), gathered from the probe ring on the set's stream:
+        quantity "density" gives rho', "momentum" gives sum(rho u_z) / sum(rho)."""
         torch = self._torch
         if n is None:
             n = self.t - first
+        q = {"density": 0, "momentum": 1}[quantity]
         x = torch.zeros((n, self.n_probe[lattice]), dtype=torch.float64, device=self.device)
-        _check(lib().lbdem_probe_signal(self._h, lattice, int(first), int(n), ctypes.c_void_p(x.data_ptr())))
+        _check(lib().lbdem_probe_signal(self._h, lattice, int(first), int(n), q, ctypes.c_void_p(x.data_ptr())))
         return x
 
     def populations(self, lattice):

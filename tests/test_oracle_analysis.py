@@ -120,3 +120,25 @@ def test_pure_fluid_fit_matches_paper(orc, an):
     ka = np.linspace(0.0, 0.2, 2001)
     F = an.space_time_dft(x, first + 1, np.array(zs, float), [g["omega"]], ka)
     assert an.branch_speed([g["omega"]], ka, F)[0] == pytest.approx(cs, rel=3e-3)
+
+
+@pytest.mark.parametrize("f_mhz,rel_alpha,rel_c", [(1.30, 0.005, 0.002), (3.25, 0.005, 0.002),
+                                                   (6.50, 0.01, 0.004), (13.0, 0.02, 0.01)])
+def test_frequency_sweep_follows_the_lossy_wave(orc, an, f_mhz, rel_alpha, rel_c):
+    """The input frequencies of Table tab:source (continuous sine source, rho' = 2e-4) in the
+    pure fluid: the fitted absorption and speed follow the closed form of Eq. (1Dwave) with
+    tau_s = tau = 1 and c_s = 1/sqrt(3); the lattice's own dispersion grows with frequency
+    (1.3 % in alpha_s and 0.85 % in c_s at 13 MHz, a wavelength of 29 nodes)."""
+    cs = _golden()["sound_speed"]["value"]
+    om = inputs.source_omega(f_mhz)
+    zs = tuple(1 + 7 * i for i in range(64))
+    s = orc.Sim(1, 1, 1400, tau=1.0, bc=(0, 0, 0, 0, 2, 2), wave=orc.WAVE_SINE, amp=inputs.SOURCE_AMP, omega=om,
+                t_n=100000, probe_z=zs)
+    s.step(3200)
+    pr = s.probes()
+    first, n = 1200, 1998
+    x = pr[first:first + n, :, 1] / pr[first:first + n, :, 0] / inputs.SOURCE_AMP
+    A, al, k, c = an.wave_fit(x, first + 1, np.array(zs, float), om)
+    assert al == pytest.approx(an.lossy_alpha(om, cs, 1.0), rel=rel_alpha)
+    assert c == pytest.approx(cs, rel=rel_c)
+    assert abs(A - (-1j)) < 0.01
