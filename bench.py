@@ -103,11 +103,12 @@ def arrival_velocity(probes, zs, tmax):
     return float(slope), times
 
 
-def front_velocity(probes, zs, tmax):
-    """Front speed from the first step at which the cross-section momentum reaches half of
-    its largest value at each probe plane, fitted by least squares over the planes."""
-    mom = probes[:tmax, :, 2] / probes[:tmax, :, 3]
-    times = [float(np.argmax(mom[:, k] >= 0.5 * mom[:, k].max()) + 1) for k in range(mom.shape[1])]
+def front_velocity(probes, zs, tmax, amp):
+    """Front speed of a step source: the first step at which the cross-section averaged
+    density rho' reaches half of the step's amplitude at each probe plane, fitted by least
+    squares over the planes."""
+    rho = probes[:tmax, :, 1] / probes[:tmax, :, 0]
+    times = [float(np.argmax(rho[:, k] >= 0.5 * amp) + 1) for k in range(rho.shape[1])]
     return float(np.polyfit(np.asarray(times), np.asarray(zs, float), 1)[0])
 
 
@@ -392,10 +393,9 @@ def sweep_bench(steps, warmup, kernel_steps, precision="fp32"):
         pr = gs.probes(k, 0, tmax)
         zs = lats[k]["probe_z"]
         # planes beyond the inlet that the pulse reaches within the record; a step source
-        # has no momentum peak, its front is timed where the momentum first reaches half
-        # of its largest value
+        # has no momentum peak, its front is timed where rho' first reaches half the step
         if r["wave"] == inputs.WAVE_STEP:
-            c = front_velocity(pr[:, 2:12, :], zs[2:12], tmax)
+            c = front_velocity(pr[:, 2:12, :], zs[2:12], tmax, r["amp"])
         else:
             c, _ = arrival_velocity(pr[:, 2:12, :], zs[2:12], tmax)
         speeds.append({"f_mhz": r["f_mhz"], "wave": {1: "sine", 2: "cosine", 3: "step"}[r["wave"]],
@@ -416,6 +416,86 @@ def sweep_bench(steps, warmup, kernel_steps, precision="fp32"):
                        "kernel_ms": {"refresh": kt[4], "fluid": kt[2], "links": kt[0], "motion": kt[1], "remap": kt[3]},
                        "fluid_roofline_frac": alg / (kt[2] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "p_wave_velocity_by_source": speeds}}
+    print(json.dumps(line), flush=True)
+
+
+def drag_force(v_rel, radius, tau, rho_f=1.0):
+    """Eq. (termVel): drag of a sphere at relative speed v_rel, with C_d = 24/Re + 3.6/Re^0.313,
+    Re = 2 v_rel R / nu and nu = (tau - 1/2) / 3."""
+    nu = (tau - 0.5) / 3.0
+    re = 2.0 * v_rel * radius / nu
+    cd = 24.0 / re + 3.6 / re ** 0.313
+    return 0.5 * cd * math.pi * radius ** 2 * rho_f * v_rel ** 2
+
+
+def settling_bench(steps=40000, taus=(0.6, 0.8, 1.0, 1.4, 1.8, 2.0), precision="fp32", every=100,
+                   kernel_steps=200):
+    """The settling sweep of Sec. 3.1 at the paper's size: a 160^3 fully periodic cube, one
+    sphere of radius 5.005 released at rest at the centre under F_g = 0.1 (net of buoyancy),
+    tau from 0.6 to 2.0.  The terminal speed is the relative speed |V_p - u_bar| averaged
+    over the second half of the run (sampled every `every` steps: the sphere's speed
+    ripples as it crosses lattice planes), with u_bar, the fluid velocity averaged over the
+    lattice, from the momentum balance of the periodic box (F_g t = m_p V_p + rho_f N u_bar)
+    and checked against the populations at the end; its drag by Eq. (termVel) is compared
+    with F_g.  The all-fluid 4.1 M-cell lattice is also a second roofline case of the fluid
+    kernel."""
+    import torch
+    from paper_1808_08921_amd import inputs
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    # lattice vectors in the order of Eq. (3d19q), the order of the populations the library returns
+    c = np.array([[1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0, 0],
+                  [0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0],
+                  [0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1, 0]], dtype=np.float64)
+    rows = []
+    roof = None
+    for tau in taus:
+        params, pk = inputs.settling_periodic_case(tau)
+        radius = float(pk["radius"][0])
+        m_p = params["rho_p"] * 4.0 / 3.0 * math.pi * radius ** 3
+        fg = float(pk["fg"][0, 2])
+        gs = LatticeSet([params], precision=precision, graph_steps=8, probe_ring=16)
+        gs.particles_set(0, pk["x"], pk["radius"], fg=pk["fg"], fixed=pk["fixed"])
+        nfl = int((gs.owner(0) < 0).sum())
+        t0 = time.perf_counter()
+        samples = []
+        for _ in range(steps // every):
+            gs.step(every)
+            v = gs.particles_get(0)["v"][0]
+            u_bar = -m_p * v / (params["rho_f"] * nfl)
+            u_bar[2] += fg * gs.t / (params["rho_f"] * nfl)
+            samples.append((gs.t, float(np.linalg.norm(v - u_bar)), float(v[2]), float(u_bar[2])))
+        wall = time.perf_counter() - t0
+        f = gs.populations(0)
+        fluid = gs.owner(0) < 0
+        u_pop = (c @ f[:, fluid]).sum(1) / f[:, fluid].sum()
+        if tau == 1.0:
+            kt = kernel_times(gs, kernel_steps)
+            alg = 2 * 19 * BYTES_PER_VALUE[precision] * nfl
+            roof = {"fluid_kernel_ms": kt[2], "fluid_nodes": nfl,
+                    "achieved_GBs": alg / (kt[2] * 1e-3) / 1e9, "frac": alg / (kt[2] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "kernel_ms": {"refresh": kt[4], "fluid": kt[2], "links": kt[0], "motion": kt[1], "remap": kt[3]}}
+        status = gs.status()
+        gs.close()
+        del f
+        torch.cuda.empty_cache()
+        vr = np.array([x[1] for x in samples[len(samples) // 2:]])
+        v_t = float(vr.mean())
+        fd = drag_force(v_t, radius, tau)
+        q = len(samples) // 4
+        rows.append({"tau": tau, "v_t": v_t, "v_t_ripple": float(vr.std() / v_t),
+                     "v_t_quarters": [float(np.mean([x[1] for x in samples[k * q:(k + 1) * q]])) for k in range(4)],
+                     "re": 2 * v_t * radius / ((tau - 0.5) / 3.0), "drag_eq_termVel": fd,
+                     "rel_err_vs_Fg": (fd - fg) / fg, "u_bar_end_balance": samples[-1][3],
+                     "u_bar_end_populations": float(u_pop[2]), "status": status, "wall_s": wall})
+        _log(f"settling tau {tau}: V_t {v_t:.5e} drag {fd:.5f} err {(fd - fg) / fg:+.4f} "
+             f"u_bar {samples[-1][3]:.4e} / {u_pop[2]:.4e} ({wall:.1f} s)")
+    line = {"metric": "settling sweep (Sec. 3.1): drag error of Eq. (termVel) vs F_g", "value": None,
+            "unit": "relative error", "n_gpus": 1, "steps": steps, "warmup": 0, "higher_is_better": False,
+            "dtype": {"fp32": "f32", "fp64": "f64"}.get(precision, precision), "data": "synthetic",
+            "config": {"workload": "160^3 fully periodic cube, one sphere R = 5.005, F_g = 0.1, tau 0.6..2.0",
+                       "precision": precision},
+            "results": rows, "fluid_roofline_160cube": roof}
     print(json.dumps(line), flush=True)
 
 
@@ -501,6 +581,10 @@ def main():
                     help="write the counter summary from two rocprofv3 --pmc CSV files")
     ap.add_argument("--ensemble", type=int, default=0, metavar="N",
                     help="run the batched-ensemble workload with N lattices instead of the main line")
+    ap.add_argument("--settling", type=int, default=0, metavar="STEPS",
+                    help="run the 160^3 periodic settling sweep over tau with STEPS steps per tau instead")
+    ap.add_argument("--taus", type=float, nargs="+", default=[0.6, 0.8, 1.0, 1.4, 1.8, 2.0],
+                    help="relaxation times of the settling sweep")
     ap.add_argument("--sweep", action="store_true",
                     help="run the Table tab:source sweep (six FCC cases, one per source) as a batched ensemble")
     ap.add_argument("--dispersion", action="store_true",
@@ -509,6 +593,9 @@ def main():
     args = ap.parse_args()
     if args.dispersion:
         dispersion_bench()
+        return
+    if args.settling:
+        settling_bench(steps=args.settling, taus=tuple(args.taus))
         return
     if args.sweep:
         sweep_bench(args.steps, args.warmup, args.kernel_steps)

@@ -115,8 +115,9 @@ typedef struct lbdem_config {
                              lists with compact storage (only listed nodes hold populations,
                              per plane in list order; moved when the lists are rebuilt; needs
                              ny * ceil(nx / 32) <= 8192; a third population buffer); -1 =
-                             automatic (2 where every plane fits, else 1 for 16-bit storage
-                             and 0 otherwise).  Host access to populations, particle set-up
+                             automatic (0 when max_particles spheres of max_radius could
+                             cover at most a quarter of the set's cells; else 2 where every
+                             plane fits, else 1 for 16-bit storage and 0 otherwise).  Host access to populations, particle set-up
                              and adjoint windows see the node layout either way. */
     int32_t list_margin;  /* node lists: a lattice's lists are rebuilt once a particle's
                              displacement since the last rebuild plus list_margin times its

@@ -151,15 +151,25 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
 {
     G.mem.assign(n, MemberDev{});
     G.prec = cfg->precision;
-    // automatic: node lists with compact storage (the fastest mapping measured at every
-    // precision), unless an x-y plane has too many row-table words for it; then node lists
-    // for 16-bit storage, where partial-line writes cost less than the idle lanes of dense
-    // tiles, and dense tiles with whole-line writes otherwise
+    // automatic: dense tiles when the particles can cover at most a quarter of the cells
+    // (lists would skip little, and rebuilding the lists of a large, mostly fluid lattice
+    // costs more than they save); else node lists with compact storage (the fastest
+    // mapping measured at every precision), unless an x-y plane has too many row-table
+    // words for it; then node lists for 16-bit storage, where partial-line writes cost
+    // less than the idle lanes of dense tiles, and dense tiles with whole-line writes
+    // otherwise
     int mode = cfg->node_lists;
     if (mode < 0) {
         bool fits = true;
-        for (int m = 0; m < n; ++m) fits = fits && (long long)lat[m].ny * ((lat[m].nx + 31) / 32) <= kMaxPlaneWords;
-        mode = fits ? 2 : ((cfg->precision == LBDEM_FP16DEV || cfg->precision == LBDEM_BF16DEV) ? 1 : 0);
+        double solid = 0.0, cells = 0.0;
+        for (int m = 0; m < n; ++m) {
+            fits = fits && (long long)lat[m].ny * ((lat[m].nx + 31) / 32) <= kMaxPlaneWords;
+            const double r = lat[m].max_radius;
+            solid += (double)lat[m].max_particles * (4.0 / 3.0) * 3.14159265358979323846 * r * r * r;
+            cells += (double)lat[m].nx * lat[m].ny * lat[m].nz;
+        }
+        if (solid <= 0.25 * cells) mode = 0;
+        else mode = fits ? 2 : ((cfg->precision == LBDEM_FP16DEV || cfg->precision == LBDEM_BF16DEV) ? 1 : 0);
     }
     G.listmode = mode != 0 ? 1 : 0;
     G.compact = mode == 2 ? 1 : 0;

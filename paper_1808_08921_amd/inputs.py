@@ -234,3 +234,17 @@ def impulse_fcc_case(seed: int = 0, ncx: int = 2, ncy: int = 2, ncz: int = 6, a:
     x[first_free, 2] -= push * mean_overlap
     pk = dict(pk, x=x)
     return params, pk
+
+
+def settling_periodic_case(tau: float, n: int = 160, r0: float = 5.0, overlap: float = 0.01, fg: float = 0.1,
+                           rho_p: float = 2.466):
+    """Single sphere settling in a fully periodic cube (Sec. 3.1): radius R0 + |u_n|/2
+    (5.005 for the paper's values), released at rest at the centre, driven by the constant
+    force F_g = (0, 0, fg) net of buoyancy; the fluid carries no body force."""
+    radius = r0 + 0.5 * overlap
+    params = dict(nx=n, ny=n, nz=n, tau=tau, rho_f=1.0, bc=(PERIODIC,) * 6, wave=WAVE_NONE, amp=0.0, omega=0.0,
+                  t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=rho_p, probe_z=(), max_radius=float(math.ceil(radius)),
+                  max_particles=1)
+    pk = {"x": np.array([[n / 2.0, n / 2.0, n / 2.0]]), "radius": np.array([radius]),
+          "fixed": np.zeros(1, np.uint8), "fg": np.array([[0.0, 0.0, fg]]), "shape": (n, n, n)}
+    return params, pk

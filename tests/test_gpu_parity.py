@@ -245,6 +245,24 @@ def test_settling_sphere_walls_fp64():
         _compare_state(gs, 0, s, pk)
 
 
+@pytest.mark.parametrize("tau,centre,node_lists", [(0.8, (16.0, 16.0, 16.0), None), (0.6, (16.0, 16.0, 16.0), None),
+                                                   (1.4, (1.3, 30.6, 31.85), None), (1.4, (1.3, 30.6, 31.85), 2)])
+def test_settling_sphere_periodic_fp64(tau, centre, node_lists):
+    """The settling set-up of Sec. 3.1 (fully periodic cube, R = 5.005, F_g = 0.1 net of
+    buoyancy) in a 32^3 box; the last cases start next to the box corner, so the sphere
+    straddles three periodic faces and crosses the top face while it falls upwards (with
+    the automatic mapping, dense tiles here, and with compact node lists)."""
+    params, pk = inputs.settling_periodic_case(tau, n=32)
+    pk = dict(pk, x=np.array([centre]))
+    s = _oracle(params, pk)
+    with _gpu_set([params], graph_steps=8, node_lists=node_lists) as gs:
+        _set_particles(gs, 0, pk)
+        gs.step(150)
+        s.step(150)
+        _compare_state(gs, 0, s, pk)
+        assert gs.status() == 0
+
+
 def test_friction_contacts_fp64():
     """Two spheres pressed together and sheared: Hertz + Mindlin with a Coulomb cap."""
     params = dict(nx=40, ny=24, nz=24, tau=1.0, bc=(0,) * 6, E=10.0, nu=0.2, mu=0.3, rho_p=2.0, max_particles=3)
