@@ -103,12 +103,12 @@ def arrival_velocity(probes, zs, tmax):
     return float(slope), times
 
 
-def front_velocity(probes, zs, tmax, amp):
+def front_velocity(probes, zs, tmax):
     """Front speed of a step source: the first step at which the cross-section averaged
-    density rho' reaches half of the step's amplitude at each probe plane, fitted by least
-    squares over the planes."""
+    density rho' reaches half of its largest value at each probe plane (the pulse weakens
+    along the packing), fitted by least squares over the planes."""
     rho = probes[:tmax, :, 1] / probes[:tmax, :, 0]
-    times = [float(np.argmax(rho[:, k] >= 0.5 * amp) + 1) for k in range(rho.shape[1])]
+    times = [float(np.argmax(rho[:, k] >= 0.5 * rho[:, k].max()) + 1) for k in range(rho.shape[1])]
     return float(np.polyfit(np.asarray(times), np.asarray(zs, float), 1)[0])
 
 
@@ -393,9 +393,9 @@ def sweep_bench(steps, warmup, kernel_steps, precision="fp32"):
         pr = gs.probes(k, 0, tmax)
         zs = lats[k]["probe_z"]
         # planes beyond the inlet that the pulse reaches within the record; a step source
-        # has no momentum peak, its front is timed where rho' first reaches half the step
+        # has no momentum peak, its front is timed where rho' first reaches half its peak
         if r["wave"] == inputs.WAVE_STEP:
-            c = front_velocity(pr[:, 2:12, :], zs[2:12], tmax, r["amp"])
+            c = front_velocity(pr[:, 2:12, :], zs[2:12], tmax)
         else:
             c, _ = arrival_velocity(pr[:, 2:12, :], zs[2:12], tmax)
         speeds.append({"f_mhz": r["f_mhz"], "wave": {1: "sine", 2: "cosine", 3: "step"}[r["wave"]],
