@@ -160,3 +160,25 @@ def test_pure_fluid_wave_end_to_end():
     assert fit["c"] == pytest.approx(cs, rel=2e-3)
     assert abs(fit["A"] - complex(gold["pure_fluid_fit"]["A_re"], gold["pure_fluid_fit"]["A_im"])) < 0.03
     assert c_ridge == pytest.approx(cs, rel=3e-3)
+
+
+def test_st_dft_full_size_sampled_against_oracle():
+    """The benchmark's launch: a 20000 x 24 record on a 1024 x 1024 grid.  Sampled spectrum
+    values (rows and columns spread over the grid, ragged ends included) and the ridge of
+    sampled rows against the oracle's transform of those rows."""
+    torch, lb = _lb()
+    nt, nz, nw, nk = 20000, 24, 1024, 1024
+    zpos = 16.0 * np.arange(nz)
+    om = 2 * math.pi / 200
+    x = inputs.probe_signal(nt, zpos, om, -0.6 - 0.1j, 6e-3, om / 0.7, offset=1e-3, harmonic=0.1, noise=0.02, seed=3)
+    w0, dw = 0.0, 0.2 / nw
+    k0, dk = -math.pi / 16, (2 * math.pi / 16) / nk
+    F, r = lb.st_dft(torch.from_numpy(x).cuda(), zpos, 0.0, w0, dw, nw, k0, dk, nk)
+    Fg, rg = F.cpu().numpy(), r.cpu().numpy()
+    rows = np.array([0, 1, 63, 64, 255, 511, int(round(om / dw)), 1000, 1023])
+    ka = _grid(k0, dk, nk)
+    Fo = an.space_time_dft(x, 0.0, zpos, _grid(w0, dw, nw)[rows], ka)
+    scale = np.abs(x).sum()
+    err = np.abs(Fg[rows] - Fo).max() / scale
+    assert err < 1e-12, err
+    _check_ridge(Fo, rg[rows], 4 * err * scale / np.abs(Fo).max() + 1e-13)

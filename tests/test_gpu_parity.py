@@ -328,3 +328,33 @@ def test_reduced_precision_error_bounds(precision, tol_f, tol_probe):
         rp = np.abs(pg[..., 1] / pg[..., 0] - po[..., 1] / po[..., 0]).max()
         assert df <= tol_f, df
         assert rp <= tol_probe, rp
+
+
+def test_settling_full_size_momentum_balance():
+    """The 160^3 settling set-up (Sec. 3.1) at full size, FP32 storage as benchmarked: the
+    periodic box has no other external force than F_g, so the fluid momentum summed from
+    the populations equals F_g t - m_p V_p (up to the MEM's refill and emptying exchange)."""
+    params, pk = inputs.settling_periodic_case(1.0)
+    c = _printed_matrix_local()
+    with _gpu_set([params], precision="fp32", graph_steps=8) as gs:
+        _set_particles(gs, 0, pk)
+        gs.step(2000)
+        f = gs.populations(0)
+        fluid = gs.owner(0) < 0
+        p = gs.particles_get(0)
+        assert gs.status() == 0
+    mom = (c.T @ f[:, fluid]).sum(1)
+    m_p = params["rho_p"] * 4.0 / 3.0 * math.pi * pk["radius"][0] ** 3
+    want = 0.1 * 2000 - m_p * p["v"][0, 2]
+    assert mom[2] == pytest.approx(want, rel=2e-3)
+    assert abs(mom[0]) < 1e-3 * want and abs(mom[1]) < 1e-3 * want
+    # the sphere falls along +z at about the terminal speed of Eq. (termVel) reached later
+    assert 4e-3 < p["v"][0, 2] < 8e-3
+
+
+def _printed_matrix_local():
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "d3q19_velocity_matrix.txt")
+    rows = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    return np.array(rows, dtype=float).T  # (19, 3)
