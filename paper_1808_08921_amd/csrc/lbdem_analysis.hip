@@ -3,7 +3,7 @@
 // Space-time DFT of a probe record x[t][z] on a chosen (omega, kappa) grid, the ridge of its
 // spectrum, and the fit of the stationary lossy wave of Eq. (1Dwave).  FP64 throughout.
 //
-// Time stage: one lane per frequency omega_m and one wave per group of kZB columns; the
+// Time stage: one lane per kMPL frequencies omega_m and one wave per group of kZB columns; the
 // lanes of a wave share each record row (staged in LDS, read as broadcasts) and advance
 // their phase factor exp(-j omega_m t) by a complex rotation, re-anchored with an exact
 // sincos every kAnchor steps, so the time stage costs about two FMAs per sample and
@@ -22,7 +22,8 @@ namespace lbdem {
 namespace {
 
 constexpr int kZB = 8;        // columns per wave in the time stage
-constexpr int kAnchor = 16;   // steps between exact phase anchors
+constexpr int kAnchor = 64;   // steps between exact phase anchors (one record row per lane)
+constexpr int kMPL = 2;       // frequencies per lane in the time stage
 constexpr int kTargetBlocks = 1024;
 
 __device__ inline double2 cmul_acc(double2 acc, double2 a, double2 b)
@@ -44,59 +45,75 @@ __global__ __launch_bounds__(256) void k_dft_time(const double *__restrict__ x, 
     const int wv = threadIdx.x >> 6;
     const int mb = blockIdx.x % nwb;
     const long long c = blockIdx.x / nwb;
-    const int m = mb * 64 + lane;
+    const int m0 = mb * 64 * kMPL + lane;  // the lane's frequencies m0 + 64 f
     const int z0 = (blockIdx.y * (blockDim.x >> 6) + wv) * kZB;
     if (z0 >= nz) return;  // whole wave; the kernel has no block-wide barrier
     const int zn = min(kZB, nz - z0);
     const long long ta = c * chunk;
     const long long tb = min(ta + chunk, nt);
-    const double om = w0 + (double)m * dw;
-    double rs, rc;
-    sincos(om, &rs, &rc);
-    double ar[kZB], ai[kZB];
+    double om[kMPL], rs[kMPL], rc[kMPL];
 #pragma unroll
-    for (int q = 0; q < kZB; ++q) ar[q] = ai[q] = 0.0;
-    // lane -> (row lane / 4, columns 2 (lane % 4) and 2 (lane % 4) + 1) of a tile
-    const int lr = lane >> 2, lc = 2 * (lane & 3);
-    double v0, v1;
+    for (int f = 0; f < kMPL; ++f) {
+        om[f] = w0 + (double)(m0 + 64 * f) * dw;
+        sincos(om[f], &rs[f], &rc[f]);
+    }
+    double ar[kMPL][kZB], ai[kMPL][kZB];
+#pragma unroll
+    for (int f = 0; f < kMPL; ++f)
+#pragma unroll
+        for (int q = 0; q < kZB; ++q) ar[f][q] = ai[f][q] = 0.0;
+    // lane -> row `lane` of a tile, all kZB columns
+    double v[kZB];
     auto fetch = [&](long long t) {
-        const long long u = t + lr;
-        v0 = (u < tb && lc < zn) ? x[u * nz + z0 + lc] : 0.0;
-        v1 = (u < tb && lc + 1 < zn) ? x[u * nz + z0 + lc + 1] : 0.0;
+        const long long u = t + lane;
+#pragma unroll
+        for (int q = 0; q < kZB; ++q) v[q] = (u < tb && q < zn) ? x[u * nz + z0 + q] : 0.0;
     };
     double2 *tw = tile[wv];
     fetch(ta);
     for (long long t = ta; t < tb; t += kAnchor) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        tw[lr * (kZB / 2) + (lc >> 1)] = make_double2(v0, v1);
+#pragma unroll
+        for (int h = 0; h < kZB / 2; ++h) tw[lane * (kZB / 2) + h] = make_double2(v[2 * h], v[2 * h + 1]);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (t + kAnchor < tb) fetch(t + kAnchor);
-        double s, co;
-        sincos(om * (t0 + (double)t), &s, &co);  // exp(-j theta) = co - j s
+        double s[kMPL], co[kMPL];
+#pragma unroll
+        for (int f = 0; f < kMPL; ++f) sincos(om[f] * (t0 + (double)t), &s[f], &co[f]);  // exp(-j theta) = co - j s
         const int nr = (int)min((long long)kAnchor, tb - t);
         for (int r = 0; r < nr; ++r) {
 #pragma unroll
             for (int h = 0; h < kZB / 2; ++h) {
                 const double2 v = tw[r * (kZB / 2) + h];
-                ar[2 * h] = fma(v.x, co, ar[2 * h]);
-                ai[2 * h] = fma(-v.x, s, ai[2 * h]);
-                ar[2 * h + 1] = fma(v.y, co, ar[2 * h + 1]);
-                ai[2 * h + 1] = fma(-v.y, s, ai[2 * h + 1]);
+#pragma unroll
+                for (int f = 0; f < kMPL; ++f) {
+                    ar[f][2 * h] = fma(v.x, co[f], ar[f][2 * h]);
+                    ai[f][2 * h] = fma(-v.x, s[f], ai[f][2 * h]);
+                    ar[f][2 * h + 1] = fma(v.y, co[f], ar[f][2 * h + 1]);
+                    ai[f][2 * h + 1] = fma(-v.y, s[f], ai[f][2 * h + 1]);
+                }
             }
             // exp(-j (theta + omega)) = (co - j s)(rc - j rs)
-            const double cn = fma(co, rc, -s * rs);
-            const double sn = fma(s, rc, co * rs);
-            co = cn;
-            s = sn;
+#pragma unroll
+            for (int f = 0; f < kMPL; ++f) {
+                const double cn = fma(co[f], rc[f], -s[f] * rs[f]);
+                const double sn = fma(s[f], rc[f], co[f] * rs[f]);
+                co[f] = cn;
+                s[f] = sn;
+            }
         }
     }
-    if (m < nw) {
-        double2 *dst = part + ((size_t)c * nw + m) * nz + z0;
 #pragma unroll
-        for (int q = 0; q < kZB; ++q)
-            if (q < zn) dst[q] = make_double2(ar[q], ai[q]);
+    for (int f = 0; f < kMPL; ++f) {
+        const int m = m0 + 64 * f;
+        if (m < nw) {
+            double2 *dst = part + ((size_t)c * nw + m) * nz + z0;
+#pragma unroll
+            for (int q = 0; q < kZB; ++q)
+                if (q < zn) dst[q] = make_double2(ar[f][q], ai[f][q]);
+        }
     }
 }
 
@@ -196,7 +213,7 @@ __global__ __launch_bounds__(64) void k_harmonic(const double *__restrict__ x, l
 // then one lane unwraps the phases along the columns and fits the two straight lines
 constexpr int kFitLds = 2048;
 
-__global__ __launch_bounds__(256) void k_wave_fit(const double2 *__restrict__ ph, int nslice, long long nt,
+__global__ __launch_bounds__(1024) void k_wave_fit(const double2 *__restrict__ ph, int nslice, long long nt,
                                                   const double *zpos, int nz, double omega, double2 *la,
                                                   double *__restrict__ out)
 {
@@ -322,12 +339,12 @@ inline long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 DftPlan dft_plan(long long nt, int nz, int nw, int nk)
 {
     DftPlan p;
-    p.nwb = (int)ceil_div(nw, 64);
+    p.nwb = (int)ceil_div(nw, 64 * kMPL);
     const int wpb = (int)std::min<long long>(4, ceil_div(nz, kZB));  // waves per block
     p.threads = 64 * wpb;
     p.nzb = (int)ceil_div(nz, (long long)wpb * kZB);
     long long nchunk = std::max<long long>(1, kTargetBlocks / ((long long)p.nwb * p.nzb));
-    nchunk = std::min(nchunk, std::max<long long>(1, ceil_div(nt, 4 * kAnchor)));
+    nchunk = std::min(nchunk, std::max<long long>(1, ceil_div(nt, kAnchor)));
     long long chunk = ceil_div(nt, nchunk);
     chunk = ceil_div(chunk, kAnchor) * kAnchor;
     p.chunk = chunk;
@@ -370,7 +387,7 @@ hipError_t launch_wave_fit(const double *x, long long nt, int nz, const double *
     double2 *ph = (double2 *)work;
     double2 *la = (double2 *)((char *)work + p.part_bytes);
     hipLaunchKernelGGL(k_harmonic, dim3(nz, p.nchunk), dim3(64), 0, st, x, nt, nz, t0, omega, p.chunk, ph);
-    hipLaunchKernelGGL(k_wave_fit, dim3(1), dim3(256), 0, st, (const double2 *)ph, p.nchunk, nt, zpos, nz, omega, la,
+    hipLaunchKernelGGL(k_wave_fit, dim3(1), dim3(1024), 0, st, (const double2 *)ph, p.nchunk, nt, zpos, nz, omega, la,
                        out);
     return hipGetLastError();
 }
