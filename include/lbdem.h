@@ -117,14 +117,20 @@ typedef struct lbdem_config {
                              ny * ceil(nx / 32) <= 8192; a third population buffer); -1 =
                              automatic (0 when max_particles spheres of max_radius could
                              cover at most a quarter of the set's cells; else 2 where every
-                             plane fits, else 1 for 16-bit storage and 0 otherwise).  Host access to populations, particle set-up
-                             and adjoint windows see the node layout either way. */
+                             plane fits, else 1 for 16-bit storage and 0 otherwise).  Host
+                             access to populations, particle set-up and adjoint windows see
+                             the node layout either way. */
     int32_t list_margin;  /* node lists: a lattice's lists are rebuilt once a particle's
                              displacement since the last rebuild plus list_margin times its
                              last step reaches the skin (12 times the lattice's largest last
                              step, within [0.05, 0.25] lu); 0..8, default 2.  Under compact
                              storage a node uncovered outside the lists anyway has its refill
                              kept until the rebuild that follows at the next step. */
+    int32_t fluid_off;    /* 1 = hydrodynamics switched off, as for the dry granular chain of
+                             Sec. 3.2: a step moves the particles under their contacts and
+                             F_g only (no fluid step, no link forces, no conversion momenta);
+                             the node map still follows the particles, while populations and
+                             probes carry no meaning; 0 (default) = the coupled step. */
 } lbdem_config;
 
 typedef struct lbdem_set lbdem_set;

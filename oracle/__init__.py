@@ -68,6 +68,7 @@ def lib():
         L.orc_rho_in_value.restype = D
         L.orc_rho_in_value.argtypes = [I, D, D, D, L64, L64]
         L.orc_set_frozen.argtypes = [P, I]
+        L.orc_set_fluid_off.argtypes = [P, I]
         L.orc_set_velocities.argtypes = [P, dp, dp]
         L.orc_adjoint.restype = I
         L.orc_adjoint.argtypes = [P, L64, D, D, dp, dp, dp, dp, dp]
@@ -175,6 +176,11 @@ class Sim:
     def set_frozen(self, frozen=True):
         """Frozen geometry: particles keep X, V, Omega; no DEM and no re-projection."""
         lib().orc_set_frozen(self._h, 1 if frozen else 0)
+
+    def set_fluid_off(self, off=True):
+        """Hydrodynamics switched off (the dry granular chain of Sec. 3.2): steps move the
+        particles under contacts and their own forces only."""
+        lib().orc_set_fluid_off(self._h, 1 if off else 0)
 
     def set_velocities(self, v=None, w=None):
         v = None if v is None else _f64(v).reshape(self.np, 3)

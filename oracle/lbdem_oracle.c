@@ -175,6 +175,7 @@ typedef struct {
     double *probe;
     long probe_cap;
     int frozen;     /* 1: particles keep X, V, Omega; no DEM and no re-projection */
+    int fluid_off;  /* 1: hydrodynamics switched off (Sec. 3.2, dry granular chain): DEM only */
 } orc_sim;
 
 static int axis_n(const orc_sim *s, int a) { return a == 0 ? s->p.nx : (a == 1 ? s->p.ny : s->p.nz); }
@@ -629,6 +630,16 @@ void orc_step(void *h, long nsteps)
 {
     orc_sim *s = (orc_sim *)h;
     for (long it = 0; it < nsteps; ++it) {
+        if (s->fluid_off) {
+            /* no fluid step: the particles feel contacts and their own forces only */
+            if (s->np > 0) {
+                const size_t b3 = (size_t)3 * s->np * sizeof(double);
+                memset(s->Fl, 0, b3); memset(s->Tl, 0, b3); memset(s->Ph, 0, b3); memset(s->Lh, 0, b3);
+                if (!s->frozen) dem(s);
+            }
+            s->t += 1;
+            continue;
+        }
         stream(s);
         boundary_collide_probe(s);
         if (!s->frozen) {
@@ -729,6 +740,7 @@ void orc_zou_he(double *f, double rho, int outlet) { zou_he(f, rho, outlet); }
  * faces through the columns of their affine map, streaming by following every
  * population to its single consumer. */
 void orc_set_frozen(void *h, int frozen) { ((orc_sim *)h)->frozen = frozen; }
+void orc_set_fluid_off(void *h, int off) { ((orc_sim *)h)->fluid_off = off; }
 
 void orc_set_velocities(void *h, const double *V, const double *W)
 {

@@ -75,6 +75,7 @@ struct Geometry {
     int listmode = 1;
     int compact = 0;
     int list_margin = 2;
+    int fluid_off = 0;
     long long rt_words = 0;
     int ring_len = 1;
     int chg_cap = 0;
@@ -95,6 +96,7 @@ int validate(int32_t n, const lbdem_params *lat, const lbdem_config *cfg)
     if (cfg->graph_steps < 0 || cfg->graph_steps > 64) return fail(LBDEM_EINVAL, "graph_steps must be 0..64");
     if (cfg->node_lists < -1 || cfg->node_lists > 2) return fail(LBDEM_EINVAL, "node_lists must be -1, 0, 1 or 2");
     if (cfg->list_margin < 0 || cfg->list_margin > 8) return fail(LBDEM_EINVAL, "list_margin must be 0..8");
+    if (cfg->fluid_off != 0 && cfg->fluid_off != 1) return fail(LBDEM_EINVAL, "fluid_off must be 0 or 1");
     for (int m = 0; m < n; ++m) {
         const lbdem_params &p = lat[m];
         if (cfg->node_lists == 2 && (long long)p.ny * ((p.nx + 31) / 32) > kMaxPlaneWords)
@@ -174,6 +176,7 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
     G.listmode = mode != 0 ? 1 : 0;
     G.compact = mode == 2 ? 1 : 0;
     G.list_margin = cfg->list_margin;
+    G.fluid_off = cfg->fluid_off;
     int nzt = cfg->z_per_thread ? cfg->z_per_thread : 2;
     int nzmin = lat[0].nz;
     for (int m = 1; m < n; ++m) nzmin = std::min(nzmin, lat[m].nz);
@@ -267,6 +270,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.listmode = G.listmode;
     s.compact = G.compact;
     s.list_margin = (double)G.list_margin;
+    s.fluid_off = G.fluid_off;
     s.es = (int)es;
     s.rt = c.take<uint2>((size_t)std::max<long long>(G.compact ? G.rt_words : 1, 1));
     s.popC = c.take<char>(G.compact ? es * kQ * (size_t)G.cells : 1);
@@ -500,15 +504,21 @@ int build_graph(lbdem_set *S, int steps)
         kp.gridDim = dim3(refresh_grid(S->ds));
         kp.kernelParams = fluid_args;
         HIPCHK(hipGraphAddKernelNode(&n4, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
-        kp.func = fluid_kernel_ptr(S->G.prec, S->G.compact);
-        kp.gridDim = dim3(S->ds.tiles_total);
-        kp.kernelParams = fluid_args;
-        HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n4, 1, &kp));
-        kp.func = links_kernel_ptr(S->G.prec);
-        kp.gridDim = dim3(links_grid(S->ds));
-        kp.blockDim = dim3(links_block());
-        kp.kernelParams = part_args;
-        HIPCHK(hipGraphAddKernelNode(&n0, S->graph, &n2, 1, &kp));
+        if (S->G.fluid_off) {
+            // hydrodynamics switched off: no fluid step and no link forces
+            n0 = n4;
+            kp.kernelParams = part_args;
+        } else {
+            kp.func = fluid_kernel_ptr(S->G.prec, S->G.compact);
+            kp.gridDim = dim3(S->ds.tiles_total);
+            kp.kernelParams = fluid_args;
+            HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n4, 1, &kp));
+            kp.func = links_kernel_ptr(S->G.prec);
+            kp.gridDim = dim3(links_grid(S->ds));
+            kp.blockDim = dim3(links_block());
+            kp.kernelParams = part_args;
+            HIPCHK(hipGraphAddKernelNode(&n0, S->graph, &n2, 1, &kp));
+        }
         kp.blockDim = dim3(256);
         kp.func = motion_kernel_ptr();
         kp.gridDim = dim3(motion_grid(S->ds));
@@ -546,6 +556,7 @@ int launch_step_eager(lbdem_set *S)
     static const int order[kKernels] = {4, 2, 0, 1, 3};
     for (int o = 0; o < kKernels; ++o) {
         const int k = order[o];
+        if (S->G.fluid_off && (k == 0 || k == 2)) continue;  // no link forces, no fluid step
         int e0 = -1, e1 = -1;
         if (S->timing) {
             if (S->ev_next + 2 > S->ev_pool.size()) {
@@ -592,6 +603,7 @@ int lbdem_default_config(lbdem_config *cfg)
     cfg->tile_x = 0;
     cfg->node_lists = -1;
     cfg->list_margin = 2;
+    cfg->fluid_off = 0;
     cfg->z_per_thread = 0;
     cfg->graph_steps = 8;
     return LBDEM_OK;

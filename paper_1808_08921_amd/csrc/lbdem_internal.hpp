@@ -67,6 +67,7 @@ struct MemberDev {
 // Everything a kernel needs, passed by value.
 struct DevSet {
     int nmem;
+    int fluid_off;            // 1: hydrodynamics switched off (particles feel contacts and F_g only)
     const MemberDev *mem;
     int tiles_total;
     int nzt;                  // z planes per fluid-kernel thread

@@ -1238,13 +1238,16 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
     // the link kernel's chunk sums (lane c * kChunks + q holds component c of chunk q) and
     // the rest of p's state for the update, loaded up front
     static_assert(6 * kChunks <= 64, "one lane per chunk-sum component");
+    // (with the hydrodynamics switched off there are neither link forces nor conversion
+    // momenta)
+    const bool hyd = !s.fluid_off;
     double ppv = 0.0;
-    if (mode == 0 && lane < 6 * kChunks)
+    if (mode == 0 && hyd && lane < 6 * kChunks)
         ppv = s.ppart[((long long)p * kChunks + lane % kChunks) * 6 + lane / kChunks];
     double Phv[3], Lhv[3], Fgv[3], Vpv[3], Wpv[3];
     for (int a = 0; a < 3; ++a) {
-        Phv[a] = s.Ph[3 * p + a];
-        Lhv[a] = s.Lh[3 * p + a];
+        Phv[a] = hyd ? s.Ph[3 * p + a] : 0.0;
+        Lhv[a] = hyd ? s.Lh[3 * p + a] : 0.0;
         Fgv[a] = s.Fg[3 * p + a];
         Vpv[a] = Vo[3 * p + a];
         Wpv[a] = Wo[3 * p + a];

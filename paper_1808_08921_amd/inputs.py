@@ -248,3 +248,20 @@ def settling_periodic_case(tau: float, n: int = 160, r0: float = 5.0, overlap: f
     pk = {"x": np.array([[n / 2.0, n / 2.0, n / 2.0]]), "radius": np.array([radius]),
           "fixed": np.zeros(1, np.uint8), "fg": np.array([[0.0, 0.0, fg]]), "shape": (n, n, n)}
     return params, pk
+
+
+def dry_chain_case(side: int = 16, length: int = 620, rho_p: float = 2.466):
+    """The dry granular chain of Sec. 3.2 (second benchmark, hydrodynamics switched off):
+    60 spheres of radius 5.005 at z = i (2R - 0.01) on the axis x = y = side / 2, the first
+    one moved to z = 10.001, E_p = 10, nu_p = 0.2.  Without fluid the lattice only hosts
+    the node map; its cross-section is `side` (the paper's 12 is narrower than the library
+    allows for a periodic axis around a sphere of this radius, which changes nothing here)."""
+    pk = chain_case(side=side, length=length)
+    x = pk["x"].copy()
+    x[0, 2] = 10.001
+    pk = dict(pk, x=x)
+    params = dict(nx=side, ny=side, nz=length, tau=1.0, rho_f=1.0,
+                  bc=(PERIODIC, PERIODIC, PERIODIC, PERIODIC, PRESSURE, PRESSURE), wave=WAVE_NONE, amp=0.0,
+                  omega=0.0, t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=rho_p, probe_z=(),
+                  max_particles=len(x), max_radius=6.0)
+    return params, pk

@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("probe_ring", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("z_per_thread", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("node_lists", ctypes.c_int32),
-                ("list_margin", ctypes.c_int32)]
+                ("list_margin", ctypes.c_int32), ("fluid_off", ctypes.c_int32)]
 
 
 _lib = None
@@ -153,7 +153,7 @@ class LatticeSet:
     """
 
     def __init__(self, lattices, precision="fp32", probe_ring=4096, tile_x=0, z_per_thread=0, graph_steps=8,
-                 device="cuda", node_lists=None, list_margin=None):
+                 device="cuda", node_lists=None, list_margin=None, fluid_off=False):
         import torch
 
         self._torch = torch
@@ -174,6 +174,8 @@ class LatticeSet:
             cfg.node_lists = int(node_lists)
         if list_margin is not None:
             cfg.list_margin = int(list_margin)
+        # hydrodynamics switched off (the dry granular chain of Sec. 3.2)
+        cfg.fluid_off = 1 if fluid_off else 0
         nbytes = ctypes.c_size_t()
         _check(L.lbdem_workspace_size(n, arr, ctypes.byref(cfg), ctypes.byref(nbytes)))
         self.workspace_bytes = nbytes.value

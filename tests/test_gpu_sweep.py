@@ -118,3 +118,30 @@ def test_mechanical_impulse_fcc_matches_oracle():
                 near = max(np.abs(o["v"][layer[k], 2]).max() for k in (1, 2, 3))
                 far = max(np.abs(o["v"][layer[k], 2]).max() for k in range(6, len(zl) - 1))
                 assert near > 1e-3 and far < 1e-5, (near, far)
+
+
+def test_dry_chain_fluid_off_matches_oracle():
+    """The dry granular chain of Sec. 3.2 (hydrodynamics switched off, first sphere moved by
+    1e-3 against the second): positions and velocities follow the oracle's DEM-only steps,
+    and the chain's momentum stays zero (contacts only)."""
+    torch, lb = _lb()
+    params, pk = inputs.dry_chain_case()
+    steps = 400
+    with lb.LatticeSet([params], precision="fp64", probe_ring=16, fluid_off=True) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], fixed=pk["fixed"])
+        gs.step(steps)
+        g = gs.particles_get(0)
+        assert gs.status() == 0
+    s = oracle.Sim(params["nx"], params["ny"], params["nz"], tau=params["tau"], bc=params["bc"], E=params["E"],
+                   nu=params["nu"], mu=params["mu"], rho_p=params["rho_p"])
+    s.set_fluid_off(True)
+    s.set_particles(pk["x"], pk["radius"], fixed=pk["fixed"])
+    s.step(steps)
+    o = s.particles()
+    assert np.abs(g["x"] - o["x"]).max() <= 1e-10 * np.abs(o["x"]).max()
+    vscale = np.abs(o["v"]).max()
+    assert vscale > 0
+    assert np.abs(g["v"] - o["v"]).max() <= 1e-10 * vscale
+    assert np.abs(g["force"]).max() == 0.0  # no hydrodynamic force
+    assert np.abs(o["v"].sum(0)).max() <= 1e-12 * vscale * len(o["v"])
+    assert np.abs(g["v"].sum(0)).max() <= 1e-12 * vscale * len(g["v"])

@@ -564,3 +564,23 @@ def test_settling_sphere_closed_box(orc):
     # bracketed by its inscribed (radius 16) and equal-area (radius 32/sqrt(pi))
     # cylinders: K = 2.7 ... 3.2; the bottom wall 10 lu below the sphere adds a little.
     assert 2.4 < ratio < 4.0
+
+
+def test_fluid_off_head_on_collision_is_elastic(orc):
+    """Hydrodynamics switched off (the dry granular chain of Sec. 3.2): two equal spheres
+    meeting head on under the undamped Hertz law of Eq. (fdLawn) leave with their velocities
+    exchanged (restitution 1, up to the integrator's error) and zero total momentum; the
+    fluid is not touched."""
+    s = orc.Sim(48, 24, 24, tau=1.0, bc=(0,) * 6, E=10.0, nu=0.2, mu=0.0, rho_p=2.0)
+    s.set_fluid_off(True)
+    f0 = s.populations()
+    v = 0.01
+    s.set_particles(np.array([[15.0, 12.0, 12.0], [25.4, 12.0, 12.0]]), np.array([5.0, 5.0]),
+                    v=np.array([[v, 0.0, 0.0], [-v, 0.0, 0.0]]))
+    s.step(300)
+    p = s.particles()
+    assert np.abs(p["v"].sum(0)).max() < 1e-17
+    assert p["v"][0, 0] == pytest.approx(-v, rel=1e-3)
+    assert p["v"][1, 0] == pytest.approx(v, rel=1e-3)
+    assert np.abs(p["v"][:, 1:]).max() == 0.0
+    assert np.array_equal(s.populations(), f0)
