@@ -171,7 +171,9 @@ int lbdem_set_stream(lbdem_set *set, void *hip_stream);
  * particle never moves and has V = Omega = 0).  v, w, fg and fixed may be NULL (zeros).
  * Populations are not modified.  Errors: LBDEM_EINVAL when n exceeds max_particles, a
  * radius is not positive or exceeds max_radius, a centre lies outside a non-periodic extent, or a periodic
- * axis is shorter than 2 R + 4. */
+ * axis is shorter than 2 R + 4 for a mobile particle, or not longer than 2 R for a fixed
+ * one (a node lies inside at most one image of a sphere; the re-projection and link
+ * discovery of a moving sphere need its own images farther away). */
 int lbdem_particles_set(lbdem_set *set, int32_t lattice, int32_t n, const double *x, const double *v,
                         const double *w, const double *radius, const double *fg, const uint8_t *fixed);
 

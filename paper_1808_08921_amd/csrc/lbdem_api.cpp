@@ -820,8 +820,12 @@ int lbdem_particles_set(lbdem_set *S, int32_t lattice, int32_t n, const double *
             double c = x[3 * q + a];
             if (!std::isfinite(c)) return fail(LBDEM_EINVAL, "particle %d: non-finite position", q);
             if (M.per[a]) {
-                if (dims[a] < 2.0 * R + 4.0)
-                    return fail(LBDEM_EINVAL, "particle %d: periodic axis %d shorter than 2R + 4", q, a);
+                // a node lies inside at most one image of a sphere; a moving sphere also
+                // needs its own images beyond the reach of its re-projection and links
+                const bool fixed_q = fixed && fixed[q];
+                if (fixed_q ? !(dims[a] > 2.0 * R) : dims[a] < 2.0 * R + 4.0)
+                    return fail(LBDEM_EINVAL, "particle %d: periodic axis %d shorter than %s", q, a,
+                                fixed_q ? "2R (fixed particle)" : "2R + 4");
                 c = std::fmod(c, (double)dims[a]);
                 if (c < 0.0) c += dims[a];
             } else if (c < 0.0 || c > dims[a] - 1) {

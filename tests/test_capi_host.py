@@ -109,3 +109,4 @@ def test_dft_workspace_size_and_validation(lb):
     # null pointers are rejected before any device work
     assert L.lbdem_st_dft(None, 10, 4, None, 0.0, 0.0, 0.1, 4, 0.0, 0.1, 4, None, None, None, 0, None) == lb.EINVAL
     assert L.lbdem_wave_fit(None, 10, 4, None, 0.0, 0.3, None, None, 0, None) == lb.EINVAL
+
