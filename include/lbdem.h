@@ -172,8 +172,11 @@ int lbdem_set_stream(lbdem_set *set, void *hip_stream);
  * Populations are not modified.  Errors: LBDEM_EINVAL when n exceeds max_particles, a
  * radius is not positive or exceeds max_radius, a centre lies outside a non-periodic extent, or a periodic
  * axis is shorter than 2 R + 4 for a mobile particle, or not longer than 2 R for a fixed
- * one (a node lies inside at most one image of a sphere; the re-projection and link
- * discovery of a moving sphere need its own images farther away). */
+ * one.  (A node lies inside at most one image of a sphere.  The torque arm and wall
+ * velocity of a node's links are taken from the node's nearest image, exact while a node
+ * borders one image only; in an axis shorter than 2 R + 4 a node midway between two images
+ * borders both, which a fixed sphere tolerates: its wall velocity is zero and only the
+ * torque it reports is affected.) */
 int lbdem_particles_set(lbdem_set *set, int32_t lattice, int32_t n, const double *x, const double *v,
                         const double *w, const double *radius, const double *fg, const uint8_t *fixed);
 
