@@ -408,7 +408,7 @@ def st_dft(x, zpos, t0, w0, dw, nw, k0, dk, nk, ridge=True, work=None):
     if work is None:
         work, nb = _workspace(torch, nt, nz, nw, nk, x.device)
     else:
-        nb = work.numel()
+        nb = work.numel() * work.element_size()
     F = torch.empty((nw, nk, 2), dtype=torch.float64, device=x.device)
     r = torch.empty(nw, dtype=torch.int32, device=x.device) if ridge else None
     st = torch.cuda.current_stream(x.device).cuda_stream
