@@ -614,8 +614,8 @@ def main():
         counters_workload(args.counters)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab decomposition is "
-              "a design note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); a slab decomposition over several "
+              "GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
