@@ -326,8 +326,11 @@ def _exact_owner(shape, X, R, periodic):
 
 
 def test_projection_matches_exact_rationals(orc):
-    # binary-exact centres and radii: ties d = R on nodes, overlapping spheres with
-    # equidistant nodes, and a sphere wrapping across the periodic x face
+    # binary-exact centres and radii: ties d = R on nodes (sphere 0 with R = 2 has nodes at
+    # offsets (2,0,0), (0,2,0), ...), two overlapping spheres (0 and 1: the lens nodes at
+    # x = 5, 6 lie nearer to one centre or the other, no node is equidistant; ties between
+    # spheres are pinned by the mirror-symmetric pair below), and a sphere wrapping across
+    # the periodic x face
     X = [(4.0, 4.0, 4.0), (7.0, 4.0, 4.0), (0.25, 8.5, 3.75), (10.0, 10.0, 8.0)]
     R = [2.0, 2.0, 2.5, 1.75]
     shape = (12, 13, 11)
@@ -336,6 +339,74 @@ def test_projection_matches_exact_rationals(orc):
     assert np.array_equal(s.owner(), _exact_owner(shape, X, R, (True, True, False)))
     own = s.owner()
     assert (own == 0).sum() > 0 and (own == 2)[:, :, -1].any()  # wrapped sphere reaches x = 11
+
+
+@pytest.mark.parametrize("swap", [False, True])
+def test_projection_tie_between_spheres_goes_to_smaller_index(orc, swap):
+    """Two spheres mirror-symmetric about the node (5, 5, 5): that node and its four
+    neighbours in the mirror plane x = 5 are equally far from both centres, and belong to
+    the sphere with the smaller index whichever of the two it is (reading of the silent
+    overlap case: smallest d^2, then smallest index)."""
+    X = [(4.0, 5.0, 5.0), (6.0, 5.0, 5.0)]
+    if swap:
+        X = X[::-1]
+    R = [1.5, 1.5]
+    shape = (11, 10, 10)
+    s = orc.Sim(*shape, tau=1.0, bc=(0, 0, 0, 0, 1, 1))
+    s.set_particles(np.array(X), np.array(R))
+    own = s.owner()
+    assert np.array_equal(own, _exact_owner(shape, X, R, (True, True, False)))
+    for i, j, k in [(5, 5, 5), (5, 4, 5), (5, 6, 5), (5, 5, 4), (5, 5, 6)]:
+        assert own[k, j, i] == 0
+    assert (own == 1).sum() == (own == 0).sum() - 5
+
+
+# ---------------------------------------------------------------------------
+# probes
+# ---------------------------------------------------------------------------
+def test_probe_fields_of_a_uniform_state(orc):
+    """A spatially uniform state of a periodic box streams onto itself and the collision
+    keeps rho and rho u, so every probe plane of n nodes reports n, n (rho - rho_f),
+    n rho u_z and n rho at every step, with rho and rho u the moments of the initial
+    populations (u with three different components, so that a transposed momentum
+    component or a wrong power of rho shows)."""
+    c = _printed_matrix().astype(float)
+    w = np.array([1 / 18] * 6 + [1 / 36] * 12 + [1 / 3])
+    nx, ny, nz = 5, 6, 7
+    rng = np.random.default_rng(21)
+    f0 = w * (1.0123 + 0.05 * rng.standard_normal(19))
+    rho, j = f0.sum(), f0 @ c
+    assert len({round(v, 12) for v in j}) == 3
+    s = orc.Sim(nx, ny, nz, tau=0.9, probe_z=(0, 3, 6))
+    s.set_populations(np.broadcast_to(f0[:, None, None, None], (19, nz, ny, nx)))
+    s.step(40)
+    pr = s.probes()
+    n = nx * ny
+    assert np.all(pr[:, :, 0] == n)
+    assert np.allclose(pr[:, :, 1], n * (rho - 1.0), rtol=1e-12, atol=0)
+    assert np.allclose(pr[:, :, 2], n * j[2], rtol=1e-12, atol=0)
+    assert np.allclose(pr[:, :, 3], n * rho, rtol=1e-14, atol=0)
+
+
+def test_probe_fields_match_plane_moments(orc):
+    """Probe records of a non-uniform periodic state against the plane sums of rho and
+    rho u_z recomputed with numpy from the populations after each step (the collision
+    keeps both moments, so the pre-collision moments the probes take are the same)."""
+    c = _printed_matrix().astype(float)
+    nx, ny, nz = 6, 5, 8
+    s = orc.Sim(nx, ny, nz, tau=0.7, probe_z=(1, 4, 7))
+    s.set_populations(inputs.random_populations((nx, ny, nz), amp=2e-2, seed=17))
+    for t in range(6):
+        s.step(1)
+        g = s.populations()
+        rho = g.sum(0)
+        jz = np.einsum("d...,d->...", g, c[:, 2])
+        pr = s.probes(t, 1)[0]
+        for k, z in enumerate((1, 4, 7)):
+            assert pr[k, 0] == nx * ny
+            assert pr[k, 1] == pytest.approx((rho[z] - 1.0).sum(), rel=1e-11, abs=1e-15)
+            assert pr[k, 2] == pytest.approx(jz[z].sum(), rel=1e-11, abs=1e-15)
+            assert pr[k, 3] == pytest.approx(rho[z].sum(), rel=1e-14)
 
 
 # ---------------------------------------------------------------------------
@@ -518,6 +589,49 @@ def test_symplectic_euler_free_motion(orc):
     p = s.particles()
     assert np.allclose(p["v"][0], a * 40, rtol=1e-9)
     assert np.allclose(p["x"][0], X0 + a * 40 * 41 / 2, rtol=1e-9)
+
+
+def test_fixed_sphere_keeps_its_state(orc):
+    """A fixed sphere (the end layers of the FCC packing, Sec. 4.1) keeps its position
+    bit for bit and V = Omega = 0, whatever it is given at set-up and whatever load it
+    feels (an external force and the fluid driven by the density face); a mobile twin
+    under the same load moves."""
+    kw = dict(tau=1.0, bc=(0, 0, 0, 0, 2, 2), wave=orc.WAVE_COSINE, amp=1e-2, omega=2 * math.pi / 20, t_n=20,
+              rho_p=1.0)
+    X = np.array([[8.3, 7.9, 12.2]])
+    runs = {}
+    for fixed in (1, 0):
+        s = orc.Sim(16, 16, 24, **kw)
+        s.set_particles(X, np.array([4.0]), v=np.array([[0.02, 0.0, -0.01]]), w=np.array([[0.0, 1e-3, 0.0]]),
+                        fg=np.array([[1e-2, -2e-2, 3e-2]]), fixed=np.array([fixed]))
+        s.step(30)
+        runs[fixed] = s.particles()
+    p = runs[1]
+    assert np.array_equal(p["x"], X)
+    assert not p["v"].any() and not p["w"].any()
+    assert np.abs(p["force"]).max() > 1e-6
+    assert np.abs(runs[0]["x"] - X).max() > 0.1
+
+
+def test_contact_across_periodic_seam(orc):
+    """Hydrodynamics off: two equal spheres meeting head on across the periodic x face
+    exchange their velocities (undamped Hertz, Eq. fdLawn), exactly as the same pair does
+    half a box away from the seam (translation invariance of the minimum image)."""
+    L, R, v = 48, 5.0, 0.01
+    out = []
+    for shift in (0.0, 24.0):
+        s = orc.Sim(L, 24, 24, tau=1.0, bc=(0,) * 6, E=10.0, nu=0.2, mu=0.0, rho_p=2.0)
+        s.set_fluid_off(True)
+        x = np.array([[5.2, 12.0, 12.0], [42.8, 12.0, 12.0]])
+        x[:, 0] = (x[:, 0] + shift) % L
+        s.set_particles(x, np.array([R, R]), v=np.array([[-v, 0.0, 0.0], [v, 0.0, 0.0]]))
+        s.step(300)
+        out.append(s.particles()["v"])
+    for vv in out:
+        assert vv[0, 0] == pytest.approx(v, rel=1e-3)
+        assert vv[1, 0] == pytest.approx(-v, rel=1e-3)
+        assert np.abs(vv.sum(0)).max() < 1e-17
+    assert np.allclose(out[0], out[1], rtol=1e-9, atol=1e-15)
 
 
 def test_hertz_binary_collision_duration(orc):
