@@ -17,15 +17,23 @@
  *   - Populations are stored post-collision, f~_d(x,t), as [19][ncell].
  *
  * One step t -> t+1 (the paper gives no order; this is the order used throughout):
- *   1. pull streaming (Eq. stream) with half-way bounce-back on moving particle
- *      surfaces (Eq. mem) and the momentum-exchange link force (Eq. fFS);
- *   2. pressure / density boundary on the z faces (Sec. "Acoustic source",
+ *   1. link pass: the link force of Eq. (fFS) with the bounce-back of Eq. (mem)
+ *      substituted is 2 c_d f~_d(x,t) minus a term linear in the particle's velocities;
+ *      per particle the first part (F0, T0) and the matrix Z of the second are summed;
+ *   2. DEM: Hertz normal / Mindlin tangential contacts (Eqs. fdLawn, fdLaws) at X(t),
+ *      Newton-Euler (Eqs. translate, rotate) with symplectic Euler, dt = 1, the velocity
+ *      of the step solved together with the momentum the fluid exchanges in it (the
+ *      implicit update of the momentum-exchange scheme of Ladd and Verberg, which the
+ *      paper cites for its coupling); the conversion impulses of the last re-projection
+ *      act here (Eqs. coupleF, coupleT);
+ *   3. pull streaming (Eq. stream) with half-way bounce-back on the particle surfaces at
+ *      X(t) moving with the new velocities (Eq. mem) and the link force (Eq. fFS);
+ *   4. pressure / density boundary on the z faces (Sec. "Acoustic source",
  *      non-equilibrium bounce-back) driven by the waveform (Eq. source, Table source);
- *   3. BGK collision (Eqs. bgk, BGKequili, rhoAndU);
- *   4. cross-section probes (Sec. "Pressure wave ..." and "Model parameters");
- *   5. DEM: Hertz normal / Mindlin tangential contacts (Eqs. fdLawn, fdLaws), Newton-Euler
- *      (Eqs. translate, rotate) with symplectic Euler, dt = 1;
- *   6. re-projection of the particles on the lattice and conversion of covered /
+ *   5. BGK collision (Eqs. bgk, BGKequili, rhoAndU);
+ *   6. cross-section probes (Sec. "Pressure wave ..." and "Model parameters");
+ *   7. the particles move, X(t+1) = X(t) + V(t+1);
+ *   8. re-projection of the particles on the lattice and conversion of covered /
  *      uncovered nodes (Eqs. convertFS, convertSF); the conversion impulses act on the
  *      particles in the next step's DEM update (Eqs. coupleF, coupleT).
  *
@@ -339,7 +347,7 @@ int orc_set_particles(void *h, int n, const double *x, const double *v, const do
 }
 
 /* ------------------------------------------------------------------------- */
-/* Step 1: streaming with boundaries.                                        */
+/* Streaming with boundaries.                                                */
 /* ------------------------------------------------------------------------- */
 /* Source classification for incoming direction e at node (i,j,k).
  * Returns 0 and the wrapped source node, 1 for a stationary half-way wall, 2 for a
@@ -410,7 +418,7 @@ static void stream(orc_sim *s)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Steps 2-4: density faces, collision, probes.                              */
+/* Density faces, collision, probes.                                         */
 /* ------------------------------------------------------------------------- */
 static void boundary_collide_probe(orc_sim *s)
 {
@@ -449,7 +457,7 @@ static void boundary_collide_probe(orc_sim *s)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Step 5: DEM.                                                              */
+/* DEM.                                                                      */
 /* ------------------------------------------------------------------------- */
 /* Contact of particle i with particle j (i's side).  Eq. (fdLawn): Hertz normal force
  * F_n = 2 E u_n sqrt(R* |u_n|) / (3(1 - nu^2)), R* = 1/(1/R_i + 1/R_j).
@@ -500,22 +508,99 @@ int orc_contact(const double *Xi, const double *Xj, double Ri, double Rj, const 
     return 1;
 }
 
-static void dem(orc_sim *s)
+/* Link pass.  For a link (fluid node x, direction e whose source x - c_e lies in particle
+ * q, d = e* pointing into q), Eq. (fFS) with Eq. (mem) substituted is
+ *   F = c_d f~_d(x,t) - c_e f_e(x,t+1) = 2 c_d f~_d(x,t) - (2 w_d / c_s^2) rho_f c_d (c_d . V_b),
+ * V_b = V_q + Omega_q x r_b, r_b = x_b - X_q, x_b = x + c_d/2.  With a_d = (c_d, r_b x c_d),
+ * c_d . V_b = a_d . (V, Omega), so the force and its torque r_b x F about X_q are
+ *   (F, T) = F0 - Z (V, Omega),   F0 = sum 2 f~_d(x,t) a_d,   Z = sum (2 w_d / c_s^2) rho_f a_d a_d^T.
+ * F0 [np][6] and Z [np][6][6] are summed here from f~(t) and the node map of time t. */
+static void link_pass(const orc_sim *s, double *F0, double *Z)
+{
+    const int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
+    const long N = s->ncell;
+    for (long q = 0; q < 6L * s->np; ++q) F0[q] = 0.0;
+    for (long q = 0; q < 36L * s->np; ++q) Z[q] = 0.0;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long n = ((long)k * ny + j) * nx + i;
+                if (s->owner[n] >= 0) continue;
+                for (int e = 0; e < Q - 1; ++e) {
+                    int si, sj, sk;
+                    if (source_of(s, i, j, k, e, &si, &sj, &sk) != 0) continue;
+                    int q = s->owner[((long)sk * ny + sj) * nx + si];
+                    if (q < 0) continue;
+                    int d = opposite(e);
+                    double xb[3] = {i + 0.5 * CX[d], j + 0.5 * CY[d], k + 0.5 * CZ[d]};
+                    double r[3], c[3] = {CX[d], CY[d], CZ[d]}, rc[3];
+                    for (int a = 0; a < 3; ++a) r[a] = min_image(s, a, xb[a] - s->X[3 * q + a]);
+                    cross(r, c, rc);
+                    double av[6] = {c[0], c[1], c[2], rc[0], rc[1], rc[2]};
+                    double f2 = 2.0 * s->f[d * N + n];
+                    double kz = 2.0 * weight(d) / CS2 * s->p.rho_f;
+                    for (int a = 0; a < 6; ++a) {
+                        F0[6 * q + a] += f2 * av[a];
+                        for (int b = 0; b < 6; ++b) Z[36 * q + 6 * a + b] += kz * av[a] * av[b];
+                    }
+                }
+            }
+}
+
+/* Solves A x = b for a symmetric positive definite 6 x 6 A by the Cholesky factorisation
+ * A = L L^T (forward, then backward substitution); b is overwritten by x. */
+static void cholesky_solve6(double A[6][6], double b[6])
+{
+    double L[6][6] = {{0}};
+    for (int j = 0; j < 6; ++j) {
+        double d = A[j][j];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        L[j][j] = sqrt(d);
+        for (int i = j + 1; i < 6; ++i) {
+            double v = A[i][j];
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            L[i][j] = v / L[j][j];
+        }
+    }
+    for (int i = 0; i < 6; ++i) {
+        double v = b[i];
+        for (int k = 0; k < i; ++k) v -= L[i][k] * b[k];
+        b[i] = v / L[i][i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double v = b[i];
+        for (int k = i + 1; k < 6; ++k) v -= L[k][i] * b[k];
+        b[i] = v / L[i][i];
+    }
+}
+
+/* DEM update of the velocities.  Eqs. (translate), (rotate) with symplectic Euler over the
+ * step, dt = 1: M (V', Omega') = M (V, Omega) + (F, T), where the hydrodynamic part of
+ * (F, T) is the momentum the fluid exchanges in this step, F0 - Z (V', Omega') (link pass),
+ * plus the conversion impulses of the last re-projection (Eqs. coupleF, coupleT); contacts
+ * (Hertz normal, Mindlin tangential) are evaluated at X(t), V(t), Omega(t), plus the
+ * external force.  Reading (the implicit update of the Ladd-Verberg momentum-exchange
+ * scheme): the fluid's bounce-back of this step uses the same velocities V', Omega' that
+ * this update produces, so (M + Z)(V', Omega') = M (V, Omega) + F0 + contacts + F_g +
+ * pending impulses, solved per particle.  (The explicit alternative, bounce-back at V(t)
+ * and the particle updated afterwards, lets a period-two mode of the thin fluid
+ * filaments next to the contacts of a dense packing grow.)  Fixed particles keep
+ * V = Omega = 0.  F_h, T_h first receive the pending impulses used here (the link part
+ * is added by the streaming step). */
+static void dem(orc_sim *s, const double *F0, const double *Z)
 {
     int np = s->np;
     double box[3];
     for (int a = 0; a < 3; ++a) box[a] = periodic(s, a) ? (double)axis_n(s, a) : 0.0;
-    double *Ftot = calloc((size_t)3 * (np > 0 ? np : 1), sizeof(double));
-    double *Ttot = calloc((size_t)3 * (np > 0 ? np : 1), sizeof(double));
+    double *rhs = calloc((size_t)6 * (np > 0 ? np : 1), sizeof(double));
     contact_rec *nh = calloc((size_t)(np > 0 ? np : 1) * s->hist_cap, sizeof(contact_rec));
     int *nn = calloc((size_t)(np > 0 ? np : 1), sizeof(int));
     for (int i = 0; i < np; ++i) {
-        /* Eqs. (coupleF), (coupleT): link sums + conversion impulses of the last remap */
         for (int a = 0; a < 3; ++a) {
-            s->Fh[3 * i + a] = s->Fl[3 * i + a] + s->Ph[3 * i + a];
-            s->Th[3 * i + a] = s->Tl[3 * i + a] + s->Lh[3 * i + a];
-            Ftot[3 * i + a] = s->Fh[3 * i + a] + s->Fg[3 * i + a];
-            Ttot[3 * i + a] = s->Th[3 * i + a];
+            s->Fh[3 * i + a] = s->Ph[3 * i + a];
+            s->Th[3 * i + a] = s->Lh[3 * i + a];
+            rhs[6 * i + a] = (F0 ? F0[6 * i + a] : 0.0) + s->Ph[3 * i + a] + s->Fg[3 * i + a];
+            rhs[6 * i + 3 + a] = (F0 ? F0[6 * i + 3 + a] : 0.0) + s->Lh[3 * i + a];
         }
         for (int j = 0; j < np; ++j) {
             if (j == i) continue;
@@ -526,7 +611,7 @@ static void dem(orc_sim *s)
             double F[3], T[3], ftn[3];
             if (orc_contact(s->X + 3 * i, s->X + 3 * j, s->R[i], s->R[j], s->V + 3 * i, s->V + 3 * j,
                             s->W + 3 * i, s->W + 3 * j, s->p.E, s->p.nu, s->p.mu, box, ft_old, F, T, ftn)) {
-                for (int a = 0; a < 3; ++a) { Ftot[3 * i + a] += F[a]; Ttot[3 * i + a] += T[a]; }
+                for (int a = 0; a < 3; ++a) { rhs[6 * i + a] += F[a]; rhs[6 * i + 3 + a] += T[a]; }
                 if (s->p.mu > 0.0 && nn[i] < s->hist_cap) {
                     contact_rec *rec = nh + i * s->hist_cap + nn[i]++;
                     rec->j = j;
@@ -535,12 +620,33 @@ static void dem(orc_sim *s)
             }
         }
     }
-    /* Eqs. (translate), (rotate), symplectic Euler with dt = 1; fixed particles stay. */
     for (int i = 0; i < np; ++i) {
         if (s->fixed[i]) continue;
+        double A[6][6], b[6];
+        for (int a = 0; a < 6; ++a) {
+            for (int c = 0; c < 6; ++c) A[a][c] = Z ? Z[36 * i + 6 * a + c] : 0.0;
+            double inertia = a < 3 ? s->m[i] : s->I[i];
+            A[a][a] += inertia;
+            b[a] = inertia * (a < 3 ? s->V[3 * i + a] : s->W[3 * i + a - 3]) + rhs[6 * i + a];
+        }
+        cholesky_solve6(A, b);
+        for (int a = 0; a < 3; ++a) { s->V[3 * i + a] = b[a]; s->W[3 * i + a] = b[3 + a]; }
+    }
+    for (int i = 0; i < 3 * np; ++i) { s->Ph[i] = 0.0; s->Lh[i] = 0.0; }
+    free(s->hist);
+    free(s->nhist);
+    s->hist = nh;
+    s->nhist = nn;
+    free(rhs);
+}
+
+/* Positions after the step: X(t+1) = X(t) + V(t+1) (symplectic Euler), wrapped on
+ * periodic axes; fixed particles stay. */
+static void move(orc_sim *s)
+{
+    for (int i = 0; i < s->np; ++i) {
+        if (s->fixed[i]) continue;
         for (int a = 0; a < 3; ++a) {
-            s->V[3 * i + a] += Ftot[3 * i + a] / s->m[i];
-            s->W[3 * i + a] += Ttot[3 * i + a] / s->I[i];
             double x = s->X[3 * i + a] + s->V[3 * i + a];
             if (periodic(s, a)) {
                 double n = (double)axis_n(s, a);
@@ -550,17 +656,10 @@ static void dem(orc_sim *s)
             s->X[3 * i + a] = x;
         }
     }
-    for (int i = 0; i < 3 * np; ++i) { s->Ph[i] = 0.0; s->Lh[i] = 0.0; }
-    free(s->hist);
-    free(s->nhist);
-    s->hist = nh;
-    s->nhist = nn;
-    free(Ftot);
-    free(Ttot);
 }
 
 /* ------------------------------------------------------------------------- */
-/* Step 6: re-projection with covered / uncovered node conversion.           */
+/* Re-projection with covered / uncovered node conversion.                   */
 /* ------------------------------------------------------------------------- */
 /* Readings of Eqs. (convertFS), (convertSF): the printed signs contradict the stated
  * purpose (momentum conservation); the conversions are applied so that fluid plus
@@ -634,18 +733,29 @@ void orc_step(void *h, long nsteps)
             /* no fluid step: the particles feel contacts and their own forces only */
             if (s->np > 0) {
                 const size_t b3 = (size_t)3 * s->np * sizeof(double);
-                memset(s->Fl, 0, b3); memset(s->Tl, 0, b3); memset(s->Ph, 0, b3); memset(s->Lh, 0, b3);
-                if (!s->frozen) dem(s);
+                memset(s->Ph, 0, b3); memset(s->Lh, 0, b3);
+                if (!s->frozen) { dem(s, NULL, NULL); move(s); }
             }
             s->t += 1;
             continue;
         }
-        stream(s);
-        boundary_collide_probe(s);
-        if (!s->frozen) {
-            dem(s);
-            remap(s);
+        if (s->frozen) {
+            stream(s);
+            boundary_collide_probe(s);
+            s->t += 1;
+            continue;
         }
+        double *F0 = calloc((size_t)6 * (s->np > 0 ? s->np : 1), sizeof(double));
+        double *Z = calloc((size_t)36 * (s->np > 0 ? s->np : 1), sizeof(double));
+        link_pass(s, F0, Z);
+        dem(s, F0, Z);
+        free(F0);
+        free(Z);
+        stream(s);
+        for (int q = 0; q < 3 * s->np; ++q) { s->Fh[q] += s->Fl[q]; s->Th[q] += s->Tl[q]; }
+        boundary_collide_probe(s);
+        move(s);
+        remap(s);
         s->t += 1;
     }
 }
