@@ -182,16 +182,29 @@ int lbdem_particles_set(lbdem_set *set, int32_t lattice, int32_t n, const double
 
 /* Copy the current particle state of lattice `lattice` to host arrays (n x 3 each, any
  * may be NULL): position, velocity, angular velocity, and the hydrodynamic force and
- * torque of the last step, F_f-s and T_f-s of Eqs. (coupleF), (coupleT) (link sums plus
- * the conversion impulses applied in that step).  n must equal the particle count. */
+ * torque of the last step, F_f-s and T_f-s of Eqs. (coupleF), (coupleT): the momentum
+ * its links exchanged with the fluid in that step plus the conversion impulses applied
+ * in it.  n must equal the particle count. */
 int lbdem_particles_get(lbdem_set *set, int32_t lattice, int32_t n, double *x, double *v, double *w,
                         double *force, double *torque);
 
-/* Queue nsteps coupled time steps of every lattice of the set.  Each step: the links of
- * every particle (moving-surface bounce-back values and link forces); contacts and
- * symplectic-Euler motion of the particles; pull streaming, density faces, BGK collision
- * and probes (one fused kernel); re-projection with refill / emptying.  Asynchronous;
- * errors found on the device are reported by lbdem_status. */
+/* Queue nsteps coupled time steps of every lattice of the set (Secs. 2.1-2.4; the paper
+ * gives no order, this is the library's).  Each step t -> t+1, one kernel each:
+ *   1. the node map of step t takes the previous re-projection's changes, and the link
+ *      words of the nodes around them are refreshed;
+ *   2. link pass: per particle, the link force of Eq. (fFS) with the bounce-back of
+ *      Eq. (mem) substituted, split into its part known from f~(t) and the matrix of its
+ *      part linear in the particle's velocities;
+ *   3. motion (Eqs. translate, rotate; symplectic Euler, dt = 1): Hertz / Mindlin contacts
+ *      (Eqs. fdLawn, fdLaws) at X(t), the external force, the conversion impulses of the
+ *      previous re-projection and the link force, the velocities of the step solved
+ *      together with the momentum the fluid exchanges in it (implicit in that momentum,
+ *      Eqs. coupleF, coupleT); X(t+1) = X(t) + V(t+1);
+ *   4. pull streaming (Eq. stream) with stationary walls and half-way bounce-back on the
+ *      particle surfaces at X(t) moving with the new velocities (Eq. mem), density faces
+ *      (Sec. 2.4), BGK collision (Eqs. bgk, BGKequili, rhoAndU) and probe sums;
+ *   5. re-projection at X(t+1) with refill / emptying (Eqs. convertFS, convertSF).
+ * Asynchronous; errors found on the device are reported by lbdem_status. */
 int lbdem_step(lbdem_set *set, int64_t nsteps);
 
 /* Number of steps taken so far (synchronises). */
@@ -221,6 +234,35 @@ int lbdem_populations_set(lbdem_set *set, int32_t lattice, const double *f);
 
 /* Node map of lattice `lattice`: -1 for fluid, else the index of the covering particle. */
 int lbdem_owner_get(lbdem_set *set, int32_t lattice, int32_t *owner);
+
+/* Macroscopic fields of lattice `lattice` at the current time level, computed on the
+ * device from the post-collision populations in FP64 (Eq. rhoAndU: rho = sum_d f_d, rho u
+ * = sum_d f_d c_d; the collision keeps both, so they are also the moments the step's
+ * collision used): rho [ncell], u [3][ncell] (component-major), owner [ncell] as for
+ * lbdem_owner_get.  At solid nodes rho and u are 0.  Any output may be NULL.  Host arrays;
+ * synchronises.  Errors: LBDEM_EINVAL, LBDEM_ENOMEM (device scratch), LBDEM_EDEVICE. */
+int lbdem_fields_get(lbdem_set *set, int32_t lattice, double *rho, double *u, int32_t *owner);
+
+/* ---- Checkpoint and resume ----
+ * A checkpoint holds the whole state of a set at a step boundary: populations, node maps
+ * and link words, particle state (positions, velocities, forces, pending conversion
+ * impulses, contact histories), the library's particle and node lists, the probe ring,
+ * the step counter and the status bits.  Stepping a set restored from a checkpoint taken
+ * after k steps for m more steps gives bit for bit the state of k + m steps.  A
+ * checkpoint loads only into a set created with the same parameters and configuration
+ * (graph_steps aside) by the same library build; no adjoint window may be bound to the
+ * set.  buf is caller-owned host memory. */
+
+/* Bytes of a checkpoint of the set. */
+int lbdem_state_size(lbdem_set *set, size_t *bytes);
+
+/* Write a checkpoint into buf (cap bytes; *used receives its size).  Synchronises.
+ * Errors: LBDEM_EINVAL (null argument), LBDEM_ENOMEM (cap too small), LBDEM_EDEVICE. */
+int lbdem_state_save(lbdem_set *set, void *buf, size_t cap, size_t *used);
+
+/* Restore the set from a checkpoint of `size` bytes.  Synchronises.  Errors: LBDEM_EINVAL
+ * (not a checkpoint of a set with these parameters), LBDEM_EDEVICE. */
+int lbdem_state_load(lbdem_set *set, const void *buf, size_t size);
 
 /* Kernel timing with HIP events on the set's stream.  While enabled, lbdem_step launches
  * kernels one by one and brackets every launch with a pair of events.  lbdem_timing_read

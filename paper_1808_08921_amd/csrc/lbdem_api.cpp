@@ -1,7 +1,7 @@
 // lbdem_api.cpp -- host side of the C interface declared in include/lbdem.h.
 //
 // Validates arguments, lays the device buffers of a set out in one workspace, uploads
-// the per-lattice tables, and queues the three step kernels, either one by one or as
+// the per-lattice tables, and queues the five step kernels, either one by one or as
 // replays of a HIP graph built from kernel nodes.  No step arithmetic happens here: the
 // host only prepares tables (waveform values, probe maps) and copies data in and out.
 #include <algorithm>
@@ -289,7 +289,6 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.own[1] = c.take<int>(G.cells);
     s.lw = c.take<unsigned long long>(2 * (size_t)G.cells);
     s.ncell_total = G.cells;
-    for (int k = 0; k < 4; ++k) s.fnode[k] = c.take<double>(4 * (size_t)G.cells);
     s.chg_cap = G.chg_cap;
     s.chg[0] = c.take<int>(2 * (size_t)G.chg_cap);
     s.chg[1] = c.take<int>(2 * (size_t)G.chg_cap);
@@ -323,7 +322,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.margin = c.take<double>(P);
     s.fixed = c.take<int>(P);
     s.pmem = c.take<int>(P);
-    s.ppart = c.take<double>((size_t)P * kChunks * 6);
+    s.ppart = c.take<double>((size_t)P * kChunks * kLinkComp);
     s.nearl = c.take<int>((size_t)P * kNearCap);
     s.nnear = c.take<int>(P);
     s.near_at = c.take<long long>(P);
@@ -334,6 +333,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.lcnt = c.take<int>(P);
     s.xcell = c.take<int>((size_t)P * G.lcap);
     s.xslot = c.take<int>((size_t)P * G.lcap);
+    s.xgrp = c.take<unsigned>((size_t)P * G.lcap);
     s.xcnt = c.take<int>((size_t)P * kChunks);
     s.lreb = c.take<long long>(P);
     s.ldirty = c.take<long long>((size_t)P * kChunks);
@@ -387,6 +387,7 @@ struct lbdem_set {
     lbdem_config cfg{};
     hipStream_t stream = nullptr;
     void *ws = nullptr;
+    size_t ws_bytes = 0;      // bytes of the workspace the set uses
     bool owns_ws = false;
     int64_t t_host = 0;
     // compact storage: populations currently held at their nodes (after creation or an
@@ -499,33 +500,38 @@ int build_graph(lbdem_set *S, int steps)
         kp.blockDim = dim3(256);
         kp.sharedMemBytes = 0;
         kp.extra = nullptr;
-        // refresh -> fluid -> links -> motion -> re-projection
+        // refresh -> links -> motion -> fluid -> re-projection
         kp.func = refresh_kernel_ptr(S->G.prec);
         kp.gridDim = dim3(refresh_grid(S->ds));
         kp.kernelParams = fluid_args;
         HIPCHK(hipGraphAddKernelNode(&n4, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
         if (S->G.fluid_off) {
-            // hydrodynamics switched off: no fluid step and no link forces
+            // hydrodynamics switched off: no link pass and no fluid step
             n0 = n4;
-            kp.kernelParams = part_args;
         } else {
-            kp.func = fluid_kernel_ptr(S->G.prec, S->G.compact);
-            kp.gridDim = dim3(S->ds.tiles_total);
-            kp.kernelParams = fluid_args;
-            HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n4, 1, &kp));
             kp.func = links_kernel_ptr(S->G.prec);
             kp.gridDim = dim3(links_grid(S->ds));
             kp.blockDim = dim3(links_block());
             kp.kernelParams = part_args;
-            HIPCHK(hipGraphAddKernelNode(&n0, S->graph, &n2, 1, &kp));
+            HIPCHK(hipGraphAddKernelNode(&n0, S->graph, &n4, 1, &kp));
         }
         kp.blockDim = dim3(256);
+        kp.kernelParams = part_args;
         kp.func = motion_kernel_ptr();
         kp.gridDim = dim3(motion_grid(S->ds));
         HIPCHK(hipGraphAddKernelNode(&n1, S->graph, &n0, 1, &kp));
+        if (S->G.fluid_off) {
+            n2 = n1;
+        } else {
+            kp.func = fluid_kernel_ptr(S->G.prec, S->G.compact);
+            kp.gridDim = dim3(S->ds.tiles_total);
+            kp.kernelParams = fluid_args;
+            HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n1, 1, &kp));
+        }
         kp.func = remap_kernel_ptr_prec(S->G.prec);
         kp.gridDim = dim3(remap_grid(S->ds));
-        HIPCHK(hipGraphAddKernelNode(&n3, S->graph, &n1, 1, &kp));
+        kp.kernelParams = part_args;
+        HIPCHK(hipGraphAddKernelNode(&n3, S->graph, &n2, 1, &kp));
         prev = n3;
     }
     HIPCHK(hipGraphInstantiate(&S->gexec, S->graph, nullptr, nullptr, 0));
@@ -551,9 +557,9 @@ int harvest_events(lbdem_set *S)
 
 int launch_step_eager(lbdem_set *S)
 {
-    // launch order refresh, fluid, links, motion, re-projection; timing slots keep the
+    // launch order refresh, links, motion, fluid, re-projection; timing slots keep the
     // order links, motion, fluid, re-projection, refresh of lbdem_timing_read
-    static const int order[kKernels] = {4, 2, 0, 1, 3};
+    static const int order[kKernels] = {4, 0, 1, 2, 3};
     for (int o = 0; o < kKernels; ++o) {
         const int k = order[o];
         if (S->G.fluid_off && (k == 0 || k == 2)) continue;  // no link forces, no fluid step
@@ -659,6 +665,7 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
         S->owns_ws = true;
     }
     carve(S->G, (char *)S->ws, S->ds);
+    S->ws_bytes = need;
     DevSet &s = S->ds;
     hipStream_t st = S->stream;
     auto cleanup = [&](int code) {
@@ -1133,6 +1140,166 @@ int lbdem_owner_get(lbdem_set *S, int32_t lattice, int32_t *owner)
     HIPCHK(hipMemcpy(owner, S->ds.own[t & 1] + M.cell_off, sizeof(int) * M.ncell, hipMemcpyDeviceToHost));
     for (long long k = 0; k < M.ncell; ++k)
         if (owner[k] >= 0) owner[k] -= M.p_off;
+    return LBDEM_OK;
+}
+
+int lbdem_fields_get(lbdem_set *S, int32_t lattice, double *rho, double *u, int32_t *owner)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    if (owner) {
+        rc = lbdem_owner_get(S, lattice, owner);
+        if (rc) return rc;
+    }
+    if (!rho && !u) return LBDEM_OK;
+    rc = node_layout(S);
+    if (rc) return rc;
+    const MemberDev &M = S->G.mem[lattice];
+    double *dev = nullptr;
+    hipError_t e = hipMalloc(&dev, sizeof(double) * 4 * (size_t)M.ncell);
+    if (e != hipSuccess) return fail(LBDEM_ENOMEM, "hipMalloc of the field scratch: %s", hipGetErrorString(e));
+    std::vector<double> host(4 * (size_t)M.ncell);
+    e = launch_fields(S->G.prec, S->ds, lattice, M.ncell, dev, S->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+    if (e == hipSuccess) e = hipMemcpy(host.data(), dev, sizeof(double) * host.size(), hipMemcpyDeviceToHost);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return fail(LBDEM_EDEVICE, "fields: %s", hipGetErrorString(e));
+    const size_t n = (size_t)M.ncell;
+    if (rho) std::memcpy(rho, host.data(), sizeof(double) * n);
+    if (u) std::memcpy(u, host.data() + n, sizeof(double) * 3 * n);
+    return LBDEM_OK;
+}
+
+} // extern "C"
+
+namespace {
+
+// Checkpoint layout: header, the host copy of the per-lattice constants, then the
+// workspace image without the scratch population buffer of compact storage (it holds
+// nothing between kernels).
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, n_lat;
+    uint64_t ws_bytes, skip_off, skip_bytes, digest;
+    int64_t t_host;
+    int32_t node_layout, reserved;
+};
+constexpr uint32_t kCkptVersion = 1;
+
+void fnv(uint64_t &h, const void *p, size_t n)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t k = 0; k < n; ++k) { h ^= b[k]; h *= 1099511628211ull; }
+}
+
+// Digest of everything a checkpoint depends on: every parameter field and the set-wide
+// configuration except graph_steps (field by field, so padding bytes do not enter).
+uint64_t set_digest(const lbdem_set *S)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (const lbdem_params &p : S->params) {
+        fnv(h, &p.nx, 12); fnv(h, p.face_bc, sizeof(p.face_bc)); fnv(h, &p.tau, 8); fnv(h, &p.rho_f, 8);
+        fnv(h, &p.wave, 4); fnv(h, &p.rho_amp, 8); fnv(h, &p.omega, 8); fnv(h, &p.t_n, 8); fnv(h, &p.young_E, 8);
+        fnv(h, &p.poisson_nu, 8); fnv(h, &p.friction_mu, 8); fnv(h, &p.rho_p, 8); fnv(h, &p.n_probe, 4);
+        fnv(h, p.probe_z, 4 * (size_t)std::max(0, std::min(p.n_probe, LBDEM_MAX_PROBES)));
+        fnv(h, &p.max_particles, 4); fnv(h, &p.max_radius, 8); fnv(h, &p.tile_x, 4);
+    }
+    const lbdem_config &c = S->cfg;
+    fnv(h, &c.precision, 4); fnv(h, &c.probe_ring, 4); fnv(h, &c.tile_x, 4); fnv(h, &c.z_per_thread, 4);
+    fnv(h, &c.node_lists, 4); fnv(h, &c.list_margin, 4); fnv(h, &c.fluid_off, 4);
+    const uint64_t ws = S->ws_bytes;
+    fnv(h, &ws, 8);
+    return h;
+}
+
+void ckpt_ranges(const lbdem_set *S, uint64_t &skip_off, uint64_t &skip_bytes)
+{
+    skip_off = (uint64_t)((const char *)S->ds.popC - (const char *)S->ws);
+    skip_bytes = S->G.compact ? (uint64_t)elem_size(S->G.prec) * kQ * (uint64_t)S->G.cells : 0;
+}
+
+} // namespace
+
+extern "C" {
+
+int lbdem_state_size(lbdem_set *S, size_t *bytes)
+{
+    if (!S || !bytes) return fail(LBDEM_EINVAL, "null argument");
+    uint64_t so, sb;
+    ckpt_ranges(S, so, sb);
+    *bytes = sizeof(CkptHeader) + sizeof(MemberDev) * S->G.mem.size() + (S->ws_bytes - sb);
+    return LBDEM_OK;
+}
+
+int lbdem_state_save(lbdem_set *S, void *buf, size_t cap, size_t *used)
+{
+    if (!S || !buf) return fail(LBDEM_EINVAL, "null argument");
+    size_t need = 0;
+    int rc = lbdem_state_size(S, &need);
+    if (rc) return rc;
+    if (cap < need) return fail(LBDEM_ENOMEM, "checkpoint needs %zu bytes, buffer holds %zu", need, cap);
+    rc = sync_set(S);
+    if (rc) return rc;
+    CkptHeader h{};
+    std::memcpy(h.magic, "LBDEMCKP", 8);
+    h.version = kCkptVersion;
+    h.n_lat = (uint32_t)S->G.mem.size();
+    h.ws_bytes = S->ws_bytes;
+    ckpt_ranges(S, h.skip_off, h.skip_bytes);
+    h.digest = set_digest(S);
+    h.t_host = S->t_host;
+    h.node_layout = S->node_layout ? 1 : 0;
+    char *o = (char *)buf;
+    std::memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    std::memcpy(o, S->G.mem.data(), sizeof(MemberDev) * S->G.mem.size());
+    o += sizeof(MemberDev) * S->G.mem.size();
+    const char *ws = (const char *)S->ws;
+    HIPCHK(hipMemcpy(o, ws, h.skip_off, hipMemcpyDeviceToHost));
+    o += h.skip_off;
+    const uint64_t tail = h.ws_bytes - h.skip_off - h.skip_bytes;
+    HIPCHK(hipMemcpy(o, ws + h.skip_off + h.skip_bytes, tail, hipMemcpyDeviceToHost));
+    if (used) *used = need;
+    return LBDEM_OK;
+}
+
+int lbdem_state_load(lbdem_set *S, const void *buf, size_t size)
+{
+    if (!S || !buf) return fail(LBDEM_EINVAL, "null argument");
+    CkptHeader h;
+    if (size < sizeof(h)) return fail(LBDEM_EINVAL, "not a checkpoint (too short)");
+    std::memcpy(&h, buf, sizeof(h));
+    if (std::memcmp(h.magic, "LBDEMCKP", 8) != 0 || h.version != kCkptVersion)
+        return fail(LBDEM_EINVAL, "not a checkpoint of this library");
+    uint64_t so, sb;
+    ckpt_ranges(S, so, sb);
+    if (h.n_lat != S->G.mem.size() || h.ws_bytes != S->ws_bytes || h.skip_off != so || h.skip_bytes != sb ||
+        h.digest != set_digest(S))
+        return fail(LBDEM_EINVAL, "checkpoint of a set with other parameters");
+    size_t need = 0;
+    int rc = lbdem_state_size(S, &need);
+    if (rc) return rc;
+    if (size != need) return fail(LBDEM_EINVAL, "checkpoint of %zu bytes, %zu expected", size, need);
+    rc = sync_set(S);
+    if (rc) return rc;
+    const char *in = (const char *)buf + sizeof(h);
+    std::vector<MemberDev> mem(h.n_lat);
+    std::memcpy(mem.data(), in, sizeof(MemberDev) * h.n_lat);
+    in += sizeof(MemberDev) * h.n_lat;
+    char *ws = (char *)S->ws;
+    HIPCHK(hipMemcpy(ws, in, h.skip_off, hipMemcpyHostToDevice));
+    in += h.skip_off;
+    HIPCHK(hipMemcpy(ws + h.skip_off + h.skip_bytes, in, h.ws_bytes - h.skip_off - h.skip_bytes,
+                     hipMemcpyHostToDevice));
+    // the host's copy of the per-lattice constants (particle counts, fluid-kernel grid)
+    S->G.mem = mem;
+    int tiles = 0;
+    for (const MemberDev &M : S->G.mem) tiles = std::max(tiles, M.tile_off + M.ntx * M.nty * M.ntz);
+    S->G.tiles = tiles;
+    S->ds.tiles_total = tiles;
+    S->t_host = h.t_host;
+    S->node_layout = h.node_layout != 0;
+    if (S->gexec) return build_graph(S, S->graph_steps);
     return LBDEM_OK;
 }
 

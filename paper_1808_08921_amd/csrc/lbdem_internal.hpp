@@ -26,7 +26,10 @@ constexpr double kListSkin = 0.25;
 constexpr double kSkinMin = 0.05;
 constexpr double kSkinSteps = 12.0;
 constexpr int kPendCap = 16384;     // refills of unlisted nodes awaiting the next list rebuild
-constexpr int kChunks = 8;          // workgroups per particle in the particle kernel
+constexpr int kChunks = 8;          // waves per particle in the link pass
+// components of a link-pass partial: F0 (3), T0 (3), then the upper triangle of the 6 x 6
+// matrix Z of the velocity-dependent link force, row by row (21)
+constexpr int kLinkComp = 27;
 constexpr int kEmpty = 0x7fffffff;
 // Link words of a fluid node x (two 64-bit words per node: lw[c] and lw[ncell_total + c]).
 // Word 0: bits 0-17 the directions e whose source x - c_e is inside a particle, bits 18-35
@@ -101,11 +104,6 @@ struct DevSet {
     int *own[2];
     unsigned long long *lw;   // link words, two per node (all lattices) [2*ncell_total]
     long long ncell_total;
-    // per slot of a fluid node's link words: the deviation part of the link force
-    // sum c_d (df~_d + df_e) over its links to that particle and the link directions
-    // (bit pattern of the last component); FP64 (or FP32) records [ncell_total][4] per
-    // slot, at the node's storage slot (its rank in the lists under compact storage)
-    double *fnode[4];
     int *chg[2];
     int chg_cap;
     int *chgcnt;              // [2]
@@ -121,9 +119,10 @@ struct DevSet {
     int ptot;
     double *X[2], *V[2], *W[2];
     double *R, *m, *I, *Fg, *Fh, *Th, *Ph, *Lh, *Xref, *margin;
-    float *pf[2];             // FP32 copy of X, V, Omega per particle (12 floats), by parity
+    float *pf[2];             // FP32 wall state of the fluid kernel per particle (12 floats): X(t) and the
+                              // velocities V, Omega of step t, at the parity of t
     int *fixed, *pmem;
-    double *ppart;            // link-force partials per (particle, chunk) [ptot*kChunks*6]
+    double *ppart;            // link-pass partials per (particle, chunk) [ptot*kChunks*kLinkComp]
     int *nearl, *nnear;       // [ptot*kNearCap], [ptot]
     long long *near_at;       // step at which each near list was built [ptot]
     // shell list per particle around X_ref: node, d_ref - R, link-candidate directions
@@ -135,6 +134,7 @@ struct DevSet {
     // its own compacted run [ptot*lcap], counts [ptot*kChunks]
     int *xcell, *xcnt;
     int *xslot;               // storage slot of each cached entry's node [ptot*lcap]
+    unsigned *xgrp;           // the particle's link directions at each cached entry's node [ptot*lcap]
     long long *lreb;          // step after which the shell list was last rebuilt [ptot]
     long long *ldirty;        // last step in which a node of a chunk's z-slab, or next to
                               // it, changed owner [ptot*kChunks]
@@ -188,6 +188,7 @@ hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_remap_prec(int prec, const DevSet &s, int mode, int only_member, hipStream_t st);
 hipError_t launch_init_pops(int prec, const DevSet &s, long long total_cells, hipStream_t st);
 hipError_t launch_expand(int prec, const DevSet &s, hipStream_t st);
+hipError_t launch_fields(int prec, const DevSet &s, int m, long long ncell, double *out, hipStream_t st);
 // kernel entry points and grid sizes, for building HIP graphs
 void *refresh_kernel_ptr(int prec);
 void *links_kernel_ptr(int prec);

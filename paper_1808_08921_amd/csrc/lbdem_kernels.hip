@@ -3,26 +3,33 @@
 // Method: Cheng, Luding, Rivas, Harting, Magnanimo, "Hydro-micromechanical modeling of
 // wave propagation in saturated granular media", arXiv 1808.08921, Sec. 2.
 //
-// Four kernels make one time step t -> t+1 of every lattice of a set, in this order:
-//   k_fluid      one thread per (x, y) column of a tile, nzt planes deep: refreshes the
-//                tile's link words from the previous step's node changes, then pull
-//                streaming (Eq. stream) with stationary walls and, from each link of a
-//                fluid node to a particle, the moving-wall bounce-back of Eq. (mem); the
-//                density faces (Sec. 2.4), BGK collision (Eqs. bgk, BGKequili, rhoAndU),
-//                probe partial sums, and per node and particle the sum c_d f~_d over its
-//                links for the momentum exchange.
-//   k_links      kChunks workgroups per particle: the link force and torque of Eq. (fFS)
-//                over the particle's shell list, summed in a fixed order.
-//   k_motion     one workgroup per particle: Eqs. (coupleF), (coupleT) with the
-//                conversion impulses of the previous re-projection, Hertz / Mindlin
-//                contacts (Eqs. fdLawn, fdLaws), symplectic Euler (Eqs. translate, rotate).
-//   k_remap      one workgroup per particle: re-projects the particle on the lattice
-//                (Sec. 2.3) where its motion can have changed a node, converts covered
-//                and uncovered nodes (Eqs. convertFS, convertSF) and records the
-//                impulses that act in the next step; extra workgroups reduce the probe
-//                planes; the step counter advances.
-// The population layout is SoA [19][nz][ny][nx] per lattice; the fluid kernel is
-// bound by HBM bandwidth (about 1.5 flop per byte at FP32) and uses no MFMA.
+// Five kernels make one time step t -> t+1 of every lattice of a set, in this order
+// (Secs. 2.1-2.4; the paper gives no order, this one is the build's reading):
+//   k_refresh    brings the node map of step t up to date with the previous re-projection's
+//                changes, refreshes the link words of the changed nodes and their
+//                neighbours, and rebuilds the node lists (moving the populations of changed
+//                planes under compact storage) once a particle may have crossed their skin.
+//   k_links      kChunks waves per particle: the link pass.  With Eq. (mem) substituted, the
+//                link force of Eq. (fFS) is 2 c_d f~_d(x,t) minus a term linear in the
+//                particle's velocities; per (particle, chunk) the first part and its torque
+//                (F0, T0) and the 6 x 6 matrix Z of the second are summed in FP64 from f~(t).
+//   k_motion     one wave per particle: contacts (Eqs. fdLawn, fdLaws) at X(t), then the
+//                velocities of the step from (M + Z)(V', Omega') = M (V, Omega) + F0 + contacts
+//                + F_g + the conversion impulses of the previous re-projection (Eqs. translate,
+//                rotate, coupleF, coupleT; implicit in the exchanged momentum), X(t+1).
+//   k_fluid      one thread per listed node of a z plane (compact storage, the default), or
+//                per node of a dense tile: pull streaming (Eq. stream) with stationary walls,
+//                moving half-way bounce-back at the particles' new velocities (Eq. mem), the
+//                density faces (Sec. 2.4), BGK collision (Eqs. bgk, BGKequili, rhoAndU) and
+//                probe partial sums.
+//   k_remap      one wave per particle: re-projects the particle on the lattice (Sec. 2.3)
+//                where its motion can have changed a node, converts covered and uncovered
+//                nodes (Eqs. convertFS, convertSF) and records the impulses that act in the
+//                next step; extra workgroups reduce the probe planes; the step counter
+//                advances.
+// Populations are SoA, [19][nz][ny][nx] per lattice in the node layout, or per z plane at
+// the ranks of the plane's listed nodes under compact storage.  The fluid kernel is bound
+// by HBM bandwidth (about 1.5 flop per byte at FP32) and uses no MFMA.
 #include "lbdem_internal.hpp"
 
 namespace lbdem {
@@ -474,7 +481,7 @@ __device__ __forceinline__ void mark_words(const DevSet &s, const MemberDev *M, 
 // ---------------------------------------------------------------------------
 // fluid kernel
 // ---------------------------------------------------------------------------
-// FP32 copy of a particle's state for the fluid kernel: X, V, Omega, padding
+// FP32 copy of a particle's wall state for the fluid kernel: X, V, Omega, padding
 __device__ __forceinline__ void pack_state(float *o, const double *X, const double *V, const double *W)
 {
     for (int a = 0; a < 3; ++a) { o[a] = (float)X[a]; o[4 + a] = (float)V[a]; o[8 + a] = (float)W[a]; }
@@ -504,12 +511,13 @@ __device__ __forceinline__ void wall_velocity_f(const MemberDev *M, const float4
 
 // Velocity of particle q's surface point nearest to node (i, j, k), V_b = V + Omega x r
 // with r = x - X (minimum image), in the collision precision C; used with c_d . V_b for
-// the link (x, d).
+// the link (x, d).  X is the position at time t, V and Omega the velocities of the step
+// (written by the motion kernel at the other parity).
 template <typename C>
 __device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *M, int q, int i, int j, int k,
                                               int par, C &u0, C &u1, C &u2)
 {
-    const double *X = s.X[par] + 3 * q, *V = s.V[par] + 3 * q, *W = s.W[par] + 3 * q;
+    const double *X = s.X[par] + 3 * q, *V = s.V[par ^ 1] + 3 * q, *W = s.W[par ^ 1] + 3 * q;
     const C r0 = (C)mimg((double)i - X[0], M->per[0], M->box[0]);
     const C r1 = (C)mimg((double)j - X[1], M->per[1], M->box[1]);
     const C r2 = (C)mimg((double)k - X[2], M->per[2], M->box[2]);
@@ -521,14 +529,12 @@ __device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *
 
 // Eq. (mem) for the links of a fluid node: f_e = f~_d(x,t) - 2 (w_d / c_s^2) rho_f V_b . c_d,
 // d = e*, for every direction e whose source is inside a particle; f[e] holds the deviation
-// f~_d(x,t) - w_d rho_f (the same relation holds for deviations since w_e = w_d).  For the
-// momentum exchange of Eq. (fFS), F = sum c_d (f~_d + f_e) over the node's links to one
-// particle = D + 2 rho_f sum c_d w_d with the deviation part D = sum c_d (df~_d + df_e); the
-// node stores D (collision precision) and the link directions per slot of its link words,
-// and the link kernel adds the rest-state part in FP64.
+// f~_d(x,t) - w_d rho_f (the same relation holds for deviations since w_e = w_d).  V_b comes
+// from the particle's position at t and its velocities of the step; the momentum these
+// links exchange was accounted for by the link pass and the motion kernel.
 template <typename C>
 __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M, C (&f)[kQ], unsigned long long w0,
-                                            int i, int j, int k, int par, double rho_f, long long gc, long long gr)
+                                            int i, int j, int k, int par, double rho_f, long long gc)
 {
     const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + gc] : 0ull;
     const int ng = (w0 >> 62) ? 4 : 2;
@@ -545,7 +551,6 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
         } else {
             wall_velocity<C>(s, M, M->p_off + q, i, j, k, par, u0, u1, u2);
         }
-        C G0 = C(0), G1 = C(0), G2 = C(0);
 #pragma unroll
         for (int e = 0; e < kQ - 1; ++e) {
             if (!((grp >> e) & 1u)) continue;
@@ -554,21 +559,7 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
             if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
             if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
             if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
-            const C fo = f[e];
-            const C fe = fo - (C)(kMW[d] * rho_f) * cu;
-            f[e] = fe;
-            const C fs = fo + fe;
-            if (kCX[d] > 0) G0 += fs; else if (kCX[d] < 0) G0 -= fs;
-            if (kCY[d] > 0) G1 += fs; else if (kCY[d] < 0) G1 -= fs;
-            if (kCZ[d] > 0) G2 += fs; else if (kCZ[d] < 0) G2 -= fs;
-        }
-        // the record: the deviation part of F and the link directions (bit pattern)
-        if constexpr (sizeof(C) == 4) {
-            reinterpret_cast<float4 *>(s.fnode[g])[gr] = make_float4(G0, G1, G2, __uint_as_float(grp));
-        } else {
-            double2 *fn = reinterpret_cast<double2 *>(s.fnode[g] + 4 * gr);
-            fn[0] = make_double2(G0, G1);
-            fn[1] = make_double2(G2, __longlong_as_double((long long)grp));
+            f[e] = f[e] - (C)(kMW[d] * rho_f) * cu;
         }
     }
 }
@@ -946,7 +937,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     #pragma unroll
                 for (int e = 0; e < kQ; ++e)
                     f[e] = (fl && !((unk >> e) & 1u)) ? decode_dev<P>(raw[e], e, rho_fd) : C(0);
-                if (lmask != 0u) moving_wall<C>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell, cell_off + me);
+                if (lmask != 0u) moving_wall<C>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell);
 
                 if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, drho_in, false);
                 if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, C(0), true);
@@ -1028,16 +1019,6 @@ __device__ __forceinline__ void axis_range(double c, double h, int n, int per, i
 }
 
 
-// One wave per (particle p, chunk of p's shell list): the momentum exchange of p's links,
-// i.e. of every fluid node x and direction e whose source x - c_e lies in p.  With d = e*
-// pointing into p, Eq. (fFS) gives F = c_d f~_d(x,t) - c_e f_e(x,t+1) = c_d (f~_d + f_e),
-// and Eq. (mem) f_e = f~_d - 2 (w_d / c_s^2) rho_f V_b . c_d, V_b = V_p + Omega_p x
-// (x_b - X_p) at x_b = x + c_d / 2.  Since x_b - X_p = (x - X_p) + c_d / 2, V_b . c_d =
-// c_d . (V_p + Omega_p x (x - X_p)), and the torque (x_b - X_p) x F = (x - X_p) x F.  The
-// fluid kernel of the step has stored G = sum c_d f~_d over the node's links to p; here
-// F = 2 G - sum 2 (w_d / c_s^2) rho_f c_d (c_d . V_b), summed in FP64 in a fixed order per
-// chunk (Eqs. coupleF, coupleT).  A chunk holds ~100-200 links, so a single wave serves it
-// with its loads batched kLinkBatch entries deep, and the whole grid is resident at once.
 // n / d for 0 <= n < 2^31 and a divisor d > 0 that every lane shares, through the FP64
 // reciprocal (rounded within one unit of the quotient, then corrected)
 __device__ __forceinline__ int div_uni(int n, int d, double inv)
@@ -1050,10 +1031,10 @@ __device__ __forceinline__ int div_uni(int n, int d, double inv)
 }
 
 constexpr int kLinksBlock = 64;
-constexpr int kLinkBatch = 4;
-// Link-direction masks for the rest-state part of a link force, 2 rho_f sum_d w_d c_d over
-// the links e (d = e*, so c_d = -c_e): per axis and weight class (w = 1/18 on the axes,
-// e < 6; 1/36 on the diagonals), the links whose c_d component is +1 or -1.
+constexpr int kLinkBatch = 1;
+// Direction masks over the links e (d = e*, c_d = -c_e), for sums over a node's links by
+// counting: per axis and weight class (w = 1/18 on the axes, e < 6; 1/36 on the
+// diagonals) the links whose c_d component is +1 or -1 ...
 constexpr unsigned link_mask(int axis, int sign, bool diag)
 {
     unsigned m = 0u;
@@ -1063,9 +1044,34 @@ constexpr unsigned link_mask(int axis, int sign, bool diag)
     }
     return m;
 }
+// ... and the diagonal links whose components along axes a and b have the product +1 or -1
+constexpr unsigned pair_mask(int a, int b, int sign)
+{
+    unsigned m = 0u;
+    for (int e = 6; e < kQ - 1; ++e) {
+        const int ca = a == 0 ? kCX[e] : a == 1 ? kCY[e] : kCZ[e];
+        const int cb = b == 0 ? kCX[e] : b == 1 ? kCY[e] : kCZ[e];
+        if (ca * cb == sign) m |= 1u << e;
+    }
+    return m;
+}
+
+// Link pass, one wave per (particle p, chunk of p's shell list).  A link of p is a fluid
+// node x and a direction e whose source x - c_e lies in p; with d = e* pointing into p,
+// Eq. (fFS) with Eq. (mem) substituted gives
+//   F = c_d f~_d(x,t) - c_e f_e(x,t+1) = 2 c_d f~_d(x,t) - (2 w_d / c_s^2) rho_f c_d (c_d . V_b),
+// V_b = V_p + Omega_p x (x_b - X_p), x_b = x + c_d/2.  Since (x_b - X_p) x c_d = (x - X_p) x c_d
+// = r x c_d, the force and its torque about X_p over the step are (F, T) = F0 - Z (V, Omega)
+// with F0 = (G, r x G), G = sum 2 c_d f~_d(x,t), and Z = sum (2 w_d / c_s^2) rho_f a_d a_d^T,
+// a_d = (c_d, r x c_d).  Per node, with S = sum over its links to p of 6 w_d rho_f c_d c_d^T
+// and [r] the matrix of r x .: Z_VV = S, Z_OmegaV = [r] S, Z_OmegaOmega = [r] S [r]^T.  G is
+// summed from the deviations f~_d - w_d rho_f (the rest part 2 rho_f sum w_d c_d and S come
+// from counts of links per direction class), the sums over the chunk in FP64 in a fixed
+// order; the motion kernel adds the chunks in chunk order and solves for (V, Omega).
 template <int P>
 __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int only)
 {
+    using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
@@ -1085,7 +1091,9 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
     const long long cell_off = uni(M->cell_off);
     const double rho_f = uni(M->rho_f);
+    const int nc = (int)uni(M->ncell);
     const int nxy = nx * ny;
+    const S *A = (const S *)(par ? s.popB : s.popA) + uni(M->pop_off);
     const long long lbase = (long long)p * s.lcap;
     const int k0 = s.lchunk[p * (kChunks + 1) + chunk], k1 = s.lchunk[p * (kChunks + 1) + chunk + 1];
     // (a list rebuild under compact storage moves the nodes' storage slots)
@@ -1094,43 +1102,40 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     const int cnt_old = s.xcnt[p * kChunks + chunk];
     int *xc = s.xcell + lbase + k0;
     int *xs = s.xslot + lbase + k0;
-
-    // Links of p at a fluid node x: the link words of x (refreshed by this step's fluid
-    // kernel) give p's slot at x, whose link-force sum the fluid kernel has stored.
-    auto links_of_p = [&](int cell, int &slot) -> unsigned {
-        const unsigned long long w0 = s.lw[cell_off + cell];
-        slot = -1;
-        if (((unsigned)w0 & 0x3ffffu) == 0u) return 0u;
-        const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + cell_off + cell] : 0ull;
-        const int ng = (w0 >> 62) ? 4 : 2;
-        for (int g = 0; g < ng; ++g) {
-            int q;
-            const unsigned grp = slot_dirs(w0, w1, g, q);
-            if (grp != 0u && q == pl) { slot = g; return grp; }
-        }
-        return 0u;
-    };
+    unsigned *xg = s.xgrp + lbase + k0;
 
     // (1) the chunk's shell-list entries that hold links of p, compacted in list order;
     // kept from the previous step unless the list was rebuilt or a node within one plane
-    // of the chunk's slab changed owner in the previous step
+    // of the chunk's slab changed owner in the previous step (the refresh of this step
+    // has brought the link words up to date)
     int cntx;
     if (fresh) {
         cntx = 0;
         for (int base = k0; base < k1; base += kLinksBlock) {
             const int k = base + lane;
-            bool has = false;
-            int cell = 0, slot = -1;
+            unsigned grp = 0u;
+            int cell = 0;
             if (k < k1 && s.lmask[lbase + k] != 0u) {
                 cell = s.lcell[lbase + k];
-                has = links_of_p(cell, slot) != 0u;
+                const unsigned long long w0 = s.lw[cell_off + cell];
+                if (((unsigned)w0 & 0x3ffffu) != 0u) {
+                    const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + cell_off + cell] : 0ull;
+                    const int ng = (w0 >> 62) ? 4 : 2;
+                    for (int g = 0; g < ng; ++g) {
+                        int q;
+                        const unsigned gd = slot_dirs(w0, w1, g, q);
+                        if (gd != 0u && q == pl) { grp = gd; break; }
+                    }
+                }
             }
+            const bool has = grp != 0u;
             const unsigned long long bal = __ballot(has);
             if (has) {
                 const int at = cntx + __popcll(bal & ((1ull << lane) - 1ull));
                 const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
-                xc[at] = (int)((unsigned)cell | ((unsigned)slot << 30));
+                xc[at] = cell;
                 xs[at] = node_slot(s, M, cell, rem - jj * nx, jj, kk);
+                xg[at] = grp;
             }
             cntx += __popcll(bal);
         }
@@ -1141,81 +1146,163 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         cntx = cnt_old;
     }
 
-    // (2) Eqs. (fFS), (coupleF), (coupleT): force and torque (x - X_p) x F over the links.
-    // An entry holds the node and p's slot in its link words; both are current, since a
-    // change of the words at a node marks the chunk for rebuilding.  The fluid kernel has
-    // stored the deviation part D of F and the link directions in the slot's record.
-    auto read_rec = [&](int sl, int at, double &D0, double &D1, double &D2, unsigned &grp) {
-        if constexpr (sizeof(C) == 4) {
-            const float4 v = reinterpret_cast<const float4 *>(s.fnode[sl])[cell_off + at];
-            D0 = v.x; D1 = v.y; D2 = v.z;
-            grp = __float_as_uint(v.w);
-        } else {
-            const double2 *fp = reinterpret_cast<const double2 *>(s.fnode[sl] + 4 * (cell_off + at));
-            const double2 a = fp[0], b = fp[1];
-            D0 = a.x; D1 = a.y; D2 = b.x;
-            grp = (unsigned)__double_as_longlong(b.y);
-        }
-    };
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;
+    // (2) F0, T0 and Z over the entries
+    double acc[kLinkComp];
+#pragma unroll
+    for (int c = 0; c < kLinkComp; ++c) acc[c] = 0.0;
+    const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;   // 2 rho_f w_d
+    const double z18 = rho_f / 3.0, z36 = rho_f / 6.0;                  // 6 rho_f w_d
     const double inv_nxy = 1.0 / (double)nxy, inv_nx = 1.0 / (double)nx;
     for (int base = 0; base < cntx; base += kLinksBlock * kLinkBatch) {
-        // an entry is cell | slot << 30: slots 2 and 3 set the sign bit, so validity is
-        // kept apart from the entry's value
-        unsigned ent[kLinkBatch];
-        int at[kLinkBatch];
-        bool val[kLinkBatch];
+        int cellb[kLinkBatch], atb[kLinkBatch];
+        unsigned gb[kLinkBatch];
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b) {
             const int k = base + b * kLinksBlock + lane;
-            val[b] = k < cntx;
-            ent[b] = val[b] ? (unsigned)xc[k] : 0u;
-            at[b] = val[b] ? xs[k] : 0;
+            const bool v = k < cntx;
+            cellb[b] = v ? xc[k] : 0;
+            atb[b] = v ? max(xs[k], 0) : 0; // (a node with links is fluid, hence listed)
+            gb[b] = v ? xg[k] : 0u;
         }
-        double D[kLinkBatch][3];
-        unsigned grp[kLinkBatch];
+        // f~_d(x, t) of every link of the batch (d = e*, loads issued for all directions;
+        // a lane without that link reads the node's first population)
+        C fv[kLinkBatch][kQ - 1];
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b)
-            read_rec((int)(ent[b] >> 30), max(at[b], 0), D[b][0], D[b][1], D[b][2], grp[b]);
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                const bool on = (gb[b] >> e) & 1u;
+                const S raw = ldo(A, (unsigned)(on ? kOPP[e] * nc + atb[b] : atb[b]));
+                fv[b][e] = on ? decode_dev<P>(raw, kOPP[e], rho_f) : C(0);
+            }
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b) {
-            if (!val[b]) continue;
-            const int cell = (int)(ent[b] & 0x3fffffffu);
+            const unsigned g = gb[b];
+            if (g == 0u) continue;
+            // G = sum 2 c_d (f~_d - w_d rho_f) + 2 rho_f sum w_d c_d
+            double D0 = 0.0, D1 = 0.0, D2 = 0.0;
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                const int d = kOPP[e];
+                const double v = (double)fv[b][e];
+                if (kCX[d] > 0) D0 += v; else if (kCX[d] < 0) D0 -= v;
+                if (kCY[d] > 0) D1 += v; else if (kCY[d] < 0) D1 -= v;
+                if (kCZ[d] > 0) D2 += v; else if (kCZ[d] < 0) D2 -= v;
+            }
+            auto rest = [&](int axis) {
+                const int na = (int)__popc(g & link_mask(axis, 1, false)) - (int)__popc(g & link_mask(axis, -1, false));
+                const int nd = (int)__popc(g & link_mask(axis, 1, true)) - (int)__popc(g & link_mask(axis, -1, true));
+                return a18 * (double)na + a36 * (double)nd;
+            };
+            const double G0 = 2.0 * D0 + rest(0), G1 = 2.0 * D1 + rest(1), G2 = 2.0 * D2 + rest(2);
+            // S = sum 6 w_d rho_f c_d c_d^T over the node's links, from counts
+            auto diag = [&](int axis) {
+                return z18 * (double)__popc(g & (link_mask(axis, 1, false) | link_mask(axis, -1, false))) +
+                       z36 * (double)__popc(g & (link_mask(axis, 1, true) | link_mask(axis, -1, true)));
+            };
+            auto offd = [&](int a, int b2) {
+                // (the counts are unsigned: take the difference as a signed integer)
+                const int n = (int)__popc(g & pair_mask(a, b2, 1)) - (int)__popc(g & pair_mask(a, b2, -1));
+                return z36 * (double)n;
+            };
+            const double Sxx = diag(0), Syy = diag(1), Szz = diag(2);
+            const double Sxy = offd(0, 1), Sxz = offd(0, 2), Syz = offd(1, 2);
+            const double Sm[3][3] = {{Sxx, Sxy, Sxz}, {Sxy, Syy, Syz}, {Sxz, Syz, Szz}};
+            const int cell = cellb[b];
             const int kk = div_uni(cell, nxy, inv_nxy), rem = cell - kk * nxy;
             const int jj = div_uni(rem, nx, inv_nx), ii = rem - jj * nx;
             const double r0 = mimg((double)ii - X0, per0, box0);
             const double r1 = mimg((double)jj - X1, per1, box1);
             const double r2 = mimg((double)kk - X2, per2, box2);
-            // F = D + 2 rho_f sum_d w_d c_d over p's links at the node (d pointing into p),
-            // the sum taken as counts of links per direction class
-            const unsigned g = grp[b];
-            auto rest = [&](int axis) {
-                const int na = __popc(g & link_mask(axis, 1, false)) - __popc(g & link_mask(axis, -1, false));
-                const int nd = __popc(g & link_mask(axis, 1, true)) - __popc(g & link_mask(axis, -1, true));
-                return a18 * (double)na + a36 * (double)nd;
-            };
-            const double F0 = D[b][0] + rest(0), F1 = D[b][1] + rest(1), F2 = D[b][2] + rest(2);
-            acc[0] += F0; acc[1] += F1; acc[2] += F2;
-            acc[3] += r1 * F2 - r2 * F1;
-            acc[4] += r2 * F0 - r0 * F2;
-            acc[5] += r0 * F1 - r1 * F0;
+            acc[0] += G0; acc[1] += G1; acc[2] += G2;
+            acc[3] += r1 * G2 - r2 * G1;
+            acc[4] += r2 * G0 - r0 * G2;
+            acc[5] += r0 * G1 - r1 * G0;
+            // Q = [r] S (row a of Q: r x (column of S)); Z_OmegaV = Q, Z_VOmega = Q^T
+            double Qm[3][3];
+#pragma unroll
+            for (int n = 0; n < 3; ++n) {
+                Qm[0][n] = r1 * Sm[2][n] - r2 * Sm[1][n];
+                Qm[1][n] = r2 * Sm[0][n] - r0 * Sm[2][n];
+                Qm[2][n] = r0 * Sm[1][n] - r1 * Sm[0][n];
+            }
+            // Z_OmegaOmega = Q [r]^T: entry (a, b) = (r x row a of Q)_b
+            double Wm[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                Wm[a][0] = r1 * Qm[a][2] - r2 * Qm[a][1];
+                Wm[a][1] = r2 * Qm[a][0] - r0 * Qm[a][2];
+                Wm[a][2] = r0 * Qm[a][1] - r1 * Qm[a][0];
+            }
+            // upper triangle of Z, row by row: rows 0-2 (V), then rows 3-5 (Omega)
+            int z = 6;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                for (int b2 = a; b2 < 3; ++b2) acc[z++] += Sm[a][b2];
+#pragma unroll
+                for (int b2 = 0; b2 < 3; ++b2) acc[z++] += Qm[b2][a];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b2 = a; b2 < 3; ++b2) acc[z++] += Wm[a][b2];
         }
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] = wave_sum(acc[c]);
+    for (int c = 0; c < kLinkComp; ++c) acc[c] = wave_sum(acc[c]);
     if (lane == 0) {
-        double *pp = s.ppart + ((long long)p * kChunks + chunk) * 6;
-        for (int c = 0; c < 6; ++c) pp[c] = acc[c];
+        double *pp = s.ppart + ((long long)p * kChunks + chunk) * kLinkComp;
+#pragma unroll
+        for (int c = 0; c < kLinkComp; ++c) pp[c] = acc[c];
+    }
+}
+
+// Solves A x = b for a symmetric positive definite 6 x 6 A (upper triangle given) by the
+// Cholesky factorisation A = L L^T; b is overwritten by x.
+__device__ __forceinline__ void chol_solve6(double (&A)[6][6], double (&b)[6])
+{
+    double L[6][6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double d = A[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        L[j][j] = sqrt(d);
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            double v = A[j][i];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            L[i][j] = v / L[j][j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double v = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= L[i][k] * b[k];
+        b[i] = v / L[i][i];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        double v = b[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k) v -= L[k][i] * b[k];
+        b[i] = v / L[i][i];
     }
 }
 
 // One wave per particle, kMotionWaves particles per workgroup.
-// mode 0: Eqs. (coupleF), (coupleT): the link force and torque (chunk partials summed in
-//         chunk order) plus the conversion impulses of the previous re-projection; Hertz /
-//         Mindlin contacts (Eqs. fdLawn, fdLaws) with the particles of the near list and
-//         the external force; symplectic Euler (Eqs. translate, rotate), dt = 1; fixed
-//         particles stay.
+// mode 0: Eqs. (translate), (rotate) over the step with symplectic Euler, dt = 1: Hertz /
+//         Mindlin contacts (Eqs. fdLawn, fdLaws) with the particles of the near list at
+//         X(t), V(t), the external force, the conversion impulses of the previous
+//         re-projection, and the momentum exchanged with the fluid in this step, F0 - Z
+//         (V', Omega') from the link pass (chunk partials summed in chunk order), solved
+//         for the velocities of the step, (M + Z)(V', Omega') = M (V, Omega) + F0 + the
+//         rest; X(t+1) = X(t) + V'.  F_h, T_h of Eqs. (coupleF), (coupleT) are reported.
+//         Fixed particles stay.  The fluid kernel's wall state (X(t), V', Omega') is
+//         written in FP32.
 // mode 1: near-neighbour list (every particle within R_p + R_q + kNearMargin) and the FP32
 //         state copy (set-up); later lists are built by the re-projection kernel.
 constexpr int kMotionWaves = 4;
@@ -1235,15 +1322,21 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
     const double R = s.R[p];
     const int per0 = M->per[0], per1 = M->per[1], per2 = M->per[2];
     const double box0 = M->box[0], box1 = M->box[1], box2 = M->box[2];
-    // the link kernel's chunk sums (lane c * kChunks + q holds component c of chunk q) and
-    // the rest of p's state for the update, loaded up front
-    static_assert(6 * kChunks <= 64, "one lane per chunk-sum component");
+    // the link pass's sums (lane c < kLinkComp adds component c over the chunks, in chunk
+    // order) and the rest of p's state for the update, loaded up front
+    static_assert(kLinkComp <= 64, "one lane per link-pass component");
     // (with the hydrodynamics switched off there are neither link forces nor conversion
     // momenta)
     const bool hyd = !s.fluid_off;
     double ppv = 0.0;
-    if (mode == 0 && hyd && lane < 6 * kChunks)
-        ppv = s.ppart[((long long)p * kChunks + lane % kChunks) * 6 + lane / kChunks];
+    if (mode == 0 && hyd && lane < kLinkComp) {
+        const double *pp = s.ppart + (long long)p * kChunks * kLinkComp + lane;
+        double ch[kChunks];
+#pragma unroll
+        for (int q = 0; q < kChunks; ++q) ch[q] = pp[q * kLinkComp];
+#pragma unroll
+        for (int q = 0; q < kChunks; ++q) ppv += ch[q];
+    }
     double Phv[3], Lhv[3], Fgv[3], Vpv[3], Wpv[3];
     for (int a = 0; a < 3; ++a) {
         Phv[a] = hyd ? s.Ph[3 * p + a] : 0.0;
@@ -1354,58 +1447,88 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
 #pragma unroll
     for (int c = 0; c < 6; ++c) con[c] = wave_sum(con[c]);
 
-    // the chunk sums in chunk order (every lane takes the same values)
-    double acc[6];
+    // the link pass's sums (every lane takes the same values): F0, T0, upper triangle of Z
+    double lp[kLinkComp];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < kChunks; ++q) v += readlane_d(ppv, c * kChunks + q);
-        acc[c] = v;
-    }
-    // symplectic Euler: V and Omega from the total force and torque, then X from the new V
+    for (int c = 0; c < kLinkComp; ++c) lp[c] = readlane_d(ppv, c);
     if (lane == 0) {
-        double Fh[3], Th[3];
-        for (int a = 0; a < 3; ++a) {
-            Fh[a] = acc[a] + Phv[a];
-            Th[a] = acc[3 + a] + Lhv[a];
-            s.Fh[3 * p + a] = Fh[a];
-            s.Th[3 * p + a] = Th[a];
-        }
         double *Xn = s.X[par ^ 1], *Vn = s.V[par ^ 1], *Wn = s.W[par ^ 1];
         const double Xc[3] = {X0, X1, X2};
         const int per[3] = {per0, per1, per2};
         const double box[3] = {box0, box1, box2};
+        // (M + Z)(V', Omega') = M (V, Omega) + F0 + contacts + F_g + pending impulses
+        double A[6][6], b[6];
+        {
+            int z = 6;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int c = a; c < 6; ++c) A[a][c] = lp[z++];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            A[a][a] += mass;
+            A[3 + a][3 + a] += inert;
+            b[a] = mass * Vpv[a] + (((lp[a] + Phv[a]) + Fgv[a]) + con[a]);
+            b[3 + a] = inert * Wpv[a] + ((lp[3 + a] + Lhv[a]) + con[3 + a]);
+        }
+        double x[6] = {b[0], b[1], b[2], b[3], b[4], b[5]};
+        chol_solve6(A, x);
+        double v[3] = {x[0], x[1], x[2]}, w[3] = {x[3], x[4], x[5]};
         if (fixed_p) {
-            for (int a = 0; a < 3; ++a) { Xn[3 * p + a] = Xc[a]; Vn[3 * p + a] = 0.0; Wn[3 * p + a] = 0.0; }
+            for (int a = 0; a < 3; ++a) { v[a] = 0.0; w[a] = 0.0; }
         } else {
-            for (int a = 0; a < 3; ++a) {
-                const double Ft = (Fh[a] + Fgv[a]) + con[a];
-                const double Tt = Th[a] + con[3 + a];
-                double v = Vpv[a] + Ft / mass;
-                double w = Wpv[a] + Tt / inert;
-                // a step beyond 0.25 lu (or a non-finite state) is an error (status 0x10);
-                // the particle is then held to that step and inside the lattice, so that
-                // every index derived from its position stays in range
-                if (!(fabs(v) <= 0.25) || !isfinite(w)) {
-                    atomicOr(s.flags, 0x10u);
-                    if (!isfinite(v) || !isfinite(w)) { v = 0.0; w = 0.0; }
-                    else v = fmin(fmax(v, -0.25), 0.25);
-                }
-                Vn[3 * p + a] = v;
-                Wn[3 * p + a] = w;
-                double x = Xc[a] + v;
-                if (per[a]) {
-                    if (x >= box[a]) x -= box[a];
-                    else if (x < 0.0) x += box[a];
+            // a step beyond 0.25 lu (or a non-finite state) is an error (status 0x10); the
+            // particle is then held to a step of 0.25 lu and inside the lattice, so that
+            // every index derived from its position stays in range
+            const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            const bool fin = isfinite(v2) && isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2]);
+            if (!fin || !(v2 <= 0.0625)) {
+                atomicOr(s.flags, 0x10u);
+                if (!fin) {
+                    for (int a = 0; a < 3; ++a) { v[a] = 0.0; w[a] = 0.0; }
                 } else {
-                    if (x < 0.0 || x > box[a] - 1.0) atomicOr(s.flags, 0x10u);
-                    x = fmin(fmax(x, 0.0), box[a] - 1.0);
+                    const double sc = 0.25 / sqrt(v2);
+                    for (int a = 0; a < 3; ++a) v[a] *= sc;
                 }
-                Xn[3 * p + a] = x;
             }
         }
-        pack_state(s.pf[par ^ 1] + 12 * p, Xn + 3 * p, Vn + 3 * p, Wn + 3 * p);
+        // F_h, T_h: the momentum exchanged with the fluid over the step, F0 - Z (V', Omega'),
+        // plus the pending impulses used here (Eqs. coupleF, coupleT)
+        const double xv[6] = {v[0], v[1], v[2], w[0], w[1], w[2]};
+        double zx[6] = {0, 0, 0, 0, 0, 0};
+        {
+            int z = 6;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int c = a; c < 6; ++c) {
+                    const double zz = lp[z++];
+                    zx[a] += zz * xv[c];
+                    if (c != a) zx[c] += zz * xv[a];
+                }
+        }
+        for (int a = 0; a < 3; ++a) {
+            s.Fh[3 * p + a] = (lp[a] - zx[a]) + Phv[a];
+            s.Th[3 * p + a] = (lp[3 + a] - zx[3 + a]) + Lhv[a];
+        }
+        for (int a = 0; a < 3; ++a) {
+            Vn[3 * p + a] = v[a];
+            Wn[3 * p + a] = w[a];
+            double xa = Xc[a] + v[a];
+            if (fixed_p) {
+                xa = Xc[a];
+            } else if (per[a]) {
+                if (xa >= box[a]) xa -= box[a];
+                else if (xa < 0.0) xa += box[a];
+            } else {
+                if (xa < 0.0 || xa > box[a] - 1.0) atomicOr(s.flags, 0x10u);
+                xa = fmin(fmax(xa, 0.0), box[a] - 1.0);
+            }
+            Xn[3 * p + a] = xa;
+        }
+        // the fluid kernel's wall state of this step: X(t) and the new velocities
+        pack_state(s.pf[par] + 12 * p, Xo + 3 * p, v, w);
     }
 }
 
@@ -2012,6 +2135,39 @@ __global__ __launch_bounds__(256) void k_init_pops(DevSet s, long long total_cel
 }
 
 // ---------------------------------------------------------------------------
+// macroscopic fields of one lattice (node layout): rho = sum_d f_d, rho u = sum_d f_d c_d
+// (Eq. rhoAndU) in FP64, directions in index order; 0 at solid nodes.  out: [4][ncell]
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_fields(DevSet s, int m, double *out)
+{
+    const long long t = *s.tstep;
+    const int par = (int)(t & 1);
+    const MemberDev *M = s.mem + m;
+    const long long nc = M->ncell;
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    using S = typename Prec<P>::S;
+    const S *A = (const S *)(par ? s.popB : s.popA) + M->pop_off;
+    double rho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+    if (s.own[par][M->cell_off + c] < 0) {
+        const float rho_ff = (float)M->rho_f;
+        for (int d = 0; d < kQ; ++d) {
+            const double f = (double)ld<P>(A, (unsigned)(d * nc + c), d, rho_ff);
+            rho += f;
+            j0 += f * kCXd[d];
+            j1 += f * kCYd[d];
+            j2 += f * kCZd[d];
+        }
+        j0 /= rho; j1 /= rho; j2 /= rho;
+    }
+    out[c] = rho;
+    out[nc + c] = j0;
+    out[2 * nc + c] = j1;
+    out[3 * nc + c] = j2;
+}
+
+// ---------------------------------------------------------------------------
 // compact storage back to the node layout (before the host reads or writes populations,
 // or replaces particles): per plane, listed nodes move from their slots to their nodes,
 // every other node takes the rest state w_d rho_f, and the row tables become the identity
@@ -2607,6 +2763,18 @@ hipError_t launch_init_pops(int prec, const DevSet &s, long long total_cells, hi
     case PREC_FP32: hipLaunchKernelGGL(k_init_pops<PREC_FP32>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
     case PREC_FP16DEV: hipLaunchKernelGGL(k_init_pops<PREC_FP16DEV>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
     default: hipLaunchKernelGGL(k_init_pops<PREC_BF16DEV>, dim3(grid), dim3(256), 0, st, s, total_cells); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(int prec, const DevSet &s, int m, long long ncell, double *out, hipStream_t st)
+{
+    const dim3 g((unsigned)((ncell + 255) / 256)), b(256);
+    switch (prec) {
+    case PREC_FP64: hipLaunchKernelGGL(k_fields<PREC_FP64>, g, b, 0, st, s, m, out); break;
+    case PREC_FP32: hipLaunchKernelGGL(k_fields<PREC_FP32>, g, b, 0, st, s, m, out); break;
+    case PREC_FP16DEV: hipLaunchKernelGGL(k_fields<PREC_FP16DEV>, g, b, 0, st, s, m, out); break;
+    default: hipLaunchKernelGGL(k_fields<PREC_BF16DEV>, g, b, 0, st, s, m, out); break;
     }
     return hipGetLastError();
 }

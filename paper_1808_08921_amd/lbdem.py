@@ -86,6 +86,10 @@ def lib():
         L.lbdem_populations_get.argtypes = [P, I32, dp]
         L.lbdem_populations_set.argtypes = [P, I32, dp]
         L.lbdem_owner_get.argtypes = [P, I32, ctypes.POINTER(ctypes.c_int32)]
+        L.lbdem_fields_get.argtypes = [P, I32, dp, dp, ctypes.POINTER(ctypes.c_int32)]
+        L.lbdem_state_size.argtypes = [P, ctypes.POINTER(SZ)]
+        L.lbdem_state_save.argtypes = [P, VP, SZ, ctypes.POINTER(SZ)]
+        L.lbdem_state_load.argtypes = [P, VP, SZ]
         L.lbdem_timing_enable.argtypes = [P, ctypes.c_int]
         L.lbdem_timing_read.argtypes = [P, dp, ctypes.POINTER(I64)]
         L.lbdem_tile_info.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
@@ -102,7 +106,8 @@ def lib():
         for name in ("lbdem_default_config", "lbdem_workspace_size", "lbdem_create", "lbdem_destroy",
                      "lbdem_set_stream", "lbdem_particles_set", "lbdem_particles_get", "lbdem_step", "lbdem_time",
                      "lbdem_synchronize", "lbdem_status", "lbdem_probe_read", "lbdem_populations_get",
-                     "lbdem_populations_set", "lbdem_owner_get", "lbdem_timing_enable", "lbdem_timing_read",
+                     "lbdem_populations_set", "lbdem_owner_get", "lbdem_fields_get", "lbdem_state_size",
+                     "lbdem_state_save", "lbdem_state_load", "lbdem_timing_enable", "lbdem_timing_read",
                      "lbdem_tile_info", "lbdem_adj_workspace_size", "lbdem_adj_create", "lbdem_adj_forward",
                      "lbdem_adj_backward", "lbdem_adj_destroy", "lbdem_probe_signal", "lbdem_dft_workspace_size",
                      "lbdem_st_dft", "lbdem_wave_fit"):
@@ -276,6 +281,33 @@ class LatticeSet:
         o = np.zeros(self.shapes[lattice], dtype=np.int32)
         _check(lib().lbdem_owner_get(self._h, lattice, o.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return o
+
+    def fields(self, lattice):
+        """rho [nz][ny][nx], u [3][nz][ny][nx] (0 at solid nodes) and the node map, computed on
+        the device from the current populations."""
+        shp = self.shapes[lattice]
+        rho, u = np.zeros(shp), np.zeros((3,) + shp)
+        o = np.zeros(shp, dtype=np.int32)
+        _check(lib().lbdem_fields_get(self._h, lattice, _dp(rho), _dp(u),
+                                      o.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return rho, u, o
+
+    def state_save(self):
+        """Checkpoint of the whole set as a bytes object."""
+        n = ctypes.c_size_t()
+        _check(lib().lbdem_state_size(self._h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        used = ctypes.c_size_t()
+        _check(lib().lbdem_state_save(self._h, buf, n.value, ctypes.byref(used)))
+        return buf.raw[: used.value]
+
+    def state_load(self, data, n_particles=None):
+        """Restore the set from a checkpoint made by state_save on a set with the same
+        parameters; n_particles (per lattice) restores the binding's particle counts."""
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        _check(lib().lbdem_state_load(self._h, buf, len(data)))
+        if n_particles is not None:
+            self.n_particles = list(n_particles)
 
     def timing_enable(self, on=True):
         _check(lib().lbdem_timing_enable(self._h, 1 if on else 0))

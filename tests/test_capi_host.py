@@ -51,14 +51,13 @@ def test_workspace_size_and_validation(lb):
                         t_n=200, probe_z=range(0, 384, 16), max_particles=1024, max_radius=9.0)
     rc, n = _size(lb, [ok])
     assert rc == lb.OK
-    # per node: FP32 populations (2 x 19 x 4 B), two node maps (8 B), two link words (16 B)
-    # and four 32-byte FP64 link-force records (128 B); then the per-particle shell lists
-    # (16 B per entry, about 5.6 k entries per sphere of radius 9)
+    # per node: FP32 populations (two buffers and the scratch buffer of compact storage,
+    # the default mapping: 3 x 19 x 4 B), two node maps (8 B), two link words (16 B), the
+    # node list and the parked-refill index (8 B); then the per-particle shell lists (20 B
+    # per entry, about 5.6 k entries per sphere of radius 9) and small tables
     cells = 96 * 96 * 384
-    # two population buffers and the scratch buffer of compact storage (the default
-    # mapping), node maps, link words, per-node wall records
-    per_node = 3 * 19 * 4 + 8 + 16 + 128
-    assert per_node * cells < n < per_node * cells + 1024 * 5600 * 16 * 1.5 + (64 << 20)
+    per_node = 3 * 19 * 4 + 8 + 16 + 8
+    assert per_node * cells <= n < per_node * cells + 1024 * 5600 * 20 * 1.5 + (64 << 20)
     bad = [
         lb.make_params(8, 8, 8, tau=0.5),                         # tau must exceed 1/2
         lb.make_params(8, 8, 8, bc=(0, 1, 0, 0, 0, 0)),            # periodic paired with a wall
@@ -94,6 +93,11 @@ def test_null_arguments_are_rejected(lb):
     assert L.lbdem_synchronize(None) == lb.EINVAL
     assert L.lbdem_destroy(None) == lb.OK
     assert L.lbdem_default_config(None) == lb.EINVAL
+    n = ctypes.c_size_t()
+    assert L.lbdem_state_size(None, ctypes.byref(n)) == lb.EINVAL
+    assert L.lbdem_state_save(None, None, 0, None) == lb.EINVAL
+    assert L.lbdem_state_load(None, None, 0) == lb.EINVAL
+    assert L.lbdem_fields_get(None, 0, None, None, None) == lb.EINVAL
 
 
 def test_dft_workspace_size_and_validation(lb):

@@ -1,0 +1,170 @@
+"""GPU checks of the boundary calls beyond the step: checkpoint and resume
+(lbdem_state_save / lbdem_state_load), the macroscopic fields (lbdem_fields_get) against
+the oracle, and the node map's tie rule between overlapping spheres against exact
+rationals."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_08921_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _set(params, precision, **kw):
+    import torch
+
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    assert torch.cuda.is_available()
+    return LatticeSet([params], precision=precision, **kw)
+
+
+def _moving_fcc(seed=4):
+    """2 x 2 x 2 FCC cells (32 spheres, 48^3) driven by the density face, the mobile
+    spheres given seeded velocities of about 0.02 lu per step so that nodes are covered
+    and uncovered and the node lists are rebuilt within a few steps."""
+    params, pk = inputs.wave_fcc_case(seed=seed, ncx=2, ncy=2, ncz=2, a=24.0, period=20.0)
+    params["probe_z"] = (0, 16, 32)
+    params["max_particles"] = len(pk["x"])
+    rng = np.random.default_rng(seed)
+    v = 0.02 * rng.uniform(-1.0, 1.0, (len(pk["x"]), 3))
+    v[pk["fixed"] == 1] = 0.0
+    pk["v"] = v
+    pk["w"] = 1e-3 * rng.uniform(-1.0, 1.0, (len(pk["x"]), 3))
+    return params, pk
+
+
+def _snapshot(gs):
+    return gs.populations(0), gs.owner(0), gs.particles_get(0), gs.probes(0, 0, gs.t)
+
+
+def _assert_same(a, b):
+    assert np.array_equal(a[0], b[0]), "populations differ"
+    assert np.array_equal(a[1], b[1]), "node maps differ"
+    for k in a[2]:
+        assert np.array_equal(a[2][k], b[2][k]), f"particle {k} differs"
+    assert np.array_equal(a[3], b[3]), "probe records differ"
+
+
+@pytest.mark.parametrize("precision,node_lists", [("fp32", 2), ("fp16", 2), ("fp64", 0)])
+def test_checkpoint_resume_is_bit_exact(precision, node_lists):
+    """k steps, save, m steps == a fresh set loaded from the checkpoint, m steps (and the
+    first set rewound to its own checkpoint), bit for bit: populations, node map, particle
+    state and forces, probe records."""
+    params, pk = _moving_fcc()
+    k, m = 13, 11
+    with _set(params, precision, node_lists=node_lists, graph_steps=4) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], v=pk["v"], w=pk["w"], fixed=pk["fixed"])
+        gs.step(k)
+        ck = gs.state_save()
+        gs.step(m)
+        ref = _snapshot(gs)
+        assert gs.t == k + m
+        # the same set, rewound
+        gs.state_load(ck)
+        assert gs.t == k
+        gs.step(m)
+        _assert_same(_snapshot(gs), ref)
+    with _set(params, precision, node_lists=node_lists, graph_steps=0) as gs2:
+        gs2.state_load(ck, n_particles=[len(pk["x"])])
+        assert gs2.t == k
+        gs2.step(m)
+        _assert_same(_snapshot(gs2), ref)
+
+
+def test_checkpoint_moves_nodes_between_states():
+    """The resumed run really depends on the checkpoint: conversions happened between
+    save and the end, and a checkpoint does not load into a set with other parameters."""
+    from paper_1808_08921_amd.lbdem import LbdemError
+
+    params, pk = _moving_fcc()
+    with _set(params, "fp32", node_lists=2) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], v=pk["v"], w=pk["w"], fixed=pk["fixed"])
+        own0 = gs.owner(0)
+        gs.step(10)
+        ck = gs.state_save()
+        assert int((gs.owner(0) != own0).sum()) > 100
+    other = dict(params, tau=0.9)
+    with _set(other, "fp32", node_lists=2) as gs3:
+        with pytest.raises(LbdemError):
+            gs3.state_load(ck)
+        with pytest.raises(LbdemError):
+            gs3.state_load(ck[: len(ck) // 2])
+
+
+def test_fields_match_oracle_moments():
+    """rho and u from lbdem_fields_get after 9 coupled FP64 steps with moving spheres,
+    against the moments of the oracle's populations (Eq. rhoAndU), and the node map."""
+    params, pk = _moving_fcc(seed=7)
+    p = params
+    s = oracle.Sim(p["nx"], p["ny"], p["nz"], tau=p["tau"], bc=p["bc"], wave=p["wave"], amp=p["amp"],
+                   omega=p["omega"], t_n=p["t_n"], E=p["E"], nu=p["nu"], mu=p["mu"], rho_p=p["rho_p"],
+                   probe_z=p["probe_z"])
+    s.set_particles(pk["x"], pk["radius"], v=pk["v"], w=pk["w"], fixed=pk["fixed"])
+    s.step(9)
+    with _set(params, "fp64", graph_steps=0) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], v=pk["v"], w=pk["w"], fixed=pk["fixed"])
+        gs.step(9)
+        rho, u, own = gs.fields(0)
+    oo = s.owner()
+    assert np.array_equal(own, oo)
+    f = s.populations()
+    c = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 0], [1, -1, 0],
+                  [1, 0, 1], [1, 0, -1], [-1, 1, 0], [-1, -1, 0], [-1, 0, 1], [-1, 0, -1], [0, 1, 1], [0, 1, -1],
+                  [0, -1, 1], [0, -1, -1], [0, 0, 0]], dtype=float)
+    fl = oo < 0
+    r_o = f.sum(0)
+    u_o = np.einsum("d...,da->a...", f, c) / r_o
+    assert np.abs(rho[fl] - r_o[fl]).max() <= 1e-12
+    assert np.abs(u[:, fl] - u_o[:, fl]).max() <= 1e-10 * np.abs(u_o[:, fl]).max()
+    assert not rho[~fl].any() and not u[:, ~fl].any()
+    assert np.abs(u_o[:, fl]).max() > 1e-4  # the spheres stir the fluid
+
+
+def _exact_owner(shape, X, R, periodic):
+    nx, ny, nz = shape
+    own = -np.ones((nz, ny, nx), dtype=np.int32)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                best = None
+                for q in range(len(R)):
+                    d2 = Fraction(0)
+                    for a, (pp, n) in enumerate(zip((i, j, k), (nx, ny, nz))):
+                        dx = Fraction(pp) - Fraction(X[q][a])
+                        if periodic[a]:
+                            if dx > Fraction(n, 2):
+                                dx -= n
+                            elif dx < -Fraction(n, 2):
+                                dx += n
+                        d2 += dx * dx
+                    if d2 <= Fraction(R[q]) ** 2 and (best is None or d2 < best[0]):
+                        best = (d2, q)
+                if best is not None:
+                    own[k, j, i] = best[1]
+    return own
+
+
+@pytest.mark.parametrize("swap", [False, True])
+def test_projection_tie_between_spheres_on_gpu(swap):
+    """Two spheres mirror-symmetric about the node (5, 5, 5): the five equidistant nodes
+    belong to the smaller index, bit-exact with exact rationals, at set-up and after a
+    step in which the pair is re-projected."""
+    X = [(4.0, 5.0, 5.0), (6.0, 5.0, 5.0)]
+    if swap:
+        X = X[::-1]
+    R = [1.5, 1.5]
+    shape = (11, 10, 10)
+    params = dict(nx=11, ny=10, nz=10, tau=1.0, bc=(0, 0, 0, 0, 1, 1), max_particles=2, max_radius=2.0)
+    want = _exact_owner(shape, X, R, (True, True, False))
+    with _set(params, "fp64", graph_steps=0) as gs:
+        gs.particles_set(0, np.array(X), np.array(R), fixed=np.ones(2, np.uint8))
+        assert np.array_equal(gs.owner(0), want)
+        gs.step(1)
+        assert np.array_equal(gs.owner(0), want)
+    for i, j, k in [(5, 5, 5), (5, 4, 5), (5, 6, 5), (5, 5, 4), (5, 5, 6)]:
+        assert want[k, j, i] == 0
