@@ -365,6 +365,16 @@ int lbdem_st_dft(const double *x, int64_t nt, int32_t nz, const double *zpos, do
 int lbdem_wave_fit(const double *x, int64_t nt, int32_t nz, const double *zpos, double t0, double omega,
                    double *out, void *work, size_t work_bytes, void *stream);
 
+/* lbdem_wave_fit without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments and results as lbdem_wave_fit; the fit's scratch is a static device array
+ * of 4 MiB per GPU, held until the process ends (its address is looked up on the first
+ * call on each device).  Calls on one GPU share that array: calls that overlap on one GPU
+ * race and must be ordered by the caller.  Allocates no memory.  Errors: as for
+ * lbdem_wave_fit, and LBDEM_ENOMEM when the sizes need more than the static scratch. */
+int lbdem_wave_fit_noalloc(const double *x, int64_t nt, int32_t nz, const double *zpos, double t0, double omega,
+                           double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

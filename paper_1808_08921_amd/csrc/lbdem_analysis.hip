@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <stdint.h>
 
 #include "lbdem_internal.hpp"
@@ -400,6 +401,33 @@ hipError_t launch_probe_signal(const double *ring, int ring_len, int nprobe, lon
     hipLaunchKernelGGL(k_probe_signal, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, ring, ring_len, nprobe,
                        first, n, quantity, x);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free fit (lbdem_wave_fit_noalloc): a file-scope device array,
+// one copy per GPU held until the process ends.  Host code never uses the array's name as
+// an address: its device address is taken once per device with hipGetSymbolAddress (with
+// that device current) and kept.  Calls on one GPU share the array, so calls that overlap
+// on one GPU race; the fit's kernels write every scratch value before reading it.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace lbdem

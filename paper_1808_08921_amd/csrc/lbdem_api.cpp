@@ -1072,6 +1072,23 @@ int lbdem_wave_fit(const double *x, int64_t nt, int32_t nz, const double *zpos, 
     return LBDEM_OK;
 }
 
+int lbdem_wave_fit_noalloc(const double *x, int64_t nt, int32_t nz, const double *zpos, double t0, double omega,
+                           double *out, void *stream)
+{
+    int rc = check_dft_sizes(nt, nz, 1, 1);
+    if (rc) return rc;
+    if (!x || !zpos || !out) return fail(LBDEM_EINVAL, "null pointer");
+    if (!(omega != 0.0) || !std::isfinite(omega)) return fail(LBDEM_EINVAL, "omega must be finite and non-zero");
+    const size_t need = dft_bytes(nt, nz, 1, 1);
+    if (need > kNoAllocScratchBytes)
+        return fail(LBDEM_ENOMEM, "the fit needs %zu bytes of scratch, more than the %zu-byte static scratch", need,
+                    kNoAllocScratchBytes);
+    void *work = nullptr;
+    HIPCHK(noalloc_scratch(&work));
+    HIPCHK(launch_wave_fit(x, nt, nz, zpos, t0, omega, out, work, (hipStream_t)stream));
+    return LBDEM_OK;
+}
+
 int lbdem_populations_get(lbdem_set *S, int32_t lattice, double *f)
 {
     int rc = check_lattice(S, lattice);

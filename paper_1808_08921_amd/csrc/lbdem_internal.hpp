@@ -222,6 +222,10 @@ hipError_t launch_st_dft(const DftPlan &p, const double *x, long long nt, int nz
                          void *work, hipStream_t st);
 hipError_t launch_wave_fit(const double *x, long long nt, int nz, const double *zpos, double t0, double omega,
                            double *out, void *work, hipStream_t st);
+// the allocation-free fit's static device scratch: its size, and its address on the
+// current device (looked up once per device)
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+hipError_t noalloc_scratch(void **ptr);
 hipError_t launch_probe_signal(const double *ring, int ring_len, int nprobe, long long first, long long n,
                                int quantity, double *x, hipStream_t st);
 

@@ -103,6 +103,7 @@ def lib():
         L.lbdem_dft_workspace_size.argtypes = [I64, I32, I32, I32, ctypes.POINTER(SZ)]
         L.lbdem_st_dft.argtypes = [VP, I64, I32, VP, D, D, D, I32, D, D, I32, VP, VP, VP, SZ, VP]
         L.lbdem_wave_fit.argtypes = [VP, I64, I32, VP, D, D, VP, VP, SZ, VP]
+        L.lbdem_wave_fit_noalloc.argtypes = [VP, I64, I32, VP, D, D, VP, VP]
         for name in ("lbdem_default_config", "lbdem_workspace_size", "lbdem_create", "lbdem_destroy",
                      "lbdem_set_stream", "lbdem_particles_set", "lbdem_particles_get", "lbdem_step", "lbdem_time",
                      "lbdem_synchronize", "lbdem_status", "lbdem_probe_read", "lbdem_populations_get",
@@ -110,7 +111,7 @@ def lib():
                      "lbdem_state_save", "lbdem_state_load", "lbdem_timing_enable", "lbdem_timing_read",
                      "lbdem_tile_info", "lbdem_adj_workspace_size", "lbdem_adj_create", "lbdem_adj_forward",
                      "lbdem_adj_backward", "lbdem_adj_destroy", "lbdem_probe_signal", "lbdem_dft_workspace_size",
-                     "lbdem_st_dft", "lbdem_wave_fit"):
+                     "lbdem_st_dft", "lbdem_wave_fit", "lbdem_wave_fit_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -465,3 +466,17 @@ def wave_fit(x, zpos, t0, omega):
                                 ctypes.c_void_p(work.data_ptr()), nb, ctypes.c_void_p(st)))
     o = out.cpu().numpy()
     return {"A": complex(o[0], o[1]), "alpha": float(o[2]), "k": float(o[3]), "c": float(o[4]), "n_used": int(o[5])}
+
+
+def wave_fit_noalloc(x, zpos, t0, omega, out=None):
+    """wave_fit through the allocation-free entry point (static device scratch).  ``out``:
+    an optional float64 CUDA tensor of 6 values to write into; returns it."""
+    torch, x, zpos = _analysis_args(x, zpos)
+    nt, nz = x.shape
+    if out is None:
+        out = torch.empty(6, dtype=torch.float64, device=x.device)
+    st = torch.cuda.current_stream(x.device).cuda_stream
+    _check(lib().lbdem_wave_fit_noalloc(ctypes.c_void_p(x.data_ptr()), int(nt), int(nz),
+                                        ctypes.c_void_p(zpos.data_ptr()), float(t0), float(omega),
+                                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st)))
+    return out
