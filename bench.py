@@ -50,10 +50,10 @@ def _case(seed=0):
     return params, pk
 
 
-def _make(params, pk, precision, graph_steps=8):
+def _make(params, pk, precision, graph_steps=8, probe_ring=4096):
     from paper_1808_08921_amd.lbdem import LatticeSet
 
-    gs = LatticeSet([params], precision=precision, graph_steps=graph_steps, probe_ring=4096)
+    gs = LatticeSet([params], precision=precision, graph_steps=graph_steps, probe_ring=probe_ring)
     gs.particles_set(0, pk["x"], pk["radius"], fixed=pk["fixed"])
     return gs
 
@@ -112,35 +112,59 @@ def front_velocity(probes, zs, tmax):
     return float(np.polyfit(np.asarray(times), np.asarray(zs, float), 1)[0])
 
 
-def precision_errors(params, pk, steps=900, planes=12):
+def precision_errors(params, pk, steps=20000, arrival_steps=900, planes=12, every=100):
     """Error of each storage precision against the FP64 GPU path (itself checked against
-    the FP64 CPU oracle to 1e-10 by the test-suite) on the same workload."""
+    the FP64 CPU oracle to 1e-10 by the test-suite) over the workload's full length: the
+    P-wave arrival speed (planes 1-12, from the first `arrival_steps` steps, before the
+    outlet's reflection comes back), particle velocities sampled every `every` steps and
+    the cross-section averaged density of every probe plane at every step."""
     out = {}
     ref = None
     zs = list(params["probe_z"])[1:planes + 1]
     for prec in ("fp64", "fp32", "fp16", "bf16"):
-        gs = _make(params, pk, prec, graph_steps=8)
+        gs = _make(params, pk, prec, graph_steps=8, probe_ring=steps)
         vs = []
-        for _ in range(steps // 100):
-            gs.step(100)
+        for _ in range(steps // every):
+            gs.step(every)
             vs.append(gs.particles_get(0)["v"])
-        probes = gs.probes(0, 0, steps)[:, 1:planes + 1, :]
-        vel, _ = arrival_velocity(probes, zs, steps)
+        probes = gs.probes(0, 0, steps)
+        status = gs.status()
+        vel, _ = arrival_velocity(probes[:, 1:planes + 1, :], zs, arrival_steps)
         vs = np.stack(vs)
         gs.close()
+        rho = probes[..., 1] / np.maximum(probes[..., 0], 1.0)
         if prec == "fp64":
-            ref = (vel, vs, probes)
-            out[prec] = {"p_wave_velocity": vel}
+            ref = (vel, vs, rho)
+            out[prec] = {"p_wave_velocity": vel, "steps": steps, "status": status,
+                         "max_particle_speed": float(np.abs(vs).max())}
             continue
-        rho_ref = ref[2][..., 1] / ref[2][..., 0]
-        rho = probes[..., 1] / probes[..., 0]
         out[prec] = {
             "p_wave_velocity": vel,
             "p_wave_velocity_rel_err": abs(vel - ref[0]) / abs(ref[0]),
             "particle_velocity_rel_err": float(np.linalg.norm(vs - ref[1]) / np.linalg.norm(ref[1])),
-            "probe_rho_prime_rel_err": float(np.abs(rho - rho_ref).max() / np.abs(rho_ref).max()),
+            "probe_rho_prime_rel_err": float(np.abs(rho - ref[2]).max() / np.abs(ref[2]).max()),
+            "steps": steps, "status": status,
         }
     return out
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo and the process's
+    CPU affinity)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, avail, os.cpu_count()
 
 
 def cpu_baseline(params, pk, budget_s=20.0):
@@ -164,8 +188,10 @@ def cpu_baseline(params, pk, budget_s=20.0):
             break
     dt = time.perf_counter() - t0
     s.close()
+    model, avail, total = host_cpu()
     return {"value": nfl * n / dt / 1e6, "unit": "MLUPS (fluid nodes)", "cores": 1, "kind": "oracle",
-            "sample": f"{n} full steps of the 96x96x384 FCC case (oracle, FP64, one host thread)"}
+            "sample": f"{n} full steps of the 96x96x384 FCC case (oracle, FP64, one host thread)",
+            "host_cpu": model, "host_cpus_available": avail, "host_cpus_total": total}
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1808_08921_amd", "csrc", "lbdem_kernels.hip")
@@ -568,8 +594,6 @@ def dispersion_bench(calls=50, warmup=5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # the default window (steps 200-1400 of the FCC case) ends before the slow growth of
-    # particle velocities that the undamped packing develops after about 1500 steps
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--kernel-steps", type=int, default=200, help="eager steps timed per kernel with HIP events")

@@ -289,6 +289,8 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.own[1] = c.take<int>(G.cells);
     s.lw = c.take<unsigned long long>(2 * (size_t)G.cells);
     s.ncell_total = G.cells;
+    s.frec = c.take<char>(4 * (size_t)G.cells * (G.prec == PREC_FP64 ? 32 : 16));
+    s.rec_step = c.take<long long>(1);
     s.chg_cap = G.chg_cap;
     s.chg[0] = c.take<int>(2 * (size_t)G.chg_cap);
     s.chg[1] = c.take<int>(2 * (size_t)G.chg_cap);
@@ -323,6 +325,7 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.fixed = c.take<int>(P);
     s.pmem = c.take<int>(P);
     s.ppart = c.take<double>((size_t)P * kChunks * kLinkComp);
+    s.zcache = c.take<double>((size_t)P * kChunks * kZComp);
     s.nearl = c.take<int>((size_t)P * kNearCap);
     s.nnear = c.take<int>(P);
     s.near_at = c.take<long long>(P);
@@ -500,7 +503,7 @@ int build_graph(lbdem_set *S, int steps)
         kp.blockDim = dim3(256);
         kp.sharedMemBytes = 0;
         kp.extra = nullptr;
-        // refresh -> links -> motion -> fluid -> re-projection
+        // refresh -> link records -> link pass -> motion -> fluid -> re-projection
         kp.func = refresh_kernel_ptr(S->G.prec);
         kp.gridDim = dim3(refresh_grid(S->ds));
         kp.kernelParams = fluid_args;
@@ -509,11 +512,16 @@ int build_graph(lbdem_set *S, int steps)
             // hydrodynamics switched off: no link pass and no fluid step
             n0 = n4;
         } else {
+            hipGraphNode_t nr;
+            kp.func = records_kernel_ptr(S->G.prec, S->G.compact);
+            kp.gridDim = dim3(S->ds.tiles_total);
+            kp.kernelParams = fluid_args;
+            HIPCHK(hipGraphAddKernelNode(&nr, S->graph, &n4, 1, &kp));
             kp.func = links_kernel_ptr(S->G.prec);
             kp.gridDim = dim3(links_grid(S->ds));
             kp.blockDim = dim3(links_block());
             kp.kernelParams = part_args;
-            HIPCHK(hipGraphAddKernelNode(&n0, S->graph, &n4, 1, &kp));
+            HIPCHK(hipGraphAddKernelNode(&n0, S->graph, &nr, 1, &kp));
         }
         kp.blockDim = dim3(256);
         kp.kernelParams = part_args;
@@ -575,7 +583,11 @@ int launch_step_eager(lbdem_set *S)
         }
         hipError_t err;
         if (k == 4) err = launch_refresh(S->G.prec, S->ds, S->stream);
-        else if (k == 0) err = launch_links(S->G.prec, S->ds, S->stream);
+        else if (k == 0) {
+            // the link records and the link pass share the links timing slot
+            err = launch_records(S->G.prec, S->ds, S->stream);
+            if (err == hipSuccess) err = launch_links(S->G.prec, S->ds, S->stream);
+        }
         else if (k == 1) err = launch_motion(S->ds, 0, -1, S->stream);
         else if (k == 2) err = launch_fluid(S->G.prec, S->ds, S->stream);
         else err = launch_remap_prec(S->G.prec, S->ds, 0, -1, S->stream);
@@ -768,6 +780,7 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     CHK(hipMemsetAsync(s.lzr, 0, sizeof(int) * 2 * P, st));
     CHK(hipMemsetAsync(s.lchunk, 0, sizeof(int) * P * (kChunks + 1), st));
     CHK(hipMemsetAsync(s.tstep, 0, sizeof(long long), st));
+    CHK(hipMemsetAsync(s.rec_step, 0x80, sizeof(long long), st)); // no link records yet
     CHK(hipMemsetAsync(s.tcopy, 0, sizeof(long long), st));
     CHK(hipMemsetAsync(s.flags, 0, sizeof(unsigned), st));
     CHK(launch_init_pops(S->G.prec, s, S->G.cells, st));
@@ -1142,6 +1155,8 @@ int lbdem_populations_set(lbdem_set *S, int32_t lattice, const double *f)
         }
     }
     HIPCHK(hipMemcpy(dst, raw.data(), raw.size(), hipMemcpyHostToDevice));
+    // the link records no longer describe the populations
+    HIPCHK(hipMemset(S->ds.rec_step, 0x80, sizeof(long long)));
     return LBDEM_OK;
 }
 

@@ -27,9 +27,11 @@ constexpr double kSkinMin = 0.05;
 constexpr double kSkinSteps = 12.0;
 constexpr int kPendCap = 16384;     // refills of unlisted nodes awaiting the next list rebuild
 constexpr int kChunks = 8;          // waves per particle in the link pass
-// components of a link-pass partial: F0 (3), T0 (3), then the upper triangle of the 6 x 6
-// matrix Z of the velocity-dependent link force, row by row (21)
-constexpr int kLinkComp = 27;
+// components of a link-pass partial per (particle, chunk): F0 (3) and sum xr x G (3), xr the
+// node position relative to the shell list's reference point
+constexpr int kLinkComp = 6;
+// cached link-set sums per (particle, chunk): S (6, upper triangle), Qx (9, row-major), Wx (6)
+constexpr int kZComp = 21;
 constexpr int kEmpty = 0x7fffffff;
 // Link words of a fluid node x (two 64-bit words per node: lw[c] and lw[ncell_total + c]).
 // Word 0: bits 0-17 the directions e whose source x - c_e is inside a particle, bits 18-35
@@ -40,6 +42,7 @@ constexpr int kEmpty = 0x7fffffff;
 constexpr int kMaxLocal = 8191;     // particles per lattice (13-bit local indices)
 constexpr int kRefreshBlocks = 512; // workgroups of the start-of-step refresh kernel
 constexpr int kMaxPlaneWords = 8192; // row-table words of one x-y plane held in LDS (compact storage)
+constexpr int kRtLds = 1536;        // row-table words a fluid-kernel workgroup stages in LDS (compact storage)
 
 // Per-lattice constants (one entry per lattice of the set).
 struct MemberDev {
@@ -104,6 +107,12 @@ struct DevSet {
     int *own[2];
     unsigned long long *lw;   // link words, two per node (all lattices) [2*ncell_total]
     long long ncell_total;
+    // per slot of a fluid node's link words, written by k_records of step t for the link
+    // pass of step t: G = sum c_d (f~_d(x,t) - w_d rho_f) over the slot's links and the link
+    // directions (FP32 float4, FP64 two double2), [4][ncell_total] at the node's storage
+    // slot; rec_step: the step whose k_records wrote them
+    void *frec;
+    long long *rec_step;
     int *chg[2];
     int chg_cap;
     int *chgcnt;              // [2]
@@ -123,6 +132,7 @@ struct DevSet {
                               // velocities V, Omega of step t, at the parity of t
     int *fixed, *pmem;
     double *ppart;            // link-pass partials per (particle, chunk) [ptot*kChunks*kLinkComp]
+    double *zcache;           // link-set sums per (particle, chunk), rebuilt with its entries [ptot*kChunks*kZComp]
     int *nearl, *nnear;       // [ptot*kNearCap], [ptot]
     long long *near_at;       // step at which each near list was built [ptot]
     // shell list per particle around X_ref: node, d_ref - R, link-candidate directions
@@ -182,6 +192,7 @@ enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16DEV = 2, PREC_BF16DEV = 3 };
 
 // kernel launchers (lbdem_kernels.hip)
 hipError_t launch_refresh(int prec, const DevSet &s, hipStream_t st);
+hipError_t launch_records(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_links(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_motion(const DevSet &s, int mode, int only_member, hipStream_t st);
 hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st);
@@ -191,6 +202,7 @@ hipError_t launch_expand(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_fields(int prec, const DevSet &s, int m, long long ncell, double *out, hipStream_t st);
 // kernel entry points and grid sizes, for building HIP graphs
 void *refresh_kernel_ptr(int prec);
+void *records_kernel_ptr(int prec, int compact);
 void *links_kernel_ptr(int prec);
 void *motion_kernel_ptr();
 void *fluid_kernel_ptr(int prec, int compact);

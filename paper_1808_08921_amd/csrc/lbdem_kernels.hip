@@ -314,7 +314,10 @@ __device__ __forceinline__ C feq_dev(int d, C drho, C rho, C ux, C uy, C uz, C u
         const double cs2 = kCS2;
         return kWd[d] * (drho + rho * (cu / cs2 + (cu * cu) / (2.0 * cs2 * cs2) - uu / (2.0 * cs2)));
     } else {
-        return (C)kWd[d] * (drho + rho * (C(3) * cu + C(4.5) * (cu * cu) - C(1.5) * uu));
+        // FP32 collision arithmetic with fused multiply-adds (uu3 = 1.5 u.u)
+        const C uu3 = C(1.5) * uu;
+        const C poly = __builtin_fmaf(C(4.5) * cu, cu, __builtin_fmaf(C(3), cu, -uu3));
+        return (C)kWd[d] * __builtin_fmaf(rho, poly, drho);
     }
 }
 
@@ -339,6 +342,37 @@ __device__ __forceinline__ void store_dev(typename Prec<P>::S *a, unsigned idx, 
     if constexpr (P == PREC_FP64 || P == PREC_FP32) sto(a, idx, (S)((C)(kWd[d] * rho_f) + df));
     else if constexpr (P == PREC_FP16DEV) sto(a, idx, (S)(df * kInvW[d]));
     else sto(a, idx, f32_to_bf16(df * kInvW[d]));
+}
+
+// Record of one link slot of a fluid node for this step's link pass: the deviation part of
+// sum 2 c_d f~_d(x,t) over the slot's links (as G = sum c_d (f~_d - w_d rho_f); the
+// rest-state part comes from counts) and the link directions; FP32 float4, FP64 2 x double2,
+// at [slot][storage slot of the node]
+template <int P>
+__device__ __forceinline__ void put_record(const DevSet &s, int g, long long gr, typename Prec<P>::C G0,
+                                           typename Prec<P>::C G1, typename Prec<P>::C G2, unsigned grp)
+{
+    if constexpr (sizeof(typename Prec<P>::C) == 4) {
+        reinterpret_cast<float4 *>(s.frec)[g * s.ncell_total + gr] = make_float4(G0, G1, G2, __uint_as_float(grp));
+    } else {
+        double2 *r = reinterpret_cast<double2 *>(s.frec) + 2 * (g * s.ncell_total + gr);
+        r[0] = make_double2(G0, G1);
+        r[1] = make_double2(G2, __longlong_as_double((long long)grp));
+    }
+}
+template <int P>
+__device__ __forceinline__ unsigned get_record(const DevSet &s, int g, long long gr, double &G0, double &G1, double &G2)
+{
+    if constexpr (sizeof(typename Prec<P>::C) == 4) {
+        const float4 v = reinterpret_cast<const float4 *>(s.frec)[g * s.ncell_total + gr];
+        G0 = v.x; G1 = v.y; G2 = v.z;
+        return __float_as_uint(v.w);
+    } else {
+        const double2 *r = reinterpret_cast<const double2 *>(s.frec) + 2 * (g * s.ncell_total + gr);
+        const double2 a = r[0], b = r[1];
+        G0 = a.x; G1 = a.y; G2 = b.x;
+        return (unsigned)__double_as_longlong(b.y);
+    }
 }
 
 // Rank of a true predicate among the workgroup's threads (thread order) and the total.
@@ -797,6 +831,86 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
     }
 }
 
+// Link records of step t for the link pass, one thread per listed node (or per node of a
+// dense tile), on the fluid kernel's grid, after the refresh (link words and storage slots
+// of step t final): per fluid node with links and per slot of its link words, G = sum c_d
+// (f~_d(x,t) - w_d rho_f) over the slot's links, read from the node's own storage slot
+// (consecutive threads read consecutive slots).
+template <int P, bool CMP>
+__global__ __launch_bounds__(256) void k_records(DevSet s)
+{
+    using S = typename Prec<P>::S;
+    using C = typename Prec<P>::C;
+    const long long t = *s.tstep;
+    const int par = (int)(t & 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *s.rec_step = t;
+    const int g = xcd_swizzle(blockIdx.x, gridDim.x);
+    const MemberDev *M = member_of_tile(s, g);
+    const int tl = g - uni(M->tile_off);
+    const int ntx = uni(M->ntx), nty = uni(M->nty);
+    const int nx = uni(M->nx), ny = uni(M->ny), nz = uni(M->nz);
+    const int nxy = nx * ny;
+    const unsigned nc = (unsigned)uni(M->ncell);
+    const long long cell_off = uni(M->cell_off);
+    const S *A = (const S *)(par ? s.popB : s.popA) + uni(M->pop_off);
+    const double rho_f = uni(M->rho_f);
+    auto records = [&](int cell, int slot) {
+        const long long gc = cell_off + cell;
+        const unsigned long long w0 = s.lw[gc];
+        if (((unsigned)w0 & 0x3ffffu) == 0u) return;
+        const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + gc] : 0ull;
+        const int ng = (w0 >> 62) ? 4 : 2;
+        // the node's populations in the link directions (every direction some slot uses;
+        // a direction no lane of the wave needs is not loaded at all)
+        const unsigned all = (unsigned)w0 & 0x3ffffu;
+        C v[kQ - 1];
+#pragma unroll
+        for (int e = 0; e < kQ - 1; ++e) {
+            const int d = kOPP[e];
+            const bool on = (all >> e) & 1u;
+            v[e] = C(0);
+            if (on) v[e] = decode_dev<P>(ldo(A, (unsigned)d * nc + (unsigned)slot), d, rho_f);
+        }
+#pragma unroll 1
+        for (int gg = 0; gg < ng; ++gg) {
+            int q;
+            const unsigned grp = slot_dirs(w0, w1, gg, q);
+            if (grp == 0u) continue;
+            C G0 = C(0), G1 = C(0), G2 = C(0);
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                if (!((grp >> e) & 1u)) continue;
+                const int d = kOPP[e];
+                if (kCX[d] > 0) G0 += v[e]; else if (kCX[d] < 0) G0 -= v[e];
+                if (kCY[d] > 0) G1 += v[e]; else if (kCY[d] < 0) G1 -= v[e];
+                if (kCZ[d] > 0) G2 += v[e]; else if (kCZ[d] < 0) G2 -= v[e];
+            }
+            put_record<P>(s, gg, cell_off + slot, G0, G1, G2, grp);
+        }
+    };
+    if (s.listmode) {
+        const int lb = tl % ntx, z = tl / ntx;
+        const int cnt = s.ccnt[uni(M->pz_off) + z];
+        for (int lbx = lb; lbx * 256 < cnt; lbx += ntx) {
+            const int kk = lbx * 256 + (int)threadIdx.x;
+            if (kk >= cnt) break;
+            const int c = s.clist[cell_off + (long long)z * nxy + kk];
+            records(c, CMP ? z * nxy + kk : c);
+        }
+    } else {
+        const int bxl = uni(M->bx_log2);
+        const int lx = threadIdx.x & ((1 << bxl) - 1), ly = threadIdx.x >> bxl;
+        const int tx = tl % ntx, trem = tl / ntx, ty = trem % nty, tz = trem / nty;
+        const int i = (tx << bxl) + lx, j = ty * uni(M->by) + ly;
+        if (i >= nx || j >= ny) return;
+        const int z0 = tz * s.nzt, z1 = min(z0 + s.nzt, nz);
+        for (int z = z0; z < z1; ++z) {
+            const int c = (z * ny + j) * nx + i;
+            records(c, c);
+        }
+    }
+}
+
 // Pull streaming (Eq. stream), stationary half-way walls, moving half-way walls on the
 // particles (Eq. mem, from the node's link words), the density faces (Sec. 2.4), BGK
 // collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.
@@ -837,7 +951,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     // one chunk of the work: the nodes (i, j) of planes z0 .. z1-1 (dense tiles), or one
     // listed node of plane z0 at slot me0 (node lists); accum adds the probe partial sums
     // to those of an earlier chunk of the same workgroup
-    auto run = [&](int i, int j, int z0, int z1, int me0, bool vij, bool accum) {
+    // compact storage: the row-table words of the workgroup's source rows, staged in LDS
+    // (rows j0 - 1 .. j1 + 1 of planes z - 1, z, z + 1 for the chunk's nodes in rows j0 .. j1)
+    __shared__ uint2 rt_lds[kRtLds];
+    __shared__ int jr[2];
+
+    auto run = [&](int i, int j, int z0, int z1, int me0, bool vij, bool accum, const uint2 *lrt, int jb,
+                   int nrows) {
         // offsets to the x-1 / x+1 / y-1 / y+1 neighbours (wrapped on periodic axes) and the
         // kind of face crossed to reach them (0 inside or periodic, 1 wall, 2 density face)
         int oxm = (i > 0) ? -1 : (nx - 1), oxp = (i < nx - 1) ? 1 : -(nx - 1);
@@ -886,12 +1006,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                     const int wx = (i == 0) ? nx - 1 : 0;
                     const unsigned bw = 1u << (wx & 31);
                     uint2 wv[9], ww[9];
+                    if (lrt) {
     #pragma unroll
-                    for (int r = 0; r < 9; ++r) {
-                        const int jj = wrapc(j + r / 3 - 1, ny), zz = wrapc(z + r % 3 - 1, nz);
-                        const long long row = ((long long)zz * ny + jj) * nw;
-                        wv[r] = rtab[row + (i >> 5)];
-                        ww[r] = per_x ? rtab[row + (wx >> 5)] : make_uint2(0u, 0u);
+                        for (int r = 0; r < 9; ++r) {
+                            const int row = ((r % 3) * nrows + (j + r / 3 - 1 - jb)) * nw;
+                            wv[r] = lrt[row + (i >> 5)];
+                            ww[r] = per_x ? lrt[row + (wx >> 5)] : make_uint2(0u, 0u);
+                        }
+                    } else {
+    #pragma unroll
+                        for (int r = 0; r < 9; ++r) {
+                            const int jj = wrapc(j + r / 3 - 1, ny), zz = wrapc(z + r % 3 - 1, nz);
+                            const long long row = ((long long)zz * ny + jj) * nw;
+                            wv[r] = rtab[row + (i >> 5)];
+                            ww[r] = per_x ? rtab[row + (wx >> 5)] : make_uint2(0u, 0u);
+                        }
                     }
     #pragma unroll
                     for (int e = 0; e < kQ - 1; ++e) {
@@ -951,12 +1080,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                     pr2 = (double)jz;
                     pr3 = rho_fd + (double)drho;
                 }
-                const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
-                const C uu = ux * ux + uy * uy + uz * uz;
+                C ux, uy, uz, uu;
+                if constexpr (sizeof(C) == 8) {
+                    ux = jx / rho; uy = jy / rho; uz = jz / rho;
+                    uu = ux * ux + uy * uy + uz * uz;
+                } else {
+                    const C ir = C(1) / rho;
+                    ux = jx * ir; uy = jy * ir; uz = jz * ir;
+                    uu = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+                }
     #pragma unroll
                 for (int d = 0; d < kQ; ++d) {
                     const C fe = feq_dev<C>(d, drho, rho, ux, uy, uz, uu);
-                    store_dev<P>(B, (unsigned)(d * nc) + (unsigned)me, d, f[d] + omega * (fe - f[d]), rho_fd);
+                    C post;
+                    if constexpr (sizeof(C) == 8) post = f[d] + omega * (fe - f[d]);
+                    else post = __builtin_fmaf(omega, fe - f[d], f[d]);
+                    store_dev<P>(B, (unsigned)(d * nc) + (unsigned)me, d, post, rho_fd);
                 }
             }
             const int pidx = s.pzmap[pz_off + z];
@@ -989,8 +1128,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
             const bool v = kk < cnt;
             const int c = v ? s.clist[cell_off + (long long)z * nxy + kk] - z * nxy : 0;
             const int jj = c / nx;
+            const uint2 *lrt = nullptr;
+            int jb = 0, nrows = 0;
+            if constexpr (CMP) {
+                // the chunk's nodes lie in rows jr[0] .. jr[1] (x-fastest list order): stage
+                // the row-table words of their source rows once for the workgroup, unless
+                // they do not fit (then each thread reads its own from the tables)
+                const int last = min(cnt - lbx * 256, 256) - 1;
+                if (threadIdx.x == 0) jr[0] = jj;
+                if ((int)threadIdx.x == last) jr[1] = jj;
+                __syncthreads();
+                jb = jr[0] - 1;
+                nrows = jr[1] - jr[0] + 3;
+                const int nw = uni(M->nw);
+                const int tot = 3 * nrows * nw;
+                if (tot <= kRtLds) {
+                    const uint2 *rtab = s.rt + uni(M->rt_off);
+                    for (int w = threadIdx.x; w < tot; w += 256) {
+                        const int pz = w / (nrows * nw), rem = w - pz * (nrows * nw);
+                        const int u = rem / nw, wq = rem - u * nw;
+                        const int zz = wrapc(z + pz - 1, nz), jg = wrapc(jb + u, ny);
+                        rt_lds[w] = rtab[((long long)zz * ny + jg) * nw + wq];
+                    }
+                    lrt = rt_lds;
+                }
+                __syncthreads();
+            }
             // the node's slot under compact storage
-            run(c - jj * nx, jj, z, z + 1, z * nxy + kk, v, lbx != lb);
+            run(c - jj * nx, jj, z, z + 1, z * nxy + kk, v, lbx != lb, lrt, jb, nrows);
+            // (the next chunk stages its own rows once every thread is done with these)
+            if constexpr (CMP) __syncthreads();
         }
     } else {
         const int bxl = uni(M->bx_log2);
@@ -999,7 +1166,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
         const int i = (tx << bxl) + lx;
         const int j = ty * uni(M->by) + ly;
         const int z0 = tz * s.nzt;
-        run(i, j, z0, min(z0 + s.nzt, nz), 0, (i < nx) && (j < ny), false);
+        run(i, j, z0, min(z0 + s.nzt, nz), 0, (i < nx) && (j < ny), false, nullptr, 0, 0);
     }
 }
 
@@ -1031,7 +1198,7 @@ __device__ __forceinline__ int div_uni(int n, int d, double inv)
 }
 
 constexpr int kLinksBlock = 64;
-constexpr int kLinkBatch = 1;
+constexpr int kLinkBatch = 4;
 // Direction masks over the links e (d = e*, c_d = -c_e), for sums over a node's links by
 // counting: per axis and weight class (w = 1/18 on the axes, e < 6; 1/36 on the
 // diagonals) the links whose c_d component is +1 or -1 ...
@@ -1068,11 +1235,11 @@ constexpr unsigned pair_mask(int a, int b, int sign)
 // summed from the deviations f~_d - w_d rho_f (the rest part 2 rho_f sum w_d c_d and S come
 // from counts of links per direction class), the sums over the chunk in FP64 in a fixed
 // order; the motion kernel adds the chunks in chunk order and solves for (V, Omega).
+// The deviation sums of a node's links come from the record k_records wrote for the node's
+// slot in this step.
 template <int P>
 __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int only)
 {
-    using S = typename Prec<P>::S;
-    using C = typename Prec<P>::C;
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
     const int lane = threadIdx.x;
@@ -1091,9 +1258,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
     const long long cell_off = uni(M->cell_off);
     const double rho_f = uni(M->rho_f);
-    const int nc = (int)uni(M->ncell);
     const int nxy = nx * ny;
-    const S *A = (const S *)(par ? s.popB : s.popA) + uni(M->pop_off);
     const long long lbase = (long long)p * s.lcap;
     const int k0 = s.lchunk[p * (kChunks + 1) + chunk], k1 = s.lchunk[p * (kChunks + 1) + chunk + 1];
     // (a list rebuild under compact storage moves the nodes' storage slots)
@@ -1114,7 +1279,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         for (int base = k0; base < k1; base += kLinksBlock) {
             const int k = base + lane;
             unsigned grp = 0u;
-            int cell = 0;
+            int cell = 0, slot = 0;
             if (k < k1 && s.lmask[lbase + k] != 0u) {
                 cell = s.lcell[lbase + k];
                 const unsigned long long w0 = s.lw[cell_off + cell];
@@ -1124,7 +1289,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
                     for (int g = 0; g < ng; ++g) {
                         int q;
                         const unsigned gd = slot_dirs(w0, w1, g, q);
-                        if (gd != 0u && q == pl) { grp = gd; break; }
+                        if (gd != 0u && q == pl) { grp = gd; slot = g; break; }
                     }
                 }
             }
@@ -1133,7 +1298,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
             if (has) {
                 const int at = cntx + __popcll(bal & ((1ull << lane) - 1ull));
                 const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
-                xc[at] = cell;
+                xc[at] = (int)((unsigned)cell | ((unsigned)slot << 30));
                 xs[at] = node_slot(s, M, cell, rem - jj * nx, jj, kk);
                 xg[at] = grp;
             }
@@ -1146,56 +1311,33 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         cntx = cnt_old;
     }
 
-    // (2) F0, T0 and Z over the entries
-    double acc[kLinkComp];
-#pragma unroll
-    for (int c = 0; c < kLinkComp; ++c) acc[c] = 0.0;
+    // Positions of the entries' nodes relative to the shell list's reference point X_ref,
+    // xr = x - X_ref (minimum image; X_ref moves only when the shell list is rebuilt, which
+    // rebuilds the entries).  With delta = X - X_ref, r = xr - delta, so the torque is
+    // sum xr x G - delta x F0, and Z follows from sums over the link set alone:
+    // S = sum S_n, Qx = sum [xr] S_n, Wx = sum [xr] S_n [xr]^T (the motion kernel applies delta).
+    const double R0 = s.Xref[3 * p], R1 = s.Xref[3 * p + 1], R2 = s.Xref[3 * p + 2];
     const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;   // 2 rho_f w_d
     const double z18 = rho_f / 3.0, z36 = rho_f / 6.0;                  // 6 rho_f w_d
     const double inv_nxy = 1.0 / (double)nxy, inv_nx = 1.0 / (double)nx;
-    for (int base = 0; base < cntx; base += kLinksBlock * kLinkBatch) {
-        int cellb[kLinkBatch], atb[kLinkBatch];
-        unsigned gb[kLinkBatch];
+    auto rel_pos = [&](int cell, double &x0, double &x1, double &x2) {
+        const int kk = div_uni(cell, nxy, inv_nxy), rem = cell - kk * nxy;
+        const int jj = div_uni(rem, nx, inv_nx), ii = rem - jj * nx;
+        x0 = mimg((double)ii - R0, per0, box0);
+        x1 = mimg((double)jj - R1, per1, box1);
+        x2 = mimg((double)kk - R2, per2, box2);
+    };
+
+    // (2) link-set sums of a rebuilt chunk: S, Qx, Wx (21 values, cached per chunk)
+    if (fresh) {
+        double zs[21];
 #pragma unroll
-        for (int b = 0; b < kLinkBatch; ++b) {
-            const int k = base + b * kLinksBlock + lane;
-            const bool v = k < cntx;
-            cellb[b] = v ? xc[k] : 0;
-            atb[b] = v ? max(xs[k], 0) : 0; // (a node with links is fluid, hence listed)
-            gb[b] = v ? xg[k] : 0u;
-        }
-        // f~_d(x, t) of every link of the batch (d = e*, loads issued for all directions;
-        // a lane without that link reads the node's first population)
-        C fv[kLinkBatch][kQ - 1];
-#pragma unroll
-        for (int b = 0; b < kLinkBatch; ++b)
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e) {
-                const bool on = (gb[b] >> e) & 1u;
-                const S raw = ldo(A, (unsigned)(on ? kOPP[e] * nc + atb[b] : atb[b]));
-                fv[b][e] = on ? decode_dev<P>(raw, kOPP[e], rho_f) : C(0);
-            }
-#pragma unroll
-        for (int b = 0; b < kLinkBatch; ++b) {
-            const unsigned g = gb[b];
-            if (g == 0u) continue;
-            // G = sum 2 c_d (f~_d - w_d rho_f) + 2 rho_f sum w_d c_d
-            double D0 = 0.0, D1 = 0.0, D2 = 0.0;
-#pragma unroll
-            for (int e = 0; e < kQ - 1; ++e) {
-                const int d = kOPP[e];
-                const double v = (double)fv[b][e];
-                if (kCX[d] > 0) D0 += v; else if (kCX[d] < 0) D0 -= v;
-                if (kCY[d] > 0) D1 += v; else if (kCY[d] < 0) D1 -= v;
-                if (kCZ[d] > 0) D2 += v; else if (kCZ[d] < 0) D2 -= v;
-            }
-            auto rest = [&](int axis) {
-                const int na = (int)__popc(g & link_mask(axis, 1, false)) - (int)__popc(g & link_mask(axis, -1, false));
-                const int nd = (int)__popc(g & link_mask(axis, 1, true)) - (int)__popc(g & link_mask(axis, -1, true));
-                return a18 * (double)na + a36 * (double)nd;
-            };
-            const double G0 = 2.0 * D0 + rest(0), G1 = 2.0 * D1 + rest(1), G2 = 2.0 * D2 + rest(2);
-            // S = sum 6 w_d rho_f c_d c_d^T over the node's links, from counts
+        for (int c = 0; c < 21; ++c) zs[c] = 0.0;
+        for (int k = lane; k < cntx; k += kLinksBlock) {
+            const unsigned g = xg[k];
+            double x0, x1, x2;
+            rel_pos((int)((unsigned)xc[k] & 0x3fffffffu), x0, x1, x2);
+            // S_n = sum 6 w_d rho_f c_d c_d^T over the node's links, from counts
             auto diag = [&](int axis) {
                 return z18 * (double)__popc(g & (link_mask(axis, 1, false) | link_mask(axis, -1, false))) +
                        z36 * (double)__popc(g & (link_mask(axis, 1, true) | link_mask(axis, -1, true)));
@@ -1205,48 +1347,82 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
                 const int n = (int)__popc(g & pair_mask(a, b2, 1)) - (int)__popc(g & pair_mask(a, b2, -1));
                 return z36 * (double)n;
             };
-            const double Sxx = diag(0), Syy = diag(1), Szz = diag(2);
             const double Sxy = offd(0, 1), Sxz = offd(0, 2), Syz = offd(1, 2);
-            const double Sm[3][3] = {{Sxx, Sxy, Sxz}, {Sxy, Syy, Syz}, {Sxz, Syz, Szz}};
-            const int cell = cellb[b];
-            const int kk = div_uni(cell, nxy, inv_nxy), rem = cell - kk * nxy;
-            const int jj = div_uni(rem, nx, inv_nx), ii = rem - jj * nx;
-            const double r0 = mimg((double)ii - X0, per0, box0);
-            const double r1 = mimg((double)jj - X1, per1, box1);
-            const double r2 = mimg((double)kk - X2, per2, box2);
-            acc[0] += G0; acc[1] += G1; acc[2] += G2;
-            acc[3] += r1 * G2 - r2 * G1;
-            acc[4] += r2 * G0 - r0 * G2;
-            acc[5] += r0 * G1 - r1 * G0;
-            // Q = [r] S (row a of Q: r x (column of S)); Z_OmegaV = Q, Z_VOmega = Q^T
-            double Qm[3][3];
+            const double Sm[3][3] = {{diag(0), Sxy, Sxz}, {Sxy, diag(1), Syz}, {Sxz, Syz, diag(2)}};
+            // Q = [xr] S_n (row a: xr x (column of S_n)), W = Q [xr]^T
+            double Qm[3][3], Wm[3][3];
 #pragma unroll
             for (int n = 0; n < 3; ++n) {
-                Qm[0][n] = r1 * Sm[2][n] - r2 * Sm[1][n];
-                Qm[1][n] = r2 * Sm[0][n] - r0 * Sm[2][n];
-                Qm[2][n] = r0 * Sm[1][n] - r1 * Sm[0][n];
+                Qm[0][n] = x1 * Sm[2][n] - x2 * Sm[1][n];
+                Qm[1][n] = x2 * Sm[0][n] - x0 * Sm[2][n];
+                Qm[2][n] = x0 * Sm[1][n] - x1 * Sm[0][n];
             }
-            // Z_OmegaOmega = Q [r]^T: entry (a, b) = (r x row a of Q)_b
-            double Wm[3][3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                Wm[a][0] = r1 * Qm[a][2] - r2 * Qm[a][1];
-                Wm[a][1] = r2 * Qm[a][0] - r0 * Qm[a][2];
-                Wm[a][2] = r0 * Qm[a][1] - r1 * Qm[a][0];
+                Wm[a][0] = x1 * Qm[a][2] - x2 * Qm[a][1];
+                Wm[a][1] = x2 * Qm[a][0] - x0 * Qm[a][2];
+                Wm[a][2] = x0 * Qm[a][1] - x1 * Qm[a][0];
             }
-            // upper triangle of Z, row by row: rows 0-2 (V), then rows 3-5 (Omega)
-            int z = 6;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-#pragma unroll
-                for (int b2 = a; b2 < 3; ++b2) acc[z++] += Sm[a][b2];
-#pragma unroll
-                for (int b2 = 0; b2 < 3; ++b2) acc[z++] += Qm[b2][a];
-            }
+            int z = 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b2 = a; b2 < 3; ++b2) acc[z++] += Wm[a][b2];
+                for (int b2 = a; b2 < 3; ++b2) zs[z++] += Sm[a][b2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b2 = 0; b2 < 3; ++b2) zs[z++] += Qm[a][b2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b2 = a; b2 < 3; ++b2) zs[z++] += Wm[a][b2];
+        }
+#pragma unroll
+        for (int c = 0; c < 21; ++c) zs[c] = wave_sum(zs[c]);
+        if (lane == 0) {
+            double *zc = s.zcache + ((long long)p * kChunks + chunk) * kZComp;
+#pragma unroll
+            for (int c = 0; c < 21; ++c) zc[c] = zs[c];
+        }
+    }
+
+    // (3) F0 = sum 2 c_d f~_d and sum xr x (the node's part of F0) over the entries
+    double acc[kLinkComp];
+#pragma unroll
+    for (int c = 0; c < kLinkComp; ++c) acc[c] = 0.0;
+    for (int base = 0; base < cntx; base += kLinksBlock * kLinkBatch) {
+        int cellb[kLinkBatch];
+        unsigned gb[kLinkBatch];
+        double Db[kLinkBatch][3];
+#pragma unroll
+        for (int b = 0; b < kLinkBatch; ++b) {
+            const int k = base + b * kLinksBlock + lane;
+            const bool v = k < cntx;
+            const unsigned ent = v ? (unsigned)xc[k] : 0u;
+            cellb[b] = (int)(ent & 0x3fffffffu);
+            // (a node with links is fluid, hence listed; entries past the count read the
+            // first record and carry no directions)
+            const int at = v ? max(xs[k], 0) : 0;
+            gb[b] = v ? xg[k] : 0u;
+            (void)get_record<P>(s, (int)(ent >> 30), cell_off + at, Db[b][0], Db[b][1], Db[b][2]);
+        }
+#pragma unroll
+        for (int b = 0; b < kLinkBatch; ++b) {
+            const unsigned g = gb[b];
+            if (g == 0u) continue;
+            // G = sum 2 c_d (f~_d - w_d rho_f) + 2 rho_f sum w_d c_d
+            auto rest = [&](int axis) {
+                const int na = (int)__popc(g & link_mask(axis, 1, false)) - (int)__popc(g & link_mask(axis, -1, false));
+                const int nd = (int)__popc(g & link_mask(axis, 1, true)) - (int)__popc(g & link_mask(axis, -1, true));
+                return a18 * (double)na + a36 * (double)nd;
+            };
+            const double G0 = 2.0 * Db[b][0] + rest(0), G1 = 2.0 * Db[b][1] + rest(1), G2 = 2.0 * Db[b][2] + rest(2);
+            double x0, x1, x2;
+            rel_pos(cellb[b], x0, x1, x2);
+            acc[0] += G0; acc[1] += G1; acc[2] += G2;
+            acc[3] += x1 * G2 - x2 * G1;
+            acc[4] += x2 * G0 - x0 * G2;
+            acc[5] += x0 * G1 - x1 * G0;
         }
     }
 #pragma unroll
@@ -1322,21 +1498,26 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
     const double R = s.R[p];
     const int per0 = M->per[0], per1 = M->per[1], per2 = M->per[2];
     const double box0 = M->box[0], box1 = M->box[1], box2 = M->box[2];
-    // the link pass's sums (lane c < kLinkComp adds component c over the chunks, in chunk
-    // order) and the rest of p's state for the update, loaded up front
-    static_assert(kLinkComp <= 64, "one lane per link-pass component");
+    // the link pass's sums (lane c < kLinkComp adds component c of the partials over the
+    // chunks, lane kLinkComp + c component c of the cached link-set sums, in chunk order)
+    // and the rest of p's state for the update, loaded up front
+    static_assert(kLinkComp + kZComp <= 64, "one lane per link-pass component");
     // (with the hydrodynamics switched off there are neither link forces nor conversion
     // momenta)
     const bool hyd = !s.fluid_off;
     double ppv = 0.0;
-    if (mode == 0 && hyd && lane < kLinkComp) {
-        const double *pp = s.ppart + (long long)p * kChunks * kLinkComp + lane;
+    if (mode == 0 && hyd && lane < kLinkComp + kZComp) {
+        const bool part = lane < kLinkComp;
+        const int stride = part ? kLinkComp : kZComp;
+        const double *pp = part ? s.ppart + (long long)p * kChunks * kLinkComp + lane
+                                : s.zcache + (long long)p * kChunks * kZComp + (lane - kLinkComp);
         double ch[kChunks];
 #pragma unroll
-        for (int q = 0; q < kChunks; ++q) ch[q] = pp[q * kLinkComp];
+        for (int q = 0; q < kChunks; ++q) ch[q] = pp[q * stride];
 #pragma unroll
         for (int q = 0; q < kChunks; ++q) ppv += ch[q];
     }
+    const double Xr0 = s.Xref[3 * p], Xr1 = s.Xref[3 * p + 1], Xr2 = s.Xref[3 * p + 2];
     double Phv[3], Lhv[3], Fgv[3], Vpv[3], Wpv[3];
     for (int a = 0; a < 3; ++a) {
         Phv[a] = hyd ? s.Ph[3 * p + a] : 0.0;
@@ -1447,23 +1628,68 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
 #pragma unroll
     for (int c = 0; c < 6; ++c) con[c] = wave_sum(con[c]);
 
-    // the link pass's sums (every lane takes the same values): F0, T0, upper triangle of Z
-    double lp[kLinkComp];
+    // the link pass's sums (every lane takes the same values): F0, sum xr x G, then the
+    // link-set sums S, Qx, Wx
+    double lp[kLinkComp + kZComp];
 #pragma unroll
-    for (int c = 0; c < kLinkComp; ++c) lp[c] = readlane_d(ppv, c);
+    for (int c = 0; c < kLinkComp + kZComp; ++c) lp[c] = readlane_d(ppv, c);
     if (lane == 0) {
         double *Xn = s.X[par ^ 1], *Vn = s.V[par ^ 1], *Wn = s.W[par ^ 1];
         const double Xc[3] = {X0, X1, X2};
         const int per[3] = {per0, per1, per2};
         const double box[3] = {box0, box1, box2};
-        // (M + Z)(V', Omega') = M (V, Omega) + F0 + contacts + F_g + pending impulses
-        double A[6][6], b[6];
+        // delta = X - X_ref: the torque arm of a link node is xr - delta
+        const double dl[3] = {mimg(X0 - Xr0, per0, box0), mimg(X1 - Xr1, per1, box1), mimg(X2 - Xr2, per2, box2)};
+        // T0 = sum xr x G - delta x F0
+        lp[3] -= dl[1] * lp[2] - dl[2] * lp[1];
+        lp[4] -= dl[2] * lp[0] - dl[0] * lp[2];
+        lp[5] -= dl[0] * lp[1] - dl[1] * lp[0];
+        // Z: Z_VV = S, Z_OmegaV = Qx - [delta] S, Z_OmegaOmega = Wx - Qx [delta]^T - [delta] Qx^T
+        // + [delta] S [delta]^T, with [delta] v = delta x v
+        double Sm[3][3], Qm[3][3], Wm[3][3];
         {
-            int z = 6;
-#pragma unroll
+            const double *zz = lp + kLinkComp;
+            int z = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int c = a; c < 3; ++c) { Sm[a][c] = zz[z]; Sm[c][a] = zz[z]; ++z; }
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) Qm[a][c] = zz[z++];
+            for (int a = 0; a < 3; ++a)
+                for (int c = a; c < 3; ++c) { Wm[a][c] = zz[z]; Wm[c][a] = zz[z]; ++z; }
+        }
+        const double Dm[3][3] = {{0.0, -dl[2], dl[1]}, {dl[2], 0.0, -dl[0]}, {-dl[1], dl[0], 0.0}};
+        double DS[3][3], ZOV[3][3], ZOO[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) {
+                double v = 0.0;
+                for (int k = 0; k < 3; ++k) v += Dm[a][k] * Sm[k][c];
+                DS[a][c] = v;
+                ZOV[a][c] = Qm[a][c] - v;
+            }
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) {
+                double qd = 0.0, dq = 0.0, dsd = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    qd += Qm[a][k] * Dm[c][k];
+                    dq += Dm[a][k] * Qm[c][k];
+                    dsd += DS[a][k] * Dm[c][k];
+                }
+                ZOO[a][c] = ((Wm[a][c] - qd) - dq) + dsd;
+            }
+        // (M + Z)(V', Omega') = M (V, Omega) + F0 + contacts + F_g + pending impulses; Z's
+        // upper triangle: rows 0-2 (V) S and Z_VOmega = Z_OmegaV^T, rows 3-5 Z_OmegaOmega
+        double A[6][6], b[6];
+        double zup[21];
+        {
+            int z = 0;
+            for (int a = 0; a < 3; ++a) {
+                for (int c = a; c < 3; ++c) A[a][c] = Sm[a][c];
+                for (int c = 0; c < 3; ++c) A[a][3 + c] = ZOV[c][a];
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int c = a; c < 3; ++c) A[3 + a][3 + c] = ZOO[a][c];
             for (int a = 0; a < 6; ++a)
-#pragma unroll
-                for (int c = a; c < 6; ++c) A[a][c] = lp[z++];
+                for (int c = a; c < 6; ++c) zup[z++] = A[a][c];
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1498,12 +1724,12 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
         const double xv[6] = {v[0], v[1], v[2], w[0], w[1], w[2]};
         double zx[6] = {0, 0, 0, 0, 0, 0};
         {
-            int z = 6;
+            int z = 0;
 #pragma unroll
             for (int a = 0; a < 6; ++a)
 #pragma unroll
                 for (int c = a; c < 6; ++c) {
-                    const double zz = lp[z++];
+                    const double zz = zup[z++];
                     zx[a] += zz * xv[c];
                     if (c != a) zx[c] += zz * xv[a];
                 }
@@ -2620,6 +2846,24 @@ hipError_t launch_refresh(int prec, const DevSet &s, hipStream_t st)
 }
 int motion_grid(const DevSet &s) { return max((s.ptot + kMotionWaves - 1) / kMotionWaves, 1); }
 int remap_grid(const DevSet &s) { return max((s.ptot + kRemapWaves - 1) / kRemapWaves + s.nprobe_total, 1); }
+
+template <bool CMP>
+void *records_ptr(int prec)
+{
+    switch (prec) {
+    case PREC_FP64: return (void *)&k_records<PREC_FP64, CMP>;
+    case PREC_FP32: return (void *)&k_records<PREC_FP32, CMP>;
+    case PREC_FP16DEV: return (void *)&k_records<PREC_FP16DEV, CMP>;
+    default: return (void *)&k_records<PREC_BF16DEV, CMP>;
+    }
+}
+void *records_kernel_ptr(int prec, int compact) { return compact ? records_ptr<true>(prec) : records_ptr<false>(prec); }
+hipError_t launch_records(int prec, const DevSet &s, hipStream_t st)
+{
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(DevSet)>(records_kernel_ptr(prec, s.compact)), dim3(s.tiles_total),
+                       dim3(256), 0, st, s);
+    return hipGetLastError();
+}
 
 template <bool CMP>
 void launch_fluid_t(int prec, const DevSet &s, hipStream_t st)

@@ -53,10 +53,11 @@ def test_workspace_size_and_validation(lb):
     assert rc == lb.OK
     # per node: FP32 populations (two buffers and the scratch buffer of compact storage,
     # the default mapping: 3 x 19 x 4 B), two node maps (8 B), two link words (16 B), the
-    # node list and the parked-refill index (8 B); then the per-particle shell lists (20 B
-    # per entry, about 5.6 k entries per sphere of radius 9) and small tables
+    # node list and the parked-refill index (8 B), four 16-byte link records (64 B); then
+    # the per-particle shell lists (20 B per entry, about 5.6 k entries per sphere of
+    # radius 9) and small tables
     cells = 96 * 96 * 384
-    per_node = 3 * 19 * 4 + 8 + 16 + 8
+    per_node = 3 * 19 * 4 + 8 + 16 + 8 + 64
     assert per_node * cells <= n < per_node * cells + 1024 * 5600 * 20 * 1.5 + (64 << 20)
     bad = [
         lb.make_params(8, 8, 8, tau=0.5),                         # tau must exceed 1/2
