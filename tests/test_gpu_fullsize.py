@@ -5,6 +5,8 @@ The FCC wave case is run at 96 x 96 x 384 (1024 spheres) exactly as bench.py lau
 (HIP graphs of 8 steps, automatic tiles) for a few steps, which the oracle can afford:
 FP64 to the 1e-10 bar with bit-exact node maps; FP32 against the same FP64 oracle state.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -67,33 +69,93 @@ def test_full_size_fcc_bench_configuration(fcc_oracle, precision, tol_f, tol_pro
         assert np.abs(rg - ro).max() <= tol_probe * np.abs(ro).max() + 1e-15
         g, o = gs.particles_get(0), s.particles()
         assert np.abs(g["x"] - o["x"]).max() <= 1e-10 * 384
-        # the hydrodynamic force is a sum over ~4.8k links of terms ~0.1 that cancel to
-        # ~1e-3; its rounding floor per step (~1e-12 in FP64, ~4.8k x 4e-9 ~ 2e-5 with
-        # FP32 populations, any summation order) bounds how well two codes can agree on
-        # velocities this early (|v| ~ 1e-6)
+        # the hydrodynamic force is a sum over ~4.8k links whose partial sums reach |F|
+        # (up to ~40 on spheres whose surface a neighbour's lens cuts); two summation
+        # orders of it differ by ~|F| 2^-52 sqrt(4.8k) per step in FP64 (4.8k x 4e-9 ~ 2e-5
+        # with FP32 populations), which bounds how well two codes can agree on velocities
+        # this early (|v| ~ 1e-6): 8 steps of that over the lightest sphere's mass
         m_min = params["rho_p"] * 4.0 / 3.0 * np.pi * float(np.min(pk["radius"])) ** 3
-        floor = (1e-12 if precision == "fp64" else 2e-5) * 8 / m_min
+        f_step = np.abs(o["force"]).max() * 2.0 ** -52 * math.sqrt(4.8e3) if precision == "fp64" else 2e-5
+        floor = f_step * 8 / m_min
         assert np.abs(g["v"] - o["v"]).max() <= tol_v * np.abs(o["v"]).max() + floor
         assert gs.status() == 0
 
 
-def test_settling_sphere_long_window_fp64():
-    """Config 1 (32^3 walls, R = 6, density ratio 2, g = 1e-5, tau = 0.8): trajectory
-    parity over 400 steps, sampled every 50 steps."""
+def _brenner(h, radius, nmax=60):
+    """Drag of a sphere of this radius moving normal to a plane wall at centre distance h,
+    relative to Stokes drag (Brenner's exact series, 1961)."""
+    a = math.acosh(h / radius)
+    tot = 0.0
+    for n in range(1, nmax):
+        num = 2.0 * math.sinh((2 * n + 1) * a) + (2 * n + 1) * math.sinh(2.0 * a)
+        den = 4.0 * math.sinh((n + 0.5) * a) ** 2 - (2 * n + 1) ** 2 * math.sinh(a) ** 2
+        tot += n * (n + 1) / ((2 * n - 1) * (2 * n + 3)) * (num / den - 1.0)
+    return 4.0 / 3.0 * math.sinh(a) * tot
+
+
+def test_settling_sphere_config_1_fp64():
+    """Config 1 as stated: 32^3 box with half-way walls, a sphere of radius 6 at the top
+    centre (centre 2 lu below the top wall's gap, (15.5, 15.5, 23.5)), density ratio 2,
+    g = 1e-5, tau = 0.8, 1000 FP64 steps: trajectory parity with the oracle every 100
+    steps, node maps exact; then the settling speed against Stokes drag with the walls'
+    correction.  The top wall is 8 lu from the centre (h / R = 1.33) and dominates:
+    Brenner's exact drag factor for a sphere moving normal to a plane wall is 4.0 - 4.3
+    there, the side walls alone (Haberman-Sayre, the duct bracketed by cylinders of radius
+    16 and 32 / sqrt(pi)) give 2.7 - 3.2.  The measured factor must be at least the nearer
+    wall's alone and at most the sum of the two excess drags."""
     from paper_1808_08921_amd.lbdem import LatticeSet
 
     params, pk = inputs.settling_case()
     params["max_particles"] = 1
+    assert tuple(pk["x"][0]) == (15.5, 15.5, 23.5)
     s = _oracle(params, pk)
     with LatticeSet([params], precision="fp64", graph_steps=8) as gs:
         gs.particles_set(0, pk["x"], pk["radius"], fg=pk["fg"], fixed=pk["fixed"])
-        for _ in range(8):
-            gs.step(50)
-            s.step(50)
+        for _ in range(10):
+            gs.step(100)
+            s.step(100)
             g, o = gs.particles_get(0), s.particles()
             assert np.abs(g["x"] - o["x"]).max() <= 1e-10 * 32
             assert np.abs(g["v"] - o["v"]).max() <= 1e-10 * np.abs(o["v"]).max()
             assert np.array_equal(gs.owner(0), s.owner())
-        # falling: V_z < 0 and growing in magnitude toward the terminal velocity
-        assert g["v"][0, 2] < 0.0
+        assert gs.t == 1000 and gs.status() == 0
+    s.close()
+    nu = (params["tau"] - 0.5) / 3.0
+    radius = float(pk["radius"][0])
+    v_stokes = -pk["fg"][0, 2] / (6.0 * math.pi * nu * radius)
+    vz = g["v"][0, 2]
+    assert vz < 0.0
+    ratio = v_stokes / -vz
+    top = params["nz"] - 0.5                      # half-way wall above the last node
+    h_start, h_end = top - pk["x"][0, 2], top - g["x"][0, 2]
+    assert _brenner(h_end, radius) <= ratio <= 3.2 + _brenner(h_start, radius) - 1.0, ratio
+
+
+def test_full_size_fcc_moving_spheres_fp64():
+    """The full 96 x 96 x 384 FCC case in FP64 with the mobile spheres given seeded
+    velocities of up to 0.02 lu per step: 25 steps with nodes covered and uncovered every
+    step and the compact node lists rebuilt as the spheres cross the list skin; node maps
+    bit-exact and particles within 1e-10 of the oracle every 5 steps."""
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    params, pk = inputs.wave_fcc_case(seed=0)
+    params["max_particles"] = len(pk["x"])
+    rng = np.random.default_rng(31)
+    v = rng.uniform(-0.02, 0.02, (len(pk["x"]), 3))
+    v[pk["fixed"] == 1] = 0.0
+    s = _oracle(params, dict(pk, v=v))
+    with LatticeSet([params], precision="fp64", graph_steps=8) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], v=v, fixed=pk["fixed"])
+        own0 = gs.owner(0)
+        for _ in range(5):
+            gs.step(5)
+            s.step(5)
+            own_g, own_o = gs.owner(0), s.owner()
+            assert np.array_equal(own_g, own_o), f"{int((own_g != own_o).sum())} nodes differ"
+            g, o = gs.particles_get(0), s.particles()
+            assert np.abs(g["x"] - o["x"]).max() <= 1e-10 * 384
+            assert np.abs(g["v"] - o["v"]).max() <= 1e-10 * np.abs(o["v"]).max()
+            assert np.abs(g["force"] - o["force"]).max() <= 1e-10 * np.abs(o["force"]).max()
+        assert int((own_g != own0).sum()) > 10000   # conversions all over the packing
+        assert gs.status() & 0x1da == 0
     s.close()

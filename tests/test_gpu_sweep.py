@@ -51,9 +51,16 @@ def test_source_table_ensemble_matches_oracle():
             s = _oracle_column(300, r, zs)
             s.step(600)
             po = s.probes()
-            d_rho = np.abs(pg[:, :, 1] / pg[:, :, 0] - po[:, :, 1] / po[:, :, 0]).max()
-            d_mom = np.abs(pg[:, :, 2] / pg[:, :, 3] - po[:, :, 2] / po[:, :, 3]).max()
-            assert d_rho <= 1e-11 and d_mom <= 1e-11, (r, d_rho, d_mom)
+            ro, mo = po[:, :, 1] / po[:, :, 0], po[:, :, 2] / po[:, :, 3]
+            d_rho = np.abs(pg[:, :, 1] / pg[:, :, 0] - ro).max()
+            d_mom = np.abs(pg[:, :, 2] / pg[:, :, 3] - mo).max()
+            # 1e-10 of each signal's own scale (its largest value over planes and steps), plus
+            # the oracle's rounding floor: it carries the full populations (~1/18 ... 1/3),
+            # rounded at 2^-53 relative each step, so after 600 steps its plane averages of
+            # rho' and rho u_z can have moved by up to ~600 x 2^-53 ~ 7e-14 on their own
+            floor = 600 * 2.0 ** -53
+            assert d_rho <= 1e-10 * np.abs(ro).max() + floor, (r, d_rho)
+            assert d_mom <= 1e-10 * np.abs(mo).max() + floor, (r, d_mom)
             # the source acts: the inlet plane follows the waveform, the far planes are reached
             assert np.abs(po[:, 0, 1]).max() > 0.5 * r["amp"]
             assert np.abs(po[:, 5, 1]).max() > 1e-3 * r["amp"]
