@@ -82,3 +82,40 @@ def lossy_alpha(omega, c_s, tau_s):
     """Spatial absorption coefficient of Eq. (1Dwave) for sound speed c_s and relaxation time tau_s."""
     q = np.sqrt(1.0 + (omega * tau_s) ** 2)
     return omega / (c_s * np.sqrt(2.0)) * np.sqrt((q - 1.0) / q)
+
+
+def biot_velocities(k_dry, g_dry, phi, k_p, k_f, rho_p, rho_f, r=0.5):
+    """Wave velocities of a saturated poroelastic packing from Biot's theory (Sec. "Biot's
+    equations of wave velocities in saturated poroelastic media", Eqs. vp and vs): the fast
+    and slow P-waves and the S-wave, from the dry packing's moduli k_dry, g_dry, the
+    porosity phi, the particles' and the fluid's bulk moduli k_p, k_f and densities rho_p,
+    rho_f, with the tortuosity alpha = 1 - r (1 - 1/phi).
+
+    Reading: the denominator of Eq. (vp) is 2 (rho_11 rho_22 - rho_12^2), the discriminant
+    of the quadratic det(rho v^2 - E) = 0 that Eq. (vp) solves (the printed rho_12 rho_22 is
+    taken as a typo).  Returns (v_fast, v_slow, v_s)."""
+    alpha = 1.0 - r * (1.0 - 1.0 / phi)
+    rho11 = (1.0 - phi) * rho_p - (1.0 - alpha) * phi * rho_f
+    rho22 = alpha * phi * rho_f
+    rho12 = (1.0 - alpha) * phi * rho_f
+    rho_hat = (1.0 - phi) * rho_p + phi * rho_f
+    den = 1.0 - phi - k_dry / k_p + phi * k_p / k_f
+    P = ((1.0 - phi) * (1.0 - phi - k_dry / k_p) * k_p + phi * k_p * k_dry / k_f) / den + 4.0 / 3.0 * g_dry
+    Q = (1.0 - phi - k_dry / k_p) * phi * k_p / den
+    R = phi * phi * k_p / den
+    delta = P * rho22 + R * rho11 - 2.0 * Q * rho12
+    disc = np.sqrt(delta * delta - 4.0 * (rho11 * rho22 - rho12 * rho12) * (P * R - Q * Q))
+    two_d = 2.0 * (rho11 * rho22 - rho12 * rho12)
+    v_fast = np.sqrt((delta + disc) / two_d)
+    v_slow = np.sqrt((delta - disc) / two_d)
+    v_s = np.sqrt(g_dry / (rho_hat - phi * rho_f / alpha))
+    return float(v_fast), float(v_slow), float(v_s)
+
+
+def biot_moduli(k_dry, g_dry, phi, k_p, k_f):
+    """Biot's elastic moduli P, Q, R of the same section (for checks)."""
+    den = 1.0 - phi - k_dry / k_p + phi * k_p / k_f
+    P = ((1.0 - phi) * (1.0 - phi - k_dry / k_p) * k_p + phi * k_p * k_dry / k_f) / den + 4.0 / 3.0 * g_dry
+    Q = (1.0 - phi - k_dry / k_p) * phi * k_p / den
+    R = phi * phi * k_p / den
+    return P, Q, R

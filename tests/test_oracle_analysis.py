@@ -142,3 +142,50 @@ def test_frequency_sweep_follows_the_lossy_wave(orc, an, f_mhz, rel_alpha, rel_c
     assert al == pytest.approx(an.lossy_alpha(om, cs, 1.0), rel=rel_alpha)
     assert c == pytest.approx(cs, rel=rel_c)
     assert abs(A - (-1j)) < 0.01
+
+
+# ---------------------------------------------------------------------------
+# Biot's wave velocities (Sec. "Biot's equations ...", Eqs. vp, vs)
+# ---------------------------------------------------------------------------
+_BIOT_CASES = [
+    # k_dry, g_dry, phi, k_p, k_f, rho_p, rho_f (lattice units: the FCC packing's porosity,
+    # E* = 10.37 and nu = 0.2 give k_p = E / (3 (1 - 2 nu)), k_f = rho_f c_s^2 = 1/3)
+    (0.05, 0.04, 0.266, 10.37 / 1.8, 1.0 / 3.0, 2.466, 1.0),
+    (0.5, 0.35, 0.266, 10.37 / 1.8, 1.0 / 3.0, 2.466, 1.0),
+    (2.0, 1.5, 0.40, 12.0, 2.25, 2.65, 1.0),
+]
+
+
+@pytest.mark.parametrize("case", _BIOT_CASES)
+def test_biot_velocities_solve_the_characteristic_equation(an, case):
+    """The fast and slow P-wave speeds of Eq. (vp) are the two roots of
+    det(rho v^2 - E) = 0 with E = [[P, Q], [Q, R]] and the mass matrix [[rho11, rho12],
+    [rho12, rho22]]: generalized eigenvalues computed by numpy (this fixes the printed
+    denominator's reading, rho11 rho22 - rho12^2).  The S-wave speed of Eq. (vs) is the
+    nonzero root of the shear problem det(rho v^2 - diag(G_dry, 0)) = 0, G_dry / (rho11 -
+    rho12^2 / rho22)."""
+    k_dry, g_dry, phi, k_p, k_f, rho_p, rho_f = case
+    vf, vsl, vs = an.biot_velocities(*case)
+    P, Q, R = an.biot_moduli(k_dry, g_dry, phi, k_p, k_f)
+    alpha = 1.0 - 0.5 * (1.0 - 1.0 / phi)
+    rho12 = (1.0 - alpha) * phi * rho_f
+    rho11 = (1.0 - phi) * rho_p - rho12
+    rho22 = alpha * phi * rho_f
+    M = np.array([[rho11, rho12], [rho12, rho22]])
+    E = np.array([[P, Q], [Q, R]])
+    ev = np.sort(np.linalg.eigvals(np.linalg.solve(M, E)).real)
+    assert vsl ** 2 == pytest.approx(ev[0], rel=1e-12)
+    assert vf ** 2 == pytest.approx(ev[1], rel=1e-12)
+    assert vs ** 2 == pytest.approx(g_dry / (rho11 - rho12 ** 2 / rho22), rel=1e-12)
+    assert vf > vsl > 0.0 and vs > 0.0
+
+
+@pytest.mark.parametrize("case", _BIOT_CASES)
+def test_biot_moduli_give_gassmanns_undrained_modulus(an, case):
+    """P + 2Q + R - (4/3) G_dry is the undrained bulk modulus of the saturated packing,
+    which Gassmann's relation gives independently: K_dry + (1 - K_dry/K_p)^2 /
+    (phi/K_f + (1 - phi)/K_p - K_dry/K_p^2)."""
+    k_dry, g_dry, phi, k_p, k_f, rho_p, rho_f = case
+    P, Q, R = an.biot_moduli(k_dry, g_dry, phi, k_p, k_f)
+    k_sat = k_dry + (1.0 - k_dry / k_p) ** 2 / (phi / k_f + (1.0 - phi) / k_p - k_dry / k_p ** 2)
+    assert P + 2.0 * Q + R - 4.0 / 3.0 * g_dry == pytest.approx(k_sat, rel=1e-12)
