@@ -167,31 +167,86 @@ def host_cpu():
     return model, avail, os.cpu_count()
 
 
-def cpu_baseline(params, pk, budget_s=20.0):
-    """The FP64 oracle on the host (single thread) on the same workload: steps of the
-    full 96 x 96 x 384 lattice until about `budget_s` seconds have passed."""
+def _oracle_steps(params, pk, budget_s, max_steps, ready=None):
+    """Steps of the oracle on the full FCC case until about `budget_s` seconds have passed
+    (at most `max_steps`); `ready` is called after the set-up, before the timed loop.
+    Returns (fluid nodes, steps, seconds)."""
     import oracle
 
-    oracle.build()
     p = params
     s = oracle.Sim(p["nx"], p["ny"], p["nz"], tau=p["tau"], bc=p["bc"], wave=p["wave"], amp=p["amp"],
                    omega=p["omega"], t_n=p["t_n"], E=p["E"], nu=p["nu"], mu=p["mu"], rho_p=p["rho_p"],
                    probe_z=p["probe_z"])
     s.set_particles(pk["x"], pk["radius"], fixed=pk["fixed"])
     nfl = int((s.owner() < 0).sum())
+    if ready is not None:
+        ready()
     t0 = time.perf_counter()
     n = 0
     while True:
         s.step(1)
         n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 50:
+        if time.perf_counter() - t0 > budget_s or n >= max_steps:
             break
     dt = time.perf_counter() - t0
     s.close()
+    return nfl, n, dt
+
+
+def cpu_worker(budget_s):
+    """One process of the all-core baseline: set up, report, wait for the start line on
+    stdin, run the timed steps and print (fluid nodes, steps, seconds) as JSON."""
+    params, pk = _case(seed=0)
+
+    def ready():
+        print("ready", flush=True)
+        sys.stdin.readline()
+
+    nfl, n, dt = _oracle_steps(params, pk, budget_s, 1 << 30, ready)
+    print(json.dumps({"fluid_nodes": nfl, "steps": n, "seconds": dt}), flush=True)
+
+
+def cpu_baseline(params, pk, budget_s=15.0, all_core_s=15.0, max_procs=16):
+    """The FP64 oracle on the host on the same workload, timed two ways: one thread (steps of
+    the full 96 x 96 x 384 lattice until about `budget_s` seconds have passed), and every
+    available core, as one independent oracle process per core stepping its own copy of the
+    case (the oracle itself is single-threaded and is not changed for this); the processes
+    start their timed loops together and the whole host's rate is the sum of theirs."""
+    import subprocess
+
+    import oracle
+
+    oracle.build()
+    nfl, n, dt = _oracle_steps(params, pk, budget_s, 50)
     model, avail, total = host_cpu()
-    return {"value": nfl * n / dt / 1e6, "unit": "MLUPS (fluid nodes)", "cores": 1, "kind": "oracle",
-            "sample": f"{n} full steps of the 96x96x384 FCC case (oracle, FP64, one host thread)",
-            "host_cpu": model, "host_cpus_available": avail, "host_cpus_total": total}
+    single = {"value": nfl * n / dt / 1e6, "unit": "MLUPS (fluid nodes)", "cores": 1,
+              "sample": f"{n} full steps of the 96x96x384 FCC case (oracle, FP64, one host thread)"}
+    k = max(1, min(avail or 1, max_procs))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(all_core_s)],
+                              stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env)
+             for _ in range(k)]
+    try:
+        for pr in procs:
+            if pr.stdout.readline().strip() != "ready":
+                raise RuntimeError("an oracle worker failed during set-up")
+        for pr in procs:
+            pr.stdin.write("go\n")
+            pr.stdin.flush()
+        res = []
+        for pr in procs:
+            res.append(json.loads(pr.stdout.readline()))
+            pr.wait(timeout=600)
+    finally:
+        for pr in procs:
+            if pr.poll() is None:
+                pr.kill()
+    rate = sum(r["fluid_nodes"] * r["steps"] / r["seconds"] for r in res) / 1e6
+    return {"value": rate, "unit": "MLUPS (fluid nodes)", "cores": k, "kind": "oracle",
+            "sample": f"{k} concurrent oracle processes (one per available core), "
+                      f"{min(r['steps'] for r in res)}-{max(r['steps'] for r in res)} full steps each of "
+                      f"the 96x96x384 FCC case (FP64, about {all_core_s:g} s)",
+            "single_thread": single, "host_cpu": model, "host_cpus_available": avail, "host_cpus_total": total}
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1808_08921_amd", "csrc", "lbdem_kernels.hip")
@@ -614,7 +669,11 @@ def main():
     ap.add_argument("--dispersion", action="store_true",
                     help="run the dispersion-analysis workload (space-time DFT of a probe record) instead")
     ap.add_argument("--adjoint", action="store_true", help="run the adjoint-window workload instead of the main line")
+    ap.add_argument("--cpu-worker", type=float, default=0.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args.cpu_worker)
+        return
     if args.dispersion:
         dispersion_bench()
         return

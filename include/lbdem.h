@@ -45,6 +45,7 @@ extern "C" {
 #define LBDEM_ENOMEM (-4)    /* the workspace is too small or host memory ran out */
 #define LBDEM_ESTATE (-5)    /* the call is not valid in the current state */
 #define LBDEM_ERANGE (-6)    /* a requested step range is not (or no longer) recorded */
+#define LBDEM_ENUMERIC (-7)  /* the fluid's density left the positive finite numbers (lbdem_status) */
 
 /* face boundary kinds */
 #define LBDEM_PERIODIC 0 /* periodic pair of faces */
@@ -78,6 +79,9 @@ extern "C" {
 #define LBDEM_STATUS_LIST_PARKED 0x200u      /* compact storage: a node turned fluid outside the node lists; its refill
                                                 waited for the next step's list rebuild (results valid; a larger
                                                 list_margin avoids it) */
+#define LBDEM_STATUS_NONFINITE 0x400u        /* watchdog: after a collision a fluid node's density was NaN,
+                                                infinite or not positive (error; checked at every node and
+                                                step by the fluid kernel) */
 
 /* One lattice and its physics (Sec. 2; Table 1 "tab:params" for the FCC runs). */
 typedef struct lbdem_params {
@@ -131,6 +135,9 @@ typedef struct lbdem_config {
                              F_g only (no fluid step, no link forces, no conversion momenta);
                              the node map still follows the particles, while populations and
                              probes carry no meaning; 0 (default) = the coupled step. */
+    int32_t particle_ring; /* number of most recent steps whose particle velocities are kept for
+                              lbdem_particle_signal: 0 (default, none) .. 2^24, 24 bytes per
+                              step and particle of the set */
 } lbdem_config;
 
 typedef struct lbdem_set lbdem_set;
@@ -214,7 +221,8 @@ int lbdem_time(lbdem_set *set, int64_t *t);
 int lbdem_synchronize(lbdem_set *set);
 
 /* Device status bits (LBDEM_STATUS_*) accumulated since create or the last clear
- * (synchronises).  Returns LBDEM_ECAPACITY when an error bit is set. */
+ * (synchronises).  Returns LBDEM_ENUMERIC when the watchdog bit (NONFINITE) is set, else
+ * LBDEM_ECAPACITY when another error bit is set. */
 int lbdem_status(lbdem_set *set, uint32_t *bits, int clear);
 
 /* Probe records of steps [first, first + n) of lattice `lattice` into
@@ -337,6 +345,33 @@ int lbdem_adj_destroy(lbdem_adj *adj);
  * lbdem_probe_read returns; the record of step s is taken at time level s + 1.
  * Errors: LBDEM_EINVAL for another quantity, LBDEM_ERANGE as for lbdem_probe_read. */
 int lbdem_probe_signal(lbdem_set *set, int32_t lattice, int64_t first, int64_t n, int32_t quantity, double *x);
+
+/* Particle-velocity signal of lattice `lattice` for steps [first, first + n), gathered on
+ * the device from the particle-velocity ring (lbdem_config.particle_ring) on the set's
+ * stream into x[n][n_layers] (device memory): for each step, the average of velocity
+ * component `component` (0, 1, 2 = x, y, z) over the particles of each layer; the record of
+ * step s is the velocity at time level s + 1, the one a particle moves with from X(s) to
+ * X(s + 1) (the dispersion relations of the solid phase are read from the space-time DFT
+ * of such signals, Sec. 4.3).  layer: host array [the lattice's particle count], the layer
+ * of each particle (0 .. n_layers - 1) or -1 to leave it out; a layer without particles
+ * gives 0.  Each layer is summed in particle index order.  The call returns when x is
+ * written.  Errors: LBDEM_EINVAL for bad arguments, LBDEM_ERANGE for steps not held (the
+ * ring keeps the last particle_ring steps since the lattice's particles were last set),
+ * LBDEM_ENOMEM, LBDEM_EDEVICE. */
+int lbdem_particle_signal(lbdem_set *set, int32_t lattice, int64_t first, int64_t n, const int32_t *layer,
+                          int32_t n_layers, int32_t component, double *x);
+
+/* Biot's wave velocities of a saturated poroelastic packing (Sec. "Biot's equations of wave
+ * velocities in saturated poroelastic media", Eqs. vp, vs), for comparison with the
+ * simulated ones: from the dry packing's bulk and shear moduli k_dry, g_dry (not given by
+ * the paper, an input), the porosity phi (0 < phi < 1), the bulk moduli of the particles
+ * and the fluid k_p, k_f (k_p = E_p / (3 (1 - 2 nu_p)), k_f = rho_f c_s^2) and their
+ * densities, with the tortuosity alpha = 1 - r (1 - 1/phi) (r = 0.5 for spheres).  The
+ * denominator of Eq. (vp) is read as 2 (rho11 rho22 - rho12^2).  out[3] (host): fast P-wave,
+ * slow P-wave and S-wave speeds.  Host computation.  Errors: LBDEM_EINVAL for a null
+ * output or inputs that give no real speeds. */
+int lbdem_biot_velocities(double k_dry, double g_dry, double phi, double k_p, double k_f, double rho_p,
+                          double rho_f, double r, double *out);
 
 /* Device workspace bytes for lbdem_st_dft and lbdem_wave_fit with these sizes. */
 int lbdem_dft_workspace_size(int64_t nt, int32_t nz, int32_t nw, int32_t nk, size_t *bytes);

@@ -333,6 +333,26 @@ __global__ __launch_bounds__(256) void k_probe_signal(const double *__restrict__
     x[i] = cnt > 0.0 ? (quantity == 0 ? rec[1] / cnt : rec[2] / rec[3]) : 0.0;
 }
 
+// x[i][l] = average of velocity component `component` over the particles of layer l after
+// step first + i, from the particle-velocity ring; the members of layer l are
+// members[start[l] .. start[l + 1]) in index order (a fixed summation order)
+__global__ __launch_bounds__(256) void k_particle_signal(const double *__restrict__ ring, int ring_len, int ptot,
+                                                         int p_off, long long first, long long n,
+                                                         const int *__restrict__ start,
+                                                         const int *__restrict__ members, int n_layers,
+                                                         int component, double *__restrict__ x)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * n_layers) return;
+    const long long st = i / n_layers;
+    const int l = (int)(i - st * n_layers);
+    const double *rec = ring + ((first + st) % ring_len) * (long long)ptot * 3;
+    const int a = start[l], b = start[l + 1];
+    double sum = 0.0;
+    for (int k = a; k < b; ++k) sum += rec[(long long)(p_off + members[k]) * 3 + component];
+    x[i] = b > a ? sum / (double)(b - a) : 0.0;
+}
+
 inline long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -390,6 +410,17 @@ hipError_t launch_wave_fit(const double *x, long long nt, int nz, const double *
     hipLaunchKernelGGL(k_harmonic, dim3(nz, p.nchunk), dim3(64), 0, st, x, nt, nz, t0, omega, p.chunk, ph);
     hipLaunchKernelGGL(k_wave_fit, dim3(1), dim3(1024), 0, st, (const double2 *)ph, p.nchunk, nt, zpos, nz, omega, la,
                        out);
+    return hipGetLastError();
+}
+
+hipError_t launch_particle_signal(const double *ring, int ring_len, int ptot, int p_off, long long first,
+                                  long long n, const int *start, const int *members, int n_layers, int component,
+                                  double *x, hipStream_t st)
+{
+    const long long tot = n * n_layers;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_particle_signal, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, ring, ring_len, ptot,
+                       p_off, first, n, start, members, n_layers, component, x);
     return hipGetLastError();
 }
 

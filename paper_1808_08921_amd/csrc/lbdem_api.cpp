@@ -78,6 +78,7 @@ struct Geometry {
     int fluid_off = 0;
     long long rt_words = 0;
     int ring_len = 1;
+    int pv_ring = 0;
     int chg_cap = 0;
     int lcap = 1;
     int bcap = 1;
@@ -97,6 +98,8 @@ int validate(int32_t n, const lbdem_params *lat, const lbdem_config *cfg)
     if (cfg->node_lists < -1 || cfg->node_lists > 2) return fail(LBDEM_EINVAL, "node_lists must be -1, 0, 1 or 2");
     if (cfg->list_margin < 0 || cfg->list_margin > 8) return fail(LBDEM_EINVAL, "list_margin must be 0..8");
     if (cfg->fluid_off != 0 && cfg->fluid_off != 1) return fail(LBDEM_EINVAL, "fluid_off must be 0 or 1");
+    if (cfg->particle_ring < 0 || cfg->particle_ring > (1 << 24))
+        return fail(LBDEM_EINVAL, "particle_ring must be 0..2^24");
     for (int m = 0; m < n; ++m) {
         const lbdem_params &p = lat[m];
         if (cfg->node_lists == 2 && (long long)p.ny * ((p.nx + 31) / 32) > kMaxPlaneWords)
@@ -182,6 +185,7 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
     for (int m = 1; m < n; ++m) nzmin = std::min(nzmin, lat[m].nz);
     G.nzt = G.listmode ? 1 : std::max(1, std::min(nzt, nzmin));
     G.ring_len = cfg->probe_ring;
+    G.pv_ring = cfg->particle_ring;
     long long cells = 0, ring = 0, wave = 0, pz = 0;
     int tiles = 0, pt = 0, npr = 0;
     for (int m = 0; m < n; ++m) {
@@ -325,6 +329,8 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.fixed = c.take<int>(P);
     s.pmem = c.take<int>(P);
     s.ppart = c.take<double>((size_t)P * kChunks * kLinkComp);
+    s.pv_ring = G.pv_ring;
+    s.pvring = c.take<double>(G.pv_ring > 0 ? (size_t)G.pv_ring * P * 3 : 1);
     s.zcache = c.take<double>((size_t)P * kChunks * kZComp);
     s.nearl = c.take<int>((size_t)P * kNearCap);
     s.nnear = c.take<int>(P);
@@ -624,6 +630,7 @@ int lbdem_default_config(lbdem_config *cfg)
     cfg->fluid_off = 0;
     cfg->z_per_thread = 0;
     cfg->graph_steps = 8;
+    cfg->particle_ring = 0;
     return LBDEM_OK;
 }
 
@@ -872,6 +879,7 @@ int lbdem_particles_set(lbdem_set *S, int32_t lattice, int32_t n, const double *
     long long t = 0;
     HIPCHK(hipMemcpy(&t, S->ds.tstep, sizeof(long long), hipMemcpyDeviceToHost));
     const int par = (int)(t & 1);
+    M.pv_from = t;
     DevSet &s = S->ds;
     hipStream_t st = S->stream;
     const size_t o3 = 3 * (size_t)M.p_off, o1 = M.p_off;
@@ -984,6 +992,7 @@ int lbdem_status(lbdem_set *S, uint32_t *bits, int clear)
     if (clear) HIPCHK(hipMemset(S->ds.flags, 0, sizeof(unsigned)));
     const unsigned errs = LBDEM_STATUS_NEAR_OVERFLOW | LBDEM_STATUS_HISTORY_OVERFLOW | LBDEM_STATUS_TOO_FAST |
                           LBDEM_STATUS_SHELL_OVERFLOW | LBDEM_STATUS_LINK_OVERFLOW | LBDEM_STATUS_LIST_MISS;
+    if (f & LBDEM_STATUS_NONFINITE) return fail(LBDEM_ENUMERIC, "device status 0x%x: non-finite fluid density", f);
     if (f & errs) return fail(LBDEM_ECAPACITY, "device status 0x%x", f);
     return LBDEM_OK;
 }
@@ -1024,6 +1033,97 @@ int lbdem_probe_signal(lbdem_set *S, int32_t lattice, int64_t first, int64_t n, 
                     (long long)(first + n), (long long)t, S->G.ring_len);
     if (M.n_probe == 0 || n == 0) return LBDEM_OK;
     HIPCHK(launch_probe_signal(S->ds.ring + M.ring_off, S->G.ring_len, M.n_probe, first, n, quantity, x, S->stream));
+    return LBDEM_OK;
+}
+
+int lbdem_particle_signal(lbdem_set *S, int32_t lattice, int64_t first, int64_t n, const int32_t *layer,
+                          int32_t n_layers, int32_t component, double *x)
+{
+    int rc = check_lattice(S, lattice);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && !x)) return fail(LBDEM_EINVAL, "bad output");
+    if (component < 0 || component > 2) return fail(LBDEM_EINVAL, "component must be 0, 1 or 2");
+    if (n_layers < 1 || n_layers > (1 << 20)) return fail(LBDEM_EINVAL, "n_layers must be 1..2^20");
+    const MemberDev &M = S->G.mem[lattice];
+    if (M.np > 0 && !layer) return fail(LBDEM_EINVAL, "null layer array");
+    int64_t t = 0;
+    rc = lbdem_time(S, &t);
+    if (rc) return rc;
+    const int ring = S->G.pv_ring;
+    if (ring < 1) return fail(LBDEM_ERANGE, "the set keeps no particle velocities (particle_ring 0)");
+    if (first < 0 || first + n > t || first < t - ring || first < M.pv_from)
+        return fail(LBDEM_ERANGE, "steps [%lld, %lld) not held (t = %lld, ring %d, particles set at %lld)",
+                    (long long)first, (long long)(first + n), (long long)t, ring, M.pv_from);
+    // the members of each layer in index order: members[start[l] .. start[l + 1])
+    std::vector<int> start(n_layers + 1, 0);
+    for (int q = 0; q < M.np; ++q) {
+        const int l = layer[q];
+        if (l < -1 || l >= n_layers)
+            return fail(LBDEM_EINVAL, "particle %d: layer %d outside -1..%d", q, l, n_layers - 1);
+        if (l >= 0) ++start[l + 1];
+    }
+    for (int l = 0; l < n_layers; ++l) start[l + 1] += start[l];
+    std::vector<int> members(std::max(start[n_layers], 1), 0);
+    {
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        for (int q = 0; q < M.np; ++q)
+            if (layer[q] >= 0) members[fill[layer[q]]++] = q;
+    }
+    if (n == 0) return LBDEM_OK;
+    int *dev = nullptr;
+    const size_t words = start.size() + members.size();
+    if (hipMalloc((void **)&dev, words * sizeof(int)) != hipSuccess)
+        return fail(LBDEM_ENOMEM, "no device memory for %zu layer words", words);
+    hipError_t e = hipMemcpyAsync(dev, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, S->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dev + start.size(), members.data(), members.size() * sizeof(int), hipMemcpyHostToDevice,
+                           S->stream);
+    if (e == hipSuccess)
+        e = launch_particle_signal(S->ds.pvring, ring, S->G.ptot, M.p_off, first, n, dev, dev + start.size(),
+                                   n_layers, component, x, S->stream);
+    // the host arrays and the device copy live until the copies and the kernel are done
+    if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+    const hipError_t ef = hipFree(dev);
+    if (e != hipSuccess) return fail(LBDEM_EDEVICE, "particle signal: %s", hipGetErrorString(e));
+    if (ef != hipSuccess) return fail(LBDEM_EDEVICE, "particle signal: %s", hipGetErrorString(ef));
+    return LBDEM_OK;
+}
+
+int lbdem_biot_velocities(double k_dry, double g_dry, double phi, double k_p, double k_f, double rho_p,
+                          double rho_f, double r, double *out)
+{
+    if (!out) return fail(LBDEM_EINVAL, "null output");
+    if (!(phi > 0.0 && phi < 1.0) || !(k_p > 0.0) || !(k_f > 0.0) || !(rho_p > 0.0) || !(rho_f > 0.0) ||
+        !(k_dry >= 0.0) || !(g_dry >= 0.0) || !std::isfinite(k_dry + g_dry + k_p + k_f + rho_p + rho_f + r))
+        return fail(LBDEM_EINVAL, "moduli and densities must be positive (k_dry, g_dry >= 0), 0 < phi < 1");
+    // Biot's elastic coefficients of the saturated packing, with c = 1 - phi - k_dry / k_p
+    // and d = c + phi k_p / k_f: P = ((1 - phi) c k_p + phi k_p k_dry / k_f) / d + 4/3 g_dry,
+    // Q = phi c k_p / d, R = phi^2 k_p / d
+    const double c = 1.0 - phi - k_dry / k_p;
+    const double d = c + phi * k_p / k_f;
+    const double P = ((1.0 - phi) * c * k_p + phi * k_p * k_dry / k_f) / d + 4.0 / 3.0 * g_dry;
+    const double Q = phi * c * k_p / d;
+    const double R = phi * phi * k_p / d;
+    // inertial coupling through the tortuosity alpha = 1 - r (1 - 1 / phi)
+    const double alpha = 1.0 - r * (1.0 - 1.0 / phi);
+    const double r12 = (1.0 - alpha) * phi * rho_f;
+    const double r11 = (1.0 - phi) * rho_p - r12;
+    const double r22 = phi * rho_f - r12;
+    const double det = r11 * r22 - r12 * r12;
+    // Eq. (vp): v^2 are the roots of det v^4 - (P r22 + R r11 - 2 Q r12) v^2 + (P R - Q^2) = 0
+    const double bsum = P * r22 + R * r11 - 2.0 * Q * r12;
+    const double disc = bsum * bsum - 4.0 * det * (P * R - Q * Q);
+    if (!(det > 0.0) || !(disc >= 0.0) || !(bsum > 0.0))
+        return fail(LBDEM_EINVAL, "these inputs give no real wave speeds");
+    const double v2f = (bsum + std::sqrt(disc)) / (2.0 * det);
+    // the smaller root without cancellation: the product of the roots over the larger one
+    const double v2s = (P * R - Q * Q) / det / v2f;
+    // Eq. (vs): the shear wave moves the solid with the fluid mass the coupling drags along
+    const double v2t = g_dry / (r11 - r12 * r12 / r22);
+    if (!(v2s >= 0.0) || !(v2t >= 0.0)) return fail(LBDEM_EINVAL, "these inputs give no real wave speeds");
+    out[0] = std::sqrt(v2f);
+    out[1] = std::sqrt(v2s);
+    out[2] = std::sqrt(v2t);
     return LBDEM_OK;
 }
 
@@ -1239,6 +1339,7 @@ uint64_t set_digest(const lbdem_set *S)
     const lbdem_config &c = S->cfg;
     fnv(h, &c.precision, 4); fnv(h, &c.probe_ring, 4); fnv(h, &c.tile_x, 4); fnv(h, &c.z_per_thread, 4);
     fnv(h, &c.node_lists, 4); fnv(h, &c.list_margin, 4); fnv(h, &c.fluid_off, 4);
+    fnv(h, &c.particle_ring, 4);
     const uint64_t ws = S->ws_bytes;
     fnv(h, &ws, 8);
     return h;

@@ -68,6 +68,7 @@ struct MemberDev {
     double E, nu, mu, rho_p;
     int nw;                   // 32-node words per x row (compact storage)
     long long rt_off;         // offset of this lattice's row tables (compact storage)
+    long long pv_from;        // first step whose particle velocities the ring holds for this lattice
 };
 
 // Everything a kernel needs, passed by value.
@@ -131,6 +132,8 @@ struct DevSet {
     float *pf[2];             // FP32 wall state of the fluid kernel per particle (12 floats): X(t) and the
                               // velocities V, Omega of step t, at the parity of t
     int *fixed, *pmem;
+    double *pvring;           // particle velocities after each step [pv_ring][ptot][3] (0 steps: none)
+    int pv_ring;
     double *ppart;            // link-pass partials per (particle, chunk) [ptot*kChunks*kLinkComp]
     double *zcache;           // link-set sums per (particle, chunk), rebuilt with its entries [ptot*kChunks*kZComp]
     int *nearl, *nnear;       // [ptot*kNearCap], [ptot]
@@ -238,6 +241,9 @@ hipError_t launch_wave_fit(const double *x, long long nt, int nz, const double *
 // current device (looked up once per device)
 constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
 hipError_t noalloc_scratch(void **ptr);
+hipError_t launch_particle_signal(const double *ring, int ring_len, int ptot, int p_off, long long first,
+                                  long long n, const int *start, const int *members, int n_layers, int component,
+                                  double *x, hipStream_t st);
 hipError_t launch_probe_signal(const double *ring, int ring_len, int nprobe, long long first, long long n,
                                int quantity, double *x, hipStream_t st);
 

@@ -1074,6 +1074,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                 C drho, jx, jy, jz;
                 moments<C>(f, drho, jx, jy, jz);
                 const C rho = (C)rho_fd + drho;
+                // watchdog: a fluid node whose density is not a positive finite number
+                // (status 0x400; NaN fails the first comparison)
+                if (fl && !(rho > C(0) && rho < C(1e30))) atomicOr(s.flags, 0x400u);
                 if (fl) {
                     pr0 = 1.0;
                     pr1 = (double)drho;
@@ -1737,6 +1740,10 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
         for (int a = 0; a < 3; ++a) {
             s.Fh[3 * p + a] = (lp[a] - zx[a]) + Phv[a];
             s.Th[3 * p + a] = (lp[3 + a] - zx[3 + a]) + Lhv[a];
+        }
+        if (s.pv_ring > 0) {
+            double *pv = s.pvring + ((t % s.pv_ring) * (long long)s.ptot + p) * 3;
+            pv[0] = v[0]; pv[1] = v[1]; pv[2] = v[2];
         }
         for (int a = 0; a < 3; ++a) {
             Vn[3 * p + a] = v[a];

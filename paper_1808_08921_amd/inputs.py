@@ -85,6 +85,14 @@ def wave_fcc_case(seed: int = 0, ncx: int = 4, ncy: int = 4, ncz: int = 16, a: f
     return params, pk
 
 
+def fcc_layers(x, a: float = 24.0, z_shift: float | None = None):
+    """Layer index of each sphere of an FCC packing made by fcc_packing: its planes normal to
+    z are a / 2 apart, starting at z_shift (default a / 4)."""
+    if z_shift is None:
+        z_shift = a / 4.0
+    return np.rint((np.asarray(x)[:, 2] - z_shift) / (0.5 * a)).astype(np.int32)
+
+
 def settling_case(n: int = 32, radius: float = 6.0, density_ratio: float = 2.0, g: float = 1e-5,
                   tau: float = 0.8, centre=None):
     """Single sphere settling in a closed box with half-way walls on every face.  The

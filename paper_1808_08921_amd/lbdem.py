@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbdem.so")
 
-OK, EINVAL, EDEVICE, ECAPACITY, ENOMEM, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EDEVICE, ECAPACITY, ENOMEM, ESTATE, ERANGE, ENUMERIC = 0, -1, -2, -3, -4, -5, -6, -7
 PERIODIC, WALL, PRESSURE = 0, 1, 2
 WAVE_NONE, WAVE_SINE, WAVE_COSINE, WAVE_STEP = 0, 1, 2, 3
 FP64, FP32, FP16DEV, BF16DEV = 0, 1, 2, 3
@@ -28,6 +28,10 @@ STATUS_CHANGE_OVERFLOW = 0x4
 STATUS_HISTORY_OVERFLOW = 0x8
 STATUS_TOO_FAST = 0x10
 STATUS_SHELL_OVERFLOW = 0x40
+STATUS_LINK_OVERFLOW = 0x80
+STATUS_LIST_MISS = 0x100
+STATUS_LIST_PARKED = 0x200
+STATUS_NONFINITE = 0x400
 
 
 class LbdemError(RuntimeError):
@@ -55,7 +59,7 @@ class Params(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("probe_ring", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("z_per_thread", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("node_lists", ctypes.c_int32),
-                ("list_margin", ctypes.c_int32), ("fluid_off", ctypes.c_int32)]
+                ("list_margin", ctypes.c_int32), ("fluid_off", ctypes.c_int32), ("particle_ring", ctypes.c_int32)]
 
 
 _lib = None
@@ -100,6 +104,8 @@ def lib():
         L.lbdem_adj_destroy.argtypes = [P]
         D = ctypes.c_double
         L.lbdem_probe_signal.argtypes = [P, I32, I64, I64, I32, VP]
+        L.lbdem_particle_signal.argtypes = [P, I32, I64, I64, ctypes.POINTER(I32), I32, I32, VP]
+        L.lbdem_biot_velocities.argtypes = [D, D, D, D, D, D, D, D, dp]
         L.lbdem_dft_workspace_size.argtypes = [I64, I32, I32, I32, ctypes.POINTER(SZ)]
         L.lbdem_st_dft.argtypes = [VP, I64, I32, VP, D, D, D, I32, D, D, I32, VP, VP, VP, SZ, VP]
         L.lbdem_wave_fit.argtypes = [VP, I64, I32, VP, D, D, VP, VP, SZ, VP]
@@ -111,7 +117,8 @@ def lib():
                      "lbdem_state_save", "lbdem_state_load", "lbdem_timing_enable", "lbdem_timing_read",
                      "lbdem_tile_info", "lbdem_adj_workspace_size", "lbdem_adj_create", "lbdem_adj_forward",
                      "lbdem_adj_backward", "lbdem_adj_destroy", "lbdem_probe_signal", "lbdem_dft_workspace_size",
-                     "lbdem_st_dft", "lbdem_wave_fit", "lbdem_wave_fit_noalloc"):
+                     "lbdem_st_dft", "lbdem_wave_fit", "lbdem_wave_fit_noalloc", "lbdem_particle_signal",
+                     "lbdem_biot_velocities"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -159,7 +166,7 @@ class LatticeSet:
     """
 
     def __init__(self, lattices, precision="fp32", probe_ring=4096, tile_x=0, z_per_thread=0, graph_steps=8,
-                 device="cuda", node_lists=None, list_margin=None, fluid_off=False):
+                 device="cuda", node_lists=None, list_margin=None, fluid_off=False, particle_ring=0):
         import torch
 
         self._torch = torch
@@ -182,6 +189,8 @@ class LatticeSet:
             cfg.list_margin = int(list_margin)
         # hydrodynamics switched off (the dry granular chain of Sec. 3.2)
         cfg.fluid_off = 1 if fluid_off else 0
+        # steps of particle velocities kept for particle_signal
+        cfg.particle_ring = int(particle_ring)
         nbytes = ctypes.c_size_t()
         _check(L.lbdem_workspace_size(n, arr, ctypes.byref(cfg), ctypes.byref(nbytes)))
         self.workspace_bytes = nbytes.value
@@ -246,9 +255,14 @@ class LatticeSet:
     def status(self, clear=False):
         b = ctypes.c_uint32()
         rc = lib().lbdem_status(self._h, ctypes.byref(b), 1 if clear else 0)
-        if rc not in (OK, ECAPACITY):
+        if rc not in (OK, ECAPACITY, ENUMERIC):
             _check(rc)
         return b.value
+
+    def check(self):
+        """Raise LbdemError when a device error bit is set (ENUMERIC for the density watchdog)."""
+        b = ctypes.c_uint32()
+        _check(lib().lbdem_status(self._h, ctypes.byref(b), 0))
 
     def probes(self, lattice, first=0, n=None):
         if n is None:
@@ -267,6 +281,22 @@ class LatticeSet:
         q = {"density": 0, "momentum": 1}[quantity]
         x = torch.zeros((n, self.n_probe[lattice]), dtype=torch.float64, device=self.device)
         _check(lib().lbdem_probe_signal(self._h, lattice, int(first), int(n), q, ctypes.c_void_p(x.data_ptr())))
+        return x
+
+    def particle_signal(self, lattice, layer, n_layers, first=0, n=None, component=2):
+        """Layer-averaged particle velocities for steps [first, first + n) as a device tensor
+        [n][n_layers] (float64), gathered from the particle-velocity ring: ``layer[q]`` is the
+        layer of particle q (-1: left out), ``component`` the velocity component (0, 1, 2)."""
+        torch = self._torch
+        if n is None:
+            n = self.t - first
+        lay = np.ascontiguousarray(np.asarray(layer, dtype=np.int32))
+        if lay.shape != (self.n_particles[lattice],):
+            raise ValueError(f"need one layer per particle ({self.n_particles[lattice]}), got {lay.shape}")
+        x = torch.zeros((n, n_layers), dtype=torch.float64, device=self.device)
+        _check(lib().lbdem_particle_signal(self._h, lattice, int(first), int(n),
+                                           lay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_layers),
+                                           int(component), ctypes.c_void_p(x.data_ptr())))
         return x
 
     def populations(self, lattice):
@@ -376,6 +406,14 @@ class AdjointWindow:
             self.close()
         except Exception:
             pass
+
+
+def biot_velocities(k_dry, g_dry, phi, k_p, k_f, rho_p, rho_f, r=0.5):
+    """Biot's fast and slow P-wave and S-wave speeds of a saturated packing (Eqs. vp, vs)."""
+    out = np.zeros(3)
+    _check(lib().lbdem_biot_velocities(float(k_dry), float(g_dry), float(phi), float(k_p), float(k_f),
+                                       float(rho_p), float(rho_f), float(r), _dp(out)))
+    return float(out[0]), float(out[1]), float(out[2])
 
 
 def _probe_function():

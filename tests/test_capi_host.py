@@ -115,3 +115,33 @@ def test_dft_workspace_size_and_validation(lb):
     assert L.lbdem_st_dft(None, 10, 4, None, 0.0, 0.0, 0.1, 4, 0.0, 0.1, 4, None, None, None, 0, None) == lb.EINVAL
     assert L.lbdem_wave_fit(None, 10, 4, None, 0.0, 0.3, None, None, 0, None) == lb.EINVAL
 
+
+
+_BIOT = [
+    (0.05, 0.04, 0.266, 10.37 / 1.8, 1.0 / 3.0, 2.466, 1.0, 0.5),
+    (0.5, 0.35, 0.266, 10.37 / 1.8, 1.0 / 3.0, 2.466, 1.0, 0.5),
+    (2.0, 1.5, 0.40, 12.0, 2.25, 2.65, 1.0, 0.5),
+    (2.0, 1.5, 0.40, 12.0, 2.25, 2.65, 1.0, 0.0),            # no inertial coupling
+]
+
+
+@pytest.mark.parametrize("case", _BIOT)
+def test_biot_velocities_match_the_oracle(lb, case):
+    """Eqs. (vp), (vs) in the library (a host computation) against the oracle's closed form."""
+    from oracle import analysis
+
+    got = lb.biot_velocities(*case)
+    want = analysis.biot_velocities(*case)
+    for g, w in zip(got, want):
+        assert g == pytest.approx(w, rel=1e-12)
+
+
+def test_biot_velocities_reject_bad_inputs(lb):
+    L = lb.lib()
+    out = (ctypes.c_double * 3)()
+    assert L.lbdem_biot_velocities(0.5, 0.35, 0.3, 5.0, 1.0 / 3.0, 2.5, 1.0, 0.5, None) == lb.EINVAL
+    for bad in [(0.5, 0.35, 0.0, 5.0, 0.3, 2.5, 1.0, 0.5), (0.5, 0.35, 1.0, 5.0, 0.3, 2.5, 1.0, 0.5),
+                (0.5, 0.35, 0.3, -5.0, 0.3, 2.5, 1.0, 0.5), (-0.5, 0.35, 0.3, 5.0, 0.3, 2.5, 1.0, 0.5),
+                (0.5, 0.35, 0.3, 5.0, 0.3, 2.5, float("nan"), 0.5)]:
+        assert L.lbdem_biot_velocities(*bad, out) == lb.EINVAL, bad
+    assert L.lbdem_particle_signal(None, 0, 0, 1, None, 1, 2, None) == lb.EINVAL

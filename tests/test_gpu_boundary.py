@@ -168,3 +168,90 @@ def test_projection_tie_between_spheres_on_gpu(swap):
         assert np.array_equal(gs.owner(0), want)
     for i, j, k in [(5, 5, 5), (5, 4, 5), (5, 6, 5), (5, 5, 4), (5, 5, 6)]:
         assert want[k, j, i] == 0
+
+
+def test_particle_signal_matches_oracle():
+    """Layer-averaged particle velocities (lbdem_particle_signal) against the oracle's
+    particle velocities after each step, averaged per FCC layer in index order: the moving
+    2 x 2 x 2 packing, 30 FP64 steps, a ring of 16 steps, every component; then the ring's
+    limits (older steps, steps before the particles were set, no ring)."""
+    from paper_1808_08921_amd.lbdem import LbdemError
+
+    params, pk = _moving_fcc()
+    layer = inputs.fcc_layers(pk["x"], a=24.0)
+    assert sorted(set(layer.tolist())) == [0, 1, 2, 3]
+    layer[pk["fixed"] == 1] = -1                 # the held end layers are left out
+    steps, ring = 30, 16
+    s = oracle.Sim(params["nx"], params["ny"], params["nz"], tau=params["tau"], rho_f=params["rho_f"],
+                   bc=params["bc"], wave=params["wave"], amp=params["amp"], omega=params["omega"],
+                   t_n=params["t_n"], E=params["E"], nu=params["nu"], mu=params["mu"], rho_p=params["rho_p"],
+                   probe_z=params["probe_z"])
+    s.set_particles(pk["x"], pk["radius"], v=pk["v"], w=pk["w"], fixed=pk["fixed"])
+    vs = []
+    for _ in range(steps):
+        s.step(1)
+        vs.append(s.particles()["v"])
+    s.close()
+    vs = np.array(vs)                            # [step][particle][3]
+    with _set(params, "fp64", node_lists=2, graph_steps=4, particle_ring=ring) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], v=pk["v"], w=pk["w"], fixed=pk["fixed"])
+        gs.step(steps)
+        for comp in range(3):
+            got = gs.particle_signal(0, layer, 4, first=steps - ring, n=ring, component=comp).cpu().numpy()
+            want = np.zeros((ring, 4))
+            for l in (1, 2):
+                want[:, l] = vs[steps - ring:, layer == l, comp].mean(axis=1)
+            assert np.all(got[:, [0, 3]] == 0.0)        # layers without members give 0
+            scale = np.abs(want).max()
+            assert scale > 1e-4
+            assert np.abs(got - want).max() <= 1e-10 * scale, comp
+        # the last step's record is the velocity the particles hold now
+        v_now = gs.particles_get(0)["v"]
+        last = gs.particle_signal(0, layer, 4, first=steps - 1, n=1, component=2).cpu().numpy()
+        assert last[0, 1] == pytest.approx(v_now[layer == 1, 2].mean(), rel=1e-14, abs=1e-18)
+        for first, n in [(steps - ring - 1, 4), (steps - 2, 4), (-1, 1)]:
+            with pytest.raises(LbdemError):
+                gs.particle_signal(0, layer, 4, first=first, n=n)
+        with pytest.raises(LbdemError):
+            gs.particle_signal(0, np.full(len(layer), 4, np.int32), 4, first=steps - 1, n=1)
+        # particles set anew: the ring restarts at that step
+        gs.particles_set(0, pk["x"], pk["radius"], v=pk["v"], fixed=pk["fixed"])
+        gs.step(3)
+        assert gs.particle_signal(0, layer, 4, first=steps, n=3).shape == (3, 4)
+        with pytest.raises(LbdemError):
+            gs.particle_signal(0, layer, 4, first=steps - 1, n=2)
+    with _set(params, "fp32", graph_steps=4) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], fixed=pk["fixed"])
+        gs.step(2)
+        with pytest.raises(LbdemError):
+            gs.particle_signal(0, layer, 4, first=0, n=1)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "bf16"])
+@pytest.mark.parametrize("bad", ["nan", "negative"])
+def test_density_watchdog(precision, bad):
+    """A population state with a bad spot (one NaN population, or a block of nodes whose
+    density is -1, which streaming keeps negative inside the block) raises the watchdog bit
+    after the next step and lbdem_status returns LBDEM_ENUMERIC; the same lattice without
+    the bad spot stays clean."""
+    from paper_1808_08921_amd.lbdem import ENUMERIC, STATUS_NONFINITE, LbdemError
+
+    params = dict(nx=16, ny=12, nz=10, tau=0.8, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), probe_z=(3,))
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    f = np.broadcast_to(w[:, None, None, None], (19, 10, 12, 16)).copy()
+    with _set(params, precision, graph_steps=2) as gs:
+        gs.set_populations(0, f)
+        gs.step(2)
+        assert gs.status() == 0
+        gs.check()
+        g = gs.populations(0)
+        if bad == "nan":
+            g[4, 5, 6, 7] = np.nan
+        else:
+            g[:, 3:8, 4:9, 5:10] = -w[:, None, None, None]     # density -1 inside the block
+        gs.set_populations(0, g)
+        gs.step(1)
+        assert gs.status() & STATUS_NONFINITE
+        with pytest.raises(LbdemError) as e:
+            gs.check()
+        assert f"error {ENUMERIC}" in str(e.value)
