@@ -103,6 +103,12 @@ typedef struct lbdem_params {
     double max_radius;       /* largest particle radius this lattice will hold (sizes per-particle tables) */
     int32_t tile_x;          /* fluid-kernel tile x extent for this lattice: 8, 16, 32, 64, or 0 = the
                                 set's lbdem_config.tile_x (chosen per lattice by an autotuner) */
+    int32_t rest_free;       /* 0 (default): the link force of Eq. (fFS) as printed, on the full
+                                populations; 1: without the part of the rest state f_d = w_d rho_f.
+                                That part sums to zero over the links of a particle that touches no
+                                other; where particles touch, the links their contact hides leave a
+                                net push of the rest pressure rho_f c_s^2 over a lattice-sized patch,
+                                which option 1 removes (the two agree for separated particles) */
 } lbdem_params;
 
 /* Settings shared by all lattices of a set. */
@@ -178,12 +184,12 @@ int lbdem_set_stream(lbdem_set *set, void *hip_stream);
  * particle never moves and has V = Omega = 0).  v, w, fg and fixed may be NULL (zeros).
  * Populations are not modified.  Errors: LBDEM_EINVAL when n exceeds max_particles, a
  * radius is not positive or exceeds max_radius, a centre lies outside a non-periodic extent, or a periodic
- * axis is shorter than 2 R + 4 for a mobile particle, or not longer than 2 R for a fixed
- * one.  (A node lies inside at most one image of a sphere.  The torque arm and wall
- * velocity of a node's links are taken from the node's nearest image, exact while a node
- * borders one image only; in an axis shorter than 2 R + 4 a node midway between two images
- * borders both, which a fixed sphere tolerates: its wall velocity is zero and only the
- * torque it reports is affected.) */
+ * axis is not longer than 2 R + 1.5.  (A node then lies inside at most one image of a
+ * sphere, and the midpoint of each link lies less than half a period from the centre of
+ * the image its source is in.  On a lattice with a periodic axis shorter than
+ * 2 max_radius + 4 a fluid node can border two images of one sphere: its links are grouped
+ * per (particle, image), each group with its own torque arm and wall velocity, so such a
+ * node can hold at most four groups.) */
 int lbdem_particles_set(lbdem_set *set, int32_t lattice, int32_t n, const double *x, const double *v,
                         const double *w, const double *radius, const double *fg, const uint8_t *fixed);
 
@@ -307,8 +313,9 @@ int lbdem_adj_workspace_size(lbdem_set *set, int32_t lattice, int64_t nsteps, in
 
 /* Bind a window to lattice `lattice` of `set` (synchronises the set's stream).  workspace:
  * caller-owned device memory of at least lbdem_adj_workspace_size bytes, 256-byte aligned,
- * kept alive until lbdem_adj_destroy.  Errors: LBDEM_EINVAL, LBDEM_ENOMEM (workspace too
- * small), LBDEM_EDEVICE. */
+ * kept alive until lbdem_adj_destroy.  Errors: LBDEM_EINVAL (also for a lattice with a
+ * periodic axis shorter than 2 max_radius + 4, whose per-image link groups the window does
+ * not model), LBDEM_ENOMEM (workspace too small), LBDEM_EDEVICE. */
 int lbdem_adj_create(lbdem_set *set, int32_t lattice, int64_t nsteps, int32_t ckpt_every, void *workspace,
                      size_t workspace_bytes, lbdem_adj **out);
 

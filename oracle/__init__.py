@@ -69,6 +69,7 @@ def lib():
         L.orc_rho_in_value.argtypes = [I, D, D, D, L64, L64]
         L.orc_set_frozen.argtypes = [P, I]
         L.orc_set_fluid_off.argtypes = [P, I]
+        L.orc_set_rest_free.argtypes = [P, I]
         L.orc_set_velocities.argtypes = [P, dp, dp]
         L.orc_adjoint.restype = I
         L.orc_adjoint.argtypes = [P, L64, D, D, dp, dp, dp, dp, dp]
@@ -148,7 +149,7 @@ class Sim:
     """One lattice with its particles, stepped by the oracle."""
 
     def __init__(self, nx, ny, nz, tau=1.0, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), wave=WAVE_NONE, amp=0.0,
-                 omega=0.0, t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=1.0, probe_z=()):
+                 omega=0.0, t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=1.0, probe_z=(), rest_free=False):
         self.shape = (nz, ny, nx)
         self.ncell = nx * ny * nz
         self.rho_f = rho_f
@@ -161,6 +162,8 @@ class Sim:
         if not self._h:
             raise ValueError("oracle: invalid lattice parameters")
         self.np = 0
+        if rest_free:
+            self.set_rest_free(True)
 
     def close(self):
         if self._h:
@@ -181,6 +184,11 @@ class Sim:
         """Hydrodynamics switched off (the dry granular chain of Sec. 3.2): steps move the
         particles under contacts and their own forces only."""
         lib().orc_set_fluid_off(self._h, 1 if off else 0)
+
+    def set_rest_free(self, on=True):
+        """Link forces of Eq. (fFS) without the rest state's part w_d rho_f (a reading for
+        touching particles; for separated ones the part sums to zero)."""
+        lib().orc_set_rest_free(self._h, 1 if on else 0)
 
     def set_velocities(self, v=None, w=None):
         v = None if v is None else _f64(v).reshape(self.np, 3)

@@ -184,6 +184,7 @@ typedef struct {
     long probe_cap;
     int frozen;     /* 1: particles keep X, V, Omega; no DEM and no re-projection */
     int fluid_off;  /* 1: hydrodynamics switched off (Sec. 3.2, dry granular chain): DEM only */
+    int rest_free;  /* 1: link forces without the rest state's part (see orc_set_rest_free) */
 } orc_sim;
 
 static int axis_n(const orc_sim *s, int a) { return a == 0 ? s->p.nx : (a == 1 ? s->p.ny : s->p.nz); }
@@ -410,6 +411,11 @@ static void stream(orc_sim *s)
                     double F[3] = {CX[d] * s->f[d * N + n] - CX[e] * fnew,
                                    CY[d] * s->f[d * N + n] - CY[e] * fnew,
                                    CZ[d] * s->f[d * N + n] - CZ[e] * fnew};
+                    if (s->rest_free) {
+                        /* without the rest state's part: f~_d and f_{d*} each less w_d rho_f */
+                        double rest = 2.0 * weight(d) * s->p.rho_f;
+                        F[0] -= CX[d] * rest; F[1] -= CY[d] * rest; F[2] -= CZ[d] * rest;
+                    }
                     double T[3];
                     cross(r, F, T);
                     for (int a = 0; a < 3; ++a) { s->Fl[3 * q + a] += F[a]; s->Tl[3 * q + a] += T[a]; }
@@ -537,7 +543,8 @@ static void link_pass(const orc_sim *s, double *F0, double *Z)
                     for (int a = 0; a < 3; ++a) r[a] = min_image(s, a, xb[a] - s->X[3 * q + a]);
                     cross(r, c, rc);
                     double av[6] = {c[0], c[1], c[2], rc[0], rc[1], rc[2]};
-                    double f2 = 2.0 * s->f[d * N + n];
+                    /* (rest_free: without the rest state's part w_d rho_f) */
+                    double f2 = 2.0 * (s->f[d * N + n] - (s->rest_free ? weight(d) * s->p.rho_f : 0.0));
                     double kz = 2.0 * weight(d) / CS2 * s->p.rho_f;
                     for (int a = 0; a < 6; ++a) {
                         F0[6 * q + a] += f2 * av[a];
@@ -851,6 +858,10 @@ void orc_zou_he(double *f, double rho, int outlet) { zou_he(f, rho, outlet); }
  * population to its single consumer. */
 void orc_set_frozen(void *h, int frozen) { ((orc_sim *)h)->frozen = frozen; }
 void orc_set_fluid_off(void *h, int off) { ((orc_sim *)h)->fluid_off = off; }
+
+/* rest_free = 1: the link force of Eq. (fFS) without the part of the rest state
+ * f_d = w_d rho_f (a reading for touching particles; identical for separated ones) */
+void orc_set_rest_free(void *h, int on) { ((orc_sim *)h)->rest_free = on; }
 
 void orc_set_velocities(void *h, const double *V, const double *W)
 {

@@ -130,6 +130,7 @@ int validate(int32_t n, const lbdem_params *lat, const lbdem_config *cfg)
                 if (p.probe_z[k2] == p.probe_z[k]) return fail(LBDEM_EINVAL, "lattice %d: duplicate probe plane", m);
         }
         if (p.tile_x != 0 && !is_pow2_tile(p.tile_x)) return fail(LBDEM_EINVAL, "lattice %d: tile_x must be 0, 8, 16, 32 or 64", m);
+        if (p.rest_free != 0 && p.rest_free != 1) return fail(LBDEM_EINVAL, "lattice %d: rest_free must be 0 or 1", m);
         if (p.max_particles < 0 || p.max_particles > kMaxLocal) return fail(LBDEM_EINVAL, "lattice %d: max_particles", m);
         if (p.max_particles > 0 && !(p.max_radius > 0.0 && p.max_radius < 1024.0))
             return fail(LBDEM_EINVAL, "lattice %d: max_radius must be positive when particles are allowed", m);
@@ -209,9 +210,12 @@ void build_geometry(int32_t n, const lbdem_params *lat, const lbdem_config *cfg,
         tiles += M.ntx * M.nty * M.ntz;
         for (int f = 0; f < 6; ++f) M.bc[f] = p.face_bc[f];
         const int dims[3] = {p.nx, p.ny, p.nz};
+        M.narrow = 0;
+        M.rest_free = p.rest_free ? 1 : 0;
         for (int a = 0; a < 3; ++a) {
             M.per[a] = p.face_bc[2 * a] == LBDEM_PERIODIC;
             M.box[a] = (double)dims[a];
+            if (M.per[a] && dims[a] < 2.0 * p.max_radius + 4.0) M.narrow = 1;
         }
         M.ncell = (long long)p.nx * p.ny * p.nz;
         M.cell_off = cells;
@@ -847,12 +851,11 @@ int lbdem_particles_set(lbdem_set *S, int32_t lattice, int32_t n, const double *
             double c = x[3 * q + a];
             if (!std::isfinite(c)) return fail(LBDEM_EINVAL, "particle %d: non-finite position", q);
             if (M.per[a]) {
-                // a node lies inside at most one image of a sphere; a moving sphere also
-                // needs its own images beyond the reach of its re-projection and links
-                const bool fixed_q = fixed && fixed[q];
-                if (fixed_q ? !(dims[a] > 2.0 * R) : dims[a] < 2.0 * R + 4.0)
-                    return fail(LBDEM_EINVAL, "particle %d: periodic axis %d shorter than %s", q, a,
-                                fixed_q ? "2R (fixed particle)" : "2R + 4");
+                // a node lies inside at most one image of a sphere, and the midpoint of a
+                // link into an image (at most R + 1/2 from its centre along an axis) lies
+                // less than half a period from that image's centre, which identifies it
+                if (!(dims[a] > 2.0 * R + 1.5))
+                    return fail(LBDEM_EINVAL, "particle %d: periodic axis %d not longer than 2R + 1.5", q, a);
                 c = std::fmod(c, (double)dims[a]);
                 if (c < 0.0) c += dims[a];
             } else if (c < 0.0 || c > dims[a] - 1) {
@@ -1334,7 +1337,7 @@ uint64_t set_digest(const lbdem_set *S)
         fnv(h, &p.wave, 4); fnv(h, &p.rho_amp, 8); fnv(h, &p.omega, 8); fnv(h, &p.t_n, 8); fnv(h, &p.young_E, 8);
         fnv(h, &p.poisson_nu, 8); fnv(h, &p.friction_mu, 8); fnv(h, &p.rho_p, 8); fnv(h, &p.n_probe, 4);
         fnv(h, p.probe_z, 4 * (size_t)std::max(0, std::min(p.n_probe, LBDEM_MAX_PROBES)));
-        fnv(h, &p.max_particles, 4); fnv(h, &p.max_radius, 8); fnv(h, &p.tile_x, 4);
+        fnv(h, &p.max_particles, 4); fnv(h, &p.max_radius, 8); fnv(h, &p.tile_x, 4); fnv(h, &p.rest_free, 4);
     }
     const lbdem_config &c = S->cfg;
     fnv(h, &c.precision, 4); fnv(h, &c.probe_ring, 4); fnv(h, &c.tile_x, 4); fnv(h, &c.z_per_thread, 4);
@@ -1553,6 +1556,8 @@ int lbdem_adj_create(lbdem_set *S, int32_t lattice, int64_t nsteps, int32_t ckpt
     const MemberDev &M = S->G.mem[lattice];
     const lbdem_params &p = S->params[lattice];
     if (M.ncell > (1LL << 31) / kQ) return fail(LBDEM_EINVAL, "lattice too large for the adjoint window");
+    if (M.narrow)
+        return fail(LBDEM_EINVAL, "the adjoint window needs periodic axes of at least 2 max_radius + 4");
     std::unique_ptr<lbdem_adj> J(new lbdem_adj());
     J->set = S;
     J->lattice = lattice;

@@ -69,6 +69,11 @@ struct MemberDev {
     int nw;                   // 32-node words per x row (compact storage)
     long long rt_off;         // offset of this lattice's row tables (compact storage)
     long long pv_from;        // first step whose particle velocities the ring holds for this lattice
+    // 1: a periodic axis shorter than 2 max_radius + 4, where a fluid node can have links
+    // into two images of one particle; its links are then grouped per (particle, image)
+    // and the arm of a group is taken from the midpoint of one of its links
+    int narrow;
+    int rest_free;            // 1: link forces without the rest state's part (lbdem_params.rest_free)
 };
 
 // Everything a kernel needs, passed by value.

@@ -134,6 +134,46 @@ __device__ __forceinline__ double mimg(double dx, int per, double n)
     return dx;
 }
 
+// Position of fluid node (i, j, k) relative to the image of a particle centre X that holds
+// the node's link group grp (directions e whose source x - c_e lies in that image): the
+// minimum image of x - X, or, on a narrow periodic lattice, where two images can border one
+// node, the minimum image of the first link's midpoint x - c_e / 2 (always less than half
+// a period from its own image's centre) plus c_e / 2.
+__device__ __forceinline__ void group_arm(const MemberDev *M, unsigned grp, int i, int j, int k, double X0, double X1,
+                                          double X2, double &r0, double &r1, double &r2)
+{
+    if (M->narrow) {
+        const int e = __ffs(grp) - 1;
+        const double h0 = 0.5 * (double)kCXd[e], h1 = 0.5 * (double)kCYd[e], h2 = 0.5 * (double)kCZd[e];
+        r0 = mimg(((double)i - h0) - X0, M->per[0], M->box[0]) + h0;
+        r1 = mimg(((double)j - h1) - X1, M->per[1], M->box[1]) + h1;
+        r2 = mimg(((double)k - h2) - X2, M->per[2], M->box[2]) + h2;
+    } else {
+        r0 = mimg((double)i - X0, M->per[0], M->box[0]);
+        r1 = mimg((double)j - X1, M->per[1], M->box[1]);
+        r2 = mimg((double)k - X2, M->per[2], M->box[2]);
+    }
+}
+
+// Image of particle centre X (per axis -1, 0 or +1 periods, packed 2 bits an axis) that
+// holds the source (si, sj, sk) of a link, given unwrapped (it may lie one node outside
+// the lattice); 0 on a lattice that is not narrow.
+__device__ __forceinline__ int source_image(const MemberDev *M, int si, int sj, int sk, const double *X)
+{
+    if (!M->narrow) return 0;
+    const int s3[3] = {si, sj, sk};
+    int code = 0;
+    for (int a = 0; a < 3; ++a) {
+        int n = 0;
+        if (M->per[a]) {
+            const double d = (double)s3[a] - X[a];
+            n = (d > 0.5 * M->box[a]) ? 1 : (d < -0.5 * M->box[a]) ? -1 : 0;
+        }
+        code |= (n + 1) << (2 * a);
+    }
+    return code;
+}
+
 __device__ __forceinline__ double dist2(const MemberDev *M, int i, int j, int k, double X0, double X1, double X2)
 {
     const double dx = mimg((double)i - X0, M->per[0], M->box[0]);
@@ -429,21 +469,24 @@ __device__ __forceinline__ void move_values(const char *src, long long from, cha
 
 // Link words of node (i, j, k) of lattice M from the node map own (this lattice's part):
 // for a fluid node x, the directions e whose source x - c_e lies inside a particle and the
-// slot (0..3, in the order the particles are met) of the particle owning each source.
-__device__ void link_words(const MemberDev *M, const int *own, int i, int j, int k, unsigned long long &w0,
-                           unsigned long long &w1)
+// slot (0..3, in the order the particles are met) of the particle owning each source; on
+// a narrow lattice a slot is a (particle, image) pair, the image of each source found from
+// the particle positions X (the set's array at time t).
+__device__ void link_words(const MemberDev *M, const int *own, const double *X, int i, int j, int k,
+                           unsigned long long &w0, unsigned long long &w1)
 {
     const int nx = M->nx, ny = M->ny, nz = M->nz;
     w0 = 0ull;
     w1 = 0ull;
     if (own[(k * ny + j) * nx + i] >= 0) return;
     unsigned mask = 0u, lo = 0u, hi = 0u;
-    int id[4] = {-1, -1, -1, -1};
+    int id[4] = {-1, -1, -1, -1}, img[4] = {0, 0, 0, 0};
     int nid = 0;
     bool over = false;
 #pragma unroll 1
     for (int e = 0; e < kQ - 1; ++e) {
         int c[3] = {i - kCXd[e], j - kCYd[e], k - kCZd[e]};
+        const int u[3] = {c[0], c[1], c[2]};
         const int dims[3] = {nx, ny, nz};
         bool ok = true;
         for (int a = 0; a < 3; ++a) {
@@ -456,10 +499,12 @@ __device__ void link_words(const MemberDev *M, const int *own, int i, int j, int
         const int o = own[(c[2] * ny + c[1]) * nx + c[0]];
         if (o < 0) continue;
         const int q = o - M->p_off;
+        const int im = source_image(M, u[0], u[1], u[2], X + 3 * (long long)o);
         int sl = 0;
-        while (sl < nid && id[sl] != q) ++sl;
+        while (sl < nid && (id[sl] != q || img[sl] != im)) ++sl;
         if (sl == nid) {
             if (nid == 4) { over = true; continue; }
+            img[nid] = im;
             id[nid++] = q;
         }
         mask |= 1u << e;
@@ -531,30 +576,42 @@ __device__ __forceinline__ float mimg_f(float dx, int per, float n)
     return dx;
 }
 
-// V_b = V + Omega x r at node (i, j, k) from a packed FP32 state q (X, V, Omega)
-__device__ __forceinline__ void wall_velocity_f(const MemberDev *M, const float4 (&q)[3], int i, int j, int k,
-                                                float &u0, float &u1, float &u2)
+// V_b = V + Omega x r at node (i, j, k) from a packed FP32 state q (X, V, Omega), r the
+// node's position relative to the image of the particle that holds link group grp (the
+// minimum image, or from a link's midpoint on a narrow lattice, as group_arm)
+__device__ __forceinline__ void wall_velocity_f(const MemberDev *M, const float4 (&q)[3], unsigned grp, int i, int j,
+                                                int k, float &u0, float &u1, float &u2)
 {
-    const float r0 = mimg_f((float)i - q[0].x, M->per[0], (float)M->box[0]);
-    const float r1 = mimg_f((float)j - q[0].y, M->per[1], (float)M->box[1]);
-    const float r2 = mimg_f((float)k - q[0].z, M->per[2], (float)M->box[2]);
+    float r0, r1, r2;
+    if (M->narrow) {
+        const int e = __ffs(grp) - 1;
+        const float h0 = 0.5f * (float)kCXd[e], h1 = 0.5f * (float)kCYd[e], h2 = 0.5f * (float)kCZd[e];
+        r0 = mimg_f(((float)i - h0) - q[0].x, M->per[0], (float)M->box[0]) + h0;
+        r1 = mimg_f(((float)j - h1) - q[0].y, M->per[1], (float)M->box[1]) + h1;
+        r2 = mimg_f(((float)k - h2) - q[0].z, M->per[2], (float)M->box[2]) + h2;
+    } else {
+        r0 = mimg_f((float)i - q[0].x, M->per[0], (float)M->box[0]);
+        r1 = mimg_f((float)j - q[0].y, M->per[1], (float)M->box[1]);
+        r2 = mimg_f((float)k - q[0].z, M->per[2], (float)M->box[2]);
+    }
     u0 = q[1].x + (q[2].y * r2 - q[2].z * r1);
     u1 = q[1].y + (q[2].z * r0 - q[2].x * r2);
     u2 = q[1].z + (q[2].x * r1 - q[2].y * r0);
 }
 
-// Velocity of particle q's surface point nearest to node (i, j, k), V_b = V + Omega x r
-// with r = x - X (minimum image), in the collision precision C; used with c_d . V_b for
-// the link (x, d).  X is the position at time t, V and Omega the velocities of the step
-// (written by the motion kernel at the other parity).
+// Velocity of particle q's surface for the links of group grp at node (i, j, k), V_b = V +
+// Omega x r with r = x - X (the image that holds the group, as group_arm), in the
+// collision precision C; used with c_d . V_b for the link (x, d), which equals c_d . V_b
+// at the link's midpoint since c_d . (Omega x c_d) = 0.  X is the position at time t, V
+// and Omega the velocities of the step (written by the motion kernel at the other parity).
 template <typename C>
-__device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *M, int q, int i, int j, int k,
-                                              int par, C &u0, C &u1, C &u2)
+__device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *M, int q, unsigned grp, int i, int j,
+                                              int k, int par, C &u0, C &u1, C &u2)
 {
     const double *X = s.X[par] + 3 * q, *V = s.V[par ^ 1] + 3 * q, *W = s.W[par ^ 1] + 3 * q;
-    const C r0 = (C)mimg((double)i - X[0], M->per[0], M->box[0]);
-    const C r1 = (C)mimg((double)j - X[1], M->per[1], M->box[1]);
-    const C r2 = (C)mimg((double)k - X[2], M->per[2], M->box[2]);
+    double a0, a1, a2;
+    group_arm(M, grp, i, j, k, X[0], X[1], X[2], a0, a1, a2);
+    const C r0 = (C)a0, r1 = (C)a1, r2 = (C)a2;
     const C w0 = (C)W[0], w1 = (C)W[1], w2 = (C)W[2];
     u0 = (C)V[0] + (w1 * r2 - w2 * r1);
     u1 = (C)V[1] + (w2 * r0 - w0 * r2);
@@ -581,9 +638,9 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
         if constexpr (sizeof(C) == 4) {
             const float4 *pq = reinterpret_cast<const float4 *>(s.pf[par] + 12 * (M->p_off + q));
             const float4 qq[3] = {pq[0], pq[1], pq[2]};
-            wall_velocity_f(M, qq, i, j, k, u0, u1, u2);
+            wall_velocity_f(M, qq, grp, i, j, k, u0, u1, u2);
         } else {
-            wall_velocity<C>(s, M, M->p_off + q, i, j, k, par, u0, u1, u2);
+            wall_velocity<C>(s, M, M->p_off + q, grp, i, j, k, par, u0, u1, u2);
         }
 #pragma unroll
         for (int e = 0; e < kQ - 1; ++e) {
@@ -620,7 +677,7 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
             const int nxy = M->nx * M->ny;
             const int k = cell / nxy, rem = cell - k * nxy, j = rem / M->nx, i = rem - j * M->nx;
             unsigned long long w0, w1;
-            link_words(M, s.own[par] + M->cell_off, i, j, k, w0, w1);
+            link_words(M, s.own[par] + M->cell_off, s.X[par], i, j, k, w0, w1);
             const unsigned long long o0 = s.lw[c], o1 = s.lw[s.ncell_total + c];
             if (o0 != w0 || o1 != w1) mark_words(s, M, o0, o1, w0, w1, k, t - 1);
             s.lw[c] = w0;
@@ -652,12 +709,13 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
             const long long gc = M->cell_off + (ck * ny + cj) * nx + ci;
             unsigned long long o0 = 0ull, o1 = 0ull;
             if (lane == 0) { o0 = s.lw[gc]; o1 = s.lw[s.ncell_total + gc]; }
-            int o = -1;
+            int o = -1, im = 0;
             if (lane < kQ - 1) {
                 const int si = ci - kCXd[lane], sj = cj - kCYd[lane], sk = ck - kCZd[lane];
                 const bool ok = (M->per[0] || (si >= 0 && si < nx)) && (M->per[1] || (sj >= 0 && sj < ny)) &&
                                 (M->per[2] || (sk >= 0 && sk < nz));
                 if (ok) o = own[(wrapc(sk, nz) * ny + wrapc(sj, ny)) * nx + wrapc(si, nx)];
+                if (o >= 0) im = source_image(M, si, sj, sk, s.X[par] + 3 * (long long)o);
             } else if (lane == kQ - 1) {
                 o = own[(ck * ny + cj) * nx + ci];
             }
@@ -666,10 +724,11 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
             int id0 = -1, id1 = -1, id2 = -1, id3 = -1;
             bool ov = false;
             if (self < 0) {
+                // (on a narrow lattice a slot is a (particle, image) pair: the key packs both)
                 for (int e = 0; e < kQ - 1; ++e) {
                     const int oe = __shfl(o, e, 32);
                     if (oe < 0) continue;
-                    const int pq = oe - M->p_off;
+                    const int pq = (oe - M->p_off) | (__shfl(im, e, 32) << 24);
                     int sl;
                     if (id0 < 0 || id0 == pq) { id0 = pq; sl = 0; }
                     else if (id1 < 0 || id1 == pq) { id1 = pq; sl = 1; }
@@ -684,10 +743,11 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
             unsigned long long w0 = 0ull, w1 = 0ull;
             if (mask != 0u || ov) {
                 w0 = (unsigned long long)mask | ((unsigned long long)slo << 18) |
-                     ((unsigned long long)max(id0, 0) << 36) | ((unsigned long long)max(id1, 0) << 49) |
+                     ((unsigned long long)(max(id0, 0) & 0x1fff) << 36) |
+                     ((unsigned long long)(max(id1, 0) & 0x1fff) << 49) |
                      ((unsigned long long)(id2 >= 0) << 62) | ((unsigned long long)ov << 63);
-                w1 = (unsigned long long)shi | ((unsigned long long)max(id2, 0) << 18) |
-                     ((unsigned long long)max(id3, 0) << 31);
+                w1 = (unsigned long long)shi | ((unsigned long long)(max(id2, 0) & 0x1fff) << 18) |
+                     ((unsigned long long)(max(id3, 0) & 0x1fff) << 31);
             }
             if (lane == 0) {
                 if (o0 != w0 || o1 != w1) mark_words(s, M, o0, o1, w0, w1, ck, t - 1);
@@ -1261,6 +1321,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
     const long long cell_off = uni(M->cell_off);
     const double rho_f = uni(M->rho_f);
+    const bool rest_free = uni(M->rest_free) != 0;
     const int nxy = nx * ny;
     const long long lbase = (long long)p * s.lcap;
     const int k0 = s.lchunk[p * (kChunks + 1) + chunk], k1 = s.lchunk[p * (kChunks + 1) + chunk + 1];
@@ -1281,31 +1342,45 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         cntx = 0;
         for (int base = k0; base < k1; base += kLinksBlock) {
             const int k = base + lane;
-            unsigned grp = 0u;
-            int cell = 0, slot = 0;
+            int cell = 0;
+            unsigned long long w0 = 0ull, w1 = 0ull;
             if (k < k1 && s.lmask[lbase + k] != 0u) {
                 cell = s.lcell[lbase + k];
-                const unsigned long long w0 = s.lw[cell_off + cell];
-                if (((unsigned)w0 & 0x3ffffu) != 0u) {
-                    const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + cell_off + cell] : 0ull;
-                    const int ng = (w0 >> 62) ? 4 : 2;
-                    for (int g = 0; g < ng; ++g) {
-                        int q;
-                        const unsigned gd = slot_dirs(w0, w1, g, q);
-                        if (gd != 0u && q == pl) { grp = gd; slot = g; break; }
-                    }
+                w0 = s.lw[cell_off + cell];
+                if (((unsigned)w0 & 0x3ffffu) == 0u) w0 = 0ull;
+                else if (w0 >> 62) w1 = s.lw[s.ncell_total + cell_off + cell];
+            }
+            const int ng = (w0 >> 62) ? 4 : 2;
+            // one entry per slot of p at the node: one pass, or more on a narrow lattice,
+            // where a node can hold links into two images of p (one slot each)
+            int g0 = 0;
+            for (;;) {
+                unsigned grp = 0u;
+                int slot = 0;
+                for (int g = g0; g < ng; ++g) {
+                    int q;
+                    const unsigned gd = slot_dirs(w0, w1, g, q);
+                    if (gd != 0u && q == pl) { grp = gd; slot = g; break; }
                 }
+                const bool has = grp != 0u;
+                const unsigned long long bal = __ballot(has);
+                if (bal == 0ull) break;
+                if (has) {
+                    const int at = cntx + __popcll(bal & ((1ull << lane) - 1ull));
+                    if (at < k1 - k0) {
+                        const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
+                        xc[at] = (int)((unsigned)cell | ((unsigned)slot << 30));
+                        xs[at] = node_slot(s, M, cell, rem - jj * nx, jj, kk);
+                        xg[at] = grp;
+                    } else {
+                        atomicOr(s.flags, 0x40u);
+                    }
+                    g0 = slot + 1;
+                } else {
+                    g0 = ng;
+                }
+                cntx = min(cntx + __popcll(bal), k1 - k0);
             }
-            const bool has = grp != 0u;
-            const unsigned long long bal = __ballot(has);
-            if (has) {
-                const int at = cntx + __popcll(bal & ((1ull << lane) - 1ull));
-                const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
-                xc[at] = (int)((unsigned)cell | ((unsigned)slot << 30));
-                xs[at] = node_slot(s, M, cell, rem - jj * nx, jj, kk);
-                xg[at] = grp;
-            }
-            cntx += __popcll(bal);
         }
         if (lane == 0) s.xcnt[p * kChunks + chunk] = cntx;
         __threadfence_block();
@@ -1323,12 +1398,21 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;   // 2 rho_f w_d
     const double z18 = rho_f / 3.0, z36 = rho_f / 6.0;                  // 6 rho_f w_d
     const double inv_nxy = 1.0 / (double)nxy, inv_nx = 1.0 / (double)nx;
-    auto rel_pos = [&](int cell, double &x0, double &x1, double &x2) {
+    // (on a narrow lattice the entry's image of p is the one that holds its link group: its
+    // arm from the current centre X, as group_arm, plus the small displacement X - X_ref)
+    const bool narrow = uni(M->narrow) != 0;
+    const double dX0 = mimg(X0 - R0, per0, box0), dX1 = mimg(X1 - R1, per1, box1), dX2 = mimg(X2 - R2, per2, box2);
+    auto rel_pos = [&](int cell, unsigned g, double &x0, double &x1, double &x2) {
         const int kk = div_uni(cell, nxy, inv_nxy), rem = cell - kk * nxy;
         const int jj = div_uni(rem, nx, inv_nx), ii = rem - jj * nx;
-        x0 = mimg((double)ii - R0, per0, box0);
-        x1 = mimg((double)jj - R1, per1, box1);
-        x2 = mimg((double)kk - R2, per2, box2);
+        if (narrow) {
+            group_arm(M, g, ii, jj, kk, X0, X1, X2, x0, x1, x2);
+            x0 += dX0; x1 += dX1; x2 += dX2;
+        } else {
+            x0 = mimg((double)ii - R0, per0, box0);
+            x1 = mimg((double)jj - R1, per1, box1);
+            x2 = mimg((double)kk - R2, per2, box2);
+        }
     };
 
     // (2) link-set sums of a rebuilt chunk: S, Qx, Wx (21 values, cached per chunk)
@@ -1339,7 +1423,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         for (int k = lane; k < cntx; k += kLinksBlock) {
             const unsigned g = xg[k];
             double x0, x1, x2;
-            rel_pos((int)((unsigned)xc[k] & 0x3fffffffu), x0, x1, x2);
+            rel_pos((int)((unsigned)xc[k] & 0x3fffffffu), g, x0, x1, x2);
             // S_n = sum 6 w_d rho_f c_d c_d^T over the node's links, from counts
             auto diag = [&](int axis) {
                 return z18 * (double)__popc(g & (link_mask(axis, 1, false) | link_mask(axis, -1, false))) +
@@ -1419,9 +1503,12 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
                 const int nd = (int)__popc(g & link_mask(axis, 1, true)) - (int)__popc(g & link_mask(axis, -1, true));
                 return a18 * (double)na + a36 * (double)nd;
             };
-            const double G0 = 2.0 * Db[b][0] + rest(0), G1 = 2.0 * Db[b][1] + rest(1), G2 = 2.0 * Db[b][2] + rest(2);
+            // (rest_free: without the rest state's part)
+            const double G0 = 2.0 * Db[b][0] + (rest_free ? 0.0 : rest(0));
+            const double G1 = 2.0 * Db[b][1] + (rest_free ? 0.0 : rest(1));
+            const double G2 = 2.0 * Db[b][2] + (rest_free ? 0.0 : rest(2));
             double x0, x1, x2;
-            rel_pos(cellb[b], x0, x1, x2);
+            rel_pos(cellb[b], g, x0, x1, x2);
             acc[0] += G0; acc[1] += G1; acc[2] += G2;
             acc[3] += x1 * G2 - x2 * G1;
             acc[4] += x2 * G0 - x0 * G2;

@@ -258,12 +258,11 @@ def settling_periodic_case(tau: float, n: int = 160, r0: float = 5.0, overlap: f
     return params, pk
 
 
-def dry_chain_case(side: int = 16, length: int = 620, rho_p: float = 2.466):
+def dry_chain_case(side: int = 12, length: int = 620, rho_p: float = 2.466):
     """The dry granular chain of Sec. 3.2 (second benchmark, hydrodynamics switched off):
     60 spheres of radius 5.005 at z = i (2R - 0.01) on the axis x = y = side / 2, the first
-    one moved to z = 10.001, E_p = 10, nu_p = 0.2.  Without fluid the lattice only hosts
-    the node map; its cross-section is `side` (the paper's 12 is narrower than the library
-    allows for a periodic axis around a sphere of this radius, which changes nothing here)."""
+    one moved to z = 10.001, E_p = 10, nu_p = 0.2, in the paper's 12 x 12 cross-section.
+    Without fluid the lattice only hosts the node map."""
     pk = chain_case(side=side, length=length)
     x = pk["x"].copy()
     x[0, 2] = 10.001

@@ -53,6 +53,7 @@ class Params(ctypes.Structure):
         ("max_particles", ctypes.c_int32),
         ("max_radius", ctypes.c_double),
         ("tile_x", ctypes.c_int32),
+        ("rest_free", ctypes.c_int32),
     ]
 
 
@@ -139,7 +140,7 @@ def _f64(a, shape):
 
 def make_params(nx, ny, nz, tau=1.0, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), wave=WAVE_NONE, amp=0.0, omega=0.0,
                 t_n=0, E=10.0, nu=0.2, mu=0.0, rho_p=1.0, probe_z=(), max_particles=0, max_radius=12.0, tile_x=0,
-                **_ignored):
+                rest_free=False, **_ignored):
     p = Params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     for k in range(6):
@@ -156,6 +157,7 @@ def make_params(nx, ny, nz, tau=1.0, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), wave=WAVE
     p.max_particles = int(max_particles)
     p.max_radius = float(max_radius)
     p.tile_x = int(tile_x)
+    p.rest_free = 1 if rest_free else 0
     return p
 
 

@@ -796,3 +796,44 @@ def test_fluid_off_head_on_collision_is_elastic(orc):
     assert p["v"][1, 0] == pytest.approx(v, rel=1e-3)
     assert np.abs(p["v"][:, 1:]).max() == 0.0
     assert np.array_equal(s.populations(), f0)
+
+
+def test_rest_free_link_force_between_touching_spheres(orc):
+    """Two fixed spheres overlapping by 0.1 in fluid at rest (f = w_d rho_f everywhere): the
+    printed Eq. (fFS) leaves a net push of the rest state towards the other sphere (the
+    links the contact hides are missing from the sum; equal and opposite on the pair), and
+    without the rest state's part (rest_free) the force is zero, since every f~_d - w_d
+    rho_f vanishes."""
+    X = np.array([[5.0, 5.2, 4.9], [9.9, 5.2, 4.9]])
+    R = np.array([2.5, 2.5])
+    out = {}
+    for rf in (False, True):
+        s = orc.Sim(16, 10, 10, tau=0.8, bc=(0,) * 6, rho_p=2.0, rest_free=rf)
+        s.set_particles(X, R, fixed=np.array([1, 1]))
+        s.step(1)
+        out[rf] = s.particles()["force"]
+        s.close()
+    f = out[False]
+    assert f[0, 0] > 1e-3 and f[1, 0] < -1e-3
+    assert np.abs(f[0] + f[1]).max() <= 1e-14
+    assert not out[True].any()
+
+
+def test_rest_free_changes_nothing_for_a_separated_sphere(orc):
+    """A moving, spinning sphere alone in a periodic box: over a closed set of links the
+    rest state's part of Eq. (fFS), 2 rho_f sum w_d c_d (and its moment), vanishes, so the
+    two readings give the same trajectory and forces up to rounding."""
+    X = np.array([[8.3, 7.9, 9.2]])
+    out = {}
+    for rf in (False, True):
+        s = orc.Sim(16, 16, 18, tau=0.9, bc=(0,) * 6, rho_p=1.5, rest_free=rf)
+        s.set_particles(X, np.array([3.7]), v=np.array([[0.03, -0.01, 0.02]]), w=np.array([[0.0, 2e-3, -1e-3]]))
+        s.step(25)
+        out[rf] = s.particles()
+        s.close()
+    a, b = out[False], out[True]
+    fs = np.abs(a["force"]).max()
+    assert fs > 1e-3
+    assert np.abs(a["force"] - b["force"]).max() <= 1e-10 * fs
+    assert np.abs(a["x"] - b["x"]).max() <= 1e-12
+    assert np.abs(a["w"] - b["w"]).max() <= 1e-10 * np.abs(a["w"]).max()
