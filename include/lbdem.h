@@ -313,9 +313,8 @@ int lbdem_adj_workspace_size(lbdem_set *set, int32_t lattice, int64_t nsteps, in
 
 /* Bind a window to lattice `lattice` of `set` (synchronises the set's stream).  workspace:
  * caller-owned device memory of at least lbdem_adj_workspace_size bytes, 256-byte aligned,
- * kept alive until lbdem_adj_destroy.  Errors: LBDEM_EINVAL (also for a lattice with a
- * periodic axis shorter than 2 max_radius + 4, whose per-image link groups the window does
- * not model), LBDEM_ENOMEM (workspace too small), LBDEM_EDEVICE. */
+ * kept alive until lbdem_adj_destroy.  Errors: LBDEM_EINVAL, LBDEM_ENOMEM (workspace too
+ * small), LBDEM_EDEVICE. */
 int lbdem_adj_create(lbdem_set *set, int32_t lattice, int64_t nsteps, int32_t ckpt_every, void *workspace,
                      size_t workspace_bytes, lbdem_adj **out);
 

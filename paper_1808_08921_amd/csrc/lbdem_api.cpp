@@ -279,6 +279,8 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.compact = G.compact;
     s.list_margin = (double)G.list_margin;
     s.fluid_off = G.fluid_off;
+    s.narrow = 0;
+    for (const MemberDev &M : G.mem) s.narrow |= M.narrow;
     s.es = (int)es;
     s.rt = c.take<uint2>((size_t)std::max<long long>(G.compact ? G.rt_words : 1, 1));
     s.popC = c.take<char>(G.compact ? es * kQ * (size_t)G.cells : 1);
@@ -527,7 +529,7 @@ int build_graph(lbdem_set *S, int steps)
             kp.gridDim = dim3(S->ds.tiles_total);
             kp.kernelParams = fluid_args;
             HIPCHK(hipGraphAddKernelNode(&nr, S->graph, &n4, 1, &kp));
-            kp.func = links_kernel_ptr(S->G.prec);
+            kp.func = links_kernel_ptr(S->G.prec, S->ds.narrow);
             kp.gridDim = dim3(links_grid(S->ds));
             kp.blockDim = dim3(links_block());
             kp.kernelParams = part_args;
@@ -541,7 +543,7 @@ int build_graph(lbdem_set *S, int steps)
         if (S->G.fluid_off) {
             n2 = n1;
         } else {
-            kp.func = fluid_kernel_ptr(S->G.prec, S->G.compact);
+            kp.func = fluid_kernel_ptr(S->G.prec, S->G.compact, S->ds.narrow);
             kp.gridDim = dim3(S->ds.tiles_total);
             kp.kernelParams = fluid_args;
             HIPCHK(hipGraphAddKernelNode(&n2, S->graph, &n1, 1, &kp));
@@ -1556,8 +1558,6 @@ int lbdem_adj_create(lbdem_set *S, int32_t lattice, int64_t nsteps, int32_t ckpt
     const MemberDev &M = S->G.mem[lattice];
     const lbdem_params &p = S->params[lattice];
     if (M.ncell > (1LL << 31) / kQ) return fail(LBDEM_EINVAL, "lattice too large for the adjoint window");
-    if (M.narrow)
-        return fail(LBDEM_EINVAL, "the adjoint window needs periodic axes of at least 2 max_radius + 4");
     std::unique_ptr<lbdem_adj> J(new lbdem_adj());
     J->set = S;
     J->lattice = lattice;

@@ -80,6 +80,7 @@ struct MemberDev {
 struct DevSet {
     int nmem;
     int fluid_off;            // 1: hydrodynamics switched off (particles feel contacts and F_g only)
+    int narrow;               // 1: some lattice of the set is narrow (MemberDev::narrow)
     const MemberDev *mem;
     int tiles_total;
     int nzt;                  // z planes per fluid-kernel thread
@@ -211,9 +212,9 @@ hipError_t launch_fields(int prec, const DevSet &s, int m, long long ncell, doub
 // kernel entry points and grid sizes, for building HIP graphs
 void *refresh_kernel_ptr(int prec);
 void *records_kernel_ptr(int prec, int compact);
-void *links_kernel_ptr(int prec);
+void *links_kernel_ptr(int prec, int narrow);
 void *motion_kernel_ptr();
-void *fluid_kernel_ptr(int prec, int compact);
+void *fluid_kernel_ptr(int prec, int compact, int narrow);
 void *remap_kernel_ptr_prec(int prec);
 int refresh_grid(const DevSet &s);
 int links_grid(const DevSet &s);

@@ -136,13 +136,14 @@ __device__ __forceinline__ double mimg(double dx, int per, double n)
 
 // Position of fluid node (i, j, k) relative to the image of a particle centre X that holds
 // the node's link group grp (directions e whose source x - c_e lies in that image): the
-// minimum image of x - X, or, on a narrow periodic lattice, where two images can border one
-// node, the minimum image of the first link's midpoint x - c_e / 2 (always less than half
-// a period from its own image's centre) plus c_e / 2.
+// minimum image of x - X, or, in a set with a narrow periodic lattice (NR), where two
+// images can border one node, the minimum image of the first link's midpoint x - c_e / 2
+// (always less than half a period from its own image's centre) plus c_e / 2.
+template <bool NR>
 __device__ __forceinline__ void group_arm(const MemberDev *M, unsigned grp, int i, int j, int k, double X0, double X1,
                                           double X2, double &r0, double &r1, double &r2)
 {
-    if (M->narrow) {
+    if constexpr (NR) {
         const int e = __ffs(grp) - 1;
         const double h0 = 0.5 * (double)kCXd[e], h1 = 0.5 * (double)kCYd[e], h2 = 0.5 * (double)kCZd[e];
         r0 = mimg(((double)i - h0) - X0, M->per[0], M->box[0]) + h0;
@@ -578,12 +579,13 @@ __device__ __forceinline__ float mimg_f(float dx, int per, float n)
 
 // V_b = V + Omega x r at node (i, j, k) from a packed FP32 state q (X, V, Omega), r the
 // node's position relative to the image of the particle that holds link group grp (the
-// minimum image, or from a link's midpoint on a narrow lattice, as group_arm)
+// minimum image, or from a link's midpoint in a set with a narrow lattice, as group_arm)
+template <bool NR>
 __device__ __forceinline__ void wall_velocity_f(const MemberDev *M, const float4 (&q)[3], unsigned grp, int i, int j,
                                                 int k, float &u0, float &u1, float &u2)
 {
     float r0, r1, r2;
-    if (M->narrow) {
+    if constexpr (NR) {
         const int e = __ffs(grp) - 1;
         const float h0 = 0.5f * (float)kCXd[e], h1 = 0.5f * (float)kCYd[e], h2 = 0.5f * (float)kCZd[e];
         r0 = mimg_f(((float)i - h0) - q[0].x, M->per[0], (float)M->box[0]) + h0;
@@ -604,13 +606,13 @@ __device__ __forceinline__ void wall_velocity_f(const MemberDev *M, const float4
 // collision precision C; used with c_d . V_b for the link (x, d), which equals c_d . V_b
 // at the link's midpoint since c_d . (Omega x c_d) = 0.  X is the position at time t, V
 // and Omega the velocities of the step (written by the motion kernel at the other parity).
-template <typename C>
+template <typename C, bool NR>
 __device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *M, int q, unsigned grp, int i, int j,
                                               int k, int par, C &u0, C &u1, C &u2)
 {
     const double *X = s.X[par] + 3 * q, *V = s.V[par ^ 1] + 3 * q, *W = s.W[par ^ 1] + 3 * q;
     double a0, a1, a2;
-    group_arm(M, grp, i, j, k, X[0], X[1], X[2], a0, a1, a2);
+    group_arm<NR>(M, grp, i, j, k, X[0], X[1], X[2], a0, a1, a2);
     const C r0 = (C)a0, r1 = (C)a1, r2 = (C)a2;
     const C w0 = (C)W[0], w1 = (C)W[1], w2 = (C)W[2];
     u0 = (C)V[0] + (w1 * r2 - w2 * r1);
@@ -623,7 +625,7 @@ __device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *
 // f~_d(x,t) - w_d rho_f (the same relation holds for deviations since w_e = w_d).  V_b comes
 // from the particle's position at t and its velocities of the step; the momentum these
 // links exchange was accounted for by the link pass and the motion kernel.
-template <typename C>
+template <typename C, bool NR>
 __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M, C (&f)[kQ], unsigned long long w0,
                                             int i, int j, int k, int par, double rho_f, long long gc)
 {
@@ -638,9 +640,9 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
         if constexpr (sizeof(C) == 4) {
             const float4 *pq = reinterpret_cast<const float4 *>(s.pf[par] + 12 * (M->p_off + q));
             const float4 qq[3] = {pq[0], pq[1], pq[2]};
-            wall_velocity_f(M, qq, grp, i, j, k, u0, u1, u2);
+            wall_velocity_f<NR>(M, qq, grp, i, j, k, u0, u1, u2);
         } else {
-            wall_velocity<C>(s, M, M->p_off + q, grp, i, j, k, par, u0, u1, u2);
+            wall_velocity<C, NR>(s, M, M->p_off + q, grp, i, j, k, par, u0, u1, u2);
         }
 #pragma unroll
         for (int e = 0; e < kQ - 1; ++e) {
@@ -974,7 +976,7 @@ __global__ __launch_bounds__(256) void k_records(DevSet s)
 // Pull streaming (Eq. stream), stationary half-way walls, moving half-way walls on the
 // particles (Eq. mem, from the node's link words), the density faces (Sec. 2.4), BGK
 // collision (Eqs. bgk, BGKequili, rhoAndU) and probe partial sums.
-template <int P, bool CMP>
+template <int P, bool CMP, bool NR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 3 : (CMP ? 6 : 5)))) void k_fluid(DevSet s)
 {
     using S = typename Prec<P>::S;
@@ -1126,7 +1128,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     #pragma unroll
                 for (int e = 0; e < kQ; ++e)
                     f[e] = (fl && !((unk >> e) & 1u)) ? decode_dev<P>(raw[e], e, rho_fd) : C(0);
-                if (lmask != 0u) moving_wall<C>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell);
+                if (lmask != 0u) moving_wall<C, NR>(s, M, f, lwv, i, j, z, par, rho_fd, cell_off + cell);
 
                 if (z == 0 && bc4 == BC_PRESSURE) zou_he<C>(f, drho_in, false);
                 if (z == nz - 1 && bc5 == BC_PRESSURE) zou_he<C>(f, C(0), true);
@@ -1300,7 +1302,7 @@ constexpr unsigned pair_mask(int a, int b, int sign)
 // order; the motion kernel adds the chunks in chunk order and solves for (V, Omega).
 // The deviation sums of a node's links come from the record k_records wrote for the node's
 // slot in this step.
-template <int P>
+template <int P, bool NR>
 __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int only)
 {
     const long long t = *s.tstep;
@@ -1351,10 +1353,10 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
                 else if (w0 >> 62) w1 = s.lw[s.ncell_total + cell_off + cell];
             }
             const int ng = (w0 >> 62) ? 4 : 2;
-            // one entry per slot of p at the node: one pass, or more on a narrow lattice,
-            // where a node can hold links into two images of p (one slot each)
+            // one entry per slot of p at the node: one pass, or more in a set with a narrow
+            // lattice, where a node can hold links into two images of p (one slot each)
             int g0 = 0;
-            for (;;) {
+            for (int pass = 0; pass < (NR ? 4 : 1); ++pass) {
                 unsigned grp = 0u;
                 int slot = 0;
                 for (int g = g0; g < ng; ++g) {
@@ -1398,15 +1400,15 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;   // 2 rho_f w_d
     const double z18 = rho_f / 3.0, z36 = rho_f / 6.0;                  // 6 rho_f w_d
     const double inv_nxy = 1.0 / (double)nxy, inv_nx = 1.0 / (double)nx;
-    // (on a narrow lattice the entry's image of p is the one that holds its link group: its
-    // arm from the current centre X, as group_arm, plus the small displacement X - X_ref)
-    const bool narrow = uni(M->narrow) != 0;
+    // (in a set with a narrow lattice the entry's image of p is the one that holds its link
+    // group: its arm from the current centre X, as group_arm, plus the small displacement
+    // X - X_ref)
     const double dX0 = mimg(X0 - R0, per0, box0), dX1 = mimg(X1 - R1, per1, box1), dX2 = mimg(X2 - R2, per2, box2);
     auto rel_pos = [&](int cell, unsigned g, double &x0, double &x1, double &x2) {
         const int kk = div_uni(cell, nxy, inv_nxy), rem = cell - kk * nxy;
         const int jj = div_uni(rem, nx, inv_nx), ii = rem - jj * nx;
-        if (narrow) {
-            group_arm(M, g, ii, jj, kk, X0, X1, X2, x0, x1, x2);
+        if constexpr (NR) {
+            group_arm<true>(M, g, ii, jj, kk, X0, X1, X2, x0, x1, x2);
             x0 += dX0; x1 += dX1; x2 += dX2;
         } else {
             x0 = mimg((double)ii - R0, per0, box0);
@@ -2593,9 +2595,12 @@ __device__ __forceinline__ unsigned adj_gather(const AdjDev &a, const typename P
         const int sc = (c[2] * ny + c[1]) * nx + c[0];
         const int q = a.own[sc];
         if (q < 0) { g[e] = decode_dev<P>(fin[e * nc + sc], e, a.rho_f); continue; }
-        const double r0 = mimg((double)i - a.X[3 * q], M.per[0], M.box[0]);
-        const double r1 = mimg((double)j - a.X[3 * q + 1], M.per[1], M.box[1]);
-        const double r2 = mimg((double)k - a.X[3 * q + 2], M.per[2], M.box[2]);
+        // (on a narrow lattice, from the link's midpoint, which fixes the image, as group_arm)
+        const double h0 = M.narrow ? 0.5 * kCX[e] : 0.0, h1 = M.narrow ? 0.5 * kCY[e] : 0.0,
+                     h2 = M.narrow ? 0.5 * kCZ[e] : 0.0;
+        const double r0 = mimg(((double)i - h0) - a.X[3 * q], M.per[0], M.box[0]) + h0;
+        const double r1 = mimg(((double)j - h1) - a.X[3 * q + 1], M.per[1], M.box[1]) + h1;
+        const double r2 = mimg(((double)k - h2) - a.X[3 * q + 2], M.per[2], M.box[2]) + h2;
         const double *V = a.V + 3 * q, *W = a.W + 3 * q;
         const double u0 = V[0] + (W[1] * r2 - W[2] * r1);
         const double u1 = V[1] + (W[2] * r0 - W[0] * r2);
@@ -2885,26 +2890,32 @@ __global__ __launch_bounds__(256) void k_adj_vgrad(AdjDev a)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <bool CMP>
+template <bool CMP, bool NR>
 void *fluid_ptr(int prec)
 {
     switch (prec) {
-    case PREC_FP64: return (void *)&k_fluid<PREC_FP64, CMP>;
-    case PREC_FP32: return (void *)&k_fluid<PREC_FP32, CMP>;
-    case PREC_FP16DEV: return (void *)&k_fluid<PREC_FP16DEV, CMP>;
-    default: return (void *)&k_fluid<PREC_BF16DEV, CMP>;
+    case PREC_FP64: return (void *)&k_fluid<PREC_FP64, CMP, NR>;
+    case PREC_FP32: return (void *)&k_fluid<PREC_FP32, CMP, NR>;
+    case PREC_FP16DEV: return (void *)&k_fluid<PREC_FP16DEV, CMP, NR>;
+    default: return (void *)&k_fluid<PREC_BF16DEV, CMP, NR>;
     }
 }
-void *fluid_kernel_ptr(int prec, int compact) { return compact ? fluid_ptr<true>(prec) : fluid_ptr<false>(prec); }
-void *links_kernel_ptr(int prec)
+void *fluid_kernel_ptr(int prec, int compact, int narrow)
+{
+    if (narrow) return compact ? fluid_ptr<true, true>(prec) : fluid_ptr<false, true>(prec);
+    return compact ? fluid_ptr<true, false>(prec) : fluid_ptr<false, false>(prec);
+}
+template <bool NR>
+void *links_ptr(int prec)
 {
     switch (prec) {
-    case PREC_FP64: return (void *)&k_links<PREC_FP64>;
-    case PREC_FP32: return (void *)&k_links<PREC_FP32>;
-    case PREC_FP16DEV: return (void *)&k_links<PREC_FP16DEV>;
-    default: return (void *)&k_links<PREC_BF16DEV>;
+    case PREC_FP64: return (void *)&k_links<PREC_FP64, NR>;
+    case PREC_FP32: return (void *)&k_links<PREC_FP32, NR>;
+    case PREC_FP16DEV: return (void *)&k_links<PREC_FP16DEV, NR>;
+    default: return (void *)&k_links<PREC_BF16DEV, NR>;
     }
 }
+void *links_kernel_ptr(int prec, int narrow) { return narrow ? links_ptr<true>(prec) : links_ptr<false>(prec); }
 void *motion_kernel_ptr() { return (void *)&k_motion; }
 void *remap_kernel_ptr_prec(int prec)
 {
@@ -2959,20 +2970,10 @@ hipError_t launch_records(int prec, const DevSet &s, hipStream_t st)
     return hipGetLastError();
 }
 
-template <bool CMP>
-void launch_fluid_t(int prec, const DevSet &s, hipStream_t st)
-{
-    switch (prec) {
-    case PREC_FP64: hipLaunchKernelGGL((k_fluid<PREC_FP64, CMP>), dim3(s.tiles_total), dim3(256), 0, st, s); break;
-    case PREC_FP32: hipLaunchKernelGGL((k_fluid<PREC_FP32, CMP>), dim3(s.tiles_total), dim3(256), 0, st, s); break;
-    case PREC_FP16DEV: hipLaunchKernelGGL((k_fluid<PREC_FP16DEV, CMP>), dim3(s.tiles_total), dim3(256), 0, st, s); break;
-    default: hipLaunchKernelGGL((k_fluid<PREC_BF16DEV, CMP>), dim3(s.tiles_total), dim3(256), 0, st, s); break;
-    }
-}
 hipError_t launch_fluid(int prec, const DevSet &s, hipStream_t st)
 {
-    if (s.compact) launch_fluid_t<true>(prec, s, st);
-    else launch_fluid_t<false>(prec, s, st);
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(DevSet)>(fluid_kernel_ptr(prec, s.compact, s.narrow)),
+                       dim3(s.tiles_total), dim3(256), 0, st, s);
     return hipGetLastError();
 }
 
@@ -2980,14 +2981,9 @@ int links_block() { return kLinksBlock; }
 
 hipError_t launch_links(int prec, const DevSet &s, hipStream_t st)
 {
-    const dim3 g(links_grid(s)), b(kLinksBlock);
     const int mode = 0, only = -1;
-    switch (prec) {
-    case PREC_FP64: hipLaunchKernelGGL(k_links<PREC_FP64>, g, b, 0, st, s, mode, only); break;
-    case PREC_FP32: hipLaunchKernelGGL(k_links<PREC_FP32>, g, b, 0, st, s, mode, only); break;
-    case PREC_FP16DEV: hipLaunchKernelGGL(k_links<PREC_FP16DEV>, g, b, 0, st, s, mode, only); break;
-    default: hipLaunchKernelGGL(k_links<PREC_BF16DEV>, g, b, 0, st, s, mode, only); break;
-    }
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(DevSet, int, int)>(links_kernel_ptr(prec, s.narrow)),
+                       dim3(links_grid(s)), dim3(kLinksBlock), 0, st, s, mode, only);
     return hipGetLastError();
 }
 
