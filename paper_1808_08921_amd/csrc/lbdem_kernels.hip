@@ -620,6 +620,21 @@ __device__ __forceinline__ void wall_velocity(const DevSet &s, const MemberDev *
     u2 = (C)V[2] + (w0 * r1 - w1 * r0);
 }
 
+// Wall velocity of particle q for the link group grp at node (i, j, k), from the packed
+// FP32 state (FP32 and 16-bit storage) or the FP64 state.
+template <typename C, bool NR>
+__device__ __forceinline__ void slot_velocity(const DevSet &s, const MemberDev *M, int q, unsigned grp, int i, int j,
+                                              int k, int par, C &u0, C &u1, C &u2)
+{
+    if constexpr (sizeof(C) == 4) {
+        const float4 *pq = reinterpret_cast<const float4 *>(s.pf[par] + 12 * (M->p_off + q));
+        const float4 qq[3] = {pq[0], pq[1], pq[2]};
+        wall_velocity_f<NR>(M, qq, grp, i, j, k, u0, u1, u2);
+    } else {
+        wall_velocity<C, NR>(s, M, M->p_off + q, grp, i, j, k, par, u0, u1, u2);
+    }
+}
+
 // Eq. (mem) for the links of a fluid node: f_e = f~_d(x,t) - 2 (w_d / c_s^2) rho_f V_b . c_d,
 // d = e*, for every direction e whose source is inside a particle; f[e] holds the deviation
 // f~_d(x,t) - w_d rho_f (the same relation holds for deviations since w_e = w_d).  V_b comes
@@ -629,30 +644,46 @@ template <typename C, bool NR>
 __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M, C (&f)[kQ], unsigned long long w0,
                                             int i, int j, int k, int par, double rho_f, long long gc)
 {
+    const unsigned mask = (unsigned)w0 & 0x3ffffu, lo = (unsigned)(w0 >> 18) & 0x3ffffu;
     const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + gc] : 0ull;
-    const int ng = (w0 >> 62) ? 4 : 2;
-#pragma unroll 1
-    for (int g = 0; g < ng; ++g) {
-        int q;
-        const unsigned grp = slot_dirs(w0, w1, g, q);
-        if (grp == 0u) continue;
-        C u0, u1, u2;
-        if constexpr (sizeof(C) == 4) {
-            const float4 *pq = reinterpret_cast<const float4 *>(s.pf[par] + 12 * (M->p_off + q));
-            const float4 qq[3] = {pq[0], pq[1], pq[2]};
-            wall_velocity_f<NR>(M, qq, grp, i, j, k, u0, u1, u2);
-        } else {
-            wall_velocity<C, NR>(s, M, M->p_off + q, grp, i, j, k, par, u0, u1, u2);
-        }
+    const unsigned hi = (unsigned)w1 & 0x3ffffu;
+    // slots 0 and 1 together: both particle states are loaded at once, then every direction
+    // takes the velocity of its slot without a branch
+    const unsigned g0 = mask & ~lo & ~hi, g1 = mask & lo & ~hi;
+    C a0, a1, a2, b0, b1, b2;
+    slot_velocity<C, NR>(s, M, (int)(w0 >> 36) & 0x1fff, g0 ? g0 : 1u, i, j, k, par, a0, a1, a2);
+    slot_velocity<C, NR>(s, M, (int)(w0 >> 49) & 0x1fff, g1 ? g1 : 1u, i, j, k, par, b0, b1, b2);
 #pragma unroll
-        for (int e = 0; e < kQ - 1; ++e) {
-            if (!((grp >> e) & 1u)) continue;
-            const int d = kOPP[e];
-            C cu = C(0);
-            if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
-            if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
-            if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
-            f[e] = f[e] - (C)(kMW[d] * rho_f) * cu;
+    for (int e = 0; e < kQ - 1; ++e) {
+        const int d = kOPP[e];
+        const bool one = (lo >> e) & 1u;
+        const C u0 = one ? b0 : a0, u1 = one ? b1 : a1, u2 = one ? b2 : a2;
+        C cu = C(0);
+        if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
+        if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
+        if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
+        const C m = (((mask & ~hi) >> e) & 1u) ? (C)(kMW[d] * rho_f) : C(0);
+        f[e] = f[e] - m * cu;
+    }
+    // slots 2 and 3 (nodes bordering more than two particles)
+    if (hi != 0u) {
+#pragma unroll 1
+        for (int g = 2; g < 4; ++g) {
+            int q;
+            const unsigned grp = slot_dirs(w0, w1, g, q);
+            if (grp == 0u) continue;
+            C u0, u1, u2;
+            slot_velocity<C, NR>(s, M, q, grp, i, j, k, par, u0, u1, u2);
+#pragma unroll
+            for (int e = 0; e < kQ - 1; ++e) {
+                const int d = kOPP[e];
+                C cu = C(0);
+                if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
+                if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
+                if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
+                const C m = ((grp >> e) & 1u) ? (C)(kMW[d] * rho_f) : C(0);
+                f[e] = f[e] - m * cu;
+            }
         }
     }
 }
