@@ -328,7 +328,7 @@ def measured_traffic(kernel_name="lbdem::k_fluid<1, true>("):
     return None
 
 
-def ensemble_bench(n_members, steps, warmup, kernel_steps, precision="fp32"):
+def ensemble_bench(n_members, steps, warmup, kernel_steps, precision="fp32", emit=True):
     """The batched-ensemble workload: n_members uneven FCC samples (2x2x8 to 4x4x16 cubic
     cells, overlaps 1e-4..1e-2 R0, inlet periods 50..400 steps) advanced together, one
     launch per kernel per step, graph-replayed; fluid tiles chosen by the autotuner."""
@@ -372,10 +372,12 @@ def ensemble_bench(n_members, steps, warmup, kernel_steps, precision="fp32"):
                        "node_lists": lists, "z_per_thread": nzt, "tile_x_by_nx": {str(k): v for k, v in sorted(
                            {d["nx"]: d["tile_x"] for d in tuned}.items())}},
             "results": out, "autotune_report": report}
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
-def adjoint_bench(nsteps=2000, ckpt=100):
+def adjoint_bench(nsteps=2000, ckpt=100, emit=True):
     """The adjoint workload: 64x64x256 lattice, frozen touching FCC packing of 275 spheres of
     radius 8 (walls in x and y, density faces in z), a 2000-step window with checkpoints
     every 100 steps.  Loss: L2 misfit of the probe signals against a twin target made by
@@ -447,7 +449,9 @@ def adjoint_bench(nsteps=2000, ckpt=100):
             "config": {"workload": f"64x64x256 frozen FCC, {n} spheres R=8, {nsteps} steps, checkpoint every {ckpt}",
                        "loss": "L2 probe misfit vs twin target (tau+0.01, 1.1 A)"},
             "results": out, "finite_differences_fp64": fd, "checks": checks}
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 def sweep_bench(steps, warmup, kernel_steps, precision="fp32"):
@@ -654,6 +658,8 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=200, help="eager steps timed per kernel with HIP events")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip FP16/BF16 timing and the error study")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 64-lattice ensemble and adjoint-window summaries of the main line")
     ap.add_argument("--counters", type=int, default=0, metavar="STEPS",
                     help="only run the workload of the rocprofv3 counter passes (STEPS eager steps + a copy)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -761,6 +767,18 @@ def main():
                                       "roofline_frac": ab / (r["kernel_ms"][2] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         _log("error study against the FP64 path")
         line["errors_vs_fp64"] = precision_errors(params, pk)
+    if not args.no_extra:
+        # the batched ensemble and the adjoint window, summarised beside the main line
+        _log("64-lattice ensemble")
+        ens = ensemble_bench(64, 400, 50, 100, emit=False)
+        _log("adjoint window")
+        adj = adjoint_bench(emit=False)
+        line["other_workloads"] = {
+            "ensemble_64": {"workload": ens["config"]["workload"], "cells": ens["config"]["cells"],
+                            "mlups": ens["value"], "ms_per_step": ens["ms_per_step"],
+                            "results": ens["results"]},
+            "adjoint_window": {"workload": adj["config"]["workload"], "results": adj["results"],
+                               "checks": adj["checks"]}}
     if not args.no_cpu:
         _log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(params, pk)
