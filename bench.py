@@ -314,7 +314,7 @@ def summarize_counters(fetch_csv, write_csv, out_path, command):
     print("\n".join(lines))
 
 
-def measured_traffic(kernel_name="lbdem::k_fluid<1, true>("):
+def measured_traffic(kernel_name="lbdem::k_fluid<1, true, false>("):
     """HBM bytes per dispatch of the FP32 fluid kernel from the committed counter summary,
     or None when it is missing or was taken on another version of the kernel source."""
     if not os.path.exists(COUNTERS_FILE):
@@ -514,7 +514,7 @@ def drag_force(v_rel, radius, tau, rho_f=1.0):
 
 
 def settling_bench(steps=40000, taus=(0.6, 0.8, 1.0, 1.4, 1.8, 2.0), precision="fp32", every=100,
-                   kernel_steps=200):
+                   kernel_steps=200, emit=True):
     """The settling sweep of Sec. 3.1 at the paper's size: a 160^3 fully periodic cube, one
     sphere of radius 5.005 released at rest at the centre under F_g = 0.1 (net of buoyancy),
     tau from 0.6 to 2.0.  The terminal speed is the relative speed |V_p - u_bar| averaged
@@ -581,7 +581,9 @@ def settling_bench(steps=40000, taus=(0.6, 0.8, 1.0, 1.4, 1.8, 2.0), precision="
             "config": {"workload": "160^3 fully periodic cube, one sphere R = 5.005, F_g = 0.1, tau 0.6..2.0",
                        "precision": precision},
             "results": rows, "fluid_roofline_160cube": roof}
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 def dispersion_bench(calls=50, warmup=5):
@@ -659,7 +661,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip FP16/BF16 timing and the error study")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 64-lattice ensemble and adjoint-window summaries of the main line")
+                    help="skip the ensemble, adjoint-window and settling-sweep summaries of the main line")
     ap.add_argument("--counters", type=int, default=0, metavar="STEPS",
                     help="only run the workload of the rocprofv3 counter passes (STEPS eager steps + a copy)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -773,12 +775,18 @@ def main():
         ens = ensemble_bench(64, 400, 50, 100, emit=False)
         _log("adjoint window")
         adj = adjoint_bench(emit=False)
+        _log("settling sweep")
+        st = settling_bench(emit=False)
         line["other_workloads"] = {
             "ensemble_64": {"workload": ens["config"]["workload"], "cells": ens["config"]["cells"],
                             "mlups": ens["value"], "ms_per_step": ens["ms_per_step"],
                             "results": ens["results"]},
             "adjoint_window": {"workload": adj["config"]["workload"], "results": adj["results"],
-                               "checks": adj["checks"]}}
+                               "checks": adj["checks"]},
+            "settling_sweep": {"workload": st["config"]["workload"], "steps_per_tau": st["steps"],
+                               "drag_rel_err_vs_Fg": {str(r["tau"]): r["rel_err_vs_Fg"] for r in st["results"]},
+                               "v_t": {str(r["tau"]): r["v_t"] for r in st["results"]},
+                               "fluid_roofline_160cube": st["fluid_roofline_160cube"]}}
     if not args.no_cpu:
         _log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(params, pk)
