@@ -1295,6 +1295,7 @@ __device__ __forceinline__ int div_uni(int n, int d, double inv)
 
 constexpr int kLinksBlock = 64;
 constexpr int kLinkBatch = 4;
+constexpr int kLinkScan = 4;  // shell cells per lane per scan round of a rebuilt chunk
 // Direction masks over the links e (d = e*, c_d = -c_e), for sums over a node's links by
 // counting: per axis and weight class (w = 1/18 on the axes, e < 6; 1/36 on the
 // diagonals) the links whose c_d component is +1 or -1 ...
@@ -1373,46 +1374,68 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     int cntx;
     if (fresh) {
         cntx = 0;
-        for (int base = k0; base < k1; base += kLinksBlock) {
-            const int k = base + lane;
-            int cell = 0;
-            unsigned long long w0 = 0ull, w1 = 0ull;
-            if (k < k1 && s.lmask[lbase + k] != 0u) {
-                cell = s.lcell[lbase + k];
-                w0 = s.lw[cell_off + cell];
-                if (((unsigned)w0 & 0x3ffffu) == 0u) w0 = 0ull;
-                else if (w0 >> 62) w1 = s.lw[s.ncell_total + cell_off + cell];
+        // kLinkScan cells per lane and round: their list masks and cells, then their link
+        // words, then the second words and storage slots are loaded in three rounds
+        // instead of three per cell; the cells are then taken in list order
+        for (int base = k0; base < k1; base += kLinksBlock * kLinkScan) {
+            unsigned mk[kLinkScan];
+            int cl[kLinkScan];
+#pragma unroll
+            for (int b = 0; b < kLinkScan; ++b) {
+                const int k = base + b * kLinksBlock + lane;
+                mk[b] = k < k1 ? s.lmask[lbase + k] : 0u;
+                cl[b] = k < k1 ? s.lcell[lbase + k] : 0;
             }
-            const int ng = (w0 >> 62) ? 4 : 2;
-            // one entry per slot of p at the node: one pass, or more in a set with a narrow
-            // lattice, where a node can hold links into two images of p (one slot each)
-            int g0 = 0;
-            for (int pass = 0; pass < (NR ? 4 : 1); ++pass) {
-                unsigned grp = 0u;
-                int slot = 0;
-                for (int g = g0; g < ng; ++g) {
-                    int q;
-                    const unsigned gd = slot_dirs(w0, w1, g, q);
-                    if (gd != 0u && q == pl) { grp = gd; slot = g; break; }
+            unsigned long long w0b[kLinkScan];
+#pragma unroll
+            for (int b = 0; b < kLinkScan; ++b) w0b[b] = mk[b] != 0u ? s.lw[cell_off + cl[b]] : 0ull;
+            unsigned long long w1b[kLinkScan];
+            int nsb[kLinkScan];
+#pragma unroll
+            for (int b = 0; b < kLinkScan; ++b) {
+                if (((unsigned)w0b[b] & 0x3ffffu) == 0u) w0b[b] = 0ull;
+                w1b[b] = (w0b[b] >> 62) ? s.lw[s.ncell_total + cell_off + cl[b]] : 0ull;
+                nsb[b] = 0;
+                if (w0b[b] != 0ull) {
+                    const int cell = cl[b], kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
+                    nsb[b] = node_slot(s, M, cell, rem - jj * nx, jj, kk);
                 }
-                const bool has = grp != 0u;
-                const unsigned long long bal = __ballot(has);
-                if (bal == 0ull) break;
-                if (has) {
-                    const int at = cntx + __popcll(bal & ((1ull << lane) - 1ull));
-                    if (at < k1 - k0) {
-                        const int kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
-                        xc[at] = (int)((unsigned)cell | ((unsigned)slot << 30));
-                        xs[at] = node_slot(s, M, cell, rem - jj * nx, jj, kk);
-                        xg[at] = grp;
-                    } else {
-                        atomicOr(s.flags, 0x40u);
+            }
+#pragma unroll
+            for (int b = 0; b < kLinkScan; ++b) {
+                const int cell = cl[b];
+                const unsigned long long w0 = w0b[b], w1 = w1b[b];
+                const int ng = (w0 >> 62) ? 4 : 2;
+                // one entry per slot of p at the node: one pass, or more in a set with a
+                // narrow lattice, where a node can hold links into two images of p (one slot
+                // each)
+                int g0 = 0;
+                for (int pass = 0; pass < (NR ? 4 : 1); ++pass) {
+                    unsigned grp = 0u;
+                    int slot = 0;
+                    for (int g = g0; g < ng; ++g) {
+                        int q;
+                        const unsigned gd = slot_dirs(w0, w1, g, q);
+                        if (gd != 0u && q == pl) { grp = gd; slot = g; break; }
                     }
-                    g0 = slot + 1;
-                } else {
-                    g0 = ng;
+                    const bool has = grp != 0u;
+                    const unsigned long long bal = __ballot(has);
+                    if (bal == 0ull) break;
+                    if (has) {
+                        const int at = cntx + __popcll(bal & ((1ull << lane) - 1ull));
+                        if (at < k1 - k0) {
+                            xc[at] = (int)((unsigned)cell | ((unsigned)slot << 30));
+                            xs[at] = nsb[b];
+                            xg[at] = grp;
+                        } else {
+                            atomicOr(s.flags, 0x40u);
+                        }
+                        g0 = slot + 1;
+                    } else {
+                        g0 = ng;
+                    }
+                    cntx = min(cntx + __popcll(bal), k1 - k0);
                 }
-                cntx = min(cntx + __popcll(bal), k1 - k0);
             }
         }
         if (lane == 0) s.xcnt[p * kChunks + chunk] = cntx;

@@ -255,3 +255,42 @@ def test_density_watchdog(precision, bad):
         with pytest.raises(LbdemError) as e:
             gs.check()
         assert f"error {ENUMERIC}" in str(e.value)
+
+
+@pytest.mark.parametrize("vc", [0.17, 0.2])
+def test_speed_guard_on_diagonal_approach(vc):
+    """Two spheres (R = 4, hydrodynamics off) approach each other along the x-y diagonal
+    with velocities (vc, vc, 0) and its opposite.  At vc = 0.17 (|V| = 0.240) the step
+    limit of 0.25 lu holds: no status bit, and the Hertz collision follows the oracle's
+    DEM-only steps (positions and velocities to 1e-10; the near lists are rebuilt every
+    five steps with a margin that covers two such particles closing).  At vc = 0.2 (each
+    component under 0.25, |V| = 0.283 above it) the first step raises LBDEM_STATUS_TOO_FAST
+    and the particles are held to 0.25 lu per step."""
+    from paper_1808_08921_amd.lbdem import STATUS_TOO_FAST
+
+    params = dict(nx=48, ny=48, nz=24, tau=1.0, bc=(0,) * 6, E=10.0, nu=0.2, mu=0.0, rho_p=2.0,
+                  max_particles=2, max_radius=4.0)
+    X = np.array([[12.0, 12.0, 12.0], [21.0, 21.0, 12.0]])
+    v = np.array([[vc, vc, 0.0], [-vc, -vc, 0.0]])
+    R = np.array([4.0, 4.0])
+    steps = 60
+    with _set(params, "fp64", graph_steps=4, fluid_off=True) as gs:
+        gs.particles_set(0, X, R, v=v)
+        gs.step(1 if vc >= 0.2 else steps)
+        g = gs.particles_get(0)
+        st = gs.status()
+    if vc >= 0.2:
+        assert st & STATUS_TOO_FAST
+        assert np.linalg.norm(g["v"], axis=1).max() <= 0.25 * (1 + 1e-12)
+        return
+    assert st == 0
+    s = oracle.Sim(48, 48, 24, tau=1.0, bc=(0,) * 6, E=10.0, nu=0.2, mu=0.0, rho_p=2.0)
+    s.set_fluid_off(True)
+    s.set_particles(X, R, v=v)
+    s.step(steps)
+    o = s.particles()
+    s.close()
+    # they met (Hertz contact reversed their approach) within the window
+    assert o["v"][0, 0] < 0.0
+    assert np.abs(g["x"] - o["x"]).max() <= 1e-10 * 48
+    assert np.abs(g["v"] - o["v"]).max() <= 1e-10 * np.abs(o["v"]).max()
