@@ -953,19 +953,33 @@ __global__ __launch_bounds__(256) void k_records(DevSet s)
         if (((unsigned)w0 & 0x3ffffu) == 0u) return;
         const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + gc] : 0ull;
         const int ng = (w0 >> 62) ? 4 : 2;
-        // the node's populations in the link directions (every direction some slot uses;
-        // a direction no lane of the wave needs is not loaded at all)
+        // the node's populations in the link directions, loaded without a branch
         const unsigned all = (unsigned)w0 & 0x3ffffu;
         C v[kQ - 1];
 #pragma unroll
         for (int e = 0; e < kQ - 1; ++e) {
             const int d = kOPP[e];
             const bool on = (all >> e) & 1u;
-            v[e] = C(0);
-            if (on) v[e] = decode_dev<P>(ldo(A, (unsigned)d * nc + (unsigned)slot), d, rho_f);
+            // (every lane loads; a lane without the link reads the array's first element)
+            const C x = decode_dev<P>(ldo(A, on ? (unsigned)d * nc + (unsigned)slot : 0u), d, rho_f);
+            v[e] = on ? x : C(0);
         }
+        // slots 0 and 1 in one pass without branches (v is 0 outside the links)
+        const unsigned lo = (unsigned)(w0 >> 18) & 0x3ffffu, hi = (unsigned)w1 & 0x3ffffu;
+        const unsigned g0 = all & ~lo & ~hi, g1 = all & lo & ~hi;
+        C A0 = C(0), A1 = C(0), A2 = C(0), B0 = C(0), B1 = C(0), B2 = C(0);
+#pragma unroll
+        for (int e = 0; e < kQ - 1; ++e) {
+            const int d = kOPP[e];
+            const C va = ((g0 >> e) & 1u) ? v[e] : C(0), vb = ((g1 >> e) & 1u) ? v[e] : C(0);
+            if (kCX[d] > 0) { A0 += va; B0 += vb; } else if (kCX[d] < 0) { A0 -= va; B0 -= vb; }
+            if (kCY[d] > 0) { A1 += va; B1 += vb; } else if (kCY[d] < 0) { A1 -= va; B1 -= vb; }
+            if (kCZ[d] > 0) { A2 += va; B2 += vb; } else if (kCZ[d] < 0) { A2 -= va; B2 -= vb; }
+        }
+        if (g0 != 0u) put_record<P>(s, 0, cell_off + slot, A0, A1, A2, g0);
+        if (g1 != 0u) put_record<P>(s, 1, cell_off + slot, B0, B1, B2, g1);
 #pragma unroll 1
-        for (int gg = 0; gg < ng; ++gg) {
+        for (int gg = 2; gg < ng; ++gg) {
             int q;
             const unsigned grp = slot_dirs(w0, w1, gg, q);
             if (grp == 0u) continue;
@@ -1146,11 +1160,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                     unk |= (kind == BC_PRESSURE) ? (1u << e) : 0u;
                 }
                 raw[18] = ldo(A, fl ? (unsigned)(18 * nc) + (unsigned)me : 0u);
-                // every load is in flight before the first use (no branch between them)
-                asm volatile("" : "+v"(raw[0]), "+v"(raw[1]), "+v"(raw[2]), "+v"(raw[3]), "+v"(raw[4]), "+v"(raw[5]),
-                                  "+v"(raw[6]), "+v"(raw[7]), "+v"(raw[8]), "+v"(raw[9]), "+v"(raw[10]), "+v"(raw[11]),
-                                  "+v"(raw[12]), "+v"(raw[13]), "+v"(raw[14]), "+v"(raw[15]), "+v"(raw[16]),
-                                  "+v"(raw[17]), "+v"(raw[18]));
                 // the arithmetic works on deviations f_d - w_d rho_f from the rest state: Eqs.
                 // (stream), (mem) and the density faces are affine with the same coefficients
                 // for f and its deviation (w_d = w_{d*}; the weights of each Zou-He closure sum
