@@ -1392,22 +1392,29 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
 #pragma unroll
             for (int b = 0; b < kLinkScan; ++b) {
                 const int k = base + b * kLinksBlock + lane;
-                mk[b] = k < k1 ? s.lmask[lbase + k] : 0u;
-                cl[b] = k < k1 ? s.lcell[lbase + k] : 0;
+                // (every lane loads: past the chunk's end it reads the chunk's first entry)
+                const int kc = k < k1 ? k : k0;
+                const unsigned mkr = s.lmask[lbase + kc];
+                const int clr = s.lcell[lbase + kc];
+                mk[b] = k < k1 ? mkr : 0u;
+                cl[b] = k < k1 ? clr : 0;
             }
             unsigned long long w0b[kLinkScan];
 #pragma unroll
-            for (int b = 0; b < kLinkScan; ++b) w0b[b] = mk[b] != 0u ? s.lw[cell_off + cl[b]] : 0ull;
+            for (int b = 0; b < kLinkScan; ++b) {
+                const unsigned long long wr = s.lw[cell_off + cl[b]];
+                w0b[b] = mk[b] != 0u ? wr : 0ull;
+            }
             unsigned long long w1b[kLinkScan];
             int nsb[kLinkScan];
 #pragma unroll
             for (int b = 0; b < kLinkScan; ++b) {
                 if (((unsigned)w0b[b] & 0x3ffffu) == 0u) w0b[b] = 0ull;
                 w1b[b] = (w0b[b] >> 62) ? s.lw[s.ncell_total + cell_off + cl[b]] : 0ull;
-                nsb[b] = 0;
-                if (w0b[b] != 0ull) {
+                {
                     const int cell = cl[b], kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
-                    nsb[b] = node_slot(s, M, cell, rem - jj * nx, jj, kk);
+                    const int ns = node_slot(s, M, cell, rem - jj * nx, jj, kk);
+                    nsb[b] = w0b[b] != 0ull ? ns : 0;
                 }
             }
 #pragma unroll
@@ -1550,12 +1557,15 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         for (int b = 0; b < kLinkBatch; ++b) {
             const int k = base + b * kLinksBlock + lane;
             const bool v = k < cntx;
-            const unsigned ent = v ? (unsigned)xc[k] : 0u;
+            const int kv = v ? k : 0;
+            const unsigned ent = v ? (unsigned)xc[kv] : 0u;
             cellb[b] = (int)(ent & 0x3fffffffu);
             // (a node with links is fluid, hence listed; entries past the count read the
             // first record and carry no directions)
-            const int at = v ? max(xs[k], 0) : 0;
-            gb[b] = v ? xg[k] : 0u;
+            const int xsr = xs[kv];
+            const unsigned xgr = xg[kv];
+            const int at = v ? max(xsr, 0) : 0;
+            gb[b] = v ? xgr : 0u;
             (void)get_record<P>(s, (int)(ent >> 30), cell_off + at, Db[b][0], Db[b][1], Db[b][2]);
         }
 #pragma unroll
