@@ -2174,8 +2174,12 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
         const int k = lane + 64 * i;
-        bc[i] = (k < bnum) ? s.bcell[(long long)pc * s.bcap + k] : 0;
-        bd[i] = (k < bnum) ? s.bdr[(long long)pc * s.bcap + k] : 0.0f;
+        // (every lane loads: past the band's end it reads the first entry)
+        const int kc = (k < bnum) ? k : 0;
+        const int bcr = s.bcell[(long long)pc * s.bcap + kc];
+        const float bdr = s.bdr[(long long)pc * s.bcap + kc];
+        bc[i] = (k < bnum) ? bcr : 0;
+        bd[i] = (k < bnum) ? bdr : 0.0f;
     }
     const MemberDev *Mp = nullptr;
     if (active) {
@@ -2206,7 +2210,10 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
         const int *cur = s.own[par] + Mp->cell_off;
         int was[kPre];
 #pragma unroll
-        for (int i = 0; i < kPre; ++i) was[i] = (lane + 64 * i < bnum) ? cur[bc[i]] : -1;
+        for (int i = 0; i < kPre; ++i) {
+            const int wr = cur[bc[i]];
+            was[i] = (lane + 64 * i < bnum) ? wr : -1;
+        }
         // the wave's staged neighbours are visible to all its lanes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
