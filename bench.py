@@ -586,6 +586,54 @@ def settling_bench(steps=40000, taus=(0.6, 0.8, 1.0, 1.4, 1.8, 2.0), precision="
     return line
 
 
+def pure_fluid_bench(steps=2000, warmup=200, kernel_steps=200):
+    """The pure-fluid roofline reference: the config-2 lattice (96 x 96 x 384) fully periodic
+    without particles, started from f = w_d (1 + 1e-3 sin(2 pi z / 384)) (a small acoustic
+    wave), in every storage precision; the fluid kernel runs on dense tiles (the automatic
+    mapping without particles).  Also the bandwidth of a plain 1 GiB device copy, the
+    achievable figure beside the 8 TB/s peak."""
+    import torch
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    nx, ny, nz = 96, 96, 384
+    w = np.array([1 / 18] * 6 + [1 / 36] * 12 + [1 / 3])      # order of Eq. (3d19q): rest last
+    prof = 1.0 + 1e-3 * np.sin(2.0 * math.pi * np.arange(nz) / nz)
+    f = w[:, None, None, None] * prof[None, :, None, None] * np.ones((1, 1, ny, nx))
+    out = {}
+    for prec in ("fp32", "fp16", "bf16", "fp64"):
+        params = dict(nx=nx, ny=ny, nz=nz, tau=1.0, bc=(0,) * 6, probe_z=tuple(range(0, nz, 16)), max_particles=0)
+        gs = LatticeSet([params], precision=prec, graph_steps=8, probe_ring=64)
+        gs.set_populations(0, f)
+        dt = time_steps(gs, steps, warmup)
+        kt = kernel_times(gs, kernel_steps)
+        status = gs.status()
+        gs.close()
+        torch.cuda.empty_cache()
+        alg = 2 * 19 * BYTES_PER_VALUE[prec] * nx * ny * nz
+        out[prec] = {"ms_per_step": 1e3 * dt / steps, "fluid_kernel_ms": float(kt[2]),
+                     "achieved_GBs": alg / (kt[2] * 1e-3) / 1e9, "frac": alg / (kt[2] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": alg, "status": status}
+        _log(f"pure fluid {prec}: {out[prec]}")
+    # achievable copy bandwidth: 1 GiB read and 1 GiB written per copy
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 20 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"workload": "96x96x384 fully periodic pure fluid, small sine wave in z, dense tiles",
+            "steps": steps, "by_precision": out, "device_copy_GBs": copy_gbs,
+            "device_copy_frac_of_peak": copy_gbs / HBM_PEAK_GBS}
+
+
 def dispersion_bench(calls=50, warmup=5):
     """The dispersion-analysis workload (Sec. 3.2): a probe record of 20000 steps x 24 planes
     (the FCC wave case's probes every 16 lu) through the space-time DFT on a 1024 x 1024
@@ -775,6 +823,8 @@ def main():
         ens = ensemble_bench(64, 400, 50, 100, emit=False)
         _log("adjoint window")
         adj = adjoint_bench(emit=False)
+        _log("pure fluid reference")
+        pf = pure_fluid_bench()
         _log("settling sweep")
         st = settling_bench(emit=False)
         line["other_workloads"] = {
@@ -783,6 +833,7 @@ def main():
                             "results": ens["results"]},
             "adjoint_window": {"workload": adj["config"]["workload"], "results": adj["results"],
                                "checks": adj["checks"]},
+            "pure_fluid_reference": pf,
             "settling_sweep": {"workload": st["config"]["workload"], "steps_per_tau": st["steps"],
                                "drag_rel_err_vs_Fg": {str(r["tau"]): r["rel_err_vs_Fg"] for r in st["results"]},
                                "v_t": {str(r["tau"]): r["v_t"] for r in st["results"]},

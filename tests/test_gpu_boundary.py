@@ -253,7 +253,7 @@ def test_density_watchdog(precision, bad):
     from paper_1808_08921_amd.lbdem import ENUMERIC, STATUS_NONFINITE, LbdemError
 
     params = dict(nx=16, ny=12, nz=10, tau=0.8, rho_f=1.0, bc=(0, 0, 0, 0, 0, 0), probe_z=(3,))
-    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    w = np.array([1 / 18] * 6 + [1 / 36] * 12 + [1 / 3])        # Eq. (3d19q) order: rest last
     f = np.broadcast_to(w[:, None, None, None], (19, 10, 12, 16)).copy()
     with _set(params, precision, graph_steps=2) as gs:
         gs.set_populations(0, f)
