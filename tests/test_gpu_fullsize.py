@@ -35,6 +35,32 @@ def fcc_oracle():
     s.close()
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_full_size_fcc_other_seeds_fp64(seed):
+    """The full-size FCC case with the packings of seeds 1 and 2 (other overlap jitter), FP64,
+    8 steps as the benchmark launches them: node maps bit-exact, populations 1e-10,
+    particles within the force-rounding floor of the seed-0 test."""
+    from paper_1808_08921_amd.lbdem import LatticeSet
+
+    params, pk = inputs.wave_fcc_case(seed=seed)
+    params["max_particles"] = len(pk["x"])
+    s = _oracle(params, pk)
+    s.step(8)
+    with LatticeSet([params], precision="fp64", graph_steps=8, probe_ring=64) as gs:
+        gs.particles_set(0, pk["x"], pk["radius"], fixed=pk["fixed"])
+        gs.step(8)
+        assert np.array_equal(gs.owner(0), s.owner())
+        fl = s.owner() < 0
+        assert np.abs(gs.populations(0)[:, fl] - s.populations()[:, fl]).max() <= 1e-10
+        g, o = gs.particles_get(0), s.particles()
+        assert np.abs(g["x"] - o["x"]).max() <= 1e-10 * 384
+        m_min = params["rho_p"] * 4.0 / 3.0 * np.pi * float(np.min(pk["radius"])) ** 3
+        floor = np.abs(o["force"]).max() * 2.0 ** -52 * math.sqrt(4.8e3) * 8 / m_min
+        assert np.abs(g["v"] - o["v"]).max() <= 1e-10 * np.abs(o["v"]).max() + floor
+        assert gs.status() == 0
+    s.close()
+
+
 # FP32: populations up to 1/3 are stored with a unit in the last place of 2^-25 = 3.0e-8;
 # the bound allows four of them after 8 steps of FP32 arithmetic
 @pytest.mark.parametrize("precision,tol_f,tol_probe,tol_v", [("fp64", 1e-10, 1e-10, 1e-10),
