@@ -587,7 +587,7 @@ def settling_bench(steps=40000, taus=(0.6, 0.8, 1.0, 1.4, 1.8, 2.0), precision="
 
 
 def pure_fluid_bench(steps=2000, warmup=200, kernel_steps=200):
-    """The pure-fluid roofline reference: the config-2 lattice (96 x 96 x 384) fully periodic
+    """The pure-fluid roofline reference: the FCC case's lattice (96 x 96 x 384) fully periodic
     without particles, started from f = w_d (1 + 1e-3 sin(2 pi z / 384)) (a small acoustic
     wave), in every storage precision; the fluid kernel runs on dense tiles (the automatic
     mapping without particles).  Also the bandwidth of a plain 1 GiB device copy, the

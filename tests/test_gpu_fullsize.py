@@ -119,8 +119,8 @@ def _brenner(h, radius, nmax=60):
     return 4.0 / 3.0 * math.sinh(a) * tot
 
 
-def test_settling_sphere_config_1_fp64():
-    """Config 1 as stated: 32^3 box with half-way walls, a sphere of radius 6 at the top
+def test_settling_sphere_near_top_wall_1000_steps_fp64():
+    """The settling-sphere workload: 32^3 box with half-way walls, a sphere of radius 6 at the top
     centre (centre 2 lu below the top wall's gap, (15.5, 15.5, 23.5)), density ratio 2,
     g = 1e-5, tau = 0.8, 1000 FP64 steps: trajectory parity with the oracle every 100
     steps, node maps exact; then the settling speed against Stokes drag with the walls'
