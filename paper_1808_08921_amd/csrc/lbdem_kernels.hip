@@ -3,12 +3,16 @@
 // Method: Cheng, Luding, Rivas, Harting, Magnanimo, "Hydro-micromechanical modeling of
 // wave propagation in saturated granular media", arXiv 1808.08921, Sec. 2.
 //
-// Five kernels make one time step t -> t+1 of every lattice of a set, in this order
-// (Secs. 2.1-2.4; the paper gives no order, this one is the build's reading):
+// Six kernels make one time step t -> t+1 of every lattice of a set, in this order
+// (Secs. 2.1-2.4; the paper gives no order: this one lets the particle velocities of the
+// step be solved together with the momentum their links exchange in it):
 //   k_refresh    brings the node map of step t up to date with the previous re-projection's
 //                changes, refreshes the link words of the changed nodes and their
 //                neighbours, and rebuilds the node lists (moving the populations of changed
 //                planes under compact storage) once a particle may have crossed their skin.
+//   k_records    one thread per listed node (or node of a dense tile): per link slot of a
+//                fluid node, the sum of c_d (f~_d(x,t) - w_d rho_f) over the slot's links,
+//                for the link pass.
 //   k_links      kChunks waves per particle: the link pass.  With Eq. (mem) substituted, the
 //                link force of Eq. (fFS) is 2 c_d f~_d(x,t) minus a term linear in the
 //                particle's velocities; per (particle, chunk) the first part and its torque
@@ -212,6 +216,15 @@ __device__ __forceinline__ double wave_sum(double v)
     v += dpp_d<0x141, 0xF>(v); // row_half_mirror
     v += dpp_d<0x140, 0xF>(v); // row_mirror
     return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
+}
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+    v += dpp_i<0xB1, 0xF>(v, 0);
+    v += dpp_i<0x4E, 0xF>(v, 0);
+    v += dpp_i<0x141, 0xF>(v, 0);
+    v += dpp_i<0x140, 0xF>(v, 0);
+    return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+           (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 // Minimum over the 64 lanes, returned to every lane.
 __device__ __forceinline__ int wave_min(int v)
@@ -1375,6 +1388,66 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     int *xc = s.xcell + lbase + k0;
     int *xs = s.xslot + lbase + k0;
     unsigned *xg = s.xgrp + lbase + k0;
+    const double R0 = s.Xref[3 * p], R1 = s.Xref[3 * p + 1], R2 = s.Xref[3 * p + 2];
+    const double inv_nxy = 1.0 / (double)nxy, inv_nx = 1.0 / (double)nx;
+
+    // Link-set sums of a rebuilt chunk (the 6 x 6 matrix Z of the implicit update is
+    // assembled from them): with S_n = sum over a node's links of 6 w_d rho_f c_d c_d^T and
+    // xr its position relative to X_ref, S = sum S_n, Qx = sum [xr] S_n, Wx = sum [xr] S_n
+    // [xr]^T ([v] the matrix of v x .).  On a lattice without narrow periodic axes they are
+    // summed exactly, in integers, while the chunk's entries are found: S_n = z36 S'_n with
+    // S'_n integer (6 w_d rho_f is 2 z36 on the axes and z36 on the diagonals), and xr = I -
+    // fr with I the node's integer offset from floor(X_ref) (minimum image) and fr = X_ref -
+    // floor(X_ref), so S = z36 sum S', Qx = z36 (sum [I] S' - [fr] sum S') and Wx = z36 (sum
+    // [I] S' [I]^T - T - T^T + [fr] (sum S') [fr]^T), T = (sum [I] S') [fr]^T.  (|I| stays
+    // below R + 3: the sums of S' and [I] S' fit 32 bits, those of [I] S' [I]^T take 64.)
+    const int fl0 = (int)floor(R0), fl1 = (int)floor(R1), fl2 = (int)floor(R2);
+    int zsi[15];
+    long long zwl[6];
+#pragma unroll
+    for (int c = 0; c < 15; ++c) zsi[c] = 0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) zwl[c] = 0;
+    auto add_link_set = [&](int cell, unsigned g) {
+        const int kk = div_uni(cell, nxy, inv_nxy), rem = cell - kk * nxy;
+        const int jj = div_uni(rem, nx, inv_nx), ii = rem - jj * nx;
+        auto arm = [](int c, double R, int fl, int per, double box) {
+            const double dx = (double)c - R;
+            const int n = (int)box;
+            return (c - fl) + ((per && dx > 0.5 * box) ? -n : ((per && dx < -0.5 * box) ? n : 0));
+        };
+        const int I0 = arm(ii, R0, fl0, per0, box0), I1 = arm(jj, R1, fl1, per1, box1), I2 = arm(kk, R2, fl2, per2, box2);
+        auto diag = [&](int axis) {
+            return 2 * (int)__popc(g & (link_mask(axis, 1, false) | link_mask(axis, -1, false))) +
+                   (int)__popc(g & (link_mask(axis, 1, true) | link_mask(axis, -1, true)));
+        };
+        auto offd = [&](int a, int b2) {
+            return (int)__popc(g & pair_mask(a, b2, 1)) - (int)__popc(g & pair_mask(a, b2, -1));
+        };
+        const int Sxx = diag(0), Syy = diag(1), Szz = diag(2);
+        const int Sxy = offd(0, 1), Sxz = offd(0, 2), Syz = offd(1, 2);
+        // [I] S' by columns (column n of S' is (S'_xn, S'_yn, S'_zn)), then row a of
+        // [I] S' [I]^T as I x (row a of [I] S')
+        auto cross = [](int a0, int a1, int a2, int b0, int b1, int b2, int &c0, int &c1, int &c2) {
+            c0 = a1 * b2 - a2 * b1;
+            c1 = a2 * b0 - a0 * b2;
+            c2 = a0 * b1 - a1 * b0;
+        };
+        int q00, q10, q20, q01, q11, q21, q02, q12, q22;
+        cross(I0, I1, I2, Sxx, Sxy, Sxz, q00, q10, q20);
+        cross(I0, I1, I2, Sxy, Syy, Syz, q01, q11, q21);
+        cross(I0, I1, I2, Sxz, Syz, Szz, q02, q12, q22);
+        zsi[0] += Sxx; zsi[1] += Sxy; zsi[2] += Sxz; zsi[3] += Syy; zsi[4] += Syz; zsi[5] += Szz;
+        zsi[6] += q00; zsi[7] += q01; zsi[8] += q02;
+        zsi[9] += q10; zsi[10] += q11; zsi[11] += q12;
+        zsi[12] += q20; zsi[13] += q21; zsi[14] += q22;
+        int w00, w01, w02, w10, w11, w12, w20, w21, w22;
+        cross(I0, I1, I2, q00, q01, q02, w00, w01, w02);
+        cross(I0, I1, I2, q10, q11, q12, w10, w11, w12);
+        cross(I0, I1, I2, q20, q21, q22, w20, w21, w22);
+        (void)w10; (void)w20; (void)w21;
+        zwl[0] += w00; zwl[1] += w01; zwl[2] += w02; zwl[3] += w11; zwl[4] += w12; zwl[5] += w22;
+    };
 
     // (1) the chunk's shell-list entries that hold links of p, compacted in list order;
     // kept from the previous step unless the list was rebuilt or a node within one plane
@@ -1466,10 +1539,8 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     // rebuilds the entries).  With delta = X - X_ref, r = xr - delta, so the torque is
     // sum xr x G - delta x F0, and Z follows from sums over the link set alone:
     // S = sum S_n, Qx = sum [xr] S_n, Wx = sum [xr] S_n [xr]^T (the motion kernel applies delta).
-    const double R0 = s.Xref[3 * p], R1 = s.Xref[3 * p + 1], R2 = s.Xref[3 * p + 2];
     const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;   // 2 rho_f w_d
     const double z18 = rho_f / 3.0, z36 = rho_f / 6.0;                  // 6 rho_f w_d
-    const double inv_nxy = 1.0 / (double)nxy, inv_nx = 1.0 / (double)nx;
     // (in a set with a narrow lattice the entry's image of p is the one that holds its link
     // group: its arm from the current centre X, as group_arm, plus the small displacement
     // X - X_ref)
@@ -1487,8 +1558,71 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         }
     };
 
-    // (2) link-set sums of a rebuilt chunk: S, Qx, Wx (21 values, cached per chunk)
-    if (fresh) {
+    // (2) link-set sums of a rebuilt chunk: S, Qx, Wx (21 values, cached per chunk); exact
+    // integer sums from the scan, or, in a set with a narrow lattice, FP64 sums over the
+    // entries in list order
+    if (!NR && fresh) {
+        for (int k = lane; k < cntx; k += kLinksBlock) add_link_set((int)((unsigned)xc[k] & 0x3fffffffu), xg[k]);
+        int si[15];
+#pragma unroll
+        for (int c = 0; c < 15; ++c) si[c] = wave_sum_i(zsi[c]);
+        double wl[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) wl[c] = wave_sum((double)zwl[c]); // exact: integers below 2^53
+        if (lane == 0) {
+            const double f0 = R0 - (double)fl0, f1 = R1 - (double)fl1, f2 = R2 - (double)fl2;
+            double Ss[3][3], Qs[3][3], Ws[3][3];
+            {
+                int z = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = a; c < 3; ++c) { Ss[a][c] = (double)si[z]; Ss[c][a] = (double)si[z]; ++z; }
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Qs[a][c] = (double)si[z++];
+                z = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = a; c < 3; ++c) { Ws[a][c] = wl[z]; Ws[c][a] = wl[z]; ++z; }
+            }
+            // fr x (column n of M) for M = sum S'; fr x (row a of M) for M = sum [I] S' and
+            // for M = [fr] sum S'
+            double FS[3][3], T[3][3], FSF[3][3];
+#pragma unroll
+            for (int n = 0; n < 3; ++n) {
+                FS[0][n] = f1 * Ss[2][n] - f2 * Ss[1][n];
+                FS[1][n] = f2 * Ss[0][n] - f0 * Ss[2][n];
+                FS[2][n] = f0 * Ss[1][n] - f1 * Ss[0][n];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                T[a][0] = f1 * Qs[a][2] - f2 * Qs[a][1];
+                T[a][1] = f2 * Qs[a][0] - f0 * Qs[a][2];
+                T[a][2] = f0 * Qs[a][1] - f1 * Qs[a][0];
+                FSF[a][0] = f1 * FS[a][2] - f2 * FS[a][1];
+                FSF[a][1] = f2 * FS[a][0] - f0 * FS[a][2];
+                FSF[a][2] = f0 * FS[a][1] - f1 * FS[a][0];
+            }
+            double *zc = s.zcache + ((long long)p * kChunks + chunk) * kZComp;
+            int z = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = a; c < 3; ++c) zc[z++] = z36 * Ss[a][c];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) zc[z++] = z36 * (Qs[a][c] - FS[a][c]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = a; c < 3; ++c) zc[z++] = z36 * (((Ws[a][c] - T[a][c]) - T[c][a]) + FSF[a][c]);
+        }
+    }
+    if (NR && fresh) {
         double zs[21];
 #pragma unroll
         for (int c = 0; c < 21; ++c) zs[c] = 0.0;
@@ -1552,7 +1686,8 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     for (int base = 0; base < cntx; base += kLinksBlock * kLinkBatch) {
         int cellb[kLinkBatch];
         unsigned gb[kLinkBatch];
-        double Db[kLinkBatch][3];
+        // (records are kept in the collision precision until they are summed)
+        typename Prec<P>::C Db[kLinkBatch][3];
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b) {
             const int k = base + b * kLinksBlock + lane;
@@ -1566,7 +1701,14 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
             const unsigned xgr = xg[kv];
             const int at = v ? max(xsr, 0) : 0;
             gb[b] = v ? xgr : 0u;
-            (void)get_record<P>(s, (int)(ent >> 30), cell_off + at, Db[b][0], Db[b][1], Db[b][2]);
+            if constexpr (sizeof(typename Prec<P>::C) == 4) {
+                const float4 v4 = reinterpret_cast<const float4 *>(s.frec)[(int)(ent >> 30) * s.ncell_total + cell_off + at];
+                Db[b][0] = v4.x; Db[b][1] = v4.y; Db[b][2] = v4.z;
+            } else {
+                double G0, G1, G2;
+                (void)get_record<P>(s, (int)(ent >> 30), cell_off + at, G0, G1, G2);
+                Db[b][0] = G0; Db[b][1] = G1; Db[b][2] = G2;
+            }
         }
 #pragma unroll
         for (int b = 0; b < kLinkBatch; ++b) {
@@ -1579,9 +1721,9 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
                 return a18 * (double)na + a36 * (double)nd;
             };
             // (rest_free: without the rest state's part)
-            const double G0 = 2.0 * Db[b][0] + (rest_free ? 0.0 : rest(0));
-            const double G1 = 2.0 * Db[b][1] + (rest_free ? 0.0 : rest(1));
-            const double G2 = 2.0 * Db[b][2] + (rest_free ? 0.0 : rest(2));
+            const double G0 = 2.0 * (double)Db[b][0] + (rest_free ? 0.0 : rest(0));
+            const double G1 = 2.0 * (double)Db[b][1] + (rest_free ? 0.0 : rest(1));
+            const double G2 = 2.0 * (double)Db[b][2] + (rest_free ? 0.0 : rest(2));
             double x0, x1, x2;
             rel_pos(cellb[b], g, x0, x1, x2);
             acc[0] += G0; acc[1] += G1; acc[2] += G2;
@@ -1600,22 +1742,24 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
 }
 
 // Solves A x = b for a symmetric positive definite 6 x 6 A (upper triangle given) by the
-// Cholesky factorisation A = L L^T; b is overwritten by x.
-__device__ __forceinline__ void chol_solve6(double (&A)[6][6], double (&b)[6])
+// factorisation A = L D L^T (L unit lower triangular, D diagonal), with one division per
+// pivot; b is overwritten by x.
+__device__ __forceinline__ void ldl_solve6(double (&A)[6][6], double (&b)[6])
 {
-    double L[6][6];
+    double L[6][6], E[6][6], iD[6]; // E[i][j] = L[i][j] D[j]
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         double d = A[j][j];
 #pragma unroll
-        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-        L[j][j] = sqrt(d);
+        for (int k = 0; k < j; ++k) d -= L[j][k] * E[j][k];
+        iD[j] = 1.0 / d;
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double v = A[j][i];
 #pragma unroll
-            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
-            L[i][j] = v / L[j][j];
+            for (int k = 0; k < j; ++k) v -= L[i][k] * E[j][k];
+            E[i][j] = v;
+            L[i][j] = v * iD[j];
         }
     }
 #pragma unroll
@@ -1623,14 +1767,16 @@ __device__ __forceinline__ void chol_solve6(double (&A)[6][6], double (&b)[6])
         double v = b[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) v -= L[i][k] * b[k];
-        b[i] = v / L[i][i];
+        b[i] = v;
     }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) b[i] *= iD[i];
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         double v = b[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) v -= L[k][i] * b[k];
-        b[i] = v / L[i][i];
+        b[i] = v;
     }
 }
 
@@ -1864,7 +2010,7 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
             b[3 + a] = inert * Wpv[a] + ((lp[3 + a] + Lhv[a]) + con[3 + a]);
         }
         double x[6] = {b[0], b[1], b[2], b[3], b[4], b[5]};
-        chol_solve6(A, x);
+        ldl_solve6(A, x);
         double v[3] = {x[0], x[1], x[2]}, w[3] = {x[3], x[4], x[5]};
         if (fixed_p) {
             for (int a = 0; a < 3; ++a) { v[a] = 0.0; w[a] = 0.0; }
@@ -2326,8 +2472,19 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
     // ------------------------------------------------------------------------------
     // phase B: shell-list rebuilds and near-list builds, the whole workgroup per particle
     // ------------------------------------------------------------------------------
+    // (the near lists of the workgroup's particles are built in one pass over the
+    // candidates when those particles share a lattice, which is the rule)
+    int near_w = 0, near_m = -1;
+    bool near_joint = true;
     for (int w = 0; w < kRemapWaves; ++w) {
-        const int fw = flagw[w];
+        if (!(flagw[w] & 4)) continue;
+        const int mw = s.pmem[blockIdx.x * kRemapWaves + w];
+        near_joint = near_joint && (near_m < 0 || mw == near_m);
+        near_m = mw;
+        near_w |= 1 << w;
+    }
+    for (int w = 0; w < kRemapWaves; ++w) {
+        const int fw = flagw[w] & (near_joint ? 3 : 7);
         if ((fw & 6) == 0) continue;
         const int pw = blockIdx.x * kRemapWaves + w;
         RemapCtx c;
@@ -2506,6 +2663,51 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
                 s.near_at[pw] = t + 1;
             }
             __syncthreads();
+        }
+    }
+    if (near_joint && near_w != 0) {
+        // the same near lists for the particles of the workgroup together: each candidate's
+        // position is loaded once and tested against every one of them
+        const MemberDev *M = s.mem + near_m;
+        const int q0 = M->p_off, nq = M->np;
+        const int per[3] = {M->per[0], M->per[1], M->per[2]};
+        const double box[3] = {M->box[0], M->box[1], M->box[2]};
+        double Rw[kRemapWaves];
+#pragma unroll
+        for (int w = 0; w < kRemapWaves; ++w) Rw[w] = s.R[min((int)blockIdx.x * kRemapWaves + w, s.ptot - 1)];
+        int near_total[kRemapWaves] = {};
+        for (int base = 0; base < nq; base += 256) {
+            const int jj = base + tid;
+            const int q = q0 + min(jj, nq - 1);
+            const double Y0 = Xs[3 * q], Y1 = Xs[3 * q + 1], Y2 = Xs[3 * q + 2], Rq = s.R[q];
+#pragma unroll
+            for (int w = 0; w < kRemapWaves; ++w) {
+                if (!((near_w >> w) & 1)) continue;
+                const int pw = blockIdx.x * kRemapWaves + w;
+                bool isnear = false;
+                if (jj < nq && q != pw) {
+                    const double d0 = mimg(Y0 - ctxw[w][0], per[0], box[0]);
+                    const double d1 = mimg(Y1 - ctxw[w][1], per[1], box[1]);
+                    const double d2 = mimg(Y2 - ctxw[w][2], per[2], box[2]);
+                    isnear = sqrt((d0 * d0 + d1 * d1) + d2 * d2) <= Rw[w] + Rq + kNearMargin;
+                }
+                int tot = 0;
+                const int rk = block_rank(isnear, tot, cnt4);
+                if (isnear) {
+                    const int slot = near_total[w] + rk;
+                    if (slot < kNearCap) s.nearl[(long long)pw * kNearCap + slot] = q;
+                    else atomicOr(s.flags, 0x2u);
+                }
+                near_total[w] += tot;
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < kRemapWaves; ++w) {
+            if (tid == w && ((near_w >> w) & 1)) {
+                const int pw = blockIdx.x * kRemapWaves + w;
+                s.nnear[pw] = min(near_total[w], kNearCap);
+                s.near_at[pw] = t + 1;
+            }
         }
     }
     // the conversion momentum of each particle of the workgroup
