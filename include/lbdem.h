@@ -60,7 +60,7 @@ extern "C" {
 
 /* storage precision of the populations (collision arithmetic in brackets) */
 #define LBDEM_FP64 0    /* double [double] */
-#define LBDEM_FP32 1    /* float [float] */
+#define LBDEM_FP32 1    /* float of f - w_d rho_f [float] */
 #define LBDEM_FP16DEV 2 /* IEEE half of q = f/w_d - rho_f [float] */
 #define LBDEM_BF16DEV 3 /* bfloat16 of q = f/w_d - rho_f [float] */
 

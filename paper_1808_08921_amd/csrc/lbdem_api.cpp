@@ -1234,7 +1234,7 @@ int lbdem_populations_get(lbdem_set *S, int32_t lattice, double *f)
         const int d = (int)(k / M.ncell);
         switch (S->G.prec) {
         case PREC_FP64: f[k] = ((const double *)raw.data())[k]; break;
-        case PREC_FP32: f[k] = ((const float *)raw.data())[k]; break;
+        case PREC_FP32: f[k] = (double)(((const float *)raw.data())[k] + (float)(kWh[d] * M.rho_f)); break;
         case PREC_FP16DEV: f[k] = (double)((float)kWh[d] * (rf + (float)((const _Float16 *)raw.data())[k])); break;
         default: f[k] = (double)((float)kWh[d] * (rf + bf16_to_f32_host(((const uint16_t *)raw.data())[k]))); break;
         }
@@ -1261,7 +1261,7 @@ int lbdem_populations_set(lbdem_set *S, int32_t lattice, const double *f)
         const int d = (int)(k / M.ncell);
         switch (S->G.prec) {
         case PREC_FP64: ((double *)raw.data())[k] = f[k]; break;
-        case PREC_FP32: ((float *)raw.data())[k] = (float)f[k]; break;
+        case PREC_FP32: ((float *)raw.data())[k] = (float)f[k] - (float)(kWh[d] * M.rho_f); break;
         case PREC_FP16DEV: ((_Float16 *)raw.data())[k] = (_Float16)((float)f[k] * kInvWh[d] - rf); break;
         default: ((uint16_t *)raw.data())[k] = f32_to_bf16_host((float)f[k] * kInvWh[d] - rf); break;
         }

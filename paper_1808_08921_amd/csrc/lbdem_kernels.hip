@@ -91,29 +91,34 @@ __device__ __forceinline__ void sto(T *base, unsigned idx, T v)
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (unsigned)sizeof(T)) = v;
 }
 
-// decode population d from storage
+// decode population d from storage: FP64 holds f, FP32 the deviation f - w_d rho_f (the
+// rest value rounded once to FP32), the 16-bit forms q = f / w_d - rho_f
 template <int P>
-__device__ __forceinline__ typename Prec<P>::C ld(const typename Prec<P>::S *a, unsigned idx, int d, float rho_f)
+__device__ __forceinline__ typename Prec<P>::C ld(const typename Prec<P>::S *a, unsigned idx, int d, double rho_f)
 {
-    if constexpr (P == PREC_FP64 || P == PREC_FP32) {
+    if constexpr (P == PREC_FP64) {
         return ldo(a, idx);
+    } else if constexpr (P == PREC_FP32) {
+        return ldo(a, idx) + (float)(kWd[d] * rho_f);
     } else if constexpr (P == PREC_FP16DEV) {
-        return (float)kWd[d] * (rho_f + (float)ldo(a, idx));
+        return (float)kWd[d] * ((float)rho_f + (float)ldo(a, idx));
     } else {
-        return (float)kWd[d] * (rho_f + bf16_to_f32(ldo(a, idx)));
+        return (float)kWd[d] * ((float)rho_f + bf16_to_f32(ldo(a, idx)));
     }
 }
-// encode population d to storage: 16-bit forms hold q = f / w_d - rho_f
+// encode population d to storage
 template <int P>
-__device__ __forceinline__ void st(typename Prec<P>::S *a, unsigned idx, int d, typename Prec<P>::C f, float rho_f)
+__device__ __forceinline__ void st(typename Prec<P>::S *a, unsigned idx, int d, typename Prec<P>::C f, double rho_f)
 {
     using S = typename Prec<P>::S;
-    if constexpr (P == PREC_FP64 || P == PREC_FP32) {
+    if constexpr (P == PREC_FP64) {
         sto(a, idx, (S)f);
+    } else if constexpr (P == PREC_FP32) {
+        sto(a, idx, f - (float)(kWd[d] * rho_f));
     } else if constexpr (P == PREC_FP16DEV) {
-        sto(a, idx, (S)(f * kInvW[d] - rho_f));
+        sto(a, idx, (S)(f * kInvW[d] - (float)rho_f));
     } else {
-        sto(a, idx, f32_to_bf16(f * kInvW[d] - rho_f));
+        sto(a, idx, f32_to_bf16(f * kInvW[d] - (float)rho_f));
     }
 }
 
@@ -323,17 +328,41 @@ __device__ __forceinline__ void zou_he(C (&f)[kQ], C rho, bool top)
     }
 }
 
+// acc + sign * v, or sign * v when acc holds no term yet (a sum started from 0 would keep
+// an addition of 0 that IEEE signed zeros do not let the compiler drop)
+template <typename C>
+__device__ __forceinline__ void acc_term(C &acc, bool &any, int sign, C v)
+{
+    if (sign == 0) return;
+    if (any) acc = (sign > 0) ? acc + v : acc - v;
+    else acc = (sign > 0) ? v : -v;
+    any = true;
+}
+
+// c_d . u
+template <typename C>
+__device__ __forceinline__ C cdot(int d, C ux, C uy, C uz)
+{
+    C cu = C(0);
+    bool any = false;
+    acc_term(cu, any, kCX[d], ux);
+    acc_term(cu, any, kCY[d], uy);
+    acc_term(cu, any, kCZ[d], uz);
+    return cu;
+}
+
 // rho = sum f, j = sum f c (Eq. rhoAndU), summed in direction order
 template <typename C>
 __device__ __forceinline__ void moments(const C (&f)[kQ], C &rho, C &jx, C &jy, C &jz)
 {
     C r = C(0), x = C(0), y = C(0), z = C(0);
+    bool ar = false, ax = false, ay = false, az = false;
 #pragma unroll
     for (int d = 0; d < kQ; ++d) {
-        r += f[d];
-        if (kCX[d] > 0) x += f[d]; else if (kCX[d] < 0) x -= f[d];
-        if (kCY[d] > 0) y += f[d]; else if (kCY[d] < 0) y -= f[d];
-        if (kCZ[d] > 0) z += f[d]; else if (kCZ[d] < 0) z -= f[d];
+        acc_term(r, ar, 1, f[d]);
+        acc_term(x, ax, kCX[d], f[d]);
+        acc_term(y, ay, kCY[d], f[d]);
+        acc_term(z, az, kCZ[d], f[d]);
     }
     rho = r; jx = x; jy = y; jz = z;
 }
@@ -342,10 +371,7 @@ __device__ __forceinline__ void moments(const C (&f)[kQ], C &rho, C &jx, C &jy, 
 template <typename C>
 __device__ __forceinline__ C feq(int d, C rho, C ux, C uy, C uz, C uu)
 {
-    C cu = C(0);
-    if (kCX[d] > 0) cu += ux; else if (kCX[d] < 0) cu -= ux;
-    if (kCY[d] > 0) cu += uy; else if (kCY[d] < 0) cu -= uy;
-    if (kCZ[d] > 0) cu += uz; else if (kCZ[d] < 0) cu -= uz;
+    const C cu = cdot(d, ux, uy, uz);
     if constexpr (sizeof(C) == 8) {
         const double cs2 = kCS2;
         return kWd[d] * rho * (1.0 + cu / cs2 + (cu * cu) / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
@@ -360,10 +386,7 @@ __device__ __forceinline__ C feq(int d, C rho, C ux, C uy, C uz, C uu)
 template <typename C>
 __device__ __forceinline__ C feq_dev(int d, C drho, C rho, C ux, C uy, C uz, C uu)
 {
-    C cu = C(0);
-    if (kCX[d] > 0) cu += ux; else if (kCX[d] < 0) cu -= ux;
-    if (kCY[d] > 0) cu += uy; else if (kCY[d] < 0) cu -= uy;
-    if (kCZ[d] > 0) cu += uz; else if (kCZ[d] < 0) cu -= uz;
+    const C cu = cdot(d, ux, uy, uz);
     if constexpr (sizeof(C) == 8) {
         const double cs2 = kCS2;
         return kWd[d] * (drho + rho * (cu / cs2 + (cu * cu) / (2.0 * cs2 * cs2) - uu / (2.0 * cs2)));
@@ -375,13 +398,14 @@ __device__ __forceinline__ C feq_dev(int d, C drho, C rho, C ux, C uy, C uz, C u
     }
 }
 
-// stored value of population d -> deviation f_d - w_d rho_f (the 16-bit forms store
-// q = f / w_d - rho_f, so the deviation is w_d q)
+// stored value of population d -> deviation f_d - w_d rho_f (FP32 stores the deviation;
+// the 16-bit forms store q = f / w_d - rho_f, so the deviation is w_d q)
 template <int P>
 __device__ __forceinline__ typename Prec<P>::C decode_dev(typename Prec<P>::S v, int d, double rho_f)
 {
     using C = typename Prec<P>::C;
-    if constexpr (P == PREC_FP64 || P == PREC_FP32) return v - (C)(kWd[d] * rho_f);
+    if constexpr (P == PREC_FP64) return v - (C)(kWd[d] * rho_f);
+    else if constexpr (P == PREC_FP32) return v;
     else if constexpr (P == PREC_FP16DEV) return (float)kWd[d] * (float)v;
     else return (float)kWd[d] * bf16_to_f32(v);
 }
@@ -393,7 +417,8 @@ __device__ __forceinline__ void store_dev(typename Prec<P>::S *a, unsigned idx, 
 {
     using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
-    if constexpr (P == PREC_FP64 || P == PREC_FP32) sto(a, idx, (S)((C)(kWd[d] * rho_f) + df));
+    if constexpr (P == PREC_FP64) sto(a, idx, (S)((C)(kWd[d] * rho_f) + df));
+    else if constexpr (P == PREC_FP32) sto(a, idx, df);
     else if constexpr (P == PREC_FP16DEV) sto(a, idx, (S)(df * kInvW[d]));
     else sto(a, idx, f32_to_bf16(df * kInvW[d]));
 }
@@ -671,10 +696,7 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
         const int d = kOPP[e];
         const bool one = (lo >> e) & 1u;
         const C u0 = one ? b0 : a0, u1 = one ? b1 : a1, u2 = one ? b2 : a2;
-        C cu = C(0);
-        if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
-        if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
-        if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
+        const C cu = cdot(d, u0, u1, u2);
         const C m = (((mask & ~hi) >> e) & 1u) ? (C)(kMW[d] * rho_f) : C(0);
         f[e] = f[e] - m * cu;
     }
@@ -690,10 +712,7 @@ __device__ __forceinline__ void moving_wall(const DevSet &s, const MemberDev *M,
 #pragma unroll
             for (int e = 0; e < kQ - 1; ++e) {
                 const int d = kOPP[e];
-                C cu = C(0);
-                if (kCX[d] > 0) cu += u0; else if (kCX[d] < 0) cu -= u0;
-                if (kCY[d] > 0) cu += u1; else if (kCY[d] < 0) cu -= u1;
-                if (kCZ[d] > 0) cu += u2; else if (kCZ[d] < 0) cu -= u2;
+                const C cu = cdot(d, u0, u1, u2);
                 const C m = ((grp >> e) & 1u) ? (C)(kMW[d] * rho_f) : C(0);
                 f[e] = f[e] - m * cu;
             }
@@ -896,7 +915,7 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
                         S *CbS = reinterpret_cast<S *>(Cb);
                         for (int d = 0; d < kQ; ++d)
                             st<P>(CbS, (unsigned)(d * nc + to), d, (typename Prec<P>::C)feq<double>(d, rb, u0, u1, u2, uu),
-                                  (float)M->rho_f);
+                                  M->rho_f);
                         continue;
                     }
                     if (s.es == 8) move_values<unsigned long long>(A, old, Cb, to, nc);
@@ -1167,8 +1186,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                     // f_e(x, t+1) = f~_e(x - c_e, t); from a wall or a particle the population
                     // comes back from this node, f~_{e*}(x, t); across a density face it is unknown
                     const bool back = (kind != 0) || ((lmask >> e) & 1u);
-                    const unsigned idx = back ? (unsigned)(kOPP[e] * nc) + (unsigned)me
-                                              : (unsigned)(e * nc) + (unsigned)(compact ? src[e] : cell + off);
+                    // (offsets from array e: the select is taken between per-lane offsets, so
+                    // that no per-lane multiply by nc is formed)
+                    const unsigned from = compact ? (unsigned)src[e] : (unsigned)(cell + off);
+                    const unsigned idx = (unsigned)(e * nc) +
+                                         (back ? (unsigned)((kOPP[e] - e) * nc) + (unsigned)me : from);
                     raw[e] = ldo(A, fl ? idx : 0u);
                     unk |= (kind == BC_PRESSURE) ? (1u << e) : 0u;
                 }
@@ -2208,7 +2230,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
         const double r2 = mimg((double)kk - c.X[2], c.per[2], c.box[2]);
         S *Bn = (S *)(sn ? s.popB : s.popA) + M->pop_off;
         const int nc = (int)M->ncell;
-        const float rho_ff = (float)M->rho_f;
+        const double rho_ff = M->rho_f;
         if (was < 0 && best == p) {
             // Eq. (convertFS): a covered node hands its momentum to the particle
             const int sl = node_slot(s, M, cell, ii, jj, kk);
@@ -2730,7 +2752,7 @@ __global__ __launch_bounds__(256) void k_init_pops(DevSet s, long long total_cel
     const int cell = (int)(c - M->cell_off);
     const int nc = (int)M->ncell;
     S *A = (S *)s.popA + M->pop_off, *B = (S *)s.popB + M->pop_off;
-    const float rho_ff = (float)M->rho_f;
+    const double rho_ff = M->rho_f;
     for (int d = 0; d < kQ; ++d) {
         const typename Prec<P>::C v = (typename Prec<P>::C)(kWd[d] * M->rho_f);
         st<P>(A, d * nc + cell, d, v, rho_ff);
@@ -2755,7 +2777,7 @@ __global__ __launch_bounds__(256) void k_fields(DevSet s, int m, double *out)
     const S *A = (const S *)(par ? s.popB : s.popA) + M->pop_off;
     double rho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
     if (s.own[par][M->cell_off + c] < 0) {
-        const float rho_ff = (float)M->rho_f;
+        const double rho_ff = M->rho_f;
         for (int d = 0; d < kQ; ++d) {
             const double f = (double)ld<P>(A, (unsigned)(d * nc + c), d, rho_ff);
             rho += f;
@@ -2794,7 +2816,7 @@ __global__ __launch_bounds__(256) void k_expand(DevSet s)
         const long long nc = M->ncell;
         S *A = (S *)(par ? s.popB : s.popA) + M->pop_off;
         S *Cb = (S *)s.popC + M->pop_off;
-        const float rho_ff = (float)M->rho_f;
+        const double rho_ff = M->rho_f;
         const long long z0 = (long long)z * nxy;
         // the list of this plane is the one the row tables were built from
         for (int c = threadIdx.x; c < nxy; c += blockDim.x) {
