@@ -1450,10 +1450,11 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
         const int Sxy = offd(0, 1), Sxz = offd(0, 2), Syz = offd(1, 2);
         // [I] S' by columns (column n of S' is (S'_xn, S'_yn, S'_zn)), then row a of
         // [I] S' [I]^T as I x (row a of [I] S')
+        // (24-bit multiplies: every factor is far below 2^23)
         auto cross = [](int a0, int a1, int a2, int b0, int b1, int b2, int &c0, int &c1, int &c2) {
-            c0 = a1 * b2 - a2 * b1;
-            c1 = a2 * b0 - a0 * b2;
-            c2 = a0 * b1 - a1 * b0;
+            c0 = __mul24(a1, b2) - __mul24(a2, b1);
+            c1 = __mul24(a2, b0) - __mul24(a0, b2);
+            c2 = __mul24(a0, b1) - __mul24(a1, b0);
         };
         int q00, q10, q20, q01, q11, q21, q02, q12, q22;
         cross(I0, I1, I2, Sxx, Sxy, Sxz, q00, q10, q20);
@@ -1507,7 +1508,8 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
                 if (((unsigned)w0b[b] & 0x3ffffu) == 0u) w0b[b] = 0ull;
                 w1b[b] = (w0b[b] >> 62) ? s.lw[s.ncell_total + cell_off + cl[b]] : 0ull;
                 {
-                    const int cell = cl[b], kk = cell / nxy, rem = cell - kk * nxy, jj = rem / nx;
+                    const int cell = cl[b], kk = div_uni(cell, nxy, inv_nxy), rem = cell - kk * nxy;
+                    const int jj = div_uni(rem, nx, inv_nx);
                     const int ns = node_slot(s, M, cell, rem - jj * nx, jj, kk);
                     nsb[b] = w0b[b] != 0ull ? ns : 0;
                 }
