@@ -2131,6 +2131,9 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
     __shared__ double accw[kRemapWaves][6];
     __shared__ double ctxw[kRemapWaves][9]; // x, x_ref unwrapped next to x, lr, dr, overlap depth
     __shared__ int flagw[kRemapWaves];
+    // each wave's queue of candidate nodes (cell, owner before the projection or -2)
+    constexpr int kQueue = 256;
+    __shared__ int qcell[kRemapWaves][kQueue], qwas[kRemapWaves][kQueue];
     // the step being completed: copied by the fluid kernel (mode 0); the counter itself is
     // advanced here and read by no workgroup of this kernel
     const long long t = (mode == 0) ? *s.tcopy : *s.tstep;
@@ -2455,20 +2458,47 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
             const int *lc = band ? s.bcell + (long long)p * s.bcap : s.lcell + lbase;
             const float *dl = band ? s.bdr + (long long)p * s.bcap : s.ldr + lbase;
             const int dxy = Mp->nx * Mp->ny, dx = Mp->nx;
-            for (int k = lane, i = 0; k < n; k += 64, ++i) {
-                // the first kPre band entries of each lane and their owners are loaded already
-                int cell = 0, wpre = -2;
-                double dk = 0.0;
-                bool pre = false;
+            static_assert(64 * kPre == kQueue, "one queue slot per entry of a batch");
+            const unsigned long long below = (1ull << lane) - 1ull;
+            // kPre entries per lane at a time (the first batch of the band is loaded
+            // already): the ones within the candidate range go to the wave's queue in list
+            // order, and the queue is evaluated 64 nodes at a time, so a wave evaluates
+            // ceil(candidates / 64) rounds per batch instead of one round per entry round
+            for (int base = 0; base < n; base += kQueue) {
+                int qn = 0;
 #pragma unroll
-                for (int u = 0; u < kPre; ++u)
-                    if (band && i == u) { cell = bc[u]; dk = (double)bd[u]; wpre = was[u]; pre = true; }
-                if (!pre) { cell = lc[k]; dk = (double)dl[k]; }
-                if (dk < -lr - 1e-6 || dk > dr + 1e-6) continue;
-                const int kk = cell / dxy;
-                const int rem = cell - kk * dxy;
-                const int jj = rem / dx, ii = rem - jj * dx;
-                evaluate(c, ii, jj, kk, cell, dist2c(c, ii, jj, kk, c.X[0], c.X[1], c.X[2]), wpre, acc, conv);
+                for (int u = 0; u < kPre; ++u) {
+                    const int k = base + 64 * u + lane;
+                    int cell = 0, wpre = -2;
+                    double dk = 0.0;
+                    if (band && base == 0) {
+                        cell = bc[u]; dk = (double)bd[u]; wpre = was[u];
+                    } else if (k < n) {
+                        cell = lc[k]; dk = (double)dl[k];
+                    }
+                    const bool take = k < n && !(dk < -lr - 1e-6 || dk > dr + 1e-6);
+                    const unsigned long long bal = __ballot(take);
+                    if (take) {
+                        const int at = qn + __popcll(bal & below);
+                        qcell[wv][at] = cell;
+                        qwas[wv][at] = wpre;
+                    }
+                    qn += __popcll(bal);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int q = lane; q < qn; q += 64) {
+                    const int cell = qcell[wv][q], wpre = qwas[wv][q];
+                    const int kk = cell / dxy;
+                    const int rem = cell - kk * dxy;
+                    const int jj = rem / dx, ii = rem - jj * dx;
+                    evaluate(c, ii, jj, kk, cell, dist2c(c, ii, jj, kk, c.X[0], c.X[1], c.X[2]), wpre, acc, conv);
+                }
+                // (the next batch refills the queue once every lane has read its entry)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
         flag = 1 | (rebuild ? 2 : 0) | ((mode == 0 && t + 1 - nat_ld >= kNearEvery) ? 4 : 0);
