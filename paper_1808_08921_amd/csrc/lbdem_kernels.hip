@@ -814,8 +814,16 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
                 w1 = (unsigned long long)shi | ((unsigned long long)(max(id2, 0) & 0x1fff) << 18) |
                      ((unsigned long long)(max(id3, 0) & 0x1fff) << 31);
             }
+            // a changed word marks the chunks around plane ck of every particle it names,
+            // old or new: lane l < 8 takes slot l & 3 of the old (l < 4) or the new words, so
+            // the particles' chunk layouts are loaded in one round
+            const unsigned long long g0w = __shfl(o0, 0, 32), g1w = __shfl(o1, 0, 32);
+            if ((g0w != w0 || g1w != w1) && lane < 8) {
+                int q;
+                const unsigned dirs = (lane < 4) ? slot_dirs(g0w, g1w, lane & 3, q) : slot_dirs(w0, w1, lane & 3, q);
+                if (dirs != 0u) mark_dirty(s, M, M->p_off + q, ck, t - 1);
+            }
             if (lane == 0) {
-                if (o0 != w0 || o1 != w1) mark_words(s, M, o0, o1, w0, w1, ck, t - 1);
                 s.lw[gc] = w0;
                 s.lw[s.ncell_total + gc] = w1;
                 over |= ov;
@@ -1386,14 +1394,21 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     const int lane = threadIdx.x;
     const int p = blockIdx.x / kChunks, chunk = blockIdx.x - p * kChunks;
     if (p >= s.ptot || mode != 0) return;
+    // the chunk's state is loaded together with p's lattice, before the checks that need
+    // the lattice (everything here is indexed by p < ptot)
     const int m = uni(s.pmem[p]);
+    const double *Xo = s.X[par];
+    const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
+    const int k0 = s.lchunk[p * (kChunks + 1) + chunk], k1 = s.lchunk[p * (kChunks + 1) + chunk + 1];
+    // (a list rebuild under compact storage moves the nodes' storage slots)
+    const bool fresh = (s.lreb[p] == t - 1) || (s.ldirty[p * kChunks + chunk] == t - 1) ||
+                       (s.compact && *s.relist_at == t);
+    const int cnt_old = s.xcnt[p * kChunks + chunk];
     const MemberDev *M = s.mem + m;
     const int pl = p - uni(M->p_off);
     if (pl >= uni(M->np)) return;
     if (only >= 0 && m != only) return;
 
-    const double *Xo = s.X[par];
-    const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
     const int nx = uni(M->nx), ny = uni(M->ny);
     const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
     const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
@@ -1402,11 +1417,6 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     const bool rest_free = uni(M->rest_free) != 0;
     const int nxy = nx * ny;
     const long long lbase = (long long)p * s.lcap;
-    const int k0 = s.lchunk[p * (kChunks + 1) + chunk], k1 = s.lchunk[p * (kChunks + 1) + chunk + 1];
-    // (a list rebuild under compact storage moves the nodes' storage slots)
-    const bool fresh = (s.lreb[p] == t - 1) || (s.ldirty[p * kChunks + chunk] == t - 1) ||
-                       (s.compact && *s.relist_at == t);
-    const int cnt_old = s.xcnt[p * kChunks + chunk];
     int *xc = s.xcell + lbase + k0;
     int *xs = s.xslot + lbase + k0;
     unsigned *xg = s.xgrp + lbase + k0;
@@ -1824,15 +1834,12 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
     const int lane = threadIdx.x & 63;
     const int p = blockIdx.x * kMotionWaves + (int)(threadIdx.x >> 6);
     if (p >= s.ptot) return; // the whole wave: waves never synchronise here
+    // p's state, its link-pass sums and its near list are loaded together, before the
+    // checks that need its lattice (everything here is indexed by p < ptot)
     const int m = s.pmem[p];
-    const MemberDev *M = s.mem + m;
-    if (p - M->p_off >= M->np) return;
-    if (only >= 0 && m != only) return;
     const double *Xo = s.X[par], *Vo = s.V[par], *Wo = s.W[par];
     const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
     const double R = s.R[p];
-    const int per0 = M->per[0], per1 = M->per[1], per2 = M->per[2];
-    const double box0 = M->box[0], box1 = M->box[1], box2 = M->box[2];
     // the link pass's sums (lane c < kLinkComp adds component c of the partials over the
     // chunks, lane kLinkComp + c component c of the cached link-set sums, in chunk order)
     // and the rest of p's state for the update, loaded up front
@@ -1863,24 +1870,33 @@ __global__ __launch_bounds__(64 * kMotionWaves) void k_motion(DevSet s, int mode
     }
     const double mass = s.m[p], inert = s.I[p];
     const int fixed_p = s.fixed[p];
+    const int nn_ld = s.nnear[p];
+    const int *nl = s.nearl + (long long)p * kNearCap;
+    const int nl_ld = nl[lane & (kNearCap - 1)];
+    const int hno = s.hn[par][p];
+    const MemberDev *M = s.mem + m;
+    if (p - M->p_off >= M->np) return;
+    if (only >= 0 && m != only) return;
+    const int per0 = M->per[0], per1 = M->per[1], per2 = M->per[2];
+    const double box0 = M->box[0], box1 = M->box[1], box2 = M->box[2];
 
     // contacts over the near list (mode 0) or the near-list build (mode 1)
     const int q0 = M->p_off, nq = M->np;
     const double E = M->E, nu = M->nu, mu = M->mu;
     const int *hjo = s.hj[par] + (long long)p * kHistCap;
     const double *hfo = s.hf[par] + (long long)p * kHistCap * 3;
-    const int hno = s.hn[par][p];
     int *hjn = s.hj[par ^ 1] + (long long)p * kHistCap;
     double *hfn = s.hf[par ^ 1] + (long long)p * kHistCap * 3;
     double con[6] = {0, 0, 0, 0, 0, 0};
     int near_total = 0, hist_total = 0;
     const bool build = mode != 0;
-    const int ncand = build ? nq : min(s.nnear[p], kNearCap);
-    const int *nl = s.nearl + (long long)p * kNearCap;
+    const int ncand = build ? nq : min(nn_ld, kNearCap);
     const unsigned long long below = (1ull << lane) - 1ull;
+    static_assert(kNearCap <= 64, "a near list fits one wave");
     for (int base = 0; base < ncand; base += 64) {
         const int jj = base + lane;
-        const int q = (jj < ncand) ? (build ? q0 + jj : nl[jj]) : -1;
+        // (a near list has at most kNearCap <= 64 entries: lane jj < ncand took entry jj)
+        const int q = (jj < ncand) ? (build ? q0 + jj : nl_ld) : -1;
         bool isnear = false, keep = false;
         double ftn[3] = {0, 0, 0};
         if (jj < ncand && q != p) {
