@@ -298,6 +298,8 @@ size_t carve(const Geometry &G, char *base, DevSet &s)
     s.own[0] = c.take<int>(G.cells);
     s.own[1] = c.take<int>(G.cells);
     s.lw = c.take<unsigned long long>(2 * (size_t)G.cells);
+    s.lwc = c.take<unsigned long long>((size_t)G.cells);
+    s.lwc_bad = c.take<long long>(1);
     s.ncell_total = G.cells;
     s.frec = c.take<char>(4 * (size_t)G.cells * (G.prec == PREC_FP64 ? 32 : 16));
     s.rec_step = c.take<long long>(1);
@@ -763,6 +765,7 @@ int lbdem_create(int32_t n_lat, const lbdem_params *lat, const lbdem_config *cfg
     CHK(hipMemsetAsync(s.own[0], 0xff, sizeof(int) * S->G.cells, st));
     CHK(hipMemsetAsync(s.own[1], 0xff, sizeof(int) * S->G.cells, st));
     CHK(hipMemsetAsync(s.lw, 0, sizeof(unsigned long long) * 2 * S->G.cells, st));
+    CHK(hipMemsetAsync(s.lwc_bad, 0x80, sizeof(long long), st)); // (the first step rebuilds the lists)
     CHK(hipMemsetAsync(s.relist_at, 0, sizeof(long long), st)); // lists are built by the first step
     {
         std::vector<double> sk(S->G.mem.size(), kListSkin);

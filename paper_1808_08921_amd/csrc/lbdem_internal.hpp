@@ -113,6 +113,11 @@ struct DevSet {
     // node maps (index = parity), change lists (pairs cell, owner) and counts
     int *own[2];
     unsigned long long *lw;   // link words, two per node (all lattices) [2*ncell_total]
+    // compact storage: the first link word of each listed node at its storage slot, or
+    // kSolidWord for a listed solid node (the fluid and record kernels read these in slot
+    // order), and the step at which a full copy of the node map made them all stale
+    unsigned long long *lwc;  // [ncell_total]
+    long long *lwc_bad;
     long long ncell_total;
     // per slot of a fluid node's link words, written by k_records of step t for the link
     // pass of step t: G = sum c_d (f~_d(x,t) - w_d rho_f) over the slot's links and the link

@@ -567,6 +567,14 @@ __device__ __forceinline__ unsigned slot_dirs(unsigned long long w0, unsigned lo
     return mask & ((g & 1) ? lo : ~lo) & ((g & 2) ? hi : ~hi);
 }
 
+// Compact copy of a listed node's first link word: the word without its overflow bit for
+// a fluid node, kSolidWord for a solid one.
+constexpr unsigned long long kSolidWord = 1ull << 63;
+__device__ __forceinline__ unsigned long long compact_word(unsigned long long w0, bool solid)
+{
+    return solid ? kSolidWord : (w0 & ~kSolidWord);
+}
+
 // Marks the chunks of q's shell list whose z-slab lies within one plane of z.
 __device__ __forceinline__ void mark_dirty(const DevSet &s, const MemberDev *M, int q, int z, long long t)
 {
@@ -734,7 +742,11 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     bool over = false;
+    // (a step that rebuilds the node lists rewrites every compact word in the record kernel)
+    const bool fix_compact = s.compact && !(s.listmode && *s.relist_at == t);
     if (cnt > s.chg_cap) {
+        // (every link word may change: the record kernel rewrites every compact word)
+        if (t0 == 0) *s.lwc_bad = t;
         for (long long c = t0; c < s.ncell_total; c += stride) {
             s.own[par ^ 1][c] = s.own[par][c];
             const MemberDev *M = member_of_cell(s, c);
@@ -823,9 +835,12 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
                 const unsigned dirs = (lane < 4) ? slot_dirs(g0w, g1w, lane & 3, q) : slot_dirs(w0, w1, lane & 3, q);
                 if (dirs != 0u) mark_dirty(s, M, M->p_off + q, ck, t - 1);
             }
+            // the node's compact word at its storage slot, when listed
+            const int ns = fix_compact ? node_slot(s, M, (ck * ny + cj) * nx + ci, ci, cj, ck) : -1;
             if (lane == 0) {
                 s.lw[gc] = w0;
                 s.lw[s.ncell_total + gc] = w1;
+                if (ns >= 0) s.lwc[M->cell_off + ns] = compact_word(w0, self >= 0);
                 over |= ov;
             }
         }
@@ -987,9 +1002,24 @@ __global__ __launch_bounds__(256) void k_records(DevSet s)
     const long long cell_off = uni(M->cell_off);
     const S *A = (const S *)(par ? s.popB : s.popA) + uni(M->pop_off);
     const double rho_f = uni(M->rho_f);
+    // compact storage: every listed node's compact word is rewritten here after a list
+    // rebuild or a full copy of the node map, and read from its slot otherwise
+    const bool full_compact = CMP && (*s.relist_at == t || *s.lwc_bad == t);
+    const int *own = s.own[par] + cell_off;
     auto records = [&](int cell, int slot) {
         const long long gc = cell_off + cell;
-        const unsigned long long w0 = s.lw[gc];
+        unsigned long long w0;
+        if constexpr (CMP) {
+            if (full_compact) {
+                w0 = compact_word(s.lw[gc], own[cell] >= 0);
+                s.lwc[cell_off + slot] = w0;
+            } else {
+                w0 = s.lwc[cell_off + slot];
+            }
+            if (w0 & kSolidWord) return;
+        } else {
+            w0 = s.lw[gc];
+        }
         if (((unsigned)w0 & 0x3ffffu) == 0u) return;
         const unsigned long long w1 = (w0 >> 62) ? s.lw[s.ncell_total + gc] : 0ull;
         const int ng = (w0 >> 62) ? 4 : 2;
@@ -1118,7 +1148,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
             asm volatile("" : "+v"(oxm), "+v"(oxp), "+v"(oym), "+v"(oyp), "+v"(kxm), "+v"(kxp), "+v"(kym), "+v"(kyp));
             const int cell = (z * ny + j) * nx + i;
             bool fl = false;
-            if (vij) fl = ldo(own, (unsigned)cell) < 0;
+            unsigned long long wc = 0ull;
+            if constexpr (CMP) {
+                // the node's compact word, at its slot (which the thread knows before its cell)
+                wc = s.lwc[cell_off + me0];
+                fl = vij && !(wc & kSolidWord);
+            } else {
+                if (vij) fl = ldo(own, (unsigned)cell) < 0;
+            }
             double pr0 = 0.0, pr1 = 0.0, pr2 = 0.0, pr3 = 0.0;
             // Dense tiles with 4- and 8-byte storage write every node of a row, so each store
             // covers whole cache lines: a solid node loads nothing and stores the rest state
@@ -1131,8 +1168,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                 const int kzm = (z > 0) ? 0 : bc4, kzp = (z < nz - 1) ? 0 : bc5;
                 // Loads are issued for every lane, a solid lane reading the first element of the
                 // array (one shared line) instead of branching around each load.
-                const unsigned long long lwr = s.lw[fl ? cell_off + cell : 0];
-                const unsigned long long lwv = fl ? lwr : 0ull;
+                unsigned long long lwv;
+                if constexpr (CMP) {
+                    lwv = fl ? wc : 0ull;
+                } else {
+                    const unsigned long long lwr = s.lw[fl ? cell_off + cell : 0];
+                    lwv = fl ? lwr : 0ull;
+                }
                 const unsigned lmask = (unsigned)lwv & 0x3ffffu;
                 // storage slot of this node: the node itself, or its rank in the plane's list
                 // (as an offset from the node that the compiler cannot see through: it keeps
