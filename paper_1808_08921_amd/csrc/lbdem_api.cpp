@@ -534,8 +534,8 @@ int build_graph(lbdem_set *S, int steps)
             n0 = n4;
         } else {
             hipGraphNode_t nr;
-            kp.func = records_kernel_ptr(S->G.prec, S->G.compact);
-            kp.gridDim = dim3(S->ds.tiles_total);
+            kp.func = records_kernel_ptr(S->G.prec, S->G.compact, S->ds.narrow);
+            kp.gridDim = dim3(records_grid(S->ds));
             kp.kernelParams = fluid_args;
             HIPCHK(hipGraphAddKernelNode(&nr, S->graph, &n4, 1, &kp));
             kp.func = links_kernel_ptr(S->G.prec, S->ds.narrow);

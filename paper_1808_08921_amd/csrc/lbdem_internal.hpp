@@ -216,7 +216,8 @@ hipError_t launch_expand(int prec, const DevSet &s, hipStream_t st);
 hipError_t launch_fields(int prec, const DevSet &s, int m, long long ncell, double *out, hipStream_t st);
 // kernel entry points and grid sizes, for building HIP graphs
 void *refresh_kernel_ptr(int prec);
-void *records_kernel_ptr(int prec, int compact);
+void *records_kernel_ptr(int prec, int compact, int narrow);
+int records_grid(const DevSet &s);
 void *links_kernel_ptr(int prec, int narrow);
 void *motion_kernel_ptr();
 void *fluid_kernel_ptr(int prec, int compact, int narrow);

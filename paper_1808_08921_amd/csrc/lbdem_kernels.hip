@@ -984,15 +984,29 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
 // of step t final): per fluid node with links and per slot of its link words, G = sum c_d
 // (f~_d(x,t) - w_d rho_f) over the slot's links, read from the node's own storage slot
 // (consecutive threads read consecutive slots).
-template <int P, bool CMP>
-__global__ __launch_bounds__(256) void k_records(DevSet s)
+template <bool NR>
+__device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk, long long t);
+
+// Workgroups of the record kernel that rebuild stale link chunks, four chunks each.
+__host__ __device__ __forceinline__ int rebuild_blocks(const DevSet &s) { return (s.ptot * kChunks + 3) / 4; }
+
+template <int P, bool CMP, bool NR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 4 : 6))) void k_records(DevSet s)
 {
     using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
     const long long t = *s.tstep;
     const int par = (int)(t & 1);
     if (blockIdx.x == 0 && threadIdx.x == 0) *s.rec_step = t;
-    const int g = xcd_swizzle(blockIdx.x, gridDim.x);
+    // the first workgroups rebuild the stale link chunks, one wave per chunk: those waves
+    // are few, long and latency-bound, so they start first and run beside the node waves
+    const int nrb = rebuild_blocks(s);
+    if ((int)blockIdx.x < nrb) {
+        const int ci = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+        if (ci < s.ptot * kChunks) rebuild_chunk<NR>(s, ci / kChunks, ci - (ci / kChunks) * kChunks, t);
+        return;
+    }
+    const int g = xcd_swizzle((int)blockIdx.x - nrb, (int)gridDim.x - nrb);
     const MemberDev *M = member_of_tile(s, g);
     const int tl = g - uni(M->tile_off);
     const int ntx = uni(M->ntx), nty = uni(M->nty);
@@ -1414,28 +1428,18 @@ constexpr unsigned pair_mask(int a, int b, int sign)
     return m;
 }
 
-// Link pass, one wave per (particle p, chunk of p's shell list).  A link of p is a fluid
-// node x and a direction e whose source x - c_e lies in p; with d = e* pointing into p,
-// Eq. (fFS) with Eq. (mem) substituted gives
-//   F = c_d f~_d(x,t) - c_e f_e(x,t+1) = 2 c_d f~_d(x,t) - (2 w_d / c_s^2) rho_f c_d (c_d . V_b),
-// V_b = V_p + Omega_p x (x_b - X_p), x_b = x + c_d/2.  Since (x_b - X_p) x c_d = (x - X_p) x c_d
-// = r x c_d, the force and its torque about X_p over the step are (F, T) = F0 - Z (V, Omega)
-// with F0 = (G, r x G), G = sum 2 c_d f~_d(x,t), and Z = sum (2 w_d / c_s^2) rho_f a_d a_d^T,
-// a_d = (c_d, r x c_d).  Per node, with S = sum over its links to p of 6 w_d rho_f c_d c_d^T
-// and [r] the matrix of r x .: Z_VV = S, Z_OmegaV = [r] S, Z_OmegaOmega = [r] S [r]^T.  G is
-// summed from the deviations f~_d - w_d rho_f (the rest part 2 rho_f sum w_d c_d and S come
-// from counts of links per direction class), the sums over the chunk in FP64 in a fixed
-// order; the motion kernel adds the chunks in chunk order and solves for (V, Omega).
-// The deviation sums of a node's links come from the record k_records wrote for the node's
-// slot in this step.
-template <int P, bool NR>
-__global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int only)
+// Rebuild of one chunk of a particle's shell list (the wave of the calling lanes, for
+// particle p): when the shell list was rebuilt, the node lists were rebuilt (storage slots
+// move) or a node within one plane of the chunk's slab changed owner in the previous step,
+// the chunk's entries that hold links of p are found again, compacted in list order, and
+// its link-set sums recomputed; every other chunk keeps its entries.  It reads the link
+// words of this step (after the refresh) and no link record: the record kernel runs it in
+// waves of its own before its node waves, and the link pass reads the entries.
+template <bool NR>
+__device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk, long long t)
 {
-    const long long t = *s.tstep;
     const int par = (int)(t & 1);
-    const int lane = threadIdx.x;
-    const int p = blockIdx.x / kChunks, chunk = blockIdx.x - p * kChunks;
-    if (p >= s.ptot || mode != 0) return;
+    const int lane = threadIdx.x & 63;
     // the chunk's state is loaded together with p's lattice, before the checks that need
     // the lattice (everything here is indexed by p < ptot)
     const int m = uni(s.pmem[p]);
@@ -1445,18 +1449,16 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     // (a list rebuild under compact storage moves the nodes' storage slots)
     const bool fresh = (s.lreb[p] == t - 1) || (s.ldirty[p * kChunks + chunk] == t - 1) ||
                        (s.compact && *s.relist_at == t);
-    const int cnt_old = s.xcnt[p * kChunks + chunk];
+    if (!fresh) return;
     const MemberDev *M = s.mem + m;
     const int pl = p - uni(M->p_off);
     if (pl >= uni(M->np)) return;
-    if (only >= 0 && m != only) return;
 
     const int nx = uni(M->nx), ny = uni(M->ny);
     const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
     const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
     const long long cell_off = uni(M->cell_off);
     const double rho_f = uni(M->rho_f);
-    const bool rest_free = uni(M->rest_free) != 0;
     const int nxy = nx * ny;
     const long long lbase = (long long)p * s.lcap;
     int *xc = s.xcell + lbase + k0;
@@ -1528,9 +1530,8 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     // kept from the previous step unless the list was rebuilt or a node within one plane
     // of the chunk's slab changed owner in the previous step (the refresh of this step
     // has brought the link words up to date)
-    int cntx;
-    if (fresh) {
-        cntx = 0;
+    int cntx = 0;
+    {
         // kLinkScan cells per lane and round: their list masks and cells, then their link
         // words, then the second words and storage slots are loaded in three rounds
         // instead of three per cell; the cells are then taken in list order
@@ -1604,18 +1605,19 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
             }
         }
         if (lane == 0) s.xcnt[p * kChunks + chunk] = cntx;
-        __threadfence_block();
-        __syncthreads();
-    } else {
-        cntx = cnt_old;
+        // (the link-set sums read the entries back: this wave's stores are made visible to
+        // the wave itself; the other waves of its workgroup rebuild other chunks)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
+
 
     // Positions of the entries' nodes relative to the shell list's reference point X_ref,
     // xr = x - X_ref (minimum image; X_ref moves only when the shell list is rebuilt, which
     // rebuilds the entries).  With delta = X - X_ref, r = xr - delta, so the torque is
     // sum xr x G - delta x F0, and Z follows from sums over the link set alone:
     // S = sum S_n, Qx = sum [xr] S_n, Wx = sum [xr] S_n [xr]^T (the motion kernel applies delta).
-    const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;   // 2 rho_f w_d
     const double z18 = rho_f / 3.0, z36 = rho_f / 6.0;                  // 6 rho_f w_d
     // (in a set with a narrow lattice the entry's image of p is the one that holds its link
     // group: its arm from the current centre X, as group_arm, plus the small displacement
@@ -1637,7 +1639,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
     // (2) link-set sums of a rebuilt chunk: S, Qx, Wx (21 values, cached per chunk); exact
     // integer sums from the scan, or, in a set with a narrow lattice, FP64 sums over the
     // entries in list order
-    if (!NR && fresh) {
+    if (!NR) {
         for (int k = lane; k < cntx; k += kLinksBlock) add_link_set((int)((unsigned)xc[k] & 0x3fffffffu), xg[k]);
         int si[15];
 #pragma unroll
@@ -1698,7 +1700,7 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
                 for (int c = a; c < 3; ++c) zc[z++] = z36 * (((Ws[a][c] - T[a][c]) - T[c][a]) + FSF[a][c]);
         }
     }
-    if (NR && fresh) {
+    if (NR) {
         double zs[21];
 #pragma unroll
         for (int c = 0; c < 21; ++c) zs[c] = 0.0;
@@ -1754,6 +1756,81 @@ __global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int o
             for (int c = 0; c < 21; ++c) zc[c] = zs[c];
         }
     }
+
+}
+
+// Link pass, one wave per (particle p, chunk of p's shell list).  A link of p is a fluid
+// node x and a direction e whose source x - c_e lies in p; with d = e* pointing into p,
+// Eq. (fFS) with Eq. (mem) substituted gives
+//   F = c_d f~_d(x,t) - c_e f_e(x,t+1) = 2 c_d f~_d(x,t) - (2 w_d / c_s^2) rho_f c_d (c_d . V_b),
+// V_b = V_p + Omega_p x (x_b - X_p), x_b = x + c_d/2.  Since (x_b - X_p) x c_d = (x - X_p) x c_d
+// = r x c_d, the force and its torque about X_p over the step are (F, T) = F0 - Z (V, Omega)
+// with F0 = (G, r x G), G = sum 2 c_d f~_d(x,t), and Z = sum (2 w_d / c_s^2) rho_f a_d a_d^T,
+// a_d = (c_d, r x c_d).  Per node, with S = sum over its links to p of 6 w_d rho_f c_d c_d^T
+// and [r] the matrix of r x .: Z_VV = S, Z_OmegaV = [r] S, Z_OmegaOmega = [r] S [r]^T.  G is
+// summed from the deviations f~_d - w_d rho_f (the rest part 2 rho_f sum w_d c_d and S come
+// from counts of links per direction class), the sums over the chunk in FP64 in a fixed
+// order; the motion kernel adds the chunks in chunk order and solves for (V, Omega).
+// The deviation sums of a node's links come from the record k_records wrote for the node's
+// slot in this step.
+template <int P, bool NR>
+__global__ __launch_bounds__(kLinksBlock) void k_links(DevSet s, int mode, int only)
+{
+    const long long t = *s.tstep;
+    const int par = (int)(t & 1);
+    const int lane = threadIdx.x;
+    const int p = blockIdx.x / kChunks, chunk = blockIdx.x - p * kChunks;
+    if (p >= s.ptot || mode != 0) return;
+    // the chunk's state is loaded together with p's lattice, before the checks that need
+    // the lattice (everything here is indexed by p < ptot)
+    const int m = uni(s.pmem[p]);
+    const double *Xo = s.X[par];
+    const double X0 = Xo[3 * p], X1 = Xo[3 * p + 1], X2 = Xo[3 * p + 2];
+    const int k0 = s.lchunk[p * (kChunks + 1) + chunk], k1 = s.lchunk[p * (kChunks + 1) + chunk + 1];
+    // the chunk's entries (rebuilt by the record kernel of this step where they changed)
+    const int cntx = s.xcnt[p * kChunks + chunk];
+    const MemberDev *M = s.mem + m;
+    const int pl = p - uni(M->p_off);
+    if (pl >= uni(M->np)) return;
+    if (only >= 0 && m != only) return;
+
+    const int nx = uni(M->nx), ny = uni(M->ny);
+    const int per0 = uni(M->per[0]), per1 = uni(M->per[1]), per2 = uni(M->per[2]);
+    const double box0 = uni(M->box[0]), box1 = uni(M->box[1]), box2 = uni(M->box[2]);
+    const long long cell_off = uni(M->cell_off);
+    const double rho_f = uni(M->rho_f);
+    const bool rest_free = uni(M->rest_free) != 0;
+    const int nxy = nx * ny;
+    const long long lbase = (long long)p * s.lcap;
+    const int *xc = s.xcell + lbase + k0;
+    const int *xs = s.xslot + lbase + k0;
+    const unsigned *xg = s.xgrp + lbase + k0;
+    const double R0 = s.Xref[3 * p], R1 = s.Xref[3 * p + 1], R2 = s.Xref[3 * p + 2];
+    const double inv_nxy = 1.0 / (double)nxy, inv_nx = 1.0 / (double)nx;
+
+
+    // Positions of the entries' nodes relative to the shell list's reference point X_ref,
+    // xr = x - X_ref (minimum image; X_ref moves only when the shell list is rebuilt, which
+    // rebuilds the entries).  With delta = X - X_ref, r = xr - delta, so the torque is
+    // sum xr x G - delta x F0, and Z follows from sums over the link set alone:
+    // S = sum S_n, Qx = sum [xr] S_n, Wx = sum [xr] S_n [xr]^T (the motion kernel applies delta).
+    const double a18 = 2.0 * rho_f / 18.0, a36 = 2.0 * rho_f / 36.0;   // 2 rho_f w_d
+    // (in a set with a narrow lattice the entry's image of p is the one that holds its link
+    // group: its arm from the current centre X, as group_arm, plus the small displacement
+    // X - X_ref)
+    const double dX0 = mimg(X0 - R0, per0, box0), dX1 = mimg(X1 - R1, per1, box1), dX2 = mimg(X2 - R2, per2, box2);
+    auto rel_pos = [&](int cell, unsigned g, double &x0, double &x1, double &x2) {
+        const int kk = div_uni(cell, nxy, inv_nxy), rem = cell - kk * nxy;
+        const int jj = div_uni(rem, nx, inv_nx), ii = rem - jj * nx;
+        if constexpr (NR) {
+            group_arm<true>(M, g, ii, jj, kk, X0, X1, X2, x0, x1, x2);
+            x0 += dX0; x1 += dX1; x2 += dX2;
+        } else {
+            x0 = mimg((double)ii - R0, per0, box0);
+            x1 = mimg((double)jj - R1, per1, box1);
+            x2 = mimg((double)kk - R2, per2, box2);
+        }
+    };
 
     // (3) F0 = sum 2 c_d f~_d and sum xr x (the node's part of F0) over the entries
     double acc[kLinkComp];
@@ -3346,21 +3423,26 @@ hipError_t launch_refresh(int prec, const DevSet &s, hipStream_t st)
 int motion_grid(const DevSet &s) { return max((s.ptot + kMotionWaves - 1) / kMotionWaves, 1); }
 int remap_grid(const DevSet &s) { return max((s.ptot + kRemapWaves - 1) / kRemapWaves + s.nprobe_total, 1); }
 
-template <bool CMP>
+template <bool CMP, bool NR>
 void *records_ptr(int prec)
 {
     switch (prec) {
-    case PREC_FP64: return (void *)&k_records<PREC_FP64, CMP>;
-    case PREC_FP32: return (void *)&k_records<PREC_FP32, CMP>;
-    case PREC_FP16DEV: return (void *)&k_records<PREC_FP16DEV, CMP>;
-    default: return (void *)&k_records<PREC_BF16DEV, CMP>;
+    case PREC_FP64: return (void *)&k_records<PREC_FP64, CMP, NR>;
+    case PREC_FP32: return (void *)&k_records<PREC_FP32, CMP, NR>;
+    case PREC_FP16DEV: return (void *)&k_records<PREC_FP16DEV, CMP, NR>;
+    default: return (void *)&k_records<PREC_BF16DEV, CMP, NR>;
     }
 }
-void *records_kernel_ptr(int prec, int compact) { return compact ? records_ptr<true>(prec) : records_ptr<false>(prec); }
+void *records_kernel_ptr(int prec, int compact, int narrow)
+{
+    if (narrow) return compact ? records_ptr<true, true>(prec) : records_ptr<false, true>(prec);
+    return compact ? records_ptr<true, false>(prec) : records_ptr<false, false>(prec);
+}
+int records_grid(const DevSet &s) { return rebuild_blocks(s) + s.tiles_total; }
 hipError_t launch_records(int prec, const DevSet &s, hipStream_t st)
 {
-    hipLaunchKernelGGL(reinterpret_cast<void (*)(DevSet)>(records_kernel_ptr(prec, s.compact)), dim3(s.tiles_total),
-                       dim3(256), 0, st, s);
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(DevSet)>(records_kernel_ptr(prec, s.compact, s.narrow)),
+                       dim3(records_grid(s)), dim3(256), 0, st, s);
     return hipGetLastError();
 }
 
