@@ -10,13 +10,15 @@
 //                changes, refreshes the link words of the changed nodes and their
 //                neighbours, and rebuilds the node lists (moving the populations of changed
 //                planes under compact storage) once a particle may have crossed their skin.
-//   k_records    one thread per listed node (or node of a dense tile): per link slot of a
-//                fluid node, the sum of c_d (f~_d(x,t) - w_d rho_f) over the slot's links,
-//                for the link pass.
+//   k_records    first kChunks waves per particle, rebuilding the link entries of the
+//                chunks of its shell list whose link words changed, with their link-set
+//                sums (the 6 x 6 matrix Z of the motion kernel comes from them); then one
+//                thread per listed node (or node of a dense tile): per link slot of a fluid
+//                node, the sum of c_d (f~_d(x,t) - w_d rho_f) over the slot's links.
 //   k_links      kChunks waves per particle: the link pass.  With Eq. (mem) substituted, the
 //                link force of Eq. (fFS) is 2 c_d f~_d(x,t) minus a term linear in the
 //                particle's velocities; per (particle, chunk) the first part and its torque
-//                (F0, T0) and the 6 x 6 matrix Z of the second are summed in FP64 from f~(t).
+//                (F0, T0) are summed in FP64 from the records of f~(t).
 //   k_motion     one wave per particle: contacts (Eqs. fdLawn, fdLaws) at X(t), then the
 //                velocities of the step from (M + Z)(V', Omega') = M (V, Omega) + F0 + contacts
 //                + F_g + the conversion impulses of the previous re-projection (Eqs. translate,
@@ -2266,6 +2268,7 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
     __shared__ double accw[kRemapWaves][6];
     __shared__ double ctxw[kRemapWaves][9]; // x, x_ref unwrapped next to x, lr, dr, overlap depth
     __shared__ int flagw[kRemapWaves];
+    __shared__ int ncnt[kRemapWaves][4]; // near-list candidates per (particle, wave)
     // each wave's queue of candidate nodes (cell, owner before the projection or -2)
     constexpr int kQueue = 256;
     __shared__ int qcell[kRemapWaves][kQueue], qwas[kRemapWaves][kQueue];
@@ -2865,30 +2868,47 @@ __global__ __launch_bounds__(256) void k_remap(DevSet s, int mode, int only)
 #pragma unroll
         for (int w = 0; w < kRemapWaves; ++w) Rw[w] = s.R[min((int)blockIdx.x * kRemapWaves + w, s.ptot - 1)];
         int near_total[kRemapWaves] = {};
+        const unsigned long long below = (1ull << (tid & 63)) - 1ull;
         for (int base = 0; base < nq; base += 256) {
             const int jj = base + tid;
             const int q = q0 + min(jj, nq - 1);
             const double Y0 = Xs[3 * q], Y1 = Xs[3 * q + 1], Y2 = Xs[3 * q + 2], Rq = s.R[q];
+            // the candidate's verdict for every particle of the workgroup, then one exchange
+            // of the waves' counts ranks the candidates of all of them in thread order
+            bool isnear[kRemapWaves];
+            unsigned long long bal[kRemapWaves];
 #pragma unroll
             for (int w = 0; w < kRemapWaves; ++w) {
-                if (!((near_w >> w) & 1)) continue;
                 const int pw = blockIdx.x * kRemapWaves + w;
-                bool isnear = false;
-                if (jj < nq && q != pw) {
+                isnear[w] = false;
+                if (((near_w >> w) & 1) && jj < nq && q != pw) {
                     const double d0 = mimg(Y0 - ctxw[w][0], per[0], box[0]);
                     const double d1 = mimg(Y1 - ctxw[w][1], per[1], box[1]);
                     const double d2 = mimg(Y2 - ctxw[w][2], per[2], box[2]);
-                    isnear = sqrt((d0 * d0 + d1 * d1) + d2 * d2) <= Rw[w] + Rq + kNearMargin;
+                    isnear[w] = sqrt((d0 * d0 + d1 * d1) + d2 * d2) <= Rw[w] + Rq + kNearMargin;
                 }
-                int tot = 0;
-                const int rk = block_rank(isnear, tot, cnt4);
-                if (isnear) {
-                    const int slot = near_total[w] + rk;
+                bal[w] = __ballot(isnear[w]);
+                if ((tid & 63) == 0) ncnt[w][wv] = __popcll(bal[w]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < kRemapWaves; ++w) {
+                int off = 0, tot = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = ncnt[w][v];
+                    off += (v < wv) ? c : 0;
+                    tot += c;
+                }
+                if (isnear[w]) {
+                    const int slot = near_total[w] + off + __popcll(bal[w] & below);
+                    const int pw = blockIdx.x * kRemapWaves + w;
                     if (slot < kNearCap) s.nearl[(long long)pw * kNearCap + slot] = q;
                     else atomicOr(s.flags, 0x2u);
                 }
                 near_total[w] += tot;
             }
+            __syncthreads();
         }
 #pragma unroll
         for (int w = 0; w < kRemapWaves; ++w) {
