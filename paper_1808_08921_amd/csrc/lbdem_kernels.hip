@@ -1404,7 +1404,7 @@ __device__ __forceinline__ int div_uni(int n, int d, double inv)
 }
 
 constexpr int kLinksBlock = 64;
-constexpr int kLinkBatch = 4;
+constexpr int kLinkBatch = 2;
 constexpr int kLinkScan = 4;  // shell cells per lane per scan round of a rebuilt chunk
 // Direction masks over the links e (d = e*, c_d = -c_e), for sums over a node's links by
 // counting: per axis and weight class (w = 1/18 on the axes, e < 6; 1/36 on the
