@@ -26,7 +26,7 @@ constexpr double kListSkin = 0.25;
 constexpr double kSkinMin = 0.05;
 constexpr double kSkinSteps = 12.0;
 constexpr int kPendCap = 16384;     // refills of unlisted nodes awaiting the next list rebuild
-constexpr int kChunks = 8;          // waves per particle in the link pass
+constexpr int kChunks = 8;          // chunks of a shell list: waves per particle in the link pass
 // components of a link-pass partial per (particle, chunk): F0 (3) and sum xr x G (3), xr the
 // node position relative to the shell list's reference point
 constexpr int kLinkComp = 6;

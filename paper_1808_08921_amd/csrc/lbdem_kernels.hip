@@ -981,17 +981,18 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
     }
 }
 
-// Link records of step t for the link pass, one thread per listed node (or per node of a
-// dense tile), on the fluid kernel's grid, after the refresh (link words and storage slots
-// of step t final): per fluid node with links and per slot of its link words, G = sum c_d
-// (f~_d(x,t) - w_d rho_f) over the slot's links, read from the node's own storage slot
-// (consecutive threads read consecutive slots).
 template <bool NR>
 __device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk, long long t);
 
 // Workgroups of the record kernel that rebuild stale link chunks, four chunks each.
 __host__ __device__ __forceinline__ int rebuild_blocks(const DevSet &s) { return (s.ptot * kChunks + 3) / 4; }
 
+// After the refresh (link words and storage slots of step t final): first the rebuild of
+// the stale link chunks (rebuild_chunk), one wave per (particle, chunk); then the link
+// records of step t for the link pass, one thread per listed node (or per node of a dense
+// tile) on the fluid kernel's grid: per fluid node with links and per slot of its link
+// words, G = sum c_d (f~_d(x,t) - w_d rho_f) over the slot's links, read from the node's
+// own storage slot (consecutive threads read consecutive slots).
 template <int P, bool CMP, bool NR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 4 : 6))) void k_records(DevSet s)
 {
