@@ -982,7 +982,8 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
 }
 
 template <bool NR>
-__device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk, long long t);
+__device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk, long long t, int *lc, unsigned *lg);
+constexpr int kLinkLds = 384; // entries of a rebuilt chunk kept in LDS for its link-set sums
 
 // Workgroups of the record kernel that rebuild stale link chunks, four chunks each.
 __host__ __device__ __forceinline__ int rebuild_blocks(const DevSet &s) { return (s.ptot * kChunks + 3) / 4; }
@@ -1005,8 +1006,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     // are few, long and latency-bound, so they start first and run beside the node waves
     const int nrb = rebuild_blocks(s);
     if ((int)blockIdx.x < nrb) {
-        const int ci = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-        if (ci < s.ptot * kChunks) rebuild_chunk<NR>(s, ci / kChunks, ci - (ci / kChunks) * kChunks, t);
+        __shared__ int rb_c[4][kLinkLds];
+        __shared__ unsigned rb_g[4][kLinkLds];
+        const int wv = (int)(threadIdx.x >> 6);
+        const int ci = (int)blockIdx.x * 4 + wv;
+        if (ci < s.ptot * kChunks) rebuild_chunk<NR>(s, ci / kChunks, ci - (ci / kChunks) * kChunks, t, rb_c[wv], rb_g[wv]);
         return;
     }
     const int g = xcd_swizzle((int)blockIdx.x - nrb, (int)gridDim.x - nrb);
@@ -1439,7 +1443,7 @@ constexpr unsigned pair_mask(int a, int b, int sign)
 // words of this step (after the refresh) and no link record: the record kernel runs it in
 // waves of its own before its node waves, and the link pass reads the entries.
 template <bool NR>
-__device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk, long long t)
+__device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk, long long t, int *lc, unsigned *lg)
 {
     const int par = (int)(t & 1);
     const int lane = threadIdx.x & 63;
@@ -1596,6 +1600,12 @@ __device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk,
                             xc[at] = (int)((unsigned)cell | ((unsigned)slot << 30));
                             xs[at] = nsb[b];
                             xg[at] = grp;
+                            // (the first kLinkLds entries also in this wave's LDS, where the
+                            // link-set sums read them)
+                            if (at < kLinkLds) {
+                                lc[at] = (int)((unsigned)cell | ((unsigned)slot << 30));
+                                lg[at] = grp;
+                            }
                         } else {
                             atomicOr(s.flags, 0x40u);
                         }
@@ -1608,12 +1618,20 @@ __device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk,
             }
         }
         if (lane == 0) s.xcnt[p * kChunks + chunk] = cntx;
-        // (the link-set sums read the entries back: this wave's stores are made visible to
-        // the wave itself; the other waves of its workgroup rebuild other chunks)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // (the link-set sums read the entries back, from LDS, or from memory for a chunk
+        // with more than kLinkLds entries: the wave's writes are made visible to the wave
+        // itself; the other waves of its workgroup rebuild other chunks)
+        if (cntx <= kLinkLds) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
     }
+    const bool from_lds = cntx <= kLinkLds;
 
 
     // Positions of the entries' nodes relative to the shell list's reference point X_ref,
@@ -1643,7 +1661,10 @@ __device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk,
     // integer sums from the scan, or, in a set with a narrow lattice, FP64 sums over the
     // entries in list order
     if (!NR) {
-        for (int k = lane; k < cntx; k += kLinksBlock) add_link_set((int)((unsigned)xc[k] & 0x3fffffffu), xg[k]);
+        if (from_lds)
+            for (int k = lane; k < cntx; k += kLinksBlock) add_link_set((int)((unsigned)lc[k] & 0x3fffffffu), lg[k]);
+        else
+            for (int k = lane; k < cntx; k += kLinksBlock) add_link_set((int)((unsigned)xc[k] & 0x3fffffffu), xg[k]);
         int si[15];
 #pragma unroll
         for (int c = 0; c < 15; ++c) si[c] = wave_sum_i(zsi[c]);
@@ -1708,9 +1729,9 @@ __device__ __forceinline__ void rebuild_chunk(const DevSet &s, int p, int chunk,
 #pragma unroll
         for (int c = 0; c < 21; ++c) zs[c] = 0.0;
         for (int k = lane; k < cntx; k += kLinksBlock) {
-            const unsigned g = xg[k];
+            const unsigned g = from_lds ? lg[k] : xg[k];
             double x0, x1, x2;
-            rel_pos((int)((unsigned)xc[k] & 0x3fffffffu), g, x0, x1, x2);
+            rel_pos((int)((unsigned)(from_lds ? lc[k] : xc[k]) & 0x3fffffffu), g, x0, x1, x2);
             // S_n = sum 6 w_d rho_f c_d c_d^T over the node's links, from counts
             auto diag = [&](int axis) {
                 return z18 * (double)__popc(g & (link_mask(axis, 1, false) | link_mask(axis, -1, false))) +
