@@ -739,13 +739,17 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
 {
     using S = typename Prec<P>::S;
     const long long t = *s.tstep;
+    // (both change counts and the list-rebuild step are loaded with the step counter)
+    const int cnt0 = s.chgcnt[0], cnt1 = s.chgcnt[1];
+    const long long relist_at = *s.relist_at;
     const int par = (int)(t & 1);
-    const int cnt = s.chgcnt[par ^ 1];
+    const int cnt = par ? cnt0 : cnt1;
+    const bool relist = s.listmode && relist_at == t;
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     bool over = false;
     // (a step that rebuilds the node lists rewrites every compact word in the record kernel)
-    const bool fix_compact = s.compact && !(s.listmode && *s.relist_at == t);
+    const bool fix_compact = s.compact && !relist;
     if (cnt > s.chg_cap) {
         // (every link word may change: the record kernel rewrites every compact word)
         if (t0 == 0) *s.lwc_bad = t;
@@ -854,7 +858,7 @@ __global__ __launch_bounds__(256) void k_refresh(DevSet s)
     // less than the skin inside its particle's surface.  Only such a node can become
     // fluid before a particle has moved the skin.  The skin follows the lattice's
     // fastest particle (kSkinSteps of its last step, within [kSkinMin, kListSkin]).
-    if (s.listmode && *s.relist_at == t) {
+    if (relist) {
         __shared__ int cnt4[4];
         __shared__ double vred[4];
         for (long long q = t0; q < s.ptot; q += stride)
