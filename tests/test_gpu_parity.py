@@ -178,6 +178,25 @@ def test_compact_planes_beyond_the_grid_estimate_fp64():
         assert gs.status() & 0x1da == 0
 
 
+def test_large_moving_sphere_fp64():
+    """One sphere of radius 20 moving through a periodic 48^3 box: a chunk of its shell list
+    holds more link entries than a rebuild keeps in LDS (its link-set sums read the entries
+    back from memory), and past a tenth of a node of motion the re-projection takes its
+    candidates from the whole shell list, in many batches; the state matches the oracle."""
+    params = dict(nx=48, ny=48, nz=48, tau=0.8, bc=(0,) * 6, rho_p=2.0, max_particles=1, max_radius=20.0,
+                  probe_z=[10, 24])
+    pk = {"x": np.array([[23.6, 24.3, 24.1]]), "radius": np.array([20.0]),
+          "v": np.array([[0.02, -0.015, 0.01]]), "w": np.array([[0.0, 0.001, -0.0005]])}
+    s = _oracle(params, pk)
+    with _gpu_set([params], graph_steps=4) as gs:
+        _set_particles(gs, 0, pk)
+        for n in (8, 12):
+            gs.step(n)
+            s.step(n)
+            _compare_state(gs, 0, s, pk)
+        assert gs.status() & 0x1da == 0
+
+
 @pytest.mark.parametrize("margin", [0, 2])
 def test_moving_sphere_parked_refills_fp64(margin):
     """Compact storage with the list rebuild trigger's look-ahead switched off: nodes turn
