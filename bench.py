@@ -251,6 +251,11 @@ def cpu_baseline(params, pk, budget_s=15.0, all_core_s=15.0, max_procs=16):
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1808_08921_amd", "csrc", "lbdem_kernels.hip")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_fluid_fcc96x96x384_fp32_counters.txt")
+
+
+def counters_file(precision):
+    """Path of the committed counter summary of the FCC case at one storage precision."""
+    return os.path.join(ROOT, "profiles", f"k_fluid_fcc96x96x384_{precision}_counters.txt")
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read and 1 GiB written
 
 
@@ -261,13 +266,14 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def counters_workload(steps):
-    """Workload for the rocprofv3 counter passes: `steps` eager steps of the FP32 FCC case,
-    then a plain device-to-device copy of COPY_BYTES that calibrates the counters."""
+def counters_workload(steps, precision="fp32"):
+    """Workload for the rocprofv3 counter passes: `steps` eager steps of the FCC case at the
+    given storage precision, then a plain device-to-device copy of COPY_BYTES that
+    calibrates the counters."""
     import torch
 
     params, pk = _case(seed=0)
-    gs = _make(params, pk, "fp32", graph_steps=0)
+    gs = _make(params, pk, precision, graph_steps=0)
     gs.step(steps)
     gs.synchronize()
     gs.close()
@@ -279,7 +285,7 @@ def counters_workload(steps):
     _log("counter workload done")
 
 
-def summarize_counters(fetch_csv, write_csv, out_path, command):
+def summarize_counters(fetch_csv, write_csv, out_path, command, precision="fp32"):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of each kernel from two rocprofv3 --pmc
     passes, scaled by the same counters' reading for the calibration copy (COPY_BYTES read
     and written), written as a text summary with the kernel source hash."""
@@ -298,7 +304,8 @@ def summarize_counters(fetch_csv, write_csv, out_path, command):
     copy_name = max((k for k in fetch if "copy" in k.lower()), key=lambda k: max(fetch[k]))
     f_scale = COPY_BYTES / (max(fetch[copy_name]) * 1024.0)
     w_scale = COPY_BYTES / (max(write[copy_name]) * 1024.0)
-    lines = [f"# rocprofv3 counters, FCC 96x96x384 FP32 (1024 spheres), per dispatch",
+    label = {"fp32": "FP32", "fp16": "FP16 deviations", "bf16": "BF16 deviations"}[precision]
+    lines = [f"# rocprofv3 counters, FCC 96x96x384 {label} (1024 spheres), per dispatch",
              f"# command: {command}",
              f"# kernel source sha256[:16]: {kernel_source_hash()}",
              f"# calibration: {copy_name} copying {COPY_BYTES} B reads FETCH_SIZE {max(fetch[copy_name]):.0f} KiB, "
@@ -712,6 +719,8 @@ def main():
                     help="skip the ensemble, adjoint-window and settling-sweep summaries of the main line")
     ap.add_argument("--counters", type=int, default=0, metavar="STEPS",
                     help="only run the workload of the rocprofv3 counter passes (STEPS eager steps + a copy)")
+    ap.add_argument("--counters-precision", choices=("fp32", "fp16", "bf16"), default="fp32",
+                    help="storage precision of the counter workload and of its summary's file")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="write the counter summary from two rocprofv3 --pmc CSV files")
     ap.add_argument("--ensemble", type=int, default=0, metavar="N",
@@ -747,10 +756,11 @@ def main():
         return
     if args.summarize_counters:
         fetch_csv, write_csv, command = args.summarize_counters
-        summarize_counters(fetch_csv, write_csv, COUNTERS_FILE, command)
+        summarize_counters(fetch_csv, write_csv, counters_file(args.counters_precision), command,
+                           args.counters_precision)
         return
     if args.counters:
-        counters_workload(args.counters)
+        counters_workload(args.counters, args.counters_precision)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a slab decomposition over several "
