@@ -1141,6 +1141,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     const double rho_fd = uni(M->rho_f);
     const C omega = (C)uni(M->omega);
     const int bc4 = uni(M->bc[4]), bc5 = uni(M->bc[5]);
+    // (the rest of the lattice's constants are read here too: the barriers of the node
+    // loop below would otherwise make each wave read them again after them)
+    const int bc0 = uni(M->bc[0]), bc1 = uni(M->bc[1]), bc2 = uni(M->bc[2]), bc3 = uni(M->bc[3]);
+    const long long rt_off = CMP ? uni(M->rt_off) : 0ll;
+    const int nw = CMP ? uni(M->nw) : 0, per_x = uni(M->per[0]);
     const long long t_n = uni(M->t_n);
     long long ti = t + 1;
     if (ti > t_n + 1) ti = t_n + 1;
@@ -1159,13 +1164,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
     __shared__ int jr[2];
 
     auto run = [&](int i, int j, int z0, int z1, int me0, bool vij, bool accum, const uint2 *lrt, int jb,
-                   int nrows) {
+                   int nrows, unsigned long long wcl) {
         // offsets to the x-1 / x+1 / y-1 / y+1 neighbours (wrapped on periodic axes) and the
         // kind of face crossed to reach them (0 inside or periodic, 1 wall, 2 density face)
         int oxm = (i > 0) ? -1 : (nx - 1), oxp = (i < nx - 1) ? 1 : -(nx - 1);
-        int kxm = (i > 0) ? 0 : uni(M->bc[0]), kxp = (i < nx - 1) ? 0 : uni(M->bc[1]);
+        int kxm = (i > 0) ? 0 : bc0, kxp = (i < nx - 1) ? 0 : bc1;
         int oym = (j > 0) ? -nx : (ny - 1) * nx, oyp = (j < ny - 1) ? nx : -(ny - 1) * nx;
-        int kym = (j > 0) ? 0 : uni(M->bc[2]), kyp = (j < ny - 1) ? 0 : uni(M->bc[3]);
+        int kym = (j > 0) ? 0 : bc2, kyp = (j < ny - 1) ? 0 : bc3;
 
         for (int z = z0; z < z1; ++z) {
             // keep the 18 per-direction offsets from being hoisted out of the loop: they are
@@ -1175,8 +1180,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
             bool fl = false;
             unsigned long long wc = 0ull;
             if constexpr (CMP) {
-                // the node's compact word, at its slot (which the thread knows before its cell)
-                wc = s.lwc[cell_off + me0];
+                // the node's compact word, at its slot (loaded with the node's cell)
+                wc = wcl;
                 fl = vij && !(wc & kSolidWord);
             } else {
                 if (vij) fl = ldo(own, (unsigned)cell) < 0;
@@ -1214,8 +1219,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                 // x face reads the table word at the other end of the row.
                 int src[kQ - 1];
                 if (compact) {
-                    const uint2 *rtab = s.rt + uni(M->rt_off);
-                    const int nw = uni(M->nw), per_x = uni(M->per[0]);
+                    const uint2 *rtab = s.rt + rt_off;
                     const unsigned b = 1u << (i & 31);
                     const int wx = (i == 0) ? nx - 1 : 0;
                     const unsigned bw = 1u << (wx & 31);
@@ -1342,6 +1346,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
             const int kk = lbx * 256 + (int)threadIdx.x;
             const bool v = kk < cnt;
             const int c = v ? s.clist[cell_off + (long long)z * nxy + kk] - z * nxy : 0;
+            // compact storage: the node's first link word (or the solid marker) at its slot
+            const unsigned long long wcl = (CMP && v) ? s.lwc[cell_off + (long long)z * nxy + kk] : 0ull;
             const int jj = c / nx;
             const uint2 *lrt = nullptr;
             int jb = 0, nrows = 0;
@@ -1355,10 +1361,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                 __syncthreads();
                 jb = jr[0] - 1;
                 nrows = jr[1] - jr[0] + 3;
-                const int nw = uni(M->nw);
                 const int tot = 3 * nrows * nw;
                 if (tot <= kRtLds) {
-                    const uint2 *rtab = s.rt + uni(M->rt_off);
+                    const uint2 *rtab = s.rt + rt_off;
                     for (int w = threadIdx.x; w < tot; w += 256) {
                         const int pz = w / (nrows * nw), rem = w - pz * (nrows * nw);
                         const int u = rem / nw, wq = rem - u * nw;
@@ -1370,7 +1375,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
                 __syncthreads();
             }
             // the node's slot under compact storage
-            run(c - jj * nx, jj, z, z + 1, z * nxy + kk, v, lbx != lb, lrt, jb, nrows);
+            run(c - jj * nx, jj, z, z + 1, z * nxy + kk, v, lbx != lb, lrt, jb, nrows, wcl);
             // (the next chunk stages its own rows once every thread is done with these)
             if constexpr (CMP) __syncthreads();
         }
@@ -1381,7 +1386,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == PREC_F
         const int i = (tx << bxl) + lx;
         const int j = ty * uni(M->by) + ly;
         const int z0 = tz * s.nzt;
-        run(i, j, z0, min(z0 + s.nzt, nz), 0, (i < nx) && (j < ny), false, nullptr, 0, 0);
+        run(i, j, z0, min(z0 + s.nzt, nz), 0, (i < nx) && (j < ny), false, nullptr, 0, 0, 0ull);
     }
 }
 
